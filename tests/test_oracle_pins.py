@@ -1,0 +1,476 @@
+"""Pins for the FP64 oracle against facts the paper and mathematics fix.
+
+Nothing here re-types an oracle formula and compares it with itself: each
+test checks a closed form, an invariant, a special case computed by an
+independent library routine, finite differences of the oracle's own
+evaluation, or a count printed in the paper.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.special as sps
+import scipy.stats as sst
+from scipy.spatial import cKDTree
+
+import workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rand_q(rng, J, lo=-1.0, hi=1.0):
+    return rng.uniform(lo, hi, size=(J, 3))
+
+
+# ---------------------------------------------------------------- layout pins
+def test_param_counts_match_paper(orc):
+    """Tab. main / Tab. ablation: R^3 x channels; the default model is 13 floats
+    per vertex = 5 (grid key) + 8 (moved key)."""
+    gold = json.load(open(os.path.join(GOLD, "paper_param_counts.json")))
+    for e in gold["entries"]:
+        assert e["R"] ** 3 * e["channels"] == e["params"], e["cite"]
+    b = gold["channel_budget"]
+    assert sum(v for k, v in b["grid_key"].items() if k != "cite") + \
+        sum(v for k, v in b["moved_key"].items() if k != "cite") == orc.NCH == 13
+    g = orc.Grid(R=4)
+    assert orc.num_keys(g) == 2 * 4 ** 3
+    assert orc.num_keys(orc.Grid(R=4, offsets=0)) == 4 ** 3
+
+
+def test_every_channel_enters_the_model(orc):
+    """Each of the 13 channels changes the output somewhere (no dead channel)."""
+    rng = np.random.default_rng(0)
+    g = orc.Grid(R=3)
+    th = W.perturbed_theta(3, 5)
+    q = rand_q(rng, 64)
+    O0, _, _ = orc.eval_global(orc.build_keys(g, th), q)
+    for ch in range(13):
+        t2 = th.copy()
+        t2[..., ch] += 0.05
+        O1, _, _ = orc.eval_global(orc.build_keys(g, t2), q)
+        assert np.abs(O1 - O0).max() > 1e-6, ch
+
+
+def test_lattice_is_float32_rounded_uniform(orc):
+    g = orc.Grid(R=7, lo=-1.0, hi=1.0)
+    t = orc.lattice(g)
+    ref = np.linspace(-1.0, 1.0, 7).astype(np.float32).astype(np.float64)
+    assert np.array_equal(t, ref)
+
+
+# ------------------------------------------------------ forward special cases
+def test_one_key_returns_its_polynomial(orc):
+    """A single key: softmax weight 1, so O = f(q - c) and lse = s."""
+    rng = np.random.default_rng(1)
+    key = np.array([[0.1, -0.2, 0.3, 50.0, 0.7, 1.5, -2.0, 0.25]])
+    q = rand_q(rng, 20)
+    O, lse, _ = orc.eval_global(key, q)
+    x = q - key[0, :3]
+    assert np.allclose(O, 0.7 + x @ key[0, 5:], rtol=0, atol=1e-14)
+    assert np.allclose(lse, -50.0 * (x * x).sum(1), rtol=1e-14, atol=1e-14)
+
+
+def test_two_keys_logistic_blend(orc):
+    """Two keys: the softmax is the logistic function of the logit gap."""
+    rng = np.random.default_rng(2)
+    keys = np.array([[0.0, 0.0, 0.0, 30.0, 1.0, 0.5, 0.0, 0.0],
+                     [0.4, 0.1, -0.2, 80.0, -1.0, 0.0, 2.0, -1.0]])
+    q = rand_q(rng, 50, -0.5, 0.7)
+    O, _, _ = orc.eval_global(keys, q)
+    s = [-k[3] * ((q - k[:3]) ** 2).sum(1) for k in keys]
+    f = [k[4] + (q - k[:3]) @ k[5:] for k in keys]
+    w0 = sps.expit(s[0] - s[1])
+    assert np.allclose(O, w0 * f[0] + (1 - w0) * f[1], rtol=1e-12, atol=1e-13)
+
+
+def test_order0_fixed_grid_is_nadaraya_watson(orc):
+    """f^0 on fixed grid keys with one common beta is Gaussian-kernel
+    Nadaraya-Watson regression (Sec. 3.1): compare with the estimator built
+    from scipy's multivariate normal density of covariance 1/(2 beta) I."""
+    rng = np.random.default_rng(3)
+    R, beta = 4, 9.0
+    g = orc.Grid(R=R, offsets=0)
+    th = np.zeros((R, R, R, 13), np.float32)
+    th[..., 0] = rng.uniform(0.2, 2.0, size=(R, R, R))
+    th[..., 4] = np.float32(np.log(beta))
+    keys = orc.build_keys(g, th)
+    beta_used = keys[0, 3]
+    q = rand_q(rng, 40, -0.9, 0.9)
+    O, _, _ = orc.eval_global(keys, q)
+    v = keys[:, 4]
+    cov = np.eye(3) / (2.0 * beta_used)
+    K = np.stack([sst.multivariate_normal(mean=k, cov=cov).pdf(q) for k in keys[:, :3]], 1)
+    nw = (K @ v) / K.sum(1)
+    assert np.allclose(O, nw, rtol=1e-10, atol=1e-12)
+
+
+def test_lse_separates_over_axes_on_the_lattice(orc):
+    """Equal betas on the fixed lattice: sum over vertices of
+    exp(-beta ||q - k||^2) factorises into three 1-D sums."""
+    rng = np.random.default_rng(4)
+    R = 5
+    g = orc.Grid(R=R, offsets=0)
+    th = W.plain_theta(R, rho0=2.5)
+    keys = orc.build_keys(g, th)
+    t = orc.lattice(g)
+    beta = keys[0, 3]
+    q = rand_q(rng, 30)
+    _, lse, _ = orc.eval_global(keys, q)
+    ref = sum(sps.logsumexp(-beta * (q[:, d:d + 1] - t[None, :]) ** 2, axis=1) for d in range(3))
+    assert np.allclose(lse, ref, rtol=1e-13, atol=1e-12)
+
+
+def test_large_beta_selects_nearest_key(orc):
+    """beta -> infinity: the output is the polynomial of the nearest centre
+    (found with a k-d tree)."""
+    rng = np.random.default_rng(5)
+    R = 4
+    g = orc.Grid(R=R)
+    th = W.perturbed_theta(R, 7, rho0=9.0, rho_spread=0.0, offset_cells=0.4)
+    th[..., 4] = 11.0
+    th[..., 12] = 11.0
+    keys = orc.build_keys(g, th)
+    q = rand_q(rng, 300, -0.95, 0.95)
+    d, idx = cKDTree(keys[:, :3]).query(q, k=2)
+    ok = (d[:, 1] ** 2 - d[:, 0] ** 2) > 0.02   # clear winner: gap x beta ~ 1200
+    O, _, _ = orc.eval_global(keys, q)
+    k = keys[idx[:, 0]]
+    f = k[:, 4] + ((q - k[:, :3]) * k[:, 5:]).sum(1)
+    assert ok.sum() > 100
+    assert np.allclose(O[ok], f[ok], rtol=0, atol=1e-9)
+
+
+def test_convexity_and_constant_reproduction(orc):
+    """Softmax weights are a convex combination (Sec. 3.1): with f^0 the output
+    lies within [min v, max v]; equal values are reproduced to rounding."""
+    rng = np.random.default_rng(6)
+    g = orc.Grid(R=3)
+    th = W.perturbed_theta(3, 8)
+    th[..., 1:4] = 0
+    th[..., 9:12] = 0
+    keys = orc.build_keys(g, th)
+    q = rand_q(rng, 100)
+    O, _, _ = orc.eval_global(keys, q)
+    assert O.min() >= keys[:, 4].min() - 1e-12 and O.max() <= keys[:, 4].max() + 1e-12
+    th[..., 0] = 0.375
+    th[..., 8] = 0.375
+    O, _, _ = orc.eval_global(orc.build_keys(g, th), q)
+    assert np.allclose(O, 0.375, rtol=4e-16, atol=0)
+
+
+def linear_theta(R, alpha, b, seed=0, lo=-1.0, hi=1.0):
+    """Every key (grid and moved, any beta, any offset) carries the same
+    linear function alpha + b.q written around its own centre."""
+    rng = np.random.default_rng(seed)
+    th = W.perturbed_theta(R, seed)
+    t = np.linspace(lo, hi, R).astype(np.float32).astype(np.float64)
+    K = np.stack(np.meshgrid(t, t, t, indexing="ij"), -1)
+    C = K + th[..., 5:8].astype(np.float64)
+    th = th.astype(np.float64)
+    th[..., 0] = alpha + K @ b
+    th[..., 1:4] = b
+    th[..., 8] = alpha + C @ b
+    th[..., 9:12] = b
+    del rng
+    return th.astype(np.float32)
+
+
+def test_linear_field_reproduction(orc):
+    """If every key carries alpha + b.(c + x) then f_a(q) = alpha + b.q for all a,
+    so O(q) = alpha + b.q for any scales and offsets (Sec. 3.2 shift
+    invariance + convexity); dO/dq = b (Eq. func-normal)."""
+    rng = np.random.default_rng(7)
+    R = 4
+    g = orc.Grid(R=R)
+    alpha, b = 0.3, np.array([0.5, -1.25, 2.0])
+    th = linear_theta(R, alpha, b, seed=3)
+    keys = orc.build_keys(g, th)
+    # the float32 storage rounds alpha + b.c; compare against the stored values
+    q = rand_q(rng, 200)
+    O, _, sig = orc.eval_global(keys, q)
+    assert np.allclose(O, alpha + q @ b, rtol=0, atol=2e-6 * sig.max())
+    Ot, _, _ = orc.eval_trunc(g, keys, q, 20.0)
+    assert np.allclose(Ot, alpha + q @ b, rtol=0, atol=2e-6 * sig.max())
+    # exact double-precision values remove the float32 rounding of alpha + b.c
+    keys[:, 4] = alpha + keys[:, :3] @ b
+    dq = orc.eval_qgrad(keys, q)
+    assert np.allclose(dq, b[None, :], rtol=0, atol=1e-12)
+
+
+def test_shift_invariance(orc):
+    """Translating lattice and queries together leaves O unchanged (f depends
+    on q - k only, Sec. 3.2)."""
+    rng = np.random.default_rng(8)
+    th = W.perturbed_theta(5, 9)
+    q = rand_q(rng, 50)
+    # R = 5 on [-1, 1] and on [-0.75, 1.25]: both lattices are exact in float32
+    O0, l0, _ = orc.eval_global(orc.build_keys(orc.Grid(R=5, lo=-1, hi=1), th), q)
+    O1, l1, _ = orc.eval_global(orc.build_keys(orc.Grid(R=5, lo=-0.75, hi=1.25), th), q + 0.25)
+    assert np.allclose(O0, O1, rtol=0, atol=1e-10)
+    assert np.allclose(l0, l1, rtol=1e-12, atol=1e-9)
+
+
+# ------------------------------------------------------------- query gradient
+def test_query_gradient_matches_central_differences(orc):
+    rng = np.random.default_rng(9)
+    g = orc.Grid(R=3)
+    keys = orc.build_keys(g, W.perturbed_theta(3, 10, rho0=2.0))
+    q = rand_q(rng, 25, -0.8, 0.8)
+    G = orc.eval_qgrad(keys, q)
+    h = 1e-6
+    for d in range(3):
+        e = np.zeros(3)
+        e[d] = h
+        fd = (orc.eval_global(keys, q + e)[0] - orc.eval_global(keys, q - e)[0]) / (2 * h)
+        assert np.allclose(G[:, d], fd, rtol=1e-6, atol=1e-7)
+
+
+# ----------------------------------------------------------------- gradients
+def _loss(orc, keys, q, dl):
+    return float(dl @ orc.eval_global(keys, q)[0])
+
+
+def test_key_gradients_match_central_differences(orc):
+    """Sec. 3.6 closed forms (every entry of every key, both key kinds)
+    against central differences of sum_j dL/dO_j O(q_j)."""
+    rng = np.random.default_rng(11)
+    g = orc.Grid(R=3)
+    keys = orc.build_keys(g, W.perturbed_theta(3, 12, rho0=2.0, rho_spread=1.0))
+    q = rand_q(rng, 40, -0.9, 0.9)
+    dl = rng.standard_normal(40)
+    gk, ak = orc.grad_global(keys, q, dl)
+    # central-difference rounding noise: ~ eps * sum_j |dl_j O_j| / h
+    Lmag = float(np.abs(dl) @ np.abs(orc.eval_global(keys, q)[0]))
+    worst = 0.0
+    for a in range(keys.shape[0]):
+        for c in range(8):
+            h = 1e-6 * max(1.0, abs(keys[a, c]))
+            kp, km = keys.copy(), keys.copy()
+            kp[a, c] += h
+            km[a, c] -= h
+            fd = (_loss(orc, kp, q, dl) - _loss(orc, km, q, dl)) / (2 * h)
+            noise = 50 * np.finfo(float).eps * Lmag / h
+            err = abs(fd - gk[a, c]) / (1e-6 * ak[a, c] + noise)
+            worst = max(worst, err)
+    assert worst < 1.0, worst
+
+
+def _theta_loss(orc, g, th, q, dl):
+    return _loss(orc, orc.build_keys(g, th), q, dl)
+
+
+def test_theta_channel_gradients_match_central_differences(orc):
+    """The 13-channel mapping (rho = ln beta chain rule, dL/dDelta = dL/dc,
+    fixed grid centres) against Richardson-extrapolated central differences
+    in the stored float32 parameters."""
+    rng = np.random.default_rng(13)
+    R = 3
+    g = orc.Grid(R=R)
+    th = W.perturbed_theta(R, 14, rho0=2.0, rho_spread=0.5)
+    q = rand_q(rng, 40, -0.9, 0.9)
+    dl = rng.standard_normal(40)
+    keys = orc.build_keys(g, th)
+    gk, ak = orc.grad_global(keys, q, dl)
+    gt = orc.grad_theta(g, th, gk)
+    at = orc.grad_theta(g, th, ak)
+    for trial in range(40):
+        i = tuple(rng.integers(0, R, size=3))
+        ch = int(rng.integers(0, 13))
+
+        def D(h):
+            tp, tm = th.copy(), th.copy()
+            tp[i + (ch,)] = np.float32(th[i + (ch,)] + h)
+            tm[i + (ch,)] = np.float32(th[i + (ch,)] - h)
+            span = float(tp[i + (ch,)]) - float(tm[i + (ch,)])
+            return (_theta_loss(orc, g, tp, q, dl) - _theta_loss(orc, g, tm, q, dl)) / span
+
+        h = 2.0 ** -8
+        fd = (4 * D(h / 2) - D(h)) / 3
+        scale = at[i + (ch,)] * (np.exp(th[i + (4,)]) if ch == 4 else 1.0) + 1e-6
+        if ch == 12:
+            scale = at[i + (ch,)] * np.exp(th[i + (12,)]) + 1e-6
+        assert abs(fd - gt[i + (ch,)]) <= 2e-5 * scale + 1e-9, (i, ch, fd, gt[i + (ch,)])
+
+
+def test_gradients_match_torch_autograd(orc):
+    """The same gradients from torch autograd (FP64) through an independently
+    written forward on a tiny problem."""
+    import torch
+    rng = np.random.default_rng(15)
+    R = 2
+    g = orc.Grid(R=R)
+    th = W.perturbed_theta(R, 16, rho0=1.5)
+    q = rand_q(rng, 30)
+    dl = rng.standard_normal(30)
+    gt = orc.grad_theta(g, th, orc.grad_global(orc.build_keys(g, th), q, dl)[0])
+
+    T = torch.tensor(th.astype(np.float64), requires_grad=True)
+    t = torch.tensor(orc.lattice(g))
+    K = torch.stack(torch.meshgrid(t, t, t, indexing="ij"), -1).reshape(-1, 3)
+    P = T.reshape(-1, 13)
+    Q = torch.tensor(q)
+    centres = torch.cat([K, K + P[:, 5:8]])
+    betas = torch.cat([P[:, 4].exp(), P[:, 12].exp()])
+    vals = torch.cat([P[:, 0], P[:, 8]])
+    slopes = torch.cat([P[:, 1:4], P[:, 9:12]])
+    X = Q[:, None, :] - centres[None]
+    logits = -betas[None] * (X * X).sum(-1)
+    F = vals[None] + (X * slopes[None]).sum(-1)
+    O = (torch.softmax(logits, dim=1) * F).sum(1)
+    (O * torch.tensor(dl)).sum().backward()
+    ref = T.grad.numpy()
+    ref[..., 5:8] = ref[..., 5:8]  # moved centres: dL/dDelta
+    assert np.allclose(gt, ref, rtol=1e-9, atol=1e-11)
+
+
+def test_linear_field_gradient_invariants(orc):
+    """With a linear field, f_a - O = 0 for every pair, so dO/dbeta = 0 and
+    dO/dc_a = -w_a b; summed: dL/dc_a = -b dL/do_a (Sec. 3.6)."""
+    rng = np.random.default_rng(17)
+    R = 3
+    g = orc.Grid(R=R)
+    b = np.array([0.25, -0.5, 1.0])
+    keys = orc.build_keys(g, linear_theta(R, -0.1, b, seed=4))
+    # rebuild values exactly in double so f_a - O vanishes to rounding
+    keys[:, 4] = -0.1 + keys[:, :3] @ b
+    keys[:, 5:] = b
+    q = rand_q(rng, 50)
+    dl = rng.standard_normal(50)
+    gk, ak = orc.grad_global(keys, q, dl)
+    assert np.abs(gk[:, 3]).max() <= 1e-12 * (1 + ak[:, 3].max())
+    assert np.allclose(gk[:, 0:3], -gk[:, 4:5] * b[None], rtol=0, atol=1e-12)
+
+
+# ----------------------------------------------------------------- truncation
+def test_truncation_error_within_bound(orc):
+    """Dropping only keys with s < M - T changes O by at most the dropped
+    mass (<= nkeys e^-T) times 2 max |f|; large T recovers the global sum."""
+    rng = np.random.default_rng(19)
+    R = 6
+    g = orc.Grid(R=R)
+    th = W.perturbed_theta(R, 20, rho0=3.0, rho_spread=1.0, offset_cells=1.0)
+    keys = orc.build_keys(g, th)
+    q = rand_q(rng, 400)
+    O, lse, sig = orc.eval_global(keys, q)
+    fmax = np.abs(keys[:, 4]).max() + 4 * np.abs(keys[:, 5:]).max()
+    for T in (6.0, 10.0):
+        Ot, lt, _ = orc.eval_trunc(g, keys, q, T)
+        eps = keys.shape[0] * np.exp(-T)
+        assert np.all(np.abs(Ot - O) <= 2 * eps * fmax / (1 - min(eps, 0.5)))
+        assert np.all(lt <= lse + 1e-12) and np.all(lse - lt <= eps / (1 - min(eps, 0.5)))
+        assert np.abs(Ot - O).max() > 0  # the truncation really dropped something
+    Ot, lt, _ = orc.eval_trunc(g, keys, q, 1e4)
+    assert np.allclose(Ot, O, rtol=0, atol=1e-12) and np.allclose(lt, lse, atol=1e-12)
+
+
+def test_truncated_gradient_limits(orc):
+    rng = np.random.default_rng(21)
+    R = 4
+    g = orc.Grid(R=R)
+    keys = orc.build_keys(g, W.perturbed_theta(R, 22, rho0=3.0))
+    q = rand_q(rng, 100)
+    dl = rng.standard_normal(100)
+    gk, ak = orc.grad_global(keys, q, dl)
+    gt, at = orc.grad_trunc(g, keys, q, dl, 1e4)
+    assert np.allclose(gt, gk, rtol=1e-10, atol=1e-12)
+    gt, at = orc.grad_trunc(g, keys, q, dl, 20.0)
+    assert np.all(np.abs(gt - gk) <= 1e-4 * ak + 1e-6 * ak.max(axis=0))
+
+
+def test_truncated_mode_keeps_points_outside_domain_correct(orc):
+    rng = np.random.default_rng(23)
+    g = orc.Grid(R=5)
+    keys = orc.build_keys(g, W.perturbed_theta(5, 24, rho0=4.0))
+    q = rand_q(rng, 100, -1.6, 1.6)
+    O, _, _ = orc.eval_global(keys, q)
+    Ot, _, _ = orc.eval_trunc(g, keys, q, 30.0)
+    assert np.allclose(Ot, O, rtol=0, atol=1e-9)
+
+
+# ---------------------------------------------------------------------- Adam
+@pytest.mark.parametrize("wd", [0.0, 0.01])
+def test_adamw_matches_torch(orc, wd):
+    import torch
+    rng = np.random.default_rng(25)
+    n = 64
+    p0 = rng.standard_normal(n)
+    grads = [rng.standard_normal(n) for _ in range(4)]
+    P = torch.tensor(p0, requires_grad=True)
+    opt = torch.optim.AdamW([P], lr=6e-4, betas=(0.9, 0.999), eps=1e-8, weight_decay=wd)
+    th, m, v = p0.copy(), np.zeros(n), np.zeros(n)
+    for s, gr in enumerate(grads, start=1):
+        P.grad = torch.tensor(gr)
+        opt.step()
+        th, m, v = orc.adam(th, m, v, gr, s, lr=6e-4, wd=wd)
+    assert np.allclose(th, P.detach().numpy(), rtol=0, atol=1e-15)
+
+
+# ---------------------------------------------------------------- mean-shift
+def test_meanshift_single_point_moves_every_key_onto_it(orc):
+    g = orc.Grid(R=3)
+    s = np.array([[0.123, -0.456, 0.789]])
+    D = orc.meanshift(g, s, 100.0)
+    t = orc.lattice(g)
+    K = np.stack(np.meshgrid(t, t, t, indexing="ij"), -1).reshape(-1, 3)
+    assert np.allclose(K + D, s, rtol=0, atol=1e-15)
+
+
+def test_meanshift_symmetric_set_keeps_centre_key(orc):
+    g = orc.Grid(R=3)  # vertex 13 sits at the origin
+    s = np.array([[0.1, 0, 0], [-0.1, 0, 0], [0, 0.2, 0], [0, -0.2, 0], [0, 0, 0.3], [0, 0, -0.3]])
+    D = orc.meanshift(g, s, 100.0)
+    assert np.allclose(D[13], 0.0, atol=1e-15)
+
+
+def test_meanshift_matches_library_softmax_and_survives_far_keys(orc):
+    """Sec. 3.3 mean-shift = softmax(-bw ||k - s||^2)-weighted mean minus k;
+    keys ~10 away would underflow exp(-100 d^2) without the common factor."""
+    rng = np.random.default_rng(27)
+    g = orc.Grid(R=3, lo=-10.0, hi=10.0)
+    s = rng.standard_normal((300, 3)) * 0.3
+    D = orc.meanshift(g, s, 100.0)
+    t = orc.lattice(g)
+    K = np.stack(np.meshgrid(t, t, t, indexing="ij"), -1).reshape(-1, 3)
+    d2 = ((K[:, None, :] - s[None]) ** 2).sum(-1)
+    ref = sps.softmax(-100.0 * d2, axis=1) @ s - K
+    assert np.all(np.isfinite(D))
+    assert np.allclose(D, ref, rtol=0, atol=1e-9)
+
+
+# ------------------------------------------------------------------ fit step
+def test_fit_step_composes_loss_gradient_and_adam(orc):
+    rng = np.random.default_rng(29)
+    R = 3
+    g = orc.Grid(R=R)
+    th = W.perturbed_theta(R, 30)
+    q = rand_q(rng, 200)
+    o = np.linalg.norm(q, axis=1) - 0.5
+    n = R ** 3 * 13
+    out = orc.fit_step(g, th, np.zeros(n), np.zeros(n), 1, q, o)
+    O, _, _ = orc.eval_global(orc.build_keys(g, th), q)
+    assert np.isclose(out["loss"], np.mean((O - o) ** 2), rtol=1e-14)
+    assert np.isclose(out["l1"], np.mean(np.abs(O - o)), rtol=1e-14)
+    gk, _ = orc.grad_global(orc.build_keys(g, th), q, 2 * (O - o) / len(q))
+    gt = orc.grad_theta(g, th, gk)
+    assert np.allclose(out["grad"], gt, rtol=1e-12, atol=1e-15)
+    # step 1 of Adam moves each parameter by lr * g / (|g| + eps)
+    step = out["theta"] - th.astype(np.float64)
+    assert np.allclose(step, -6e-4 * gt / (np.abs(gt) + 1e-8), rtol=1e-9, atol=1e-13)
+    tr = orc.fit_step(g, th, np.zeros(n), np.zeros(n), 1, q, o, mode=1, T=1e4)
+    assert np.allclose(tr["grad"], out["grad"], rtol=1e-10, atol=1e-14)
+
+
+def test_fit_step_on_exact_linear_target_is_stationary(orc):
+    rng = np.random.default_rng(31)
+    R = 3
+    g = orc.Grid(R=R)
+    b = np.array([0.5, 0.25, -0.75])
+    th = linear_theta(R, 0.125, b, seed=5)
+    keys = orc.build_keys(g, th)
+    q = rand_q(rng, 100)
+    O, _, _ = orc.eval_global(keys, q)
+    n = R ** 3 * 13
+    out = orc.fit_step(g, th, np.zeros(n), np.zeros(n), 1, q, O)
+    assert out["loss"] == 0.0
+    assert np.array_equal(out["theta"], th.astype(np.float64).reshape(out["theta"].shape))
