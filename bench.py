@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Throughput of the fused efunc fit step on one MI355X.
+
+A step is one efunc_fit_step over one minibatch of synthetic points:
+moved-key binning, query binning into lattice cells, the tile kernel
+(forward, MSE loss, dL/dO and backward with tile-level gradient flush), the
+certificate fallback, the FP64 loss reduction and AdamW.  Inputs (a small
+pool of pre-generated batches) are resident in HBM before timing starts.
+
+Default workload "csg16_r32": 32^3 x 13 float32 parameters (paper
+initialisation: rho = 7, mean-shift offsets from 16,384 surface samples),
+target = smooth union (k = 0.05) of 16 seeded spheres/boxes, 2^21 points per
+iteration (half uniform in [-1,1]^3, half surface samples + N(0, 0.01^2)).
+
+Prints one JSON line.  Roofline: the dominant kernel (the tile kernel) is
+bound by plain FP32 vector ALU work, so `achieved` is algorithmic FP32
+operations per launch divided by its event-timed average duration, against
+the non-packed FP32 lane-operation peak of the chip (see ROOFLINE_PEAK).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fit points·iters/sec (fused fwd+bwd)"
+
+# Algorithmic FP32 operations per key-query pair, counted from the arithmetic
+# each pass must do (an FMA, add, mul, sub or exp2 is one operation):
+#   forward:  x = q - c (3), |x|^2 (3), exponent fma (1), exp2 (1),
+#             f = o + x.d (3), e += l (1), m += l f (1)                 = 13
+#   backward: x (3), |x|^2 (3), exponent fma (1), exp2 (1), f (3),
+#             delta = g w (1), u = delta (f - O) (2), sums for o, d, beta
+#             (1 + 3 + 1)                                              = 19
+#             moved keys add the centre sums u x (3)                   = 22
+OPS_FWD = 13
+OPS_BWD_GRID = 19
+OPS_BWD_MOVED = 22
+# 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: one FP32 lane-operation per lane
+# per clock (packed FP32 is not used), 39.3 T lane-ops/s.
+ROOFLINE_PEAK = 256 * 4 * 16 * 2.4e9
+
+
+def kernel_source_sha() -> str:
+    src = os.path.join(ROOT, "paper_2505_21319_amd", "csrc", "efunc_kernels.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per tile-kernel launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"k_tile_fit_{workload}_pmc.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(workload, q, o, R, theta, sample):
+    """The FP64 oracle's fit step (global support, the definition) timed on a
+    bounded sample of the same batch: half uniform, half near-surface."""
+    import oracle as orc
+    J = len(q)
+    h = sample // 2
+    idx = np.concatenate([np.arange(h), J // 2 + np.arange(sample - h)])
+    qs, os_ = q[idx].astype(np.float64), o[idx].astype(np.float64)
+    g = orc.Grid(R=R)
+    n = theta.size
+    t0 = time.perf_counter()
+    orc.fit_step(g, theta, np.zeros(n), np.zeros(n), 1, qs, os_)
+    dt = time.perf_counter() - t0
+    return {"value": sample / dt, "unit": "points*iters/s", "cores": orc.threads(), "kind": "oracle",
+            "sample": f"{sample} points of iteration 0 ({h} uniform + {sample - h} near-surface), "
+                      f"one FP64 fit step with global support over all {2 * R ** 3} keys; "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="csg16_r32")
+    ap.add_argument("--batches", type=int, default=4, help="distinct resident batches cycled")
+    ap.add_argument("--cpu-sample", type=int, default=32768)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build measures one GPU only: the fused fit step "
+                                   "runs on a single device; run with --gpus 1"}))
+        sys.exit(2)
+
+    import torch
+    if args.copy_calib_mib:
+        n = args.copy_calib_mib * (1 << 20) // 4
+        a = torch.ones(n, device="cuda", dtype=torch.float32)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
+        return
+
+    import workloads as W
+    from paper_2505_21319_amd import efunc as E
+
+    dev = torch.device("cuda:0")
+    w = W.get(args.workload)
+    R, J = w.R, w.J
+    t_gen = time.perf_counter()
+    batches = []
+    for it in range(args.batches):
+        q, o = W.make_batch(w, it, device=dev)
+        batches.append((torch.from_numpy(q).to(dev), torch.from_numpy(o).to(dev)))
+    surf = W.surface_points(w, 16384, seed=W.seed_for(w, -2, "meanshift"), device=dev)
+    t_gen = time.perf_counter() - t_gen
+
+    eng = E.Engine(R, J)
+    theta = torch.empty(R, R, R, 13, device=dev, dtype=torch.float32)
+    eng.init_params(theta, torch.from_numpy(surf.astype(np.float32)).to(dev), 100.0, 7.0)
+    theta0 = theta.cpu().numpy()
+    m = torch.zeros_like(theta)
+    v = torch.zeros_like(theta)
+    loss = torch.zeros(2, device=dev, dtype=torch.float64)
+
+    step = 0
+    for _ in range(args.warmup):
+        step += 1
+        q, o = batches[step % len(batches)]
+        eng.fit_step(theta, m, v, step, q, o, loss)
+    torch.cuda.synchronize()
+
+    E.efunc_set_timing(eng.ctx, True)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step += 1
+        q, o = batches[step % len(batches)]
+        eng.fit_step(theta, m, v, step, q, o, loss)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    tile_ms, launches = E.efunc_read_timing(eng.ctx)
+    st = eng.stats()
+    lossv = loss.cpu().numpy()
+    E.efunc_set_timing(eng.ctx, False)
+
+    ms_step = total_ms / args.steps
+    value = J * args.steps / (total_ms * 1e-3)
+    tile_avg_s = tile_ms / max(launches, 1) * 1e-3
+    pairs = st["pairs"]
+    pm = st["pairs_moved"]
+    ops = pairs * OPS_FWD + (pairs - pm) * OPS_BWD_GRID + pm * OPS_BWD_MOVED
+    achieved = ops / tile_avg_s
+    traffic = measured_traffic(args.workload)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "points*iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload,
+            "R": R,
+            "params": R ** 3 * 13,
+            "points_per_iter": J,
+            "target": (f"smooth union (k=0.05) of {w.n_prims} seeded spheres/boxes"
+                       if w.shape == "csg" else "sphere r=0.5"),
+            "mix": "50% uniform in [-1,1]^3, 50% surface + N(0, 0.01^2)",
+            "init": "rho=7, zero values, mean-shift offsets (16384 surface samples, bandwidth 100)",
+            "t_cut": 20.0,
+            "resident_batches": args.batches,
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_tile<FIT>",
+            "achieved": achieved / 1e12,
+            "peak": ROOFLINE_PEAK / 1e12,
+            "unit": "Tops/s",
+            "frac": achieved / ROOFLINE_PEAK,
+            "traffic": traffic,
+            "tile_kernel_ms": tile_avg_s * 1e3,
+            "pairs_per_launch": pairs,
+            "moved_pairs_per_launch": pm,
+            "ops_per_launch": ops,
+        },
+        "stats": {"W": st["W"], "tiles": st["n_tiles"], "uncertified": st["n_uncertified"],
+                  "beta_min": st["beta_min"], "loss_mse": float(lossv[0]), "loss_l1": float(lossv[1]),
+                  "gen_seconds": t_gen, "kernel_source_sha": kernel_source_sha()},
+    }
+    if not args.no_cpu_baseline:
+        q0, o0 = (x.cpu().numpy() for x in batches[0])
+        out["cpu_baseline"] = cpu_baseline(w, q0, o0, R, theta0, args.cpu_sample)
+    eng.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

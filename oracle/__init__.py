@@ -10,10 +10,12 @@ from .oracle import (  # noqa: F401
     build_oracle,
     load,
     num_keys,
+    threads,
     lattice,
     build_keys,
     eval_global,
     eval_qgrad,
+    eval_cond,
     eval_trunc,
     grad_global,
     grad_trunc,

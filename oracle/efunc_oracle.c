@@ -9,8 +9,20 @@
 
 #include <float.h>
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
+
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 int64_t oracle_num_keys(const oracle_grid* g)
 {
@@ -111,6 +123,28 @@ void oracle_eval(const double* keys, int64_t nkeys, const double* q, int64_t J,
         if (O) O[j] = o;
         if (lse) lse[j] = l;
         if (sigma) sigma[j] = s;
+    }
+}
+
+/* Conditioning of the evaluation with respect to the logits:
+ * kappa = sum_a w_a |s_a| |f_a - O|.  A logit computed in a precision with
+ * unit roundoff u carries an error of a few u |s_a|, which moves O by about
+ * u kappa; test tolerances use it as the logit term of the error scale. */
+void oracle_eval_cond(const double* keys, int64_t nkeys, const double* q, int64_t J,
+                      double* kappa)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t j = 0; j < J; ++j) {
+        const double* qj = q + 3 * j;
+        double O, lse, sig;
+        eval_one(keys, nkeys, qj, &O, &lse, &sig);
+        double k = 0.0;
+        for (int64_t a = 0; a < nkeys; ++a) {
+            const double* kk = keys + a * ORACLE_KEY;
+            const double s = logit(kk, qj);
+            k += exp(s - lse) * fabs(s) * fabs(value(kk, qj) - O);
+        }
+        kappa[j] = k;
     }
 }
 

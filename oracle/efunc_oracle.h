@@ -51,6 +51,9 @@ typedef struct {
     int32_t raw_beta; /* 0: channels 4/12 hold ln(beta); 1: they hold beta */
 } oracle_grid;
 
+/* Number of OpenMP threads the oracle's parallel loops use. */
+int oracle_threads(void);
+
 int64_t oracle_num_keys(const oracle_grid* g);
 /* FP32 lattice coordinate t[n] as a double. */
 double oracle_lattice(const oracle_grid* g, int64_t n);
@@ -62,6 +65,11 @@ void oracle_build_keys(const oracle_grid* g, const float* theta, double* keys);
  * sigma = sum_a w_a (|o_a| + sum_k |x_k| |d_ak|).  Any output may be NULL. */
 void oracle_eval(const double* keys, int64_t nkeys, const double* q, int64_t J,
                  double* O, double* lse, double* sigma);
+
+/* Logit conditioning kappa_j = sum_a w_a |s_a| |f_a - O_j| (a tolerance scale
+ * for reduced-precision evaluations, not part of the method). */
+void oracle_eval_cond(const double* keys, int64_t nkeys, const double* q, int64_t J,
+                      double* kappa);
 
 /* Query gradient dO/dq (Eq. func-normal), global support.  dOdq: J x 3. */
 void oracle_eval_qgrad(const double* keys, int64_t nkeys, const double* q,

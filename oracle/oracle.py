@@ -65,6 +65,8 @@ def load():
         if not os.path.exists(_LIB_PATH):
             build_oracle(force=True)
         lib = C.CDLL(_LIB_PATH)
+        lib.oracle_threads.argtypes = []
+        lib.oracle_threads.restype = C.c_int
         lib.oracle_num_keys.argtypes = [_G]
         lib.oracle_num_keys.restype = _I64
         lib.oracle_lattice.argtypes = [_G, _I64]
@@ -72,6 +74,7 @@ def load():
         lib.oracle_build_keys.argtypes = [_G, _F, _D]
         lib.oracle_eval.argtypes = [_D, _I64, _D, _I64, _D, _D, _D]
         lib.oracle_eval_qgrad.argtypes = [_D, _I64, _D, _I64, _D]
+        lib.oracle_eval_cond.argtypes = [_D, _I64, _D, _I64, _D]
         lib.oracle_grad.argtypes = [_D, _I64, _D, _I64, _D, _D, _D]
         lib.oracle_grad_theta.argtypes = [_G, _F, _D, _D]
         lib.oracle_eval_trunc.argtypes = [_G, _D, _D, _I64, C.c_double, _D, _D, _D]
@@ -123,6 +126,10 @@ def _f32(a):
     return np.ascontiguousarray(a, dtype=np.float32)
 
 
+def threads() -> int:
+    return int(load().oracle_threads())
+
+
 def num_keys(g: Grid) -> int:
     gc = g.c()
     return int(load().oracle_num_keys(C.byref(gc)))
@@ -150,6 +157,14 @@ def eval_global(keys, q):
     O, lse, sig = (np.empty(J) for _ in range(3))
     load().oracle_eval(_d(keys), keys.shape[0], _d(q), J, _d(O), _d(lse), _d(sig))
     return O, lse, sig
+
+
+def eval_cond(keys, q):
+    """Logit conditioning kappa_j = sum_a w_a |s_a| |f_a - O_j| (tolerance scale)."""
+    keys, q = _f64(keys), _f64(q).reshape(-1, 3)
+    out = np.empty(q.shape[0])
+    load().oracle_eval_cond(_d(keys), keys.shape[0], _d(q), q.shape[0], _d(out))
+    return out
 
 
 def eval_qgrad(keys, q):

@@ -1,0 +1,484 @@
+// C ABI of the efunc engine (declared in include/efunc.h): argument checks,
+// workspace ownership, stream plumbing and error reporting.  No exception
+// crosses this boundary.
+#include "efunc.h"
+#include "efunc_internal.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+using namespace efunc;
+
+constexpr int MAX_TIMED = 4096;
+
+struct efunc_ctx {
+    efunc_config cfg;
+    Geo geo;
+    Work w;
+    hipStream_t last_stream;
+    int device;
+    std::vector<void*> allocs;
+    bool timing = false;
+    std::vector<hipEvent_t> ev;  // 2 * MAX_TIMED when timing has been enabled
+    int nrec = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(EFUNC_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+template <typename T>
+hipError_t dalloc(efunc_ctx* c, T** p, size_t count)
+{
+    void* q = nullptr;
+    const size_t bytes = (count ? count : 1) * sizeof(T);
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) return e;
+    c->allocs.push_back(q);
+    *p = static_cast<T*>(q);
+    return hipSuccess;
+}
+
+void free_all(efunc_ctx* c)
+{
+    for (void* p : c->allocs) (void)hipFree(p);
+    c->allocs.clear();
+}
+
+// Vertex coordinates: float32(lo + (hi - lo) n / (R - 1)), computed in double.
+std::vector<float> lattice(const efunc_config& c)
+{
+    std::vector<float> t(c.R);
+    for (int n = 0; n < c.R; ++n)
+        t[n] = (float)((double)c.lo + ((double)c.hi - (double)c.lo) * (double)n / (double)(c.R - 1));
+    return t;
+}
+
+int check_ctx(efunc_ctx* ctx)
+{
+    if (!ctx) return fail(EFUNC_EINVAL, "ctx is NULL");
+    return EFUNC_OK;
+}
+
+int check_J(efunc_ctx* ctx, int64_t J)
+{
+    if (J < 0) return fail(EFUNC_EINVAL, "J = %lld < 0", (long long)J);
+    if (J > ctx->w.max_points)
+        return fail(EFUNC_ESIZE, "J = %lld exceeds max_points = %lld of the context", (long long)J,
+                    (long long)ctx->w.max_points);
+    return EFUNC_OK;
+}
+
+int check_ptr(const void* p, const char* name, size_t align)
+{
+    if (!p) return fail(EFUNC_EINVAL, "%s is NULL", name);
+    if (!aligned(p, align)) return fail(EFUNC_EINVAL, "%s is not %zu-byte aligned", name, align);
+    return EFUNC_OK;
+}
+
+int check_opt(const void* p, const char* name, size_t align)
+{
+    if (p && !aligned(p, align)) return fail(EFUNC_EINVAL, "%s is not %zu-byte aligned", name, align);
+    return EFUNC_OK;
+}
+
+Problem base_problem(efunc_ctx* ctx)
+{
+    Problem p;
+    memset(&p, 0, sizeof(p));
+    p.g = ctx->geo;
+    p.offsets = ctx->cfg.offsets;
+    p.T = ctx->cfg.t_cut;
+    p.window = ctx->cfg.window;
+    if (ctx->timing && ctx->nrec < MAX_TIMED) {
+        p.ev_start = ctx->ev[2 * ctx->nrec];
+        p.ev_stop = ctx->ev[2 * ctx->nrec + 1];
+        ctx->nrec++;
+    }
+    return p;
+}
+
+void destroy_events(efunc_ctx* c)
+{
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    c->ev.clear();
+    c->timing = false;
+    c->nrec = 0;
+}
+
+// With check_finite, synchronise and read the non-finite counter of the key
+// preparation (and scan the queries on the host side of the same sync).
+int finite_check(efunc_ctx* ctx, hipStream_t s, const float* q, int64_t J)
+{
+    if (!ctx->cfg.check_finite) return EFUNC_OK;
+    DevStats st;
+    hipError_t e = hipMemcpyAsync(&st, ctx->w.st, sizeof(st), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "check_finite readback");
+    if (st.nonfinite) return fail(EFUNC_ENONFINITE, "%d non-finite parameters", st.nonfinite);
+    if (q && J > 0) {
+        std::vector<float> h(3 * (size_t)J);
+        e = hipMemcpy(h.data(), q, h.size() * sizeof(float), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "check_finite query readback");
+        for (float x : h)
+            if (!isfinite(x)) return fail(EFUNC_ENONFINITE, "non-finite query coordinate");
+    }
+    return EFUNC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void efunc_default_config(efunc_config* cfg, int32_t R)
+{
+    if (!cfg) return;
+    cfg->R = R;
+    cfg->lo = -1.0f;
+    cfg->hi = 1.0f;
+    cfg->offsets = 1;
+    cfg->t_cut = 20.0f;
+    cfg->window = 0;
+    cfg->deterministic = 0;
+    cfg->check_finite = 0;
+}
+
+void efunc_default_adam(efunc_adam* a)
+{
+    if (!a) return;
+    a->lr = 6e-4f;
+    a->beta1 = 0.9f;
+    a->beta2 = 0.999f;
+    a->eps = 1e-8f;
+    a->weight_decay = 0.0f;
+}
+
+const char* efunc_last_error(void) { return g_err.c_str(); }
+
+int efunc_create(const efunc_config* cfg, int64_t max_points, efunc_ctx** out)
+{
+    g_err.clear();
+    if (!out) return fail(EFUNC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!cfg) return fail(EFUNC_EINVAL, "cfg is NULL");
+    if (cfg->R < 2 || cfg->R > 1024) return fail(EFUNC_EINVAL, "R = %d outside [2, 1024]", cfg->R);
+    if (!(cfg->lo < cfg->hi) || !isfinite(cfg->lo) || !isfinite(cfg->hi))
+        return fail(EFUNC_EINVAL, "lattice bounds must satisfy lo < hi, finite");
+    if (cfg->offsets != 0 && cfg->offsets != 1) return fail(EFUNC_EINVAL, "offsets must be 0 or 1");
+    if (!(cfg->t_cut > 0.0f) || !isfinite(cfg->t_cut)) return fail(EFUNC_EINVAL, "t_cut must be > 0");
+    if (cfg->window < 0 || cfg->window > WMAX)
+        return fail(EFUNC_EINVAL, "window = %d outside [0, %d]", cfg->window, WMAX);
+    if (cfg->deterministic != 0) return fail(EFUNC_EUNSUPPORTED, "deterministic mode is not built");
+    if (max_points < 0 || max_points > (int64_t)INT32_MAX - PMAX)
+        return fail(EFUNC_EINVAL, "max_points = %lld outside [0, 2^31 - %d)", (long long)max_points, PMAX);
+
+    efunc_ctx* c = new (std::nothrow) efunc_ctx();
+    if (!c) return fail(EFUNC_EINVAL, "out of host memory");
+    c->cfg = *cfg;
+    c->last_stream = nullptr;
+    hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(e, "hipGetDevice");
+    }
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, c->device);
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(e, "hipGetDeviceProperties");
+    }
+
+    const int64_t R = cfg->R, I = R * R * R, C1 = R - 1, C = C1 * C1 * C1;
+    const int64_t mp = max_points > 0 ? max_points : 1;
+    Work& w = c->w;
+    w.I = I;
+    w.C = C;
+    w.max_points = max_points;
+    w.max_tiles = mp / PMAX + (C < mp ? C : mp) + 1;
+    w.num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
+    const int64_t nblk = (C + 1 + SCAN_TILE - 1) / SCAN_TILE;
+
+    hipError_t err = hipSuccess;
+#define ALLOC(ptr, n) \
+    if (err == hipSuccess) err = dalloc(c, &(ptr), (size_t)(n))
+    ALLOC(w.tlat, R);
+    ALLOC(w.gk, 2 * I);
+    ALLOC(w.mcell, I);
+    ALLOC(w.mrank, I);
+    ALLOC(w.mcount, C);
+    ALLOC(w.mstart, C + 1);
+    ALLOC(w.mrec, 3 * I);
+    ALLOC(w.mk, 3 * I);
+    ALLOC(w.pcell, mp);
+    ALLOC(w.prank, mp);
+    ALLOC(w.pcount, C);
+    ALLOC(w.pstart, C + 1);
+    ALLOC(w.tstart, C + 1);
+    ALLOC(w.tiles, w.max_tiles);
+    ALLOC(w.ps, mp);
+    ALLOC(w.pv, mp);
+    ALLOC(w.pidx, mp);
+    ALLOC(w.fb, mp);
+    ALLOC(w.lpart, w.max_tiles);
+    ALLOC(w.scan_blk, 2 * nblk + 2);
+    ALLOC(w.grad, NCH * I);
+    ALLOC(w.st, 1);
+#undef ALLOC
+    if (err != hipSuccess) {
+        free_all(c);
+        delete c;
+        return hip_fail(err, "hipMalloc of the workspace");
+    }
+    const std::vector<float> t = lattice(*cfg);
+    err = hipMemcpy(w.tlat, t.data(), sizeof(float) * R, hipMemcpyHostToDevice);
+    if (err == hipSuccess) err = hipMemset(w.grad, 0, sizeof(float) * NCH * I);
+    if (err == hipSuccess) err = hipMemset(w.st, 0, sizeof(DevStats));
+    if (err == hipSuccess) err = hipDeviceSynchronize();
+    if (err != hipSuccess) {
+        free_all(c);
+        delete c;
+        return hip_fail(err, "workspace initialisation");
+    }
+    Geo& g = c->geo;
+    g.R = (int)R;
+    g.C1 = (int)C1;
+    g.lo = cfg->lo;
+    g.hi = cfg->hi;
+    g.lo_d = cfg->lo;
+    g.h_d = ((double)cfg->hi - (double)cfg->lo) / (double)C1;
+    g.inv_h_d = 1.0 / g.h_d;
+    g.h = (float)g.h_d;
+    g.inv_h = (float)g.inv_h_d;
+    g.tlat = w.tlat;
+    *out = c;
+    return EFUNC_OK;
+}
+
+int efunc_destroy(efunc_ctx* ctx)
+{
+    g_err.clear();
+    if (!ctx) return EFUNC_OK;
+    hipError_t e = hipDeviceSynchronize();
+    destroy_events(ctx);
+    free_all(ctx);
+    delete ctx;
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize in destroy");
+    return EFUNC_OK;
+}
+
+int efunc_init_params(efunc_ctx* ctx, float* theta, const float* surf, int64_t Ns,
+                      float bandwidth, float rho0, void* stream)
+{
+    g_err.clear();
+    int rc;
+    if ((rc = check_ctx(ctx))) return rc;
+    if ((rc = check_ptr(theta, "theta", 4))) return rc;
+    if (Ns < 0) return fail(EFUNC_EINVAL, "Ns < 0");
+    if (Ns > 0 && (rc = check_ptr(surf, "surf", 4))) return rc;
+    if (!(bandwidth > 0.0f) || !isfinite(bandwidth)) return fail(EFUNC_EINVAL, "bandwidth must be > 0");
+    if (!isfinite(rho0)) return fail(EFUNC_EINVAL, "rho0 must be finite");
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last_stream = s;
+    hipError_t e = run_init_params(ctx->w, ctx->geo, theta, surf, Ns, bandwidth, rho0, s);
+    if (e != hipSuccess) return hip_fail(e, "init_params launch");
+    return EFUNC_OK;
+}
+
+int efunc_eval(efunc_ctx* ctx, const float* theta, const float* q, int64_t J, float* O,
+               float* lse, float* dOdq, int64_t* n_uncertified, void* stream)
+{
+    g_err.clear();
+    int rc;
+    if ((rc = check_ctx(ctx))) return rc;
+    if ((rc = check_J(ctx, J))) return rc;
+    if ((rc = check_opt(lse, "lse", 4)) || (rc = check_opt(dOdq, "dOdq", 4)) ||
+        (rc = check_opt(n_uncertified, "n_uncertified", 8)))
+        return rc;
+    if (J == 0) return EFUNC_OK;
+    if ((rc = check_ptr(theta, "theta", 4)) || (rc = check_ptr(q, "q", 4)) ||
+        (rc = check_ptr(O, "O", 4)))
+        return rc;
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last_stream = s;
+    Problem p = base_problem(ctx);
+    p.J = J;
+    p.theta = theta;
+    p.q = q;
+    p.O_out = O;
+    p.lse_out = lse;
+    p.dOdq_out = dOdq;
+    p.grad = ctx->w.grad;
+    hipError_t e = run_tiles(ctx->w, p, MODE_EVAL, s);
+    if (e == hipSuccess && n_uncertified) e = run_count_uncertified(ctx->w, n_uncertified, s);
+    if (e != hipSuccess) return hip_fail(e, "eval launch");
+    return finite_check(ctx, s, q, J);
+}
+
+int efunc_grad(efunc_ctx* ctx, const float* theta, const float* q, const float* O,
+               const float* lse, const float* dLdO, int64_t J, float* grad, void* stream)
+{
+    g_err.clear();
+    int rc;
+    if ((rc = check_ctx(ctx))) return rc;
+    if ((rc = check_J(ctx, J))) return rc;
+    if (J == 0) return EFUNC_OK;
+    if ((rc = check_ptr(theta, "theta", 4)) || (rc = check_ptr(q, "q", 4)) ||
+        (rc = check_ptr(O, "O", 4)) || (rc = check_ptr(lse, "lse", 4)) ||
+        (rc = check_ptr(dLdO, "dLdO", 4)) || (rc = check_ptr(grad, "grad", 4)))
+        return rc;
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last_stream = s;
+    Problem p = base_problem(ctx);
+    p.J = J;
+    p.theta = theta;
+    p.q = q;
+    p.aux = dLdO;
+    p.O_in = O;
+    p.lse_in = lse;
+    p.grad = grad;
+    hipError_t e = run_tiles(ctx->w, p, MODE_GRAD, s);
+    if (e != hipSuccess) return hip_fail(e, "grad launch");
+    return finite_check(ctx, s, q, J);
+}
+
+int efunc_fit_step(efunc_ctx* ctx, float* theta, float* m, float* v, int64_t step,
+                   const efunc_adam* adam, const float* q, const float* o, int64_t J,
+                   double* loss_out, void* stream)
+{
+    g_err.clear();
+    int rc;
+    if ((rc = check_ctx(ctx))) return rc;
+    if ((rc = check_J(ctx, J))) return rc;
+    if (step < 1) return fail(EFUNC_EINVAL, "step = %lld < 1", (long long)step);
+    if ((rc = check_opt(loss_out, "loss_out", 8))) return rc;
+    if (J == 0) return EFUNC_OK;
+    if ((rc = check_ptr(theta, "theta", 4)) || (rc = check_ptr(m, "m", 4)) ||
+        (rc = check_ptr(v, "v", 4)) || (rc = check_ptr(q, "q", 4)) || (rc = check_ptr(o, "o", 4)))
+        return rc;
+    efunc_adam hp;
+    if (adam) hp = *adam; else efunc_default_adam(&hp);
+    if (!(hp.lr >= 0.0f) || !(hp.beta1 >= 0.0f && hp.beta1 < 1.0f) ||
+        !(hp.beta2 >= 0.0f && hp.beta2 < 1.0f) || !(hp.eps > 0.0f) || !(hp.weight_decay >= 0.0f))
+        return fail(EFUNC_EINVAL, "invalid Adam hyper-parameters");
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last_stream = s;
+    Problem p = base_problem(ctx);
+    p.J = J;
+    p.theta = theta;
+    p.q = q;
+    p.aux = o;
+    p.grad = ctx->w.grad;
+    hipError_t e = run_tiles(ctx->w, p, MODE_FIT, s);
+    if (e == hipSuccess && loss_out) e = run_loss_finalize(ctx->w, J, loss_out, s);
+    if (e != hipSuccess) return hip_fail(e, "fit_step launch");
+    if ((rc = finite_check(ctx, s, q, J))) {
+        // leave the internal gradient clean for the next call
+        (void)run_zero_floats(ctx->w.grad, (int64_t)NCH * ctx->w.I, s);
+        return rc;
+    }
+    const double bc1 = 1.0 - pow((double)hp.beta1, (double)step);
+    const double bc2 = 1.0 - pow((double)hp.beta2, (double)step);
+    e = run_adam(ctx->w, theta, m, v, (int64_t)NCH * ctx->w.I, hp.lr, hp.beta1, hp.beta2, hp.eps,
+                 hp.weight_decay, (float)bc1, (float)bc2, s);
+    if (e != hipSuccess) return hip_fail(e, "adam launch");
+    return EFUNC_OK;
+}
+
+int efunc_get_stats(efunc_ctx* ctx, efunc_stats* out)
+{
+    g_err.clear();
+    int rc;
+    if ((rc = check_ctx(ctx))) return rc;
+    if (!out) return fail(EFUNC_EINVAL, "out is NULL");
+    DevStats st;
+    int ntiles = 0;
+    hipStream_t s = ctx->last_stream;
+    hipError_t e = hipMemcpyAsync(&st, ctx->w.st, sizeof(st), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&ntiles, ctx->w.tstart + ctx->w.C, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "stats readback");
+    out->W = st.W;
+    out->n_tiles = ntiles;
+    out->n_uncertified = st.nfb;
+    out->pairs = (int64_t)st.pairs;
+    out->pairs_moved = (int64_t)st.pairs_moved;
+    uint32_t b = st.bmin_bits, gb = st.bgmax_bits;
+    memcpy(&out->beta_min, &b, 4);
+    memcpy(&out->beta_grid_max, &gb, 4);
+    out->n_nonfinite = st.nonfinite;
+    return EFUNC_OK;
+}
+
+int efunc_set_timing(efunc_ctx* ctx, int32_t enable)
+{
+    g_err.clear();
+    int rc;
+    if ((rc = check_ctx(ctx))) return rc;
+    if (!enable) {
+        hipError_t e = hipDeviceSynchronize();
+        destroy_events(ctx);
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+        return EFUNC_OK;
+    }
+    if (ctx->ev.empty()) {
+        ctx->ev.resize(2 * MAX_TIMED);
+        for (auto& e : ctx->ev) {
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) {
+                e = nullptr;
+                destroy_events(ctx);
+                return hip_fail(r, "hipEventCreate");
+            }
+        }
+    }
+    ctx->timing = true;
+    ctx->nrec = 0;
+    return EFUNC_OK;
+}
+
+int efunc_read_timing(efunc_ctx* ctx, double* tile_ms, int64_t* launches)
+{
+    g_err.clear();
+    int rc;
+    if ((rc = check_ctx(ctx))) return rc;
+    if (!tile_ms || !launches) return fail(EFUNC_EINVAL, "NULL output");
+    double tot = 0.0;
+    for (int i = 0; i < ctx->nrec; ++i) {
+        hipError_t e = hipEventSynchronize(ctx->ev[2 * i + 1]);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ctx->ev[2 * i], ctx->ev[2 * i + 1]);
+        if (e != hipSuccess) return hip_fail(e, "event timing");
+        tot += ms;
+    }
+    *tile_ms = tot;
+    *launches = ctx->nrec;
+    ctx->nrec = 0;
+    return EFUNC_OK;
+}
+
+}  // extern "C"

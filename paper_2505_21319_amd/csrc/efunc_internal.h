@@ -1,0 +1,109 @@
+// Internal declarations shared by the efunc HIP kernels and the C-ABI host
+// code.  Not part of the public interface (include/efunc.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace efunc {
+
+constexpr int NCH = 13;
+constexpr int BLOCK = 256;      // threads per workgroup (4 wave64)
+constexpr int PMAX = 256;       // queries per tile
+constexpr int KC = 256;         // keys per LDS chunk
+constexpr int MAXSEG = 1024;    // moved-key row segments per window ((2W+1)^2, W <= 15)
+constexpr int WMAX = 15;        // largest window half-width
+constexpr int SCAN_TILE = 1024; // elements per block in the prefix scans
+constexpr float LOG2E = 1.4426950408889634f;
+constexpr float LN2 = 0.6931471805599453f;
+
+// Per-context device statistics and counters (one instance in device memory).
+struct DevStats {
+    unsigned int bmin_bits;   // min beta over all keys (positive float bits)
+    unsigned int bgmax_bits;  // max beta over grid keys
+    int W;                    // window half-width of this call
+    int queue;                // tile work-queue head
+    int nfb;                  // queries appended to the fallback list
+    int fbqueue;              // fallback work-queue head
+    int nonfinite;            // non-finite parameters seen by the key preparation
+    int pad;
+    unsigned long long pairs; // key-query pairs in windows
+    unsigned long long pairs_moved;  // of which with moved keys
+    double fb_loss[2];        // loss sums of fallback queries
+};
+
+// Lattice geometry passed by value to every kernel.
+struct Geo {
+    int R;         // vertices per axis
+    int C1;        // cells per axis = R - 1
+    float lo, hi;
+    float h, inv_h;
+    double lo_d, h_d, inv_h_d;
+    const float* tlat;  // [R] float32 vertex coordinates
+};
+
+// Device workspace owned by a context.
+struct Work {
+    int64_t I, C, max_points, max_tiles;
+    float* tlat;          // [R]
+    float4* gk;           // [2 I]  grid key records {nb, o, d.x, d.y}, {d.z, beta, 0, 0}
+    int* mcell;           // [I]    cell of each moved key
+    int* mrank;           // [I]    rank inside its cell
+    int* mcount;          // [C]
+    int* mstart;          // [C+1]
+    float4* mrec;         // [3 I]  moved key records by vertex
+    float4* mk;           // [3 I]  moved key records binned by cell:
+                          //        {c_hi.xyz, nb}, {o', d'.xyz}, {c_lo.xyz, vid bits}
+    int* pcell;           // [max_points]
+    int* prank;           // [max_points]
+    int* pcount;          // [C]
+    int* pstart;          // [C+1]
+    int* tstart;          // [C+1]
+    int4* tiles;          // [max_tiles]  {cell, first, count, 0}
+    float4* ps;           // [max_points] {q.xyz, aux}
+    float4* pv;           // [max_points] {O, lse, 0, 0} (backward inputs)
+    int* pidx;            // [max_points] original query index
+    int* fb;              // [max_points] fallback list (sorted query positions)
+    double2* lpart;       // [max_tiles]  per-tile loss sums
+    int* scan_blk;        // [2 * ceil((C+1)/SCAN_TILE) + 2] scan block sums
+    float* grad;          // [13 I] internal gradient of efunc_fit_step (kept zero)
+    DevStats* st;
+    int num_cu;
+};
+
+enum Mode { MODE_FIT = 0, MODE_EVAL = 1, MODE_GRAD = 2 };
+
+struct Problem {
+    Geo g;
+    int offsets;
+    float T;            // truncation threshold (nats)
+    int window;         // forced W (0 = auto)
+    int64_t J;
+    // inputs
+    const float* theta;
+    const float* q;
+    const float* aux;   // FIT: targets o; GRAD: dL/dO
+    const float* O_in;  // GRAD
+    const float* lse_in;// GRAD
+    // outputs
+    float* O_out;       // EVAL
+    float* lse_out;     // EVAL (optional)
+    float* dOdq_out;    // EVAL (optional)
+    float* grad;        // FIT: internal; GRAD: caller's (accumulated)
+    // optional events recorded around the tile kernel
+    hipEvent_t ev_start, ev_stop;
+};
+
+// Enqueue the shared front end (key preparation and binning, query binning,
+// tiles) and then the mode's tile and fallback kernels.  Returns a HIP error.
+hipError_t run_tiles(const Work& w, const Problem& p, Mode mode, hipStream_t s);
+hipError_t run_loss_finalize(const Work& w, int64_t J, double* loss_out, hipStream_t s);
+hipError_t run_adam(const Work& w, float* theta, float* m, float* v, int64_t n, float lr,
+                    float beta1, float beta2, float eps, float wd, float bc1, float bc2,
+                    hipStream_t s);
+hipError_t run_init_params(const Work& w, const Geo& g, float* theta, const float* surf,
+                           int64_t Ns, float bandwidth, float rho0, hipStream_t s);
+hipError_t run_count_uncertified(const Work& w, int64_t* out, hipStream_t s);
+hipError_t run_zero_floats(float* p, int64_t n, hipStream_t s);
+
+}  // namespace efunc

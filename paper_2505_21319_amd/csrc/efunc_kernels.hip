@@ -1,0 +1,1224 @@
+// efunc HIP kernels for gfx950 (wave64).
+//
+// One call runs: key preparation and moved-key binning, query binning into
+// lattice cells, tile construction, the tile kernel (forward of Alg. 1 with a
+// reference-shifted exponent, the MSE loss of Eq. loss, and the key-parallel
+// backward of Alg. 2 over the tile's queries), the fallback kernel for
+// queries whose window certificate fails, and for fitting the loss
+// reduction and AdamW.
+//
+// Window.  A tile is the set (or a balanced slice of at most PMAX) of queries
+// in one lattice cell (cx, cy, cz).  Its keys are the grid vertices with
+// indices in [c - W + 1, c + W] per axis and the moved keys binned into cells
+// [c - W, c + W] per axis.  Every key outside lies at least W h away from any
+// query in the cell, and beyond the window box faces in general; a query is
+// certified when even the widest excluded key (smallest beta) at the nearest
+// face has weight below exp(-T), otherwise it is re-evaluated against all
+// keys by the fallback kernel.
+#include "efunc_internal.h"
+
+#include <math.h>
+
+namespace efunc {
+
+__device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ float wave_max(float v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Sum over the workgroup; every thread gets the total.  sh: BLOCK/64 slots.
+template <typename T>
+__device__ T block_sum(T v, T* sh)
+{
+    v = wave_sum(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    T r = 0;
+#pragma unroll
+    for (int i = 0; i < BLOCK / 64; ++i) r += sh[i];
+    return r;
+}
+
+__device__ float block_max(float v, float* sh)
+{
+    v = wave_max(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    float r = -INFINITY;
+#pragma unroll
+    for (int i = 0; i < BLOCK / 64; ++i) r = fmaxf(r, sh[i]);
+    return r;
+}
+
+// Exclusive scan over the workgroup; *total receives the sum.  sh: BLOCK/64 slots.
+__device__ int block_excl_scan(int v, int* sh, int* total)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int inc = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int u = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += u;
+    }
+    __syncthreads();
+    if (lane == 63) sh[wid] = inc;
+    __syncthreads();
+    int before = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < BLOCK / 64; ++i) {
+        before += (i < wid) ? sh[i] : 0;
+        tot += sh[i];
+    }
+    *total = tot;
+    return before + inc - v;
+}
+
+__device__ __forceinline__ int cell_of(float x, const Geo& g)
+{
+    const float u = (x - g.lo) * g.inv_h;
+    if (!(u >= 1.0f)) return 0;  // also catches NaN
+    if (u >= (float)(g.C1 - 1)) return g.C1 - 1;
+    return (int)u;
+}
+
+// ---------------------------------------------------------------- utilities
+__global__ void k_fill_int(int* __restrict__ p, int64_t n, int v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_float(float* __restrict__ p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0f;
+}
+
+__global__ void k_reset_stats(DevStats* st)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->bmin_bits = 0x7f800000u;  // +inf
+        st->bgmax_bits = 0u;
+        st->W = 1;
+        st->queue = 0;
+        st->nfb = 0;
+        st->fbqueue = 0;
+        st->nonfinite = 0;
+        st->pad = 0;
+        st->pairs = 0ull;
+        st->pairs_moved = 0ull;
+        st->fb_loss[0] = 0.0;
+        st->fb_loss[1] = 0.0;
+    }
+}
+
+// --------------------------------------------------------- key preparation
+// Per vertex: the grid key record, the moved key centre k_i + Delta_i split
+// into float hi + lo parts, its (clamped) cell, and scale statistics.
+__global__ __launch_bounds__(BLOCK) void k_prep_keys(
+    const float* __restrict__ theta, Geo g, int offsets, int64_t I, float4* __restrict__ gk,
+    float4* __restrict__ mrec, int* __restrict__ mcell, int* __restrict__ mrank,
+    int* __restrict__ mcount, DevStats* __restrict__ st)
+{
+    __shared__ float sh_f[BLOCK / 64];
+    __shared__ int sh_i[BLOCK / 64];
+    const int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
+    float bmin = INFINITY, bgmax = 0.0f;
+    int nonfinite = 0;
+    if (i < I) {
+        const float* p = theta + i * NCH;
+        float v[NCH];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            v[c] = p[c];
+            nonfinite += isfinite(v[c]) ? 0 : 1;
+        }
+        const float beta = expf(v[4]);
+        gk[2 * i] = make_float4(-beta * LOG2E, v[0], v[1], v[2]);
+        gk[2 * i + 1] = make_float4(v[3], beta, 0.0f, 0.0f);
+        bmin = beta;
+        bgmax = beta;
+        if (offsets) {
+            const int R = g.R;
+            const int ix = (int)(i / ((int64_t)R * R)), iy = (int)((i / R) % R), iz = (int)(i % R);
+            const double c[3] = {(double)g.tlat[ix] + (double)v[5], (double)g.tlat[iy] + (double)v[6],
+                                 (double)g.tlat[iz] + (double)v[7]};
+            int m[3];
+            float hi[3], lo[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double u = (c[d] - g.lo_d) * g.inv_h_d;
+                m[d] = !(u >= 1.0) ? 0 : (u >= (double)(g.C1 - 1) ? g.C1 - 1 : (int)u);
+                hi[d] = (float)c[d];
+                lo[d] = (float)(c[d] - (double)hi[d]);
+            }
+            const float beta2 = expf(v[12]);
+            mrec[3 * i] = make_float4(hi[0], hi[1], hi[2], -beta2 * LOG2E);
+            mrec[3 * i + 1] = make_float4(v[8], v[9], v[10], v[11]);
+            mrec[3 * i + 2] = make_float4(lo[0], lo[1], lo[2], __int_as_float((int)i));
+            const int cell = (m[0] * g.C1 + m[1]) * g.C1 + m[2];
+            mcell[i] = cell;
+            mrank[i] = atomicAdd(&mcount[cell], 1);
+            bmin = fminf(bmin, beta2);
+        }
+    }
+    // reductions: min beta, max grid beta, non-finite count
+    float r = bmin;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) r = fminf(r, __shfl_xor(r, off, 64));
+    if ((threadIdx.x & 63) == 0) sh_f[threadIdx.x >> 6] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float mn = sh_f[0];
+        for (int k = 1; k < BLOCK / 64; ++k) mn = fminf(mn, sh_f[k]);
+        if (mn >= 0.0f) atomicMin(&st->bmin_bits, __float_as_uint(mn));
+    }
+    __syncthreads();
+    const float mx = wave_max(bgmax);
+    if ((threadIdx.x & 63) == 0) sh_f[threadIdx.x >> 6] = mx;
+    const int nf = wave_sum(nonfinite);
+    if ((threadIdx.x & 63) == 0) sh_i[threadIdx.x >> 6] = nf;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float m2 = sh_f[0];
+        int n2 = sh_i[0];
+        for (int k = 1; k < BLOCK / 64; ++k) {
+            m2 = fmaxf(m2, sh_f[k]);
+            n2 += sh_i[k];
+        }
+        if (m2 > 0.0f) atomicMax(&st->bgmax_bits, __float_as_uint(m2));
+        if (n2) atomicAdd(&st->nonfinite, n2);
+    }
+}
+
+// Window half-width from the scale statistics: the smallest W >= 1 with
+// beta_min (W h)^2 >= T + beta_grid_max (3/4) h^2, so that every query inside
+// the lattice passes its certificate (its nearest vertex is within sqrt(3)/2 h).
+__global__ void k_window(DevStats* st, Geo g, float T, int Wforce)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int W;
+    if (Wforce > 0) {
+        W = Wforce;
+    } else {
+        const double bmin = (double)__uint_as_float(st->bmin_bits);
+        const double bg = (double)__uint_as_float(st->bgmax_bits);
+        const double need = (double)T + bg * 0.75 * g.h_d * g.h_d * (1.0 + 1e-4) + 1e-6;
+        const double wd = sqrt(need / bmin) / g.h_d;
+        W = (wd == wd && wd < (double)WMAX) ? (int)ceil(wd) : WMAX;
+        if (W < 1) W = 1;
+    }
+    if (W > WMAX) W = WMAX;
+    st->W = W;
+}
+
+// --------------------------------------------------------------- prefix scan
+// Exclusive scans of per-cell counts (and, with TILES, of per-cell tile
+// counts ceil(count / PMAX)).  Three phases: block sums, one-block scan of
+// the block sums, block-local scans plus offsets.
+template <bool TILES>
+__global__ __launch_bounds__(BLOCK) void k_scan_reduce(const int* __restrict__ cnt, int64_t n,
+                                                       int* __restrict__ blk)
+{
+    __shared__ int sh[BLOCK / 64];
+    const int64_t base = blockIdx.x * (int64_t)SCAN_TILE;
+    int sx = 0, sy = 0;
+    for (int k = threadIdx.x; k < SCAN_TILE; k += BLOCK) {
+        const int64_t i = base + k;
+        if (i < n) {
+            const int c = cnt[i];
+            sx += c;
+            if (TILES) sy += (c + PMAX - 1) / PMAX;
+        }
+    }
+    sx = block_sum(sx, sh);
+    sy = block_sum(sy, sh);
+    if (threadIdx.x == 0) {
+        blk[2 * blockIdx.x] = sx;
+        blk[2 * blockIdx.x + 1] = sy;
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scan_blocks(int* __restrict__ blk, int nb)
+{
+    __shared__ int sh[BLOCK / 64];
+    int carry_x = 0, carry_y = 0;
+    for (int base = 0; base < nb; base += BLOCK) {
+        const int i = base + threadIdx.x;
+        const int x = i < nb ? blk[2 * i] : 0;
+        const int y = i < nb ? blk[2 * i + 1] : 0;
+        int tx, ty;
+        const int ex = block_excl_scan(x, sh, &tx);
+        const int ey = block_excl_scan(y, sh, &ty);
+        if (i < nb) {
+            blk[2 * i] = carry_x + ex;
+            blk[2 * i + 1] = carry_y + ey;
+        }
+        carry_x += tx;
+        carry_y += ty;
+    }
+    if (threadIdx.x == 0) {
+        blk[2 * nb] = carry_x;
+        blk[2 * nb + 1] = carry_y;
+    }
+}
+
+template <bool TILES>
+__global__ __launch_bounds__(BLOCK) void k_scan_apply(const int* __restrict__ cnt, int64_t n,
+                                                      const int* __restrict__ blk, int nb,
+                                                      int* __restrict__ start, int* __restrict__ tstart)
+{
+    __shared__ int sh[BLOCK / 64];
+    constexpr int PER = SCAN_TILE / BLOCK;
+    const int64_t base = blockIdx.x * (int64_t)SCAN_TILE + threadIdx.x * (int64_t)PER;
+    int cx[PER], cy[PER];
+    int sx = 0, sy = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int64_t i = base + k;
+        const int c = i < n ? cnt[i] : 0;
+        cx[k] = c;
+        cy[k] = TILES ? (c + PMAX - 1) / PMAX : 0;
+        sx += cx[k];
+        sy += cy[k];
+    }
+    int tx, ty;
+    int ox = block_excl_scan(sx, sh, &tx) + blk[2 * blockIdx.x];
+    int oy = TILES ? block_excl_scan(sy, sh, &ty) + blk[2 * blockIdx.x + 1] : 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int64_t i = base + k;
+        if (i < n) {
+            start[i] = ox;
+            if (TILES) tstart[i] = oy;
+        }
+        ox += cx[k];
+        oy += cy[k];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        start[n] = blk[2 * nb];
+        if (TILES) tstart[n] = blk[2 * nb + 1];
+    }
+}
+
+__global__ void k_scatter_keys(int64_t I, const int* __restrict__ mcell, const int* __restrict__ mrank,
+                               const int* __restrict__ mstart, const float4* __restrict__ mrec,
+                               float4* __restrict__ mk)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= I) return;
+    const int64_t pos = (int64_t)mstart[mcell[i]] + mrank[i];
+    mk[3 * pos] = mrec[3 * i];
+    mk[3 * pos + 1] = mrec[3 * i + 1];
+    mk[3 * pos + 2] = mrec[3 * i + 2];
+}
+
+// ------------------------------------------------------------ query binning
+__global__ void k_count_points(const float* __restrict__ q, int64_t J, Geo g, int* __restrict__ pcell,
+                               int* __restrict__ prank, int* __restrict__ pcount)
+{
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= J) return;
+    const int c = (cell_of(q[3 * j], g) * g.C1 + cell_of(q[3 * j + 1], g)) * g.C1 +
+                  cell_of(q[3 * j + 2], g);
+    pcell[j] = c;
+    prank[j] = atomicAdd(&pcount[c], 1);
+}
+
+__global__ void k_scatter_points(const float* __restrict__ q, const float* __restrict__ aux,
+                                 const float* __restrict__ Oin, const float* __restrict__ lsein,
+                                 int64_t J, const int* __restrict__ pcell,
+                                 const int* __restrict__ prank, const int* __restrict__ pstart,
+                                 float4* __restrict__ ps, float4* __restrict__ pv,
+                                 int* __restrict__ pidx)
+{
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= J) return;
+    const int64_t pos = (int64_t)pstart[pcell[j]] + prank[j];
+    ps[pos] = make_float4(q[3 * j], q[3 * j + 1], q[3 * j + 2], aux ? aux[j] : 0.0f);
+    if (Oin) pv[pos] = make_float4(Oin[j], lsein[j], 0.0f, 0.0f);
+    pidx[pos] = (int)j;
+}
+
+// Balanced slices of at most PMAX queries per non-empty cell.
+__global__ void k_build_tiles(int64_t C, const int* __restrict__ pcount, const int* __restrict__ pstart,
+                              const int* __restrict__ tstart, int4* __restrict__ tiles)
+{
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    const int n = pcount[c];
+    if (n == 0) return;
+    const int t0 = tstart[c], nt = tstart[c + 1] - t0;
+    for (int k = 0; k < nt; ++k) {
+        const int a = (int)((int64_t)k * n / nt), b = (int)((int64_t)(k + 1) * n / nt);
+        tiles[t0 + k] = make_int4((int)c, pstart[c] + a, b - a, 0);
+    }
+}
+
+// ------------------------------------------------------------------ tiles
+struct TileArgs {
+    Geo g;
+    int offsets;
+    float T2;      // T log2(e)
+    float two_over_J;
+    const float4* gk;
+    const float4* mk;
+    const int* mstart;
+    const float4* ps;
+    const float4* pv;
+    const int* pidx;
+    const int4* tiles;
+    const int* ntiles;  // &tstart[C]
+    int* fb;
+    double2* lpart;
+    DevStats* st;
+    float* O_out;
+    float* lse_out;
+    float* dOdq_out;
+    float* grad;
+    int64_t I;
+};
+
+struct TileSmem {
+    float4 kc[KC];        // key centre relative to the tile origin, nb = -beta log2(e)
+    float4 kv[KC];        // o, d.xyz
+    int kid[KC];          // vertex index
+    float4 pq[PMAX];      // query relative to the tile origin, aux (target or dL/dO)
+    float4 pv[PMAX];      // O, lse2 (log2 units), g = dL/dO, reference exponent
+    float2 red[BLOCK];
+    int seg_src[MAXSEG];
+    int seg_off[MAXSEG + 1];
+    int isc[BLOCK / 64];
+    float fsc[BLOCK / 64];
+    double dsc[BLOCK / 64];
+    int tile;
+};
+
+// Backward accumulation over the tile's queries for one key held in
+// registers: key-parallel, as in Alg. 2.  MOVED adds the centre gradient sums.
+template <bool MOVED>
+__device__ __forceinline__ void bwd_key(const TileSmem& S, int P, int ph, int Sb, float4 kc,
+                                        float4 kv, float acc[8])
+{
+#pragma unroll 2
+    for (int p = ph; p < P; p += Sb) {
+        const float4 pq = S.pq[p];
+        const float4 pv = S.pv[p];
+        const float dx = pq.x - kc.x, dy = pq.y - kc.y, dz = pq.z - kc.z;
+        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        const float w = ex2(fmaf(kc.w, r2, -pv.y));
+        const float f = fmaf(dx, kv.y, fmaf(dy, kv.z, fmaf(dz, kv.w, kv.x)));
+        const float del = pv.z * w;
+        const float u = del * (f - pv.x);
+        acc[0] += del;
+        acc[1] = fmaf(del, dx, acc[1]);
+        acc[2] = fmaf(del, dy, acc[2]);
+        acc[3] = fmaf(del, dz, acc[3]);
+        acc[4] = fmaf(u, r2, acc[4]);
+        if (MOVED) {
+            acc[5] = fmaf(u, dx, acc[5]);
+            acc[6] = fmaf(u, dy, acc[6]);
+            acc[7] = fmaf(u, dz, acc[7]);
+        }
+    }
+}
+
+template <int MODE, bool QGRAD>
+__global__ __launch_bounds__(BLOCK) void k_tile(TileArgs a)
+{
+    __shared__ TileSmem S;
+    const int tid = threadIdx.x;
+    const Geo& g = a.g;
+    const int R = g.R, C1 = g.C1;
+    const int W = a.st->W;
+    const float bmin2 = __uint_as_float(a.st->bmin_bits) * LOG2E;
+    const int ntiles = *a.ntiles;
+
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) S.tile = atomicAdd(&a.st->queue, 1);
+        __syncthreads();
+        const int tile = S.tile;
+        if (tile >= ntiles) break;
+        const int4 td = a.tiles[tile];
+        const int cell = td.x, p0 = td.y, P = td.z;
+        const int cx = cell / (C1 * C1), cy = (cell / C1) % C1, cz = cell % C1;
+
+        // ---- window: grid vertices and moved-key row segments
+        const int vx0 = max(cx - W + 1, 0), vx1 = min(cx + W, R - 1);
+        const int vy0 = max(cy - W + 1, 0), vy1 = min(cy + W, R - 1);
+        const int vz0 = max(cz - W + 1, 0), vz1 = min(cz + W, R - 1);
+        const int nvy = vy1 - vy0 + 1, nvz = vz1 - vz0 + 1;
+        const int Kg = (vx1 - vx0 + 1) * nvy * nvz;
+        int Km = 0, nseg = 0;
+        if (a.offsets) {
+            const int mx0 = max(cx - W, 0), mx1 = min(cx + W, C1 - 1);
+            const int my0 = max(cy - W, 0), my1 = min(cy + W, C1 - 1);
+            const int mz0 = max(cz - W, 0), mz1 = min(cz + W, C1 - 1);
+            const int nmy = my1 - my0 + 1;
+            nseg = (mx1 - mx0 + 1) * nmy;
+            for (int base = 0; base < nseg; base += BLOCK) {
+                const int s = base + tid;
+                int len = 0;
+                if (s < nseg) {
+                    const int row = ((mx0 + s / nmy) * C1 + (my0 + s % nmy)) * C1;
+                    const int src = a.mstart[row + mz0];
+                    len = a.mstart[row + mz1 + 1] - src;
+                    S.seg_src[s] = src;
+                }
+                int total;
+                const int ex = block_excl_scan(len, S.isc, &total);
+                if (s < nseg) S.seg_off[s] = Km + ex;
+                Km += total;
+            }
+            if (tid == 0) S.seg_off[nseg] = Km;
+        }
+        const int K = Kg + Km;
+        const double ox = g.tlat[cx], oy = g.tlat[cy], oz = g.tlat[cz];
+
+        // ---- queries into LDS, relative to the tile origin
+        for (int p = tid; p < P; p += BLOCK) {
+            const float4 v = a.ps[p0 + p];
+            S.pq[p] = make_float4((float)((double)v.x - ox), (float)((double)v.y - oy),
+                                  (float)((double)v.z - oz), v.w);
+            if (MODE == MODE_GRAD) {
+                const float4 u = a.pv[p0 + p];
+                S.pv[p] = make_float4(u.x, u.y * LOG2E, v.w, 0.0f);
+            }
+        }
+
+        // stage window keys [k0, k0 + nk) into LDS slots [0, nk)
+        auto stage = [&](int k0, int nk) {
+            for (int k = tid; k < nk; k += BLOCK) {
+                const int kk = k0 + k;
+                float4 kc, kv;
+                int vid;
+                if (kk < Kg) {
+                    const int ix = vx0 + kk / (nvy * nvz), rr = kk % (nvy * nvz);
+                    const int iy = vy0 + rr / nvz, iz = vz0 + rr % nvz;
+                    vid = (ix * R + iy) * R + iz;
+                    const float4 a0 = a.gk[2 * (int64_t)vid], a1 = a.gk[2 * (int64_t)vid + 1];
+                    kc = make_float4((float)((double)g.tlat[ix] - ox), (float)((double)g.tlat[iy] - oy),
+                                     (float)((double)g.tlat[iz] - oz), a0.x);
+                    kv = make_float4(a0.y, a0.z, a0.w, a1.x);
+                } else {
+                    const int km = kk - Kg;
+                    int lo = 0, hi = nseg - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (S.seg_off[mid] <= km) lo = mid; else hi = mid - 1;
+                    }
+                    const int64_t slot = (int64_t)S.seg_src[lo] + (km - S.seg_off[lo]);
+                    const float4 b0 = a.mk[3 * slot], b1 = a.mk[3 * slot + 1], b2 = a.mk[3 * slot + 2];
+                    kc = make_float4((float)(((double)b0.x - ox) + (double)b2.x),
+                                     (float)(((double)b0.y - oy) + (double)b2.y),
+                                     (float)(((double)b0.z - oz) + (double)b2.z), b0.w);
+                    kv = b1;
+                    vid = __float_as_int(b2.w);
+                }
+                S.kc[k] = kc;
+                S.kv[k] = kv;
+                S.kid[k] = vid;
+            }
+        };
+
+        const int nchunks = (K + KC - 1) / KC;
+        int staged = -1;  // chunk currently in LDS
+
+        if (MODE != MODE_GRAD) {
+            __syncthreads();
+            // ---- reference exponent: largest corner logit of the home cell
+            int need_exact = 0;
+            for (int p = tid; p < P; p += BLOCK) {
+                const float4 pq = S.pq[p];
+                float M0 = -INFINITY;
+#pragma unroll
+                for (int c8 = 0; c8 < 8; ++c8) {
+                    const int ix = cx + (c8 >> 2), iy = cy + ((c8 >> 1) & 1), iz = cz + (c8 & 1);
+                    const int vid = (ix * R + iy) * R + iz;
+                    const float nb = a.gk[2 * (int64_t)vid].x;
+                    const float dx = pq.x - (float)((double)g.tlat[ix] - ox);
+                    const float dy = pq.y - (float)((double)g.tlat[iy] - oy);
+                    const float dz = pq.z - (float)((double)g.tlat[iz] - oz);
+                    M0 = fmaxf(M0, nb * fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+                }
+                S.pv[p] = make_float4(0.0f, 0.0f, 0.0f, M0);
+                // exp2(s - M0) <= 2^-M0 per key; keep the sum of K such terms finite
+                if (!(-M0 + log2f((float)K + 1.0f) < 120.0f)) need_exact = 1;
+            }
+            const int exact = __syncthreads_or(need_exact);
+
+            const int Sf = max(1, BLOCK / max(P, 1));
+            const int pme = tid / Sf, ph = tid - pme * Sf;
+            const bool act = pme < P;
+
+            if (exact) {
+                // exact maximum over the window first (rare: very coarse lattices)
+                float M = -INFINITY;
+                for (int c = 0; c < nchunks; ++c) {
+                    const int k0 = c * KC, nk = min(KC, K - k0);
+                    __syncthreads();
+                    stage(k0, nk);
+                    staged = c;
+                    __syncthreads();
+                    if (act) {
+                        const float4 pq = S.pq[pme];
+                        for (int k = ph; k < nk; k += Sf) {
+                            const float4 kc = S.kc[k];
+                            const float dx = pq.x - kc.x, dy = pq.y - kc.y, dz = pq.z - kc.z;
+                            M = fmaxf(M, kc.w * fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+                        }
+                    }
+                }
+                S.red[tid].x = M;
+                __syncthreads();
+                for (int p = tid; p < P; p += BLOCK) {
+                    float mx = S.pv[p].w;
+                    for (int s = 0; s < Sf; ++s) mx = fmaxf(mx, S.red[p * Sf + s].x);
+                    S.pv[p].w = mx;
+                }
+            }
+
+            // ---- forward: e = sum 2^(s - M), m = sum 2^(s - M) f   (Alg. 1)
+            float e = 0.0f, m = 0.0f;
+            float qx = 0.0f, qy = 0.0f, qz = 0.0f, Mr = 0.0f;
+            __syncthreads();
+            if (act) {
+                const float4 pq = S.pq[pme];
+                qx = pq.x; qy = pq.y; qz = pq.z;
+                Mr = S.pv[pme].w;
+            }
+            for (int c = 0; c < nchunks; ++c) {
+                const int k0 = c * KC, nk = min(KC, K - k0);
+                if (staged != c) {
+                    __syncthreads();
+                    stage(k0, nk);
+                    staged = c;
+                    __syncthreads();
+                }
+                if (act) {
+#pragma unroll 4
+                    for (int k = ph; k < nk; k += Sf) {
+                        const float4 kc = S.kc[k], kv = S.kv[k];
+                        const float dx = qx - kc.x, dy = qy - kc.y, dz = qz - kc.z;
+                        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                        const float l = ex2(fmaf(kc.w, r2, -Mr));
+                        const float f = fmaf(dx, kv.y, fmaf(dy, kv.z, fmaf(dz, kv.w, kv.x)));
+                        e += l;
+                        m = fmaf(l, f, m);
+                    }
+                }
+            }
+            __syncthreads();
+            S.red[tid] = make_float2(e, m);
+            __syncthreads();
+
+            // ---- per query: O, lse, certificate, loss and dL/dO
+            // faces of the window box beyond which keys are excluded
+            const float flx = (cx - W + 1 > 0) ? (float)((double)g.tlat[cx - W] - ox) : -INFINITY;
+            const float fly = (cy - W + 1 > 0) ? (float)((double)g.tlat[cy - W] - oy) : -INFINITY;
+            const float flz = (cz - W + 1 > 0) ? (float)((double)g.tlat[cz - W] - oz) : -INFINITY;
+            const float fhx = (cx + W < R - 1) ? (float)((double)g.tlat[cx + W + 1] - ox) : INFINITY;
+            const float fhy = (cy + W < R - 1) ? (float)((double)g.tlat[cy + W + 1] - oy) : INFINITY;
+            const float fhz = (cz + W < R - 1) ? (float)((double)g.tlat[cz + W + 1] - oz) : INFINITY;
+            double lsq = 0.0, lab = 0.0;
+            for (int p = tid; p < P; p += BLOCK) {
+                float ee = 0.0f, mm = 0.0f;
+                for (int s = 0; s < Sf; ++s) {
+                    const float2 r = S.red[p * Sf + s];
+                    ee += r.x;
+                    mm += r.y;
+                }
+                const float4 pq = S.pq[p];
+                const float M = S.pv[p].w;
+                const float O = mm / ee;
+                const float lse2 = M + log2f(ee);
+                float D = fminf(fminf(pq.x - flx, fhx - pq.x),
+                                fminf(fminf(pq.y - fly, fhy - pq.y), fminf(pq.z - flz, fhz - pq.z)));
+                D = fmaxf(D * (1.0f - 1e-5f) - 1e-6f * g.h, 0.0f);
+                const bool cert = (bmin2 * D * D >= a.T2 - lse2) && (ee > 0.0f);
+                if (!cert) {
+                    const int slot = atomicAdd(&a.st->nfb, 1);
+                    a.fb[slot] = p0 + p;
+                }
+                if (MODE == MODE_FIT) {
+                    const float res = O - pq.w;
+                    float gj = 0.0f;
+                    if (cert) {
+                        gj = res * a.two_over_J;
+                        lsq += (double)res * (double)res;
+                        lab += fabs((double)res);
+                    }
+                    S.pv[p] = make_float4(O, lse2, gj, M);
+                } else {  // EVAL
+                    if (cert) {
+                        const int j = a.pidx[p0 + p];
+                        a.O_out[j] = O;
+                        if (a.lse_out) a.lse_out[j] = lse2 * LN2;
+                    }
+                    S.pv[p] = make_float4(O, lse2, cert ? 1.0f : 0.0f, M);
+                }
+            }
+            if (MODE == MODE_FIT) {
+                lsq = block_sum(lsq, S.dsc);
+                lab = block_sum(lab, S.dsc);
+                if (tid == 0) a.lpart[tile] = make_double2(lsq, lab);
+            }
+            __syncthreads();
+
+            if (MODE == MODE_EVAL && QGRAD) {
+                // dO/dq = sum_a w_a [d_a + 2 beta_a x (O - f_a)]  (Eq. func-normal)
+                float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+                float O = 0.0f, lse2 = 0.0f;
+                if (act) {
+                    const float4 pv = S.pv[pme];
+                    O = pv.x;
+                    lse2 = pv.y;
+                }
+                for (int c = nchunks - 1; c >= 0; --c) {
+                    const int k0 = c * KC, nk = min(KC, K - k0);
+                    if (staged != c) {
+                        __syncthreads();
+                        stage(k0, nk);
+                        staged = c;
+                        __syncthreads();
+                    }
+                    if (act) {
+                        for (int k = ph; k < nk; k += Sf) {
+                            const float4 kc = S.kc[k], kv = S.kv[k];
+                            const float dx = qx - kc.x, dy = qy - kc.y, dz = qz - kc.z;
+                            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                            const float w = ex2(fmaf(kc.w, r2, -lse2));
+                            const float f = fmaf(dx, kv.y, fmaf(dy, kv.z, fmaf(dz, kv.w, kv.x)));
+                            const float t = -2.0f * LN2 * kc.w * (O - f) * w;  // 2 beta (O - f) w
+                            gx += fmaf(w, kv.y, t * dx);
+                            gy += fmaf(w, kv.z, t * dy);
+                            gz += fmaf(w, kv.w, t * dz);
+                        }
+                    }
+                }
+                __syncthreads();
+                S.red[tid] = make_float2(gx, gy);
+                float* zf = reinterpret_cast<float*>(S.kc);  // keys no longer needed
+                __syncthreads();
+                zf[tid] = gz;
+                staged = -1;
+                __syncthreads();
+                for (int p = tid; p < P; p += BLOCK) {
+                    if (S.pv[p].z == 0.0f) continue;  // uncertified: fallback writes it
+                    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+                    for (int s = 0; s < Sf; ++s) {
+                        sx += S.red[p * Sf + s].x;
+                        sy += S.red[p * Sf + s].y;
+                        sz += zf[p * Sf + s];
+                    }
+                    const int j = a.pidx[p0 + p];
+                    a.dOdq_out[3 * (int64_t)j] = sx;
+                    a.dOdq_out[3 * (int64_t)j + 1] = sy;
+                    a.dOdq_out[3 * (int64_t)j + 2] = sz;
+                }
+            }
+        } else {
+            // ---- backward only: certificate from the given lse
+            __syncthreads();
+            const float flx = (cx - W + 1 > 0) ? (float)((double)g.tlat[cx - W] - ox) : -INFINITY;
+            const float fly = (cy - W + 1 > 0) ? (float)((double)g.tlat[cy - W] - oy) : -INFINITY;
+            const float flz = (cz - W + 1 > 0) ? (float)((double)g.tlat[cz - W] - oz) : -INFINITY;
+            const float fhx = (cx + W < R - 1) ? (float)((double)g.tlat[cx + W + 1] - ox) : INFINITY;
+            const float fhy = (cy + W < R - 1) ? (float)((double)g.tlat[cy + W + 1] - oy) : INFINITY;
+            const float fhz = (cz + W < R - 1) ? (float)((double)g.tlat[cz + W + 1] - oz) : INFINITY;
+            for (int p = tid; p < P; p += BLOCK) {
+                const float4 pq = S.pq[p];
+                float4 pv = S.pv[p];
+                float D = fminf(fminf(pq.x - flx, fhx - pq.x),
+                                fminf(fminf(pq.y - fly, fhy - pq.y), fminf(pq.z - flz, fhz - pq.z)));
+                D = fmaxf(D * (1.0f - 1e-5f) - 1e-6f * g.h, 0.0f);
+                const bool cert = bmin2 * D * D >= a.T2 - pv.y;
+                if (!cert) {
+                    const int slot = atomicAdd(&a.st->nfb, 1);
+                    a.fb[slot] = p0 + p;
+                    pv.z = 0.0f;
+                    S.pv[p] = pv;
+                }
+            }
+        }
+
+        if (MODE != MODE_EVAL) {
+            // ---- backward, key-parallel over the tile's queries (Alg. 2)
+            for (int c = nchunks - 1; c >= 0; --c) {
+                const int k0 = c * KC, nk = min(KC, K - k0);
+                __syncthreads();
+                if (staged != c) {
+                    stage(k0, nk);
+                    staged = c;
+                    __syncthreads();
+                }
+                int Sb = 1;
+                while (Sb < 64 && Sb * 2 * nk <= BLOCK) Sb *= 2;
+                const int k = tid / Sb, ph = tid - k * Sb;
+                const bool act = k < nk;
+                const bool moved = act && (k0 + k >= Kg);
+                float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                float4 kc = make_float4(0, 0, 0, 0), kv = make_float4(0, 0, 0, 0);
+                if (act) {
+                    kc = S.kc[k];
+                    kv = S.kv[k];
+                }
+                if (__any(moved)) {
+                    if (act) bwd_key<true>(S, P, ph, Sb, kc, kv, acc);
+                } else {
+                    if (act) bwd_key<false>(S, P, ph, Sb, kc, kv, acc);
+                }
+                for (int off = 1; off < Sb; off <<= 1) {
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) acc[t] += __shfl_xor(acc[t], off, 64);
+                }
+                if (act && ph == 0) {
+                    bool any = false;
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) any |= (acc[t] != 0.0f);
+                    if (any) {
+                        const int vid = S.kid[k];
+                        const float beta = -kc.w * LN2;
+                        float* gp = a.grad + (int64_t)vid * NCH;
+                        if (!moved) {
+                            unsafeAtomicAdd(gp + 0, acc[0]);
+                            unsafeAtomicAdd(gp + 1, acc[1]);
+                            unsafeAtomicAdd(gp + 2, acc[2]);
+                            unsafeAtomicAdd(gp + 3, acc[3]);
+                            unsafeAtomicAdd(gp + 4, -beta * acc[4]);
+                        } else {
+                            // dL/dc = -d sum(delta) + 2 beta sum(delta r x)
+                            unsafeAtomicAdd(gp + 5, fmaf(-kv.y, acc[0], 2.0f * beta * acc[5]));
+                            unsafeAtomicAdd(gp + 6, fmaf(-kv.z, acc[0], 2.0f * beta * acc[6]));
+                            unsafeAtomicAdd(gp + 7, fmaf(-kv.w, acc[0], 2.0f * beta * acc[7]));
+                            unsafeAtomicAdd(gp + 8, acc[0]);
+                            unsafeAtomicAdd(gp + 9, acc[1]);
+                            unsafeAtomicAdd(gp + 10, acc[2]);
+                            unsafeAtomicAdd(gp + 11, acc[3]);
+                            unsafeAtomicAdd(gp + 12, -beta * acc[4]);
+                        }
+                    }
+                }
+            }
+        }
+        if (tid == 0) {
+            atomicAdd(&a.st->pairs, (unsigned long long)P * (unsigned long long)K);
+            atomicAdd(&a.st->pairs_moved, (unsigned long long)P * (unsigned long long)Km);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- fallback
+// Queries whose certificate failed: one workgroup per query sweeps every key
+// (the global-support definition).  Keys are taken relative to the query.
+template <int MODE, bool QGRAD>
+__global__ __launch_bounds__(BLOCK) void k_fallback(TileArgs a)
+{
+    __shared__ float shf[BLOCK / 64];
+    __shared__ double shd[BLOCK / 64];
+    __shared__ int s_item;
+    const int tid = threadIdx.x;
+    const Geo& g = a.g;
+    const int R = g.R;
+    const int64_t I = a.I;
+    const int nfb = a.st->nfb;
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) s_item = atomicAdd(&a.st->fbqueue, 1);
+        __syncthreads();
+        const int item = s_item;
+        if (item >= nfb) break;
+        const int sp = a.fb[item];
+        const float4 pq = a.ps[sp];
+        const double qx = pq.x, qy = pq.y, qz = pq.z;
+
+        // key a (0 <= a < I grid, I <= a < 2I moved): offset x = q - c, nb, o, d
+        auto key = [&](int64_t ka, float& dx, float& dy, float& dz, float& nb, float4& kv) {
+            if (ka < I) {
+                const int ix = (int)(ka / ((int64_t)R * R)), iy = (int)((ka / R) % R), iz = (int)(ka % R);
+                const float4 a0 = a.gk[2 * ka], a1 = a.gk[2 * ka + 1];
+                dx = (float)(qx - (double)g.tlat[ix]);
+                dy = (float)(qy - (double)g.tlat[iy]);
+                dz = (float)(qz - (double)g.tlat[iz]);
+                nb = a0.x;
+                kv = make_float4(a0.y, a0.z, a0.w, a1.x);
+            } else {
+                const int64_t s = ka - I;
+                const float4 b0 = a.mk[3 * s], b1 = a.mk[3 * s + 1], b2 = a.mk[3 * s + 2];
+                dx = (float)((qx - (double)b0.x) - (double)b2.x);
+                dy = (float)((qy - (double)b0.y) - (double)b2.y);
+                dz = (float)((qz - (double)b0.z) - (double)b2.z);
+                nb = b0.w;
+                kv = b1;
+            }
+        };
+        const int64_t nkeys = a.offsets ? 2 * I : I;
+        float O, lse2, gj = 0.0f;
+        if (MODE != MODE_GRAD) {
+            float M = -INFINITY;
+            for (int64_t ka = tid; ka < nkeys; ka += BLOCK) {
+                float dx, dy, dz, nb;
+                float4 kv;
+                key(ka, dx, dy, dz, nb, kv);
+                M = fmaxf(M, nb * fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+            }
+            M = block_max(M, shf);
+            float e = 0.0f, m = 0.0f;
+            for (int64_t ka = tid; ka < nkeys; ka += BLOCK) {
+                float dx, dy, dz, nb;
+                float4 kv;
+                key(ka, dx, dy, dz, nb, kv);
+                const float l = ex2(fmaf(nb, fmaf(dx, dx, fmaf(dy, dy, dz * dz)), -M));
+                e += l;
+                m = fmaf(l, fmaf(dx, kv.y, fmaf(dy, kv.z, fmaf(dz, kv.w, kv.x))), m);
+            }
+            e = block_sum(e, shf);
+            m = block_sum(m, shf);
+            O = m / e;
+            lse2 = M + log2f(e);
+            if (MODE == MODE_FIT) {
+                const float res = O - pq.w;
+                gj = res * a.two_over_J;
+                if (tid == 0) {
+                    unsafeAtomicAdd(&a.st->fb_loss[0], (double)res * (double)res);
+                    unsafeAtomicAdd(&a.st->fb_loss[1], fabs((double)res));
+                }
+            } else if (tid == 0) {
+                const int j = a.pidx[sp];
+                a.O_out[j] = O;
+                if (a.lse_out) a.lse_out[j] = lse2 * LN2;
+            }
+            if (MODE == MODE_EVAL && QGRAD) {
+                float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+                for (int64_t ka = tid; ka < nkeys; ka += BLOCK) {
+                    float dx, dy, dz, nb;
+                    float4 kv;
+                    key(ka, dx, dy, dz, nb, kv);
+                    const float w = ex2(fmaf(nb, fmaf(dx, dx, fmaf(dy, dy, dz * dz)), -lse2));
+                    const float f = fmaf(dx, kv.y, fmaf(dy, kv.z, fmaf(dz, kv.w, kv.x)));
+                    const float t = -2.0f * LN2 * nb * (O - f) * w;
+                    gx += fmaf(w, kv.y, t * dx);
+                    gy += fmaf(w, kv.z, t * dy);
+                    gz += fmaf(w, kv.w, t * dz);
+                }
+                gx = block_sum(gx, shf);
+                gy = block_sum(gy, shf);
+                gz = block_sum(gz, shf);
+                if (tid == 0) {
+                    const int j = a.pidx[sp];
+                    a.dOdq_out[3 * (int64_t)j] = gx;
+                    a.dOdq_out[3 * (int64_t)j + 1] = gy;
+                    a.dOdq_out[3 * (int64_t)j + 2] = gz;
+                }
+            }
+        } else {
+            const float4 pv = a.pv[sp];
+            O = pv.x;
+            lse2 = pv.y * LOG2E;
+            gj = pq.w;
+        }
+        (void)shd;
+        if (MODE != MODE_EVAL && gj != 0.0f) {
+            for (int64_t ka = tid; ka < nkeys; ka += BLOCK) {
+                float dx, dy, dz, nb;
+                float4 kv;
+                key(ka, dx, dy, dz, nb, kv);
+                const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                const float w = ex2(fmaf(nb, r2, -lse2));
+                const float del = gj * w;
+                if (del == 0.0f) continue;
+                const float f = fmaf(dx, kv.y, fmaf(dy, kv.z, fmaf(dz, kv.w, kv.x)));
+                const float u = del * (f - O);
+                const float beta = -nb * LN2;
+                if (ka < I) {
+                    float* gp = a.grad + ka * NCH;
+                    unsafeAtomicAdd(gp + 0, del);
+                    unsafeAtomicAdd(gp + 1, del * dx);
+                    unsafeAtomicAdd(gp + 2, del * dy);
+                    unsafeAtomicAdd(gp + 3, del * dz);
+                    unsafeAtomicAdd(gp + 4, -beta * u * r2);
+                } else {
+                    const float4 b2 = a.mk[3 * (ka - I) + 2];
+                    float* gp = a.grad + (int64_t)__float_as_int(b2.w) * NCH;
+                    unsafeAtomicAdd(gp + 5, fmaf(-kv.y, del, 2.0f * beta * u * dx));
+                    unsafeAtomicAdd(gp + 6, fmaf(-kv.z, del, 2.0f * beta * u * dy));
+                    unsafeAtomicAdd(gp + 7, fmaf(-kv.w, del, 2.0f * beta * u * dz));
+                    unsafeAtomicAdd(gp + 8, del);
+                    unsafeAtomicAdd(gp + 9, del * dx);
+                    unsafeAtomicAdd(gp + 10, del * dy);
+                    unsafeAtomicAdd(gp + 11, del * dz);
+                    unsafeAtomicAdd(gp + 12, -beta * u * r2);
+                }
+            }
+        }
+    }
+}
+
+__global__ void k_count_uncertified(const DevStats* st, int64_t* out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *out = (int64_t)st->nfb;
+}
+
+// ------------------------------------------------------------- loss, Adam
+__global__ __launch_bounds__(BLOCK) void k_loss_finalize(const double2* __restrict__ lpart,
+                                                         const int* __restrict__ ntiles,
+                                                         const DevStats* __restrict__ st,
+                                                         double invJ, double* __restrict__ out)
+{
+    __shared__ double sh[BLOCK / 64];
+    const int n = *ntiles;
+    double s2 = 0.0, s1 = 0.0;
+    for (int t = threadIdx.x; t < n; t += BLOCK) {
+        const double2 v = lpart[t];
+        s2 += v.x;
+        s1 += v.y;
+    }
+    s2 = block_sum(s2, sh);
+    s1 = block_sum(s1, sh);
+    if (threadIdx.x == 0) {
+        out[0] = (s2 + st->fb_loss[0]) * invJ;
+        out[1] = (s1 + st->fb_loss[1]) * invJ;
+    }
+}
+
+// AdamW with decoupled weight decay and bias correction; clears the gradient.
+__global__ void k_adam(float* __restrict__ theta, float* __restrict__ m, float* __restrict__ v,
+                       float* __restrict__ grad, int64_t n, float lr, float b1, float b2, float eps,
+                       float wd, float bc1, float bc2)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = grad[i];
+        const float mi = fmaf(b1, m[i], (1.0f - b1) * gi);
+        const float vi = fmaf(b2, v[i], (1.0f - b2) * gi * gi);
+        const float th = theta[i];
+        m[i] = mi;
+        v[i] = vi;
+        theta[i] = th - lr * wd * th - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+        grad[i] = 0.0f;
+    }
+}
+
+// ------------------------------------------------------------- mean-shift
+// Delta_i = sum_n w_n s_n / sum_n w_n - k_i with w_n = exp(-bw ||k_i - s_n||^2),
+// weights relative to the nearest sample (Sec. 3.3).  One thread per vertex;
+// samples staged through LDS.
+__global__ __launch_bounds__(BLOCK) void k_init_params(float* __restrict__ theta, Geo g,
+                                                       const float* __restrict__ surf, int64_t Ns,
+                                                       double bw, float rho0, int64_t I)
+{
+    __shared__ double sx[BLOCK], sy[BLOCK], sz[BLOCK];
+    const int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
+    const int R = g.R;
+    const bool act = i < I;
+    const int64_t ii = act ? i : 0;
+    const double kx = g.tlat[(int)(ii / ((int64_t)R * R))];
+    const double ky = g.tlat[(int)((ii / R) % R)];
+    const double kz = g.tlat[(int)(ii % R)];
+    double dmin = INFINITY;
+    for (int64_t b = 0; b < Ns; b += BLOCK) {
+        __syncthreads();
+        const int64_t n = b + threadIdx.x;
+        if (n < Ns) {
+            sx[threadIdx.x] = surf[3 * n];
+            sy[threadIdx.x] = surf[3 * n + 1];
+            sz[threadIdx.x] = surf[3 * n + 2];
+        }
+        __syncthreads();
+        const int cnt = (int)min((int64_t)BLOCK, Ns - b);
+        for (int t = 0; t < cnt; ++t) {
+            const double dx = kx - sx[t], dy = ky - sy[t], dz = kz - sz[t];
+            dmin = fmin(dmin, dx * dx + dy * dy + dz * dz);
+        }
+    }
+    double w = 0.0, wx = 0.0, wy = 0.0, wz = 0.0;
+    for (int64_t b = 0; b < Ns; b += BLOCK) {
+        __syncthreads();
+        const int64_t n = b + threadIdx.x;
+        if (n < Ns) {
+            sx[threadIdx.x] = surf[3 * n];
+            sy[threadIdx.x] = surf[3 * n + 1];
+            sz[threadIdx.x] = surf[3 * n + 2];
+        }
+        __syncthreads();
+        const int cnt = (int)min((int64_t)BLOCK, Ns - b);
+        for (int t = 0; t < cnt; ++t) {
+            const double dx = kx - sx[t], dy = ky - sy[t], dz = kz - sz[t];
+            const double l = exp(-bw * (dx * dx + dy * dy + dz * dz - dmin));
+            w += l;
+            wx += l * sx[t];
+            wy += l * sy[t];
+            wz += l * sz[t];
+        }
+    }
+    if (!act) return;
+    float* p = theta + i * NCH;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) p[c] = 0.0f;
+    p[4] = rho0;
+    p[12] = rho0;
+    if (Ns > 0) {
+        p[5] = (float)(wx / w - kx);
+        p[6] = (float)(wy / w - ky);
+        p[7] = (float)(wz / w - kz);
+    }
+}
+
+// ---------------------------------------------------------------- drivers
+// One thread per element (per = BLOCK) or a grid-stride kernel (per > BLOCK).
+static inline unsigned grid_for(int64_t n, int per = BLOCK)
+{
+    int64_t b = (n + per - 1) / per;
+    if (b < 1) b = 1;
+    if (per > BLOCK && b > 65536) b = 65536;
+    return (unsigned)b;
+}
+
+static hipError_t scan(const int* cnt, int64_t n, int* blk, int* start, int* tstart, bool tiles,
+                       hipStream_t s)
+{
+    const int nb = (int)((n + SCAN_TILE - 1) / SCAN_TILE);
+    if (tiles) {
+        k_scan_reduce<true><<<nb, BLOCK, 0, s>>>(cnt, n, blk);
+        k_scan_blocks<<<1, BLOCK, 0, s>>>(blk, nb);
+        k_scan_apply<true><<<nb, BLOCK, 0, s>>>(cnt, n, blk, nb, start, tstart);
+    } else {
+        k_scan_reduce<false><<<nb, BLOCK, 0, s>>>(cnt, n, blk);
+        k_scan_blocks<<<1, BLOCK, 0, s>>>(blk, nb);
+        k_scan_apply<false><<<nb, BLOCK, 0, s>>>(cnt, n, blk, nb, start, tstart);
+    }
+    return hipGetLastError();
+}
+
+hipError_t run_zero_floats(float* p, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    k_fill_float<<<grid_for(n, BLOCK * 8), BLOCK, 0, s>>>(p, n);
+    return hipGetLastError();
+}
+
+hipError_t run_tiles(const Work& w, const Problem& p, Mode mode, hipStream_t s)
+{
+    const Geo& g = p.g;
+    const int64_t I = w.I, C = w.C, J = p.J;
+    k_reset_stats<<<1, 64, 0, s>>>(w.st);
+    k_fill_int<<<grid_for(C, BLOCK * 8), BLOCK, 0, s>>>(w.pcount, C, 0);
+    if (p.offsets) k_fill_int<<<grid_for(C, BLOCK * 8), BLOCK, 0, s>>>(w.mcount, C, 0);
+    // keys
+    k_prep_keys<<<grid_for(I), BLOCK, 0, s>>>(p.theta, g, p.offsets, I, w.gk, w.mrec, w.mcell,
+                                              w.mrank, w.mcount, w.st);
+    if (p.offsets) {
+        hipError_t e = scan(w.mcount, C, w.scan_blk, w.mstart, nullptr, false, s);
+        if (e != hipSuccess) return e;
+        k_scatter_keys<<<grid_for(I), BLOCK, 0, s>>>(I, w.mcell, w.mrank, w.mstart, w.mrec, w.mk);
+    }
+    k_window<<<1, 64, 0, s>>>(w.st, g, p.T, p.window);
+    // queries
+    k_count_points<<<grid_for(J), BLOCK, 0, s>>>(p.q, J, g, w.pcell, w.prank, w.pcount);
+    {
+        hipError_t e = scan(w.pcount, C, w.scan_blk, w.pstart, w.tstart, true, s);
+        if (e != hipSuccess) return e;
+    }
+    k_scatter_points<<<grid_for(J), BLOCK, 0, s>>>(p.q, p.aux, p.O_in, p.lse_in, J, w.pcell,
+                                                   w.prank, w.pstart, w.ps, w.pv, w.pidx);
+    k_build_tiles<<<grid_for(C), BLOCK, 0, s>>>(C, w.pcount, w.pstart, w.tstart, w.tiles);
+
+    TileArgs a;
+    a.g = g;
+    a.offsets = p.offsets;
+    a.T2 = p.T * LOG2E;
+    a.two_over_J = (float)(2.0 / (double)(J > 0 ? J : 1));
+    a.gk = w.gk;
+    a.mk = w.mk;
+    a.mstart = w.mstart;
+    a.ps = w.ps;
+    a.pv = w.pv;
+    a.pidx = w.pidx;
+    a.tiles = w.tiles;
+    a.ntiles = w.tstart + C;
+    a.fb = w.fb;
+    a.lpart = w.lpart;
+    a.st = w.st;
+    a.O_out = p.O_out;
+    a.lse_out = p.lse_out;
+    a.dOdq_out = p.dOdq_out;
+    a.grad = p.grad;
+    a.I = I;
+    const int64_t tiles_hint = w.max_tiles;
+    int64_t grid = (int64_t)w.num_cu * 8;
+    if (grid > tiles_hint) grid = tiles_hint;
+    if (grid < 1) grid = 1;
+    const int fgrid = w.num_cu;
+    if (p.ev_start) (void)hipEventRecord(p.ev_start, s);
+    switch (mode) {
+    case MODE_FIT:
+        k_tile<MODE_FIT, false><<<(unsigned)grid, BLOCK, 0, s>>>(a);
+        if (p.ev_stop) (void)hipEventRecord(p.ev_stop, s);
+        k_fallback<MODE_FIT, false><<<fgrid, BLOCK, 0, s>>>(a);
+        break;
+    case MODE_EVAL:
+        if (p.dOdq_out) {
+            k_tile<MODE_EVAL, true><<<(unsigned)grid, BLOCK, 0, s>>>(a);
+            if (p.ev_stop) (void)hipEventRecord(p.ev_stop, s);
+            k_fallback<MODE_EVAL, true><<<fgrid, BLOCK, 0, s>>>(a);
+        } else {
+            k_tile<MODE_EVAL, false><<<(unsigned)grid, BLOCK, 0, s>>>(a);
+            if (p.ev_stop) (void)hipEventRecord(p.ev_stop, s);
+            k_fallback<MODE_EVAL, false><<<fgrid, BLOCK, 0, s>>>(a);
+        }
+        break;
+    case MODE_GRAD:
+        k_tile<MODE_GRAD, false><<<(unsigned)grid, BLOCK, 0, s>>>(a);
+        if (p.ev_stop) (void)hipEventRecord(p.ev_stop, s);
+        k_fallback<MODE_GRAD, false><<<fgrid, BLOCK, 0, s>>>(a);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t run_loss_finalize(const Work& w, int64_t J, double* loss_out, hipStream_t s)
+{
+    k_loss_finalize<<<1, BLOCK, 0, s>>>(w.lpart, w.tstart + w.C, w.st, 1.0 / (double)J, loss_out);
+    return hipGetLastError();
+}
+
+hipError_t run_adam(const Work& w, float* theta, float* m, float* v, int64_t n, float lr,
+                    float beta1, float beta2, float eps, float wd, float bc1, float bc2,
+                    hipStream_t s)
+{
+    k_adam<<<grid_for(n, BLOCK * 4), BLOCK, 0, s>>>(theta, m, v, w.grad, n, lr, beta1, beta2, eps,
+                                                   wd, bc1, bc2);
+    return hipGetLastError();
+}
+
+hipError_t run_init_params(const Work& w, const Geo& g, float* theta, const float* surf,
+                           int64_t Ns, float bandwidth, float rho0, hipStream_t s)
+{
+    k_init_params<<<grid_for(w.I), BLOCK, 0, s>>>(theta, g, surf, Ns, (double)bandwidth, rho0, w.I);
+    return hipGetLastError();
+}
+
+hipError_t run_count_uncertified(const Work& w, int64_t* out, hipStream_t s)
+{
+    k_count_uncertified<<<1, 64, 0, s>>>(w.st, out);
+    return hipGetLastError();
+}
+
+}  // namespace efunc

@@ -1,0 +1,252 @@
+"""Python binding of the efunc C ABI (include/efunc.h).
+
+Argument marshalling only: every function below checks tensor placement,
+dtype and contiguity, passes raw device pointers and the current HIP stream
+to the function of the same name in libefunc.so, and turns a negative return
+code into EfuncError.  All computation runs in the library's HIP kernels;
+if the library is missing, importing the binding succeeds but every call
+raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libefunc.so")
+NCH = 13
+
+EFUNC_OK = 0
+EFUNC_EINVAL = -1
+EFUNC_EHIP = -2
+EFUNC_ESIZE = -3
+EFUNC_ENONFINITE = -4
+EFUNC_EUNSUPPORTED = -5
+
+
+class EfuncError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"efunc error {code}: {msg}")
+        self.code = code
+
+
+class efunc_config(C.Structure):
+    _fields_ = [("R", C.c_int32), ("lo", C.c_float), ("hi", C.c_float), ("offsets", C.c_int32),
+                ("t_cut", C.c_float), ("window", C.c_int32), ("deterministic", C.c_int32),
+                ("check_finite", C.c_int32)]
+
+
+class efunc_adam(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("weight_decay", C.c_float)]
+
+
+class efunc_stats(C.Structure):
+    _fields_ = [("W", C.c_int32), ("n_tiles", C.c_int32), ("n_uncertified", C.c_int64),
+                ("pairs", C.c_int64), ("pairs_moved", C.c_int64), ("beta_min", C.c_float),
+                ("beta_grid_max", C.c_float), ("n_nonfinite", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# every symbol declared in include/efunc.h
+EXPORTS = ["efunc_default_config", "efunc_default_adam", "efunc_create", "efunc_destroy",
+           "efunc_init_params", "efunc_eval", "efunc_grad", "efunc_fit_step", "efunc_get_stats",
+           "efunc_set_timing", "efunc_read_timing", "efunc_last_error"]
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libefunc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise EfuncError(EFUNC_EUNSUPPORTED,
+                             f"{LIB_PATH} is missing: build it with paper_2505_21319_amd.build")
+        L = C.CDLL(LIB_PATH)
+        vp, i64 = C.c_void_p, C.c_int64
+        L.efunc_default_config.argtypes = [C.POINTER(efunc_config), C.c_int32]
+        L.efunc_default_config.restype = None
+        L.efunc_default_adam.argtypes = [C.POINTER(efunc_adam)]
+        L.efunc_default_adam.restype = None
+        L.efunc_create.argtypes = [C.POINTER(efunc_config), i64, C.POINTER(vp)]
+        L.efunc_destroy.argtypes = [vp]
+        L.efunc_init_params.argtypes = [vp, vp, vp, i64, C.c_float, C.c_float, vp]
+        L.efunc_eval.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp]
+        L.efunc_grad.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp, vp]
+        L.efunc_fit_step.argtypes = [vp, vp, vp, vp, i64, C.POINTER(efunc_adam), vp, vp, i64, vp, vp]
+        L.efunc_get_stats.argtypes = [vp, C.POINTER(efunc_stats)]
+        L.efunc_set_timing.argtypes = [vp, C.c_int32]
+        L.efunc_read_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.efunc_last_error.argtypes = []
+        L.efunc_last_error.restype = C.c_char_p
+        for name in ("efunc_create", "efunc_destroy", "efunc_init_params", "efunc_eval",
+                     "efunc_grad", "efunc_fit_step", "efunc_get_stats", "efunc_set_timing",
+                     "efunc_read_timing"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != EFUNC_OK:
+        raise EfuncError(rc, lib().efunc_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor], dtype: torch.dtype, name: str, numel: Optional[int] = None):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return t.data_ptr()
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def efunc_default_config(R: int) -> efunc_config:
+    c = efunc_config()
+    lib().efunc_default_config(C.byref(c), R)
+    return c
+
+
+def efunc_default_adam() -> efunc_adam:
+    a = efunc_adam()
+    lib().efunc_default_adam(C.byref(a))
+    return a
+
+
+def efunc_create(cfg: efunc_config, max_points: int) -> C.c_void_p:
+    out = C.c_void_p()
+    _check(lib().efunc_create(C.byref(cfg), max_points, C.byref(out)))
+    return out
+
+
+def efunc_destroy(ctx) -> None:
+    _check(lib().efunc_destroy(ctx))
+
+
+def efunc_init_params(ctx, theta, surf, R: int, bandwidth=100.0, rho0=7.0, stream=None):
+    ns = 0 if surf is None else surf.numel() // 3
+    _check(lib().efunc_init_params(ctx, _ptr(theta, torch.float32, "theta", R ** 3 * NCH),
+                                   _ptr(surf, torch.float32, "surf"), ns, bandwidth, rho0,
+                                   _stream(stream)))
+
+
+def efunc_eval(ctx, theta, q, O, lse=None, dOdq=None, n_uncertified=None, stream=None):
+    J = q.numel() // 3
+    _check(lib().efunc_eval(ctx, _ptr(theta, torch.float32, "theta"),
+                            _ptr(q, torch.float32, "q", 3 * J), J,
+                            _ptr(O, torch.float32, "O", J), _ptr(lse, torch.float32, "lse", J),
+                            _ptr(dOdq, torch.float32, "dOdq", 3 * J),
+                            _ptr(n_uncertified, torch.int64, "n_uncertified", 1),
+                            _stream(stream)))
+
+
+def efunc_grad(ctx, theta, q, O, lse, dLdO, grad, stream=None):
+    J = q.numel() // 3
+    _check(lib().efunc_grad(ctx, _ptr(theta, torch.float32, "theta"),
+                            _ptr(q, torch.float32, "q", 3 * J), _ptr(O, torch.float32, "O", J),
+                            _ptr(lse, torch.float32, "lse", J),
+                            _ptr(dLdO, torch.float32, "dLdO", J), J,
+                            _ptr(grad, torch.float32, "grad", theta.numel()), _stream(stream)))
+
+
+def efunc_fit_step(ctx, theta, m, v, step: int, q, o, loss_out=None, adam: Optional[efunc_adam] = None,
+                   stream=None):
+    J = q.numel() // 3
+    n = theta.numel()
+    _check(lib().efunc_fit_step(ctx, _ptr(theta, torch.float32, "theta"),
+                                _ptr(m, torch.float32, "m", n), _ptr(v, torch.float32, "v", n),
+                                step, C.byref(adam) if adam is not None else None,
+                                _ptr(q, torch.float32, "q", 3 * J), _ptr(o, torch.float32, "o", J),
+                                J, _ptr(loss_out, torch.float64, "loss_out", 2), _stream(stream)))
+
+
+def efunc_get_stats(ctx) -> dict:
+    s = efunc_stats()
+    _check(lib().efunc_get_stats(ctx, C.byref(s)))
+    return s.as_dict()
+
+
+def efunc_set_timing(ctx, enable: bool) -> None:
+    _check(lib().efunc_set_timing(ctx, 1 if enable else 0))
+
+
+def efunc_read_timing(ctx):
+    """(summed tile-kernel milliseconds, launches) since timing was enabled/read."""
+    ms, n = C.c_double(), C.c_int64()
+    _check(lib().efunc_read_timing(ctx, C.byref(ms), C.byref(n)))
+    return ms.value, n.value
+
+
+class Engine:
+    """Owns one efunc context (convenience wrapper over the functions above)."""
+
+    def __init__(self, R: int, max_points: int, **cfg):
+        c = efunc_default_config(R)
+        for k, v in cfg.items():
+            setattr(c, k, v)
+        self.R = R
+        self.cfg = c
+        self.max_points = max_points
+        self.ctx = efunc_create(c, max_points)
+
+    def close(self):
+        if self.ctx:
+            efunc_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+    def eval(self, theta, q, with_lse=True, with_qgrad=False):
+        J = q.shape[0]
+        O = torch.empty(J, device=q.device, dtype=torch.float32)
+        lse = torch.empty(J, device=q.device, dtype=torch.float32) if with_lse else None
+        dq = torch.empty(J, 3, device=q.device, dtype=torch.float32) if with_qgrad else None
+        nu = torch.zeros(1, device=q.device, dtype=torch.int64)
+        efunc_eval(self.ctx, theta, q, O, lse, dq, nu)
+        return O, lse, dq, nu
+
+    def grad(self, theta, q, O, lse, dLdO, grad=None):
+        if grad is None:
+            grad = torch.zeros_like(theta)
+        efunc_grad(self.ctx, theta, q, O, lse, dLdO, grad)
+        return grad
+
+    def fit_step(self, theta, m, v, step, q, o, loss_out=None, adam=None):
+        efunc_fit_step(self.ctx, theta, m, v, step, q, o, loss_out, adam)
+
+    def init_params(self, theta, surf, bandwidth=100.0, rho0=7.0):
+        efunc_init_params(self.ctx, theta, surf, self.R, bandwidth, rho0)
+
+    def stats(self):
+        return efunc_get_stats(self.ctx)

@@ -1,0 +1,107 @@
+"""Shared helpers of the GPU parity tests: device transfer, the oracle
+reference for a problem, and the tolerances.
+
+Tolerances (FP32 GPU against the FP64 oracle):
+  values     |O_gpu - O_ref| <= 1e-5 * sigma_j + 8 u kappa_j, with
+             sigma_j = sum_a w_a |f_a| (the running-error scale of the blended
+             polynomials; plain relative error is meaningless where O ~ 0 on
+             the surface) and kappa_j = sum_a w_a |s_a| |f_a - O_j| (a float32
+             logit carries a few ulps u = 2^-24 of |s_a|; only coarse lattices
+             with large beta, |s| ~ 100, make this term matter).
+  lse        |lse_gpu - lse_ref| <= 1e-5 * (1 + |lse_ref|).
+  gradients  |g_gpu - g_ref| <= 1e-4 * A + 1e-6 * max_channel(A), A the sum of
+             |contributions| per entry; the floor covers terms of relative
+             weight < exp(-T) that a window may omit.
+  Adam       theta from the GPU's own gradient through the oracle's AdamW
+             agrees within 4 float32 ulps of theta plus 1e-6 lr.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+import oracle as orc
+
+DEV = "cuda:0"
+
+
+def to_dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).to(DEV)
+
+
+U32 = 2.0 ** -24
+
+
+def check_values(O, O_ref, sigma, rtol=1e-5, what="O", kappa=None):
+    O = np.asarray(O, dtype=np.float64)
+    err = np.abs(O - O_ref)
+    tol = rtol * sigma + 1e-30
+    if kappa is not None:
+        tol = tol + 8 * U32 * kappa
+    bad = err > tol
+    if bad.any():
+        k = int(np.argmax(err / tol))
+        raise AssertionError(f"{what}: {bad.sum()} of {len(O)} outside {rtol} sigma; worst j={k} "
+                             f"gpu={O[k]!r} ref={O_ref[k]!r} sigma={sigma[k]!r}")
+    return float((err / np.maximum(sigma, 1e-300)).max()) if len(O) else 0.0
+
+
+def check_lse(lse, lse_ref, rtol=1e-5):
+    lse = np.asarray(lse, dtype=np.float64)
+    err = np.abs(lse - lse_ref)
+    tol = rtol * (1.0 + np.abs(lse_ref))
+    assert np.all(err <= tol), f"lse: worst {np.max(err / tol)} x tolerance"
+
+
+def check_grad(g, g_ref, A, rtol=1e-4, floor=1e-6):
+    g = np.asarray(g, dtype=np.float64).reshape(-1, 13)
+    g_ref = g_ref.reshape(-1, 13)
+    A = A.reshape(-1, 13)
+    tol = rtol * A + floor * A.max(axis=0, keepdims=True) + 1e-30
+    err = np.abs(g - g_ref)
+    bad = err > tol
+    if bad.any():
+        i, c = np.unravel_index(np.argmax(err / tol), err.shape)
+        raise AssertionError(f"grad: {bad.sum()} entries out of tolerance; worst vertex {i} ch {c}: "
+                             f"gpu={g[i, c]!r} ref={g_ref[i, c]!r} A={A[i, c]!r}")
+    return float((err / (A + 1e-300)).max())
+
+
+def oracle_values(R, theta, q, offsets=1):
+    g = orc.Grid(R=R, offsets=offsets)
+    keys = orc.build_keys(g, theta)
+    return orc.eval_global(keys, q)
+
+
+def oracle_kappa(R, theta, q, offsets=1):
+    g = orc.Grid(R=R, offsets=offsets)
+    return orc.eval_cond(orc.build_keys(g, theta), q)
+
+
+def reference(R, theta, q, offsets=1):
+    """Oracle values, lse and both error scales under the global definition."""
+    g = orc.Grid(R=R, offsets=offsets)
+    keys = orc.build_keys(g, theta)
+    O, lse, sig = orc.eval_global(keys, q)
+    return dict(O=O, lse=lse, sigma=sig, kappa=orc.eval_cond(keys, q))
+
+
+def check_eval(O, lse, ref):
+    """Values and lse against reference() with the tolerances above; returns
+    the worst |err| / (1e-5 sigma + 8 u kappa)."""
+    worst = check_values(O, ref["O"], ref["sigma"], kappa=ref["kappa"])
+    if lse is not None:
+        check_lse(lse, ref["lse"])
+    return worst
+
+
+def oracle_grad(R, theta, q, dLdO, offsets=1):
+    g = orc.Grid(R=R, offsets=offsets)
+    keys = orc.build_keys(g, theta)
+    gk, ak = orc.grad_global(keys, q, dLdO)
+    return orc.grad_theta(g, theta, gk), orc.grad_theta(g, theta, ak)
+
+
+def ulp32(x):
+    x = np.abs(np.asarray(x, dtype=np.float32))
+    return np.spacing(x).astype(np.float64)

@@ -1,0 +1,66 @@
+"""The C-ABI library loads and exports every entry point declared in
+include/efunc.h; host-side argument validation runs without a GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HDR = os.path.join(ROOT, "include", "efunc.h")
+
+
+def declared():
+    src = open(HDR).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(efunc_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2505_21319_amd import efunc
+    if not os.path.exists(efunc.LIB_PATH):
+        from paper_2505_21319_amd import build
+        build.build()
+    return efunc.lib()
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for n in ["efunc_create", "efunc_destroy", "efunc_init_params", "efunc_eval", "efunc_grad",
+              "efunc_fit_step", "efunc_last_error"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    from paper_2505_21319_amd import efunc
+    assert sorted(efunc.EXPORTS) == declared()
+    for n in declared():
+        assert hasattr(L, n), n
+
+
+def test_defaults(L):
+    from paper_2505_21319_amd import efunc as E
+    c = E.efunc_default_config(32)
+    assert (c.R, c.lo, c.hi, c.offsets, c.t_cut, c.window) == (32, -1.0, 1.0, 1, 20.0, 0)
+    a = E.efunc_default_adam()
+    assert abs(a.lr - 6e-4) < 1e-9 and abs(a.beta2 - 0.999) < 1e-7 and a.weight_decay == 0.0
+
+
+def test_invalid_arguments_are_rejected_before_any_device_work(L):
+    from paper_2505_21319_amd import efunc as E
+    out = C.c_void_p()
+    assert L.efunc_create(None, 10, C.byref(out)) == E.EFUNC_EINVAL
+    c = E.efunc_default_config(1)
+    assert L.efunc_create(C.byref(c), 10, C.byref(out)) == E.EFUNC_EINVAL
+    assert b"R = 1" in L.efunc_last_error()
+    c = E.efunc_default_config(8)
+    c.lo, c.hi = 1.0, -1.0
+    assert L.efunc_create(C.byref(c), 10, C.byref(out)) == E.EFUNC_EINVAL
+    c = E.efunc_default_config(8)
+    assert L.efunc_create(C.byref(c), -5, C.byref(out)) == E.EFUNC_EINVAL
+    c.deterministic = 1
+    assert L.efunc_create(C.byref(c), 5, C.byref(out)) == E.EFUNC_EUNSUPPORTED
+    assert L.efunc_eval(None, None, None, 0, None, None, None, None, None) == E.EFUNC_EINVAL
+    assert L.efunc_fit_step(None, None, None, None, 1, None, None, None, 0, None, None) == E.EFUNC_EINVAL
+    assert L.efunc_destroy(None) == E.EFUNC_OK

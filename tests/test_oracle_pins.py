@@ -474,3 +474,20 @@ def test_fit_step_on_exact_linear_target_is_stationary(orc):
     out = orc.fit_step(g, th, np.zeros(n), np.zeros(n), 1, q, O)
     assert out["loss"] == 0.0
     assert np.array_equal(out["theta"], th.astype(np.float64).reshape(out["theta"].shape))
+
+
+def test_logit_conditioning_scale(orc):
+    """kappa = sum_a w_a |s_a| |f_a - O| vanishes for a constant field and for
+    a single key, and is non-negative."""
+    rng = np.random.default_rng(33)
+    g = orc.Grid(R=3)
+    th = W.perturbed_theta(3, 34)
+    q = rand_q(rng, 50)
+    k = orc.eval_cond(orc.build_keys(g, th), q)
+    assert np.all(k >= 0) and k.max() > 0
+    th[..., [1, 2, 3, 9, 10, 11]] = 0
+    th[..., 0] = 0.25
+    th[..., 8] = 0.25
+    assert np.all(orc.eval_cond(orc.build_keys(g, th), q) <= 1e-14)
+    one = np.array([[0.1, 0.2, 0.3, 40.0, 0.5, 1.0, 2.0, 3.0]])
+    assert np.all(orc.eval_cond(one, q) == 0.0)

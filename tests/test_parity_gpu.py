@@ -1,0 +1,290 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Workloads are the seeded synthetic ones of the workloads package: the tiny
+sphere fit (8^3 grid, 65,536 points) at full size under the global
+definition, plus ragged, degenerate and out-of-domain cases.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as orc
+import workloads as W
+from tests import parity as PT
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def E():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2505_21319_amd import efunc
+    efunc.lib()  # fail loudly if the HIP library is missing
+    return efunc
+
+
+def meanshift_theta(R, w, seed=0):
+    """Paper initialisation computed by the oracle: zero values, rho = 7,
+    mean-shift offsets towards 16,384 surface samples."""
+    th = W.plain_theta(R)
+    surf = W.surface_points(w, 16384, seed=seed)
+    D = orc.meanshift(orc.Grid(R=R), surf, 100.0)
+    th[..., 5:8] = D.reshape(R, R, R, 3).astype(np.float32)
+    return th, surf
+
+
+def run_eval(E, R, th, q, max_points=None, **cfg):
+    with E.Engine(R, max_points or max(len(q), 1), **cfg) as eng:
+        O, lse, _, nu = eng.eval(PT.to_dev(th), PT.to_dev(q))
+        torch.cuda.synchronize()
+        st = eng.stats()
+    return O.cpu().numpy(), lse.cpu().numpy(), int(nu.item()), st
+
+
+# ------------------------------------------------------------------ init
+def test_init_params_meanshift_matches_oracle(E):
+    R = 8
+    w = W.get("sphere_r8")
+    surf = W.surface_points(w, 16384, seed=0)
+    with E.Engine(R, 16) as eng:
+        th = torch.empty(R, R, R, 13, device=PT.DEV)
+        eng.init_params(th, PT.to_dev(surf), 100.0, 7.0)
+        torch.cuda.synchronize()
+        th = th.cpu().numpy()
+    D = orc.meanshift(orc.Grid(R=R), surf, 100.0).reshape(R, R, R, 3)
+    assert np.all(th[..., [0, 1, 2, 3, 8, 9, 10, 11]] == 0.0)
+    assert np.all(th[..., [4, 12]] == 7.0)
+    assert np.allclose(th[..., 5:8], D, rtol=0, atol=2e-6)
+
+
+# ------------------------------------------------------------------ eval
+@pytest.mark.parametrize("init", ["paper", "perturbed"])
+def test_eval_sphere_r8_full(E, init):
+    R = 8
+    w = W.get("sphere_r8")
+    q, o = W.make_batch(w, 0)
+    th = meanshift_theta(R, w)[0] if init == "paper" else W.perturbed_theta(R, 3)
+    O, lse, nu, st = run_eval(E, R, th, q)
+    ref = PT.reference(R, th, q)
+    worst = PT.check_eval(O, lse, ref)
+    assert nu == 0
+    print(f"worst err/sigma {worst:.2e}, W={st['W']}, tiles={st['n_tiles']}, pairs={st['pairs']}")
+
+
+@pytest.mark.parametrize("J", [1, 7, 255, 257, 1000])
+def test_eval_ragged_sizes(E, J):
+    R = 5
+    w = W.get("sphere_r8")
+    q, _ = W.make_batch(w, 11, J=J)
+    th = W.perturbed_theta(R, 4, rho0=5.0)
+    O, lse, nu, _ = run_eval(E, R, th, q, max_points=1024)
+    ref = PT.reference(R, th, q)
+    PT.check_eval(O, lse, ref)
+
+
+def test_eval_j0_is_noop(E):
+    R = 4
+    with E.Engine(R, 8) as eng:
+        th = PT.to_dev(W.perturbed_theta(R, 0))
+        q = torch.empty(0, 3, device=PT.DEV)
+        O = torch.empty(0, device=PT.DEV)
+        E.efunc_eval(eng.ctx, th, q, O)
+        g = torch.zeros_like(th)
+        E.efunc_grad(eng.ctx, th, q, O, O, O, g)
+        m, v = torch.zeros_like(th), torch.zeros_like(th)
+        th0 = th.clone()
+        E.efunc_fit_step(eng.ctx, th, m, v, 1, q, O)
+        torch.cuda.synchronize()
+        assert torch.equal(th, th0) and not g.any()
+
+
+def test_eval_outside_domain_uses_fallback(E):
+    """Queries far outside the lattice fail the window certificate and are
+    evaluated against every key; results still match the definition."""
+    R = 6
+    rng = np.random.default_rng(5)
+    q = rng.uniform(-1.8, 1.8, size=(3000, 3)).astype(np.float32)
+    th = W.perturbed_theta(R, 6, rho0=4.0)
+    O, lse, nu, _ = run_eval(E, R, th, q)
+    ref = PT.reference(R, th, q)
+    PT.check_eval(O, lse, ref)
+    assert nu > 0
+
+
+def test_eval_forced_small_window_falls_back(E):
+    """A forced window of one cell cannot certify most queries at R = 16;
+    the fallback must still reproduce the global result."""
+    R = 16
+    w = W.get("sphere_r8")
+    q, _ = W.make_batch(w, 2, J=4096)
+    th = W.perturbed_theta(R, 7, rho0=7.0)
+    O, lse, nu, st = run_eval(E, R, th, q, window=1)
+    ref = PT.reference(R, th, q)
+    PT.check_eval(O, lse, ref)
+    assert st["W"] == 1 and nu > 100
+
+
+def test_eval_coarse_lattice_exact_max_path(E):
+    """R = 4 with beta = exp(7): every logit is below -300 nats away from the
+    vertices, so the kernel takes the exact-maximum pass."""
+    R = 4
+    w = W.get("sphere_r8")
+    q, _ = W.make_batch(w, 3, J=5000)
+    th = W.perturbed_theta(R, 8, rho0=7.0, rho_spread=0.3)
+    O, lse, nu, _ = run_eval(E, R, th, q)
+    ref = PT.reference(R, th, q)
+    PT.check_eval(O, lse, ref)
+
+
+def test_eval_grid_keys_only(E):
+    R = 8
+    w = W.get("sphere_r8")
+    q, _ = W.make_batch(w, 4, J=8192)
+    th = W.perturbed_theta(R, 9)
+    O, lse, nu, _ = run_eval(E, R, th, q, offsets=0)
+    ref = PT.reference(R, th, q, offsets=0)
+    PT.check_eval(O, lse, ref)
+
+
+def test_eval_queries_on_lattice_vertices_and_faces(E):
+    R = 7
+    t = np.linspace(-1, 1, R).astype(np.float32)
+    V = np.stack(np.meshgrid(t, t, t, indexing="ij"), -1).reshape(-1, 3)
+    F = V.copy()
+    F[:, 0] = np.clip(F[:, 0] + (t[1] - t[0]) / 2, -1, 1)
+    q = np.concatenate([V, F]).astype(np.float32)
+    th = W.perturbed_theta(R, 10)
+    O, lse, nu, _ = run_eval(E, R, th, q)
+    ref = PT.reference(R, th, q)
+    PT.check_eval(O, None, ref)
+
+
+def test_query_gradient_matches_oracle(E):
+    R = 6
+    w = W.get("sphere_r8")
+    q, _ = W.make_batch(w, 5, J=3000)
+    th = W.perturbed_theta(R, 11, rho0=5.0)
+    with E.Engine(R, len(q)) as eng:
+        _, _, dq, _ = eng.eval(PT.to_dev(th), PT.to_dev(q), with_qgrad=True)
+        torch.cuda.synchronize()
+        dq = dq.cpu().numpy().astype(np.float64)
+    keys = orc.build_keys(orc.Grid(R=R), th)
+    ref = orc.eval_qgrad(keys, q)
+    # scale: sum_a w_a (|d_a| + 2 beta_a |x| |O - f_a|), bounded through sigma and beta
+    scale = np.abs(ref).max() + 1.0
+    assert np.allclose(dq, ref, rtol=0, atol=2e-4 * scale)
+
+
+# ------------------------------------------------------------------ grad
+@pytest.mark.parametrize("init", ["paper", "perturbed"])
+def test_grad_sphere_r8_full(E, init):
+    R = 8
+    w = W.get("sphere_r8")
+    q, o = W.make_batch(w, 1)
+    th = meanshift_theta(R, w)[0] if init == "paper" else W.perturbed_theta(R, 12)
+    Or, lr, _ = PT.oracle_values(R, th, q)
+    rng = np.random.default_rng(13)
+    dl = rng.standard_normal(len(q)) / len(q)
+    with E.Engine(R, len(q)) as eng:
+        tth = PT.to_dev(th)
+        G = eng.grad(tth, PT.to_dev(q), PT.to_dev(Or), PT.to_dev(lr), PT.to_dev(dl))
+        torch.cuda.synchronize()
+        G = G.cpu().numpy()
+    gr, ar = PT.oracle_grad(R, th, q, dl)
+    PT.check_grad(G, gr, ar)
+
+
+def test_grad_accumulates_into_caller_buffer(E):
+    R = 5
+    w = W.get("sphere_r8")
+    q, _ = W.make_batch(w, 6, J=2000)
+    th = W.perturbed_theta(R, 14, rho0=5.0)
+    Or, lr, _ = PT.oracle_values(R, th, q)
+    dl = np.random.default_rng(1).standard_normal(len(q))
+    with E.Engine(R, len(q)) as eng:
+        tth = PT.to_dev(th)
+        base = torch.full_like(tth, 0.5)
+        G = eng.grad(tth, PT.to_dev(q), PT.to_dev(Or), PT.to_dev(lr), PT.to_dev(dl), grad=base)
+        torch.cuda.synchronize()
+        G = G.cpu().numpy()
+    gr, ar = PT.oracle_grad(R, th, q, dl)
+    PT.check_grad(G - 0.5, gr, ar + 1e-7)
+
+
+def test_grad_outside_domain_fallback(E):
+    R = 6
+    rng = np.random.default_rng(7)
+    q = rng.uniform(-1.8, 1.8, size=(2000, 3)).astype(np.float32)
+    th = W.perturbed_theta(R, 15, rho0=4.0)
+    Or, lr, _ = PT.oracle_values(R, th, q)
+    dl = rng.standard_normal(len(q))
+    with E.Engine(R, len(q)) as eng:
+        G = eng.grad(PT.to_dev(th), PT.to_dev(q), PT.to_dev(Or), PT.to_dev(lr), PT.to_dev(dl))
+        torch.cuda.synchronize()
+        st = eng.stats()
+        G = G.cpu().numpy()
+    gr, ar = PT.oracle_grad(R, th, q, dl)
+    PT.check_grad(G, gr, ar)
+    assert st["n_uncertified"] > 0
+
+
+# --------------------------------------------------------------- fit step
+@pytest.mark.parametrize("init", ["paper", "perturbed"])
+def test_fit_step_sphere_r8_full(E, init):
+    """One forward + backward + AdamW step on the full tiny workload against
+    the oracle under the global definition."""
+    R = 8
+    w = W.get("sphere_r8")
+    q, o = W.make_batch(w, 0)
+    th = meanshift_theta(R, w)[0] if init == "paper" else W.perturbed_theta(R, 16)
+    n = th.size
+    with E.Engine(R, len(q)) as eng:
+        tth = PT.to_dev(th)
+        m = torch.zeros(n, device=PT.DEV)
+        v = torch.zeros(n, device=PT.DEV)
+        loss = torch.zeros(2, device=PT.DEV, dtype=torch.float64)
+        eng.fit_step(tth, m, v, 1, PT.to_dev(q), PT.to_dev(o), loss)
+        torch.cuda.synchronize()
+        th1, m1, v1, loss = (x.cpu().numpy() for x in (tth, m, v, loss))
+    ref = orc.fit_step(orc.Grid(R=R), th, np.zeros(n), np.zeros(n), 1, q, o)
+    assert abs(loss[0] - ref["loss"]) <= 1e-5 * ref["loss"]
+    assert abs(loss[1] - ref["l1"]) <= 1e-5 * ref["l1"]
+    # the GPU's gradient, recovered from the first moment m = (1 - beta1) g
+    g_gpu = m1.astype(np.float64) / (1.0 - np.float32(0.9))
+    O, _, _ = PT.oracle_values(R, th, q)
+    _, ar = PT.oracle_grad(R, th, q, 2 * (O - o) / len(q))
+    PT.check_grad(g_gpu, ref["grad"], ar)
+    # AdamW on the GPU's own gradient
+    th_ref, _, _ = orc.adam(th.reshape(-1), np.zeros(n), np.zeros(n), g_gpu.reshape(-1), 1)
+    tol = 4 * PT.ulp32(th_ref) + 1e-6 * 6e-4
+    assert np.all(np.abs(th1.reshape(-1) - th_ref) <= tol)
+    # the library takes the hyper-parameters as float32: 1 - fl32(0.999)
+    b2 = float(np.float32(0.999))
+    assert np.allclose(v1.reshape(-1), (1 - b2) * g_gpu.reshape(-1) ** 2, rtol=1e-5, atol=1e-37)
+
+
+def test_second_fit_step_starts_from_clean_gradient(E):
+    """Step 2 reports the loss of the parameters after step 1 and uses only
+    their gradient: the internal gradient buffer is cleared by the update."""
+    R = 6
+    w = W.get("sphere_r8")
+    q, o = W.make_batch(w, 9, J=20000)
+    th = W.perturbed_theta(R, 17, rho0=5.0)
+    n = th.size
+    with E.Engine(R, len(q)) as eng:
+        tth = PT.to_dev(th)
+        m = torch.zeros(n, device=PT.DEV)
+        v = torch.zeros(n, device=PT.DEV)
+        loss = torch.zeros(2, device=PT.DEV, dtype=torch.float64)
+        tq, to = PT.to_dev(q), PT.to_dev(o)
+        eng.fit_step(tth, m, v, 1, tq, to, loss)
+        th1, m1 = tth.clone(), m.clone()
+        eng.fit_step(tth, m, v, 2, tq, to, loss)
+        torch.cuda.synchronize()
+        th1, m1, m2, l2 = (x.cpu().numpy() for x in (th1, m1, m, loss))
+    O1, _, _ = PT.oracle_values(R, th1, q)
+    assert abs(l2[0] - np.mean((O1 - o) ** 2)) <= 1e-5 * np.mean((O1 - o) ** 2)
+    g2 = (m2.astype(np.float64) - np.float32(0.9) * m1.astype(np.float64)) / (1 - np.float32(0.9))
+    gr, ar = PT.oracle_grad(R, th1, q, 2 * (O1 - o) / len(q))
+    # the subtraction of the rescaled first moment adds a few ulps of m1
+    PT.check_grad(g2, gr, ar + 20 * PT.ulp32(m1).reshape(ar.shape))
