@@ -164,9 +164,9 @@ def main():
     ms_step = total_ms / args.steps
     value = J * args.steps / (total_ms * 1e-3)
     tile_avg_s = tile_ms / max(launches, 1) * 1e-3
-    pairs = st["pairs"]
-    pm = st["pairs_moved"]
-    ops = pairs * OPS_FWD + (pairs - pm) * OPS_BWD_GRID + pm * OPS_BWD_MOVED
+    pairs, pm = st["pairs"], st["pairs_moved"]
+    bp, bpm = st["bwd_pairs"], st["bwd_pairs_moved"]
+    ops = pairs * OPS_FWD + (bp - bpm) * OPS_BWD_GRID + bpm * OPS_BWD_MOVED
     achieved = ops / tile_avg_s
     traffic = measured_traffic(args.workload)
 
@@ -204,8 +204,10 @@ def main():
             "frac": achieved / ROOFLINE_PEAK,
             "traffic": traffic,
             "tile_kernel_ms": tile_avg_s * 1e3,
-            "pairs_per_launch": pairs,
-            "moved_pairs_per_launch": pm,
+            "fwd_pairs_per_launch": pairs,
+            "fwd_moved_pairs_per_launch": pm,
+            "bwd_pairs_per_launch": bp,
+            "bwd_moved_pairs_per_launch": bpm,
             "ops_per_launch": ops,
         },
         "stats": {"W": st["W"], "tiles": st["n_tiles"], "uncertified": st["n_uncertified"],

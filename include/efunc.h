@@ -79,8 +79,10 @@ typedef struct {
     int32_t W;              /* window half-width in cells */
     int32_t n_tiles;        /* point tiles processed */
     int64_t n_uncertified;  /* queries evaluated against all keys */
-    int64_t pairs;          /* key-query pairs in windows (one pass) */
+    int64_t pairs;          /* key-query pairs evaluated by the forward */
     int64_t pairs_moved;    /* of which with moved keys */
+    int64_t bwd_pairs;      /* key-query pairs evaluated by the backward */
+    int64_t bwd_pairs_moved;/* of which with moved keys */
     float beta_min;         /* smallest scale over all keys */
     float beta_grid_max;    /* largest scale over grid keys */
     int32_t n_nonfinite;    /* non-finite parameters seen by the last call */

@@ -218,9 +218,13 @@ int efunc_create(const efunc_config* cfg, int64_t max_points, efunc_ctx** out)
     w.I = I;
     w.C = C;
     w.max_points = max_points;
-    w.max_tiles = mp / PMAX + (C < mp ? C : mp) + 1;
+    const int64_t NB = (C1 + 1) / 2;
+    w.NB3 = NB * NB * NB;
+    w.NK = 8 * w.NB3;
+    // one tile per block with <= PMAX queries, else <= n/PMAX + 1 per cell
+    w.max_tiles = mp / PMAX + 8 * (mp / PMAX + 1) + (w.NB3 < mp ? w.NB3 : mp) + 1;
     w.num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
-    const int64_t nblk = (C + 1 + SCAN_TILE - 1) / SCAN_TILE;
+    const int64_t nblk = (w.NK + 1 + SCAN_TILE - 1) / SCAN_TILE;
 
     hipError_t err = hipSuccess;
 #define ALLOC(ptr, n) \
@@ -235,9 +239,10 @@ int efunc_create(const efunc_config* cfg, int64_t max_points, efunc_ctx** out)
     ALLOC(w.mk, 3 * I);
     ALLOC(w.pcell, mp);
     ALLOC(w.prank, mp);
-    ALLOC(w.pcount, C);
-    ALLOC(w.pstart, C + 1);
-    ALLOC(w.tstart, C + 1);
+    ALLOC(w.pcount, w.NK);
+    ALLOC(w.pstart, w.NK + 1);
+    ALLOC(w.btiles, w.NB3);
+    ALLOC(w.tstart, w.NB3 + 1);
     ALLOC(w.tiles, w.max_tiles);
     ALLOC(w.ps, mp);
     ALLOC(w.pv, mp);
@@ -266,6 +271,7 @@ int efunc_create(const efunc_config* cfg, int64_t max_points, efunc_ctx** out)
     Geo& g = c->geo;
     g.R = (int)R;
     g.C1 = (int)C1;
+    g.NB = (int)NB;
     g.lo = cfg->lo;
     g.hi = cfg->hi;
     g.lo_d = cfg->lo;
@@ -419,7 +425,7 @@ int efunc_get_stats(efunc_ctx* ctx, efunc_stats* out)
     hipStream_t s = ctx->last_stream;
     hipError_t e = hipMemcpyAsync(&st, ctx->w.st, sizeof(st), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(&ntiles, ctx->w.tstart + ctx->w.C, sizeof(int), hipMemcpyDeviceToHost, s);
+        e = hipMemcpyAsync(&ntiles, ctx->w.tstart + ctx->w.NB3, sizeof(int), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "stats readback");
     out->W = st.W;
@@ -427,6 +433,8 @@ int efunc_get_stats(efunc_ctx* ctx, efunc_stats* out)
     out->n_uncertified = st.nfb;
     out->pairs = (int64_t)st.pairs;
     out->pairs_moved = (int64_t)st.pairs_moved;
+    out->bwd_pairs = (int64_t)st.bwd_pairs;
+    out->bwd_pairs_moved = (int64_t)st.bwd_pairs_moved;
     uint32_t b = st.bmin_bits, gb = st.bgmax_bits;
     memcpy(&out->beta_min, &b, 4);
     memcpy(&out->beta_grid_max, &gb, 4);

@@ -9,7 +9,7 @@ namespace efunc {
 
 constexpr int NCH = 13;
 constexpr int BLOCK = 256;      // threads per workgroup (4 wave64)
-constexpr int PMAX = 256;       // queries per tile
+constexpr int PMAX = 512;       // queries per tile (two per thread at most)
 constexpr int KC = 256;         // keys per LDS chunk
 constexpr int MAXSEG = 1024;    // moved-key row segments per window ((2W+1)^2, W <= 15)
 constexpr int WMAX = 15;        // largest window half-width
@@ -29,6 +29,8 @@ struct DevStats {
     int pad;
     unsigned long long pairs; // key-query pairs in windows
     unsigned long long pairs_moved;  // of which with moved keys
+    unsigned long long bwd_pairs;    // pairs evaluated by the backward (after block truncation)
+    unsigned long long bwd_pairs_moved;
     double fb_loss[2];        // loss sums of fallback queries
 };
 
@@ -36,6 +38,7 @@ struct DevStats {
 struct Geo {
     int R;         // vertices per axis
     int C1;        // cells per axis = R - 1
+    int NB;        // 2x2x2 cell blocks per axis = ceil(C1 / 2)
     float lo, hi;
     float h, inv_h;
     double lo_d, h_d, inv_h_d;
@@ -45,6 +48,7 @@ struct Geo {
 // Device workspace owned by a context.
 struct Work {
     int64_t I, C, max_points, max_tiles;
+    int64_t NB3, NK;      // cell blocks; query sort keys = 8 NB3 (block-major cell order)
     float* tlat;          // [R]
     float4* gk;           // [2 I]  grid key records {nb, o, d.x, d.y}, {d.z, beta, 0, 0}
     int* mcell;           // [I]    cell of each moved key
@@ -54,12 +58,13 @@ struct Work {
     float4* mrec;         // [3 I]  moved key records by vertex
     float4* mk;           // [3 I]  moved key records binned by cell:
                           //        {c_hi.xyz, nb}, {o', d'.xyz}, {c_lo.xyz, vid bits}
-    int* pcell;           // [max_points]
+    int* pcell;           // [max_points] sort key of each query
     int* prank;           // [max_points]
-    int* pcount;          // [C]
-    int* pstart;          // [C+1]
-    int* tstart;          // [C+1]
-    int4* tiles;          // [max_tiles]  {cell, first, count, 0}
+    int* pcount;          // [NK]   queries per cell, block-major order
+    int* pstart;          // [NK+1]
+    int* btiles;          // [NB3]  tiles per cell block
+    int* tstart;          // [NB3+1]
+    int4* tiles;          // [max_tiles]  {first cell, first query, count, extent bits}
     float4* ps;           // [max_points] {q.xyz, aux}
     float4* pv;           // [max_points] {O, lse, 0, 0} (backward inputs)
     int* pidx;            // [max_points] original query index

@@ -123,6 +123,8 @@ __global__ void k_reset_stats(DevStats* st)
         st->pad = 0;
         st->pairs = 0ull;
         st->pairs_moved = 0ull;
+        st->bwd_pairs = 0ull;
+        st->bwd_pairs_moved = 0ull;
         st->fb_loss[0] = 0.0;
         st->fb_loss[1] = 0.0;
     }
@@ -330,13 +332,21 @@ __global__ void k_scatter_keys(int64_t I, const int* __restrict__ mcell, const i
 }
 
 // ------------------------------------------------------------ query binning
+// Queries are sorted by lattice cell in block-major order: 2x2x2 blocks of
+// cells, the 8 cells of a block consecutive, so that a block's queries are
+// contiguous whether it becomes one tile or eight.
+__device__ __forceinline__ int order_key(int cx, int cy, int cz, int NB)
+{
+    return (((cx >> 1) * NB + (cy >> 1)) * NB + (cz >> 1)) * 8 + ((cx & 1) << 2) + ((cy & 1) << 1) +
+           (cz & 1);
+}
+
 __global__ void k_count_points(const float* __restrict__ q, int64_t J, Geo g, int* __restrict__ pcell,
                                int* __restrict__ prank, int* __restrict__ pcount)
 {
     const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (j >= J) return;
-    const int c = (cell_of(q[3 * j], g) * g.C1 + cell_of(q[3 * j + 1], g)) * g.C1 +
-                  cell_of(q[3 * j + 2], g);
+    const int c = order_key(cell_of(q[3 * j], g), cell_of(q[3 * j + 1], g), cell_of(q[3 * j + 2], g), g.NB);
     pcell[j] = c;
     prank[j] = atomicAdd(&pcount[c], 1);
 }
@@ -356,18 +366,52 @@ __global__ void k_scatter_points(const float* __restrict__ q, const float* __res
     pidx[pos] = (int)j;
 }
 
-// Balanced slices of at most PMAX queries per non-empty cell.
-__global__ void k_build_tiles(int64_t C, const int* __restrict__ pcount, const int* __restrict__ pstart,
-                              const int* __restrict__ tstart, int4* __restrict__ tiles)
+// Tiles per block: a block with at most PMAX queries is one tile spanning its
+// cells; otherwise each cell gets balanced slices of at most PMAX queries.
+__global__ void k_block_tiles(int64_t NB3, const int* __restrict__ pcount, int* __restrict__ btiles)
 {
-    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (c >= C) return;
-    const int n = pcount[c];
-    if (n == 0) return;
-    const int t0 = tstart[c], nt = tstart[c + 1] - t0;
-    for (int k = 0; k < nt; ++k) {
-        const int a = (int)((int64_t)k * n / nt), b = (int)((int64_t)(k + 1) * n / nt);
-        tiles[t0 + k] = make_int4((int)c, pstart[c] + a, b - a, 0);
+    const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (b >= NB3) return;
+    int tot = 0, split = 0;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const int n = pcount[8 * b + s];
+        tot += n;
+        split += (n + PMAX - 1) / PMAX;
+    }
+    btiles[b] = tot == 0 ? 0 : (tot <= PMAX ? 1 : split);
+}
+
+__global__ void k_build_tiles(int64_t NB3, Geo g, const int* __restrict__ pcount,
+                              const int* __restrict__ pstart, const int* __restrict__ tstart,
+                              int4* __restrict__ tiles)
+{
+    const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (b >= NB3) return;
+    const int nt = tstart[b + 1] - tstart[b];
+    if (nt == 0) return;
+    const int NB = g.NB, C1 = g.C1;
+    const int bx = (int)(b / ((int64_t)NB * NB)), by = (int)((b / NB) % NB), bz = (int)(b % NB);
+    int t = tstart[b];
+    int tot = 0;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) tot += pcount[8 * b + s];
+    if (tot <= PMAX) {
+        const int ex = min(2, C1 - 2 * bx), ey = min(2, C1 - 2 * by), ez = min(2, C1 - 2 * bz);
+        const int c0 = ((2 * bx) * C1 + 2 * by) * C1 + 2 * bz;
+        tiles[t] = make_int4(c0, pstart[8 * b], tot, (ex - 1) | ((ey - 1) << 1) | ((ez - 1) << 2));
+        return;
+    }
+    for (int s = 0; s < 8; ++s) {
+        const int n = pcount[8 * b + s];
+        if (n == 0) continue;
+        const int cx = 2 * bx + (s >> 2), cy = 2 * by + ((s >> 1) & 1), cz = 2 * bz + (s & 1);
+        const int c = (cx * C1 + cy) * C1 + cz;
+        const int k = (n + PMAX - 1) / PMAX;
+        for (int i = 0; i < k; ++i) {
+            const int lo = (int)((int64_t)i * n / k), hi = (int)((int64_t)(i + 1) * n / k);
+            tiles[t++] = make_int4(c, pstart[8 * b + s] + lo, hi - lo, 0);
+        }
     }
 }
 
@@ -396,14 +440,20 @@ struct TileArgs {
 };
 
 struct TileSmem {
-    float4 kc[KC];        // key centre relative to the tile origin, nb = -beta log2(e)
-    float4 kv[KC];        // o, d.xyz
-    int kid[KC];          // vertex index
+    union {
+        struct {
+            float4 kc[KC];    // key centre relative to the tile origin, nb = -beta log2(e)
+            float4 kv[KC];    // o, d.xyz
+        };
+        float fv[8 * KC];     // backward flush: 8 channel values per kept key
+    };
+    int kid[KC];          // vertex index; -(vid + 1) for moved keys
     float4 pq[PMAX];      // query relative to the tile origin, aux (target or dL/dO)
     float4 pv[PMAX];      // O, lse2 (log2 units), g = dL/dO, reference exponent
-    float2 red[BLOCK];
+    float2 red[PMAX];
     int seg_src[MAXSEG];
     int seg_off[MAXSEG + 1];
+    float box[BLOCK / 64][8];  // per-wave bounds of the contributing queries
     int isc[BLOCK / 64];
     float fsc[BLOCK / 64];
     double dsc[BLOCK / 64];
@@ -439,9 +489,107 @@ __device__ __forceinline__ void bwd_key(const TileSmem& S, int P, int ph, int Sb
     }
 }
 
+// Bounds of a set of tile queries: box (x0, y0, z0, x1, y1, z1) and the
+// smallest value of one per-query field; every thread receives them.
+__device__ void tile_bounds(const TileSmem& S, float (&bl)[7], float* __restrict__ shbox)
+{
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int t = 0; t < 3; ++t) bl[t] = fminf(bl[t], __shfl_xor(bl[t], off, 64));
+#pragma unroll
+        for (int t = 3; t < 6; ++t) bl[t] = fmaxf(bl[t], __shfl_xor(bl[t], off, 64));
+        bl[6] = fminf(bl[6], __shfl_xor(bl[6], off, 64));
+    }
+    __syncthreads();
+    if ((tid & 63) == 0) {
+#pragma unroll
+        for (int t = 0; t < 7; ++t) shbox[(tid >> 6) * 8 + t] = bl[t];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int wv = 0; wv < BLOCK / 64; ++wv) {
+#pragma unroll
+        for (int t = 0; t < 3; ++t) bl[t] = fminf(bl[t], shbox[wv * 8 + t]);
+#pragma unroll
+        for (int t = 3; t < 6; ++t) bl[t] = fmaxf(bl[t], shbox[wv * 8 + t]);
+        bl[6] = fminf(bl[6], shbox[wv * 8 + 6]);
+    }
+    (void)S;
+}
+
+// Largest logit (log2 units, <= 0) any query inside the box can have against
+// a key centre: nb times the squared distance from the centre to the box.
+__device__ __forceinline__ float box_logit(const float (&bl)[7], float4 kc)
+{
+    const float dx = fmaxf(fmaxf(bl[0] - kc.x, kc.x - bl[3]), 0.0f);
+    const float dy = fmaxf(fmaxf(bl[1] - kc.y, kc.y - bl[4]), 0.0f);
+    const float dz = fmaxf(fmaxf(bl[2] - kc.z, kc.z - bl[5]), 0.0f);
+    return kc.w * fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+}
+
+// Forward sums over one staged chunk: keys k = ph, ph + Sf, ... against the
+// lane's NPL queries (Alg. 1 with the reference exponent M).
+template <int NPL>
+__device__ __forceinline__ void fwd_sums(const TileSmem& S, int n, int ph, int Sf, const float4 (&q)[NPL],
+                                         const float (&M)[NPL], float (&e)[NPL], float (&m)[NPL])
+{
+#pragma unroll(4 / NPL)
+    for (int k = ph; k < n; k += Sf) {
+        const float4 kc = S.kc[k], kv = S.kv[k];
+#pragma unroll
+        for (int i = 0; i < NPL; ++i) {
+            const float dx = q[i].x - kc.x, dy = q[i].y - kc.y, dz = q[i].z - kc.z;
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            const float l = ex2(fmaf(kc.w, r2, -M[i]));
+            const float f = fmaf(dx, kv.y, fmaf(dy, kv.z, fmaf(dz, kv.w, kv.x)));
+            e[i] += l;
+            m[i] = fmaf(l, f, m[i]);
+        }
+    }
+}
+
+template <int NPL>
+__device__ __forceinline__ void fwd_max(const TileSmem& S, int n, int ph, int Sf, const float4 (&q)[NPL],
+                                        float (&M)[NPL])
+{
+    for (int k = ph; k < n; k += Sf) {
+        const float4 kc = S.kc[k];
+#pragma unroll
+        for (int i = 0; i < NPL; ++i) {
+            const float dx = q[i].x - kc.x, dy = q[i].y - kc.y, dz = q[i].z - kc.z;
+            M[i] = fmaxf(M[i], kc.w * fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+        }
+    }
+}
+
+// dO/dq = sum_a w_a [d_a + 2 beta_a x (O - f_a)]  (Eq. func-normal)
+template <int NPL>
+__device__ __forceinline__ void fwd_qgrad(const TileSmem& S, int n, int ph, int Sf, const float4 (&q)[NPL],
+                                          const float (&O)[NPL], const float (&L)[NPL],
+                                          float (&gx)[NPL], float (&gy)[NPL], float (&gz)[NPL])
+{
+    for (int k = ph; k < n; k += Sf) {
+        const float4 kc = S.kc[k], kv = S.kv[k];
+#pragma unroll
+        for (int i = 0; i < NPL; ++i) {
+            const float dx = q[i].x - kc.x, dy = q[i].y - kc.y, dz = q[i].z - kc.z;
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            const float w = ex2(fmaf(kc.w, r2, -L[i]));
+            const float f = fmaf(dx, kv.y, fmaf(dy, kv.z, fmaf(dz, kv.w, kv.x)));
+            const float t = -2.0f * LN2 * kc.w * (O[i] - f) * w;  // 2 beta (O - f) w
+            gx[i] += fmaf(w, kv.y, t * dx);
+            gy[i] += fmaf(w, kv.z, t * dy);
+            gz[i] += fmaf(w, kv.w, t * dz);
+        }
+    }
+}
+
 template <int MODE, bool QGRAD>
 __global__ __launch_bounds__(BLOCK) void k_tile(TileArgs a)
 {
+    static_assert(KC == BLOCK, "one staged key per thread");
     __shared__ TileSmem S;
     const int tid = threadIdx.x;
     const Geo& g = a.g;
@@ -458,19 +606,21 @@ __global__ __launch_bounds__(BLOCK) void k_tile(TileArgs a)
         if (tile >= ntiles) break;
         const int4 td = a.tiles[tile];
         const int cell = td.x, p0 = td.y, P = td.z;
+        // the tile covers cells [c0, c1] per axis (one cell or a 2x2x2 block)
         const int cx = cell / (C1 * C1), cy = (cell / C1) % C1, cz = cell % C1;
+        const int cx1 = cx + (td.w & 1), cy1 = cy + ((td.w >> 1) & 1), cz1 = cz + ((td.w >> 2) & 1);
 
         // ---- window: grid vertices and moved-key row segments
-        const int vx0 = max(cx - W + 1, 0), vx1 = min(cx + W, R - 1);
-        const int vy0 = max(cy - W + 1, 0), vy1 = min(cy + W, R - 1);
-        const int vz0 = max(cz - W + 1, 0), vz1 = min(cz + W, R - 1);
+        const int vx0 = max(cx - W + 1, 0), vx1 = min(cx1 + W, R - 1);
+        const int vy0 = max(cy - W + 1, 0), vy1 = min(cy1 + W, R - 1);
+        const int vz0 = max(cz - W + 1, 0), vz1 = min(cz1 + W, R - 1);
         const int nvy = vy1 - vy0 + 1, nvz = vz1 - vz0 + 1;
         const int Kg = (vx1 - vx0 + 1) * nvy * nvz;
         int Km = 0, nseg = 0;
         if (a.offsets) {
-            const int mx0 = max(cx - W, 0), mx1 = min(cx + W, C1 - 1);
-            const int my0 = max(cy - W, 0), my1 = min(cy + W, C1 - 1);
-            const int mz0 = max(cz - W, 0), mz1 = min(cz + W, C1 - 1);
+            const int mx0 = max(cx - W, 0), mx1 = min(cx1 + W, C1 - 1);
+            const int my0 = max(cy - W, 0), my1 = min(cy1 + W, C1 - 1);
+            const int mz0 = max(cz - W, 0), mz1 = min(cz1 + W, C1 - 1);
             const int nmy = my1 - my0 + 1;
             nseg = (mx1 - mx0 + 1) * nmy;
             for (int base = 0; base < nseg; base += BLOCK) {
@@ -503,20 +653,26 @@ __global__ __launch_bounds__(BLOCK) void k_tile(TileArgs a)
             }
         }
 
-        // stage window keys [k0, k0 + nk) into LDS slots [0, nk)
-        auto stage = [&](int k0, int nk) {
-            for (int k = tid; k < nk; k += BLOCK) {
-                const int kk = k0 + k;
-                float4 kc, kv;
-                int vid;
+        int nmoved = 0;  // moved keys among the last staged/reculled set
+        // Stage window keys [k0, k0 + nk) (nk <= BLOCK, one per thread) and keep
+        // those whose largest logit against the query box is >= cutoff: every
+        // dropped pair has weight below 2^(cutoff - lse2) <= e^-T.  Kept keys are
+        // compacted to LDS slots [0, n); moved keys carry the tag -(vid + 1).
+        auto stage_cull = [&](int k0, int nk, const float (&bl)[7], float cutoff) -> int {
+            float4 kc = make_float4(0, 0, 0, 0), kv = make_float4(0, 0, 0, 0);
+            int tag = 0;
+            bool keep = false;
+            if (tid < nk) {
+                const int kk = k0 + tid;
                 if (kk < Kg) {
                     const int ix = vx0 + kk / (nvy * nvz), rr = kk % (nvy * nvz);
                     const int iy = vy0 + rr / nvz, iz = vz0 + rr % nvz;
-                    vid = (ix * R + iy) * R + iz;
+                    const int vid = (ix * R + iy) * R + iz;
                     const float4 a0 = a.gk[2 * (int64_t)vid], a1 = a.gk[2 * (int64_t)vid + 1];
                     kc = make_float4((float)((double)g.tlat[ix] - ox), (float)((double)g.tlat[iy] - oy),
                                      (float)((double)g.tlat[iz] - oz), a0.x);
                     kv = make_float4(a0.y, a0.z, a0.w, a1.x);
+                    tag = vid;
                 } else {
                     const int km = kk - Kg;
                     int lo = 0, hi = nseg - 1;
@@ -530,27 +686,62 @@ __global__ __launch_bounds__(BLOCK) void k_tile(TileArgs a)
                                      (float)(((double)b0.y - oy) + (double)b2.y),
                                      (float)(((double)b0.z - oz) + (double)b2.z), b0.w);
                     kv = b1;
-                    vid = __float_as_int(b2.w);
+                    tag = -(__float_as_int(b2.w) + 1);
                 }
-                S.kc[k] = kc;
-                S.kv[k] = kv;
-                S.kid[k] = vid;
+                keep = box_logit(bl, kc) >= cutoff;
             }
+            int tot;
+            const int pos = block_excl_scan(keep ? (tag < 0 ? 0x10001 : 1) : 0, S.isc, &tot) & 0xffff;
+            if (keep) {
+                S.kc[pos] = kc;
+                S.kv[pos] = kv;
+                S.kid[pos] = tag;
+            }
+            __syncthreads();
+            nmoved = tot >> 16;
+            return tot & 0xffff;
+        };
+        // Re-apply the test to the n staged keys in place.
+        auto recull = [&](int n0, const float (&bl)[7], float cutoff) -> int {
+            float4 kc = make_float4(0, 0, 0, 0), kv = make_float4(0, 0, 0, 0);
+            int tag = 0;
+            bool keep = false;
+            if (tid < n0) {
+                kc = S.kc[tid];
+                kv = S.kv[tid];
+                tag = S.kid[tid];
+                keep = box_logit(bl, kc) >= cutoff;
+            }
+            int tot;  // the scan synchronises before any slot is overwritten
+            const int pos = block_excl_scan(keep ? (tag < 0 ? 0x10001 : 1) : 0, S.isc, &tot) & 0xffff;
+            if (keep) {
+                S.kc[pos] = kc;
+                S.kv[pos] = kv;
+                S.kid[pos] = tag;
+            }
+            __syncthreads();
+            nmoved = tot >> 16;
+            return tot & 0xffff;
         };
 
         const int nchunks = (K + KC - 1) / KC;
         int staged = -1;  // chunk currently in LDS
+        int nstaged = 0, nstaged_moved = 0;  // its kept keys
+        unsigned long long fwd_pairs = 0ull, fwd_moved = 0ull;
 
         if (MODE != MODE_GRAD) {
             __syncthreads();
             // ---- reference exponent: largest corner logit of the home cell
             int need_exact = 0;
+            float bl[7] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, INFINITY};
             for (int p = tid; p < P; p += BLOCK) {
                 const float4 pq = S.pq[p];
+                const float4 qa = a.ps[p0 + p];  // absolute position: the binning's home cell
+                const int hx = cell_of(qa.x, g), hy = cell_of(qa.y, g), hz = cell_of(qa.z, g);
                 float M0 = -INFINITY;
 #pragma unroll
                 for (int c8 = 0; c8 < 8; ++c8) {
-                    const int ix = cx + (c8 >> 2), iy = cy + ((c8 >> 1) & 1), iz = cz + (c8 & 1);
+                    const int ix = hx + (c8 >> 2), iy = hy + ((c8 >> 1) & 1), iz = hz + (c8 & 1);
                     const int vid = (ix * R + iy) * R + iz;
                     const float nb = a.gk[2 * (int64_t)vid].x;
                     const float dx = pq.x - (float)((double)g.tlat[ix] - ox);
@@ -561,32 +752,45 @@ __global__ __launch_bounds__(BLOCK) void k_tile(TileArgs a)
                 S.pv[p] = make_float4(0.0f, 0.0f, 0.0f, M0);
                 // exp2(s - M0) <= 2^-M0 per key; keep the sum of K such terms finite
                 if (!(-M0 + log2f((float)K + 1.0f) < 120.0f)) need_exact = 1;
+                bl[0] = fminf(bl[0], pq.x); bl[1] = fminf(bl[1], pq.y); bl[2] = fminf(bl[2], pq.z);
+                bl[3] = fmaxf(bl[3], pq.x); bl[4] = fmaxf(bl[4], pq.y); bl[5] = fmaxf(bl[5], pq.z);
+                bl[6] = fminf(bl[6], M0);
             }
             const int exact = __syncthreads_or(need_exact);
+            tile_bounds(S, bl, &S.box[0][0]);
+            // M0 <= lse2 for every query, so this drops only pairs below e^-T
+            const float fcut = bl[6] - a.T2;
 
-            const int Sf = max(1, BLOCK / max(P, 1));
+            // lanes per query (P < BLOCK) or queries per lane (P > BLOCK, then 2)
+            const int npl = P > BLOCK ? 2 : 1;
+            const int Sf = npl == 2 ? 1 : max(1, BLOCK / max(P, 1));
             const int pme = tid / Sf, ph = tid - pme * Sf;
             const bool act = pme < P;
+            const int p1 = (pme + BLOCK < P) ? pme + BLOCK : pme;  // second query (or a copy)
 
             if (exact) {
                 // exact maximum over the window first (rare: very coarse lattices)
-                float M = -INFINITY;
+                float M[2] = {-INFINITY, -INFINITY};
+                float4 q[2] = {S.pq[act ? pme : 0], S.pq[act ? p1 : 0]};
                 for (int c = 0; c < nchunks; ++c) {
                     const int k0 = c * KC, nk = min(KC, K - k0);
                     __syncthreads();
-                    stage(k0, nk);
+                    nstaged = stage_cull(k0, nk, bl, fcut);
+                    nstaged_moved = nmoved;
                     staged = c;
-                    __syncthreads();
                     if (act) {
-                        const float4 pq = S.pq[pme];
-                        for (int k = ph; k < nk; k += Sf) {
-                            const float4 kc = S.kc[k];
-                            const float dx = pq.x - kc.x, dy = pq.y - kc.y, dz = pq.z - kc.z;
-                            M = fmaxf(M, kc.w * fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+                        if (npl == 2) {
+                            fwd_max<2>(S, nstaged, ph, Sf, q, M);
+                        } else {
+                            float4 q1[1] = {q[0]};
+                            float M1[1] = {M[0]};
+                            fwd_max<1>(S, nstaged, ph, Sf, q1, M1);
+                            M[0] = M1[0];
                         }
                     }
                 }
-                S.red[tid].x = M;
+                S.red[tid].x = M[0];
+                if (npl == 2) S.red[BLOCK + tid].x = M[1];
                 __syncthreads();
                 for (int p = tid; p < P; p += BLOCK) {
                     float mx = S.pv[p].w;
@@ -596,37 +800,38 @@ __global__ __launch_bounds__(BLOCK) void k_tile(TileArgs a)
             }
 
             // ---- forward: e = sum 2^(s - M), m = sum 2^(s - M) f   (Alg. 1)
-            float e = 0.0f, m = 0.0f;
-            float qx = 0.0f, qy = 0.0f, qz = 0.0f, Mr = 0.0f;
+            float4 q[2];
+            float Mr[2], e[2] = {0.0f, 0.0f}, m[2] = {0.0f, 0.0f};
             __syncthreads();
-            if (act) {
-                const float4 pq = S.pq[pme];
-                qx = pq.x; qy = pq.y; qz = pq.z;
-                Mr = S.pv[pme].w;
-            }
+            q[0] = S.pq[act ? pme : 0];
+            q[1] = S.pq[act ? p1 : 0];
+            Mr[0] = S.pv[act ? pme : 0].w;
+            Mr[1] = S.pv[act ? p1 : 0].w;
             for (int c = 0; c < nchunks; ++c) {
                 const int k0 = c * KC, nk = min(KC, K - k0);
                 if (staged != c) {
                     __syncthreads();
-                    stage(k0, nk);
+                    nstaged = stage_cull(k0, nk, bl, fcut);
+                    nstaged_moved = nmoved;
                     staged = c;
-                    __syncthreads();
                 }
+                fwd_pairs += (unsigned long long)nstaged * P;
+                fwd_moved += (unsigned long long)nstaged_moved * P;
                 if (act) {
-#pragma unroll 4
-                    for (int k = ph; k < nk; k += Sf) {
-                        const float4 kc = S.kc[k], kv = S.kv[k];
-                        const float dx = qx - kc.x, dy = qy - kc.y, dz = qz - kc.z;
-                        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                        const float l = ex2(fmaf(kc.w, r2, -Mr));
-                        const float f = fmaf(dx, kv.y, fmaf(dy, kv.z, fmaf(dz, kv.w, kv.x)));
-                        e += l;
-                        m = fmaf(l, f, m);
+                    if (npl == 2) {
+                        fwd_sums<2>(S, nstaged, ph, Sf, q, Mr, e, m);
+                    } else {
+                        float4 q1[1] = {q[0]};
+                        float M1[1] = {Mr[0]}, e1[1] = {e[0]}, m1[1] = {m[0]};
+                        fwd_sums<1>(S, nstaged, ph, Sf, q1, M1, e1, m1);
+                        e[0] = e1[0];
+                        m[0] = m1[0];
                     }
                 }
             }
             __syncthreads();
-            S.red[tid] = make_float2(e, m);
+            S.red[tid] = make_float2(e[0], m[0]);
+            if (npl == 2) S.red[BLOCK + tid] = make_float2(e[1], m[1]);
             __syncthreads();
 
             // ---- per query: O, lse, certificate, loss and dL/dO
@@ -634,9 +839,9 @@ __global__ __launch_bounds__(BLOCK) void k_tile(TileArgs a)
             const float flx = (cx - W + 1 > 0) ? (float)((double)g.tlat[cx - W] - ox) : -INFINITY;
             const float fly = (cy - W + 1 > 0) ? (float)((double)g.tlat[cy - W] - oy) : -INFINITY;
             const float flz = (cz - W + 1 > 0) ? (float)((double)g.tlat[cz - W] - oz) : -INFINITY;
-            const float fhx = (cx + W < R - 1) ? (float)((double)g.tlat[cx + W + 1] - ox) : INFINITY;
-            const float fhy = (cy + W < R - 1) ? (float)((double)g.tlat[cy + W + 1] - oy) : INFINITY;
-            const float fhz = (cz + W < R - 1) ? (float)((double)g.tlat[cz + W + 1] - oz) : INFINITY;
+            const float fhx = (cx1 + W < R - 1) ? (float)((double)g.tlat[cx1 + W + 1] - ox) : INFINITY;
+            const float fhy = (cy1 + W < R - 1) ? (float)((double)g.tlat[cy1 + W + 1] - oy) : INFINITY;
+            const float fhz = (cz1 + W < R - 1) ? (float)((double)g.tlat[cz1 + W + 1] - oz) : INFINITY;
             double lsq = 0.0, lab = 0.0;
             for (int p = tid; p < P; p += BLOCK) {
                 float ee = 0.0f, mm = 0.0f;
@@ -683,41 +888,36 @@ __global__ __launch_bounds__(BLOCK) void k_tile(TileArgs a)
             __syncthreads();
 
             if (MODE == MODE_EVAL && QGRAD) {
-                // dO/dq = sum_a w_a [d_a + 2 beta_a x (O - f_a)]  (Eq. func-normal)
-                float gx = 0.0f, gy = 0.0f, gz = 0.0f;
-                float O = 0.0f, lse2 = 0.0f;
-                if (act) {
-                    const float4 pv = S.pv[pme];
-                    O = pv.x;
-                    lse2 = pv.y;
-                }
+                float O2[2] = {S.pv[act ? pme : 0].x, S.pv[act ? p1 : 0].x};
+                float L2[2] = {S.pv[act ? pme : 0].y, S.pv[act ? p1 : 0].y};
+                float gx[2] = {0, 0}, gy[2] = {0, 0}, gz[2] = {0, 0};
                 for (int c = nchunks - 1; c >= 0; --c) {
                     const int k0 = c * KC, nk = min(KC, K - k0);
                     if (staged != c) {
                         __syncthreads();
-                        stage(k0, nk);
+                        nstaged = stage_cull(k0, nk, bl, fcut);
                         staged = c;
-                        __syncthreads();
                     }
                     if (act) {
-                        for (int k = ph; k < nk; k += Sf) {
-                            const float4 kc = S.kc[k], kv = S.kv[k];
-                            const float dx = qx - kc.x, dy = qy - kc.y, dz = qz - kc.z;
-                            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                            const float w = ex2(fmaf(kc.w, r2, -lse2));
-                            const float f = fmaf(dx, kv.y, fmaf(dy, kv.z, fmaf(dz, kv.w, kv.x)));
-                            const float t = -2.0f * LN2 * kc.w * (O - f) * w;  // 2 beta (O - f) w
-                            gx += fmaf(w, kv.y, t * dx);
-                            gy += fmaf(w, kv.z, t * dy);
-                            gz += fmaf(w, kv.w, t * dz);
+                        if (npl == 2) {
+                            fwd_qgrad<2>(S, nstaged, ph, Sf, q, O2, L2, gx, gy, gz);
+                        } else {
+                            float4 q1[1] = {q[0]};
+                            float o1[1] = {O2[0]}, l1[1] = {L2[0]};
+                            float x1[1] = {gx[0]}, y1[1] = {gy[0]}, z1[1] = {gz[0]};
+                            fwd_qgrad<1>(S, nstaged, ph, Sf, q1, o1, l1, x1, y1, z1);
+                            gx[0] = x1[0]; gy[0] = y1[0]; gz[0] = z1[0];
                         }
                     }
                 }
                 __syncthreads();
-                S.red[tid] = make_float2(gx, gy);
-                float* zf = reinterpret_cast<float*>(S.kc);  // keys no longer needed
-                __syncthreads();
-                zf[tid] = gz;
+                float* zf = S.fv;  // keys no longer needed
+                S.red[tid] = make_float2(gx[0], gy[0]);
+                zf[tid] = gz[0];
+                if (npl == 2) {
+                    S.red[BLOCK + tid] = make_float2(gx[1], gy[1]);
+                    zf[BLOCK + tid] = gz[1];
+                }
                 staged = -1;
                 __syncthreads();
                 for (int p = tid; p < P; p += BLOCK) {
@@ -740,9 +940,9 @@ __global__ __launch_bounds__(BLOCK) void k_tile(TileArgs a)
             const float flx = (cx - W + 1 > 0) ? (float)((double)g.tlat[cx - W] - ox) : -INFINITY;
             const float fly = (cy - W + 1 > 0) ? (float)((double)g.tlat[cy - W] - oy) : -INFINITY;
             const float flz = (cz - W + 1 > 0) ? (float)((double)g.tlat[cz - W] - oz) : -INFINITY;
-            const float fhx = (cx + W < R - 1) ? (float)((double)g.tlat[cx + W + 1] - ox) : INFINITY;
-            const float fhy = (cy + W < R - 1) ? (float)((double)g.tlat[cy + W + 1] - oy) : INFINITY;
-            const float fhz = (cz + W < R - 1) ? (float)((double)g.tlat[cz + W + 1] - oz) : INFINITY;
+            const float fhx = (cx1 + W < R - 1) ? (float)((double)g.tlat[cx1 + W + 1] - ox) : INFINITY;
+            const float fhy = (cy1 + W < R - 1) ? (float)((double)g.tlat[cy1 + W + 1] - oy) : INFINITY;
+            const float fhz = (cz1 + W < R - 1) ? (float)((double)g.tlat[cz1 + W + 1] - oz) : INFINITY;
             for (int p = tid; p < P; p += BLOCK) {
                 const float4 pq = S.pq[p];
                 float4 pv = S.pv[p];
@@ -759,27 +959,50 @@ __global__ __launch_bounds__(BLOCK) void k_tile(TileArgs a)
             }
         }
 
+        unsigned long long bwd_pairs = 0ull, bwd_moved = 0ull;
         if (MODE != MODE_EVAL) {
             // ---- backward, key-parallel over the tile's queries (Alg. 2)
+            // Box and smallest lse2 of the queries that carry a gradient; keys
+            // whose every pair with them weighs below e^-T are skipped.
+            float bl[7] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, INFINITY};
+            __syncthreads();
+            for (int p = tid; p < P; p += BLOCK) {
+                const float4 pv = S.pv[p];
+                if (pv.z == 0.0f) continue;
+                const float4 pq = S.pq[p];
+                bl[0] = fminf(bl[0], pq.x); bl[1] = fminf(bl[1], pq.y); bl[2] = fminf(bl[2], pq.z);
+                bl[3] = fmaxf(bl[3], pq.x); bl[4] = fmaxf(bl[4], pq.y); bl[5] = fmaxf(bl[5], pq.z);
+                bl[6] = fminf(bl[6], pv.y);
+            }
+            tile_bounds(S, bl, &S.box[0][0]);
+            const float bcut = bl[6] - a.T2;
+
             for (int c = nchunks - 1; c >= 0; --c) {
                 const int k0 = c * KC, nk = min(KC, K - k0);
+                int n;
                 __syncthreads();
-                if (staged != c) {
-                    stage(k0, nk);
-                    staged = c;
-                    __syncthreads();
+                if (staged == c) {
+                    n = recull(nstaged, bl, bcut);
+                } else {
+                    n = stage_cull(k0, nk, bl, bcut);
                 }
+                staged = -1;  // the flush below overwrites the staged keys
+                bwd_pairs += (unsigned long long)n * P;
+                bwd_moved += (unsigned long long)nmoved * P;
+                if (n == 0) continue;
                 int Sb = 1;
-                while (Sb < 64 && Sb * 2 * nk <= BLOCK) Sb *= 2;
-                const int k = tid / Sb, ph = tid - k * Sb;
-                const bool act = k < nk;
-                const bool moved = act && (k0 + k >= Kg);
+                while (Sb < 64 && Sb * 2 * n <= BLOCK) Sb *= 2;
+                const int kk = tid / Sb, ph = tid - kk * Sb;
+                const bool act = kk < n;
                 float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
                 float4 kc = make_float4(0, 0, 0, 0), kv = make_float4(0, 0, 0, 0);
+                int tag = 0;
                 if (act) {
-                    kc = S.kc[k];
-                    kv = S.kv[k];
+                    kc = S.kc[kk];
+                    kv = S.kv[kk];
+                    tag = S.kid[kk];
                 }
+                const bool moved = act && tag < 0;
                 if (__any(moved)) {
                     if (act) bwd_key<true>(S, P, ph, Sb, kc, kv, acc);
                 } else {
@@ -789,38 +1012,45 @@ __global__ __launch_bounds__(BLOCK) void k_tile(TileArgs a)
 #pragma unroll
                     for (int t = 0; t < 8; ++t) acc[t] += __shfl_xor(acc[t], off, 64);
                 }
+                // final channel values: o, d, rho (grid) or Delta, o', d', rho' (moved)
+                const float beta = -kc.w * LN2;
+                float val[8];
+                if (!moved) {
+                    val[0] = acc[0]; val[1] = acc[1]; val[2] = acc[2]; val[3] = acc[3];
+                    val[4] = -beta * acc[4];
+                    val[5] = val[6] = val[7] = 0.0f;
+                } else {
+                    // dL/dc = -d sum(delta) + 2 beta sum(delta r x)
+                    val[0] = fmaf(-kv.y, acc[0], 2.0f * beta * acc[5]);
+                    val[1] = fmaf(-kv.z, acc[0], 2.0f * beta * acc[6]);
+                    val[2] = fmaf(-kv.w, acc[0], 2.0f * beta * acc[7]);
+                    val[3] = acc[0]; val[4] = acc[1]; val[5] = acc[2]; val[6] = acc[3];
+                    val[7] = -beta * acc[4];
+                }
+                __syncthreads();  // staged keys no longer needed: reuse their LDS
                 if (act && ph == 0) {
-                    bool any = false;
 #pragma unroll
-                    for (int t = 0; t < 8; ++t) any |= (acc[t] != 0.0f);
-                    if (any) {
-                        const int vid = S.kid[k];
-                        const float beta = -kc.w * LN2;
-                        float* gp = a.grad + (int64_t)vid * NCH;
-                        if (!moved) {
-                            unsafeAtomicAdd(gp + 0, acc[0]);
-                            unsafeAtomicAdd(gp + 1, acc[1]);
-                            unsafeAtomicAdd(gp + 2, acc[2]);
-                            unsafeAtomicAdd(gp + 3, acc[3]);
-                            unsafeAtomicAdd(gp + 4, -beta * acc[4]);
-                        } else {
-                            // dL/dc = -d sum(delta) + 2 beta sum(delta r x)
-                            unsafeAtomicAdd(gp + 5, fmaf(-kv.y, acc[0], 2.0f * beta * acc[5]));
-                            unsafeAtomicAdd(gp + 6, fmaf(-kv.z, acc[0], 2.0f * beta * acc[6]));
-                            unsafeAtomicAdd(gp + 7, fmaf(-kv.w, acc[0], 2.0f * beta * acc[7]));
-                            unsafeAtomicAdd(gp + 8, acc[0]);
-                            unsafeAtomicAdd(gp + 9, acc[1]);
-                            unsafeAtomicAdd(gp + 10, acc[2]);
-                            unsafeAtomicAdd(gp + 11, acc[3]);
-                            unsafeAtomicAdd(gp + 12, -beta * acc[4]);
-                        }
+                    for (int t = 0; t < 8; ++t) S.fv[kk * 8 + t] = val[t];
+                }
+                __syncthreads();
+                // one atomic per key channel, eight consecutive lanes per key
+                for (int t = tid; t < n * 8; t += BLOCK) {
+                    const int kq = t >> 3, ch = t & 7;
+                    const int tg = S.kid[kq];
+                    const bool mv = tg < 0;
+                    const float x = S.fv[t];
+                    if ((mv || ch < 5) && x != 0.0f) {
+                        const int64_t v = mv ? (int64_t)(-tg - 1) : (int64_t)tg;
+                        unsafeAtomicAdd(a.grad + v * NCH + (mv ? 5 : 0) + ch, x);
                     }
                 }
             }
         }
         if (tid == 0) {
-            atomicAdd(&a.st->pairs, (unsigned long long)P * (unsigned long long)K);
-            atomicAdd(&a.st->pairs_moved, (unsigned long long)P * (unsigned long long)Km);
+            atomicAdd(&a.st->pairs, fwd_pairs);
+            atomicAdd(&a.st->pairs_moved, fwd_moved);
+            atomicAdd(&a.st->bwd_pairs, bwd_pairs);
+            atomicAdd(&a.st->bwd_pairs_moved, bwd_moved);
         }
     }
 }
@@ -1119,7 +1349,7 @@ hipError_t run_tiles(const Work& w, const Problem& p, Mode mode, hipStream_t s)
     const Geo& g = p.g;
     const int64_t I = w.I, C = w.C, J = p.J;
     k_reset_stats<<<1, 64, 0, s>>>(w.st);
-    k_fill_int<<<grid_for(C, BLOCK * 8), BLOCK, 0, s>>>(w.pcount, C, 0);
+    k_fill_int<<<grid_for(w.NK, BLOCK * 8), BLOCK, 0, s>>>(w.pcount, w.NK, 0);
     if (p.offsets) k_fill_int<<<grid_for(C, BLOCK * 8), BLOCK, 0, s>>>(w.mcount, C, 0);
     // keys
     k_prep_keys<<<grid_for(I), BLOCK, 0, s>>>(p.theta, g, p.offsets, I, w.gk, w.mrec, w.mcell,
@@ -1133,12 +1363,17 @@ hipError_t run_tiles(const Work& w, const Problem& p, Mode mode, hipStream_t s)
     // queries
     k_count_points<<<grid_for(J), BLOCK, 0, s>>>(p.q, J, g, w.pcell, w.prank, w.pcount);
     {
-        hipError_t e = scan(w.pcount, C, w.scan_blk, w.pstart, w.tstart, true, s);
+        hipError_t e = scan(w.pcount, w.NK, w.scan_blk, w.pstart, nullptr, false, s);
         if (e != hipSuccess) return e;
     }
     k_scatter_points<<<grid_for(J), BLOCK, 0, s>>>(p.q, p.aux, p.O_in, p.lse_in, J, w.pcell,
                                                    w.prank, w.pstart, w.ps, w.pv, w.pidx);
-    k_build_tiles<<<grid_for(C), BLOCK, 0, s>>>(C, w.pcount, w.pstart, w.tstart, w.tiles);
+    k_block_tiles<<<grid_for(w.NB3), BLOCK, 0, s>>>(w.NB3, w.pcount, w.btiles);
+    {
+        hipError_t e = scan(w.btiles, w.NB3, w.scan_blk, w.tstart, nullptr, false, s);
+        if (e != hipSuccess) return e;
+    }
+    k_build_tiles<<<grid_for(w.NB3), BLOCK, 0, s>>>(w.NB3, g, w.pcount, w.pstart, w.tstart, w.tiles);
 
     TileArgs a;
     a.g = g;
@@ -1152,7 +1387,7 @@ hipError_t run_tiles(const Work& w, const Problem& p, Mode mode, hipStream_t s)
     a.pv = w.pv;
     a.pidx = w.pidx;
     a.tiles = w.tiles;
-    a.ntiles = w.tstart + C;
+    a.ntiles = w.tstart + w.NB3;
     a.fb = w.fb;
     a.lpart = w.lpart;
     a.st = w.st;
@@ -1195,7 +1430,7 @@ hipError_t run_tiles(const Work& w, const Problem& p, Mode mode, hipStream_t s)
 
 hipError_t run_loss_finalize(const Work& w, int64_t J, double* loss_out, hipStream_t s)
 {
-    k_loss_finalize<<<1, BLOCK, 0, s>>>(w.lpart, w.tstart + w.C, w.st, 1.0 / (double)J, loss_out);
+    k_loss_finalize<<<1, BLOCK, 0, s>>>(w.lpart, w.tstart + w.NB3, w.st, 1.0 / (double)J, loss_out);
     return hipGetLastError();
 }
 
