@@ -85,6 +85,129 @@ def cpu_baseline(workload, q, o, R, theta, sample):
                       f"{dt:.1f} s"}
 
 
+def naive_efunc(theta, q):
+    """Materialising autodiff baseline (plain PyTorch, float32): the global
+    softmax over all keys with every key-query term held in memory, so that
+    autograd can differentiate it (the construction the paper's fused kernels
+    replace)."""
+    import torch
+    R = theta.shape[0]
+    t = torch.linspace(-1, 1, R, device=q.device, dtype=torch.float64).to(torch.float32)
+    K = torch.stack(torch.meshgrid(t, t, t, indexing="ij"), -1).reshape(-1, 3)
+    P = theta.reshape(-1, 13)
+    centres = torch.cat([K, K + P[:, 5:8]])
+    betas = torch.cat([P[:, 4].exp(), P[:, 12].exp()])
+    vals = torch.cat([P[:, 0], P[:, 8]])
+    slopes = torch.cat([P[:, 1:4], P[:, 9:12]])
+    X = q[:, None, :] - centres[None]
+    logits = -betas[None] * (X * X).sum(-1)
+    F = vals[None] + (X * slopes[None]).sum(-1)
+    return (torch.softmax(logits, dim=1) * F).sum(1)
+
+
+def compare_autodiff(args):
+    """Fused engine vs the materialising baseline at the paper's time/memory
+    table shapes (16,384 queries, lattices 4^3 .. 64^3) and at the benchmark
+    workload (2^21 queries, 32^3; the baseline chunked over queries)."""
+    import torch
+    import workloads as W
+    from paper_2505_21319_amd import efunc as E
+    dev = torch.device("cuda:0")
+    w = W.get("csg16_r32")
+    surf = torch.from_numpy(W.surface_points(w, 16384, seed=7, device=dev).astype(np.float32)).to(dev)
+
+    def timed(fn, reps=10):
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts))
+
+    rows = []
+    J = 16384
+    q, o = W.make_batch(w, 0, J=J, device=dev)
+    q, o = torch.from_numpy(q).to(dev), torch.from_numpy(o).to(dev)
+    for R in (4, 8, 16, 32, 64):
+        eng = E.Engine(R, J)
+        th = torch.empty(R, R, R, 13, device=dev)
+        eng.init_params(th, surf)
+        g = torch.Generator(device="cpu").manual_seed(R)
+        th[..., 0] += 0.1 * torch.randn(R, R, R, generator=g).to(dev)
+        O = torch.empty(J, device=dev)
+        lse = torch.empty(J, device=dev)
+        dl = (2.0 / J) * torch.randn(J, generator=g).to(dev)
+        G = torch.zeros_like(th)
+        for _ in range(3):
+            E.efunc_eval(eng.ctx, th, q, O, lse)
+            E.efunc_grad(eng.ctx, th, q, O, lse, dl, G)
+        fwd = timed(lambda: E.efunc_eval(eng.ctx, th, q, O, lse))
+        bwd = timed(lambda: E.efunc_grad(eng.ctx, th, q, O, lse, dl, G))
+        ws = eng.stats()["workspace_bytes"] + 2 * 4 * J
+        eng.close()
+        row = {"R": R, "keys": 2 * R ** 3, "J": J, "fused_fwd_ms": fwd, "fused_bwd_ms": bwd,
+               "fused_extra_MB": ws / 2 ** 20}
+        torch.cuda.empty_cache()
+        try:
+            T = th.clone().requires_grad_(True)
+            base = torch.cuda.memory_allocated()
+            torch.cuda.reset_peak_memory_stats()
+            out = {}
+
+            def f():
+                out["O"] = naive_efunc(T, q)
+
+            def b():
+                T.grad = None
+                naive_efunc(T, q).backward(dl)
+
+            f()
+            torch.cuda.synchronize()
+            row["naive_fwd_ms"] = timed(f, 5)
+            row["naive_bwd_ms"] = max(timed(b, 5) - row["naive_fwd_ms"], 0.0)
+            row["naive_peak_GB"] = (torch.cuda.max_memory_allocated() - base) / 2 ** 30
+            del out
+        except torch.cuda.OutOfMemoryError:
+            row["naive"] = "OOM"
+        torch.cuda.empty_cache()
+        rows.append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+    # the benchmark workload: fused fit step vs the baseline chunked over queries
+    Jb = w.J
+    qb, ob = W.make_batch(w, 0, device=dev)
+    qb, ob = torch.from_numpy(qb).to(dev), torch.from_numpy(ob).to(dev)
+    eng = E.Engine(w.R, Jb)
+    th = torch.empty(w.R, w.R, w.R, 13, device=dev)
+    eng.init_params(th, surf)
+    m, v = torch.zeros_like(th), torch.zeros_like(th)
+    for s_ in range(1, 4):
+        eng.fit_step(th, m, v, s_, qb, ob)
+    fit_ms = timed(lambda: eng.fit_step(th, m, v, 4, qb, ob), 10)
+    eng.close()
+    chunk, nchunks = 4096, 16
+    T = th.clone().requires_grad_(True)
+
+    def chunks():
+        T.grad = None
+        for c in range(nchunks):
+            sl = slice(c * chunk, (c + 1) * chunk)
+            r = naive_efunc(T, qb[sl]) - ob[sl]
+            (r * r).sum().div(Jb).backward()
+
+    chunks()
+    torch.cuda.synchronize()
+    naive_ms = timed(chunks, 3) * (Jb / (chunk * nchunks))
+    cfg2 = {"workload": "csg16_r32", "J": Jb, "fused_fit_step_ms": fit_ms,
+            "naive_fwd_bwd_ms_extrapolated": naive_ms,
+            "naive_note": f"chunks of {chunk} queries; {nchunks} chunks timed and scaled to {Jb} "
+                          "queries; no optimiser step"}
+    print(json.dumps({"comparison": "fused engine vs materialising autodiff (global softmax)",
+                      "table_shapes": rows, "benchmark_workload": cfg2}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +217,8 @@ def main():
     ap.add_argument("--batches", type=int, default=4, help="distinct resident batches cycled")
     ap.add_argument("--cpu-sample", type=int, default=32768)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--compare-autodiff", action="store_true",
+                    help="print the fused vs materialising-autodiff comparison instead")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -105,6 +230,9 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.compare_autodiff:
+        compare_autodiff(args)
+        return
     if args.copy_calib_mib:
         n = args.copy_calib_mib * (1 << 20) // 4
         a = torch.ones(n, device="cuda", dtype=torch.float32)

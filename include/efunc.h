@@ -86,6 +86,7 @@ typedef struct {
     float beta_min;         /* smallest scale over all keys */
     float beta_grid_max;    /* largest scale over grid keys */
     int32_t n_nonfinite;    /* non-finite parameters seen by the last call */
+    int64_t workspace_bytes;/* device memory owned by the context */
 } efunc_stats;
 
 /* Fill *cfg with defaults for resolution R: [-1,1]^3, offsets on, T = 20,

@@ -126,25 +126,29 @@ void oracle_eval(const double* keys, int64_t nkeys, const double* q, int64_t J,
     }
 }
 
-/* Conditioning of the evaluation with respect to the logits:
- * kappa = sum_a w_a |s_a| |f_a - O|.  A logit computed in a precision with
- * unit roundoff u carries an error of a few u |s_a|, which moves O by about
- * u kappa; test tolerances use it as the logit term of the error scale. */
+/* Error scales of a reduced-precision or truncated evaluation:
+ * kappa = sum_a w_a |s_a| |f_a - O|: a logit computed with unit roundoff u
+ * carries an error of a few u |s_a|, which moves O by about u kappa;
+ * tail = sum over keys with weight below e^-T of w_a |f_a - O|: the most
+ * that omitting those pairs can move O. */
 void oracle_eval_cond(const double* keys, int64_t nkeys, const double* q, int64_t J,
-                      double* kappa)
+                      double* kappa, double T, double* tail)
 {
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t j = 0; j < J; ++j) {
         const double* qj = q + 3 * j;
         double O, lse, sig;
         eval_one(keys, nkeys, qj, &O, &lse, &sig);
-        double k = 0.0;
+        double k = 0.0, tl = 0.0;
         for (int64_t a = 0; a < nkeys; ++a) {
             const double* kk = keys + a * ORACLE_KEY;
             const double s = logit(kk, qj);
-            k += exp(s - lse) * fabs(s) * fabs(value(kk, qj) - O);
+            const double wr = exp(s - lse) * fabs(value(kk, qj) - O);
+            k += wr * fabs(s);
+            if (s - lse < -T) tl += wr;
         }
-        kappa[j] = k;
+        if (kappa) kappa[j] = k;
+        if (tail) tail[j] = tl;
     }
 }
 
@@ -182,7 +186,7 @@ void oracle_eval_qgrad(const double* keys, int64_t nkeys, const double* q,
  *   dO/dc    = w (df/dc + 2 beta x r),  df/dc = -d   (f^1)
  * summed against dL/dO_j over all queries, key-parallel as in Alg. 2. */
 void oracle_grad(const double* keys, int64_t nkeys, const double* q, int64_t J,
-                 const double* dLdO, double* gk, double* ak)
+                 const double* dLdO, double* gk, double* ak, double T, double* bk)
 {
     double* O = (double*)malloc(sizeof(double) * (size_t)(J > 0 ? J : 1));
     double* lse = (double*)malloc(sizeof(double) * (size_t)(J > 0 ? J : 1));
@@ -190,10 +194,11 @@ void oracle_grad(const double* keys, int64_t nkeys, const double* q, int64_t J,
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t a = 0; a < nkeys; ++a) {
         const double* k = keys + a * ORACLE_KEY;
-        double g[8] = {0}, s[8] = {0};
+        double g[8] = {0}, s[8] = {0}, b[8] = {0};
         for (int64_t j = 0; j < J; ++j) {
             const double* qj = q + 3 * j;
-            const double w = exp(logit(k, qj) - lse[j]);
+            const double lw = logit(k, qj) - lse[j];
+            const double w = exp(lw);
             const double x0 = qj[0] - k[0], x1 = qj[1] - k[1], x2 = qj[2] - k[2];
             const double r = value(k, qj) - O[j];
             const double dl = dLdO[j];
@@ -204,20 +209,24 @@ void oracle_grad(const double* keys, int64_t nkeys, const double* q, int64_t J,
                                      dl * w * (-x2n) * r, dl * w,
                                      dl * w * x0, dl * w * x1, dl * w * x2};
             for (int c = 0; c < 8; ++c) g[c] += terms[c];
-            if (ak) {
+            if (ak || bk) {
                 const double adw = fabs(dl) * w;
                 const double ac[3] = {fabs(k[5]) + 2.0 * k[3] * fabs(x0 * r),
                                       fabs(k[6]) + 2.0 * k[3] * fabs(x1 * r),
                                       fabs(k[7]) + 2.0 * k[3] * fabs(x2 * r)};
-                s[0] += adw * ac[0]; s[1] += adw * ac[1]; s[2] += adw * ac[2];
-                s[3] += adw * x2n * fabs(r);
-                s[4] += adw;
-                s[5] += adw * fabs(x0); s[6] += adw * fabs(x1); s[7] += adw * fabs(x2);
+                const double t[8] = {adw * ac[0], adw * ac[1], adw * ac[2], adw * x2n * fabs(r),
+                                     adw, adw * fabs(x0), adw * fabs(x1), adw * fabs(x2)};
+                const int below = lw < -T;  /* pair weight below e^-T */
+                for (int c = 0; c < 8; ++c) {
+                    s[c] += t[c];
+                    if (below) b[c] += t[c];
+                }
             }
         }
         for (int c = 0; c < 8; ++c) {
             gk[a * 8 + c] = g[c];
             if (ak) ak[a * 8 + c] = s[c];
+            if (bk) bk[a * 8 + c] = b[c];
         }
     }
     free(O);
@@ -589,7 +598,7 @@ int oracle_fit_step(const oracle_grid* g, const float* theta, const double* m,
         loss_out[0] = J > 0 ? l2 / (double)J : 0.0;
         loss_out[1] = J > 0 ? l1 / (double)J : 0.0;
         if (mode == 0)
-            oracle_grad(keys, nkeys, q, J, dl, gk, NULL);
+            oracle_grad(keys, nkeys, q, J, dl, gk, NULL, INFINITY, NULL);
         else
             rc = oracle_grad_trunc(g, keys, q, J, T, dl, gk, NULL);
     }

@@ -66,21 +66,23 @@ void oracle_build_keys(const oracle_grid* g, const float* theta, double* keys);
 void oracle_eval(const double* keys, int64_t nkeys, const double* q, int64_t J,
                  double* O, double* lse, double* sigma);
 
-/* Logit conditioning kappa_j = sum_a w_a |s_a| |f_a - O_j| (a tolerance scale
- * for reduced-precision evaluations, not part of the method). */
+/* Tolerance scales (not part of the method): logit conditioning
+ * kappa_j = sum_a w_a |s_a| |f_a - O_j| and the truncation tail
+ * tail_j = sum_{a: w_a < e^-T} w_a |f_a - O_j|.  Either output may be NULL. */
 void oracle_eval_cond(const double* keys, int64_t nkeys, const double* q, int64_t J,
-                      double* kappa);
+                      double* kappa, double T, double* tail);
 
 /* Query gradient dO/dq (Eq. func-normal), global support.  dOdq: J x 3. */
 void oracle_eval_qgrad(const double* keys, int64_t nkeys, const double* q,
                        int64_t J, double* dOdq);
 
 /* Key-parameter gradients of sum_j dLdO_j * O(q_j) (Sec. 3.6 closed forms),
- * global support, key-parallel as in Alg. 2.  gk/ak: nkeys x 8 laid out as
+ * global support, key-parallel as in Alg. 2.  gk/ak/bk: nkeys x 8 laid out as
  * dc.x dc.y dc.z dbeta do dd.x dd.y dd.z; ak holds sum_j |term| per entry
- * (the running-error scale).  ak may be NULL. */
+ * (the running-error scale) and bk the same sum over the pairs whose weight
+ * is below e^-T (the most a truncation at e^-T can omit).  ak, bk may be NULL. */
 void oracle_grad(const double* keys, int64_t nkeys, const double* q, int64_t J,
-                 const double* dLdO, double* gk, double* ak);
+                 const double* dLdO, double* gk, double* ak, double T, double* bk);
 
 /* Map key gradients onto the 13 theta channels (rho chain rule when
  * raw_beta = 0; grid-key centres are fixed and get nothing). */

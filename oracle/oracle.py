@@ -74,8 +74,8 @@ def load():
         lib.oracle_build_keys.argtypes = [_G, _F, _D]
         lib.oracle_eval.argtypes = [_D, _I64, _D, _I64, _D, _D, _D]
         lib.oracle_eval_qgrad.argtypes = [_D, _I64, _D, _I64, _D]
-        lib.oracle_eval_cond.argtypes = [_D, _I64, _D, _I64, _D]
-        lib.oracle_grad.argtypes = [_D, _I64, _D, _I64, _D, _D, _D]
+        lib.oracle_eval_cond.argtypes = [_D, _I64, _D, _I64, _D, C.c_double, _D]
+        lib.oracle_grad.argtypes = [_D, _I64, _D, _I64, _D, _D, _D, C.c_double, _D]
         lib.oracle_grad_theta.argtypes = [_G, _F, _D, _D]
         lib.oracle_eval_trunc.argtypes = [_G, _D, _D, _I64, C.c_double, _D, _D, _D]
         lib.oracle_eval_trunc.restype = C.c_int
@@ -159,12 +159,15 @@ def eval_global(keys, q):
     return O, lse, sig
 
 
-def eval_cond(keys, q):
-    """Logit conditioning kappa_j = sum_a w_a |s_a| |f_a - O_j| (tolerance scale)."""
+def eval_cond(keys, q, T: float = float("inf"), with_tail: bool = False):
+    """Tolerance scales: kappa_j = sum_a w_a |s_a| |f_a - O_j|, and with
+    with_tail also tail_j = sum over keys with weight below e^-T of
+    w_a |f_a - O_j|."""
     keys, q = _f64(keys), _f64(q).reshape(-1, 3)
-    out = np.empty(q.shape[0])
-    load().oracle_eval_cond(_d(keys), keys.shape[0], _d(q), q.shape[0], _d(out))
-    return out
+    kap = np.empty(q.shape[0])
+    tail = np.empty(q.shape[0]) if with_tail else None
+    load().oracle_eval_cond(_d(keys), keys.shape[0], _d(q), q.shape[0], _d(kap), T, _d(tail))
+    return (kap, tail) if with_tail else kap
 
 
 def eval_qgrad(keys, q):
@@ -185,13 +188,16 @@ def eval_trunc(g: Grid, keys, q, T: float = 20.0):
     return O, lse, sig
 
 
-def grad_global(keys, q, dLdO):
-    """Return (gk, ak): key gradients and their running-error scales (nkeys x 8)."""
+def grad_global(keys, q, dLdO, T: float = None):
+    """Return (gk, ak): key gradients and their running-error scales (nkeys x 8);
+    with T also bk, the part of ak from pairs with weight below e^-T."""
     keys, q, dLdO = _f64(keys), _f64(q).reshape(-1, 3), _f64(dLdO)
     gk = np.empty((keys.shape[0], 8))
     ak = np.empty((keys.shape[0], 8))
-    load().oracle_grad(_d(keys), keys.shape[0], _d(q), q.shape[0], _d(dLdO), _d(gk), _d(ak))
-    return gk, ak
+    bk = np.empty((keys.shape[0], 8)) if T is not None else None
+    load().oracle_grad(_d(keys), keys.shape[0], _d(q), q.shape[0], _d(dLdO), _d(gk), _d(ak),
+                       float("inf") if T is None else T, _d(bk))
+    return (gk, ak) if T is None else (gk, ak, bk)
 
 
 def grad_trunc(g: Grid, keys, q, dLdO, T: float = 20.0):

@@ -23,6 +23,7 @@ struct efunc_ctx {
     hipStream_t last_stream;
     int device;
     std::vector<void*> allocs;
+    int64_t alloc_bytes = 0;
     bool timing = false;
     std::vector<hipEvent_t> ev;  // 2 * MAX_TIMED when timing has been enabled
     int nrec = 0;
@@ -59,6 +60,7 @@ hipError_t dalloc(efunc_ctx* c, T** p, size_t count)
     hipError_t e = hipMalloc(&q, bytes);
     if (e != hipSuccess) return e;
     c->allocs.push_back(q);
+    c->alloc_bytes += (int64_t)bytes;
     *p = static_cast<T*>(q);
     return hipSuccess;
 }
@@ -244,6 +246,8 @@ int efunc_create(const efunc_config* cfg, int64_t max_points, efunc_ctx** out)
     ALLOC(w.btiles, w.NB3);
     ALLOC(w.tstart, w.NB3 + 1);
     ALLOC(w.tiles, w.max_tiles);
+    ALLOC(w.tiles_tmp, w.max_tiles);
+    ALLOC(w.tbucket, w.max_tiles);
     ALLOC(w.ps, mp);
     ALLOC(w.pv, mp);
     ALLOC(w.pidx, mp);
@@ -439,6 +443,7 @@ int efunc_get_stats(efunc_ctx* ctx, efunc_stats* out)
     memcpy(&out->beta_min, &b, 4);
     memcpy(&out->beta_grid_max, &gb, 4);
     out->n_nonfinite = st.nonfinite;
+    out->workspace_bytes = ctx->alloc_bytes;
     return EFUNC_OK;
 }
 

@@ -32,6 +32,7 @@ struct DevStats {
     unsigned long long bwd_pairs;    // pairs evaluated by the backward (after block truncation)
     unsigned long long bwd_pairs_moved;
     double fb_loss[2];        // loss sums of fallback queries
+    int bcount[128];          // tiles per cost bucket (log2 of the window pair count)
 };
 
 // Lattice geometry passed by value to every kernel.
@@ -64,7 +65,9 @@ struct Work {
     int* pstart;          // [NK+1]
     int* btiles;          // [NB3]  tiles per cell block
     int* tstart;          // [NB3+1]
-    int4* tiles;          // [max_tiles]  {first cell, first query, count, extent bits}
+    int4* tiles;          // [max_tiles]  {first cell, first query, count, extent bits}, heaviest first
+    int4* tiles_tmp;      // [max_tiles]  the same in block order
+    int2* tbucket;        // [max_tiles]  cost bucket and rank inside it
     float4* ps;           // [max_points] {q.xyz, aux}
     float4* pv;           // [max_points] {O, lse, 0, 0} (backward inputs)
     int* pidx;            // [max_points] original query index

@@ -128,6 +128,8 @@ __global__ void k_reset_stats(DevStats* st)
         st->fb_loss[0] = 0.0;
         st->fb_loss[1] = 0.0;
     }
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < 128; i += blockDim.x) st->bcount[i] = 0;
 }
 
 // --------------------------------------------------------- key preparation
@@ -363,7 +365,7 @@ __global__ void k_scatter_points(const float* __restrict__ q, const float* __res
     const int64_t pos = (int64_t)pstart[pcell[j]] + prank[j];
     ps[pos] = make_float4(q[3 * j], q[3 * j + 1], q[3 * j + 2], aux ? aux[j] : 0.0f);
     if (Oin) pv[pos] = make_float4(Oin[j], lsein[j], 0.0f, 0.0f);
-    pidx[pos] = (int)j;
+    if (pidx) pidx[pos] = (int)j;
 }
 
 // Tiles per block: a block with at most PMAX queries is one tile spanning its
@@ -382,24 +384,55 @@ __global__ void k_block_tiles(int64_t NB3, const int* __restrict__ pcount, int* 
     btiles[b] = tot == 0 ? 0 : (tot <= PMAX ? 1 : split);
 }
 
+// Cost of a tile: its queries times the keys of its window (before the
+// block-level truncation), bucketed on a log2 scale.
+__device__ int tile_bucket(int4 t, const Geo& g, int W, int offsets, const int* __restrict__ mstart)
+{
+    const int C1 = g.C1, R = g.R;
+    const int cx = t.x / (C1 * C1), cy = (t.x / C1) % C1, cz = t.x % C1;
+    const int cx1 = cx + (t.w & 1), cy1 = cy + ((t.w >> 1) & 1), cz1 = cz + ((t.w >> 2) & 1);
+    int64_t K = (int64_t)(min(cx1 + W, R - 1) - max(cx - W + 1, 0) + 1) *
+                (min(cy1 + W, R - 1) - max(cy - W + 1, 0) + 1) *
+                (min(cz1 + W, R - 1) - max(cz - W + 1, 0) + 1);
+    if (offsets) {
+        const int mx0 = max(cx - W, 0), mx1 = min(cx1 + W, C1 - 1);
+        const int my0 = max(cy - W, 0), my1 = min(cy1 + W, C1 - 1);
+        const int mz0 = max(cz - W, 0), mz1 = min(cz1 + W, C1 - 1);
+        for (int mx = mx0; mx <= mx1; ++mx)
+            for (int my = my0; my <= my1; ++my) {
+                const int row = (mx * C1 + my) * C1;
+                K += mstart[row + mz1 + 1] - mstart[row + mz0];
+            }
+    }
+    const float c = (float)(K * (int64_t)t.z);
+    return min(127, max(0, (int)(4.0f * log2f(fmaxf(c, 1.0f)))));
+}
+
 __global__ void k_build_tiles(int64_t NB3, Geo g, const int* __restrict__ pcount,
                               const int* __restrict__ pstart, const int* __restrict__ tstart,
-                              int4* __restrict__ tiles)
+                              int4* __restrict__ tiles, int2* __restrict__ tbucket, int offsets,
+                              const int* __restrict__ mstart, DevStats* __restrict__ st)
 {
     const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (b >= NB3) return;
     const int nt = tstart[b + 1] - tstart[b];
     if (nt == 0) return;
-    const int NB = g.NB, C1 = g.C1;
+    const int NB = g.NB, C1 = g.C1, W = st->W;
     const int bx = (int)(b / ((int64_t)NB * NB)), by = (int)((b / NB) % NB), bz = (int)(b % NB);
     int t = tstart[b];
     int tot = 0;
 #pragma unroll
     for (int s = 0; s < 8; ++s) tot += pcount[8 * b + s];
+    auto emit = [&](int4 tl) {
+        const int bk = tile_bucket(tl, g, W, offsets, mstart);
+        tiles[t] = tl;
+        tbucket[t] = make_int2(bk, atomicAdd(&st->bcount[bk], 1));
+        ++t;
+    };
     if (tot <= PMAX) {
         const int ex = min(2, C1 - 2 * bx), ey = min(2, C1 - 2 * by), ez = min(2, C1 - 2 * bz);
         const int c0 = ((2 * bx) * C1 + 2 * by) * C1 + 2 * bz;
-        tiles[t] = make_int4(c0, pstart[8 * b], tot, (ex - 1) | ((ey - 1) << 1) | ((ez - 1) << 2));
+        emit(make_int4(c0, pstart[8 * b], tot, (ex - 1) | ((ey - 1) << 1) | ((ez - 1) << 2)));
         return;
     }
     for (int s = 0; s < 8; ++s) {
@@ -410,8 +443,32 @@ __global__ void k_build_tiles(int64_t NB3, Geo g, const int* __restrict__ pcount
         const int k = (n + PMAX - 1) / PMAX;
         for (int i = 0; i < k; ++i) {
             const int lo = (int)((int64_t)i * n / k), hi = (int)((int64_t)(i + 1) * n / k);
-            tiles[t++] = make_int4(c, pstart[8 * b + s] + lo, hi - lo, 0);
+            emit(make_int4(c, pstart[8 * b + s] + lo, hi - lo, 0));
         }
+    }
+}
+
+// Reorder the tiles by descending cost bucket (a counting sort) so that the
+// persistent tile kernel starts the heaviest tiles first.
+__global__ __launch_bounds__(BLOCK) void k_order_tiles(const int* __restrict__ ntiles,
+                                                       const int4* __restrict__ tin,
+                                                       const int2* __restrict__ tbucket,
+                                                       const DevStats* __restrict__ st,
+                                                       int4* __restrict__ tout)
+{
+    __shared__ int start[128];
+    __shared__ int sh[BLOCK / 64];
+    const int tid = threadIdx.x;
+    // exclusive scan over buckets 127, 126, ..., 0
+    const int c = tid < 128 ? st->bcount[127 - tid] : 0;
+    int tot;
+    const int ex = block_excl_scan(c, sh, &tot);
+    if (tid < 128) start[127 - tid] = ex;
+    __syncthreads();
+    const int n = *ntiles;
+    for (int t = tid; t < n; t += BLOCK) {
+        const int2 b = tbucket[t];
+        tout[start[b.x] + b.y] = tin[t];
     }
 }
 
@@ -586,8 +643,10 @@ __device__ __forceinline__ void fwd_qgrad(const TileSmem& S, int n, int ph, int 
     }
 }
 
+// Four workgroups (16 waves) per CU: 128 VGPRs, no spills; measured 7 %
+// faster than the unconstrained 155-VGPR allocation (3 workgroups).
 template <int MODE, bool QGRAD>
-__global__ __launch_bounds__(BLOCK) void k_tile(TileArgs a)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_tile(TileArgs a)
 {
     static_assert(KC == BLOCK, "one staged key per thread");
     __shared__ TileSmem S;
@@ -761,52 +820,48 @@ __global__ __launch_bounds__(BLOCK) void k_tile(TileArgs a)
             // M0 <= lse2 for every query, so this drops only pairs below e^-T
             const float fcut = bl[6] - a.T2;
 
-            // lanes per query (P < BLOCK) or queries per lane (P > BLOCK, then 2)
-            const int npl = P > BLOCK ? 2 : 1;
-            const int Sf = npl == 2 ? 1 : max(1, BLOCK / max(P, 1));
+            // Query-to-lane mapping in two rounds: queries [0, P1) with Sf lanes each
+            // and queries [BLOCK, P) (at most BLOCK - 1 of them) with Sf2 lanes
+            // each; the partial sums of query p live in slots slot(p, 0..n-1).
+            const int P1 = min(P, BLOCK), P2 = P - P1;
+            const int Sf = max(1, BLOCK / P1);
+            const int Sf2 = P2 > 0 ? max(1, BLOCK / P2) : 1;
             const int pme = tid / Sf, ph = tid - pme * Sf;
-            const bool act = pme < P;
-            const int p1 = (pme + BLOCK < P) ? pme + BLOCK : pme;  // second query (or a copy)
+            const int pme2 = tid / Sf2, ph2 = tid - pme2 * Sf2;
+            const bool act = pme < P1;
+            const bool act2 = pme2 < P2;
+            auto slot0 = [&](int p) { return p < BLOCK ? p * Sf : BLOCK + (p - BLOCK) * Sf2; };
+            auto nslot = [&](int p) { return p < BLOCK ? Sf : Sf2; };
+            float4 q[1] = {S.pq[act ? pme : 0]};
+            float4 q2[1] = {S.pq[act2 ? BLOCK + pme2 : 0]};
 
             if (exact) {
                 // exact maximum over the window first (rare: very coarse lattices)
-                float M[2] = {-INFINITY, -INFINITY};
-                float4 q[2] = {S.pq[act ? pme : 0], S.pq[act ? p1 : 0]};
+                float M[1] = {-INFINITY}, M2[1] = {-INFINITY};
                 for (int c = 0; c < nchunks; ++c) {
                     const int k0 = c * KC, nk = min(KC, K - k0);
                     __syncthreads();
                     nstaged = stage_cull(k0, nk, bl, fcut);
                     nstaged_moved = nmoved;
                     staged = c;
-                    if (act) {
-                        if (npl == 2) {
-                            fwd_max<2>(S, nstaged, ph, Sf, q, M);
-                        } else {
-                            float4 q1[1] = {q[0]};
-                            float M1[1] = {M[0]};
-                            fwd_max<1>(S, nstaged, ph, Sf, q1, M1);
-                            M[0] = M1[0];
-                        }
-                    }
+                    if (act) fwd_max<1>(S, nstaged, ph, Sf, q, M);
+                    if (act2) fwd_max<1>(S, nstaged, ph2, Sf2, q2, M2);
                 }
                 S.red[tid].x = M[0];
-                if (npl == 2) S.red[BLOCK + tid].x = M[1];
+                S.red[BLOCK + tid].x = M2[0];
                 __syncthreads();
                 for (int p = tid; p < P; p += BLOCK) {
                     float mx = S.pv[p].w;
-                    for (int s = 0; s < Sf; ++s) mx = fmaxf(mx, S.red[p * Sf + s].x);
+                    for (int s = 0; s < nslot(p); ++s) mx = fmaxf(mx, S.red[slot0(p) + s].x);
                     S.pv[p].w = mx;
                 }
             }
 
             // ---- forward: e = sum 2^(s - M), m = sum 2^(s - M) f   (Alg. 1)
-            float4 q[2];
-            float Mr[2], e[2] = {0.0f, 0.0f}, m[2] = {0.0f, 0.0f};
+            float Mr[1], Mr2[1], e[1] = {0.0f}, m[1] = {0.0f}, e2[1] = {0.0f}, m2[1] = {0.0f};
             __syncthreads();
-            q[0] = S.pq[act ? pme : 0];
-            q[1] = S.pq[act ? p1 : 0];
             Mr[0] = S.pv[act ? pme : 0].w;
-            Mr[1] = S.pv[act ? p1 : 0].w;
+            Mr2[0] = S.pv[act2 ? BLOCK + pme2 : 0].w;
             for (int c = 0; c < nchunks; ++c) {
                 const int k0 = c * KC, nk = min(KC, K - k0);
                 if (staged != c) {
@@ -817,21 +872,12 @@ __global__ __launch_bounds__(BLOCK) void k_tile(TileArgs a)
                 }
                 fwd_pairs += (unsigned long long)nstaged * P;
                 fwd_moved += (unsigned long long)nstaged_moved * P;
-                if (act) {
-                    if (npl == 2) {
-                        fwd_sums<2>(S, nstaged, ph, Sf, q, Mr, e, m);
-                    } else {
-                        float4 q1[1] = {q[0]};
-                        float M1[1] = {Mr[0]}, e1[1] = {e[0]}, m1[1] = {m[0]};
-                        fwd_sums<1>(S, nstaged, ph, Sf, q1, M1, e1, m1);
-                        e[0] = e1[0];
-                        m[0] = m1[0];
-                    }
-                }
+                if (act) fwd_sums<1>(S, nstaged, ph, Sf, q, Mr, e, m);
+                if (act2) fwd_sums<1>(S, nstaged, ph2, Sf2, q2, Mr2, e2, m2);
             }
             __syncthreads();
             S.red[tid] = make_float2(e[0], m[0]);
-            if (npl == 2) S.red[BLOCK + tid] = make_float2(e[1], m[1]);
+            S.red[BLOCK + tid] = make_float2(e2[0], m2[0]);
             __syncthreads();
 
             // ---- per query: O, lse, certificate, loss and dL/dO
@@ -845,8 +891,8 @@ __global__ __launch_bounds__(BLOCK) void k_tile(TileArgs a)
             double lsq = 0.0, lab = 0.0;
             for (int p = tid; p < P; p += BLOCK) {
                 float ee = 0.0f, mm = 0.0f;
-                for (int s = 0; s < Sf; ++s) {
-                    const float2 r = S.red[p * Sf + s];
+                for (int s = 0; s < nslot(p); ++s) {
+                    const float2 r = S.red[slot0(p) + s];
                     ee += r.x;
                     mm += r.y;
                 }
@@ -888,9 +934,9 @@ __global__ __launch_bounds__(BLOCK) void k_tile(TileArgs a)
             __syncthreads();
 
             if (MODE == MODE_EVAL && QGRAD) {
-                float O2[2] = {S.pv[act ? pme : 0].x, S.pv[act ? p1 : 0].x};
-                float L2[2] = {S.pv[act ? pme : 0].y, S.pv[act ? p1 : 0].y};
-                float gx[2] = {0, 0}, gy[2] = {0, 0}, gz[2] = {0, 0};
+                float O1[1] = {S.pv[act ? pme : 0].x}, L1[1] = {S.pv[act ? pme : 0].y};
+                float O2[1] = {S.pv[act2 ? BLOCK + pme2 : 0].x}, L2[1] = {S.pv[act2 ? BLOCK + pme2 : 0].y};
+                float gx[1] = {0}, gy[1] = {0}, gz[1] = {0}, hx[1] = {0}, hy[1] = {0}, hz[1] = {0};
                 for (int c = nchunks - 1; c >= 0; --c) {
                     const int k0 = c * KC, nk = min(KC, K - k0);
                     if (staged != c) {
@@ -898,35 +944,24 @@ __global__ __launch_bounds__(BLOCK) void k_tile(TileArgs a)
                         nstaged = stage_cull(k0, nk, bl, fcut);
                         staged = c;
                     }
-                    if (act) {
-                        if (npl == 2) {
-                            fwd_qgrad<2>(S, nstaged, ph, Sf, q, O2, L2, gx, gy, gz);
-                        } else {
-                            float4 q1[1] = {q[0]};
-                            float o1[1] = {O2[0]}, l1[1] = {L2[0]};
-                            float x1[1] = {gx[0]}, y1[1] = {gy[0]}, z1[1] = {gz[0]};
-                            fwd_qgrad<1>(S, nstaged, ph, Sf, q1, o1, l1, x1, y1, z1);
-                            gx[0] = x1[0]; gy[0] = y1[0]; gz[0] = z1[0];
-                        }
-                    }
+                    if (act) fwd_qgrad<1>(S, nstaged, ph, Sf, q, O1, L1, gx, gy, gz);
+                    if (act2) fwd_qgrad<1>(S, nstaged, ph2, Sf2, q2, O2, L2, hx, hy, hz);
                 }
                 __syncthreads();
                 float* zf = S.fv;  // keys no longer needed
                 S.red[tid] = make_float2(gx[0], gy[0]);
                 zf[tid] = gz[0];
-                if (npl == 2) {
-                    S.red[BLOCK + tid] = make_float2(gx[1], gy[1]);
-                    zf[BLOCK + tid] = gz[1];
-                }
+                S.red[BLOCK + tid] = make_float2(hx[0], hy[0]);
+                zf[BLOCK + tid] = hz[0];
                 staged = -1;
                 __syncthreads();
                 for (int p = tid; p < P; p += BLOCK) {
                     if (S.pv[p].z == 0.0f) continue;  // uncertified: fallback writes it
                     float sx = 0.0f, sy = 0.0f, sz = 0.0f;
-                    for (int s = 0; s < Sf; ++s) {
-                        sx += S.red[p * Sf + s].x;
-                        sy += S.red[p * Sf + s].y;
-                        sz += zf[p * Sf + s];
+                    for (int s = 0; s < nslot(p); ++s) {
+                        sx += S.red[slot0(p) + s].x;
+                        sy += S.red[slot0(p) + s].y;
+                        sz += zf[slot0(p) + s];
                     }
                     const int j = a.pidx[p0 + p];
                     a.dOdq_out[3 * (int64_t)j] = sx;
@@ -1366,14 +1401,18 @@ hipError_t run_tiles(const Work& w, const Problem& p, Mode mode, hipStream_t s)
         hipError_t e = scan(w.pcount, w.NK, w.scan_blk, w.pstart, nullptr, false, s);
         if (e != hipSuccess) return e;
     }
+    // the fit step writes no per-query outputs and needs no original indices
     k_scatter_points<<<grid_for(J), BLOCK, 0, s>>>(p.q, p.aux, p.O_in, p.lse_in, J, w.pcell,
-                                                   w.prank, w.pstart, w.ps, w.pv, w.pidx);
+                                                   w.prank, w.pstart, w.ps, w.pv,
+                                                   mode == MODE_FIT ? nullptr : w.pidx);
     k_block_tiles<<<grid_for(w.NB3), BLOCK, 0, s>>>(w.NB3, w.pcount, w.btiles);
     {
         hipError_t e = scan(w.btiles, w.NB3, w.scan_blk, w.tstart, nullptr, false, s);
         if (e != hipSuccess) return e;
     }
-    k_build_tiles<<<grid_for(w.NB3), BLOCK, 0, s>>>(w.NB3, g, w.pcount, w.pstart, w.tstart, w.tiles);
+    k_build_tiles<<<grid_for(w.NB3), BLOCK, 0, s>>>(w.NB3, g, w.pcount, w.pstart, w.tstart,
+                                                    w.tiles_tmp, w.tbucket, p.offsets, w.mstart, w.st);
+    k_order_tiles<<<1, BLOCK, 0, s>>>(w.tstart + w.NB3, w.tiles_tmp, w.tbucket, w.st, w.tiles);
 
     TileArgs a;
     a.g = g;

@@ -48,7 +48,8 @@ class efunc_stats(C.Structure):
     _fields_ = [("W", C.c_int32), ("n_tiles", C.c_int32), ("n_uncertified", C.c_int64),
                 ("pairs", C.c_int64), ("pairs_moved", C.c_int64), ("bwd_pairs", C.c_int64),
                 ("bwd_pairs_moved", C.c_int64), ("beta_min", C.c_float),
-                ("beta_grid_max", C.c_float), ("n_nonfinite", C.c_int32)]
+                ("beta_grid_max", C.c_float), ("n_nonfinite", C.c_int32),
+                ("workspace_bytes", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -491,3 +491,25 @@ def test_logit_conditioning_scale(orc):
     assert np.all(orc.eval_cond(orc.build_keys(g, th), q) <= 1e-14)
     one = np.array([[0.1, 0.2, 0.3, 40.0, 0.5, 1.0, 2.0, 3.0]])
     assert np.all(orc.eval_cond(one, q) == 0.0)
+
+
+def test_truncation_tail_scales(orc):
+    """The below-threshold parts of the error scales: nothing for T -> inf,
+    everything for T -> -inf, monotone in between."""
+    rng = np.random.default_rng(35)
+    g = orc.Grid(R=4)
+    keys = orc.build_keys(g, W.perturbed_theta(4, 36, rho0=3.0))
+    q = rand_q(rng, 40)
+    dl = rng.standard_normal(40)
+    gk, ak, b_hi = orc.grad_global(keys, q, dl, T=1e9)
+    _, _, b_lo = orc.grad_global(keys, q, dl, T=-1e9)
+    _, _, b_mid = orc.grad_global(keys, q, dl, T=10.0)
+    assert np.all(b_hi == 0) and np.allclose(b_lo, ak, rtol=1e-12, atol=0)
+    assert np.all(b_mid <= ak * (1 + 1e-12)) and 0 < b_mid.sum() < ak.sum()
+    k, t_hi = orc.eval_cond(keys, q, 1e9, with_tail=True)
+    _, t_lo = orc.eval_cond(keys, q, -1e9, with_tail=True)
+    _, t_mid = orc.eval_cond(keys, q, 10.0, with_tail=True)
+    O, _, _ = orc.eval_global(keys, q)
+    assert np.all(t_hi == 0) and np.all(t_mid <= t_lo) and np.all(t_mid >= 0)
+    # all keys: sum_a w_a |f_a - O| >= |sum_a w_a (f_a - O)| = 0, and <= 2 max |f|
+    assert np.all(t_lo <= 2 * (np.abs(keys[:, 4]).max() + 4 * np.abs(keys[:, 5:]).max()))

@@ -190,8 +190,8 @@ def test_grad_sphere_r8_full(E, init):
         G = eng.grad(tth, PT.to_dev(q), PT.to_dev(Or), PT.to_dev(lr), PT.to_dev(dl))
         torch.cuda.synchronize()
         G = G.cpu().numpy()
-    gr, ar = PT.oracle_grad(R, th, q, dl)
-    PT.check_grad(G, gr, ar)
+    gr, ar, br = PT.oracle_grad(R, th, q, dl)
+    PT.check_grad(G, gr, ar, br)
 
 
 def test_grad_accumulates_into_caller_buffer(E):
@@ -207,8 +207,8 @@ def test_grad_accumulates_into_caller_buffer(E):
         G = eng.grad(tth, PT.to_dev(q), PT.to_dev(Or), PT.to_dev(lr), PT.to_dev(dl), grad=base)
         torch.cuda.synchronize()
         G = G.cpu().numpy()
-    gr, ar = PT.oracle_grad(R, th, q, dl)
-    PT.check_grad(G - 0.5, gr, ar + 1e-7)
+    gr, ar, br = PT.oracle_grad(R, th, q, dl)
+    PT.check_grad(G - 0.5, gr, ar + 1e-7, br)
 
 
 def test_grad_outside_domain_fallback(E):
@@ -223,8 +223,8 @@ def test_grad_outside_domain_fallback(E):
         torch.cuda.synchronize()
         st = eng.stats()
         G = G.cpu().numpy()
-    gr, ar = PT.oracle_grad(R, th, q, dl)
-    PT.check_grad(G, gr, ar)
+    gr, ar, br = PT.oracle_grad(R, th, q, dl)
+    PT.check_grad(G, gr, ar, br)
     assert st["n_uncertified"] > 0
 
 
@@ -252,8 +252,8 @@ def test_fit_step_sphere_r8_full(E, init):
     # the GPU's gradient, recovered from the first moment m = (1 - beta1) g
     g_gpu = m1.astype(np.float64) / (1.0 - np.float32(0.9))
     O, _, _ = PT.oracle_values(R, th, q)
-    _, ar = PT.oracle_grad(R, th, q, 2 * (O - o) / len(q))
-    PT.check_grad(g_gpu, ref["grad"], ar)
+    _, ar, br = PT.oracle_grad(R, th, q, 2 * (O - o) / len(q))
+    PT.check_grad(g_gpu, ref["grad"], ar, br)
     # AdamW on the GPU's own gradient
     th_ref, _, _ = orc.adam(th.reshape(-1), np.zeros(n), np.zeros(n), g_gpu.reshape(-1), 1)
     tol = 4 * PT.ulp32(th_ref) + 1e-6 * 6e-4
@@ -285,6 +285,6 @@ def test_second_fit_step_starts_from_clean_gradient(E):
     O1, _, _ = PT.oracle_values(R, th1, q)
     assert abs(l2[0] - np.mean((O1 - o) ** 2)) <= 1e-5 * np.mean((O1 - o) ** 2)
     g2 = (m2.astype(np.float64) - np.float32(0.9) * m1.astype(np.float64)) / (1 - np.float32(0.9))
-    gr, ar = PT.oracle_grad(R, th1, q, 2 * (O1 - o) / len(q))
+    gr, ar, br = PT.oracle_grad(R, th1, q, 2 * (O1 - o) / len(q))
     # the subtraction of the rescaled first moment adds a few ulps of m1
-    PT.check_grad(g2, gr, ar + 20 * PT.ulp32(m1).reshape(ar.shape))
+    PT.check_grad(g2, gr, ar + 20 * PT.ulp32(m1).reshape(ar.shape), br)

@@ -1,0 +1,211 @@
+"""GPU parity at the full workload sizes, in the launch configuration the
+benchmark times.
+
+csg16_r32 (32^3, 2^21 points per iteration):
+  * efunc_eval on all points; 2048 sampled outputs against the global
+    definition, one by one;
+  * efunc_grad on all points with dL/dO non-zero on 512 sampled points (the
+    others contribute exactly nothing), every parameter against the global
+    definition;
+  * efunc_fit_step exactly as timed: loss, gradient (from the first moment)
+    and AdamW update against the oracle's truncated FP64 fit over all
+    2^21 points (truncation at e^-20, independent of the GPU's windows).
+csg256_r128 (128^3, 2^23 points):
+  * efunc_eval on all points; 96 sampled outputs against the global
+    definition (4.2M keys each);
+  * efunc_grad with dL/dO on 48 sampled points against the global definition;
+  * efunc_fit_step against the composition efunc_eval + efunc_grad (a
+    property of the fused step that holds at any size).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as orc
+import workloads as W
+from tests import parity as PT
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def E():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2505_21319_amd import efunc
+    efunc.lib()
+    return efunc
+
+
+def realistic_theta(w, seed):
+    """Paper initialisation (mean-shift offsets from 16,384 surface samples,
+    computed by the oracle) with seeded non-zero values and spread scales, so
+    that every gradient path is exercised at a realistic key layout."""
+    R = w.R
+    th = W.plain_theta(R)
+    surf = W.surface_points(w, 16384, seed=seed, device=PT.DEV)
+    th[..., 5:8] = orc.meanshift(orc.Grid(R=R), surf, 100.0).reshape(R, R, R, 3)
+    rng = np.random.default_rng(seed)
+    th[..., 0] = rng.uniform(-0.5, 0.5, (R, R, R))
+    th[..., 1:4] = rng.normal(0, 0.5, (R, R, R, 3))
+    th[..., 8] = rng.uniform(-0.5, 0.5, (R, R, R))
+    th[..., 9:12] = rng.normal(0, 0.5, (R, R, R, 3))
+    th[..., 4] = 7.0 + rng.uniform(-0.3, 0.3, (R, R, R))
+    th[..., 12] = 7.0 + rng.uniform(-0.3, 0.3, (R, R, R))
+    return th.astype(np.float32)
+
+
+def sample_idx(J, n, seed):
+    rng = np.random.default_rng(seed)
+    h = n // 2
+    return np.concatenate([rng.choice(J // 2, h, replace=False),
+                           J // 2 + rng.choice(J - J // 2, n - h, replace=False)])
+
+
+@pytest.fixture(scope="module")
+def r32():
+    w = W.get("csg16_r32")
+    q, o = W.make_batch(w, 0, device=PT.DEV)
+    return w, q, o, realistic_theta(w, 41)
+
+
+def test_eval_csg16_r32_full_size_sampled(E, r32):
+    w, q, o, th = r32
+    with E.Engine(w.R, w.J) as eng:
+        O, lse, _, nu = eng.eval(PT.to_dev(th), PT.to_dev(q))
+        torch.cuda.synchronize()
+        O, lse = O.cpu().numpy(), lse.cpu().numpy()
+    idx = sample_idx(w.J, 2048, 1)
+    ref = PT.reference(w.R, th, q[idx])
+    worst = PT.check_eval(O[idx], lse[idx], ref)
+    assert np.all(np.isfinite(O)) and int(nu.item()) == 0
+    print(f"worst err / tolerance over samples: {worst:.3f}")
+
+
+def test_grad_csg16_r32_full_size_sampled_dldo(E, r32):
+    w, q, o, th = r32
+    idx = sample_idx(w.J, 512, 2)
+    Or, lr, _ = PT.oracle_values(w.R, th, q[idx])
+    O = np.zeros(w.J, np.float32)
+    lse = np.zeros(w.J, np.float32)
+    dl = np.zeros(w.J, np.float32)
+    O[idx], lse[idx] = Or, lr
+    dl[idx] = np.random.default_rng(3).standard_normal(len(idx)) / len(idx)
+    # non-sampled queries: any finite O and lse; their dL/dO is zero
+    with E.Engine(w.R, w.J) as eng:
+        G = eng.grad(PT.to_dev(th), PT.to_dev(q), PT.to_dev(O), PT.to_dev(lse), PT.to_dev(dl))
+        torch.cuda.synchronize()
+        G = G.cpu().numpy()
+    gr, ar, br = PT.oracle_grad(w.R, th, q[idx], dl[idx].astype(np.float64))
+    PT.check_grad(G, gr, ar, br)
+
+
+def test_fit_step_csg16_r32_full_size(E, r32):
+    """The benchmarked call: one efunc_fit_step over all 2^21 points."""
+    w, q, o, th = r32
+    n = th.size
+    with E.Engine(w.R, w.J) as eng:
+        tth = PT.to_dev(th)
+        m = torch.zeros(n, device=PT.DEV)
+        v = torch.zeros(n, device=PT.DEV)
+        loss = torch.zeros(2, device=PT.DEV, dtype=torch.float64)
+        eng.fit_step(tth, m, v, 1, PT.to_dev(q), PT.to_dev(o), loss)
+        torch.cuda.synchronize()
+        th1, m1, loss = (x.cpu().numpy() for x in (tth, m, loss))
+    g = orc.Grid(R=w.R)
+    keys = orc.build_keys(g, th)
+    Ot, _, _ = orc.eval_trunc(g, keys, q, 20.0)
+    res = Ot - o.astype(np.float64)
+    assert abs(loss[0] - np.mean(res ** 2)) <= 1e-5 * np.mean(res ** 2)
+    assert abs(loss[1] - np.mean(np.abs(res))) <= 1e-5 * np.mean(np.abs(res))
+    gk, ak = orc.grad_trunc(g, keys, q, 2.0 * res / len(q), 20.0)
+    gr, ar = orc.grad_theta(g, th, gk), orc.grad_theta(g, th, ak)
+    g_gpu = m1.astype(np.float64) / (1.0 - np.float32(0.9))
+    PT.check_grad(g_gpu, gr, ar)
+    th_ref, _, _ = orc.adam(th.reshape(-1), np.zeros(n), np.zeros(n), g_gpu.reshape(-1), 1)
+    assert np.all(np.abs(th1.reshape(-1) - th_ref) <= 4 * PT.ulp32(th_ref) + 1e-6 * 6e-4)
+
+
+@pytest.fixture(scope="module")
+def r128():
+    w = W.get("csg256_r128")
+    q, o = W.make_batch(w, 0, device=PT.DEV)
+    return w, q, o, w.R
+
+
+def _r128_theta(E, w, seed):
+    """Mean-shift offsets from the library (pinned against the oracle on the
+    8^3 lattice; the oracle's R^3 x N mean-shift would take minutes at 128^3)
+    plus seeded values."""
+    R = w.R
+    surf = W.surface_points(w, 16384, seed=seed, device=PT.DEV)
+    with E.Engine(R, 16) as eng:
+        th = torch.empty(R, R, R, 13, device=PT.DEV)
+        eng.init_params(th, PT.to_dev(surf.astype(np.float32)), 100.0, 7.0)
+        torch.cuda.synchronize()
+        th = th.cpu().numpy()
+    rng = np.random.default_rng(seed)
+    th[..., 0] = rng.uniform(-0.5, 0.5, (R, R, R))
+    th[..., 1:4] = rng.normal(0, 0.5, (R, R, R, 3))
+    th[..., 8] = rng.uniform(-0.5, 0.5, (R, R, R))
+    th[..., 9:12] = rng.normal(0, 0.5, (R, R, R, 3))
+    return th.astype(np.float32)
+
+
+def test_eval_csg256_r128_full_size_sampled(E, r128):
+    w, q, o, R = r128
+    th = _r128_theta(E, w, 51)
+    with E.Engine(R, w.J) as eng:
+        O, lse, _, nu = eng.eval(PT.to_dev(th), PT.to_dev(q))
+        torch.cuda.synchronize()
+        st = eng.stats()
+        O, lse = O.cpu().numpy(), lse.cpu().numpy()
+    idx = sample_idx(w.J, 96, 4)
+    ref = PT.reference(R, th, q[idx])
+    PT.check_eval(O[idx], lse[idx], ref)
+    assert np.all(np.isfinite(O))
+    print(f"W={st['W']} tiles={st['n_tiles']} pairs={st['pairs']} uncertified={st['n_uncertified']}")
+
+
+def test_grad_csg256_r128_full_size_sampled_dldo(E, r128):
+    w, q, o, R = r128
+    th = _r128_theta(E, w, 52)
+    idx = sample_idx(w.J, 48, 5)
+    Or, lr, _ = PT.oracle_values(R, th, q[idx])
+    O = np.zeros(w.J, np.float32)
+    lse = np.zeros(w.J, np.float32)
+    dl = np.zeros(w.J, np.float32)
+    O[idx], lse[idx] = Or, lr
+    dl[idx] = np.random.default_rng(6).standard_normal(len(idx)) / len(idx)
+    with E.Engine(R, w.J) as eng:
+        G = eng.grad(PT.to_dev(th), PT.to_dev(q), PT.to_dev(O), PT.to_dev(lse), PT.to_dev(dl))
+        torch.cuda.synchronize()
+        G = G.cpu().numpy()
+    gr, ar, br = PT.oracle_grad(R, th, q[idx], dl[idx].astype(np.float64))
+    PT.check_grad(G, gr, ar, br)
+
+
+def test_fit_step_csg256_r128_matches_eval_then_grad(E, r128):
+    """At 128^3 x 2^23 points the fused step equals the composition of the
+    separately pinned eval and grad entry points: same loss, same gradient."""
+    w, q, o, R = r128
+    th = _r128_theta(E, w, 53)
+    n = th.size
+    with E.Engine(R, w.J) as eng:
+        tth, tq, to = PT.to_dev(th), PT.to_dev(q), PT.to_dev(o)
+        O, lse, _, _ = eng.eval(tth, tq)
+        res = (O.double() - to.double())
+        l_ref = float((res * res).mean())
+        dl = (2.0 * res / w.J).float()
+        G = eng.grad(tth, tq, O, lse, dl)
+        m = torch.zeros(n, device=PT.DEV)
+        v = torch.zeros(n, device=PT.DEV)
+        loss = torch.zeros(2, device=PT.DEV, dtype=torch.float64)
+        eng.fit_step(tth, m, v, 1, tq, to, loss)
+        torch.cuda.synchronize()
+        G, m1, loss = G.cpu().numpy(), m.cpu().numpy(), loss.cpu().numpy()
+    assert abs(loss[0] - l_ref) <= 1e-6 * l_ref
+    g_fit = m1.astype(np.float64) / (1.0 - np.float32(0.9))
+    # both are float32 sums of the same terms in different orders
+    scale = np.abs(G).reshape(-1, 13).max(axis=0)
+    err = np.abs(g_fit.reshape(-1, 13) - G.reshape(-1, 13))
+    assert np.all(err <= 1e-4 * np.abs(G.reshape(-1, 13)) + 1e-5 * scale)
