@@ -56,14 +56,19 @@ def kernel_source_sha() -> str:
 
 def measured_traffic(workload: str):
     """HBM bytes per tile-kernel launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"k_tile_fit_{workload}_pmc.json")
+    summary, if it was taken on the current kernel source (its lines
+    `kernel_source_sha: ...` and `hbm_bytes_per_launch: ...`)."""
+    path = os.path.join(ROOT, "profiles", f"k_tile_fit_{workload}_pmc.md")
     if not os.path.exists(path):
         return None
-    d = json.load(open(path))
-    if d.get("kernel_source_sha") != kernel_source_sha():
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.split(":", 1)[0].strip() in ("kernel_source_sha", "hbm_bytes_per_launch"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    if fields.get("kernel_source_sha") != kernel_source_sha():
         return None
-    return d.get("hbm_bytes_per_launch")
+    return int(float(fields["hbm_bytes_per_launch"]))
 
 
 def cpu_baseline(workload, q, o, R, theta, sample):
@@ -208,6 +213,123 @@ def compare_autodiff(args):
                       "table_shapes": rows, "benchmark_workload": cfg2}))
 
 
+def bench_batch(args, torch):
+    """Batched multi-shape fitting: 64 independent shapes (lattices 16^3 to
+    64^3, 2^18 to 2^22 points per iteration, both log-uniform), one resident
+    minibatch per shape, all shapes stepped together per iteration through
+    one captured HIP graph."""
+    import workloads as W
+    from paper_2505_21319_amd import efunc as E
+
+    dev = torch.device("cuda:0")
+    ws = W.batch_set("batch64", 64, 300)
+    t_gen = time.perf_counter()
+    thetas, qs, os_ = [], [], []
+    for i, w in enumerate(ws):
+        q, o = W.make_batch(w, 0, device=dev)
+        qs.append(torch.from_numpy(q).to(dev))
+        os_.append(torch.from_numpy(o).to(dev))
+        surf = W.surface_points(w, 16384, seed=W.seed_for(w, -2, "meanshift"), device=dev)
+        th = torch.empty(w.R ** 3 * 13, device=dev, dtype=torch.float32)
+        with E.Engine(w.R, 16) as e1:
+            e1.init_params(th, torch.from_numpy(surf.astype(np.float32)).to(dev), 100.0, 7.0)
+        thetas.append(th)
+        if (i + 1) % 16 == 0:
+            print(f"# generated {i + 1}/{len(ws)} shapes", file=sys.stderr, flush=True)
+    t_gen = time.perf_counter() - t_gen
+    ms_ = [torch.zeros_like(t) for t in thetas]
+    vs_ = [torch.zeros_like(t) for t in thetas]
+    loss = torch.zeros(len(ws), 2, device=dev, dtype=torch.float64)
+    Jtot = sum(w.J for w in ws)
+
+    B = E.BatchEngine([w.R for w in ws], [w.J for w in ws])
+    B.bind(thetas, ms_, vs_, qs, os_, loss)
+    tuned = None
+    if args.autotune:
+        tuned = B.autotune(reps=2)
+    step = 1
+    B.fit(step, args.warmup, use_graph=True)
+    step += args.warmup
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    B.fit(step, args.steps, use_graph=True)
+    step += args.steps
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+
+    # tile-kernel duration from directly launched iterations (events on the
+    # stream the kernel runs on)
+    n_eager = max(1, min(args.steps, 5))
+    E.efunc_batch_set_timing(B.b, True)
+    B.fit(step, n_eager, use_graph=False)
+    tile_ms, launches = E.efunc_batch_read_timing(B.b)
+    E.efunc_batch_set_timing(B.b, False)
+    sts = [B.stats(i) for i in range(len(ws))]
+    lossv = loss.cpu().numpy()
+    pairs = sum(st["pairs"] for st in sts)
+    bp = sum(st["bwd_pairs"] for st in sts)
+    bpm = sum(st["bwd_pairs_moved"] for st in sts)
+    ops = pairs * OPS_FWD + (bp - bpm) * OPS_BWD_GRID + bpm * OPS_BWD_MOVED
+    tile_avg_s = tile_ms / max(launches, 1) * 1e-3
+    achieved = ops / tile_avg_s
+    Rs = [w.R for w in ws]
+    out = {
+        "metric": "batched fit points·iters/sec (64 shapes, fused fwd+bwd)",
+        "value": Jtot * args.steps / (total_ms * 1e-3),
+        "unit": "points*iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": total_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "batch64",
+            "shapes": len(ws),
+            "R_min": min(Rs), "R_max": max(Rs),
+            "points_per_iter": Jtot,
+            "J_min": min(w.J for w in ws), "J_max": max(w.J for w in ws),
+            "params": sum(R ** 3 * 13 for R in Rs),
+            "target": "per shape a smooth union (k=0.05) of 4..64 seeded spheres/boxes",
+            "init": "rho=7, zero values, mean-shift offsets (16384 surface samples, bandwidth 100)",
+            "graph": True,
+            "tuning": B.tuning(),
+            "autotuned_ms": tuned[1] if tuned else None,
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_tile_batch",
+            "achieved": achieved / 1e12,
+            "peak": ROOFLINE_PEAK / 1e12,
+            "unit": "Tops/s",
+            "frac": achieved / ROOFLINE_PEAK,
+            "traffic": None,
+            "tile_kernel_ms": tile_avg_s * 1e3,
+            "fwd_pairs_per_launch": pairs,
+            "bwd_pairs_per_launch": bp,
+            "bwd_moved_pairs_per_launch": bpm,
+            "ops_per_launch": ops,
+        },
+        "stats": {"uncertified": sum(st["n_uncertified"] for st in sts),
+                  "tiles": sum(st["n_tiles"] for st in sts),
+                  "loss_mse_mean": float(lossv[:, 0].mean()), "gen_seconds": t_gen,
+                  "kernel_source_sha": kernel_source_sha()},
+    }
+    if not args.no_cpu_baseline:
+        w = ws[0]
+        th0 = W.plain_theta(w.R)
+        out["cpu_baseline"] = cpu_baseline(w, qs[0].cpu().numpy(), os_[0].cpu().numpy(), w.R, th0,
+                                           args.cpu_sample)
+    B.close()
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -219,6 +341,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--compare-autodiff", action="store_true",
                     help="print the fused vs materialising-autodiff comparison instead")
+    ap.add_argument("--autotune", action="store_true",
+                    help="batch64: run the autotuner before timing")
+    ap.add_argument("--tuning", default="",
+                    help="tile_cap,group_cells,blocks_per_cu for the tile kernel (default 512,1,8)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -243,6 +369,10 @@ def main():
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
         return
 
+    if args.workload == "batch64":
+        bench_batch(args, torch)
+        return
+
     import workloads as W
     from paper_2505_21319_amd import efunc as E
 
@@ -258,6 +388,8 @@ def main():
     t_gen = time.perf_counter() - t_gen
 
     eng = E.Engine(R, J)
+    if args.tuning:
+        eng.set_tuning(*[int(x) for x in args.tuning.split(",")])
     theta = torch.empty(R, R, R, 13, device=dev, dtype=torch.float32)
     eng.init_params(theta, torch.from_numpy(surf.astype(np.float32)).to(dev), 100.0, 7.0)
     theta0 = theta.cpu().numpy()
@@ -322,6 +454,7 @@ def main():
             "init": "rho=7, zero values, mean-shift offsets (16384 surface samples, bandwidth 100)",
             "t_cut": 20.0,
             "resident_batches": args.batches,
+            "tuning": eng.tuning(),
         },
         "roofline": {
             "bound": "alu",

@@ -74,6 +74,16 @@ typedef struct {
     float lr, beta1, beta2, eps, weight_decay; /* AdamW (Sec. 4.2: lr 6e-4) */
 } efunc_adam;
 
+/* Launch tuning of the tile kernel.  Results do not depend on it beyond the
+ * order of float additions (the tiles change, the window and the truncation
+ * rule do not). */
+typedef struct {
+    int32_t tile_cap;      /* queries per tile: 128, 256 or 512 (default 512) */
+    int32_t group_cells;   /* 1: a 2x2x2 block of cells with at most tile_cap queries
+                              shares one tile (default); 0: every cell has its own tiles */
+    int32_t blocks_per_cu; /* persistent workgroups launched per compute unit, 1..8 (default 8) */
+} efunc_tuning;
+
 /* Statistics of the last call on a context (host copy; see efunc_get_stats). */
 typedef struct {
     int32_t W;              /* window half-width in cells */
@@ -160,6 +170,83 @@ int efunc_get_stats(efunc_ctx* ctx, efunc_stats* out);
  * the record.  Errors: EFUNC_EINVAL, EFUNC_EHIP. */
 int efunc_set_timing(efunc_ctx* ctx, int32_t enable);
 int efunc_read_timing(efunc_ctx* ctx, double* tile_ms, int64_t* launches);
+
+/* Default tuning: tile_cap 512, group_cells 1, blocks_per_cu 8. */
+void efunc_default_tuning(efunc_tuning* t);
+
+/* Set / read the tuning of a context (host struct).  Takes effect from the
+ * next call.  Errors: EFUNC_EINVAL (values outside the ranges above). */
+int efunc_set_tuning(efunc_ctx* ctx, const efunc_tuning* t);
+int efunc_get_tuning(efunc_ctx* ctx, efunc_tuning* t);
+
+/* ------------------------------------------------------------------------
+ * Batched fitting of many shapes.  The paper fits one shape at a time; the
+ * batch runs one iteration of efunc_fit_step (Sec. 3.4 Eq. loss, AdamW of
+ * Sec. 4.2) for S independent shapes together: every shape's key and query
+ * binning and tiling (concurrently on internal streams), then ONE
+ * persistent tile kernel whose work queue holds the tiles of all shapes in
+ * one heaviest-first order, one fallback kernel, the per-shape losses and
+ * one AdamW launch over all parameter sets.  Each shape's result is that of
+ * efunc_fit_step on the same inputs up to the order of float additions.
+ * ------------------------------------------------------------------------ */
+typedef struct efunc_batch efunc_batch;
+
+/* Create a batch of n_shapes (>= 1) shapes: cfgs[s] and max_points[s] (host
+ * arrays) as for efunc_create (check_finite must be 0).  Allocates all
+ * device workspace.  Errors: EFUNC_EINVAL, EFUNC_EUNSUPPORTED, EFUNC_EHIP. */
+int efunc_batch_create(const efunc_config* cfgs, const int64_t* max_points, int32_t n_shapes,
+                       efunc_batch** out);
+
+/* Free the batch, its workspace, streams and graph (synchronises the
+ * device).  NULL is a no-op. */
+int efunc_batch_destroy(efunc_batch* b);
+
+/* Bind the data of every shape s (host arrays of n_shapes DEVICE pointers):
+ * theta[s], m[s], v[s] [R_s^3 x 13] float32 (updated in place), q[s]
+ * [J[s]][3], o[s] [J[s]] float32; J[s] (host) with 1 <= J[s] <= max_points[s].
+ * loss_out (DEVICE double [n_shapes][2], optional) receives each shape's
+ * {mean (O - o)^2, mean |O - o|} before the update of each step.  The
+ * pointers are kept and used by later efunc_batch_fit calls (any captured
+ * graph is discarded).  Errors: EFUNC_EINVAL, EFUNC_ESIZE. */
+int efunc_batch_bind(efunc_batch* b, float* const* theta, float* const* m, float* const* v,
+                     const float* const* q, const float* const* o, const int64_t* J,
+                     double* loss_out);
+
+/* Run n_steps (>= 0) fitting iterations on the bound data, with AdamW step
+ * numbers first_step, first_step + 1, ... (first_step >= 1) for all shapes.
+ * use_graph = 1: one iteration is captured into a HIP graph on first use
+ * (again after a bind, a tuning change or other Adam hyper-parameters) and
+ * replayed n_steps times on `stream`; 0: launched directly.  adam: host
+ * pointer (NULL = defaults).  Asynchronous on `stream`.
+ * Errors: EFUNC_EINVAL (not bound, bad step), EFUNC_EHIP. */
+int efunc_batch_fit(efunc_batch* b, const efunc_adam* adam, int64_t first_step, int64_t n_steps,
+                    int32_t use_graph, void* stream);
+
+/* Tuning shared by all shapes of the batch (as efunc_set_tuning). */
+int efunc_batch_set_tuning(efunc_batch* b, const efunc_tuning* t);
+int efunc_batch_get_tuning(efunc_batch* b, efunc_tuning* t);
+
+/* Autotuner: times `reps` (>= 1) directly launched iterations on the bound
+ * data for every candidate tuning (tile_cap 128/256/512 x group_cells 0/1 x
+ * blocks_per_cu 4/8), keeps the fastest (smallest median iteration time)
+ * and sets it on the batch.  theta, m and v are saved first and restored
+ * afterwards, so the bound data are unchanged; the call allocates that
+ * temporary copy and synchronises `stream`.  best (host, optional) receives
+ * the chosen tuning, best_ms (host, optional) its median iteration time.
+ * Errors: EFUNC_EINVAL (not bound), EFUNC_EHIP. */
+int efunc_batch_autotune(efunc_batch* b, const efunc_adam* adam, int32_t reps, efunc_tuning* best,
+                         double* best_ms, void* stream);
+
+/* Statistics of shape s in the last iteration (as efunc_get_stats;
+ * synchronises the device). */
+int efunc_batch_get_stats(efunc_batch* b, int32_t shape, efunc_stats* out);
+
+/* Instrumentation of directly launched iterations (use_graph = 0): with
+ * timing enabled, each iteration records HIP events around the batched tile
+ * kernel on the call's stream (up to 4096 iterations); read_timing returns
+ * the summed milliseconds and the launch count and clears the record. */
+int efunc_batch_set_timing(efunc_batch* b, int32_t enable);
+int efunc_batch_read_timing(efunc_batch* b, double* tile_ms, int64_t* launches);
 
 /* Thread-local message of the last failing call on this thread ("" if none).
  * The pointer stays valid until the next call on the same thread. */

@@ -1,8 +1,7 @@
 // C ABI of the efunc engine (declared in include/efunc.h): argument checks,
 // workspace ownership, stream plumbing and error reporting.  No exception
 // crosses this boundary.
-#include "efunc.h"
-#include "efunc_internal.h"
+#include "efunc_ctx.h"
 
 #include <math.h>
 #include <stdarg.h>
@@ -14,26 +13,12 @@
 
 using namespace efunc;
 
-constexpr int MAX_TIMED = 4096;
-
-struct efunc_ctx {
-    efunc_config cfg;
-    Geo geo;
-    Work w;
-    hipStream_t last_stream;
-    int device;
-    std::vector<void*> allocs;
-    int64_t alloc_bytes = 0;
-    bool timing = false;
-    std::vector<hipEvent_t> ev;  // 2 * MAX_TIMED when timing has been enabled
-    int nrec = 0;
-};
-
 namespace {
-
 thread_local std::string g_err;
+}
 
-int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+namespace efunc {
+
 int fail(int code, const char* fmt, ...)
 {
     char buf[512];
@@ -49,6 +34,23 @@ int hip_fail(hipError_t e, const char* what)
 {
     return fail(EFUNC_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
+
+void clear_error() { g_err.clear(); }
+
+int check_tuning(const efunc_tuning* t)
+{
+    if (!t) return fail(EFUNC_EINVAL, "tuning is NULL");
+    if (t->tile_cap != 128 && t->tile_cap != 256 && t->tile_cap != 512)
+        return fail(EFUNC_EINVAL, "tile_cap = %d is not 128, 256 or 512", t->tile_cap);
+    if (t->group_cells != 0 && t->group_cells != 1) return fail(EFUNC_EINVAL, "group_cells must be 0 or 1");
+    if (t->blocks_per_cu < 1 || t->blocks_per_cu > 8)
+        return fail(EFUNC_EINVAL, "blocks_per_cu = %d outside [1, 8]", t->blocks_per_cu);
+    return EFUNC_OK;
+}
+
+}  // namespace efunc
+
+namespace {
 
 bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
@@ -179,6 +181,14 @@ void efunc_default_adam(efunc_adam* a)
     a->weight_decay = 0.0f;
 }
 
+void efunc_default_tuning(efunc_tuning* t)
+{
+    if (!t) return;
+    t->tile_cap = PMAX;
+    t->group_cells = 1;
+    t->blocks_per_cu = 8;
+}
+
 const char* efunc_last_error(void) { return g_err.c_str(); }
 
 int efunc_create(const efunc_config* cfg, int64_t max_points, efunc_ctx** out)
@@ -223,10 +233,14 @@ int efunc_create(const efunc_config* cfg, int64_t max_points, efunc_ctx** out)
     const int64_t NB = (C1 + 1) / 2;
     w.NB3 = NB * NB * NB;
     w.NK = 8 * w.NB3;
-    // one tile per block with <= PMAX queries, else <= n/PMAX + 1 per cell
-    w.max_tiles = mp / PMAX + 8 * (mp / PMAX + 1) + (w.NB3 < mp ? w.NB3 : mp) + 1;
+    // tiles: at most mp / cap + 1 per non-empty cell when cells are split,
+    // one per grouped block, for every cap >= PMIN_CAP
+    w.max_tiles = mp / PMIN_CAP + 8 * (mp / PMIN_CAP + 1) + (C < mp ? C : mp) + 1;
     w.num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
-    const int64_t nblk = (w.NK + 1 + SCAN_TILE - 1) / SCAN_TILE;
+    w.nch = (w.max_tiles + BLOCK - 1) / BLOCK;
+    const int64_t nkeys = 128 * SLICE_KEYS * w.nch;
+    const int64_t nscan = w.NK * PSPLIT > nkeys ? w.NK * PSPLIT : nkeys;
+    const int64_t nblk = (nscan + SCAN_TILE - 1) / SCAN_TILE;
 
     hipError_t err = hipSuccess;
 #define ALLOC(ptr, n) \
@@ -241,19 +255,21 @@ int efunc_create(const efunc_config* cfg, int64_t max_points, efunc_ctx** out)
     ALLOC(w.mk, 3 * I);
     ALLOC(w.pcell, mp);
     ALLOC(w.prank, mp);
-    ALLOC(w.pcount, w.NK);
-    ALLOC(w.pstart, w.NK + 1);
+    ALLOC(w.pcount, w.NK * PSPLIT);
+    ALLOC(w.pstart, w.NK * PSPLIT + 1);
     ALLOC(w.btiles, w.NB3);
     ALLOC(w.tstart, w.NB3 + 1);
     ALLOC(w.tiles, w.max_tiles);
     ALLOC(w.tiles_tmp, w.max_tiles);
     ALLOC(w.tbucket, w.max_tiles);
+    ALLOC(w.chist, nkeys);
+    ALLOC(w.cstart, nkeys + 1);
     ALLOC(w.ps, mp);
     ALLOC(w.pv, mp);
     ALLOC(w.pidx, mp);
     ALLOC(w.fb, mp);
     ALLOC(w.lpart, w.max_tiles);
-    ALLOC(w.scan_blk, 2 * nblk + 2);
+    ALLOC(w.scan_blk, nblk + 1);
     ALLOC(w.grad, NCH * I);
     ALLOC(w.st, 1);
 #undef ALLOC
@@ -415,6 +431,29 @@ int efunc_fit_step(efunc_ctx* ctx, float* theta, float* m, float* v, int64_t ste
     e = run_adam(ctx->w, theta, m, v, (int64_t)NCH * ctx->w.I, hp.lr, hp.beta1, hp.beta2, hp.eps,
                  hp.weight_decay, (float)bc1, (float)bc2, s);
     if (e != hipSuccess) return hip_fail(e, "adam launch");
+    return EFUNC_OK;
+}
+
+int efunc_set_tuning(efunc_ctx* ctx, const efunc_tuning* t)
+{
+    g_err.clear();
+    int rc;
+    if ((rc = check_ctx(ctx)) || (rc = check_tuning(t))) return rc;
+    ctx->w.cap = t->tile_cap;
+    ctx->w.group = t->group_cells;
+    ctx->w.bpc = t->blocks_per_cu;
+    return EFUNC_OK;
+}
+
+int efunc_get_tuning(efunc_ctx* ctx, efunc_tuning* t)
+{
+    g_err.clear();
+    int rc;
+    if ((rc = check_ctx(ctx))) return rc;
+    if (!t) return fail(EFUNC_EINVAL, "out is NULL");
+    t->tile_cap = ctx->w.cap;
+    t->group_cells = ctx->w.group;
+    t->blocks_per_cu = ctx->w.bpc;
     return EFUNC_OK;
 }
 

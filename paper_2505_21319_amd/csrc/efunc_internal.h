@@ -10,30 +10,41 @@ namespace efunc {
 constexpr int NCH = 13;
 constexpr int BLOCK = 256;      // threads per workgroup (4 wave64)
 constexpr int PMAX = 512;       // queries per tile (two per thread at most)
+constexpr int PMIN_CAP = 128;   // smallest tile query cap the workspace is sized for
 constexpr int KC = 256;         // keys per LDS chunk
 constexpr int MAXSEG = 1024;    // moved-key row segments per window ((2W+1)^2, W <= 15)
 constexpr int WMAX = 15;        // largest window half-width
 constexpr int SCAN_TILE = 1024; // elements per block in the prefix scans
+constexpr int PSPLIT = 4;       // sub-counters per cell in the query histogram
+constexpr int SLICE_KEYS = 8;   // slice-index sort keys per cost bucket in the tile order
 constexpr float LOG2E = 1.4426950408889634f;
 constexpr float LN2 = 0.6931471805599453f;
 
 // Per-context device statistics and counters (one instance in device memory).
+// Fields read by every tile (scales, W) and the atomically updated counters
+// live on separate 128-byte lines: a plain load from a line that other
+// workgroups update with device-scope atomics is slow on MI355X, and so are
+// atomics from many workgroups to one line.
 struct DevStats {
     unsigned int bmin_bits;   // min beta over all keys (positive float bits)
     unsigned int bgmax_bits;  // max beta over grid keys
     int W;                    // window half-width of this call
+    int nonfinite;            // non-finite parameters seen by the key preparation
+    int pad0[28];
     int queue;                // tile work-queue head
+    int pad1[31];
     int nfb;                  // queries appended to the fallback list
     int fbqueue;              // fallback work-queue head
-    int nonfinite;            // non-finite parameters seen by the key preparation
-    int pad;
+    int pad2[30];
     unsigned long long pairs; // key-query pairs in windows
     unsigned long long pairs_moved;  // of which with moved keys
     unsigned long long bwd_pairs;    // pairs evaluated by the backward (after block truncation)
     unsigned long long bwd_pairs_moved;
     double fb_loss[2];        // loss sums of fallback queries
+    int pad3[20];
     int bcount[128];          // tiles per cost bucket (log2 of the window pair count)
 };
+static_assert(sizeof(DevStats) == 4 * 128 + 512, "DevStats layout");
 
 // Lattice geometry passed by value to every kernel.
 struct Geo {
@@ -61,22 +72,30 @@ struct Work {
                           //        {c_hi.xyz, nb}, {o', d'.xyz}, {c_lo.xyz, vid bits}
     int* pcell;           // [max_points] sort key of each query
     int* prank;           // [max_points]
-    int* pcount;          // [NK]   queries per cell, block-major order
-    int* pstart;          // [NK+1]
+    int* pcount;          // [NK*PSPLIT] queries per (cell, sub-counter), block-major order
+    int* pstart;          // [NK*PSPLIT+1]
     int* btiles;          // [NB3]  tiles per cell block
     int* tstart;          // [NB3+1]
     int4* tiles;          // [max_tiles]  {first cell, first query, count, extent bits}, heaviest first
     int4* tiles_tmp;      // [max_tiles]  the same in block order
     int2* tbucket;        // [max_tiles]  cost bucket and rank inside it
+    int64_t nch;          // chunks of BLOCK tiles in the stable tile sort
+    int* chist;           // [128 SLICE_KEYS nch]  per-chunk sort-key histograms, key-major
+    int* cstart;          // [128 SLICE_KEYS nch + 1] their exclusive scan
     float4* ps;           // [max_points] {q.xyz, aux}
     float4* pv;           // [max_points] {O, lse, 0, 0} (backward inputs)
     int* pidx;            // [max_points] original query index
     int* fb;              // [max_points] fallback list (sorted query positions)
     double2* lpart;       // [max_tiles]  per-tile loss sums
-    int* scan_blk;        // [2 * ceil((C+1)/SCAN_TILE) + 2] scan block sums
+    int* scan_blk;        // [ceil(max(8 NB3 PSPLIT, 128 SLICE_KEYS nch) / SCAN_TILE) + 1] scan block sums
     float* grad;          // [13 I] internal gradient of efunc_fit_step (kept zero)
     DevStats* st;
     int num_cu;
+    // launch tuning (runtime): tile query cap, whether sparse 2x2x2 cell
+    // blocks share one tile, persistent workgroups per CU
+    int cap = PMAX;
+    int group = 1;
+    int bpc = 8;
 };
 
 enum Mode { MODE_FIT = 0, MODE_EVAL = 1, MODE_GRAD = 2 };
@@ -102,9 +121,68 @@ struct Problem {
     hipEvent_t ev_start, ev_stop;
 };
 
+// Arguments of the tile and fallback kernels for one shape.
+struct TileArgs {
+    Geo g;
+    int offsets;
+    float T2;      // T log2(e)
+    float two_over_J;
+    const float4* gk;
+    const float4* mk;
+    const int* mstart;
+    const float4* ps;
+    const float4* pv;
+    const int* pidx;
+    const int4* tiles;
+    const int* ntiles;  // &tstart[NB3]
+    int* fb;
+    double2* lpart;
+    DevStats* st;
+    float* O_out;
+    float* lse_out;
+    float* dOdq_out;
+    float* grad;
+    int64_t I;
+};
+
+// Per-shape arguments of the batched tile ordering, loss reduction and AdamW.
+struct BatchShape {
+    const int2* tbucket;   // cost bucket and rank of each tile (block order)
+    const int* ntiles;
+    const DevStats* st;
+    const double2* lpart;
+    double invJ;
+    double* loss_out;      // [2] MSE, L1 (may be null)
+    float* theta;
+    float* m;
+    float* v;
+    float* grad;
+    int64_t n;             // 13 R^3
+};
+
+struct AdamParams {
+    float lr, beta1, beta2, eps, wd;
+};
+
 // Enqueue the shared front end (key preparation and binning, query binning,
 // tiles) and then the mode's tile and fallback kernels.  Returns a HIP error.
 hipError_t run_tiles(const Work& w, const Problem& p, Mode mode, hipStream_t s);
+// The front end alone (ordered: tiles heavy-first in w.tiles; else only the
+// block-order list w.tiles_tmp with cost buckets in w.tbucket).
+hipError_t run_front(const Work& w, const Problem& p, Mode mode, bool ordered, hipStream_t s);
+TileArgs make_tile_args(const Work& w, const Problem& p, bool ordered);
+
+// Batched fitting over S shapes: global heavy-first order of all shapes'
+// tiles, one persistent tile kernel and one fallback kernel over all of them,
+// per-shape loss reduction, AdamW with the step read from device memory.
+hipError_t run_batch_order(const BatchShape* bs, int S, int64_t max_tiles, int* goff, int2* gtiles,
+                           int* ngt, int* gqueue, hipStream_t s);
+hipError_t run_batch_tiles(const TileArgs* tab, int S, const int2* gtiles, const int* ngt,
+                           int* gqueue, int grid, int fgrid, hipEvent_t ev_stop, hipStream_t s);
+hipError_t run_batch_finish(const BatchShape* bs, int S, int64_t nmax, const int64_t* step,
+                            const AdamParams& ap, hipStream_t s);
+hipError_t run_step_set(int64_t* step, int64_t v, hipStream_t s);
+hipError_t run_step_advance(int64_t* step, hipStream_t s);
 hipError_t run_loss_finalize(const Work& w, int64_t J, double* loss_out, hipStream_t s);
 hipError_t run_adam(const Work& w, float* theta, float* m, float* v, int64_t n, float lr,
                     float beta1, float beta2, float eps, float wd, float bc1, float bc2,

@@ -7,11 +7,12 @@
 // queries whose window certificate fails, and for fitting the loss
 // reduction and AdamW.
 //
-// Window.  A tile is the set (or a balanced slice of at most PMAX) of queries
-// in one lattice cell (cx, cy, cz).  Its keys are the grid vertices with
-// indices in [c - W + 1, c + W] per axis and the moved keys binned into cells
-// [c - W, c + W] per axis.  Every key outside lies at least W h away from any
-// query in the cell, and beyond the window box faces in general; a query is
+// Window.  A tile is the set (or a balanced slice of at most the tile cap)
+// of queries in one lattice cell or in one 2x2x2 block of cells [c0, c1].
+// Its keys are the grid vertices with indices in [c0 - W + 1, c1 + W] per
+// axis and the moved keys binned into cells [c0 - W, c1 + W] per axis.
+// Every key outside lies at least W h away from any query of the tile's
+// cells, beyond the window box faces in general; a query is
 // certified when even the widest excluded key (smallest beta) at the nearest
 // face has weight below exp(-T), otherwise it is re-evaluated against all
 // keys by the fallback kernel.
@@ -120,7 +121,6 @@ __global__ void k_reset_stats(DevStats* st)
         st->nfb = 0;
         st->fbqueue = 0;
         st->nonfinite = 0;
-        st->pad = 0;
         st->pairs = 0ull;
         st->pairs_moved = 0ull;
         st->bwd_pairs = 0ull;
@@ -233,92 +233,61 @@ __global__ void k_window(DevStats* st, Geo g, float T, int Wforce)
 }
 
 // --------------------------------------------------------------- prefix scan
-// Exclusive scans of per-cell counts (and, with TILES, of per-cell tile
-// counts ceil(count / PMAX)).  Three phases: block sums, one-block scan of
-// the block sums, block-local scans plus offsets.
-template <bool TILES>
+// Exclusive scan of per-cell counts in three phases: block sums, one-block
+// scan of the block sums, block-local scans plus offsets.
 __global__ __launch_bounds__(BLOCK) void k_scan_reduce(const int* __restrict__ cnt, int64_t n,
                                                        int* __restrict__ blk)
 {
     __shared__ int sh[BLOCK / 64];
     const int64_t base = blockIdx.x * (int64_t)SCAN_TILE;
-    int sx = 0, sy = 0;
+    int sx = 0;
     for (int k = threadIdx.x; k < SCAN_TILE; k += BLOCK) {
         const int64_t i = base + k;
-        if (i < n) {
-            const int c = cnt[i];
-            sx += c;
-            if (TILES) sy += (c + PMAX - 1) / PMAX;
-        }
+        if (i < n) sx += cnt[i];
     }
     sx = block_sum(sx, sh);
-    sy = block_sum(sy, sh);
-    if (threadIdx.x == 0) {
-        blk[2 * blockIdx.x] = sx;
-        blk[2 * blockIdx.x + 1] = sy;
-    }
+    if (threadIdx.x == 0) blk[blockIdx.x] = sx;
 }
 
 __global__ __launch_bounds__(BLOCK) void k_scan_blocks(int* __restrict__ blk, int nb)
 {
     __shared__ int sh[BLOCK / 64];
-    int carry_x = 0, carry_y = 0;
+    int carry = 0;
     for (int base = 0; base < nb; base += BLOCK) {
         const int i = base + threadIdx.x;
-        const int x = i < nb ? blk[2 * i] : 0;
-        const int y = i < nb ? blk[2 * i + 1] : 0;
-        int tx, ty;
+        const int x = i < nb ? blk[i] : 0;
+        int tx;
         const int ex = block_excl_scan(x, sh, &tx);
-        const int ey = block_excl_scan(y, sh, &ty);
-        if (i < nb) {
-            blk[2 * i] = carry_x + ex;
-            blk[2 * i + 1] = carry_y + ey;
-        }
-        carry_x += tx;
-        carry_y += ty;
+        if (i < nb) blk[i] = carry + ex;
+        carry += tx;
     }
-    if (threadIdx.x == 0) {
-        blk[2 * nb] = carry_x;
-        blk[2 * nb + 1] = carry_y;
-    }
+    if (threadIdx.x == 0) blk[nb] = carry;
 }
 
-template <bool TILES>
 __global__ __launch_bounds__(BLOCK) void k_scan_apply(const int* __restrict__ cnt, int64_t n,
                                                       const int* __restrict__ blk, int nb,
-                                                      int* __restrict__ start, int* __restrict__ tstart)
+                                                      int* __restrict__ start)
 {
     __shared__ int sh[BLOCK / 64];
     constexpr int PER = SCAN_TILE / BLOCK;
     const int64_t base = blockIdx.x * (int64_t)SCAN_TILE + threadIdx.x * (int64_t)PER;
-    int cx[PER], cy[PER];
-    int sx = 0, sy = 0;
+    int cx[PER];
+    int sx = 0;
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int64_t i = base + k;
-        const int c = i < n ? cnt[i] : 0;
-        cx[k] = c;
-        cy[k] = TILES ? (c + PMAX - 1) / PMAX : 0;
+        cx[k] = i < n ? cnt[i] : 0;
         sx += cx[k];
-        sy += cy[k];
     }
-    int tx, ty;
-    int ox = block_excl_scan(sx, sh, &tx) + blk[2 * blockIdx.x];
-    int oy = TILES ? block_excl_scan(sy, sh, &ty) + blk[2 * blockIdx.x + 1] : 0;
+    int tx;
+    int ox = block_excl_scan(sx, sh, &tx) + blk[blockIdx.x];
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int64_t i = base + k;
-        if (i < n) {
-            start[i] = ox;
-            if (TILES) tstart[i] = oy;
-        }
+        if (i < n) start[i] = ox;
         ox += cx[k];
-        oy += cy[k];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        start[n] = blk[2 * nb];
-        if (TILES) tstart[n] = blk[2 * nb + 1];
-    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) start[n] = blk[nb];
 }
 
 __global__ void k_scatter_keys(int64_t I, const int* __restrict__ mcell, const int* __restrict__ mrank,
@@ -348,7 +317,9 @@ __global__ void k_count_points(const float* __restrict__ q, int64_t J, Geo g, in
 {
     const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (j >= J) return;
-    const int c = order_key(cell_of(q[3 * j], g), cell_of(q[3 * j + 1], g), cell_of(q[3 * j + 2], g), g.NB);
+    // PSPLIT sub-counters per cell spread same-address atomics of dense cells
+    const int c = order_key(cell_of(q[3 * j], g), cell_of(q[3 * j + 1], g), cell_of(q[3 * j + 2], g), g.NB) *
+                      PSPLIT + (int)(j % PSPLIT);
     pcell[j] = c;
     prank[j] = atomicAdd(&pcount[c], 1);
 }
@@ -368,134 +339,177 @@ __global__ void k_scatter_points(const float* __restrict__ q, const float* __res
     if (pidx) pidx[pos] = (int)j;
 }
 
-// Tiles per block: a block with at most PMAX queries is one tile spanning its
-// cells; otherwise each cell gets balanced slices of at most PMAX queries.
-__global__ void k_block_tiles(int64_t NB3, const int* __restrict__ pcount, int* __restrict__ btiles)
+// Tiles per block: with grouping, a block with at most cap queries is one
+// tile spanning its cells; otherwise each cell gets balanced slices of at
+// most cap queries.
+// queries in cell s of block b (from the scanned sub-counters)
+__device__ __forceinline__ int cell_count(const int* __restrict__ pstart, int64_t b, int s)
+{
+    return pstart[(8 * b + s + 1) * PSPLIT] - pstart[(8 * b + s) * PSPLIT];
+}
+
+__global__ void k_block_tiles(int64_t NB3, const int* __restrict__ pstart, int cap, int group,
+                              int* __restrict__ btiles)
 {
     const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (b >= NB3) return;
     int tot = 0, split = 0;
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
-        const int n = pcount[8 * b + s];
+        const int n = cell_count(pstart, b, s);
         tot += n;
-        split += (n + PMAX - 1) / PMAX;
+        split += (n + cap - 1) / cap;
     }
-    btiles[b] = tot == 0 ? 0 : (tot <= PMAX ? 1 : split);
+    btiles[b] = tot == 0 ? 0 : ((group && tot <= cap) ? 1 : split);
 }
 
-// Cost of a tile: its queries times the keys of its window (before the
-// block-level truncation), bucketed on a log2 scale.
-__device__ int tile_bucket(int4 t, const Geo& g, int W, int offsets, const int* __restrict__ mstart)
-{
-    const int C1 = g.C1, R = g.R;
-    const int cx = t.x / (C1 * C1), cy = (t.x / C1) % C1, cz = t.x % C1;
-    const int cx1 = cx + (t.w & 1), cy1 = cy + ((t.w >> 1) & 1), cz1 = cz + ((t.w >> 2) & 1);
-    int64_t K = (int64_t)(min(cx1 + W, R - 1) - max(cx - W + 1, 0) + 1) *
-                (min(cy1 + W, R - 1) - max(cy - W + 1, 0) + 1) *
-                (min(cz1 + W, R - 1) - max(cz - W + 1, 0) + 1);
-    if (offsets) {
-        const int mx0 = max(cx - W, 0), mx1 = min(cx1 + W, C1 - 1);
-        const int my0 = max(cy - W, 0), my1 = min(cy1 + W, C1 - 1);
-        const int mz0 = max(cz - W, 0), mz1 = min(cz1 + W, C1 - 1);
-        for (int mx = mx0; mx <= mx1; ++mx)
-            for (int my = my0; my <= my1; ++my) {
-                const int row = (mx * C1 + my) * C1;
-                K += mstart[row + mz1 + 1] - mstart[row + mz0];
-            }
-    }
-    const float c = (float)(K * (int64_t)t.z);
-    return min(127, max(0, (int)(4.0f * log2f(fmaxf(c, 1.0f)))));
-}
-
-__global__ void k_build_tiles(int64_t NB3, Geo g, const int* __restrict__ pcount,
-                              const int* __restrict__ pstart, const int* __restrict__ tstart,
-                              int4* __restrict__ tiles, int2* __restrict__ tbucket, int offsets,
-                              const int* __restrict__ mstart, DevStats* __restrict__ st)
+__global__ void k_build_tiles(int64_t NB3, Geo g, const int* __restrict__ pstart, int cap, int group,
+                              const int* __restrict__ tstart, int4* __restrict__ tiles)
 {
     const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (b >= NB3) return;
     const int nt = tstart[b + 1] - tstart[b];
     if (nt == 0) return;
-    const int NB = g.NB, C1 = g.C1, W = st->W;
+    const int NB = g.NB, C1 = g.C1;
     const int bx = (int)(b / ((int64_t)NB * NB)), by = (int)((b / NB) % NB), bz = (int)(b % NB);
+    const int first = pstart[8 * b * PSPLIT];
     int t = tstart[b];
     int tot = 0;
 #pragma unroll
-    for (int s = 0; s < 8; ++s) tot += pcount[8 * b + s];
-    auto emit = [&](int4 tl) {
-        const int bk = tile_bucket(tl, g, W, offsets, mstart);
-        tiles[t] = tl;
-        tbucket[t] = make_int2(bk, atomicAdd(&st->bcount[bk], 1));
-        ++t;
-    };
-    if (tot <= PMAX) {
+    for (int s = 0; s < 8; ++s) tot += cell_count(pstart, b, s);
+    if (group && tot <= cap) {
         const int ex = min(2, C1 - 2 * bx), ey = min(2, C1 - 2 * by), ez = min(2, C1 - 2 * bz);
         const int c0 = ((2 * bx) * C1 + 2 * by) * C1 + 2 * bz;
-        emit(make_int4(c0, pstart[8 * b], tot, (ex - 1) | ((ey - 1) << 1) | ((ez - 1) << 2)));
+        tiles[t] = make_int4(c0, first, tot, (ex - 1) | ((ey - 1) << 1) | ((ez - 1) << 2));
         return;
     }
     for (int s = 0; s < 8; ++s) {
-        const int n = pcount[8 * b + s];
+        const int n = cell_count(pstart, b, s);
         if (n == 0) continue;
         const int cx = 2 * bx + (s >> 2), cy = 2 * by + ((s >> 1) & 1), cz = 2 * bz + (s & 1);
         const int c = (cx * C1 + cy) * C1 + cz;
-        const int k = (n + PMAX - 1) / PMAX;
+        const int k = (n + cap - 1) / cap;
+        const int start = pstart[(8 * b + s) * PSPLIT];
         for (int i = 0; i < k; ++i) {
             const int lo = (int)((int64_t)i * n / k), hi = (int)((int64_t)(i + 1) * n / k);
-            emit(make_int4(c, pstart[8 * b + s] + lo, hi - lo, 0));
+            // bits 3.. carry the slice index (ordering key; extents are bits 0..2)
+            tiles[t++] = make_int4(c, start + lo, hi - lo, min(i, SLICE_KEYS - 1) << 3);
         }
     }
 }
 
-// Reorder the tiles by descending cost bucket (a counting sort) so that the
-// persistent tile kernel starts the heaviest tiles first.
-__global__ __launch_bounds__(BLOCK) void k_order_tiles(const int* __restrict__ ntiles,
-                                                       const int4* __restrict__ tin,
-                                                       const int2* __restrict__ tbucket,
-                                                       const DevStats* __restrict__ st,
-                                                       int4* __restrict__ tout)
+// Cost of each tile, one wave per tile (grid-stride over the tiles): its
+// queries times the keys of its window (before the block-level truncation),
+// bucketed on a log2 scale; the lanes sum the moved keys of the window's rows.
+__global__ __launch_bounds__(BLOCK) void k_tile_cost(const int* __restrict__ ntiles, Geo g, int offsets,
+                                                     const int* __restrict__ mstart,
+                                                     const int4* __restrict__ tiles,
+                                                     int2* __restrict__ tbucket, DevStats* __restrict__ st)
 {
-    __shared__ int start[128];
-    __shared__ int sh[BLOCK / 64];
-    const int tid = threadIdx.x;
-    // exclusive scan over buckets 127, 126, ..., 0
-    const int c = tid < 128 ? st->bcount[127 - tid] : 0;
-    int tot;
-    const int ex = block_excl_scan(c, sh, &tot);
-    if (tid < 128) start[127 - tid] = ex;
-    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int nw = (int)(gridDim.x * (BLOCK / 64));
     const int n = *ntiles;
-    for (int t = tid; t < n; t += BLOCK) {
-        const int2 b = tbucket[t];
-        tout[start[b.x] + b.y] = tin[t];
+    const int C1 = g.C1, R = g.R, W = st->W;
+    for (int t = (int)((blockIdx.x * (int64_t)BLOCK + threadIdx.x) >> 6); t < n; t += nw) {
+        const int4 tl = tiles[t];
+        const int cx = tl.x / (C1 * C1), cy = (tl.x / C1) % C1, cz = tl.x % C1;
+        const int cx1 = cx + (tl.w & 1), cy1 = cy + ((tl.w >> 1) & 1), cz1 = cz + ((tl.w >> 2) & 1);
+        long long K = 0;
+        if (offsets) {
+            const int mx0 = max(cx - W, 0), mx1 = min(cx1 + W, C1 - 1);
+            const int my0 = max(cy - W, 0), my1 = min(cy1 + W, C1 - 1);
+            const int mz0 = max(cz - W, 0), mz1 = min(cz1 + W, C1 - 1);
+            const int nmy = my1 - my0 + 1, nrow = (mx1 - mx0 + 1) * nmy;
+            for (int r = lane; r < nrow; r += 64) {
+                const int row = ((mx0 + r / nmy) * C1 + (my0 + r % nmy)) * C1;
+                K += mstart[row + mz1 + 1] - mstart[row + mz0];
+            }
+            K = wave_sum(K);
+        }
+        if (lane == 0) {
+            K += (long long)(min(cx1 + W, R - 1) - max(cx - W + 1, 0) + 1) *
+                 (min(cy1 + W, R - 1) - max(cy - W + 1, 0) + 1) *
+                 (min(cz1 + W, R - 1) - max(cz - W + 1, 0) + 1);
+            const float c = (float)(K * (long long)tl.z);
+            const int bk = min(127, max(0, (int)(4.0f * log2f(fmaxf(c, 1.0f)))));
+            // sort key (descending): cost bucket, then ascending slice index
+            tbucket[t] = make_int2(bk * SLICE_KEYS + (SLICE_KEYS - 1 - (tl.w >> 3)), 0);
+        }
     }
 }
 
-// ------------------------------------------------------------------ tiles
-struct TileArgs {
-    Geo g;
-    int offsets;
-    float T2;      // T log2(e)
-    float two_over_J;
-    const float4* gk;
-    const float4* mk;
-    const int* mstart;
-    const float4* ps;
-    const float4* pv;
-    const int* pidx;
-    const int4* tiles;
-    const int* ntiles;  // &tstart[C]
-    int* fb;
-    double2* lpart;
-    DevStats* st;
-    float* O_out;
-    float* lse_out;
-    float* dOdq_out;
-    float* grad;
-    int64_t I;
-};
+// Stable counting sort of the tiles by descending cost bucket, then by
+// ascending slice index (slices of one dense cell share their whole key
+// window, so running them back to back would have concurrent workgroups
+// flush atomics to the same keys), then block-major (spatial) order, so that
+// the persistent tile kernel starts the heaviest tiles first while
+// concurrently running tiles are spatial neighbours with overlapping but
+// different windows.  Sort keys: NKEY = 128 buckets x SLICE_KEYS slices.
+// Pass 1, per chunk of BLOCK tiles: each tile's rank among the chunk's tiles
+// of its key (wave ballots, then the waves before it), the chunk's key
+// histogram in key-major layout chist[(NKEY - 1 - key) nch + chunk], and the
+// per-bucket totals.
+__global__ __launch_bounds__(BLOCK) void k_tile_rank(const int* __restrict__ ntiles,
+                                                     int2* __restrict__ tbucket, int nch,
+                                                     int* __restrict__ chist, DevStats* __restrict__ st)
+{
+    constexpr int NKEY = 128 * SLICE_KEYS;
+    constexpr int KBITS = 10;
+    static_assert((1 << KBITS) == NKEY, "sort key bits");
+    __shared__ int wh[BLOCK / 64][NKEY];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int i = tid; i < (BLOCK / 64) * NKEY; i += BLOCK) (&wh[0][0])[i] = 0;
+    __syncthreads();
+    const int n = *ntiles;
+    const int t = blockIdx.x * BLOCK + tid;
+    const int b = t < n ? tbucket[t].x : -1;
+    unsigned long long same = __ballot(b >= 0);
+#pragma unroll
+    for (int k = 0; k < KBITS; ++k) {
+        const bool bit = b >= 0 && ((b >> k) & 1);
+        const unsigned long long m = __ballot(bit);
+        same &= bit ? m : ~m;
+    }
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const int r = __popcll(same & below);
+    if (b >= 0 && r == 0) wh[wv][b] = __popcll(same);
+    __syncthreads();
+    if (b >= 0) {
+        int before = r;
+        for (int w = 0; w < wv; ++w) before += wh[w][b];
+        tbucket[t].y = before;
+    }
+    for (int key = tid; key < NKEY; key += BLOCK) {
+        int h = 0;
+#pragma unroll
+        for (int w = 0; w < BLOCK / 64; ++w) h += wh[w][key];
+        chist[(NKEY - 1 - key) * nch + blockIdx.x] = h;
+        if (h) atomicAdd(&st->bcount[key / SLICE_KEYS], h);
+    }
+}
 
+// Pass 2 (after the scan of chist into cstart): final position of every tile
+// in the sorted order; tbucket becomes (cost bucket, rank inside the bucket).
+// tout may be null (the batched path orders all shapes' tiles together).
+__global__ __launch_bounds__(BLOCK) void k_tile_place(const int* __restrict__ ntiles,
+                                                      int2* __restrict__ tbucket, int nch,
+                                                      const int* __restrict__ cstart,
+                                                      const int4* __restrict__ tin,
+                                                      int4* __restrict__ tout)
+{
+    constexpr int NKEY = 128 * SLICE_KEYS;
+    const int t = blockIdx.x * BLOCK + threadIdx.x;
+    if (t >= *ntiles) return;
+    const int2 e = tbucket[t];
+    const int bucket = e.x / SLICE_KEYS;
+    const int pos = cstart[(NKEY - 1 - e.x) * nch + blockIdx.x] + e.y;
+    // the bucket's first key row is its largest slice key
+    const int first = cstart[(NKEY - 1 - (bucket * SLICE_KEYS + SLICE_KEYS - 1)) * nch];
+    tbucket[t] = make_int2(bucket, pos - first);
+    if (tout) tout[pos] = tin[t];
+}
+
+// ------------------------------------------------------------------ tiles
 struct TileSmem {
     union {
         struct {
@@ -645,25 +659,33 @@ __device__ __forceinline__ void fwd_qgrad(const TileSmem& S, int n, int ph, int 
 
 // Four workgroups (16 waves) per CU: 128 VGPRs, no spills; measured 7 %
 // faster than the unconstrained 155-VGPR allocation (3 workgroups).
+// Pair counts of the tiles a workgroup has run (flushed to DevStats once).
+struct PairCount {
+    unsigned long long fwd = 0, fwd_moved = 0, bwd = 0, bwd_moved = 0;
+};
+
+__device__ __forceinline__ void flush_pairs(DevStats* st, const PairCount& c)
+{
+    if (threadIdx.x == 0) {
+        if (c.fwd) atomicAdd(&st->pairs, c.fwd);
+        if (c.fwd_moved) atomicAdd(&st->pairs_moved, c.fwd_moved);
+        if (c.bwd) atomicAdd(&st->bwd_pairs, c.bwd);
+        if (c.bwd_moved) atomicAdd(&st->bwd_pairs_moved, c.bwd_moved);
+    }
+}
+
+// One tile: window, forward (Alg. 1), loss, backward (Alg. 2) and flush.
+// td is the tile descriptor, tile its index in a.tiles (loss partial slot);
+// W and bmin2 (smallest beta in log2 units) come from the shape's DevStats.
 template <int MODE, bool QGRAD>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_tile(TileArgs a)
+__device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem& S, const int4 td, const int tile,
+                                         const int W, const float bmin2, PairCount& pc)
 {
     static_assert(KC == BLOCK, "one staged key per thread");
-    __shared__ TileSmem S;
     const int tid = threadIdx.x;
     const Geo& g = a.g;
     const int R = g.R, C1 = g.C1;
-    const int W = a.st->W;
-    const float bmin2 = __uint_as_float(a.st->bmin_bits) * LOG2E;
-    const int ntiles = *a.ntiles;
-
-    for (;;) {
-        __syncthreads();
-        if (tid == 0) S.tile = atomicAdd(&a.st->queue, 1);
-        __syncthreads();
-        const int tile = S.tile;
-        if (tile >= ntiles) break;
-        const int4 td = a.tiles[tile];
+    {
         const int cell = td.x, p0 = td.y, P = td.z;
         // the tile covers cells [c0, c1] per axis (one cell or a 2x2x2 block)
         const int cx = cell / (C1 * C1), cy = (cell / C1) % C1, cz = cell % C1;
@@ -1081,23 +1103,73 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) v
                 }
             }
         }
-        if (tid == 0) {
-            atomicAdd(&a.st->pairs, fwd_pairs);
-            atomicAdd(&a.st->pairs_moved, fwd_moved);
-            atomicAdd(&a.st->bwd_pairs, bwd_pairs);
-            atomicAdd(&a.st->bwd_pairs_moved, bwd_moved);
-        }
+        pc.fwd += fwd_pairs;
+        pc.fwd_moved += fwd_moved;
+        pc.bwd += bwd_pairs;
+        pc.bwd_moved += bwd_moved;
     }
+}
+
+// Persistent tile kernel of one shape: workgroups pull tiles (heaviest
+// first) from an atomic queue until it is empty.
+template <int MODE, bool QGRAD>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_tile(TileArgs a)
+{
+    __shared__ TileSmem S;
+    const int ntiles = *a.ntiles;
+    const int W = a.st->W;
+    const float bmin2 = __uint_as_float(a.st->bmin_bits) * LOG2E;
+    PairCount pc;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) S.tile = atomicAdd(&a.st->queue, 1);
+        __syncthreads();
+        const int tile = S.tile;
+        if (tile >= ntiles) break;
+        tile_run<MODE, QGRAD>(a, S, a.tiles[tile], tile, W, bmin2, pc);
+    }
+    flush_pairs(a.st, pc);
+}
+
+// Persistent tile kernel over a batch of shapes: one queue of (shape, tile)
+// entries in global heavy-first order; each entry runs with its shape's
+// arguments.
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_tile_batch(
+    const TileArgs* __restrict__ tab, const int2* __restrict__ gtiles, const int* __restrict__ ngt,
+    int* __restrict__ gqueue)
+{
+    __shared__ TileSmem S;
+    const int n = *ngt;
+    PairCount pc;
+    int cur = -1;  // shape whose pair counts pc holds
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) S.tile = atomicAdd(gqueue, 1);
+        __syncthreads();
+        const int t = S.tile;
+        if (t >= n) break;
+        const int2 e = gtiles[t];
+        const int sh = __builtin_amdgcn_readfirstlane(e.x);
+        const int lt = __builtin_amdgcn_readfirstlane(e.y);
+        if (sh != cur) {
+            if (cur >= 0) flush_pairs(tab[cur].st, pc);
+            pc = PairCount();
+            cur = sh;
+        }
+        const TileArgs& a = tab[sh];
+        tile_run<MODE_FIT, false>(a, S, a.tiles[lt], lt, a.st->W,
+                                  __uint_as_float(a.st->bmin_bits) * LOG2E, pc);
+    }
+    if (cur >= 0) flush_pairs(tab[cur].st, pc);
 }
 
 // ---------------------------------------------------------------- fallback
 // Queries whose certificate failed: one workgroup per query sweeps every key
 // (the global-support definition).  Keys are taken relative to the query.
 template <int MODE, bool QGRAD>
-__global__ __launch_bounds__(BLOCK) void k_fallback(TileArgs a)
+__device__ __forceinline__ void fallback_run(const TileArgs& a)
 {
     __shared__ float shf[BLOCK / 64];
-    __shared__ double shd[BLOCK / 64];
     __shared__ int s_item;
     const int tid = threadIdx.x;
     const Geo& g = a.g;
@@ -1199,7 +1271,6 @@ __global__ __launch_bounds__(BLOCK) void k_fallback(TileArgs a)
             lse2 = pv.y * LOG2E;
             gj = pq.w;
         }
-        (void)shd;
         if (MODE != MODE_EVAL && gj != 0.0f) {
             for (int64_t ka = tid; ka < nkeys; ka += BLOCK) {
                 float dx, dy, dz, nb;
@@ -1233,6 +1304,20 @@ __global__ __launch_bounds__(BLOCK) void k_fallback(TileArgs a)
                 }
             }
         }
+    }
+}
+
+template <int MODE, bool QGRAD>
+__global__ __launch_bounds__(BLOCK) void k_fallback(TileArgs a)
+{
+    fallback_run<MODE, QGRAD>(a);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_fallback_batch(const TileArgs* __restrict__ tab, int S)
+{
+    for (int s = 0; s < S; ++s) {
+        const TileArgs a = tab[s];
+        fallback_run<MODE_FIT, false>(a);
     }
 }
 
@@ -1279,6 +1364,100 @@ __global__ void k_adam(float* __restrict__ theta, float* __restrict__ m, float* 
         theta[i] = th - lr * wd * th - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
         grad[i] = 0.0f;
     }
+}
+
+// ------------------------------------------------------------------ batch
+// Global heavy-first order over the tiles of all shapes: offset of each
+// (shape, cost bucket) run in descending bucket order, shapes in index order
+// inside a bucket.  Also resets the batch queue.
+__global__ __launch_bounds__(BLOCK) void k_batch_offsets(const BatchShape* __restrict__ bs, int S,
+                                                         int* __restrict__ goff, int* __restrict__ ngt,
+                                                         int* __restrict__ gqueue)
+{
+    __shared__ int sh[BLOCK / 64];
+    const int tid = threadIdx.x;
+    const int b = 127 - tid;
+    int c = 0;
+    if (tid < 128)
+        for (int s = 0; s < S; ++s) c += bs[s].st->bcount[b];
+    int tot;
+    int run = block_excl_scan(c, sh, &tot);
+    if (tid < 128)
+        for (int s = 0; s < S; ++s) {
+            goff[s * 128 + b] = run;
+            run += bs[s].st->bcount[b];
+        }
+    if (tid == 0) {
+        *ngt = tot;
+        *gqueue = 0;
+    }
+}
+
+// gtiles[position] = (shape, index in the shape's block-order tile list)
+__global__ __launch_bounds__(BLOCK) void k_batch_scatter(const BatchShape* __restrict__ bs,
+                                                         const int* __restrict__ goff,
+                                                         int2* __restrict__ gtiles)
+{
+    const int s = blockIdx.y;
+    const int n = *bs[s].ntiles;
+    const int2* __restrict__ tb = bs[s].tbucket;
+    for (int t = blockIdx.x * BLOCK + threadIdx.x; t < n; t += gridDim.x * BLOCK) {
+        const int2 b = tb[t];
+        gtiles[goff[s * 128 + b.x] + b.y] = make_int2(s, t);
+    }
+}
+
+// One workgroup per shape: loss = (tile partials + fallback sums) / J.
+__global__ __launch_bounds__(BLOCK) void k_batch_loss(const BatchShape* __restrict__ bs)
+{
+    __shared__ double sh[BLOCK / 64];
+    const BatchShape b = bs[blockIdx.x];
+    if (!b.loss_out) return;
+    const int n = *b.ntiles;
+    double s2 = 0.0, s1 = 0.0;
+    for (int t = threadIdx.x; t < n; t += BLOCK) {
+        const double2 v = b.lpart[t];
+        s2 += v.x;
+        s1 += v.y;
+    }
+    s2 = block_sum(s2, sh);
+    s1 = block_sum(s1, sh);
+    if (threadIdx.x == 0) {
+        b.loss_out[0] = (s2 + b.st->fb_loss[0]) * b.invJ;
+        b.loss_out[1] = (s1 + b.st->fb_loss[1]) * b.invJ;
+    }
+}
+
+// AdamW over every shape (blockIdx.y) with the bias corrections of the step
+// held in device memory, so that a captured graph replays later steps.
+__global__ void k_batch_adam(const BatchShape* __restrict__ bs, const int64_t* __restrict__ step,
+                             AdamParams ap)
+{
+    const BatchShape b = bs[blockIdx.y];
+    const double t = (double)*step;
+    const float bc1 = (float)(1.0 - pow((double)ap.beta1, t));
+    const float bc2 = (float)(1.0 - pow((double)ap.beta2, t));
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < b.n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = b.grad[i];
+        const float mi = fmaf(ap.beta1, b.m[i], (1.0f - ap.beta1) * gi);
+        const float vi = fmaf(ap.beta2, b.v[i], (1.0f - ap.beta2) * gi * gi);
+        const float th = b.theta[i];
+        b.m[i] = mi;
+        b.v[i] = vi;
+        b.theta[i] = th - ap.lr * ap.wd * th - ap.lr * (mi / bc1) / (sqrtf(vi / bc2) + ap.eps);
+        b.grad[i] = 0.0f;
+    }
+}
+
+__global__ void k_step_set(int64_t* step, int64_t v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *step = v;
+}
+
+__global__ void k_step_advance(int64_t* step)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *step += 1;
 }
 
 // ------------------------------------------------------------- mean-shift
@@ -1356,19 +1535,12 @@ static inline unsigned grid_for(int64_t n, int per = BLOCK)
     return (unsigned)b;
 }
 
-static hipError_t scan(const int* cnt, int64_t n, int* blk, int* start, int* tstart, bool tiles,
-                       hipStream_t s)
+static hipError_t scan(const int* cnt, int64_t n, int* blk, int* start, hipStream_t s)
 {
     const int nb = (int)((n + SCAN_TILE - 1) / SCAN_TILE);
-    if (tiles) {
-        k_scan_reduce<true><<<nb, BLOCK, 0, s>>>(cnt, n, blk);
-        k_scan_blocks<<<1, BLOCK, 0, s>>>(blk, nb);
-        k_scan_apply<true><<<nb, BLOCK, 0, s>>>(cnt, n, blk, nb, start, tstart);
-    } else {
-        k_scan_reduce<false><<<nb, BLOCK, 0, s>>>(cnt, n, blk);
-        k_scan_blocks<<<1, BLOCK, 0, s>>>(blk, nb);
-        k_scan_apply<false><<<nb, BLOCK, 0, s>>>(cnt, n, blk, nb, start, tstart);
-    }
+    k_scan_reduce<<<nb, BLOCK, 0, s>>>(cnt, n, blk);
+    k_scan_blocks<<<1, BLOCK, 0, s>>>(blk, nb);
+    k_scan_apply<<<nb, BLOCK, 0, s>>>(cnt, n, blk, nb, start);
     return hipGetLastError();
 }
 
@@ -1379,18 +1551,18 @@ hipError_t run_zero_floats(float* p, int64_t n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t run_tiles(const Work& w, const Problem& p, Mode mode, hipStream_t s)
+hipError_t run_front(const Work& w, const Problem& p, Mode mode, bool ordered, hipStream_t s)
 {
     const Geo& g = p.g;
     const int64_t I = w.I, C = w.C, J = p.J;
     k_reset_stats<<<1, 64, 0, s>>>(w.st);
-    k_fill_int<<<grid_for(w.NK, BLOCK * 8), BLOCK, 0, s>>>(w.pcount, w.NK, 0);
+    k_fill_int<<<grid_for(w.NK * PSPLIT, BLOCK * 8), BLOCK, 0, s>>>(w.pcount, w.NK * PSPLIT, 0);
     if (p.offsets) k_fill_int<<<grid_for(C, BLOCK * 8), BLOCK, 0, s>>>(w.mcount, C, 0);
     // keys
     k_prep_keys<<<grid_for(I), BLOCK, 0, s>>>(p.theta, g, p.offsets, I, w.gk, w.mrec, w.mcell,
                                               w.mrank, w.mcount, w.st);
     if (p.offsets) {
-        hipError_t e = scan(w.mcount, C, w.scan_blk, w.mstart, nullptr, false, s);
+        hipError_t e = scan(w.mcount, C, w.scan_blk, w.mstart, s);
         if (e != hipSuccess) return e;
         k_scatter_keys<<<grid_for(I), BLOCK, 0, s>>>(I, w.mcell, w.mrank, w.mstart, w.mrec, w.mk);
     }
@@ -1398,34 +1570,48 @@ hipError_t run_tiles(const Work& w, const Problem& p, Mode mode, hipStream_t s)
     // queries
     k_count_points<<<grid_for(J), BLOCK, 0, s>>>(p.q, J, g, w.pcell, w.prank, w.pcount);
     {
-        hipError_t e = scan(w.pcount, w.NK, w.scan_blk, w.pstart, nullptr, false, s);
+        hipError_t e = scan(w.pcount, w.NK * PSPLIT, w.scan_blk, w.pstart, s);
         if (e != hipSuccess) return e;
     }
     // the fit step writes no per-query outputs and needs no original indices
     k_scatter_points<<<grid_for(J), BLOCK, 0, s>>>(p.q, p.aux, p.O_in, p.lse_in, J, w.pcell,
                                                    w.prank, w.pstart, w.ps, w.pv,
                                                    mode == MODE_FIT ? nullptr : w.pidx);
-    k_block_tiles<<<grid_for(w.NB3), BLOCK, 0, s>>>(w.NB3, w.pcount, w.btiles);
+    k_block_tiles<<<grid_for(w.NB3), BLOCK, 0, s>>>(w.NB3, w.pstart, w.cap, w.group, w.btiles);
     {
-        hipError_t e = scan(w.btiles, w.NB3, w.scan_blk, w.tstart, nullptr, false, s);
+        hipError_t e = scan(w.btiles, w.NB3, w.scan_blk, w.tstart, s);
         if (e != hipSuccess) return e;
     }
-    k_build_tiles<<<grid_for(w.NB3), BLOCK, 0, s>>>(w.NB3, g, w.pcount, w.pstart, w.tstart,
-                                                    w.tiles_tmp, w.tbucket, p.offsets, w.mstart, w.st);
-    k_order_tiles<<<1, BLOCK, 0, s>>>(w.tstart + w.NB3, w.tiles_tmp, w.tbucket, w.st, w.tiles);
+    k_build_tiles<<<grid_for(w.NB3), BLOCK, 0, s>>>(w.NB3, g, w.pstart, w.cap, w.group, w.tstart,
+                                                    w.tiles_tmp);
+    int64_t cgrid = (w.max_tiles + BLOCK / 64 - 1) / (BLOCK / 64);
+    if (cgrid > (int64_t)w.num_cu * 16) cgrid = (int64_t)w.num_cu * 16;
+    k_tile_cost<<<(unsigned)cgrid, BLOCK, 0, s>>>(w.tstart + w.NB3, g, p.offsets, w.mstart,
+                                                  w.tiles_tmp, w.tbucket, w.st);
+    k_tile_rank<<<(unsigned)w.nch, BLOCK, 0, s>>>(w.tstart + w.NB3, w.tbucket, (int)w.nch, w.chist, w.st);
+    {
+        hipError_t e = scan(w.chist, 128 * SLICE_KEYS * w.nch, w.scan_blk, w.cstart, s);
+        if (e != hipSuccess) return e;
+    }
+    k_tile_place<<<(unsigned)w.nch, BLOCK, 0, s>>>(w.tstart + w.NB3, w.tbucket, (int)w.nch, w.cstart,
+                                                   w.tiles_tmp, ordered ? w.tiles : nullptr);
+    return hipGetLastError();
+}
 
+TileArgs make_tile_args(const Work& w, const Problem& p, bool ordered)
+{
     TileArgs a;
-    a.g = g;
+    a.g = p.g;
     a.offsets = p.offsets;
     a.T2 = p.T * LOG2E;
-    a.two_over_J = (float)(2.0 / (double)(J > 0 ? J : 1));
+    a.two_over_J = (float)(2.0 / (double)(p.J > 0 ? p.J : 1));
     a.gk = w.gk;
     a.mk = w.mk;
     a.mstart = w.mstart;
     a.ps = w.ps;
     a.pv = w.pv;
     a.pidx = w.pidx;
-    a.tiles = w.tiles;
+    a.tiles = ordered ? w.tiles : w.tiles_tmp;
     a.ntiles = w.tstart + w.NB3;
     a.fb = w.fb;
     a.lpart = w.lpart;
@@ -1434,10 +1620,17 @@ hipError_t run_tiles(const Work& w, const Problem& p, Mode mode, hipStream_t s)
     a.lse_out = p.lse_out;
     a.dOdq_out = p.dOdq_out;
     a.grad = p.grad;
-    a.I = I;
-    const int64_t tiles_hint = w.max_tiles;
-    int64_t grid = (int64_t)w.num_cu * 8;
-    if (grid > tiles_hint) grid = tiles_hint;
+    a.I = w.I;
+    return a;
+}
+
+hipError_t run_tiles(const Work& w, const Problem& p, Mode mode, hipStream_t s)
+{
+    hipError_t e = run_front(w, p, mode, true, s);
+    if (e != hipSuccess) return e;
+    const TileArgs a = make_tile_args(w, p, true);
+    int64_t grid = (int64_t)w.num_cu * w.bpc;
+    if (grid > w.max_tiles) grid = w.max_tiles;
     if (grid < 1) grid = 1;
     const int fgrid = w.num_cu;
     if (p.ev_start) (void)hipEventRecord(p.ev_start, s);
@@ -1464,6 +1657,49 @@ hipError_t run_tiles(const Work& w, const Problem& p, Mode mode, hipStream_t s)
         k_fallback<MODE_GRAD, false><<<fgrid, BLOCK, 0, s>>>(a);
         break;
     }
+    return hipGetLastError();
+}
+
+hipError_t run_batch_order(const BatchShape* bs, int S, int64_t max_tiles, int* goff, int2* gtiles,
+                           int* ngt, int* gqueue, hipStream_t s)
+{
+    k_batch_offsets<<<1, BLOCK, 0, s>>>(bs, S, goff, ngt, gqueue);
+    int64_t gx = (max_tiles + BLOCK - 1) / BLOCK;
+    if (gx > 64) gx = 64;
+    if (gx < 1) gx = 1;
+    k_batch_scatter<<<dim3((unsigned)gx, (unsigned)S), BLOCK, 0, s>>>(bs, goff, gtiles);
+    return hipGetLastError();
+}
+
+hipError_t run_batch_tiles(const TileArgs* tab, int S, const int2* gtiles, const int* ngt,
+                           int* gqueue, int grid, int fgrid, hipEvent_t ev_stop, hipStream_t s)
+{
+    k_tile_batch<<<grid, BLOCK, 0, s>>>(tab, gtiles, ngt, gqueue);
+    if (ev_stop) (void)hipEventRecord(ev_stop, s);
+    k_fallback_batch<<<fgrid, BLOCK, 0, s>>>(tab, S);
+    return hipGetLastError();
+}
+
+hipError_t run_batch_finish(const BatchShape* bs, int S, int64_t nmax, const int64_t* step,
+                            const AdamParams& ap, hipStream_t s)
+{
+    k_batch_loss<<<S, BLOCK, 0, s>>>(bs);
+    int64_t gx = (nmax + BLOCK * 4 - 1) / (BLOCK * 4);
+    if (gx > 1024) gx = 1024;
+    if (gx < 1) gx = 1;
+    k_batch_adam<<<dim3((unsigned)gx, (unsigned)S), BLOCK, 0, s>>>(bs, step, ap);
+    return hipGetLastError();
+}
+
+hipError_t run_step_set(int64_t* step, int64_t v, hipStream_t s)
+{
+    k_step_set<<<1, 64, 0, s>>>(step, v);
+    return hipGetLastError();
+}
+
+hipError_t run_step_advance(int64_t* step, hipStream_t s)
+{
+    k_step_advance<<<1, 64, 0, s>>>(step);
     return hipGetLastError();
 }
 

@@ -44,6 +44,13 @@ class efunc_adam(C.Structure):
                 ("weight_decay", C.c_float)]
 
 
+class efunc_tuning(C.Structure):
+    _fields_ = [("tile_cap", C.c_int32), ("group_cells", C.c_int32), ("blocks_per_cu", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class efunc_stats(C.Structure):
     _fields_ = [("W", C.c_int32), ("n_tiles", C.c_int32), ("n_uncertified", C.c_int64),
                 ("pairs", C.c_int64), ("pairs_moved", C.c_int64), ("bwd_pairs", C.c_int64),
@@ -58,7 +65,11 @@ class efunc_stats(C.Structure):
 # every symbol declared in include/efunc.h
 EXPORTS = ["efunc_default_config", "efunc_default_adam", "efunc_create", "efunc_destroy",
            "efunc_init_params", "efunc_eval", "efunc_grad", "efunc_fit_step", "efunc_get_stats",
-           "efunc_set_timing", "efunc_read_timing", "efunc_last_error"]
+           "efunc_set_timing", "efunc_read_timing", "efunc_default_tuning", "efunc_set_tuning",
+           "efunc_get_tuning", "efunc_batch_create", "efunc_batch_destroy", "efunc_batch_bind",
+           "efunc_batch_fit", "efunc_batch_set_tuning", "efunc_batch_get_tuning",
+           "efunc_batch_autotune", "efunc_batch_get_stats", "efunc_batch_set_timing",
+           "efunc_batch_read_timing", "efunc_last_error"]
 
 _lib = None
 
@@ -85,11 +96,31 @@ def lib() -> C.CDLL:
         L.efunc_get_stats.argtypes = [vp, C.POINTER(efunc_stats)]
         L.efunc_set_timing.argtypes = [vp, C.c_int32]
         L.efunc_read_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.efunc_default_tuning.argtypes = [C.POINTER(efunc_tuning)]
+        L.efunc_default_tuning.restype = None
+        L.efunc_set_tuning.argtypes = [vp, C.POINTER(efunc_tuning)]
+        L.efunc_get_tuning.argtypes = [vp, C.POINTER(efunc_tuning)]
+        pp = C.POINTER(vp)
+        L.efunc_batch_create.argtypes = [C.POINTER(efunc_config), C.POINTER(i64), C.c_int32, pp]
+        L.efunc_batch_destroy.argtypes = [vp]
+        L.efunc_batch_bind.argtypes = [vp, pp, pp, pp, pp, pp, C.POINTER(i64), vp]
+        L.efunc_batch_fit.argtypes = [vp, C.POINTER(efunc_adam), i64, i64, C.c_int32, vp]
+        L.efunc_batch_set_tuning.argtypes = [vp, C.POINTER(efunc_tuning)]
+        L.efunc_batch_get_tuning.argtypes = [vp, C.POINTER(efunc_tuning)]
+        L.efunc_batch_autotune.argtypes = [vp, C.POINTER(efunc_adam), C.c_int32,
+                                           C.POINTER(efunc_tuning), C.POINTER(C.c_double), vp]
+        L.efunc_batch_get_stats.argtypes = [vp, C.c_int32, C.POINTER(efunc_stats)]
+        L.efunc_batch_set_timing.argtypes = [vp, C.c_int32]
+        L.efunc_batch_read_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.efunc_last_error.argtypes = []
         L.efunc_last_error.restype = C.c_char_p
         for name in ("efunc_create", "efunc_destroy", "efunc_init_params", "efunc_eval",
                      "efunc_grad", "efunc_fit_step", "efunc_get_stats", "efunc_set_timing",
-                     "efunc_read_timing"):
+                     "efunc_read_timing", "efunc_set_tuning", "efunc_get_tuning",
+                     "efunc_batch_create", "efunc_batch_destroy", "efunc_batch_bind",
+                     "efunc_batch_fit", "efunc_batch_set_tuning", "efunc_batch_get_tuning",
+                     "efunc_batch_autotune", "efunc_batch_get_stats", "efunc_batch_set_timing",
+                     "efunc_batch_read_timing"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -200,6 +231,149 @@ def efunc_read_timing(ctx):
     return ms.value, n.value
 
 
+def efunc_default_tuning() -> efunc_tuning:
+    t = efunc_tuning()
+    lib().efunc_default_tuning(C.byref(t))
+    return t
+
+
+def efunc_set_tuning(ctx, t: efunc_tuning) -> None:
+    _check(lib().efunc_set_tuning(ctx, C.byref(t)))
+
+
+def efunc_get_tuning(ctx) -> efunc_tuning:
+    t = efunc_tuning()
+    _check(lib().efunc_get_tuning(ctx, C.byref(t)))
+    return t
+
+
+def _ptr_array(ts, dtype, name, numels=None):
+    arr = (C.c_void_p * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = _ptr(t, dtype, f"{name}[{i}]", None if numels is None else numels[i])
+    return arr
+
+
+def efunc_batch_create(cfgs, max_points) -> C.c_void_p:
+    n = len(cfgs)
+    carr = (efunc_config * n)(*cfgs)
+    marr = (C.c_int64 * n)(*[int(x) for x in max_points])
+    out = C.c_void_p()
+    _check(lib().efunc_batch_create(carr, marr, n, C.byref(out)))
+    return out
+
+
+def efunc_batch_destroy(b) -> None:
+    _check(lib().efunc_batch_destroy(b))
+
+
+def efunc_batch_bind(b, thetas, ms, vs, qs, os_, loss_out=None) -> None:
+    n = len(thetas)
+    if not (len(ms) == len(vs) == len(qs) == len(os_) == n):
+        raise ValueError("one tensor per shape in every list")
+    nth = [t.numel() for t in thetas]
+    Js = [q.numel() // 3 for q in qs]
+    Jarr = (C.c_int64 * n)(*Js)
+    _check(lib().efunc_batch_bind(
+        b, _ptr_array(thetas, torch.float32, "theta"), _ptr_array(ms, torch.float32, "m", nth),
+        _ptr_array(vs, torch.float32, "v", nth), _ptr_array(qs, torch.float32, "q", [3 * J for J in Js]),
+        _ptr_array(os_, torch.float32, "o", Js), Jarr,
+        _ptr(loss_out, torch.float64, "loss_out", 2 * n)))
+
+
+def efunc_batch_fit(b, first_step: int, n_steps: int, use_graph: bool = False,
+                    adam: Optional[efunc_adam] = None, stream=None) -> None:
+    _check(lib().efunc_batch_fit(b, C.byref(adam) if adam is not None else None, first_step, n_steps,
+                                 1 if use_graph else 0, _stream(stream)))
+
+
+def efunc_batch_set_tuning(b, t: efunc_tuning) -> None:
+    _check(lib().efunc_batch_set_tuning(b, C.byref(t)))
+
+
+def efunc_batch_get_tuning(b) -> efunc_tuning:
+    t = efunc_tuning()
+    _check(lib().efunc_batch_get_tuning(b, C.byref(t)))
+    return t
+
+
+def efunc_batch_autotune(b, reps: int = 3, adam: Optional[efunc_adam] = None, stream=None):
+    """(chosen tuning as a dict, its median iteration milliseconds)."""
+    t = efunc_tuning()
+    ms = C.c_double()
+    _check(lib().efunc_batch_autotune(b, C.byref(adam) if adam is not None else None, reps,
+                                      C.byref(t), C.byref(ms), _stream(stream)))
+    return t.as_dict(), ms.value
+
+
+def efunc_batch_get_stats(b, shape: int) -> dict:
+    s = efunc_stats()
+    _check(lib().efunc_batch_get_stats(b, shape, C.byref(s)))
+    return s.as_dict()
+
+
+def efunc_batch_set_timing(b, enable: bool) -> None:
+    _check(lib().efunc_batch_set_timing(b, 1 if enable else 0))
+
+
+def efunc_batch_read_timing(b):
+    ms, n = C.c_double(), C.c_int64()
+    _check(lib().efunc_batch_read_timing(b, C.byref(ms), C.byref(n)))
+    return ms.value, n.value
+
+
+class BatchEngine:
+    """Owns one efunc batch: S shapes fitted together (see efunc_batch_*)."""
+
+    def __init__(self, Rs, max_points, **cfg):
+        cfgs = []
+        for R in Rs:
+            c = efunc_default_config(int(R))
+            for k, v in cfg.items():
+                setattr(c, k, v)
+            cfgs.append(c)
+        self.Rs = [int(R) for R in Rs]
+        self.b = efunc_batch_create(cfgs, max_points)
+        self._bound = None
+
+    def close(self):
+        if self.b:
+            efunc_batch_destroy(self.b)
+            self.b = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+    def bind(self, thetas, ms, vs, qs, os_, loss_out=None):
+        efunc_batch_bind(self.b, thetas, ms, vs, qs, os_, loss_out)
+        self._bound = (thetas, ms, vs, qs, os_, loss_out)  # keep the tensors alive
+
+    def fit(self, first_step, n_steps, use_graph=False, adam=None):
+        efunc_batch_fit(self.b, first_step, n_steps, use_graph, adam)
+
+    def set_tuning(self, tile_cap=512, group_cells=1, blocks_per_cu=8):
+        t = efunc_tuning(tile_cap, group_cells, blocks_per_cu)
+        efunc_batch_set_tuning(self.b, t)
+
+    def tuning(self):
+        return efunc_batch_get_tuning(self.b).as_dict()
+
+    def autotune(self, reps=3, adam=None):
+        return efunc_batch_autotune(self.b, reps, adam)
+
+    def stats(self, shape):
+        return efunc_batch_get_stats(self.b, shape)
+
+
 class Engine:
     """Owns one efunc context (convenience wrapper over the functions above)."""
 
@@ -252,3 +426,9 @@ class Engine:
 
     def stats(self):
         return efunc_get_stats(self.ctx)
+
+    def set_tuning(self, tile_cap=512, group_cells=1, blocks_per_cu=8):
+        efunc_set_tuning(self.ctx, efunc_tuning(tile_cap, group_cells, blocks_per_cu))
+
+    def tuning(self):
+        return efunc_get_tuning(self.ctx).as_dict()

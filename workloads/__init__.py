@@ -47,6 +47,24 @@ WORKLOADS = {
                             shape_seed=3, disp_amp=0.01, disp_freq=20.0, seed=200),
 }
 
+
+
+def batch_set(name: str = "batch64", n_shapes: int = 64, seed: int = 300,
+              R_range=(16, 64), J_range=(1 << 18, 1 << 22), prims_range=(4, 64)) -> list:
+    """A seeded set of independent shapes for batched fitting: per shape a
+    smooth CSG union with a random primitive count, a lattice resolution R
+    and a per-iteration point count J both log-uniform in the given ranges."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for s in range(n_shapes):
+        R = int(round(np.exp(rng.uniform(np.log(R_range[0]), np.log(R_range[1])))))
+        J = int(round(np.exp(rng.uniform(np.log(J_range[0]), np.log(J_range[1])))))
+        n_prims = int(rng.integers(prims_range[0], prims_range[1] + 1))
+        out.append(Workload(f"{name}_s{s:02d}", R=R, J=J, shape="csg", n_prims=n_prims,
+                            shape_seed=1000 * seed + s, seed=1000 * seed + s))
+    return out
+
+
 _SHAPES: dict = {}
 _POOLS: dict = {}
 
