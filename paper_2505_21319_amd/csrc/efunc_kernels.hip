@@ -721,13 +721,21 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem& S, const i
             if (tid == 0) S.seg_off[nseg] = Km;
         }
         const int K = Kg + Km;
-        const double ox = g.tlat[cx], oy = g.tlat[cy], oz = g.tlat[cz];
+        // Tile origin.  A float32 subtraction rounds the exact difference of
+        // two float32 coordinates once, so grid keys and queries are taken
+        // relative to it in float32; moved centres (hi + lo) use double.
+        const float oxf = g.tlat[cx], oyf = g.tlat[cy], ozf = g.tlat[cz];
+        const double ox = oxf, oy = oyf, oz = ozf;
+        // floor(n / d) for the window index decode (n < 2^16, d <= 2048):
+        // multiply by m = floor((2^32 - 1) / d) + 1 and keep the high word
+        const int dyz = nvy * nvz;
+        const unsigned myz = dyz > 1 ? 0xFFFFFFFFu / (unsigned)dyz + 1u : 0u;
+        const unsigned mz = nvz > 1 ? 0xFFFFFFFFu / (unsigned)nvz + 1u : 0u;
 
         // ---- queries into LDS, relative to the tile origin
         for (int p = tid; p < P; p += BLOCK) {
             const float4 v = a.ps[p0 + p];
-            S.pq[p] = make_float4((float)((double)v.x - ox), (float)((double)v.y - oy),
-                                  (float)((double)v.z - oz), v.w);
+            S.pq[p] = make_float4(v.x - oxf, v.y - oyf, v.z - ozf, v.w);
             if (MODE == MODE_GRAD) {
                 const float4 u = a.pv[p0 + p];
                 S.pv[p] = make_float4(u.x, u.y * LOG2E, v.w, 0.0f);
@@ -746,12 +754,13 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem& S, const i
             if (tid < nk) {
                 const int kk = k0 + tid;
                 if (kk < Kg) {
-                    const int ix = vx0 + kk / (nvy * nvz), rr = kk % (nvy * nvz);
-                    const int iy = vy0 + rr / nvz, iz = vz0 + rr % nvz;
+                    const int qx = dyz > 1 ? (int)__umulhi((unsigned)kk, myz) : kk;
+                    const int rr = kk - qx * dyz;
+                    const int qy = nvz > 1 ? (int)__umulhi((unsigned)rr, mz) : rr;
+                    const int ix = vx0 + qx, iy = vy0 + qy, iz = vz0 + (rr - qy * nvz);
                     const int vid = (ix * R + iy) * R + iz;
                     const float4 a0 = a.gk[2 * (int64_t)vid], a1 = a.gk[2 * (int64_t)vid + 1];
-                    kc = make_float4((float)((double)g.tlat[ix] - ox), (float)((double)g.tlat[iy] - oy),
-                                     (float)((double)g.tlat[iz] - oz), a0.x);
+                    kc = make_float4(g.tlat[ix] - oxf, g.tlat[iy] - oyf, g.tlat[iz] - ozf, a0.x);
                     kv = make_float4(a0.y, a0.z, a0.w, a1.x);
                     tag = vid;
                 } else {
@@ -825,9 +834,9 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem& S, const i
                     const int ix = hx + (c8 >> 2), iy = hy + ((c8 >> 1) & 1), iz = hz + (c8 & 1);
                     const int vid = (ix * R + iy) * R + iz;
                     const float nb = a.gk[2 * (int64_t)vid].x;
-                    const float dx = pq.x - (float)((double)g.tlat[ix] - ox);
-                    const float dy = pq.y - (float)((double)g.tlat[iy] - oy);
-                    const float dz = pq.z - (float)((double)g.tlat[iz] - oz);
+                    const float dx = pq.x - (g.tlat[ix] - oxf);
+                    const float dy = pq.y - (g.tlat[iy] - oyf);
+                    const float dz = pq.z - (g.tlat[iz] - ozf);
                     M0 = fmaxf(M0, nb * fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
                 }
                 S.pv[p] = make_float4(0.0f, 0.0f, 0.0f, M0);
@@ -904,12 +913,12 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem& S, const i
 
             // ---- per query: O, lse, certificate, loss and dL/dO
             // faces of the window box beyond which keys are excluded
-            const float flx = (cx - W + 1 > 0) ? (float)((double)g.tlat[cx - W] - ox) : -INFINITY;
-            const float fly = (cy - W + 1 > 0) ? (float)((double)g.tlat[cy - W] - oy) : -INFINITY;
-            const float flz = (cz - W + 1 > 0) ? (float)((double)g.tlat[cz - W] - oz) : -INFINITY;
-            const float fhx = (cx1 + W < R - 1) ? (float)((double)g.tlat[cx1 + W + 1] - ox) : INFINITY;
-            const float fhy = (cy1 + W < R - 1) ? (float)((double)g.tlat[cy1 + W + 1] - oy) : INFINITY;
-            const float fhz = (cz1 + W < R - 1) ? (float)((double)g.tlat[cz1 + W + 1] - oz) : INFINITY;
+            const float flx = (cx - W + 1 > 0) ? g.tlat[cx - W] - oxf : -INFINITY;
+            const float fly = (cy - W + 1 > 0) ? g.tlat[cy - W] - oyf : -INFINITY;
+            const float flz = (cz - W + 1 > 0) ? g.tlat[cz - W] - ozf : -INFINITY;
+            const float fhx = (cx1 + W < R - 1) ? g.tlat[cx1 + W + 1] - oxf : INFINITY;
+            const float fhy = (cy1 + W < R - 1) ? g.tlat[cy1 + W + 1] - oyf : INFINITY;
+            const float fhz = (cz1 + W < R - 1) ? g.tlat[cz1 + W + 1] - ozf : INFINITY;
             double lsq = 0.0, lab = 0.0;
             for (int p = tid; p < P; p += BLOCK) {
                 float ee = 0.0f, mm = 0.0f;
@@ -994,12 +1003,12 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem& S, const i
         } else {
             // ---- backward only: certificate from the given lse
             __syncthreads();
-            const float flx = (cx - W + 1 > 0) ? (float)((double)g.tlat[cx - W] - ox) : -INFINITY;
-            const float fly = (cy - W + 1 > 0) ? (float)((double)g.tlat[cy - W] - oy) : -INFINITY;
-            const float flz = (cz - W + 1 > 0) ? (float)((double)g.tlat[cz - W] - oz) : -INFINITY;
-            const float fhx = (cx1 + W < R - 1) ? (float)((double)g.tlat[cx1 + W + 1] - ox) : INFINITY;
-            const float fhy = (cy1 + W < R - 1) ? (float)((double)g.tlat[cy1 + W + 1] - oy) : INFINITY;
-            const float fhz = (cz1 + W < R - 1) ? (float)((double)g.tlat[cz1 + W + 1] - oz) : INFINITY;
+            const float flx = (cx - W + 1 > 0) ? g.tlat[cx - W] - oxf : -INFINITY;
+            const float fly = (cy - W + 1 > 0) ? g.tlat[cy - W] - oyf : -INFINITY;
+            const float flz = (cz - W + 1 > 0) ? g.tlat[cz - W] - ozf : -INFINITY;
+            const float fhx = (cx1 + W < R - 1) ? g.tlat[cx1 + W + 1] - oxf : INFINITY;
+            const float fhy = (cy1 + W < R - 1) ? g.tlat[cy1 + W + 1] - oyf : INFINITY;
+            const float fhz = (cz1 + W < R - 1) ? g.tlat[cz1 + W + 1] - ozf : INFINITY;
             for (int p = tid; p < P; p += BLOCK) {
                 const float4 pq = S.pq[p];
                 float4 pv = S.pv[p];

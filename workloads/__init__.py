@@ -126,8 +126,9 @@ def surface_points(w: Workload, n: int, seed: int, device="cpu") -> np.ndarray:
     areas = np.array([p.area() for p in shape.prims])
     out = []
     have = 0
+    acc = 0.5  # running estimate of the fraction of samples that survive
     while have < n:
-        m = int(1.5 * (n - have)) + 64
+        m = int(1.25 * (n - have) / acc) + 64
         counts = rng.multinomial(m, areas / areas.sum())
         pts = np.concatenate([p.sample_surface(c, rng) for p, c in zip(shape.prims, counts)
                               if c > 0])
@@ -141,7 +142,9 @@ def surface_points(w: Workload, n: int, seed: int, device="cpu") -> np.ndarray:
             buried |= (d < -1e-6) & ~mine
         pts = pts[~buried.cpu().numpy()]
         pts = _project(shape, pts, device)
-        out.append(pts)
+        acc = min(1.0, max(0.02, len(pts) / m))
+        # samples come grouped by primitive: shuffle before the final cut to n
+        out.append(pts[rng.permutation(len(pts))])
         have += len(pts)
     pts = np.concatenate(out)[:n]
     return pts[rng.permutation(n)]
