@@ -4,6 +4,8 @@ Only the test suite, ``__graft_entry__.smoke()`` and the benchmark's
 ``cpu_baseline`` leg may import this package.  The HIP library never calls it
 and shares no code with it.  The C sources (``efunc_oracle.c``) hold the
 arithmetic; this module only marshals numpy arrays through ctypes.
+``oracle.variants`` (``efunc_oracle_var.c``) covers the model variants:
+polynomial degree 0/1/2, key sets and fixed or learnable scales.
 """
 from .oracle import (  # noqa: F401
     Grid,
