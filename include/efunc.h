@@ -9,11 +9,18 @@
  *     O(q) = sum_a softmax_a(-beta_a ||q - c_a||^2) (o_a + (q - c_a) . d_a)
  * over the fixed grid keys c_i = k_i and the moved keys c_i = k_i + Delta_i.
  *
- * Parameters theta: float32, C order [R][R][R][13] (vertex index
+ * Parameters theta: float32, C order [R][R][R][NCH] (vertex index
  * i = (ix * R + iy) * R + iz, vertex position k_i = (t[ix], t[iy], t[iz]),
- * t[n] = float32(lo + (hi - lo) n / (R - 1))).  Channels per vertex:
+ * t[n] = float32(lo + (hi - lo) n / (R - 1))).  Channels per vertex for the
+ * default model (NCH = 13):
  *     0 o, 1..3 d, 4 rho = ln beta            (grid key)
  *     5..7 Delta, 8 o', 9..11 d', 12 rho'     (moved key)
+ * In general (efunc_config degree / grid_keys / offsets / learn_scale): the
+ * grid part [values (nv), rho] then the moved part [Delta (3), values (nv),
+ * rho'], with nv = 1, 4, 10 value coefficients for f^0, f^1, f^2 in the order
+ * o, d.x, d.y, d.z, S_xx, S_yy, S_zz, S_xy, S_xz, S_yz, where
+ * f^2(x) = o + x.d + 1/2 (S_xx x^2 + S_yy y^2 + S_zz z^2) + S_xy xy + S_xz xz
+ * + S_yz yz; absent groups take no channels (efunc_channels).
  * Grid-key centres are fixed; every channel is trainable.
  *
  * Support.  The paper's sums run over every key (global support).  The
@@ -60,7 +67,8 @@ typedef struct efunc_ctx efunc_ctx;
 typedef struct {
     int32_t R;             /* vertices per axis, 2 <= R <= 1024 */
     float lo, hi;          /* lattice spans [lo, hi]^3, lo < hi (default -1, 1) */
-    int32_t offsets;       /* 1: grid + moved keys (Eq. func-offset, default); 0: grid keys only */
+    int32_t offsets;       /* 1: moved keys k_i + Delta_i present (Eq. func-offset, default);
+                              0: no moved keys, theta holds no Delta / moved channels */
     float t_cut;           /* truncation threshold T in nats (default 20) */
     int32_t window;        /* 0: choose the window half-width W per call from the current
                               scales; > 0: force W (queries that fail the certificate then
@@ -68,6 +76,14 @@ typedef struct {
     int32_t deterministic; /* reserved, must be 0 */
     int32_t check_finite;  /* 1: reject non-finite parameters/points with EFUNC_ENONFINITE
                               (synchronises the stream) */
+    /* Model variant (Sec. 3.2-3.3; Tab. ablation).  Defaults give the paper's
+     * default model O^{+Delta} with f^1 and learnable scales (13 channels). */
+    int32_t degree;        /* value polynomial f^0, f^1 or f^2 (Eq. poly-func): 0, 1, 2 */
+    int32_t grid_keys;     /* 1: fixed grid keys k_i present (default); 0: only the moved keys
+                              (O^Delta, Eq. func-with-offset; requires offsets = 1) */
+    int32_t learn_scale;   /* 1: one rho = ln beta channel per key (default); 0: every key has
+                              beta = exp(rho_fixed) and there is no scale channel */
+    float rho_fixed;       /* log-scale of every key when learn_scale = 0 (default 7) */
 } efunc_config;
 
 typedef struct {
@@ -100,8 +116,12 @@ typedef struct {
 } efunc_stats;
 
 /* Fill *cfg with defaults for resolution R: [-1,1]^3, offsets on, T = 20,
- * automatic window, checks off. */
+ * automatic window, checks off, degree 1, grid keys on, learnable scales. */
 void efunc_default_config(efunc_config* cfg, int32_t R);
+
+/* Channels per vertex of the model *cfg describes (13 for the default), or
+ * EFUNC_EINVAL for an invalid variant. */
+int efunc_channels(const efunc_config* cfg);
 
 /* Default AdamW hyper-parameters: lr 6e-4 (Sec. 4.2), betas (0.9, 0.999),
  * eps 1e-8, weight decay 0. */
@@ -116,8 +136,8 @@ int efunc_create(const efunc_config* cfg, int64_t max_points, efunc_ctx** out);
 /* Free the context and its workspace (synchronises the device). NULL is a no-op. */
 int efunc_destroy(efunc_ctx* ctx);
 
-/* Initialise theta [R^3 x 13] (Sec. 3.3 "Initializing Offsets", Sec. 4.3
- * "Scales/radius"): o = d = o' = d' = 0, rho = rho' = rho0 (the paper uses
+/* Initialise theta [R^3 x NCH] (Sec. 3.3 "Initializing Offsets", Sec. 4.3
+ * "Scales/radius"): all value coefficients 0, rho = rho' = rho0 (the paper uses
  * beta = exp(7)), and Delta_i by one mean-shift step towards the Ns surface
  * samples surf [Ns][3] (device):
  *   Delta_i = sum_n exp(-bw ||k_i - s_n||^2) s_n / sum_n exp(-bw ||k_i - s_n||^2) - k_i
@@ -138,7 +158,7 @@ int efunc_eval(efunc_ctx* ctx, const float* theta, const float* q, int64_t J, fl
 
 /* Backward (Alg. 2 and the closed forms of Sec. 3.6): given queries q
  * [J][3], their outputs O [J] and log-denominators lse [J] (from efunc_eval)
- * and dL/dO [J], ACCUMULATE dL/dtheta into grad [R^3 x 13] (grad += ...; the
+ * and dL/dO [J], ACCUMULATE dL/dtheta into grad [R^3 x NCH] (grad += ...; the
  * caller zeroes it).  Channels receive dL/do, dL/dd, dL/drho = beta dL/dbeta
  * for both key sets and dL/dDelta = dL/dc for moved keys.
  * Errors: EFUNC_EINVAL, EFUNC_ESIZE, EFUNC_ENONFINITE, EFUNC_EHIP. */
@@ -148,7 +168,7 @@ int efunc_grad(efunc_ctx* ctx, const float* theta, const float* q, const float* 
 /* One fitting iteration on the minibatch (q [J][3], targets o [J]) (Sec. 3.4,
  * Eq. loss; optimiser of Sec. 4.2): forward, MSE loss, dL/dO_j =
  * 2 (O_j - o_j) / J, backward, and one AdamW step with bias correction at
- * step number `step` (>= 1) on theta, m, v [R^3 x 13] (m, v: float32
+ * step number `step` (>= 1) on theta, m, v [R^3 x NCH] (m, v: float32
  * moments, zero before step 1).  loss_out (DEVICE, double[2], optional)
  * receives {mean (O - o)^2, mean |O - o|} of the parameters before the
  * update.  adam: host pointer (NULL = defaults).
@@ -192,8 +212,9 @@ int efunc_get_tuning(efunc_ctx* ctx, efunc_tuning* t);
 typedef struct efunc_batch efunc_batch;
 
 /* Create a batch of n_shapes (>= 1) shapes: cfgs[s] and max_points[s] (host
- * arrays) as for efunc_create (check_finite must be 0).  Allocates all
- * device workspace.  Errors: EFUNC_EINVAL, EFUNC_EUNSUPPORTED, EFUNC_EHIP. */
+ * arrays) as for efunc_create (check_finite must be 0; every shape has the
+ * same polynomial degree).  Allocates all device workspace.
+ * Errors: EFUNC_EINVAL, EFUNC_EUNSUPPORTED, EFUNC_EHIP. */
 int efunc_batch_create(const efunc_config* cfgs, const int64_t* max_points, int32_t n_shapes,
                        efunc_batch** out);
 
@@ -202,7 +223,7 @@ int efunc_batch_create(const efunc_config* cfgs, const int64_t* max_points, int3
 int efunc_batch_destroy(efunc_batch* b);
 
 /* Bind the data of every shape s (host arrays of n_shapes DEVICE pointers):
- * theta[s], m[s], v[s] [R_s^3 x 13] float32 (updated in place), q[s]
+ * theta[s], m[s], v[s] [R_s^3 x NCH_s] float32 (updated in place), q[s]
  * [J[s]][3], o[s] [J[s]] float32; J[s] (host) with 1 <= J[s] <= max_points[s].
  * loss_out (DEVICE double [n_shapes][2], optional) receives each shape's
  * {mean (O - o)^2, mean |O - o|} before the update of each step.  The

@@ -142,8 +142,8 @@ hipError_t enqueue_iteration(efunc_batch* b, const AdamParams& ap, hipStream_t s
     e = run_batch_order(b->d_bs, b->S, b->max_tiles_max, b->goff, b->gtiles, b->ngt, b->gqueue, s);
     if (e != hipSuccess) return e;
     if (t0) (void)hipEventRecord(t0, s);
-    e = run_batch_tiles(b->d_tab, b->S, b->gtiles, b->ngt, b->gqueue, b->num_cu * b->tune.blocks_per_cu,
-                        b->num_cu, t1, s);
+    e = run_batch_tiles(b->ctx[0]->layout.degree, b->d_tab, b->S, b->gtiles, b->ngt, b->gqueue,
+                        b->num_cu * b->tune.blocks_per_cu, b->num_cu, t1, s);
     if (e != hipSuccess) return e;
     e = run_batch_finish(b->d_bs, b->S, b->nmax, b->step, ap, s);
     if (e != hipSuccess) return e;
@@ -173,8 +173,11 @@ int efunc_batch_create(const efunc_config* cfgs, const int64_t* max_points, int3
     *out = nullptr;
     if (!cfgs || !max_points) return fail(EFUNC_EINVAL, "cfgs or max_points is NULL");
     if (n_shapes < 1 || n_shapes > 65535) return fail(EFUNC_EINVAL, "n_shapes = %d outside [1, 65535]", n_shapes);
-    for (int s = 0; s < n_shapes; ++s)
+    for (int s = 0; s < n_shapes; ++s) {
         if (cfgs[s].check_finite) return fail(EFUNC_EUNSUPPORTED, "shape %d: check_finite is not available in a batch", s);
+        if (cfgs[s].degree != cfgs[0].degree)
+            return fail(EFUNC_EUNSUPPORTED, "shape %d: every shape of a batch needs the same degree", s);
+    }
     efunc_batch* b = new (std::nothrow) efunc_batch();
     if (!b) return fail(EFUNC_EINVAL, "out of host memory");
     b->S = n_shapes;
@@ -191,7 +194,7 @@ int efunc_batch_create(const efunc_config* cfgs, const int64_t* max_points, int3
         b->ctx.push_back(c);
         b->max_tiles_max = std::max(b->max_tiles_max, c->w.max_tiles);
         b->tiles_total += c->w.max_tiles;
-        b->nmax = std::max(b->nmax, (int64_t)NCH * c->w.I);
+        b->nmax = std::max(b->nmax, (int64_t)c->layout.nch * c->w.I);
         b->num_cu = c->w.num_cu;
     }
     hipError_t e = balloc(b, &b->d_tab, n_shapes);
@@ -258,6 +261,7 @@ int efunc_batch_bind(efunc_batch* b, float* const* theta, float* const* m, float
         Problem& p = b->prob[s];
         memset(&p, 0, sizeof(p));
         p.g = c->geo;
+        p.L = c->layout;
         p.offsets = c->cfg.offsets;
         p.T = c->cfg.t_cut;
         p.window = c->cfg.window;
@@ -278,7 +282,7 @@ int efunc_batch_bind(efunc_batch* b, float* const* theta, float* const* m, float
         d.m = m[s];
         d.v = v[s];
         d.grad = c->w.grad;
-        d.n = (int64_t)NCH * c->w.I;
+        d.n = (int64_t)c->layout.nch * c->w.I;
     }
     e = hipMemcpy(b->d_tab, b->tab.data(), sizeof(TileArgs) * b->S, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b->d_bs, b->bs.data(), sizeof(BatchShape) * b->S, hipMemcpyHostToDevice);

@@ -48,6 +48,39 @@ int check_tuning(const efunc_tuning* t)
     return EFUNC_OK;
 }
 
+int make_layout(const efunc_config* cfg, Layout* out)
+{
+    if (cfg->degree < 0 || cfg->degree > 2) return fail(EFUNC_EINVAL, "degree = %d outside [0, 2]", cfg->degree);
+    if (cfg->grid_keys != 0 && cfg->grid_keys != 1) return fail(EFUNC_EINVAL, "grid_keys must be 0 or 1");
+    if (cfg->learn_scale != 0 && cfg->learn_scale != 1) return fail(EFUNC_EINVAL, "learn_scale must be 0 or 1");
+    if (!cfg->grid_keys && !cfg->offsets) return fail(EFUNC_EINVAL, "the model needs grid keys or moved keys");
+    if (!cfg->learn_scale && !isfinite(cfg->rho_fixed)) return fail(EFUNC_EINVAL, "rho_fixed must be finite");
+    Layout L;
+    L.degree = cfg->degree;
+    L.nv = cfg->degree == 0 ? 1 : (cfg->degree == 1 ? 4 : 10);
+    L.grid = cfg->grid_keys;
+    L.moved = cfg->offsets;
+    L.learn = cfg->learn_scale;
+    L.rho_fixed = cfg->rho_fixed;
+    L.gval = L.grho = L.mdel = L.mval = L.mrho = -1;
+    int c = 0;
+    if (L.grid) {
+        L.gval = c;
+        c += L.nv;
+        if (L.learn) L.grho = c++;
+    }
+    if (L.moved) {
+        L.mdel = c;
+        c += 3;
+        L.mval = c;
+        c += L.nv;
+        if (L.learn) L.mrho = c++;
+    }
+    L.nch = c;
+    *out = L;
+    return EFUNC_OK;
+}
+
 }  // namespace efunc
 
 namespace {
@@ -115,6 +148,7 @@ Problem base_problem(efunc_ctx* ctx)
     Problem p;
     memset(&p, 0, sizeof(p));
     p.g = ctx->geo;
+    p.L = ctx->layout;
     p.offsets = ctx->cfg.offsets;
     p.T = ctx->cfg.t_cut;
     p.window = ctx->cfg.window;
@@ -169,6 +203,19 @@ void efunc_default_config(efunc_config* cfg, int32_t R)
     cfg->window = 0;
     cfg->deterministic = 0;
     cfg->check_finite = 0;
+    cfg->degree = 1;
+    cfg->grid_keys = 1;
+    cfg->learn_scale = 1;
+    cfg->rho_fixed = 7.0f;
+}
+
+int efunc_channels(const efunc_config* cfg)
+{
+    g_err.clear();
+    if (!cfg) return fail(EFUNC_EINVAL, "cfg is NULL");
+    Layout L;
+    const int rc = make_layout(cfg, &L);
+    return rc ? rc : L.nch;
 }
 
 void efunc_default_adam(efunc_adam* a)
@@ -205,12 +252,15 @@ int efunc_create(const efunc_config* cfg, int64_t max_points, efunc_ctx** out)
     if (cfg->window < 0 || cfg->window > WMAX)
         return fail(EFUNC_EINVAL, "window = %d outside [0, %d]", cfg->window, WMAX);
     if (cfg->deterministic != 0) return fail(EFUNC_EUNSUPPORTED, "deterministic mode is not built");
+    Layout layout;
+    if (int rc = make_layout(cfg, &layout)) return rc;
     if (max_points < 0 || max_points > (int64_t)INT32_MAX - PMAX)
         return fail(EFUNC_EINVAL, "max_points = %lld outside [0, 2^31 - %d)", (long long)max_points, PMAX);
 
     efunc_ctx* c = new (std::nothrow) efunc_ctx();
     if (!c) return fail(EFUNC_EINVAL, "out of host memory");
     c->cfg = *cfg;
+    c->layout = layout;
     c->last_stream = nullptr;
     hipError_t e = hipGetDevice(&c->device);
     if (e != hipSuccess) {
@@ -246,13 +296,14 @@ int efunc_create(const efunc_config* cfg, int64_t max_points, efunc_ctx** out)
 #define ALLOC(ptr, n) \
     if (err == hipSuccess) err = dalloc(c, &(ptr), (size_t)(n))
     ALLOC(w.tlat, R);
-    ALLOC(w.gk, 2 * I);
+    const int gw = gk_width(layout.degree), mw = mk_width(layout.degree);
+    ALLOC(w.gk, layout.grid ? gw * I : 1);
     ALLOC(w.mcell, I);
     ALLOC(w.mrank, I);
     ALLOC(w.mcount, C);
     ALLOC(w.mstart, C + 1);
-    ALLOC(w.mrec, 3 * I);
-    ALLOC(w.mk, 3 * I);
+    ALLOC(w.mrec, layout.moved ? mw * I : 1);
+    ALLOC(w.mk, layout.moved ? mw * I : 1);
     ALLOC(w.pcell, mp);
     ALLOC(w.prank, mp);
     ALLOC(w.pcount, w.NK * PSPLIT);
@@ -270,7 +321,7 @@ int efunc_create(const efunc_config* cfg, int64_t max_points, efunc_ctx** out)
     ALLOC(w.fb, mp);
     ALLOC(w.lpart, w.max_tiles);
     ALLOC(w.scan_blk, nblk + 1);
-    ALLOC(w.grad, NCH * I);
+    ALLOC(w.grad, (int64_t)layout.nch * I);
     ALLOC(w.st, 1);
 #undef ALLOC
     if (err != hipSuccess) {
@@ -280,7 +331,7 @@ int efunc_create(const efunc_config* cfg, int64_t max_points, efunc_ctx** out)
     }
     const std::vector<float> t = lattice(*cfg);
     err = hipMemcpy(w.tlat, t.data(), sizeof(float) * R, hipMemcpyHostToDevice);
-    if (err == hipSuccess) err = hipMemset(w.grad, 0, sizeof(float) * NCH * I);
+    if (err == hipSuccess) err = hipMemset(w.grad, 0, sizeof(float) * layout.nch * I);
     if (err == hipSuccess) err = hipMemset(w.st, 0, sizeof(DevStats));
     if (err == hipSuccess) err = hipDeviceSynchronize();
     if (err != hipSuccess) {
@@ -329,7 +380,7 @@ int efunc_init_params(efunc_ctx* ctx, float* theta, const float* surf, int64_t N
     if (!isfinite(rho0)) return fail(EFUNC_EINVAL, "rho0 must be finite");
     hipStream_t s = (hipStream_t)stream;
     ctx->last_stream = s;
-    hipError_t e = run_init_params(ctx->w, ctx->geo, theta, surf, Ns, bandwidth, rho0, s);
+    hipError_t e = run_init_params(ctx->w, ctx->geo, ctx->layout, theta, surf, Ns, bandwidth, rho0, s);
     if (e != hipSuccess) return hip_fail(e, "init_params launch");
     return EFUNC_OK;
 }
@@ -423,12 +474,12 @@ int efunc_fit_step(efunc_ctx* ctx, float* theta, float* m, float* v, int64_t ste
     if (e != hipSuccess) return hip_fail(e, "fit_step launch");
     if ((rc = finite_check(ctx, s, q, J))) {
         // leave the internal gradient clean for the next call
-        (void)run_zero_floats(ctx->w.grad, (int64_t)NCH * ctx->w.I, s);
+        (void)run_zero_floats(ctx->w.grad, (int64_t)ctx->layout.nch * ctx->w.I, s);
         return rc;
     }
     const double bc1 = 1.0 - pow((double)hp.beta1, (double)step);
     const double bc2 = 1.0 - pow((double)hp.beta2, (double)step);
-    e = run_adam(ctx->w, theta, m, v, (int64_t)NCH * ctx->w.I, hp.lr, hp.beta1, hp.beta2, hp.eps,
+    e = run_adam(ctx->w, theta, m, v, (int64_t)ctx->layout.nch * ctx->w.I, hp.lr, hp.beta1, hp.beta2, hp.eps,
                  hp.weight_decay, (float)bc1, (float)bc2, s);
     if (e != hipSuccess) return hip_fail(e, "adam launch");
     return EFUNC_OK;

@@ -10,6 +10,7 @@
 
 struct efunc_ctx {
     efunc_config cfg;
+    efunc::Layout layout;
     efunc::Geo geo;
     efunc::Work w;
     hipStream_t last_stream;
@@ -31,5 +32,7 @@ int hip_fail(hipError_t e, const char* what);
 void clear_error();
 // Check a tuning record against the limits of the workspace.
 int check_tuning(const efunc_tuning* t);
+// Channel layout of a model variant; returns EFUNC_OK or EFUNC_EINVAL (message set).
+int make_layout(const efunc_config* cfg, Layout* out);
 
 }  // namespace efunc

@@ -7,7 +7,6 @@
 
 namespace efunc {
 
-constexpr int NCH = 13;
 constexpr int BLOCK = 256;      // threads per workgroup (4 wave64)
 constexpr int PMAX = 512;       // queries per tile (two per thread at most)
 constexpr int PMIN_CAP = 128;   // smallest tile query cap the workspace is sized for
@@ -46,6 +45,27 @@ struct DevStats {
 };
 static_assert(sizeof(DevStats) == 4 * 128 + 512, "DevStats layout");
 
+// Model variant and the per-vertex channel layout of theta (Sec. 3.2
+// Eq. poly-func degree; Eq. func-interp / func-with-offset / func-offset key
+// sets; learnable or fixed scales).  Channel offsets are -1 when absent:
+//   grid part:  values (nv), rho        moved part: Delta (3), values (nv), rho'
+struct Layout {
+    int degree;      // 0, 1, 2
+    int nv;          // value coefficients per key: 1, 4, 10
+    int grid;        // grid keys present
+    int moved;       // moved keys present
+    int learn;       // rho channels present (else beta = exp(rho_fixed))
+    float rho_fixed;
+    int nch;         // channels per vertex
+    int gval, grho, mdel, mval, mrho;
+};
+
+// Float4 records per key in HBM: grid {nb, o, d.x, d.y}, {d.z, beta, 0, 0};
+// moved {c_hi, nb}, {o, d}, {c_lo, vertex}; degree 2 appends
+// {S_xx/2, S_yy/2, S_zz/2, S_xy}, {S_xz, S_yz, 0, 0} to both.
+__host__ __device__ constexpr int gk_width(int deg) { return deg == 2 ? 4 : 2; }
+__host__ __device__ constexpr int mk_width(int deg) { return deg == 2 ? 5 : 3; }
+
 // Lattice geometry passed by value to every kernel.
 struct Geo {
     int R;         // vertices per axis
@@ -62,14 +82,13 @@ struct Work {
     int64_t I, C, max_points, max_tiles;
     int64_t NB3, NK;      // cell blocks; query sort keys = 8 NB3 (block-major cell order)
     float* tlat;          // [R]
-    float4* gk;           // [2 I]  grid key records {nb, o, d.x, d.y}, {d.z, beta, 0, 0}
+    float4* gk;           // [gk_width I]  grid key records
     int* mcell;           // [I]    cell of each moved key
     int* mrank;           // [I]    rank inside its cell
     int* mcount;          // [C]
     int* mstart;          // [C+1]
-    float4* mrec;         // [3 I]  moved key records by vertex
-    float4* mk;           // [3 I]  moved key records binned by cell:
-                          //        {c_hi.xyz, nb}, {o', d'.xyz}, {c_lo.xyz, vid bits}
+    float4* mrec;         // [mk_width I]  moved key records by vertex
+    float4* mk;           // [mk_width I]  moved key records binned by cell
     int* pcell;           // [max_points] sort key of each query
     int* prank;           // [max_points]
     int* pcount;          // [NK*PSPLIT] queries per (cell, sub-counter), block-major order
@@ -88,7 +107,7 @@ struct Work {
     int* fb;              // [max_points] fallback list (sorted query positions)
     double2* lpart;       // [max_tiles]  per-tile loss sums
     int* scan_blk;        // [ceil(max(8 NB3 PSPLIT, 128 SLICE_KEYS nch) / SCAN_TILE) + 1] scan block sums
-    float* grad;          // [13 I] internal gradient of efunc_fit_step (kept zero)
+    float* grad;          // [nch I] internal gradient of efunc_fit_step (kept zero)
     DevStats* st;
     int num_cu;
     // launch tuning (runtime): tile query cap, whether sparse 2x2x2 cell
@@ -102,6 +121,7 @@ enum Mode { MODE_FIT = 0, MODE_EVAL = 1, MODE_GRAD = 2 };
 
 struct Problem {
     Geo g;
+    Layout L;
     int offsets;
     float T;            // truncation threshold (nats)
     int window;         // forced W (0 = auto)
@@ -124,6 +144,7 @@ struct Problem {
 // Arguments of the tile and fallback kernels for one shape.
 struct TileArgs {
     Geo g;
+    Layout L;
     int offsets;
     float T2;      // T log2(e)
     float two_over_J;
@@ -157,7 +178,7 @@ struct BatchShape {
     float* m;
     float* v;
     float* grad;
-    int64_t n;             // 13 R^3
+    int64_t n;             // nch R^3
 };
 
 struct AdamParams {
@@ -177,7 +198,7 @@ TileArgs make_tile_args(const Work& w, const Problem& p, bool ordered);
 // per-shape loss reduction, AdamW with the step read from device memory.
 hipError_t run_batch_order(const BatchShape* bs, int S, int64_t max_tiles, int* goff, int2* gtiles,
                            int* ngt, int* gqueue, hipStream_t s);
-hipError_t run_batch_tiles(const TileArgs* tab, int S, const int2* gtiles, const int* ngt,
+hipError_t run_batch_tiles(int degree, const TileArgs* tab, int S, const int2* gtiles, const int* ngt,
                            int* gqueue, int grid, int fgrid, hipEvent_t ev_stop, hipStream_t s);
 hipError_t run_batch_finish(const BatchShape* bs, int S, int64_t nmax, const int64_t* step,
                             const AdamParams& ap, hipStream_t s);
@@ -187,8 +208,9 @@ hipError_t run_loss_finalize(const Work& w, int64_t J, double* loss_out, hipStre
 hipError_t run_adam(const Work& w, float* theta, float* m, float* v, int64_t n, float lr,
                     float beta1, float beta2, float eps, float wd, float bc1, float bc2,
                     hipStream_t s);
-hipError_t run_init_params(const Work& w, const Geo& g, float* theta, const float* surf,
-                           int64_t Ns, float bandwidth, float rho0, hipStream_t s);
+hipError_t run_init_params(const Work& w, const Geo& g, const Layout& L, float* theta,
+                           const float* surf, int64_t Ns, float bandwidth, float rho0,
+                           hipStream_t s);
 hipError_t run_count_uncertified(const Work& w, int64_t* out, hipStream_t s);
 hipError_t run_zero_floats(float* p, int64_t n, hipStream_t s);
 

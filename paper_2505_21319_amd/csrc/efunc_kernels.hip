@@ -133,36 +133,57 @@ __global__ void k_reset_stats(DevStats* st)
 }
 
 // --------------------------------------------------------- key preparation
+// Value record of a key from its theta channels vo..: {o, d.x, d.y, d.z} and,
+// for degree 2, {S_xx/2, S_yy/2, S_zz/2, S_xy}, {S_xz, S_yz, 0, 0}.
+template <int DEG>
+__device__ __forceinline__ void value_records(const float* __restrict__ p, int vo, float4& v1,
+                                              float4& q0, float4& q1)
+{
+    v1 = make_float4(p[vo], DEG >= 1 ? p[vo + 1] : 0.0f, DEG >= 1 ? p[vo + 2] : 0.0f,
+                     DEG >= 1 ? p[vo + 3] : 0.0f);
+    if (DEG == 2) {
+        q0 = make_float4(0.5f * p[vo + 4], 0.5f * p[vo + 5], 0.5f * p[vo + 6], p[vo + 7]);
+        q1 = make_float4(p[vo + 8], p[vo + 9], 0.0f, 0.0f);
+    }
+}
+
 // Per vertex: the grid key record, the moved key centre k_i + Delta_i split
 // into float hi + lo parts, its (clamped) cell, and scale statistics.
+template <int DEG>
 __global__ __launch_bounds__(BLOCK) void k_prep_keys(
-    const float* __restrict__ theta, Geo g, int offsets, int64_t I, float4* __restrict__ gk,
+    const float* __restrict__ theta, Geo g, Layout L, int64_t I, float4* __restrict__ gk,
     float4* __restrict__ mrec, int* __restrict__ mcell, int* __restrict__ mrank,
     int* __restrict__ mcount, DevStats* __restrict__ st)
 {
+    constexpr int GW = gk_width(DEG), MW = mk_width(DEG);
     __shared__ float sh_f[BLOCK / 64];
     __shared__ int sh_i[BLOCK / 64];
     const int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
     float bmin = INFINITY, bgmax = 0.0f;
     int nonfinite = 0;
     if (i < I) {
-        const float* p = theta + i * NCH;
-        float v[NCH];
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            v[c] = p[c];
-            nonfinite += isfinite(v[c]) ? 0 : 1;
+        const float* p = theta + i * L.nch;
+        for (int c = 0; c < L.nch; ++c) nonfinite += isfinite(p[c]) ? 0 : 1;
+        const float bfix = expf(L.rho_fixed);
+        float4 v1, q0, q1;
+        if (L.grid) {
+            const float beta = L.learn ? expf(p[L.grho]) : bfix;
+            value_records<DEG>(p, L.gval, v1, q0, q1);
+            gk[GW * i] = make_float4(-beta * LOG2E, v1.x, v1.y, v1.z);
+            gk[GW * i + 1] = make_float4(v1.w, beta, 0.0f, 0.0f);
+            if (DEG == 2) {
+                gk[GW * i + 2] = q0;
+                gk[GW * i + 3] = q1;
+            }
+            bmin = beta;
+            bgmax = beta;
         }
-        const float beta = expf(v[4]);
-        gk[2 * i] = make_float4(-beta * LOG2E, v[0], v[1], v[2]);
-        gk[2 * i + 1] = make_float4(v[3], beta, 0.0f, 0.0f);
-        bmin = beta;
-        bgmax = beta;
-        if (offsets) {
+        if (L.moved) {
             const int R = g.R;
             const int ix = (int)(i / ((int64_t)R * R)), iy = (int)((i / R) % R), iz = (int)(i % R);
-            const double c[3] = {(double)g.tlat[ix] + (double)v[5], (double)g.tlat[iy] + (double)v[6],
-                                 (double)g.tlat[iz] + (double)v[7]};
+            const double c[3] = {(double)g.tlat[ix] + (double)p[L.mdel],
+                                 (double)g.tlat[iy] + (double)p[L.mdel + 1],
+                                 (double)g.tlat[iz] + (double)p[L.mdel + 2]};
             int m[3];
             float hi[3], lo[3];
 #pragma unroll
@@ -172,10 +193,15 @@ __global__ __launch_bounds__(BLOCK) void k_prep_keys(
                 hi[d] = (float)c[d];
                 lo[d] = (float)(c[d] - (double)hi[d]);
             }
-            const float beta2 = expf(v[12]);
-            mrec[3 * i] = make_float4(hi[0], hi[1], hi[2], -beta2 * LOG2E);
-            mrec[3 * i + 1] = make_float4(v[8], v[9], v[10], v[11]);
-            mrec[3 * i + 2] = make_float4(lo[0], lo[1], lo[2], __int_as_float((int)i));
+            const float beta2 = L.learn ? expf(p[L.mrho]) : bfix;
+            value_records<DEG>(p, L.mval, v1, q0, q1);
+            mrec[MW * i] = make_float4(hi[0], hi[1], hi[2], -beta2 * LOG2E);
+            mrec[MW * i + 1] = v1;
+            mrec[MW * i + 2] = make_float4(lo[0], lo[1], lo[2], __int_as_float((int)i));
+            if (DEG == 2) {
+                mrec[MW * i + 3] = q0;
+                mrec[MW * i + 4] = q1;
+            }
             const int cell = (m[0] * g.C1 + m[1]) * g.C1 + m[2];
             mcell[i] = cell;
             mrank[i] = atomicAdd(&mcount[cell], 1);
@@ -290,16 +316,17 @@ __global__ __launch_bounds__(BLOCK) void k_scan_apply(const int* __restrict__ cn
     if (blockIdx.x == 0 && threadIdx.x == 0) start[n] = blk[nb];
 }
 
+template <int DEG>
 __global__ void k_scatter_keys(int64_t I, const int* __restrict__ mcell, const int* __restrict__ mrank,
                                const int* __restrict__ mstart, const float4* __restrict__ mrec,
                                float4* __restrict__ mk)
 {
+    constexpr int MW = mk_width(DEG);
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= I) return;
     const int64_t pos = (int64_t)mstart[mcell[i]] + mrank[i];
-    mk[3 * pos] = mrec[3 * i];
-    mk[3 * pos + 1] = mrec[3 * i + 1];
-    mk[3 * pos + 2] = mrec[3 * i + 2];
+#pragma unroll
+    for (int k = 0; k < MW; ++k) mk[MW * pos + k] = mrec[MW * i + k];
 }
 
 // ------------------------------------------------------------ query binning
@@ -510,13 +537,30 @@ __global__ __launch_bounds__(BLOCK) void k_tile_place(const int* __restrict__ nt
 }
 
 // ------------------------------------------------------------------ tiles
+// Curvature of a staged degree-2 key: {S_xx/2, S_yy/2, S_zz/2, S_xy}, {S_xz, S_yz}.
+template <int DEG>
+struct KeyQ {
+    __device__ KeyQ() {}
+};
+template <>
+struct KeyQ<2> {
+    float4 a;
+    float2 b;
+    __device__ KeyQ() {}
+};
+
+template <int DEG>
 struct TileSmem {
+    static constexpr int NF = DEG == 2 ? 16 : 8;  // flush slots per key
+    static constexpr int NQ = DEG == 2 ? KC : 1;
     union {
         struct {
             float4 kc[KC];    // key centre relative to the tile origin, nb = -beta log2(e)
             float4 kv[KC];    // o, d.xyz
+            float4 kqa[NQ];   // degree 2: S_xx/2, S_yy/2, S_zz/2, S_xy
+            float2 kqb[NQ];   // degree 2: S_xz, S_yz
         };
-        float fv[8 * KC];     // backward flush: 8 channel values per kept key
+        float fv[NF * KC];    // backward flush: NF channel values per kept key
     };
     int kid[KC];          // vertex index; -(vid + 1) for moved keys
     float4 pq[PMAX];      // query relative to the tile origin, aux (target or dL/dO)
@@ -531,11 +575,71 @@ struct TileSmem {
     int tile;
 };
 
+template <int DEG>
+__device__ __forceinline__ KeyQ<DEG> load_q(const TileSmem<DEG>& S, int k)
+{
+    KeyQ<DEG> q;
+    if constexpr (DEG == 2) {
+        q.a = S.kqa[k];
+        q.b = S.kqb[k];
+    }
+    (void)S;
+    (void)k;
+    return q;
+}
+
+// f(x) of Eq. poly-func: o (degree 0), o + x.d (1), + x^T S x / 2 (2),
+// the last as x (S_xx/2 x + S_xy y + S_xz z) + y (S_yy/2 y + S_yz z) + S_zz/2 z^2.
+template <int DEG>
+__device__ __forceinline__ float poly(float4 kv, const KeyQ<DEG>& kq, float dx, float dy, float dz)
+{
+    if constexpr (DEG == 0) {
+        (void)dx; (void)dy; (void)dz; (void)kq;
+        return kv.x;
+    } else {
+        float f = fmaf(dx, kv.y, fmaf(dy, kv.z, fmaf(dz, kv.w, kv.x)));
+        if constexpr (DEG == 2) {
+            const float t0 = fmaf(kq.a.x, dx, fmaf(kq.a.w, dy, kq.b.x * dz));
+            const float t1 = fmaf(kq.a.y, dy, kq.b.y * dz);
+            f = fmaf(dx, t0, fmaf(dy, t1, fmaf(kq.a.z * dz, dz, f)));
+        }
+        return f;
+    }
+}
+
+// grad_x f = d + S x (zero for degree 0).
+template <int DEG>
+__device__ __forceinline__ void poly_grad(float4 kv, const KeyQ<DEG>& kq, float dx, float dy, float dz,
+                                          float& gx, float& gy, float& gz)
+{
+    gx = gy = gz = 0.0f;
+    if constexpr (DEG >= 1) {
+        gx = kv.y;
+        gy = kv.z;
+        gz = kv.w;
+    }
+    if constexpr (DEG == 2) {
+        gx = fmaf(2.0f * kq.a.x, dx, fmaf(kq.a.w, dy, fmaf(kq.b.x, dz, gx)));
+        gy = fmaf(kq.a.w, dx, fmaf(2.0f * kq.a.y, dy, fmaf(kq.b.y, dz, gy)));
+        gz = fmaf(kq.b.x, dx, fmaf(kq.b.y, dy, fmaf(2.0f * kq.a.z, dz, gz)));
+    }
+    (void)kq; (void)dx; (void)dy; (void)dz;
+}
+
+// Backward accumulators per key: 0 sum delta; 1..3 sum delta x (degree >= 1);
+// 4 sum u |x|^2; 5..7 sum u x (moved keys); 8..13 sum delta times the
+// quadratic monomials x^2/2, y^2/2, z^2/2, xy, xz, yz (degree 2);
+// delta = g w, u = delta (f - O).
+template <int DEG>
+struct NAcc {
+    static constexpr int n = DEG == 2 ? 14 : 8;
+};
+
 // Backward accumulation over the tile's queries for one key held in
 // registers: key-parallel, as in Alg. 2.  MOVED adds the centre gradient sums.
-template <bool MOVED>
-__device__ __forceinline__ void bwd_key(const TileSmem& S, int P, int ph, int Sb, float4 kc,
-                                        float4 kv, float acc[8])
+template <bool MOVED, int DEG>
+__device__ __forceinline__ void bwd_key(const TileSmem<DEG>& S, int P, int ph, int Sb, float4 kc,
+                                        float4 kv, const KeyQ<DEG>& kq, float (&acc)[NAcc<DEG>::n])
 {
 #pragma unroll 2
     for (int p = ph; p < P; p += Sb) {
@@ -544,25 +648,36 @@ __device__ __forceinline__ void bwd_key(const TileSmem& S, int P, int ph, int Sb
         const float dx = pq.x - kc.x, dy = pq.y - kc.y, dz = pq.z - kc.z;
         const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
         const float w = ex2(fmaf(kc.w, r2, -pv.y));
-        const float f = fmaf(dx, kv.y, fmaf(dy, kv.z, fmaf(dz, kv.w, kv.x)));
+        const float f = poly<DEG>(kv, kq, dx, dy, dz);
         const float del = pv.z * w;
         const float u = del * (f - pv.x);
         acc[0] += del;
-        acc[1] = fmaf(del, dx, acc[1]);
-        acc[2] = fmaf(del, dy, acc[2]);
-        acc[3] = fmaf(del, dz, acc[3]);
+        if (DEG >= 1) {
+            acc[1] = fmaf(del, dx, acc[1]);
+            acc[2] = fmaf(del, dy, acc[2]);
+            acc[3] = fmaf(del, dz, acc[3]);
+        }
         acc[4] = fmaf(u, r2, acc[4]);
         if (MOVED) {
             acc[5] = fmaf(u, dx, acc[5]);
             acc[6] = fmaf(u, dy, acc[6]);
             acc[7] = fmaf(u, dz, acc[7]);
         }
+        if constexpr (DEG == 2) {
+            const float hx = 0.5f * del * dx, hy = 0.5f * del * dy;
+            acc[8] = fmaf(hx, dx, acc[8]);
+            acc[9] = fmaf(hy, dy, acc[9]);
+            acc[10] = fmaf(0.5f * del * dz, dz, acc[10]);
+            acc[11] = fmaf(del * dx, dy, acc[11]);
+            acc[12] = fmaf(del * dx, dz, acc[12]);
+            acc[13] = fmaf(del * dy, dz, acc[13]);
+        }
     }
 }
 
 // Bounds of a set of tile queries: box (x0, y0, z0, x1, y1, z1) and the
 // smallest value of one per-query field; every thread receives them.
-__device__ void tile_bounds(const TileSmem& S, float (&bl)[7], float* __restrict__ shbox)
+__device__ void tile_bounds(float (&bl)[7], float* __restrict__ shbox)
 {
     const int tid = threadIdx.x;
 #pragma unroll
@@ -587,7 +702,6 @@ __device__ void tile_bounds(const TileSmem& S, float (&bl)[7], float* __restrict
         for (int t = 3; t < 6; ++t) bl[t] = fmaxf(bl[t], shbox[wv * 8 + t]);
         bl[6] = fminf(bl[6], shbox[wv * 8 + 6]);
     }
-    (void)S;
 }
 
 // Largest logit (log2 units, <= 0) any query inside the box can have against
@@ -601,64 +715,56 @@ __device__ __forceinline__ float box_logit(const float (&bl)[7], float4 kc)
 }
 
 // Forward sums over one staged chunk: keys k = ph, ph + Sf, ... against the
-// lane's NPL queries (Alg. 1 with the reference exponent M).
-template <int NPL>
-__device__ __forceinline__ void fwd_sums(const TileSmem& S, int n, int ph, int Sf, const float4 (&q)[NPL],
-                                         const float (&M)[NPL], float (&e)[NPL], float (&m)[NPL])
+// lane's query (Alg. 1 with the reference exponent M).
+template <int DEG>
+__device__ __forceinline__ void fwd_sums(const TileSmem<DEG>& S, int n, int ph, int Sf, const float4 q,
+                                         const float M, float& e, float& m)
 {
-#pragma unroll(4 / NPL)
+#pragma unroll 4
     for (int k = ph; k < n; k += Sf) {
         const float4 kc = S.kc[k], kv = S.kv[k];
-#pragma unroll
-        for (int i = 0; i < NPL; ++i) {
-            const float dx = q[i].x - kc.x, dy = q[i].y - kc.y, dz = q[i].z - kc.z;
-            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            const float l = ex2(fmaf(kc.w, r2, -M[i]));
-            const float f = fmaf(dx, kv.y, fmaf(dy, kv.z, fmaf(dz, kv.w, kv.x)));
-            e[i] += l;
-            m[i] = fmaf(l, f, m[i]);
-        }
+        const KeyQ<DEG> kq = load_q(S, k);
+        const float dx = q.x - kc.x, dy = q.y - kc.y, dz = q.z - kc.z;
+        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        const float l = ex2(fmaf(kc.w, r2, -M));
+        const float f = poly<DEG>(kv, kq, dx, dy, dz);
+        e += l;
+        m = fmaf(l, f, m);
     }
 }
 
-template <int NPL>
-__device__ __forceinline__ void fwd_max(const TileSmem& S, int n, int ph, int Sf, const float4 (&q)[NPL],
-                                        float (&M)[NPL])
+template <int DEG>
+__device__ __forceinline__ void fwd_max(const TileSmem<DEG>& S, int n, int ph, int Sf, const float4 q,
+                                        float& M)
 {
     for (int k = ph; k < n; k += Sf) {
         const float4 kc = S.kc[k];
-#pragma unroll
-        for (int i = 0; i < NPL; ++i) {
-            const float dx = q[i].x - kc.x, dy = q[i].y - kc.y, dz = q[i].z - kc.z;
-            M[i] = fmaxf(M[i], kc.w * fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
-        }
+        const float dx = q.x - kc.x, dy = q.y - kc.y, dz = q.z - kc.z;
+        M = fmaxf(M, kc.w * fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
     }
 }
 
-// dO/dq = sum_a w_a [d_a + 2 beta_a x (O - f_a)]  (Eq. func-normal)
-template <int NPL>
-__device__ __forceinline__ void fwd_qgrad(const TileSmem& S, int n, int ph, int Sf, const float4 (&q)[NPL],
-                                          const float (&O)[NPL], const float (&L)[NPL],
-                                          float (&gx)[NPL], float (&gy)[NPL], float (&gz)[NPL])
+// dO/dq = sum_a w_a [grad f_a + 2 beta_a x (O - f_a)]  (Eq. func-normal)
+template <int DEG>
+__device__ __forceinline__ void fwd_qgrad(const TileSmem<DEG>& S, int n, int ph, int Sf, const float4 q,
+                                          const float O, const float L, float& gx, float& gy, float& gz)
 {
     for (int k = ph; k < n; k += Sf) {
         const float4 kc = S.kc[k], kv = S.kv[k];
-#pragma unroll
-        for (int i = 0; i < NPL; ++i) {
-            const float dx = q[i].x - kc.x, dy = q[i].y - kc.y, dz = q[i].z - kc.z;
-            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            const float w = ex2(fmaf(kc.w, r2, -L[i]));
-            const float f = fmaf(dx, kv.y, fmaf(dy, kv.z, fmaf(dz, kv.w, kv.x)));
-            const float t = -2.0f * LN2 * kc.w * (O[i] - f) * w;  // 2 beta (O - f) w
-            gx[i] += fmaf(w, kv.y, t * dx);
-            gy[i] += fmaf(w, kv.z, t * dy);
-            gz[i] += fmaf(w, kv.w, t * dz);
-        }
+        const KeyQ<DEG> kq = load_q(S, k);
+        const float dx = q.x - kc.x, dy = q.y - kc.y, dz = q.z - kc.z;
+        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        const float w = ex2(fmaf(kc.w, r2, -L));
+        const float f = poly<DEG>(kv, kq, dx, dy, dz);
+        float fx, fy, fz;
+        poly_grad<DEG>(kv, kq, dx, dy, dz, fx, fy, fz);
+        const float t = -2.0f * LN2 * kc.w * (O - f) * w;  // 2 beta (O - f) w
+        gx += fmaf(w, fx, t * dx);
+        gy += fmaf(w, fy, t * dy);
+        gz += fmaf(w, fz, t * dz);
     }
 }
 
-// Four workgroups (16 waves) per CU: 128 VGPRs, no spills; measured 7 %
-// faster than the unconstrained 155-VGPR allocation (3 workgroups).
 // Pair counts of the tiles a workgroup has run (flushed to DevStats once).
 struct PairCount {
     unsigned long long fwd = 0, fwd_moved = 0, bwd = 0, bwd_moved = 0;
@@ -677,11 +783,13 @@ __device__ __forceinline__ void flush_pairs(DevStats* st, const PairCount& c)
 // One tile: window, forward (Alg. 1), loss, backward (Alg. 2) and flush.
 // td is the tile descriptor, tile its index in a.tiles (loss partial slot);
 // W and bmin2 (smallest beta in log2 units) come from the shape's DevStats.
-template <int MODE, bool QGRAD>
-__device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem& S, const int4 td, const int tile,
+template <int MODE, bool QGRAD, int DEG>
+__device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem<DEG>& S, const int4 td, const int tile,
                                          const int W, const float bmin2, PairCount& pc)
 {
     static_assert(KC == BLOCK, "one staged key per thread");
+    constexpr int GW = gk_width(DEG), MW = mk_width(DEG);
+    const Layout& L = a.L;
     const int tid = threadIdx.x;
     const Geo& g = a.g;
     const int R = g.R, C1 = g.C1;
@@ -696,7 +804,7 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem& S, const i
         const int vy0 = max(cy - W + 1, 0), vy1 = min(cy1 + W, R - 1);
         const int vz0 = max(cz - W + 1, 0), vz1 = min(cz1 + W, R - 1);
         const int nvy = vy1 - vy0 + 1, nvz = vz1 - vz0 + 1;
-        const int Kg = (vx1 - vx0 + 1) * nvy * nvz;
+        const int Kg = L.grid ? (vx1 - vx0 + 1) * nvy * nvz : 0;
         int Km = 0, nseg = 0;
         if (a.offsets) {
             const int mx0 = max(cx - W, 0), mx1 = min(cx1 + W, C1 - 1);
@@ -749,6 +857,7 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem& S, const i
         // compacted to LDS slots [0, n); moved keys carry the tag -(vid + 1).
         auto stage_cull = [&](int k0, int nk, const float (&bl)[7], float cutoff) -> int {
             float4 kc = make_float4(0, 0, 0, 0), kv = make_float4(0, 0, 0, 0);
+            float4 q0 = make_float4(0, 0, 0, 0), q1 = make_float4(0, 0, 0, 0);
             int tag = 0;
             bool keep = false;
             if (tid < nk) {
@@ -759,9 +868,13 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem& S, const i
                     const int qy = nvz > 1 ? (int)__umulhi((unsigned)rr, mz) : rr;
                     const int ix = vx0 + qx, iy = vy0 + qy, iz = vz0 + (rr - qy * nvz);
                     const int vid = (ix * R + iy) * R + iz;
-                    const float4 a0 = a.gk[2 * (int64_t)vid], a1 = a.gk[2 * (int64_t)vid + 1];
+                    const float4 a0 = a.gk[GW * (int64_t)vid], a1 = a.gk[GW * (int64_t)vid + 1];
                     kc = make_float4(g.tlat[ix] - oxf, g.tlat[iy] - oyf, g.tlat[iz] - ozf, a0.x);
                     kv = make_float4(a0.y, a0.z, a0.w, a1.x);
+                    if (DEG == 2) {
+                        q0 = a.gk[GW * (int64_t)vid + 2];
+                        q1 = a.gk[GW * (int64_t)vid + 3];
+                    }
                     tag = vid;
                 } else {
                     const int km = kk - Kg;
@@ -771,7 +884,11 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem& S, const i
                         if (S.seg_off[mid] <= km) lo = mid; else hi = mid - 1;
                     }
                     const int64_t slot = (int64_t)S.seg_src[lo] + (km - S.seg_off[lo]);
-                    const float4 b0 = a.mk[3 * slot], b1 = a.mk[3 * slot + 1], b2 = a.mk[3 * slot + 2];
+                    const float4 b0 = a.mk[MW * slot], b1 = a.mk[MW * slot + 1], b2 = a.mk[MW * slot + 2];
+                    if (DEG == 2) {
+                        q0 = a.mk[MW * slot + 3];
+                        q1 = a.mk[MW * slot + 4];
+                    }
                     kc = make_float4((float)(((double)b0.x - ox) + (double)b2.x),
                                      (float)(((double)b0.y - oy) + (double)b2.y),
                                      (float)(((double)b0.z - oz) + (double)b2.z), b0.w);
@@ -785,6 +902,10 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem& S, const i
             if (keep) {
                 S.kc[pos] = kc;
                 S.kv[pos] = kv;
+                if (DEG == 2) {
+                    S.kqa[pos] = q0;
+                    S.kqb[pos] = make_float2(q1.x, q1.y);
+                }
                 S.kid[pos] = tag;
             }
             __syncthreads();
@@ -794,11 +915,17 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem& S, const i
         // Re-apply the test to the n staged keys in place.
         auto recull = [&](int n0, const float (&bl)[7], float cutoff) -> int {
             float4 kc = make_float4(0, 0, 0, 0), kv = make_float4(0, 0, 0, 0);
+            float4 q0 = make_float4(0, 0, 0, 0);
+            float2 q1 = make_float2(0, 0);
             int tag = 0;
             bool keep = false;
             if (tid < n0) {
                 kc = S.kc[tid];
                 kv = S.kv[tid];
+                if (DEG == 2) {
+                    q0 = S.kqa[tid];
+                    q1 = S.kqb[tid];
+                }
                 tag = S.kid[tid];
                 keep = box_logit(bl, kc) >= cutoff;
             }
@@ -807,6 +934,10 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem& S, const i
             if (keep) {
                 S.kc[pos] = kc;
                 S.kv[pos] = kv;
+                if (DEG == 2) {
+                    S.kqa[pos] = q0;
+                    S.kqb[pos] = q1;
+                }
                 S.kid[pos] = tag;
             }
             __syncthreads();
@@ -828,12 +959,13 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem& S, const i
                 const float4 pq = S.pq[p];
                 const float4 qa = a.ps[p0 + p];  // absolute position: the binning's home cell
                 const int hx = cell_of(qa.x, g), hy = cell_of(qa.y, g), hz = cell_of(qa.z, g);
-                float M0 = -INFINITY;
+                float M0 = -INFINITY;  // without grid keys: the exact pass below
 #pragma unroll
                 for (int c8 = 0; c8 < 8; ++c8) {
+                    if (!L.grid) break;
                     const int ix = hx + (c8 >> 2), iy = hy + ((c8 >> 1) & 1), iz = hz + (c8 & 1);
                     const int vid = (ix * R + iy) * R + iz;
-                    const float nb = a.gk[2 * (int64_t)vid].x;
+                    const float nb = a.gk[GW * (int64_t)vid].x;
                     const float dx = pq.x - (g.tlat[ix] - oxf);
                     const float dy = pq.y - (g.tlat[iy] - oyf);
                     const float dz = pq.z - (g.tlat[iz] - ozf);
@@ -847,9 +979,9 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem& S, const i
                 bl[6] = fminf(bl[6], M0);
             }
             const int exact = __syncthreads_or(need_exact);
-            tile_bounds(S, bl, &S.box[0][0]);
+            tile_bounds(bl, &S.box[0][0]);
             // M0 <= lse2 for every query, so this drops only pairs below e^-T
-            const float fcut = bl[6] - a.T2;
+            float fcut = bl[6] - a.T2;
 
             // Query-to-lane mapping in two rounds: queries [0, P1) with Sf lanes each
             // and queries [BLOCK, P) (at most BLOCK - 1 of them) with Sf2 lanes
@@ -863,36 +995,41 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem& S, const i
             const bool act2 = pme2 < P2;
             auto slot0 = [&](int p) { return p < BLOCK ? p * Sf : BLOCK + (p - BLOCK) * Sf2; };
             auto nslot = [&](int p) { return p < BLOCK ? Sf : Sf2; };
-            float4 q[1] = {S.pq[act ? pme : 0]};
-            float4 q2[1] = {S.pq[act2 ? BLOCK + pme2 : 0]};
+            const float4 q = S.pq[act ? pme : 0];
+            const float4 q2 = S.pq[act2 ? BLOCK + pme2 : 0];
 
             if (exact) {
-                // exact maximum over the window first (rare: very coarse lattices)
-                float M[1] = {-INFINITY}, M2[1] = {-INFINITY};
+                // exact maximum over the window first (very coarse lattices, or
+                // no grid keys to take the reference from)
+                float M = -INFINITY, M2 = -INFINITY;
                 for (int c = 0; c < nchunks; ++c) {
                     const int k0 = c * KC, nk = min(KC, K - k0);
                     __syncthreads();
                     nstaged = stage_cull(k0, nk, bl, fcut);
                     nstaged_moved = nmoved;
                     staged = c;
-                    if (act) fwd_max<1>(S, nstaged, ph, Sf, q, M);
-                    if (act2) fwd_max<1>(S, nstaged, ph2, Sf2, q2, M2);
+                    if (act) fwd_max<DEG>(S, nstaged, ph, Sf, q, M);
+                    if (act2) fwd_max<DEG>(S, nstaged, ph2, Sf2, q2, M2);
                 }
-                S.red[tid].x = M[0];
-                S.red[BLOCK + tid].x = M2[0];
+                S.red[tid].x = M;
+                S.red[BLOCK + tid].x = M2;
                 __syncthreads();
+                float mn = INFINITY;
                 for (int p = tid; p < P; p += BLOCK) {
                     float mx = S.pv[p].w;
                     for (int s = 0; s < nslot(p); ++s) mx = fmaxf(mx, S.red[slot0(p) + s].x);
                     S.pv[p].w = mx;
+                    mn = fminf(mn, mx);
                 }
+                // the exact maxima are tighter lower bounds of lse2
+                fcut = -block_max(-mn, S.fsc) - a.T2;
             }
 
             // ---- forward: e = sum 2^(s - M), m = sum 2^(s - M) f   (Alg. 1)
-            float Mr[1], Mr2[1], e[1] = {0.0f}, m[1] = {0.0f}, e2[1] = {0.0f}, m2[1] = {0.0f};
+            float e = 0.0f, m = 0.0f, e2 = 0.0f, m2 = 0.0f;
             __syncthreads();
-            Mr[0] = S.pv[act ? pme : 0].w;
-            Mr2[0] = S.pv[act2 ? BLOCK + pme2 : 0].w;
+            const float Mr = S.pv[act ? pme : 0].w;
+            const float Mr2 = S.pv[act2 ? BLOCK + pme2 : 0].w;
             for (int c = 0; c < nchunks; ++c) {
                 const int k0 = c * KC, nk = min(KC, K - k0);
                 if (staged != c) {
@@ -903,12 +1040,12 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem& S, const i
                 }
                 fwd_pairs += (unsigned long long)nstaged * P;
                 fwd_moved += (unsigned long long)nstaged_moved * P;
-                if (act) fwd_sums<1>(S, nstaged, ph, Sf, q, Mr, e, m);
-                if (act2) fwd_sums<1>(S, nstaged, ph2, Sf2, q2, Mr2, e2, m2);
+                if (act) fwd_sums<DEG>(S, nstaged, ph, Sf, q, Mr, e, m);
+                if (act2) fwd_sums<DEG>(S, nstaged, ph2, Sf2, q2, Mr2, e2, m2);
             }
             __syncthreads();
-            S.red[tid] = make_float2(e[0], m[0]);
-            S.red[BLOCK + tid] = make_float2(e2[0], m2[0]);
+            S.red[tid] = make_float2(e, m);
+            S.red[BLOCK + tid] = make_float2(e2, m2);
             __syncthreads();
 
             // ---- per query: O, lse, certificate, loss and dL/dO
@@ -965,9 +1102,9 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem& S, const i
             __syncthreads();
 
             if (MODE == MODE_EVAL && QGRAD) {
-                float O1[1] = {S.pv[act ? pme : 0].x}, L1[1] = {S.pv[act ? pme : 0].y};
-                float O2[1] = {S.pv[act2 ? BLOCK + pme2 : 0].x}, L2[1] = {S.pv[act2 ? BLOCK + pme2 : 0].y};
-                float gx[1] = {0}, gy[1] = {0}, gz[1] = {0}, hx[1] = {0}, hy[1] = {0}, hz[1] = {0};
+                const float O1 = S.pv[act ? pme : 0].x, L1 = S.pv[act ? pme : 0].y;
+                const float O2 = S.pv[act2 ? BLOCK + pme2 : 0].x, L2 = S.pv[act2 ? BLOCK + pme2 : 0].y;
+                float gx = 0, gy = 0, gz = 0, hx = 0, hy = 0, hz = 0;
                 for (int c = nchunks - 1; c >= 0; --c) {
                     const int k0 = c * KC, nk = min(KC, K - k0);
                     if (staged != c) {
@@ -975,15 +1112,15 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem& S, const i
                         nstaged = stage_cull(k0, nk, bl, fcut);
                         staged = c;
                     }
-                    if (act) fwd_qgrad<1>(S, nstaged, ph, Sf, q, O1, L1, gx, gy, gz);
-                    if (act2) fwd_qgrad<1>(S, nstaged, ph2, Sf2, q2, O2, L2, hx, hy, hz);
+                    if (act) fwd_qgrad<DEG>(S, nstaged, ph, Sf, q, O1, L1, gx, gy, gz);
+                    if (act2) fwd_qgrad<DEG>(S, nstaged, ph2, Sf2, q2, O2, L2, hx, hy, hz);
                 }
                 __syncthreads();
                 float* zf = S.fv;  // keys no longer needed
-                S.red[tid] = make_float2(gx[0], gy[0]);
-                zf[tid] = gz[0];
-                S.red[BLOCK + tid] = make_float2(hx[0], hy[0]);
-                zf[BLOCK + tid] = hz[0];
+                S.red[tid] = make_float2(gx, gy);
+                zf[tid] = gz;
+                S.red[BLOCK + tid] = make_float2(hx, hy);
+                zf[BLOCK + tid] = hz;
                 staged = -1;
                 __syncthreads();
                 for (int p = tid; p < P; p += BLOCK) {
@@ -1040,7 +1177,7 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem& S, const i
                 bl[3] = fmaxf(bl[3], pq.x); bl[4] = fmaxf(bl[4], pq.y); bl[5] = fmaxf(bl[5], pq.z);
                 bl[6] = fminf(bl[6], pv.y);
             }
-            tile_bounds(S, bl, &S.box[0][0]);
+            tile_bounds(bl, &S.box[0][0]);
             const float bcut = bl[6] - a.T2;
 
             for (int c = nchunks - 1; c >= 0; --c) {
@@ -1060,54 +1197,90 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem& S, const i
                 while (Sb < 64 && Sb * 2 * n <= BLOCK) Sb *= 2;
                 const int kk = tid / Sb, ph = tid - kk * Sb;
                 const bool act = kk < n;
-                float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                constexpr int NA = NAcc<DEG>::n;
+                constexpr int NF = TileSmem<DEG>::NF;
+                constexpr int NV = DEG == 0 ? 1 : (DEG == 1 ? 4 : 10);
+                float acc[NA];
+#pragma unroll
+                for (int t = 0; t < NA; ++t) acc[t] = 0.0f;
                 float4 kc = make_float4(0, 0, 0, 0), kv = make_float4(0, 0, 0, 0);
+                KeyQ<DEG> kq;
                 int tag = 0;
                 if (act) {
                     kc = S.kc[kk];
                     kv = S.kv[kk];
+                    kq = load_q(S, kk);
                     tag = S.kid[kk];
                 }
                 const bool moved = act && tag < 0;
                 if (__any(moved)) {
-                    if (act) bwd_key<true>(S, P, ph, Sb, kc, kv, acc);
+                    if (act) bwd_key<true, DEG>(S, P, ph, Sb, kc, kv, kq, acc);
                 } else {
-                    if (act) bwd_key<false>(S, P, ph, Sb, kc, kv, acc);
+                    if (act) bwd_key<false, DEG>(S, P, ph, Sb, kc, kv, kq, acc);
                 }
                 for (int off = 1; off < Sb; off <<= 1) {
 #pragma unroll
-                    for (int t = 0; t < 8; ++t) acc[t] += __shfl_xor(acc[t], off, 64);
+                    for (int t = 0; t < NA; ++t) acc[t] += __shfl_xor(acc[t], off, 64);
                 }
-                // final channel values: o, d, rho (grid) or Delta, o', d', rho' (moved)
+                // Final channel values (Sec. 3.6).  Grid key: values (nv), rho.
+                // Moved key: Delta = centre gradient, values (nv), rho'.
+                // dL/dv = sum delta * monomial; dL/drho = beta dL/dbeta =
+                // -beta sum u |x|^2; dL/dc = -sum delta grad_x f + 2 beta sum u x
+                // with sum delta grad_x f = d sum delta + S sum delta x.
                 const float beta = -kc.w * LN2;
-                float val[8];
-                if (!moved) {
-                    val[0] = acc[0]; val[1] = acc[1]; val[2] = acc[2]; val[3] = acc[3];
-                    val[4] = -beta * acc[4];
-                    val[5] = val[6] = val[7] = 0.0f;
-                } else {
-                    // dL/dc = -d sum(delta) + 2 beta sum(delta r x)
-                    val[0] = fmaf(-kv.y, acc[0], 2.0f * beta * acc[5]);
-                    val[1] = fmaf(-kv.z, acc[0], 2.0f * beta * acc[6]);
-                    val[2] = fmaf(-kv.w, acc[0], 2.0f * beta * acc[7]);
-                    val[3] = acc[0]; val[4] = acc[1]; val[5] = acc[2]; val[6] = acc[3];
-                    val[7] = -beta * acc[4];
+                float val[NF];
+#pragma unroll
+                for (int t = 0; t < NF; ++t) val[t] = 0.0f;
+                const int vo = moved ? 3 : 0;
+                val[vo] = acc[0];
+                if (DEG >= 1) {
+                    val[vo + 1] = acc[1];
+                    val[vo + 2] = acc[2];
+                    val[vo + 3] = acc[3];
+                }
+                if (DEG == 2) {
+#pragma unroll
+                    for (int t = 0; t < 6; ++t) val[vo + 4 + t] = acc[8 + t];
+                }
+                val[vo + NV] = -beta * acc[4];
+                if (moved) {
+                    float gx = 2.0f * beta * acc[5], gy = 2.0f * beta * acc[6], gz = 2.0f * beta * acc[7];
+                    if constexpr (DEG >= 1) {
+                        gx = fmaf(-kv.y, acc[0], gx);
+                        gy = fmaf(-kv.z, acc[0], gy);
+                        gz = fmaf(-kv.w, acc[0], gz);
+                    }
+                    if constexpr (DEG == 2) {  // - S sum(delta x)
+                        gx -= fmaf(2.0f * kq.a.x, acc[1], fmaf(kq.a.w, acc[2], kq.b.x * acc[3]));
+                        gy -= fmaf(kq.a.w, acc[1], fmaf(2.0f * kq.a.y, acc[2], kq.b.y * acc[3]));
+                        gz -= fmaf(kq.b.x, acc[1], fmaf(kq.b.y, acc[2], 2.0f * kq.a.z * acc[3]));
+                    }
+                    val[0] = gx;
+                    val[1] = gy;
+                    val[2] = gz;
                 }
                 __syncthreads();  // staged keys no longer needed: reuse their LDS
                 if (act && ph == 0) {
 #pragma unroll
-                    for (int t = 0; t < 8; ++t) S.fv[kk * 8 + t] = val[t];
+                    for (int t = 0; t < NF; ++t) S.fv[kk * NF + t] = val[t];
                 }
                 __syncthreads();
-                // one atomic per key channel, eight consecutive lanes per key
-                for (int t = tid; t < n * 8; t += BLOCK) {
-                    const int kq = t >> 3, ch = t & 7;
-                    const int tg = S.kid[kq];
+                // one atomic per key channel, NF consecutive lanes per key
+                for (int t = tid; t < n * NF; t += BLOCK) {
+                    const int kq2 = t / NF, sl = t - kq2 * NF;
+                    const int tg = S.kid[kq2];
                     const bool mv = tg < 0;
                     const float x = S.fv[t];
-                    if ((mv || ch < 5) && x != 0.0f) {
+                    int c = -1;
+                    if (!mv) {
+                        c = sl < NV ? L.gval + sl : (sl == NV ? L.grho : -1);
+                    } else {
+                        c = sl < 3 ? L.mdel + sl
+                                   : (sl < 3 + NV ? L.mval + (sl - 3) : (sl == 3 + NV ? L.mrho : -1));
+                    }
+                    if (c >= 0 && x != 0.0f) {
                         const int64_t v = mv ? (int64_t)(-tg - 1) : (int64_t)tg;
-                        unsafeAtomicAdd(a.grad + v * NCH + (mv ? 5 : 0) + ch, x);
+                        unsafeAtomicAdd(a.grad + v * L.nch + c, x);
                     }
                 }
             }
@@ -1121,10 +1294,10 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem& S, const i
 
 // Persistent tile kernel of one shape: workgroups pull tiles (heaviest
 // first) from an atomic queue until it is empty.
-template <int MODE, bool QGRAD>
+template <int MODE, bool QGRAD, int DEG>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_tile(TileArgs a)
 {
-    __shared__ TileSmem S;
+    __shared__ TileSmem<DEG> S;
     const int ntiles = *a.ntiles;
     const int W = a.st->W;
     const float bmin2 = __uint_as_float(a.st->bmin_bits) * LOG2E;
@@ -1135,7 +1308,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) v
         __syncthreads();
         const int tile = S.tile;
         if (tile >= ntiles) break;
-        tile_run<MODE, QGRAD>(a, S, a.tiles[tile], tile, W, bmin2, pc);
+        tile_run<MODE, QGRAD, DEG>(a, S, a.tiles[tile], tile, W, bmin2, pc);
     }
     flush_pairs(a.st, pc);
 }
@@ -1143,11 +1316,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) v
 // Persistent tile kernel over a batch of shapes: one queue of (shape, tile)
 // entries in global heavy-first order; each entry runs with its shape's
 // arguments.
+template <int DEG>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_tile_batch(
     const TileArgs* __restrict__ tab, const int2* __restrict__ gtiles, const int* __restrict__ ngt,
     int* __restrict__ gqueue)
 {
-    __shared__ TileSmem S;
+    __shared__ TileSmem<DEG> S;
     const int n = *ngt;
     PairCount pc;
     int cur = -1;  // shape whose pair counts pc holds
@@ -1166,8 +1340,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) v
             cur = sh;
         }
         const TileArgs& a = tab[sh];
-        tile_run<MODE_FIT, false>(a, S, a.tiles[lt], lt, a.st->W,
-                                  __uint_as_float(a.st->bmin_bits) * LOG2E, pc);
+        tile_run<MODE_FIT, false, DEG>(a, S, a.tiles[lt], lt, a.st->W,
+                                       __uint_as_float(a.st->bmin_bits) * LOG2E, pc);
     }
     if (cur >= 0) flush_pairs(tab[cur].st, pc);
 }
@@ -1175,15 +1349,20 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) v
 // ---------------------------------------------------------------- fallback
 // Queries whose certificate failed: one workgroup per query sweeps every key
 // (the global-support definition).  Keys are taken relative to the query.
-template <int MODE, bool QGRAD>
+template <int MODE, bool QGRAD, int DEG>
 __device__ __forceinline__ void fallback_run(const TileArgs& a)
 {
+    constexpr int GW = gk_width(DEG), MW = mk_width(DEG);
+    constexpr int NV = DEG == 0 ? 1 : (DEG == 1 ? 4 : 10);
     __shared__ float shf[BLOCK / 64];
     __shared__ int s_item;
     const int tid = threadIdx.x;
     const Geo& g = a.g;
+    const Layout& L = a.L;
     const int R = g.R;
     const int64_t I = a.I;
+    const int64_t ng = L.grid ? I : 0;  // grid keys first, then moved keys
+    const int64_t nkeys = ng + (L.moved ? I : 0);
     const int nfb = a.st->nfb;
     for (;;) {
         __syncthreads();
@@ -1195,34 +1374,52 @@ __device__ __forceinline__ void fallback_run(const TileArgs& a)
         const float4 pq = a.ps[sp];
         const double qx = pq.x, qy = pq.y, qz = pq.z;
 
-        // key a (0 <= a < I grid, I <= a < 2I moved): offset x = q - c, nb, o, d
-        auto key = [&](int64_t ka, float& dx, float& dy, float& dz, float& nb, float4& kv) {
-            if (ka < I) {
+        // key ka: offset x = q - c, nb, value records, vertex
+        auto key = [&](int64_t ka, float& dx, float& dy, float& dz, float& nb, float4& kv, KeyQ<DEG>& kq,
+                       int64_t& vid) {
+            float4 q0 = make_float4(0, 0, 0, 0), q1 = make_float4(0, 0, 0, 0);
+            if (ka < ng) {
                 const int ix = (int)(ka / ((int64_t)R * R)), iy = (int)((ka / R) % R), iz = (int)(ka % R);
-                const float4 a0 = a.gk[2 * ka], a1 = a.gk[2 * ka + 1];
+                const float4 a0 = a.gk[GW * ka], a1 = a.gk[GW * ka + 1];
+                if (DEG == 2) {
+                    q0 = a.gk[GW * ka + 2];
+                    q1 = a.gk[GW * ka + 3];
+                }
                 dx = (float)(qx - (double)g.tlat[ix]);
                 dy = (float)(qy - (double)g.tlat[iy]);
                 dz = (float)(qz - (double)g.tlat[iz]);
                 nb = a0.x;
                 kv = make_float4(a0.y, a0.z, a0.w, a1.x);
+                vid = ka;
             } else {
-                const int64_t s = ka - I;
-                const float4 b0 = a.mk[3 * s], b1 = a.mk[3 * s + 1], b2 = a.mk[3 * s + 2];
+                const int64_t s = ka - ng;
+                const float4 b0 = a.mk[MW * s], b1 = a.mk[MW * s + 1], b2 = a.mk[MW * s + 2];
+                if (DEG == 2) {
+                    q0 = a.mk[MW * s + 3];
+                    q1 = a.mk[MW * s + 4];
+                }
                 dx = (float)((qx - (double)b0.x) - (double)b2.x);
                 dy = (float)((qy - (double)b0.y) - (double)b2.y);
                 dz = (float)((qz - (double)b0.z) - (double)b2.z);
                 nb = b0.w;
                 kv = b1;
+                vid = -(int64_t)__float_as_int(b2.w) - 1;
             }
+            if constexpr (DEG == 2) {
+                kq.a = q0;
+                kq.b = make_float2(q1.x, q1.y);
+            }
+            (void)q0; (void)q1;
         };
-        const int64_t nkeys = a.offsets ? 2 * I : I;
         float O, lse2, gj = 0.0f;
         if (MODE != MODE_GRAD) {
             float M = -INFINITY;
             for (int64_t ka = tid; ka < nkeys; ka += BLOCK) {
                 float dx, dy, dz, nb;
                 float4 kv;
-                key(ka, dx, dy, dz, nb, kv);
+                KeyQ<DEG> kq;
+                int64_t vid;
+                key(ka, dx, dy, dz, nb, kv, kq, vid);
                 M = fmaxf(M, nb * fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
             }
             M = block_max(M, shf);
@@ -1230,10 +1427,12 @@ __device__ __forceinline__ void fallback_run(const TileArgs& a)
             for (int64_t ka = tid; ka < nkeys; ka += BLOCK) {
                 float dx, dy, dz, nb;
                 float4 kv;
-                key(ka, dx, dy, dz, nb, kv);
+                KeyQ<DEG> kq;
+                int64_t vid;
+                key(ka, dx, dy, dz, nb, kv, kq, vid);
                 const float l = ex2(fmaf(nb, fmaf(dx, dx, fmaf(dy, dy, dz * dz)), -M));
                 e += l;
-                m = fmaf(l, fmaf(dx, kv.y, fmaf(dy, kv.z, fmaf(dz, kv.w, kv.x))), m);
+                m = fmaf(l, poly<DEG>(kv, kq, dx, dy, dz), m);
             }
             e = block_sum(e, shf);
             m = block_sum(m, shf);
@@ -1256,13 +1455,17 @@ __device__ __forceinline__ void fallback_run(const TileArgs& a)
                 for (int64_t ka = tid; ka < nkeys; ka += BLOCK) {
                     float dx, dy, dz, nb;
                     float4 kv;
-                    key(ka, dx, dy, dz, nb, kv);
+                    KeyQ<DEG> kq;
+                    int64_t vid;
+                    key(ka, dx, dy, dz, nb, kv, kq, vid);
                     const float w = ex2(fmaf(nb, fmaf(dx, dx, fmaf(dy, dy, dz * dz)), -lse2));
-                    const float f = fmaf(dx, kv.y, fmaf(dy, kv.z, fmaf(dz, kv.w, kv.x)));
+                    const float f = poly<DEG>(kv, kq, dx, dy, dz);
+                    float fx, fy, fz;
+                    poly_grad<DEG>(kv, kq, dx, dy, dz, fx, fy, fz);
                     const float t = -2.0f * LN2 * nb * (O - f) * w;
-                    gx += fmaf(w, kv.y, t * dx);
-                    gy += fmaf(w, kv.z, t * dy);
-                    gz += fmaf(w, kv.w, t * dz);
+                    gx += fmaf(w, fx, t * dx);
+                    gy += fmaf(w, fy, t * dy);
+                    gz += fmaf(w, fz, t * dz);
                 }
                 gx = block_sum(gx, shf);
                 gy = block_sum(gy, shf);
@@ -1284,49 +1487,50 @@ __device__ __forceinline__ void fallback_run(const TileArgs& a)
             for (int64_t ka = tid; ka < nkeys; ka += BLOCK) {
                 float dx, dy, dz, nb;
                 float4 kv;
-                key(ka, dx, dy, dz, nb, kv);
+                KeyQ<DEG> kq;
+                int64_t vid;
+                key(ka, dx, dy, dz, nb, kv, kq, vid);
                 const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
                 const float w = ex2(fmaf(nb, r2, -lse2));
                 const float del = gj * w;
                 if (del == 0.0f) continue;
-                const float f = fmaf(dx, kv.y, fmaf(dy, kv.z, fmaf(dz, kv.w, kv.x)));
+                const float f = poly<DEG>(kv, kq, dx, dy, dz);
                 const float u = del * (f - O);
                 const float beta = -nb * LN2;
-                if (ka < I) {
-                    float* gp = a.grad + ka * NCH;
-                    unsafeAtomicAdd(gp + 0, del);
-                    unsafeAtomicAdd(gp + 1, del * dx);
-                    unsafeAtomicAdd(gp + 2, del * dy);
-                    unsafeAtomicAdd(gp + 3, del * dz);
-                    unsafeAtomicAdd(gp + 4, -beta * u * r2);
-                } else {
-                    const float4 b2 = a.mk[3 * (ka - I) + 2];
-                    float* gp = a.grad + (int64_t)__float_as_int(b2.w) * NCH;
-                    unsafeAtomicAdd(gp + 5, fmaf(-kv.y, del, 2.0f * beta * u * dx));
-                    unsafeAtomicAdd(gp + 6, fmaf(-kv.z, del, 2.0f * beta * u * dy));
-                    unsafeAtomicAdd(gp + 7, fmaf(-kv.w, del, 2.0f * beta * u * dz));
-                    unsafeAtomicAdd(gp + 8, del);
-                    unsafeAtomicAdd(gp + 9, del * dx);
-                    unsafeAtomicAdd(gp + 10, del * dy);
-                    unsafeAtomicAdd(gp + 11, del * dz);
-                    unsafeAtomicAdd(gp + 12, -beta * u * r2);
+                // dL/dv = delta * monomials (Eq. poly-func order)
+                float mono[10] = {1.0f, dx, dy, dz, 0.5f * dx * dx, 0.5f * dy * dy, 0.5f * dz * dz,
+                                  dx * dy, dx * dz, dy * dz};
+                const bool mv = vid < 0;
+                const int64_t v = mv ? -vid - 1 : vid;
+                float* gp = a.grad + v * L.nch;
+                const int vo = mv ? L.mval : L.gval, ro = mv ? L.mrho : L.grho;
+#pragma unroll
+                for (int c = 0; c < NV; ++c) unsafeAtomicAdd(gp + vo + c, del * mono[c]);
+                if (ro >= 0) unsafeAtomicAdd(gp + ro, -beta * u * r2);
+                if (mv) {
+                    float fx, fy, fz;
+                    poly_grad<DEG>(kv, kq, dx, dy, dz, fx, fy, fz);
+                    unsafeAtomicAdd(gp + L.mdel, fmaf(-fx, del, 2.0f * beta * u * dx));
+                    unsafeAtomicAdd(gp + L.mdel + 1, fmaf(-fy, del, 2.0f * beta * u * dy));
+                    unsafeAtomicAdd(gp + L.mdel + 2, fmaf(-fz, del, 2.0f * beta * u * dz));
                 }
             }
         }
     }
 }
 
-template <int MODE, bool QGRAD>
+template <int MODE, bool QGRAD, int DEG>
 __global__ __launch_bounds__(BLOCK) void k_fallback(TileArgs a)
 {
-    fallback_run<MODE, QGRAD>(a);
+    fallback_run<MODE, QGRAD, DEG>(a);
 }
 
+template <int DEG>
 __global__ __launch_bounds__(BLOCK) void k_fallback_batch(const TileArgs* __restrict__ tab, int S)
 {
     for (int s = 0; s < S; ++s) {
         const TileArgs a = tab[s];
-        fallback_run<MODE_FIT, false>(a);
+        fallback_run<MODE_FIT, false, DEG>(a);
     }
 }
 
@@ -1473,7 +1677,7 @@ __global__ void k_step_advance(int64_t* step)
 // Delta_i = sum_n w_n s_n / sum_n w_n - k_i with w_n = exp(-bw ||k_i - s_n||^2),
 // weights relative to the nearest sample (Sec. 3.3).  One thread per vertex;
 // samples staged through LDS.
-__global__ __launch_bounds__(BLOCK) void k_init_params(float* __restrict__ theta, Geo g,
+__global__ __launch_bounds__(BLOCK) void k_init_params(float* __restrict__ theta, Geo g, Layout L,
                                                        const float* __restrict__ surf, int64_t Ns,
                                                        double bw, float rho0, int64_t I)
 {
@@ -1522,15 +1726,14 @@ __global__ __launch_bounds__(BLOCK) void k_init_params(float* __restrict__ theta
         }
     }
     if (!act) return;
-    float* p = theta + i * NCH;
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) p[c] = 0.0f;
-    p[4] = rho0;
-    p[12] = rho0;
-    if (Ns > 0) {
-        p[5] = (float)(wx / w - kx);
-        p[6] = (float)(wy / w - ky);
-        p[7] = (float)(wz / w - kz);
+    float* p = theta + i * L.nch;
+    for (int c = 0; c < L.nch; ++c) p[c] = 0.0f;
+    if (L.grho >= 0) p[L.grho] = rho0;
+    if (L.mrho >= 0) p[L.mrho] = rho0;
+    if (L.moved && Ns > 0) {
+        p[L.mdel] = (float)(wx / w - kx);
+        p[L.mdel + 1] = (float)(wy / w - ky);
+        p[L.mdel + 2] = (float)(wz / w - kz);
     }
 }
 
@@ -1568,12 +1771,26 @@ hipError_t run_front(const Work& w, const Problem& p, Mode mode, bool ordered, h
     k_fill_int<<<grid_for(w.NK * PSPLIT, BLOCK * 8), BLOCK, 0, s>>>(w.pcount, w.NK * PSPLIT, 0);
     if (p.offsets) k_fill_int<<<grid_for(C, BLOCK * 8), BLOCK, 0, s>>>(w.mcount, C, 0);
     // keys
-    k_prep_keys<<<grid_for(I), BLOCK, 0, s>>>(p.theta, g, p.offsets, I, w.gk, w.mrec, w.mcell,
-                                              w.mrank, w.mcount, w.st);
+    switch (p.L.degree) {
+    case 0:
+        k_prep_keys<0><<<grid_for(I), BLOCK, 0, s>>>(p.theta, g, p.L, I, w.gk, w.mrec, w.mcell,
+                                                     w.mrank, w.mcount, w.st);
+        break;
+    case 2:
+        k_prep_keys<2><<<grid_for(I), BLOCK, 0, s>>>(p.theta, g, p.L, I, w.gk, w.mrec, w.mcell,
+                                                     w.mrank, w.mcount, w.st);
+        break;
+    default:
+        k_prep_keys<1><<<grid_for(I), BLOCK, 0, s>>>(p.theta, g, p.L, I, w.gk, w.mrec, w.mcell,
+                                                     w.mrank, w.mcount, w.st);
+    }
     if (p.offsets) {
         hipError_t e = scan(w.mcount, C, w.scan_blk, w.mstart, s);
         if (e != hipSuccess) return e;
-        k_scatter_keys<<<grid_for(I), BLOCK, 0, s>>>(I, w.mcell, w.mrank, w.mstart, w.mrec, w.mk);
+        if (p.L.degree == 2)
+            k_scatter_keys<2><<<grid_for(I), BLOCK, 0, s>>>(I, w.mcell, w.mrank, w.mstart, w.mrec, w.mk);
+        else
+            k_scatter_keys<1><<<grid_for(I), BLOCK, 0, s>>>(I, w.mcell, w.mrank, w.mstart, w.mrec, w.mk);
     }
     k_window<<<1, 64, 0, s>>>(w.st, g, p.T, p.window);
     // queries
@@ -1611,6 +1828,7 @@ TileArgs make_tile_args(const Work& w, const Problem& p, bool ordered)
 {
     TileArgs a;
     a.g = p.g;
+    a.L = p.L;
     a.offsets = p.offsets;
     a.T2 = p.T * LOG2E;
     a.two_over_J = (float)(2.0 / (double)(p.J > 0 ? p.J : 1));
@@ -1633,6 +1851,35 @@ TileArgs make_tile_args(const Work& w, const Problem& p, bool ordered)
     return a;
 }
 
+template <int DEG>
+static void launch_tiles(const TileArgs& a, Mode mode, bool qgrad, unsigned grid, int fgrid,
+                         hipEvent_t ev_stop, hipStream_t s)
+{
+    switch (mode) {
+    case MODE_FIT:
+        k_tile<MODE_FIT, false, DEG><<<grid, BLOCK, 0, s>>>(a);
+        if (ev_stop) (void)hipEventRecord(ev_stop, s);
+        k_fallback<MODE_FIT, false, DEG><<<fgrid, BLOCK, 0, s>>>(a);
+        break;
+    case MODE_EVAL:
+        if (qgrad) {
+            k_tile<MODE_EVAL, true, DEG><<<grid, BLOCK, 0, s>>>(a);
+            if (ev_stop) (void)hipEventRecord(ev_stop, s);
+            k_fallback<MODE_EVAL, true, DEG><<<fgrid, BLOCK, 0, s>>>(a);
+        } else {
+            k_tile<MODE_EVAL, false, DEG><<<grid, BLOCK, 0, s>>>(a);
+            if (ev_stop) (void)hipEventRecord(ev_stop, s);
+            k_fallback<MODE_EVAL, false, DEG><<<fgrid, BLOCK, 0, s>>>(a);
+        }
+        break;
+    case MODE_GRAD:
+        k_tile<MODE_GRAD, false, DEG><<<grid, BLOCK, 0, s>>>(a);
+        if (ev_stop) (void)hipEventRecord(ev_stop, s);
+        k_fallback<MODE_GRAD, false, DEG><<<fgrid, BLOCK, 0, s>>>(a);
+        break;
+    }
+}
+
 hipError_t run_tiles(const Work& w, const Problem& p, Mode mode, hipStream_t s)
 {
     hipError_t e = run_front(w, p, mode, true, s);
@@ -1643,28 +1890,10 @@ hipError_t run_tiles(const Work& w, const Problem& p, Mode mode, hipStream_t s)
     if (grid < 1) grid = 1;
     const int fgrid = w.num_cu;
     if (p.ev_start) (void)hipEventRecord(p.ev_start, s);
-    switch (mode) {
-    case MODE_FIT:
-        k_tile<MODE_FIT, false><<<(unsigned)grid, BLOCK, 0, s>>>(a);
-        if (p.ev_stop) (void)hipEventRecord(p.ev_stop, s);
-        k_fallback<MODE_FIT, false><<<fgrid, BLOCK, 0, s>>>(a);
-        break;
-    case MODE_EVAL:
-        if (p.dOdq_out) {
-            k_tile<MODE_EVAL, true><<<(unsigned)grid, BLOCK, 0, s>>>(a);
-            if (p.ev_stop) (void)hipEventRecord(p.ev_stop, s);
-            k_fallback<MODE_EVAL, true><<<fgrid, BLOCK, 0, s>>>(a);
-        } else {
-            k_tile<MODE_EVAL, false><<<(unsigned)grid, BLOCK, 0, s>>>(a);
-            if (p.ev_stop) (void)hipEventRecord(p.ev_stop, s);
-            k_fallback<MODE_EVAL, false><<<fgrid, BLOCK, 0, s>>>(a);
-        }
-        break;
-    case MODE_GRAD:
-        k_tile<MODE_GRAD, false><<<(unsigned)grid, BLOCK, 0, s>>>(a);
-        if (p.ev_stop) (void)hipEventRecord(p.ev_stop, s);
-        k_fallback<MODE_GRAD, false><<<fgrid, BLOCK, 0, s>>>(a);
-        break;
+    switch (p.L.degree) {
+    case 0: launch_tiles<0>(a, mode, p.dOdq_out != nullptr, (unsigned)grid, fgrid, p.ev_stop, s); break;
+    case 2: launch_tiles<2>(a, mode, p.dOdq_out != nullptr, (unsigned)grid, fgrid, p.ev_stop, s); break;
+    default: launch_tiles<1>(a, mode, p.dOdq_out != nullptr, (unsigned)grid, fgrid, p.ev_stop, s);
     }
     return hipGetLastError();
 }
@@ -1680,12 +1909,23 @@ hipError_t run_batch_order(const BatchShape* bs, int S, int64_t max_tiles, int* 
     return hipGetLastError();
 }
 
-hipError_t run_batch_tiles(const TileArgs* tab, int S, const int2* gtiles, const int* ngt,
+template <int DEG>
+static void launch_batch(const TileArgs* tab, int S, const int2* gtiles, const int* ngt, int* gqueue,
+                         int grid, int fgrid, hipEvent_t ev_stop, hipStream_t s)
+{
+    k_tile_batch<DEG><<<grid, BLOCK, 0, s>>>(tab, gtiles, ngt, gqueue);
+    if (ev_stop) (void)hipEventRecord(ev_stop, s);
+    k_fallback_batch<DEG><<<fgrid, BLOCK, 0, s>>>(tab, S);
+}
+
+hipError_t run_batch_tiles(int degree, const TileArgs* tab, int S, const int2* gtiles, const int* ngt,
                            int* gqueue, int grid, int fgrid, hipEvent_t ev_stop, hipStream_t s)
 {
-    k_tile_batch<<<grid, BLOCK, 0, s>>>(tab, gtiles, ngt, gqueue);
-    if (ev_stop) (void)hipEventRecord(ev_stop, s);
-    k_fallback_batch<<<fgrid, BLOCK, 0, s>>>(tab, S);
+    switch (degree) {
+    case 0: launch_batch<0>(tab, S, gtiles, ngt, gqueue, grid, fgrid, ev_stop, s); break;
+    case 2: launch_batch<2>(tab, S, gtiles, ngt, gqueue, grid, fgrid, ev_stop, s); break;
+    default: launch_batch<1>(tab, S, gtiles, ngt, gqueue, grid, fgrid, ev_stop, s);
+    }
     return hipGetLastError();
 }
 
@@ -1727,10 +1967,11 @@ hipError_t run_adam(const Work& w, float* theta, float* m, float* v, int64_t n, 
     return hipGetLastError();
 }
 
-hipError_t run_init_params(const Work& w, const Geo& g, float* theta, const float* surf,
-                           int64_t Ns, float bandwidth, float rho0, hipStream_t s)
+hipError_t run_init_params(const Work& w, const Geo& g, const Layout& L, float* theta,
+                           const float* surf, int64_t Ns, float bandwidth, float rho0,
+                           hipStream_t s)
 {
-    k_init_params<<<grid_for(w.I), BLOCK, 0, s>>>(theta, g, surf, Ns, (double)bandwidth, rho0, w.I);
+    k_init_params<<<grid_for(w.I), BLOCK, 0, s>>>(theta, g, L, surf, Ns, (double)bandwidth, rho0, w.I);
     return hipGetLastError();
 }
 

@@ -36,7 +36,8 @@ class EfuncError(RuntimeError):
 class efunc_config(C.Structure):
     _fields_ = [("R", C.c_int32), ("lo", C.c_float), ("hi", C.c_float), ("offsets", C.c_int32),
                 ("t_cut", C.c_float), ("window", C.c_int32), ("deterministic", C.c_int32),
-                ("check_finite", C.c_int32)]
+                ("check_finite", C.c_int32), ("degree", C.c_int32), ("grid_keys", C.c_int32),
+                ("learn_scale", C.c_int32), ("rho_fixed", C.c_float)]
 
 
 class efunc_adam(C.Structure):
@@ -63,7 +64,7 @@ class efunc_stats(C.Structure):
 
 
 # every symbol declared in include/efunc.h
-EXPORTS = ["efunc_default_config", "efunc_default_adam", "efunc_create", "efunc_destroy",
+EXPORTS = ["efunc_default_config", "efunc_channels", "efunc_default_adam", "efunc_create", "efunc_destroy",
            "efunc_init_params", "efunc_eval", "efunc_grad", "efunc_fit_step", "efunc_get_stats",
            "efunc_set_timing", "efunc_read_timing", "efunc_default_tuning", "efunc_set_tuning",
            "efunc_get_tuning", "efunc_batch_create", "efunc_batch_destroy", "efunc_batch_bind",
@@ -85,6 +86,8 @@ def lib() -> C.CDLL:
         vp, i64 = C.c_void_p, C.c_int64
         L.efunc_default_config.argtypes = [C.POINTER(efunc_config), C.c_int32]
         L.efunc_default_config.restype = None
+        L.efunc_channels.argtypes = [C.POINTER(efunc_config)]
+        L.efunc_channels.restype = C.c_int
         L.efunc_default_adam.argtypes = [C.POINTER(efunc_adam)]
         L.efunc_default_adam.restype = None
         L.efunc_create.argtypes = [C.POINTER(efunc_config), i64, C.POINTER(vp)]
@@ -161,6 +164,13 @@ def efunc_default_config(R: int) -> efunc_config:
     return c
 
 
+def efunc_channels(cfg: efunc_config) -> int:
+    n = lib().efunc_channels(C.byref(cfg))
+    if n < 0:
+        _check(n)
+    return n
+
+
 def efunc_default_adam() -> efunc_adam:
     a = efunc_adam()
     lib().efunc_default_adam(C.byref(a))
@@ -177,9 +187,9 @@ def efunc_destroy(ctx) -> None:
     _check(lib().efunc_destroy(ctx))
 
 
-def efunc_init_params(ctx, theta, surf, R: int, bandwidth=100.0, rho0=7.0, stream=None):
+def efunc_init_params(ctx, theta, surf, R: int, bandwidth=100.0, rho0=7.0, stream=None, nch=NCH):
     ns = 0 if surf is None else surf.numel() // 3
-    _check(lib().efunc_init_params(ctx, _ptr(theta, torch.float32, "theta", R ** 3 * NCH),
+    _check(lib().efunc_init_params(ctx, _ptr(theta, torch.float32, "theta", R ** 3 * nch),
                                    _ptr(surf, torch.float32, "surf"), ns, bandwidth, rho0,
                                    _stream(stream)))
 
@@ -383,6 +393,7 @@ class Engine:
             setattr(c, k, v)
         self.R = R
         self.cfg = c
+        self.nch = efunc_channels(c)
         self.max_points = max_points
         self.ctx = efunc_create(c, max_points)
 
@@ -422,7 +433,7 @@ class Engine:
         efunc_fit_step(self.ctx, theta, m, v, step, q, o, loss_out, adam)
 
     def init_params(self, theta, surf, bandwidth=100.0, rho0=7.0):
-        efunc_init_params(self.ctx, theta, surf, self.R, bandwidth, rho0)
+        efunc_init_params(self.ctx, theta, surf, self.R, bandwidth, rho0, nch=self.nch)
 
     def stats(self):
         return efunc_get_stats(self.ctx)

@@ -64,13 +64,13 @@ def check_lse(lse, lse_ref, rtol=1e-5):
     assert np.all(err <= tol), f"lse: worst {np.max(err / tol)} x tolerance"
 
 
-def check_grad(g, g_ref, A, B=None, rtol=1e-4, floor=1e-6):
-    g = np.asarray(g, dtype=np.float64).reshape(-1, 13)
-    g_ref = g_ref.reshape(-1, 13)
-    A = A.reshape(-1, 13)
+def check_grad(g, g_ref, A, B=None, rtol=1e-4, floor=1e-6, nch=13):
+    g = np.asarray(g, dtype=np.float64).reshape(-1, nch)
+    g_ref = g_ref.reshape(-1, nch)
+    A = A.reshape(-1, nch)
     tol = rtol * A + floor * A.max(axis=0, keepdims=True) + 1e-30
     if B is not None:
-        tol = tol + B.reshape(-1, 13)
+        tol = tol + B.reshape(-1, nch)
     err = np.abs(g - g_ref)
     bad = err > tol
     if bad.any():

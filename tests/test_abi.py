@@ -64,3 +64,26 @@ def test_invalid_arguments_are_rejected_before_any_device_work(L):
     assert L.efunc_eval(None, None, None, 0, None, None, None, None, None) == E.EFUNC_EINVAL
     assert L.efunc_fit_step(None, None, None, None, 1, None, None, None, 0, None, None) == E.EFUNC_EINVAL
     assert L.efunc_destroy(None) == E.EFUNC_OK
+
+
+def test_channel_counts_of_paper_variants():
+    """efunc_channels (host-only) against the channel counts the paper prints
+    for its ablation variants (Tab. ablation)."""
+    import json
+    from paper_2505_21319_amd import efunc as E
+    E.lib()
+    d = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_param_counts.json")))
+    for e in d["variants"]:
+        c = E.efunc_default_config(e["R"])
+        c.degree, c.grid_keys, c.offsets, c.learn_scale = (e["degree"], e["grid_keys"],
+                                                           e["moved_keys"], e["learn_scale"])
+        assert E.efunc_channels(c) == e["channels"], e["config"]
+        assert E.efunc_channels(c) * e["R"] ** 3 == e["params"], e["config"]
+    c = E.efunc_default_config(8)
+    c.degree = 3
+    with pytest.raises(E.EfuncError):
+        E.efunc_channels(c)
+    c = E.efunc_default_config(8)
+    c.grid_keys, c.offsets = 0, 0
+    with pytest.raises(E.EfuncError):
+        E.efunc_channels(c)

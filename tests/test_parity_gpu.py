@@ -137,11 +137,14 @@ def test_eval_coarse_lattice_exact_max_path(E):
 
 
 def test_eval_grid_keys_only(E):
+    """offsets = 0 (Eq. func-interp, the ablation's G-6): theta holds only the
+    five grid channels per vertex (value, slope, scale)."""
     R = 8
     w = W.get("sphere_r8")
     q, _ = W.make_batch(w, 4, J=8192)
     th = W.perturbed_theta(R, 9)
-    O, lse, nu, _ = run_eval(E, R, th, q, offsets=0)
+    th5 = np.ascontiguousarray(th.reshape(-1, 13)[:, :5])
+    O, lse, nu, _ = run_eval(E, R, th5, q, offsets=0)
     ref = PT.reference(R, th, q, offsets=0)
     PT.check_eval(O, lse, ref)
 
