@@ -65,7 +65,7 @@ extern "C" {
 typedef struct efunc_ctx efunc_ctx;
 
 typedef struct {
-    int32_t R;             /* vertices per axis, 2 <= R <= 1024 */
+    int32_t R;             /* vertices per axis, 2 <= R <= 512 */
     float lo, hi;          /* lattice spans [lo, hi]^3, lo < hi (default -1, 1) */
     int32_t offsets;       /* 1: moved keys k_i + Delta_i present (Eq. func-offset, default);
                               0: no moved keys, theta holds no Delta / moved channels */

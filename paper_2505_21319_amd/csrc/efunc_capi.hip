@@ -244,7 +244,8 @@ int efunc_create(const efunc_config* cfg, int64_t max_points, efunc_ctx** out)
     if (!out) return fail(EFUNC_EINVAL, "out is NULL");
     *out = nullptr;
     if (!cfg) return fail(EFUNC_EINVAL, "cfg is NULL");
-    if (cfg->R < 2 || cfg->R > 1024) return fail(EFUNC_EINVAL, "R = %d outside [2, 1024]", cfg->R);
+    // every cell and sub-counter index must fit in int32: 8 NB^3 PSPLIT < 2^31
+    if (cfg->R < 2 || cfg->R > 512) return fail(EFUNC_EINVAL, "R = %d outside [2, 512]", cfg->R);
     if (!(cfg->lo < cfg->hi) || !isfinite(cfg->lo) || !isfinite(cfg->hi))
         return fail(EFUNC_EINVAL, "lattice bounds must satisfy lo < hi, finite");
     if (cfg->offsets != 0 && cfg->offsets != 1) return fail(EFUNC_EINVAL, "offsets must be 0 or 1");

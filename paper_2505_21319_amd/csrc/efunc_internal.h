@@ -14,7 +14,7 @@ constexpr int KC = 256;         // keys per LDS chunk
 constexpr int MAXSEG = 1024;    // moved-key row segments per window ((2W+1)^2, W <= 15)
 constexpr int WMAX = 15;        // largest window half-width
 constexpr int SCAN_TILE = 1024; // elements per block in the prefix scans
-constexpr int PSPLIT = 4;       // sub-counters per cell in the query histogram
+constexpr int PSPLIT = 8;       // sub-counters per cell in the query histogram
 constexpr int SLICE_KEYS = 8;   // slice-index sort keys per cost bucket in the tile order
 constexpr float LOG2E = 1.4426950408889634f;
 constexpr float LN2 = 0.6931471805599453f;

@@ -54,6 +54,9 @@ def test_invalid_arguments_are_rejected_before_any_device_work(L):
     c = E.efunc_default_config(1)
     assert L.efunc_create(C.byref(c), 10, C.byref(out)) == E.EFUNC_EINVAL
     assert b"R = 1" in L.efunc_last_error()
+    c = E.efunc_default_config(513)
+    assert L.efunc_create(C.byref(c), 10, C.byref(out)) == E.EFUNC_EINVAL
+    assert b"R = 513" in L.efunc_last_error()
     c = E.efunc_default_config(8)
     c.lo, c.hi = 1.0, -1.0
     assert L.efunc_create(C.byref(c), 10, C.byref(out)) == E.EFUNC_EINVAL
