@@ -269,6 +269,62 @@ int efunc_batch_get_stats(efunc_batch* b, int32_t shape, efunc_stats* out);
 int efunc_batch_set_timing(efunc_batch* b, int32_t enable);
 int efunc_batch_read_timing(efunc_batch* b, double* tile_ms, int64_t* launches);
 
+/* ------------------------------------------------------------------------
+ * Learned initialiser.  The paper fits every shape from a fixed
+ * initialisation (Sec. 3.3, Sec. 4.3) and names learned / generative
+ * initialisation as future work (Sec. 5).  This network maps a coarse signed
+ * distance field sampled at the R^3 lattice vertices to an R^3 x C_L tensor
+ * (the parameter tensor, C_L = 13): n_layers 3x3x3 convolutions (zero
+ * padding, stride 1) with ReLU between layers, on the matrix cores (bf16
+ * operands, fp32 accumulation).
+ *
+ * Parameters (caller-owned fp32, DEVICE): for each layer l, W_l[co][tap][ci]
+ * (tap = (dz*3 + dy)*3 + dx over offsets -1..1) then b_l[co], concatenated.
+ * Activations are channels-last [B][R][R][R][C] and rounded to bf16 between
+ * layers; the backward rounds the incoming gradient of each layer to bf16.
+ * ------------------------------------------------------------------------ */
+typedef struct efunc_initnet efunc_initnet;
+
+/* channels: host array of n_layers + 1 counts, each in [1, 64], channels[0] = 1.
+ * Allocates the activations of up to max_shapes shapes per call. */
+int efunc_initnet_create(int32_t R, int32_t max_shapes, int32_t n_layers, const int32_t* channels,
+                         efunc_initnet** out);
+int efunc_initnet_destroy(efunc_initnet* net);
+/* Length of the flat parameter vector (EFUNC_EINVAL for NULL). */
+int64_t efunc_initnet_num_params(const efunc_initnet* net);
+/* out [B][R^3][C_L] fp32 = net(sdf [B][R^3] fp32); keeps the activations for
+ * the backward.  Errors: EFUNC_EINVAL, EFUNC_ESIZE (B > max_shapes), EFUNC_EHIP. */
+int efunc_initnet_forward(efunc_initnet* net, const float* params, const float* sdf, int32_t B,
+                          float* out, void* stream);
+/* dparams += dL/dparams for dL/dout (dout [B][R^3][C_L] fp32) of the last
+ * forward (same B, same params).  Errors: EFUNC_EINVAL, EFUNC_EHIP. */
+int efunc_initnet_backward(efunc_initnet* net, const float* dout, int32_t B, float* dparams,
+                           void* stream);
+
+/* The layer operations (bf16 buffers are uint16 bit patterns, DEVICE).
+ * efunc_conv3d_bf16: y[v][co] = sum_{tap,ci} x[nbr(v,tap)][ci] w[co][tap Cin + ci]
+ * (+ bias[co]) then ReLU when relu = 1, or times (mask[v][co] > 0) when mask
+ * is given; w packed [Cout][Kpad], Kpad a multiple of 32 >= 27 Cin, zero
+ * padded; V = B R^3 voxels; writes y_bf16 and/or y_f32 [V][Cout].  x and w
+ * 16-byte aligned.  efunc_conv3d_wgrad_bf16: dw[co][tap][ci] += sum_v
+ * dy[v][co] x[nbr(v,tap)][ci] and db[co] += sum_v dy[v][co] (db optional).
+ * efunc_conv3d_pack_weights: the forward packing wf [Cout][kpad(27 Cin)] and
+ * the data-gradient packing wd [Cin][kpad(27 Cout)] (flipped taps, so that the
+ * data gradient is efunc_conv3d_bf16 of dy with wd) of fp32 W[co][tap][ci]. */
+int efunc_conv3d_bf16(const void* x, int32_t Cin, const void* w, int32_t Kpad, int32_t Cout,
+                      const float* bias, int32_t relu, const void* mask, int32_t R, int64_t V,
+                      void* y_bf16, float* y_f32, void* stream);
+int efunc_conv3d_wgrad_bf16(const void* x, int32_t Cin, const void* dy, int32_t Cout, int32_t R,
+                            int64_t V, float* dw, float* db, void* stream);
+int efunc_conv3d_pack_weights(const float* W, int32_t Cin, int32_t Cout, void* wf, void* wd,
+                              void* stream);
+
+/* AdamW step on any fp32 parameter vector p [n] with moments m, v and
+ * gradient g (zeroed afterwards), step >= 1 (bias correction), adam host
+ * pointer (NULL = defaults). */
+int efunc_adam_update(float* p, float* m, float* v, float* g, int64_t n, int64_t step,
+                      const efunc_adam* adam, void* stream);
+
 /* Thread-local message of the last failing call on this thread ("" if none).
  * The pointer stays valid until the next call on the same thread. */
 const char* efunc_last_error(void);

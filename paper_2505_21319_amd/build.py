@@ -9,7 +9,8 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libefunc.so")
 SOURCES = [os.path.join(HERE, "csrc", "efunc_kernels.hip"),
            os.path.join(HERE, "csrc", "efunc_capi.hip"),
-           os.path.join(HERE, "csrc", "efunc_batch.hip")]
+           os.path.join(HERE, "csrc", "efunc_batch.hip"),
+           os.path.join(HERE, "csrc", "initnet.hip")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

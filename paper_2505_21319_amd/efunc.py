@@ -70,7 +70,10 @@ EXPORTS = ["efunc_default_config", "efunc_channels", "efunc_default_adam", "efun
            "efunc_get_tuning", "efunc_batch_create", "efunc_batch_destroy", "efunc_batch_bind",
            "efunc_batch_fit", "efunc_batch_set_tuning", "efunc_batch_get_tuning",
            "efunc_batch_autotune", "efunc_batch_get_stats", "efunc_batch_set_timing",
-           "efunc_batch_read_timing", "efunc_last_error"]
+           "efunc_batch_read_timing", "efunc_initnet_create", "efunc_initnet_destroy",
+           "efunc_initnet_num_params", "efunc_initnet_forward", "efunc_initnet_backward",
+           "efunc_conv3d_bf16", "efunc_conv3d_wgrad_bf16", "efunc_conv3d_pack_weights",
+           "efunc_adam_update", "efunc_last_error"]
 
 _lib = None
 
@@ -115,6 +118,17 @@ def lib() -> C.CDLL:
         L.efunc_batch_get_stats.argtypes = [vp, C.c_int32, C.POINTER(efunc_stats)]
         L.efunc_batch_set_timing.argtypes = [vp, C.c_int32]
         L.efunc_batch_read_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        i32 = C.c_int32
+        L.efunc_initnet_create.argtypes = [i32, i32, i32, C.POINTER(i32), pp]
+        L.efunc_initnet_destroy.argtypes = [vp]
+        L.efunc_initnet_num_params.argtypes = [vp]
+        L.efunc_initnet_num_params.restype = i64
+        L.efunc_initnet_forward.argtypes = [vp, vp, vp, i32, vp, vp]
+        L.efunc_initnet_backward.argtypes = [vp, vp, i32, vp, vp]
+        L.efunc_conv3d_bf16.argtypes = [vp, i32, vp, i32, i32, vp, i32, vp, i32, i64, vp, vp, vp]
+        L.efunc_conv3d_wgrad_bf16.argtypes = [vp, i32, vp, i32, i32, i64, vp, vp, vp]
+        L.efunc_conv3d_pack_weights.argtypes = [vp, i32, i32, vp, vp, vp]
+        L.efunc_adam_update.argtypes = [vp, vp, vp, vp, i64, i64, C.POINTER(efunc_adam), vp]
         L.efunc_last_error.argtypes = []
         L.efunc_last_error.restype = C.c_char_p
         for name in ("efunc_create", "efunc_destroy", "efunc_init_params", "efunc_eval",
@@ -123,7 +137,9 @@ def lib() -> C.CDLL:
                      "efunc_batch_create", "efunc_batch_destroy", "efunc_batch_bind",
                      "efunc_batch_fit", "efunc_batch_set_tuning", "efunc_batch_get_tuning",
                      "efunc_batch_autotune", "efunc_batch_get_stats", "efunc_batch_set_timing",
-                     "efunc_batch_read_timing"):
+                     "efunc_batch_read_timing", "efunc_initnet_create", "efunc_initnet_destroy",
+                     "efunc_initnet_forward", "efunc_initnet_backward", "efunc_conv3d_bf16",
+                     "efunc_conv3d_wgrad_bf16", "efunc_conv3d_pack_weights", "efunc_adam_update"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -382,6 +398,90 @@ class BatchEngine:
 
     def stats(self, shape):
         return efunc_batch_get_stats(self.b, shape)
+
+
+def kpad(k: int) -> int:
+    return (k + 31) // 32 * 32
+
+
+def efunc_conv3d_pack_weights(W, Cin: int, Cout: int, stream=None):
+    """(wf [Cout][kpad(27 Cin)], wd [Cin][kpad(27 Cout)]) bf16 packings of fp32 W[co][tap][ci]."""
+    wf = torch.empty(Cout, kpad(27 * Cin), device=W.device, dtype=torch.bfloat16)
+    wd = torch.empty(Cin, kpad(27 * Cout), device=W.device, dtype=torch.bfloat16)
+    _check(lib().efunc_conv3d_pack_weights(_ptr(W, torch.float32, "W", Cout * 27 * Cin), Cin, Cout,
+                                           wf.data_ptr(), wd.data_ptr(), _stream(stream)))
+    return wf, wd
+
+
+def efunc_conv3d_bf16(x, Cin: int, w, Cout: int, R: int, bias=None, relu=False, mask=None,
+                      y_bf16=None, y_f32=None, stream=None):
+    V = x.numel() // Cin
+    _check(lib().efunc_conv3d_bf16(_ptr(x, torch.bfloat16, "x", V * Cin), Cin,
+                                   _ptr(w, torch.bfloat16, "w", Cout * w.shape[1]), w.shape[1], Cout,
+                                   _ptr(bias, torch.float32, "bias", Cout), 1 if relu else 0,
+                                   _ptr(mask, torch.bfloat16, "mask", V * Cout), R, V,
+                                   _ptr(y_bf16, torch.bfloat16, "y_bf16", V * Cout),
+                                   _ptr(y_f32, torch.float32, "y_f32", V * Cout), _stream(stream)))
+
+
+def efunc_conv3d_wgrad_bf16(x, Cin: int, dy, Cout: int, R: int, dw, db=None, stream=None):
+    V = x.numel() // Cin
+    _check(lib().efunc_conv3d_wgrad_bf16(_ptr(x, torch.bfloat16, "x", V * Cin), Cin,
+                                         _ptr(dy, torch.bfloat16, "dy", V * Cout), Cout, R, V,
+                                         _ptr(dw, torch.float32, "dw", Cout * 27 * Cin),
+                                         _ptr(db, torch.float32, "db", Cout), _stream(stream)))
+
+
+def efunc_adam_update(p, m, v, g, step: int, adam: Optional[efunc_adam] = None, stream=None):
+    n = p.numel()
+    _check(lib().efunc_adam_update(_ptr(p, torch.float32, "p", n), _ptr(m, torch.float32, "m", n),
+                                   _ptr(v, torch.float32, "v", n), _ptr(g, torch.float32, "g", n), n,
+                                   step, C.byref(adam) if adam is not None else None, _stream(stream)))
+
+
+class InitNet:
+    """The learned-initialiser network (efunc_initnet_*): sdf [B][R^3] -> [B][R^3][C_L]."""
+
+    def __init__(self, R: int, max_shapes: int, channels):
+        self.R, self.channels = R, list(channels)
+        arr = (C.c_int32 * len(channels))(*channels)
+        out = C.c_void_p()
+        _check(lib().efunc_initnet_create(R, max_shapes, len(channels) - 1, arr, C.byref(out)))
+        self.net = out
+        self.n_params = int(lib().efunc_initnet_num_params(out))
+
+    def close(self):
+        if self.net:
+            _check(lib().efunc_initnet_destroy(self.net))
+            self.net = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+    def forward(self, params, sdf, out=None):
+        B = sdf.numel() // self.R ** 3
+        if out is None:
+            out = torch.empty(B, self.R ** 3, self.channels[-1], device=sdf.device, dtype=torch.float32)
+        _check(lib().efunc_initnet_forward(self.net, _ptr(params, torch.float32, "params", self.n_params),
+                                           _ptr(sdf, torch.float32, "sdf", B * self.R ** 3), B,
+                                           _ptr(out, torch.float32, "out", B * self.R ** 3 * self.channels[-1]),
+                                           _stream(None)))
+        return out
+
+    def backward(self, dout, dparams):
+        B = dout.numel() // (self.R ** 3 * self.channels[-1])
+        _check(lib().efunc_initnet_backward(self.net, _ptr(dout, torch.float32, "dout", dout.numel()), B,
+                                            _ptr(dparams, torch.float32, "dparams", self.n_params),
+                                            _stream(None)))
 
 
 class Engine:

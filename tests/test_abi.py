@@ -13,7 +13,7 @@ HDR = os.path.join(ROOT, "include", "efunc.h")
 def declared():
     src = open(HDR).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(efunc_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(efunc_[a-z0-9_]+)\s*\(", src)))
 
 
 @pytest.fixture(scope="module")

@@ -1,0 +1,173 @@
+"""GPU parity of the learned-initialiser network (bf16 MFMA convolutions)
+against the FP64 oracle oracle/initnet.py: every layer operation on its own
+(forward with bias and ReLU, data gradient with the ReLU mask, weight and
+bias gradients), the whole network forward and backward, and a short
+training run whose loss must fall.
+
+Tolerance: products of bf16 values are exact in fp32; the fp32 sum of K
+terms is within gamma_K = K 2^-24 / (1 - K 2^-24) of sum |terms|, plus half
+an ulp of the result."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import initnet as N
+from tests import parity as PT
+
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def E():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2505_21319_amd import efunc
+    efunc.lib()
+    return efunc
+
+
+def bf16_tensor(a):
+    return torch.from_numpy(np.asarray(a, dtype=np.float32)).to(PT.DEV).to(torch.bfloat16).contiguous()
+
+
+def gamma(K):
+    return K * U / (1 - K * U)
+
+
+def conv_abs(x, w):
+    return N._conv(np.abs(N.bf16_round(x)), np.abs(N.bf16_round(w)))
+
+
+@pytest.mark.parametrize("Cin,Cout,R,B", [(1, 32, 6, 2), (32, 64, 5, 3), (64, 13, 4, 2), (13, 64, 4, 1),
+                                           (8, 16, 7, 1)])
+def test_conv_forward_matches_oracle(E, Cin, Cout, R, B):
+    rng = np.random.default_rng(Cin * 100 + Cout)
+    x = N.bf16_round(rng.standard_normal((B, R, R, R, Cin)))
+    W = rng.standard_normal((Cout, 27, Cin)) / np.sqrt(27 * Cin)
+    b = rng.standard_normal(Cout)
+    wf, _ = E.efunc_conv3d_pack_weights(PT.to_dev(W.reshape(-1)), Cin, Cout)
+    V = B * R ** 3
+    yf = torch.empty(V * Cout, device=PT.DEV)
+    ybf = torch.empty(V * Cout, device=PT.DEV, dtype=torch.bfloat16)
+    E.efunc_conv3d_bf16(bf16_tensor(x), Cin, wf, Cout, R, bias=PT.to_dev(b.astype(np.float32)), relu=True,
+                        y_bf16=ybf, y_f32=yf)
+    torch.cuda.synchronize()
+    z, a = N.layer_forward(x, W, b.astype(np.float32).astype(np.float64), relu=True)
+    got = yf.cpu().numpy().astype(np.float64).reshape(a.shape)
+    tol = gamma(27 * Cin) * (conv_abs(x, W) + np.abs(b)) + U * np.abs(a) + 1e-30
+    assert np.all(np.abs(got - a) <= tol), np.max(np.abs(got - a) / tol)
+    # the bf16 output is the round-to-nearest-even of the fp32 output
+    assert np.array_equal(ybf.float().cpu().numpy().reshape(a.shape), N.bf16_round(got))
+
+
+@pytest.mark.parametrize("Cin,Cout,R", [(32, 64, 5), (64, 13, 4), (1, 32, 4)])
+def test_conv_data_gradient_matches_oracle(E, Cin, Cout, R):
+    """dL/dx through the flipped packing, masked by the input activation > 0."""
+    rng = np.random.default_rng(7 + Cin)
+    B = 2
+    x = N.bf16_round(np.maximum(rng.standard_normal((B, R, R, R, Cin)), 0))  # a ReLU output: mask
+    W = rng.standard_normal((Cout, 27, Cin)) / np.sqrt(27 * Cin)
+    dz = N.bf16_round(rng.standard_normal((B, R, R, R, Cout)))
+    _, wd = E.efunc_conv3d_pack_weights(PT.to_dev(W.reshape(-1)), Cin, Cout)
+    V = B * R ** 3
+    dx = torch.empty(V * Cin, device=PT.DEV)
+    E.efunc_conv3d_bf16(bf16_tensor(dz), Cout, wd, Cin, R, mask=bf16_tensor(x), y_f32=dx)
+    torch.cuda.synchronize()
+    _, _, dx_ref = N.layer_backward(x, W, dz)
+    dx_ref = dx_ref * (x > 0)
+    absref = np.abs(N.layer_backward(np.abs(x), np.abs(W), np.abs(dz))[2])
+    got = dx.cpu().numpy().astype(np.float64).reshape(dx_ref.shape)
+    tol = gamma(27 * Cout) * absref + U * np.abs(dx_ref) + 1e-30
+    assert np.all(np.abs(got - dx_ref) <= tol), np.max(np.abs(got - dx_ref) / tol)
+
+
+@pytest.mark.parametrize("Cin,Cout,R,B", [(1, 32, 6, 2), (32, 64, 5, 2), (64, 13, 4, 3), (13, 16, 3, 1)])
+def test_conv_weight_gradient_matches_oracle(E, Cin, Cout, R, B):
+    rng = np.random.default_rng(11 + Cout)
+    x = N.bf16_round(rng.standard_normal((B, R, R, R, Cin)))
+    dz = N.bf16_round(rng.standard_normal((B, R, R, R, Cout)))
+    W = rng.standard_normal((Cout, 27, Cin))
+    V = B * R ** 3
+    dw = torch.zeros(Cout * 27 * Cin, device=PT.DEV)
+    db = torch.zeros(Cout, device=PT.DEV)
+    E.efunc_conv3d_wgrad_bf16(bf16_tensor(x), Cin, bf16_tensor(dz), Cout, R, dw, db)
+    torch.cuda.synchronize()
+    dW_ref, db_ref, _ = N.layer_backward(x, W, dz)
+    dW_abs, db_abs, _ = N.layer_backward(np.abs(x), W, np.abs(dz))
+    got = dw.cpu().numpy().astype(np.float64).reshape(dW_ref.shape)
+    tol = gamma(V) * np.abs(dW_abs) + U * np.abs(dW_ref) + 1e-30
+    assert np.all(np.abs(got - dW_ref) <= tol), np.max(np.abs(got - dW_ref) / tol)
+    gb = db.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(gb - db_ref) <= gamma(V) * db_abs + 1e-30)
+
+
+def test_network_forward_backward_against_oracle_layers(E):
+    """The whole 4-layer network: the output and the parameter gradient
+    against the oracle evaluated layer by layer on the same bf16 inputs (the
+    GPU's rounding of intermediate activations to bf16 is reproduced by the
+    oracle; fp32 accumulation may flip a rounding, so the comparison allows
+    a few bf16 ulps of the output scale)."""
+    R, B = 6, 2
+    ch = [1, 16, 32, 16, 13]
+    rng = np.random.default_rng(21)
+    params = np.concatenate([np.concatenate([rng.standard_normal(co * 27 * ci) / np.sqrt(27 * ci),
+                                             0.1 * rng.standard_normal(co)])
+                             for ci, co in zip(ch[:-1], ch[1:])]).astype(np.float32)
+    sdf = rng.uniform(-1, 1, (B, R, R, R)).astype(np.float32)
+    dout = rng.standard_normal((B, R, R, R, ch[-1])).astype(np.float32)
+    with E.InitNet(R, B, ch) as net:
+        assert net.n_params == N.num_params(ch) == params.size
+        P = PT.to_dev(params)
+        out = net.forward(P, PT.to_dev(sdf))
+        dp = torch.zeros(net.n_params, device=PT.DEV)
+        net.backward(PT.to_dev(dout), dp)
+        torch.cuda.synchronize()
+        out, dp = out.cpu().numpy().astype(np.float64), dp.cpu().numpy().astype(np.float64)
+    ref, _ = N.forward(params.astype(np.float64), ch, sdf[..., None].astype(np.float64))
+    scale = np.abs(ref).max()
+    assert np.abs(out.reshape(ref.shape) - ref).max() <= 4 * 2.0 ** -8 * scale
+    g_ref = N.backward(params.astype(np.float64), ch, sdf[..., None].astype(np.float64), dout.astype(np.float64))
+    gs = np.abs(g_ref).max()
+    assert np.abs(dp - g_ref).max() <= 0.05 * gs, np.abs(dp - g_ref).max() / gs
+    assert np.corrcoef(dp, g_ref)[0, 1] > 0.999
+
+
+def test_adam_update_matches_oracle(E):
+    import oracle as orc
+    rng = np.random.default_rng(31)
+    n = 1000
+    p = rng.standard_normal(n).astype(np.float32)
+    g = rng.standard_normal(n).astype(np.float32)
+    P, M, Vv, G = PT.to_dev(p), torch.zeros(n, device=PT.DEV), torch.zeros(n, device=PT.DEV), PT.to_dev(g)
+    E.efunc_adam_update(P, M, Vv, G, 1)
+    torch.cuda.synchronize()
+    ref, _, _ = orc.adam(p.astype(np.float64), np.zeros(n), np.zeros(n), g.astype(np.float64), 1)
+    assert np.all(np.abs(P.cpu().numpy() - ref) <= 4 * PT.ulp32(ref) + 1e-6 * 6e-4)
+    assert not G.any()
+
+
+def test_training_reduces_a_regression_loss(E):
+    """Fifty AdamW steps of the network on a fixed regression target lower
+    the loss (the backward and the update wire together)."""
+    R, B = 6, 2
+    ch = [1, 16, 16, 3]
+    rng = np.random.default_rng(41)
+    params = np.concatenate([np.concatenate([rng.standard_normal(co * 27 * ci) / np.sqrt(27 * ci),
+                                             np.zeros(co)]) for ci, co in zip(ch[:-1], ch[1:])])
+    sdf = rng.uniform(-1, 1, (B, R, R, R)).astype(np.float32)
+    tgt = np.stack([sdf, sdf ** 2, np.roll(sdf, 1, axis=1)], axis=-1).reshape(B, R ** 3, 3)
+    with E.InitNet(R, B, ch) as net:
+        P = PT.to_dev(params.astype(np.float32))
+        M, Vv, G = (torch.zeros_like(P) for _ in range(3))
+        S, T = PT.to_dev(sdf), PT.to_dev(tgt)
+        adam = E.efunc_default_adam()
+        adam.lr = 3e-3
+        losses = []
+        for step in range(1, 51):
+            out = net.forward(P, S)
+            d = out - T
+            losses.append(float((d * d).mean()))
+            net.backward((2.0 / d.numel()) * d, G)
+            E.efunc_adam_update(P, M, Vv, G, step, adam)
+        torch.cuda.synchronize()
+    assert losses[-1] < 0.5 * losses[0], losses[::10]
