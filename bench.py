@@ -330,6 +330,121 @@ def bench_batch(args, torch):
     print(json.dumps(out))
 
 
+def bench_initnet(args, torch):
+    """Learned initialiser: the matrix-core throughput of the network
+    (forward + backward over a batch of 8 shapes on the 32^3 lattice) and
+    the fitting experiment (train on synthetic shapes, fit held-out shapes
+    from three initialisations)."""
+    import workloads as W
+    from paper_2505_21319_amd import efunc as E
+    from paper_2505_21319_amd import initnet_train as T
+
+    dev = torch.device("cuda:0")
+    R = 32
+    log = lambda m: print("# " + m, file=sys.stderr, flush=True)  # noqa: E731
+    n_train, n_test = args.initnet_train, args.initnet_test
+    ws = W.batch_set("initnet", n_train + n_test, 400, R_range=(R, R), J_range=(1 << 16, 1 << 16),
+                     prims_range=(8, 24))
+    t_gen = time.perf_counter()
+    data = []
+    for i, w in enumerate(ws):
+        q, o = W.make_batch(w, 0, device=dev)
+        sdf = T.coarse_sdf(lambda g, w=w: W.target(w, g), R, dev)
+        data.append((sdf, torch.from_numpy(q).to(dev), torch.from_numpy(o).to(dev), w))
+        if (i + 1) % 64 == 0:
+            log(f"generated {i + 1}/{len(ws)} shapes")
+    t_gen = time.perf_counter() - t_gen
+    train_set = [(d[0], d[1], d[2]) for d in data[:n_train]]
+    test = data[n_train:]
+
+    net = E.InitNet(R, 8, T.CHANNELS)
+    params = torch.from_numpy(T.initial_params(1)).to(dev)
+    # matrix-core throughput: forward + backward of 8 shapes, HIP events on the stream
+    sdf8 = torch.stack([d[0] for d in data[:8]])
+    dout = torch.randn(8, R ** 3, T.CHANNELS[-1], device=dev)
+    g = torch.zeros_like(params)
+    for _ in range(3):
+        net.forward(params, sdf8)
+        net.backward(dout, g)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    reps = 20
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for _ in range(reps):
+        net.forward(params, sdf8)
+    ev[1].record(stream)
+    for _ in range(reps):
+        net.backward(dout, g)
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    fwd_ms = ev[0].elapsed_time(ev[1]) / reps
+    bwd_ms = ev[1].elapsed_time(ev[2]) / reps
+    conv_flop = sum(2 * 8 * R ** 3 * 27 * ci * co for ci, co in zip(T.CHANNELS[:-1], T.CHANNELS[1:]))
+    # backward: weight gradient for every layer, data gradient for all but the first
+    bwd_flop = conv_flop + sum(2 * 8 * R ** 3 * 27 * ci * co
+                               for ci, co in list(zip(T.CHANNELS[:-1], T.CHANNELS[1:]))[1:])
+
+    # train end to end, then fit held-out shapes from three initialisations
+    t_train = time.perf_counter()
+    params = torch.from_numpy(T.initial_params(1)).to(dev)
+    losses = T.train(net, params, train_set, args.initnet_steps, 8, 1e-3, 2, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t_train
+    inits = {"paper": [], "sdf": [], "learned": []}
+    t_init = {"paper": 0.0, "sdf": 0.0, "learned": 0.0}
+    for sdf, q, o, w in test:
+        surf = torch.from_numpy(W.surface_points(w, 16384, seed=W.seed_for(w, -2, "meanshift"),
+                                                 device=dev).astype(np.float32)).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        inits["paper"].append(T.paper_theta(R, surf, dev))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        inits["sdf"].append(T.sdf_theta(R, sdf, surf, dev))
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        inits["learned"].append(net.forward(params, sdf[None]).reshape(-1).clone())
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        t_init["paper"] += t1 - t0
+        t_init["sdf"] += t2 - t1
+        t_init["learned"] += t3 - t2
+    qs, os_ = [d[1] for d in test], [d[2] for d in test]
+    results = {}
+    for name, ths in inits.items():
+        curve, secs = T.fit_curves([R] * len(test), ths, qs, os_, args.initnet_fit_steps, 50)
+        reach = T.steps_to(curve, 1e-3)
+        ok = [s for s in reach if s is not None]
+        results[name] = {
+            "mean_l1": {str(st): float(np.mean(l1)) for st, l1 in curve if st in (0, 100, 250, 500, 1000, 2000, args.initnet_fit_steps)},
+            "reached_l1_1e-3": len(ok),
+            "median_steps_to_l1_1e-3": float(np.median(ok)) if ok else None,
+            "fit_seconds": secs,
+            "init_seconds_per_shape": t_init[name] / len(test),
+        }
+        log(f"{name}: {results[name]}")
+    net.close()
+    out = {
+        "metric": "learned-initialiser network fwd+bwd throughput (bf16 MFMA conv3d)",
+        "value": (conv_flop + bwd_flop) / ((fwd_ms + bwd_ms) * 1e-3) / 1e12,
+        "unit": "TFLOP/s",
+        "n_gpus": 1, "steps": reps, "warmup": 3, "ms_per_step": fwd_ms + bwd_ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16 x bf16 -> f32",
+        "data": "synthetic",
+        "config": {"workload": "initnet", "R": R, "channels": T.CHANNELS, "batch": 8,
+                   "train_shapes": n_train, "test_shapes": n_test, "train_steps": args.initnet_steps,
+                   "fit_steps": args.initnet_fit_steps, "points_per_shape": 1 << 16},
+        "roofline": {"bound": "mfma", "achieved": (conv_flop + bwd_flop) / ((fwd_ms + bwd_ms) * 1e-3) / 1e12,
+                     "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": (conv_flop + bwd_flop) / ((fwd_ms + bwd_ms) * 1e-3) / 2.5e15, "traffic": None,
+                     "fwd_ms": fwd_ms, "bwd_ms": bwd_ms, "fwd_flop": conv_flop, "bwd_flop": bwd_flop},
+        "experiment": {"train_loss": losses, "train_seconds": t_train, "gen_seconds": t_gen,
+                       "inits": results},
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -345,6 +460,10 @@ def main():
                     help="batch64: run the autotuner before timing")
     ap.add_argument("--tuning", default="",
                     help="tile_cap,group_cells,blocks_per_cu for the tile kernel (default 512,1,8)")
+    ap.add_argument("--initnet-train", type=int, default=256, help="initnet: training shapes")
+    ap.add_argument("--initnet-test", type=int, default=64, help="initnet: held-out shapes")
+    ap.add_argument("--initnet-steps", type=int, default=600, help="initnet: network training steps")
+    ap.add_argument("--initnet-fit-steps", type=int, default=2000, help="initnet: fit steps per init")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -371,6 +490,9 @@ def main():
 
     if args.workload == "batch64":
         bench_batch(args, torch)
+        return
+    if args.workload == "initnet":
+        bench_initnet(args, torch)
         return
 
     import workloads as W

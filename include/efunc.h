@@ -177,6 +177,15 @@ int efunc_fit_step(efunc_ctx* ctx, float* theta, float* m, float* v, int64_t ste
                    const efunc_adam* adam, const float* q, const float* o, int64_t J,
                    double* loss_out, void* stream);
 
+/* The loss and its gradient without an optimiser step (for training loops
+ * that own the parameters, e.g. the learned initialiser): forward, MSE of
+ * Eq. loss on (q [J][3], o [J]), dL/dO = 2 (O - o) / J and the backward of
+ * efunc_fit_step, ACCUMULATED into grad [R^3 x NCH] (grad += dL/dtheta).
+ * loss_out (DEVICE double[2], optional) = {mean (O - o)^2, mean |O - o|}.
+ * Errors: EFUNC_EINVAL, EFUNC_ESIZE, EFUNC_ENONFINITE, EFUNC_EHIP. */
+int efunc_loss_grad(efunc_ctx* ctx, const float* theta, const float* q, const float* o, int64_t J,
+                    float* grad, double* loss_out, void* stream);
+
 /* Copy the statistics of the last call into *out (host).  Synchronises the
  * stream of that call.  Errors: EFUNC_EINVAL, EFUNC_EHIP. */
 int efunc_get_stats(efunc_ctx* ctx, efunc_stats* out);

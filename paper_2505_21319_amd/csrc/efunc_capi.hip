@@ -509,6 +509,32 @@ int efunc_get_tuning(efunc_ctx* ctx, efunc_tuning* t)
     return EFUNC_OK;
 }
 
+int efunc_loss_grad(efunc_ctx* ctx, const float* theta, const float* q, const float* o, int64_t J,
+                    float* grad, double* loss_out, void* stream)
+{
+    g_err.clear();
+    int rc;
+    if ((rc = check_ctx(ctx))) return rc;
+    if ((rc = check_J(ctx, J))) return rc;
+    if ((rc = check_opt(loss_out, "loss_out", 8))) return rc;
+    if (J == 0) return EFUNC_OK;
+    if ((rc = check_ptr(theta, "theta", 4)) || (rc = check_ptr(q, "q", 4)) || (rc = check_ptr(o, "o", 4)) ||
+        (rc = check_ptr(grad, "grad", 4)))
+        return rc;
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last_stream = s;
+    Problem p = base_problem(ctx);
+    p.J = J;
+    p.theta = theta;
+    p.q = q;
+    p.aux = o;
+    p.grad = grad;
+    hipError_t e = run_tiles(ctx->w, p, MODE_FIT, s);
+    if (e == hipSuccess && loss_out) e = run_loss_finalize(ctx->w, J, loss_out, s);
+    if (e != hipSuccess) return hip_fail(e, "loss_grad launch");
+    return finite_check(ctx, s, q, J);
+}
+
 int efunc_get_stats(efunc_ctx* ctx, efunc_stats* out)
 {
     g_err.clear();

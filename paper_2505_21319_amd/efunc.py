@@ -73,7 +73,7 @@ EXPORTS = ["efunc_default_config", "efunc_channels", "efunc_default_adam", "efun
            "efunc_batch_read_timing", "efunc_initnet_create", "efunc_initnet_destroy",
            "efunc_initnet_num_params", "efunc_initnet_forward", "efunc_initnet_backward",
            "efunc_conv3d_bf16", "efunc_conv3d_wgrad_bf16", "efunc_conv3d_pack_weights",
-           "efunc_adam_update", "efunc_last_error"]
+           "efunc_adam_update", "efunc_loss_grad", "efunc_last_error"]
 
 _lib = None
 
@@ -129,6 +129,7 @@ def lib() -> C.CDLL:
         L.efunc_conv3d_wgrad_bf16.argtypes = [vp, i32, vp, i32, i32, i64, vp, vp, vp]
         L.efunc_conv3d_pack_weights.argtypes = [vp, i32, i32, vp, vp, vp]
         L.efunc_adam_update.argtypes = [vp, vp, vp, vp, i64, i64, C.POINTER(efunc_adam), vp]
+        L.efunc_loss_grad.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp]
         L.efunc_last_error.argtypes = []
         L.efunc_last_error.restype = C.c_char_p
         for name in ("efunc_create", "efunc_destroy", "efunc_init_params", "efunc_eval",
@@ -139,7 +140,8 @@ def lib() -> C.CDLL:
                      "efunc_batch_autotune", "efunc_batch_get_stats", "efunc_batch_set_timing",
                      "efunc_batch_read_timing", "efunc_initnet_create", "efunc_initnet_destroy",
                      "efunc_initnet_forward", "efunc_initnet_backward", "efunc_conv3d_bf16",
-                     "efunc_conv3d_wgrad_bf16", "efunc_conv3d_pack_weights", "efunc_adam_update"):
+                     "efunc_conv3d_wgrad_bf16", "efunc_conv3d_pack_weights", "efunc_adam_update",
+                     "efunc_loss_grad"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -238,6 +240,14 @@ def efunc_fit_step(ctx, theta, m, v, step: int, q, o, loss_out=None, adam: Optio
                                 step, C.byref(adam) if adam is not None else None,
                                 _ptr(q, torch.float32, "q", 3 * J), _ptr(o, torch.float32, "o", J),
                                 J, _ptr(loss_out, torch.float64, "loss_out", 2), _stream(stream)))
+
+
+def efunc_loss_grad(ctx, theta, q, o, grad, loss_out=None, stream=None):
+    J = q.numel() // 3
+    _check(lib().efunc_loss_grad(ctx, _ptr(theta, torch.float32, "theta"), _ptr(q, torch.float32, "q", 3 * J),
+                                 _ptr(o, torch.float32, "o", J), J,
+                                 _ptr(grad, torch.float32, "grad", theta.numel()),
+                                 _ptr(loss_out, torch.float64, "loss_out", 2), _stream(stream)))
 
 
 def efunc_get_stats(ctx) -> dict:
@@ -531,6 +541,9 @@ class Engine:
 
     def fit_step(self, theta, m, v, step, q, o, loss_out=None, adam=None):
         efunc_fit_step(self.ctx, theta, m, v, step, q, o, loss_out, adam)
+
+    def loss_grad(self, theta, q, o, grad, loss_out=None):
+        efunc_loss_grad(self.ctx, theta, q, o, grad, loss_out)
 
     def init_params(self, theta, surf, bandwidth=100.0, rho0=7.0):
         efunc_init_params(self.ctx, theta, surf, self.R, bandwidth, rho0, nch=self.nch)

@@ -291,3 +291,33 @@ def test_second_fit_step_starts_from_clean_gradient(E):
     gr, ar, br = PT.oracle_grad(R, th1, q, 2 * (O1 - o) / len(q))
     # the subtraction of the rescaled first moment adds a few ulps of m1
     PT.check_grad(g2, gr, ar + 20 * PT.ulp32(m1).reshape(ar.shape), br)
+
+
+def test_loss_grad_equals_fit_step_gradient(E):
+    """efunc_loss_grad accumulates the gradient the fused step applies (the
+    same kernels): loss equal, gradient equal to m / (1 - beta1) of a first
+    step, and a second call doubles it."""
+    R = 8
+    w = W.get("sphere_r8")
+    q, o = W.make_batch(w, 5, J=20000)
+    th = W.perturbed_theta(R, 81)
+    n = th.size
+    with E.Engine(R, len(q)) as eng:
+        tq, to = PT.to_dev(q), PT.to_dev(o)
+        g = torch.zeros(n, device=PT.DEV)
+        l1 = torch.zeros(2, device=PT.DEV, dtype=torch.float64)
+        eng.loss_grad(PT.to_dev(th), tq, to, g, l1)
+        tth = PT.to_dev(th)
+        m = torch.zeros(n, device=PT.DEV)
+        v = torch.zeros(n, device=PT.DEV)
+        l2 = torch.zeros(2, device=PT.DEV, dtype=torch.float64)
+        eng.fit_step(tth, m, v, 1, tq, to, l2)
+        g2 = g.clone()
+        eng.loss_grad(PT.to_dev(th), tq, to, g2)
+        torch.cuda.synchronize()
+        g, g2, m, l1, l2 = (x.cpu().numpy() for x in (g, g2, m, l1, l2))
+    assert np.allclose(l1, l2, rtol=1e-6, atol=0)
+    gm = m.astype(np.float64) / (1.0 - np.float32(0.9))
+    scale = np.abs(g).reshape(-1, 13).max(axis=0)
+    assert np.all(np.abs(gm - g).reshape(-1, 13) <= 1e-4 * np.abs(g).reshape(-1, 13) + 1e-5 * scale)
+    assert np.all(np.abs(g2 - 2 * g).reshape(-1, 13) <= 1e-4 * np.abs(g).reshape(-1, 13) + 1e-5 * scale)
