@@ -343,6 +343,8 @@ def bench_initnet(args, torch):
     R = 32
     log = lambda m: print("# " + m, file=sys.stderr, flush=True)  # noqa: E731
     n_train, n_test = args.initnet_train, args.initnet_test
+    if args.initnet_conv_only:
+        n_train, n_test = 8, 0
     ws = W.batch_set("initnet", n_train + n_test, 400, R_range=(R, R), J_range=(1 << 16, 1 << 16),
                      prims_range=(8, 24))
     t_gen = time.perf_counter()
@@ -353,8 +355,15 @@ def bench_initnet(args, torch):
         data.append((sdf, torch.from_numpy(q).to(dev), torch.from_numpy(o).to(dev), w))
         if (i + 1) % 64 == 0:
             log(f"generated {i + 1}/{len(ws)} shapes")
+    train_set = []
+    for sdf, q, o, w in data[:n_train]:
+        qsets, osets = [q], [o]
+        for k in range(1, args.initnet_train_sets):
+            qk, ok_ = W.make_batch(w, k, device=dev)
+            qsets.append(torch.from_numpy(qk).to(dev))
+            osets.append(torch.from_numpy(ok_).to(dev))
+        train_set.append((sdf, qsets, osets))
     t_gen = time.perf_counter() - t_gen
-    train_set = [(d[0], d[1], d[2]) for d in data[:n_train]]
     test = data[n_train:]
 
     net = E.InitNet(R, 8, T.CHANNELS)
@@ -385,14 +394,21 @@ def bench_initnet(args, torch):
     bwd_flop = conv_flop + sum(2 * 8 * R ** 3 * 27 * ci * co
                                for ci, co in list(zip(T.CHANNELS[:-1], T.CHANNELS[1:]))[1:])
 
-    # train end to end, then fit held-out shapes from three initialisations
+    conv_res = {"metric": "learned-initialiser network fwd+bwd throughput (bf16 MFMA conv3d)",
+                "value": (conv_flop + bwd_flop) / ((fwd_ms + bwd_ms) * 1e-3) / 1e12, "unit": "TFLOP/s",
+                "fwd_ms": fwd_ms, "bwd_ms": bwd_ms}
+    if args.initnet_conv_only:
+        net.close()
+        print(json.dumps(conv_res))
+        return
+    # train end to end, then fit held-out shapes from each initialisation
     t_train = time.perf_counter()
     params = torch.from_numpy(T.initial_params(1)).to(dev)
     losses = T.train(net, params, train_set, args.initnet_steps, 8, 1e-3, 2, log=log)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t_train
-    inits = {"paper": [], "sdf": [], "learned": []}
-    t_init = {"paper": 0.0, "sdf": 0.0, "learned": 0.0}
+    inits = {"paper": [], "sdf": [], "newton": [], "learned": []}
+    t_init = {"paper": 0.0, "sdf": 0.0, "newton": 0.0, "learned": 0.0}
     for sdf, q, o, w in test:
         surf = torch.from_numpy(W.surface_points(w, 16384, seed=W.seed_for(w, -2, "meanshift"),
                                                  device=dev).astype(np.float32)).to(dev)
@@ -404,26 +420,70 @@ def bench_initnet(args, torch):
         inits["sdf"].append(T.sdf_theta(R, sdf, surf, dev))
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        inits["learned"].append(net.forward(params, sdf[None]).reshape(-1).clone())
+        inits["newton"].append(T.newton_theta(sdf, R).reshape(-1).contiguous())
         torch.cuda.synchronize()
         t3 = time.perf_counter()
+        inits["learned"].append(T.learned_theta(net, params, sdf))
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
         t_init["paper"] += t1 - t0
         t_init["sdf"] += t2 - t1
-        t_init["learned"] += t3 - t2
-    qs, os_ = [d[1] for d in test], [d[2] for d in test]
+        t_init["newton"] += t3 - t2
+        t_init["learned"] += t4 - t3
+    # learned with the paper's initialisation as fallback, the fitting loss on
+    # the shape's own training points deciding
+    chosen = [T.choose_init(R, lt, pt, d[1], d[2]) for lt, pt, d in zip(inits["learned"], inits["paper"], test)]
+    n_fallback = sum(fb for _, fb in chosen)
+    if n_fallback:
+        inits["learned_or_paper"] = [c for c, _ in chosen]
+        t_init["learned_or_paper"] = t_init["learned"] + t_init["paper"]
+    log(f"learned init kept for {len(test) - n_fallback}/{len(test)} shapes")
+    # held-out scoring points: a seed of their own, half uniform, half near the surface
+    heldout = []
+    for i, (_, _, _, w) in enumerate(test):
+        qh, oh = W.make_batch(w, 10 ** 6, J=args.initnet_heldout, device=dev)
+        heldout.append((torch.from_numpy(qh).to(dev), torch.from_numpy(oh).to(dev)))
+        if (i + 1) % 16 == 0:
+            log(f"held-out points for {i + 1}/{len(test)} shapes")
+    # training points of the fits: P point sets per held-out shape, cycled
+    P = args.initnet_point_sets
+    Jt = int(test[0][1].shape[0])
+    qpool = torch.empty(P, len(test), Jt, 3, device=dev)
+    opool = torch.empty(P, len(test), Jt, device=dev)
+    for i, (_, q, o, w) in enumerate(test):
+        qpool[0, i], opool[0, i] = q, o
+        for k in range(1, P):
+            qk, ok_ = W.make_batch(w, k, device=dev)
+            qpool[k, i], opool[k, i] = torch.from_numpy(qk).to(dev), torch.from_numpy(ok_).to(dev)
+    log(f"fit point pool: {P} sets x {len(test)} shapes x {Jt} points")
+    thr = 1e-3
     results = {}
+    marks = sorted({0, 10, 20, 50, 100, 250, 500, 1000, 2000, args.initnet_fit_steps})
     for name, ths in inits.items():
-        curve, secs = T.fit_curves([R] * len(test), ths, qs, os_, args.initnet_fit_steps, 50)
-        reach = T.steps_to(curve, 1e-3)
+        curve, secs = T.fit_curves([R] * len(test), ths, qpool, opool, args.initnet_fit_steps, heldout, log=log)
+        reach = T.steps_to(curve, thr)
         ok = [s for s in reach if s is not None]
-        results[name] = {
-            "mean_l1": {str(st): float(np.mean(l1)) for st, l1 in curve if st in (0, 100, 250, 500, 1000, 2000, args.initnet_fit_steps)},
-            "reached_l1_1e-3": len(ok),
-            "median_steps_to_l1_1e-3": float(np.median(ok)) if ok else None,
+        per_step = secs / args.initnet_fit_steps
+        init_total = t_init[name]
+        res = {
+            "heldout_l1": {str(st): float(np.mean(a)) for st, a, *_ in curve if st in marks},
+            "heldout_volume_l1": {str(st): float(np.mean(b)) for st, _, b, *_ in curve if st in marks},
+            "heldout_near_l1": {str(st): float(np.mean(c)) for st, _, _, c, _ in curve if st in marks},
+            "step_points_l1": {str(st): float(np.mean(t)) for st, *_, t in curve if st in marks and st > 0},
+            "reached": len(ok),
+            "median_steps_to_thr": float(np.median(ok)) if ok else None,
             "fit_seconds": secs,
-            "init_seconds_per_shape": t_init[name] / len(test),
+            "seconds_per_batched_step": per_step,
+            "init_seconds_total": init_total,
         }
-        log(f"{name}: {results[name]}")
+        # wall time of the whole batch: initialisation + batched steps until the
+        # half / all of the shapes reached the threshold
+        srt = sorted(ok)
+        half = (len(test) + 1) // 2
+        res["wall_seconds_half_reached"] = init_total + srt[half - 1] * per_step if len(srt) >= half else None
+        res["wall_seconds_all_reached"] = init_total + srt[-1] * per_step if len(srt) == len(test) else None
+        results[name] = res
+        log(f"{name}: {res}")
     net.close()
     out = {
         "metric": "learned-initialiser network fwd+bwd throughput (bf16 MFMA conv3d)",
@@ -440,7 +500,9 @@ def bench_initnet(args, torch):
                      "frac": (conv_flop + bwd_flop) / ((fwd_ms + bwd_ms) * 1e-3) / 2.5e15, "traffic": None,
                      "fwd_ms": fwd_ms, "bwd_ms": bwd_ms, "fwd_flop": conv_flop, "bwd_flop": bwd_flop},
         "experiment": {"train_loss": losses, "train_seconds": t_train, "gen_seconds": t_gen,
-                       "inits": results},
+                       "l1_threshold": thr, "heldout_points_per_shape": args.initnet_heldout,
+                       "fit_point_sets": P, "train_point_sets": args.initnet_train_sets,
+                       "learned_kept": len(test) - n_fallback, "inits": results},
     }
     print(json.dumps(out))
 
@@ -462,8 +524,13 @@ def main():
                     help="tile_cap,group_cells,blocks_per_cu for the tile kernel (default 512,1,8)")
     ap.add_argument("--initnet-train", type=int, default=256, help="initnet: training shapes")
     ap.add_argument("--initnet-test", type=int, default=64, help="initnet: held-out shapes")
-    ap.add_argument("--initnet-steps", type=int, default=600, help="initnet: network training steps")
+    ap.add_argument("--initnet-steps", type=int, default=3000, help="initnet: network training steps")
+    ap.add_argument("--initnet-train-sets", type=int, default=4, help="initnet: point sets per training shape")
     ap.add_argument("--initnet-fit-steps", type=int, default=2000, help="initnet: fit steps per init")
+    ap.add_argument("--initnet-heldout", type=int, default=1 << 20, help="initnet: held-out scoring points per shape")
+    ap.add_argument("--initnet-point-sets", type=int, default=8, help="initnet: point sets cycled by the fits")
+    ap.add_argument("--initnet-conv-only", action="store_true",
+                    help="initnet: time the network's forward and backward only")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()

@@ -28,10 +28,14 @@ namespace efunc {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned short u16;
 
-constexpr int CONV_BLOCK = 256;   // 4 waves, 16 voxels each
-constexpr int WG_CHUNK = 8192;    // voxels per workgroup of the weight gradient
+constexpr int CONV_BLOCK = 256;   // 4 waves
+constexpr int CONV_MB = 4;        // 16-voxel MFMA row tiles per wave: 64 voxels per wave
+constexpr int CONV_KB = 64;       // k per LDS stage of the packed weights (two MFMA steps)
+constexpr int SW_LD = CONV_KB + 8;  // LDS row stride of the staged weights (bf16 elements)
+constexpr int WG_WAVES = 3;       // weight gradient: one wave per x-offset of a (dz, dy) pair
 constexpr int MAXC = 64;          // channels per layer
 
 // float -> bf16, round to nearest even (NaN stays NaN)
@@ -47,6 +51,37 @@ __device__ __forceinline__ float bf2f(u16 h) { return __uint_as_float((uint32_t)
 
 __device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
 
+__device__ __forceinline__ u32x4 pack8(const u16* h)
+{
+    return u32x4{(uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16),
+                 (uint32_t)h[4] | ((uint32_t)h[5] << 16), (uint32_t)h[6] | ((uint32_t)h[7] << 16)};
+}
+
+// Zero the elements n..7 of eight packed bf16 values.
+__device__ __forceinline__ u32x4 keep_first(u32x4 a, int n)
+{
+    u16 h[8];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        h[2 * i] = (u16)(a[i] & 0xffffu);
+        h[2 * i + 1] = (u16)(a[i] >> 16);
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        if (i >= n) h[i] = 0;
+    return pack8(h);
+}
+
+// Workgroups are handed to the 8 XCDs round-robin by linear id.  Renumber
+// them so that XCD j works on the j-th contiguous eighth of the tiles: the
+// halo rows that neighbouring tiles share then stay in one XCD's L2.  A
+// bijection of [0, n) for any n.
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned n)
+{
+    const unsigned x = b % 8u, j = b / 8u, q = n / 8u, r = n % 8u;
+    return x < r ? x * (q + 1u) + j : r * (q + 1u) + (x - r) * q + j;
+}
+
 // Voxel index of the neighbour of (b, z, y, x) at tap, or -1 outside the lattice.
 __device__ __forceinline__ int64_t neighbour(int64_t b, int z, int y, int x, int tap, int D)
 {
@@ -56,196 +91,393 @@ __device__ __forceinline__ int64_t neighbour(int64_t b, int z, int y, int x, int
 }
 
 // y[v][co] = sum_{tap, ci} x[nbr(v, tap)][ci] w[co][tap Cin + ci] (+ bias,
-// ReLU) or, for the data gradient, times (mask[v][co] > 0).  Each wave
-// computes 16 voxels x all Cout (<= 64: up to four 16 x 16 MFMA tiles).
-// CVEC: Cin % 8 == 0, so a lane's 8 consecutive k share one tap and are one
-// 16-byte load.
+// ReLU) or, for the data gradient, times (mask[v][co] > 0).  A wave computes
+// 64 voxels x all Cout (<= 64): 4 x 4 MFMA tiles.  The packed weights pass
+// through LDS CONV_KB columns at a time, shared by the four waves; the
+// activations are gathered straight from memory (a voxel's row is re-read by
+// its 27 neighbours, from the caches).  CVEC: Cin % 8 == 0, so a lane's 8
+// consecutive k share one tap and are one 16-byte load.  The epilogue writes
+// channels-last y (bf16 and/or fp32, row stride ycs >= Cout, the channels
+// Cout..ycs-1 set to zero; the mask has the same layout) and, when yT is
+// given, the channel-major bf16 copy yT[co][v] (row stride ldT) that the
+// weight gradient reads.
 template <bool CVEC>
 __global__ __launch_bounds__(CONV_BLOCK) void k_conv(const u16* __restrict__ x, int Cin,
                                                      const u16* __restrict__ w, int Kpad, int Cout,
                                                      const float* __restrict__ bias, int relu,
                                                      const u16* __restrict__ mask, int D, int64_t V,
-                                                     u16* __restrict__ ybf, float* __restrict__ yf)
+                                                     u16* __restrict__ ybf, float* __restrict__ yf, int ycs,
+                                                     u16* __restrict__ yT, int64_t ldT)
 {
+    __shared__ __attribute__((aligned(16))) u16 sw[2][MAXC * SW_LD];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t v0 = ((int64_t)blockIdx.x * (CONV_BLOCK / 64) + wv) * 16;
-    if (v0 >= V) return;  // whole wave
     const int row = lane & 15, kq = lane >> 4;
-    const int64_t va = v0 + row;  // voxel of this lane's A row
-    const bool vin = va < V;
+    const int64_t vw = ((int64_t)xcd_block(blockIdx.x, gridDim.x) * (CONV_BLOCK / 64) + wv) * (16 * CONV_MB);
+    const bool active = vw < V;  // whole wave; inactive waves still stage weights
     const int64_t D3 = (int64_t)D * D * D;
-    const int64_t b = vin ? va / D3 : 0;
-    const int rr = (int)(va - b * D3);
-    const int z = rr / (D * D), y = (rr / D) % D, xx = rr % D;
-    const int NT = (Cout + 15) >> 4;
-    const int K = 27 * Cin;
-    f32x4 acc[4];
+    // per row tile: this lane's voxel and the 27-bit mask of its neighbours
+    // inside the lattice (bit tap)
+    int64_t vrow[CONV_MB];
+    uint32_t nmask[CONV_MB];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int kk = 0; kk < Kpad; kk += 32) {
-        const int k0 = kk + 8 * kq;
-        u32x4 ra = {0u, 0u, 0u, 0u};
-        if (CVEC) {
-            const int tap = k0 / Cin, ci = k0 - tap * Cin;
-            if (vin && k0 < K) {
-                const int64_t nv = neighbour(b, z, y, xx, tap, D);
-                if (nv >= 0) ra = *reinterpret_cast<const u32x4*>(x + nv * Cin + ci);
-            }
-        } else {
-            u16 h[8];
+    for (int m = 0; m < CONV_MB; ++m) {
+        const int64_t va = vw + 16 * m + row;
+        vrow[m] = va;
+        nmask[m] = 0u;
+        if (va < V) {
+            const int64_t bb = va / D3;
+            const int rr = (int)(va - bb * D3);
+            const int z = rr / (D * D), y = (rr / D) % D, xx = rr % D;
+            const uint32_t mz = (z > 0 ? 1u : 0u) | 2u | (z < D - 1 ? 4u : 0u);
+            const uint32_t my = (y > 0 ? 1u : 0u) | 2u | (y < D - 1 ? 4u : 0u);
+            const uint32_t mx = (xx > 0 ? 1u : 0u) | 2u | (xx < D - 1 ? 4u : 0u);
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int k = k0 + i;
-                h[i] = 0;
-                if (vin && k < K) {
-                    const int tap = k / Cin, ci = k - tap * Cin;
-                    const int64_t nv = neighbour(b, z, y, xx, tap, D);
-                    if (nv >= 0) h[i] = x[nv * Cin + ci];
-                }
-            }
-            ra = u32x4{(uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16),
-                       (uint32_t)h[4] | ((uint32_t)h[5] << 16), (uint32_t)h[6] | ((uint32_t)h[7] << 16)};
-        }
-        const bf16x8 a = as_bf16x8(ra);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            if (t < NT) {
-                const int n = t * 16 + row;
-                u32x4 rb = {0u, 0u, 0u, 0u};
-                if (n < Cout) rb = *reinterpret_cast<const u32x4*>(w + (int64_t)n * Kpad + k0);
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, as_bf16x8(rb), acc[t], 0, 0, 0);
-            }
+            for (int t = 0; t < 27; ++t)
+                nmask[m] |= ((mz >> (t / 9)) & (my >> ((t / 3) % 3)) & (mx >> (t % 3)) & 1u) << t;
         }
     }
+    int64_t vrowc[CONV_MB];  // element offset of this lane's voxel rows
+#pragma unroll
+    for (int m = 0; m < CONV_MB; ++m) vrowc[m] = vrow[m] * Cin;
+    const int NT = (Cout + 15) >> 4;
+    const int K = 27 * Cin;
+    const int nsteps = Kpad / 32;
+    // CVEC: this lane's (tap, ci) of its k-slice, advanced by 32 per step
+    int ctap = (8 * kq) / Cin, cci = (8 * kq) % Cin;
+    auto gather = [&](int step, u32x4* ra) {
+        const int k0 = 32 * step + 8 * kq;
+        if (CVEC) {
+            const int64_t toff = (int64_t)(((ctap / 9 - 1) * D + ((ctap / 3) % 3 - 1)) * D + (ctap % 3 - 1)) * Cin + cci;
+#pragma unroll
+            for (int m = 0; m < CONV_MB; ++m) {
+                ra[m] = u32x4{0u, 0u, 0u, 0u};
+                if (k0 < K && ((nmask[m] >> ctap) & 1u))
+                    ra[m] = *reinterpret_cast<const u32x4*>(x + vrowc[m] + toff);
+            }
+            cci += 32;
+            while (cci >= Cin) {
+                cci -= Cin;
+                ++ctap;
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < CONV_MB; ++m) {
+                u16 h[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int k = k0 + i;
+                    h[i] = 0;
+                    const int tap = k / Cin, ci = k - tap * Cin;
+                    if (k < K && ((nmask[m] >> tap) & 1u)) {
+                        const int toff = ((tap / 9 - 1) * D + ((tap / 3) % 3 - 1)) * D + (tap % 3 - 1);
+                        h[i] = x[(vrow[m] + toff) * Cin + ci];
+                    }
+                }
+                ra[m] = pack8(h);
+            }
+        }
+    };
+    // weight staging: each thread moves up to two 16-byte chunks per block
+    const int nchunk = Cout * (CONV_KB / 8);
+    auto wload = [&](int kb, u32x4* wr) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int i = threadIdx.x + j * CONV_BLOCK;
+            wr[j] = u32x4{0u, 0u, 0u, 0u};
+            if (i < nchunk) {
+                const int co = i / (CONV_KB / 8), c8 = i % (CONV_KB / 8);
+                const int k = kb + 8 * c8;
+                if (k < Kpad) wr[j] = *reinterpret_cast<const u32x4*>(w + (int64_t)co * Kpad + k);
+            }
+        }
+    };
+    auto wstore = [&](int buf, const u32x4* wr) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int i = threadIdx.x + j * CONV_BLOCK;
+            if (i < nchunk) {
+                const int co = i / (CONV_KB / 8), c8 = i % (CONV_KB / 8);
+                *reinterpret_cast<u32x4*>(&sw[buf][co * SW_LD + 8 * c8]) = wr[j];
+            }
+        }
+    };
+    f32x4 acc[CONV_MB][4];
+#pragma unroll
+    for (int m = 0; m < CONV_MB; ++m)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[m][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    u32x4 wr[2];
+    wload(0, wr);
+    wstore(0, wr);
+    u32x4 ra_next[CONV_MB];
+    if (active) gather(0, ra_next);
+    const int nblk = (Kpad + CONV_KB - 1) / CONV_KB;
+    for (int blk = 0; blk < nblk; ++blk) {
+        __syncthreads();  // sw[blk & 1] complete; every wave is done with sw[(blk + 1) & 1]
+        const bool more = blk + 1 < nblk;
+        if (more) wload((blk + 1) * CONV_KB, wr);  // in flight during this block's MFMAs
+        if (active) {
+            const u16* swb = sw[blk & 1];
+#pragma unroll
+            for (int ks = 0; ks < CONV_KB / 32; ++ks) {
+                const int step = blk * (CONV_KB / 32) + ks;
+                if (step >= nsteps) break;
+                u32x4 ra[CONV_MB];
+#pragma unroll
+                for (int m = 0; m < CONV_MB; ++m) ra[m] = ra_next[m];
+                if (step + 1 < nsteps) gather(step + 1, ra_next);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    if (t < NT) {
+                        const int n = t * 16 + row;
+                        u32x4 rb = {0u, 0u, 0u, 0u};
+                        if (n < Cout) rb = *reinterpret_cast<const u32x4*>(swb + n * SW_LD + 32 * ks + 8 * kq);
+#pragma unroll
+                        for (int m = 0; m < CONV_MB; ++m)
+                            acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ra[m]), as_bf16x8(rb),
+                                                                                acc[m][t], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        if (more) wstore((blk + 1) & 1, wr);
+    }
+    if (!active) return;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         if (t >= NT) break;
         const int co = t * 16 + row;
-        if (co >= Cout) continue;
+        if (co >= ycs) continue;
+        if (co >= Cout) {  // padding channels of the channels-last rows: zeros
+#pragma unroll
+            for (int m = 0; m < CONV_MB; ++m)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t v = vw + 16 * m + 4 * kq + r;
+                    if (v >= V) continue;
+                    if (ybf) ybf[v * ycs + co] = 0;
+                    if (yf) yf[v * ycs + co] = 0.0f;
+                }
+            continue;
+        }
         const float bb = bias ? bias[co] : 0.0f;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t v = v0 + 4 * kq + r;
-            if (v >= V) continue;
-            float val = acc[t][r] + bb;
-            if (relu) val = fmaxf(val, 0.0f);
-            if (mask && !(bf2f(mask[v * Cout + co]) > 0.0f)) val = 0.0f;
-            if (ybf) ybf[v * Cout + co] = f2bf(val);
-            if (yf) yf[v * Cout + co] = val;
+        for (int m = 0; m < CONV_MB; ++m) {
+            const int64_t v0 = vw + 16 * m + 4 * kq;  // C rows 4 kq + r of tile m
+            u16 hv[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t v = v0 + r;
+                hv[r] = 0;
+                if (v >= V) continue;
+                float val = acc[m][t][r] + bb;
+                if (relu) val = fmaxf(val, 0.0f);
+                if (mask && !(bf2f(mask[v * ycs + co]) > 0.0f)) val = 0.0f;
+                hv[r] = f2bf(val);
+                if (ybf) ybf[v * ycs + co] = hv[r];
+                if (yf) yf[v * ycs + co] = val;
+            }
+            if (yT) {
+                u16* dst = yT + (int64_t)co * ldT + v0;
+                if (v0 + 4 <= V) {
+                    *reinterpret_cast<u32x2*>(dst) =
+                        u32x2{(uint32_t)hv[0] | ((uint32_t)hv[1] << 16), (uint32_t)hv[2] | ((uint32_t)hv[3] << 16)};
+                } else {
+                    for (int r = 0; v0 + r < V; ++r) dst[r] = hv[r];
+                }
+            }
         }
     }
 }
 
-// dw[co][tap][ci] += sum_v dy[v][co] x[nbr(v, tap)][ci]: one workgroup per
-// (chunk of voxels, tap), the full Cout x Cin block as up to 16 MFMA tiles
-// (four per wave), both operands staged through LDS 32 voxels at a time.
-__global__ __launch_bounds__(CONV_BLOCK) void k_conv_wgrad(const u16* __restrict__ x, int Cin,
-                                                           const u16* __restrict__ dy, int Cout,
-                                                           int D, int64_t V, float* __restrict__ dw)
+// dw[co][tap][ci] += sum_v dyT[co][v] xT[ci][nbr(v, tap)] from channel-major
+// operands (row stride ld), so that a lane's 8 consecutive voxels of one
+// channel -- its MFMA k-slice -- are one aligned 16-byte load.  Workgroup =
+// three waves, the x-offsets -1, 0, +1 of one (dz, dy) pair (blockIdx.y) over
+// one chunk of voxels; each wave accumulates the whole Cout x Cin block of its
+// tap (up to 4 x 4 MFMA tiles) and adds it to dw once.  R8: D % 8 == 0, so the
+// 8 voxels lie in one x-row and the neighbour's are that row shifted by the
+// tap's y/z offset and, for dx = +-1, by one element (a funnel shift of the
+// aligned load with the adjacent element, zero past the row's ends).
+// Otherwise every element's neighbour is located on its own.
+template <bool R8>
+__global__ __launch_bounds__(64 * WG_WAVES) void k_conv_wgrad(const u16* __restrict__ xT, int Cin,
+                                                               const u16* __restrict__ dyT, int Cout,
+                                                               int64_t ld, int D, int64_t V, int64_t chunk,
+                                                               float* __restrict__ dw)
 {
-    __shared__ u16 sdy[32][MAXC + 8];
-    __shared__ u16 sx[32][MAXC + 8];
-    const int tap = blockIdx.y;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int tap = blockIdx.y * 3 + wv;
+    const int dz = tap / 9 - 1, dyo = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
     const int row = lane & 15, kq = lane >> 4;
-    const int64_t vbeg = (int64_t)blockIdx.x * WG_CHUNK;
-    const int64_t vend = vbeg + WG_CHUNK < V ? vbeg + WG_CHUNK : V;
+    const int64_t vbeg = (int64_t)blockIdx.x * chunk;
+    const int64_t vend = vbeg + chunk < V ? vbeg + chunk : V;
     const int MT = (Cout + 15) >> 4, NTc = (Cin + 15) >> 4;
     const int64_t D3 = (int64_t)D * D * D;
-    f32x4 acc[4];
+    f32x4 acc[4][4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int64_t vb = vbeg; vb < vend; vb += 32) {
-        __syncthreads();
-        for (int i = threadIdx.x; i < 32 * Cout; i += CONV_BLOCK) {
-            const int vv = i / Cout, c = i - vv * Cout;
-            const int64_t v = vb + vv;
-            sdy[vv][c] = v < vend ? dy[v * Cout + c] : (u16)0;
-        }
-        for (int i = threadIdx.x; i < 32 * Cin; i += CONV_BLOCK) {
-            const int vv = i / Cin, c = i - vv * Cin;
-            const int64_t v = vb + vv;
-            u16 val = 0;
-            if (v < vend) {
-                const int64_t bb = v / D3;
-                const int r = (int)(v - bb * D3);
-                const int64_t nv = neighbour(bb, r / (D * D), (r / D) % D, r % D, tap, D);
-                if (nv >= 0) val = x[nv * Cin + c];
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) acc[m][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    // R8: (x, y, z) of this lane's first voxel vbeg + 8 kq, kept up to date by
+    // load(), which is called once per step in order (no divisions in the loop)
+    int lx = 0, ly = 0, lz = 0;
+    if (R8) {
+        const int64_t v = vbeg + 8 * kq;
+        const int64_t r = v / D;
+        lx = (int)(v - r * D);
+        ly = (int)(r % D);
+        lz = (int)((r / D) % D);
+    }
+    // fragments of the 32-voxel step at vb: a (dyT rows), b (shifted xT rows)
+    auto load = [&](int64_t vb, u32x4* a, u32x4* b) {
+        const int64_t v = vb + 8 * kq;  // this lane's 8 voxels v .. v + 7
+        const bool live = v < vend;
+        const int nval = !live ? 0 : (vend - v >= 8 ? 8 : (int)(vend - v));
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            a[m] = u32x4{0u, 0u, 0u, 0u};
+            const int co = 16 * m + row;
+            if (m < MT && co < Cout && live) {
+                a[m] = *reinterpret_cast<const u32x4*>(dyT + (int64_t)co * ld + v);
+                if (nval < 8) a[m] = keep_first(a[m], nval);
             }
-            sx[vv][c] = val;
         }
-        __syncthreads();
+        if (R8) {
+            // lattice coordinates of v, then advanced by the 32-voxel step for the next call
+            const int x0 = lx, y = ly, z = lz;
+            lx += 32;
+            while (lx >= D) {
+                lx -= D;
+                if (++ly == D) {
+                    ly = 0;
+                    if (++lz == D) lz = 0;
+                }
+            }
+            const bool ok = live && y + dyo >= 0 && y + dyo < D && z + dz >= 0 && z + dz < D;
+            const int64_t nb = v + ((int64_t)dz * D + dyo) * D;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int t = wv + 4 * j;
-            if (t >= MT * NTc) break;
-            const int mt = t / NTc, nt = t - mt * NTc;
-            const int co = mt * 16 + row, ci = nt * 16 + row;
-            u16 ha[8], hb[8];
+            for (int n = 0; n < 4; ++n) {
+                b[n] = u32x4{0u, 0u, 0u, 0u};
+                const int ci = 16 * n + row;
+                if (n < NTc && ci < Cin && ok) {
+                    const u16* p = xT + (int64_t)ci * ld + nb;
+                    const u32x4 wq = *reinterpret_cast<const u32x4*>(p);
+                    if (dx == 0) {
+                        b[n] = wq;
+                    } else if (dx > 0) {
+                        const uint32_t e = x0 + 8 < D ? (uint32_t)p[8] : 0u;
+                        b[n] = u32x4{(wq[0] >> 16) | (wq[1] << 16), (wq[1] >> 16) | (wq[2] << 16),
+                                     (wq[2] >> 16) | (wq[3] << 16), (wq[3] >> 16) | (e << 16)};
+                    } else {
+                        const uint32_t e = x0 > 0 ? (uint32_t)p[-1] : 0u;
+                        b[n] = u32x4{e | (wq[0] << 16), (wq[0] >> 16) | (wq[1] << 16),
+                                     (wq[1] >> 16) | (wq[2] << 16), (wq[2] >> 16) | (wq[3] << 16)};
+                    }
+                }
+            }
+        } else {
+            int64_t nv[8];
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                ha[i] = co < Cout ? sdy[8 * kq + i][co] : (u16)0;
-                hb[i] = ci < Cin ? sx[8 * kq + i][ci] : (u16)0;
+                nv[i] = -1;
+                if (i < nval) {
+                    const int64_t vv = v + i;
+                    const int64_t bb = vv / D3;
+                    const int rr = (int)(vv - bb * D3);
+                    nv[i] = neighbour(bb, rr / (D * D), (rr / D) % D, rr % D, tap, D);
+                }
             }
-            const u32x4 ra = {(uint32_t)ha[0] | ((uint32_t)ha[1] << 16), (uint32_t)ha[2] | ((uint32_t)ha[3] << 16),
-                              (uint32_t)ha[4] | ((uint32_t)ha[5] << 16), (uint32_t)ha[6] | ((uint32_t)ha[7] << 16)};
-            const u32x4 rb = {(uint32_t)hb[0] | ((uint32_t)hb[1] << 16), (uint32_t)hb[2] | ((uint32_t)hb[3] << 16),
-                              (uint32_t)hb[4] | ((uint32_t)hb[5] << 16), (uint32_t)hb[6] | ((uint32_t)hb[7] << 16)};
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ra), as_bf16x8(rb), acc[j], 0, 0, 0);
+#pragma unroll
+            for (int n = 0; n < 4; ++n) {
+                u16 h[8];
+                const int ci = 16 * n + row;
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    h[i] = (n < NTc && ci < Cin && nv[i] >= 0) ? xT[(int64_t)ci * ld + nv[i]] : (u16)0;
+                b[n] = pack8(h);
+            }
         }
+    };
+    u32x4 a_next[4], b_next[4];
+    if (vbeg < vend) load(vbeg, a_next, b_next);
+    for (int64_t vb = vbeg; vb < vend; vb += 32) {
+        u32x4 a[4], b[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            a[m] = a_next[m];
+            b[m] = b_next[m];
+        }
+        if (vb + 32 < vend) load(vb + 32, a_next, b_next);  // in flight during this step's MFMAs
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n)
+                if (m < MT && n < NTc)
+                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a[m]), as_bf16x8(b[n]), acc[m][n],
+                                                                        0, 0, 0);
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int t = wv + 4 * j;
-        if (t >= MT * NTc) break;
-        const int mt = t / NTc, nt = t - mt * NTc;
-        const int ci = nt * 16 + row;
-        if (ci >= Cin) continue;
+    for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int co = mt * 16 + 4 * kq + r;
-            if (co < Cout) unsafeAtomicAdd(&dw[((int64_t)co * 27 + tap) * Cin + ci], acc[j][r]);
+        for (int n = 0; n < 4; ++n) {
+            if (m >= MT || n >= NTc) continue;
+            const int ci = 16 * n + row;
+            if (ci >= Cin) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int co = 16 * m + 4 * kq + r;
+                if (co < Cout) unsafeAtomicAdd(&dw[((int64_t)co * 27 + tap) * Cin + ci], acc[m][n][r]);
+            }
         }
-    }
 }
 
-// db[c] += sum_v dy[v][c] over a chunk of voxels per workgroup.
-__global__ __launch_bounds__(CONV_BLOCK) void k_colsum(const u16* __restrict__ dy, int C, int64_t V,
+constexpr int COLSUM_CHUNK = 8192;  // voxels per workgroup of the bias gradient
+
+// db[c] += sum_v dyT[c][v] from the channel-major copy: workgroup (chunk, c).
+__global__ __launch_bounds__(CONV_BLOCK) void k_rowsum(const u16* __restrict__ dyT, int64_t ld, int64_t V,
                                                        float* __restrict__ db)
 {
-    __shared__ float sh[CONV_BLOCK];
-    const int64_t vbeg = (int64_t)blockIdx.x * WG_CHUNK;
-    const int64_t vend = vbeg + WG_CHUNK < V ? vbeg + WG_CHUNK : V;
-    const int groups = CONV_BLOCK / C;  // threads per channel
-    const int c = threadIdx.x % C, g = threadIdx.x / C;
+    __shared__ float sh[CONV_BLOCK / 64];
+    const int c = blockIdx.y;
+    const int64_t vbeg = (int64_t)blockIdx.x * COLSUM_CHUNK;
+    const int64_t vend = vbeg + COLSUM_CHUNK < V ? vbeg + COLSUM_CHUNK : V;
     float s = 0.0f;
-    if (g < groups)
-        for (int64_t v = vbeg + g; v < vend; v += groups) s += bf2f(dy[v * C + c]);
-    sh[threadIdx.x] = (g < groups) ? s : 0.0f;
+    for (int64_t v = vbeg + threadIdx.x; v < vend; v += CONV_BLOCK) s += bf2f(dyT[(int64_t)c * ld + v]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
     __syncthreads();
-    if (threadIdx.x < C) {
+    if (threadIdx.x == 0) {
         float t = 0.0f;
-        for (int k = 0; k < groups; ++k) t += sh[k * C + threadIdx.x];
-        unsafeAtomicAdd(&db[threadIdx.x], t);
+        for (int k = 0; k < CONV_BLOCK / 64; ++k) t += sh[k];
+        unsafeAtomicAdd(&db[c], t);
     }
 }
 
-// Packed bf16 weights of one layer from the fp32 parameters W[co][tap][ci].
-__global__ void k_pack_weights(const float* __restrict__ W, int Cin, int Cout, int Kpad, int Kpad2,
-                               u16* __restrict__ wf, u16* __restrict__ wd)
+// Packed bf16 weights of one layer from the fp32 parameters W[co][tap][ci]:
+// wf[co][tap Cinp + ci] and wd[ci][tap' Coutp + co] (tap' = 26 - tap), zero
+// for the padding channels ci >= Cin, co >= Cout and past 27 Cinp / 27 Coutp.
+__global__ void k_pack_weights(const float* __restrict__ W, int Cin, int Cout, int Cinp, int Coutp, int Kpad,
+                               int Kpad2, u16* __restrict__ wf, u16* __restrict__ wd)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t nf = (int64_t)Cout * Kpad, nd = (int64_t)Cin * Kpad2;
     if (i < nf) {
         const int co = (int)(i / Kpad), k = (int)(i - (int64_t)co * Kpad);
-        wf[i] = k < 27 * Cin ? f2bf(W[(int64_t)co * 27 * Cin + k]) : (u16)0;
+        u16 v = 0;
+        if (k < 27 * Cinp) {
+            const int tp = k / Cinp, ci = k - tp * Cinp;
+            if (ci < Cin) v = f2bf(W[((int64_t)co * 27 + tp) * Cin + ci]);
+        }
+        wf[i] = v;
     }
     if (i < nd) {
         const int ci = (int)(i / Kpad2), k = (int)(i - (int64_t)ci * Kpad2);
         u16 v = 0;
-        if (k < 27 * Cout) {
-            const int tp = k / Cout, co = k - tp * Cout;
-            v = f2bf(W[((int64_t)co * 27 + (26 - tp)) * Cin + ci]);
+        if (k < 27 * Coutp) {
+            const int tp = k / Coutp, co = k - tp * Coutp;
+            if (co < Cout) v = f2bf(W[((int64_t)co * 27 + (26 - tp)) * Cin + ci]);
         }
         wd[i] = v;
     }
@@ -256,6 +488,26 @@ __global__ void k_to_bf16(const float* __restrict__ a, int64_t n, u16* __restric
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         out[i] = f2bf(a[i]);
 }
+
+// a [V][C] fp32 -> out [V][Cp] bf16 (channels C..Cp-1 zero) and the
+// channel-major copy outT [C][ld].
+__global__ void k_to_bf16_both(const float* __restrict__ a, int64_t V, int C, int Cp, u16* __restrict__ out,
+                               u16* __restrict__ outT, int64_t ld)
+{
+    const int64_t n = V * Cp;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = i / Cp;
+        const int c = (int)(i - v * Cp);
+        u16 h = 0;
+        if (c < C) {
+            h = f2bf(a[v * C + c]);
+            outT[(int64_t)c * ld + v] = h;
+        }
+        out[i] = h;
+    }
+}
+
+static inline int cpad8(int c) { return (c + 7) / 8 * 8; }
 
 static inline int kpad(int k) { return (k + 31) / 32 * 32; }
 
@@ -268,14 +520,38 @@ static unsigned blocks_for(int64_t n, int per)
 }
 
 hipError_t run_conv(const u16* x, int Cin, const u16* w, int Kp, int Cout, const float* bias, int relu,
-                    const u16* mask, int D, int64_t V, u16* ybf, float* yf, hipStream_t s)
+                    const u16* mask, int D, int64_t V, u16* ybf, float* yf, int ycs, u16* yT, int64_t ldT,
+                    hipStream_t s)
 {
-    const int64_t waves = (V + 15) / 16;
-    const unsigned grid = (unsigned)((waves + 3) / 4);
+    const int64_t per_block = 16 * CONV_MB * (CONV_BLOCK / 64);
+    const unsigned grid = (unsigned)((V + per_block - 1) / per_block);
     if (Cin % 8 == 0)
-        k_conv<true><<<grid, CONV_BLOCK, 0, s>>>(x, Cin, w, Kp, Cout, bias, relu, mask, D, V, ybf, yf);
+        k_conv<true><<<grid, CONV_BLOCK, 0, s>>>(x, Cin, w, Kp, Cout, bias, relu, mask, D, V, ybf, yf, ycs, yT, ldT);
     else
-        k_conv<false><<<grid, CONV_BLOCK, 0, s>>>(x, Cin, w, Kp, Cout, bias, relu, mask, D, V, ybf, yf);
+        k_conv<false><<<grid, CONV_BLOCK, 0, s>>>(x, Cin, w, Kp, Cout, bias, relu, mask, D, V, ybf, yf, ycs, yT,
+                                                  ldT);
+    return hipGetLastError();
+}
+
+// Voxels per workgroup of the weight gradient, a multiple of the 32-voxel
+// MFMA step: about 256 chunks for large V (2304 workgroups of 3 waves, more
+// than two rounds at 2 waves per SIMD: measured faster than one full round
+// of longer waves, which leaves the load latency exposed).
+static int64_t wgrad_chunk(int64_t V)
+{
+    int64_t c = ((V + 255) / 256 + 31) / 32 * 32;
+    return c < 256 ? 256 : c;
+}
+
+hipError_t run_wgrad(const u16* xT, int Cin, const u16* dyT, int Cout, int64_t ld, int D, int64_t V, float* dw,
+                     hipStream_t s)
+{
+    const int64_t chunk = wgrad_chunk(V);
+    const dim3 grid((unsigned)((V + chunk - 1) / chunk), 9);
+    if (D % 8 == 0)
+        k_conv_wgrad<true><<<grid, 64 * WG_WAVES, 0, s>>>(xT, Cin, dyT, Cout, ld, D, V, chunk, dw);
+    else
+        k_conv_wgrad<false><<<grid, 64 * WG_WAVES, 0, s>>>(xT, Cin, dyT, Cout, ld, D, V, chunk, dw);
     return hipGetLastError();
 }
 
@@ -286,13 +562,17 @@ using namespace efunc;
 struct efunc_initnet {
     int R = 0, L = 0, Bmax = 0;
     std::vector<int> ch;          // L + 1 channel counts
+    std::vector<int> cs;          // channel strides of the channels-last bf16 buffers (padded to 8;
+                                  // 1 for the one-channel input)
     std::vector<int64_t> woff;    // offset of W_l in the flat parameters
     std::vector<int64_t> boff;    // offset of b_l
     std::vector<int> kf, kd;      // padded k of the forward / data-gradient packing
     int64_t nparams = 0, V1 = 0;  // voxels per shape
     std::vector<u16*> wf, wd;     // packed weights per layer
-    std::vector<u16*> act;        // L bf16 activations: input + hidden layers
-    u16* gbuf[2] = {nullptr, nullptr};
+    std::vector<u16*> act;        // L bf16 activations, channels-last: input + hidden layers
+    std::vector<u16*> actT;       // their channel-major copies [C][ld] (actT[0] = act[0]: one channel)
+    u16* gbuf[2] = {nullptr, nullptr};  // layer output gradients, channels-last
+    u16* gT[2] = {nullptr, nullptr};    // and channel-major
     int last_B = 0;
     std::vector<void*> allocs;
 };
@@ -339,30 +619,38 @@ int efunc_initnet_create(int32_t R, int32_t max_shapes, int32_t n_layers, const 
     n->ch.assign(channels, channels + n_layers + 1);
     n->V1 = (int64_t)R * R * R;
     const int64_t Vmax = n->V1 * max_shapes;
+    const int64_t Vpad = (Vmax + 31) / 32 * 32;  // row stride bound of the channel-major copies
     hipError_t e = hipSuccess;
     int64_t off = 0;
     int maxc = 1;
+    for (int l = 0; l <= n_layers; ++l) n->cs.push_back(l == 0 && channels[0] == 1 ? 1 : cpad8(channels[l]));
     for (int l = 0; l < n_layers; ++l) {
         const int ci = channels[l], co = channels[l + 1];
         n->woff.push_back(off);
         off += (int64_t)co * 27 * ci;
         n->boff.push_back(off);
         off += co;
-        n->kf.push_back(kpad(27 * ci));
-        n->kd.push_back(kpad(27 * co));
+        n->kf.push_back(kpad(27 * n->cs[l]));
+        n->kd.push_back(kpad(27 * n->cs[l + 1]));
         u16 *a = nullptr, *b = nullptr;
         if (e == hipSuccess) e = nalloc(n, &a, (size_t)co * n->kf.back());
         if (e == hipSuccess) e = nalloc(n, &b, (size_t)ci * n->kd.back());
         n->wf.push_back(a);
         n->wd.push_back(b);
-        u16* act = nullptr;
-        if (e == hipSuccess) e = nalloc(n, &act, (size_t)(Vmax * ci));
+        u16 *act = nullptr, *actT = nullptr;
+        if (e == hipSuccess) e = nalloc(n, &act, (size_t)(Vpad * n->cs[l]));
+        if (l == 0 && ci == 1) actT = act;
+        else if (e == hipSuccess) e = nalloc(n, &actT, (size_t)(Vpad * ci));
         n->act.push_back(act);
-        maxc = co > maxc ? co : maxc;
-        maxc = ci > maxc ? ci : maxc;
+        n->actT.push_back(actT);
+        maxc = n->cs[l + 1] > maxc ? n->cs[l + 1] : maxc;
+        maxc = n->cs[l] > maxc ? n->cs[l] : maxc;
     }
     n->nparams = off;
-    for (int k = 0; k < 2 && e == hipSuccess; ++k) e = nalloc(n, &n->gbuf[k], (size_t)(Vmax * maxc));
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+        e = nalloc(n, &n->gbuf[k], (size_t)(Vpad * maxc));
+        if (e == hipSuccess) e = nalloc(n, &n->gT[k], (size_t)(Vpad * maxc));
+    }
     if (e != hipSuccess) {
         nfree(n);
         delete n;
@@ -397,15 +685,18 @@ int efunc_initnet_forward(efunc_initnet* n, const float* params, const float* sd
     for (int l = 0; l < n->L; ++l) {
         const int ci = n->ch[l], co = n->ch[l + 1];
         const int64_t np = (int64_t)co * n->kf[l] > (int64_t)ci * n->kd[l] ? (int64_t)co * n->kf[l] : (int64_t)ci * n->kd[l];
-        k_pack_weights<<<blocks_for(np, 256), 256, 0, s>>>(params + n->woff[l], ci, co, n->kf[l], n->kd[l],
-                                                           n->wf[l], n->wd[l]);
+        k_pack_weights<<<blocks_for(np, 256), 256, 0, s>>>(params + n->woff[l], ci, co, n->cs[l], n->cs[l + 1],
+                                                           n->kf[l], n->kd[l], n->wf[l], n->wd[l]);
     }
+    const int64_t ld = (V + 7) / 8 * 8;
     k_to_bf16<<<blocks_for(V, 256), 256, 0, s>>>(sdf, V, n->act[0]);
     hipError_t e = hipGetLastError();
     for (int l = 0; l < n->L && e == hipSuccess; ++l) {
         const bool last = l == n->L - 1;
-        e = run_conv(n->act[l], n->ch[l], n->wf[l], n->kf[l], n->ch[l + 1], params + n->boff[l], last ? 0 : 1,
-                     nullptr, n->R, V, last ? nullptr : n->act[l + 1], last ? out : nullptr, s);
+        const int co = n->ch[l + 1];
+        e = run_conv(n->act[l], n->cs[l], n->wf[l], n->kf[l], co, params + n->boff[l], last ? 0 : 1, nullptr,
+                     n->R, V, last ? nullptr : n->act[l + 1], last ? out : nullptr, last ? co : n->cs[l + 1],
+                     last ? nullptr : n->actT[l + 1], ld, s);
     }
     if (e != hipSuccess) return hip_fail(e, "initnet forward");
     n->last_B = B;
@@ -420,21 +711,24 @@ int efunc_initnet_backward(efunc_initnet* n, const float* dout, int32_t B, float
     hipStream_t s = (hipStream_t)stream;
     const int64_t V = n->V1 * B;
     const int L = n->L;
-    k_to_bf16<<<blocks_for(V * n->ch[L], 256), 256, 0, s>>>(dout, V * n->ch[L], n->gbuf[0]);
+    const int64_t ld = (V + 7) / 8 * 8;
+    k_to_bf16_both<<<blocks_for(V * n->cs[L], 256), 256, 0, s>>>(dout, V, n->ch[L], n->cs[L], n->gbuf[0], n->gT[0],
+                                                                  ld);
     hipError_t e = hipGetLastError();
     int cur = 0;
-    const unsigned chunks = (unsigned)((V + WG_CHUNK - 1) / WG_CHUNK);
+    const unsigned csum = (unsigned)((V + COLSUM_CHUNK - 1) / COLSUM_CHUNK);
     for (int l = L - 1; l >= 0 && e == hipSuccess; --l) {
         const int ci = n->ch[l], co = n->ch[l + 1];
-        k_conv_wgrad<<<dim3(chunks, 27), CONV_BLOCK, 0, s>>>(n->act[l], ci, n->gbuf[cur], co, n->R, V,
-                                                              dparams + n->woff[l]);
-        k_colsum<<<chunks, CONV_BLOCK, 0, s>>>(n->gbuf[cur], co, V, dparams + n->boff[l]);
-        e = hipGetLastError();
+        e = run_wgrad(n->actT[l], ci, n->gT[cur], co, ld, n->R, V, dparams + n->woff[l], s);
+        if (e == hipSuccess) {
+            k_rowsum<<<dim3(csum, co), CONV_BLOCK, 0, s>>>(n->gT[cur], ld, V, dparams + n->boff[l]);
+            e = hipGetLastError();
+        }
         if (l > 0 && e == hipSuccess) {
             // data gradient through the flipped weights, times the ReLU mask of
             // this layer's input (the previous layer's activation)
-            e = run_conv(n->gbuf[cur], co, n->wd[l], n->kd[l], ci, nullptr, 0, n->act[l], n->R, V,
-                         n->gbuf[1 - cur], nullptr, s);
+            e = run_conv(n->gbuf[cur], n->cs[l + 1], n->wd[l], n->kd[l], ci, nullptr, 0, n->act[l], n->R, V,
+                         n->gbuf[1 - cur], nullptr, n->cs[l], n->gT[1 - cur], ld, s);
             cur = 1 - cur;
         }
     }
@@ -444,35 +738,43 @@ int efunc_initnet_backward(efunc_initnet* n, const float* dout, int32_t B, float
 
 int efunc_conv3d_bf16(const void* x, int32_t Cin, const void* w, int32_t Kpad, int32_t Cout, const float* bias,
                       int32_t relu, const void* mask, int32_t R, int64_t V, void* y_bf16, float* y_f32,
-                      void* stream)
+                      void* yT_bf16, int64_t ldT, void* stream)
 {
     clear_error();
-    if (!x || !w || (!y_bf16 && !y_f32)) return fail(EFUNC_EINVAL, "NULL argument");
+    if (!x || !w || (!y_bf16 && !y_f32 && !yT_bf16)) return fail(EFUNC_EINVAL, "NULL argument");
     if (Cin < 1 || Cin > MAXC || Cout < 1 || Cout > MAXC) return fail(EFUNC_EINVAL, "channels outside [1, %d]", MAXC);
     if (Kpad % 32 != 0 || Kpad < 27 * Cin) return fail(EFUNC_EINVAL, "Kpad must be a multiple of 32 >= 27 Cin");
     if (R < 1 || V < 0 || V % ((int64_t)R * R * R) != 0) return fail(EFUNC_EINVAL, "V must be a multiple of R^3");
     if (Cin % 8 == 0 && (reinterpret_cast<uintptr_t>(x) % 16)) return fail(EFUNC_EINVAL, "x must be 16-byte aligned");
     if (reinterpret_cast<uintptr_t>(w) % 16) return fail(EFUNC_EINVAL, "w must be 16-byte aligned");
+    if (yT_bf16 && (ldT < V || ldT % 8 != 0 || reinterpret_cast<uintptr_t>(yT_bf16) % 16))
+        return fail(EFUNC_EINVAL, "yT needs ldT >= V, ldT a multiple of 8 and 16-byte alignment");
     if (V == 0) return EFUNC_OK;
     hipError_t e = run_conv((const u16*)x, Cin, (const u16*)w, Kpad, Cout, bias, relu, (const u16*)mask, R, V,
-                            (u16*)y_bf16, y_f32, (hipStream_t)stream);
+                            (u16*)y_bf16, y_f32, Cout, (u16*)yT_bf16, ldT, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "conv3d launch");
     return EFUNC_OK;
 }
 
-int efunc_conv3d_wgrad_bf16(const void* x, int32_t Cin, const void* dy, int32_t Cout, int32_t R, int64_t V,
-                            float* dw, float* db, void* stream)
+int efunc_conv3d_wgrad_bf16(const void* xT, int32_t Cin, const void* dyT, int32_t Cout, int64_t ld, int32_t R,
+                            int64_t V, float* dw, float* db, void* stream)
 {
     clear_error();
-    if (!x || !dy || !dw) return fail(EFUNC_EINVAL, "NULL argument");
+    if (!xT || !dyT || !dw) return fail(EFUNC_EINVAL, "NULL argument");
     if (Cin < 1 || Cin > MAXC || Cout < 1 || Cout > MAXC) return fail(EFUNC_EINVAL, "channels outside [1, %d]", MAXC);
     if (R < 1 || V < 0 || V % ((int64_t)R * R * R) != 0) return fail(EFUNC_EINVAL, "V must be a multiple of R^3");
+    if (ld < V || ld % 8 != 0) return fail(EFUNC_EINVAL, "ld must be a multiple of 8 and >= V");
+    if ((reinterpret_cast<uintptr_t>(xT) | reinterpret_cast<uintptr_t>(dyT)) % 16)
+        return fail(EFUNC_EINVAL, "xT and dyT must be 16-byte aligned");
     if (V == 0) return EFUNC_OK;
     hipStream_t s = (hipStream_t)stream;
-    const unsigned chunks = (unsigned)((V + WG_CHUNK - 1) / WG_CHUNK);
-    k_conv_wgrad<<<dim3(chunks, 27), CONV_BLOCK, 0, s>>>((const u16*)x, Cin, (const u16*)dy, Cout, R, V, dw);
-    if (db) k_colsum<<<chunks, CONV_BLOCK, 0, s>>>((const u16*)dy, Cout, V, db);
-    hipError_t e = hipGetLastError();
+    hipError_t e = run_wgrad((const u16*)xT, Cin, (const u16*)dyT, Cout, ld, R, V, dw, s);
+    if (e == hipSuccess && db) {
+        // bias gradient: sum over the channel-major rows (the rows are the per-channel series)
+        k_rowsum<<<dim3((unsigned)((V + COLSUM_CHUNK - 1) / COLSUM_CHUNK), Cout), CONV_BLOCK, 0, s>>>(
+            (const u16*)dyT, ld, V, db);
+        e = hipGetLastError();
+    }
     if (e != hipSuccess) return hip_fail(e, "conv3d wgrad launch");
     return EFUNC_OK;
 }
@@ -484,7 +786,8 @@ int efunc_conv3d_pack_weights(const float* W, int32_t Cin, int32_t Cout, void* w
     if (Cin < 1 || Cin > MAXC || Cout < 1 || Cout > MAXC) return fail(EFUNC_EINVAL, "channels outside [1, %d]", MAXC);
     const int kf = kpad(27 * Cin), kd = kpad(27 * Cout);
     const int64_t np = (int64_t)Cout * kf > (int64_t)Cin * kd ? (int64_t)Cout * kf : (int64_t)Cin * kd;
-    k_pack_weights<<<blocks_for(np, 256), 256, 0, (hipStream_t)stream>>>(W, Cin, Cout, kf, kd, (u16*)wf, (u16*)wd);
+    k_pack_weights<<<blocks_for(np, 256), 256, 0, (hipStream_t)stream>>>(W, Cin, Cout, Cin, Cout, kf, kd, (u16*)wf,
+                                                                         (u16*)wd);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "pack weights launch");
     return EFUNC_OK;

@@ -38,8 +38,17 @@ def conv_abs(x, w):
     return N._conv(np.abs(N.bf16_round(x)), np.abs(N.bf16_round(w)))
 
 
+def channel_major(a, C, ld):
+    """[V][C] values -> a [C][ld] bf16 device tensor (columns V..ld-1 hold
+    garbage that the kernels must ignore)."""
+    V = a.size // C
+    t = torch.full((C, ld), float("nan"), device=PT.DEV, dtype=torch.bfloat16)
+    t[:, :V] = bf16_tensor(np.asarray(a).reshape(V, C).T)
+    return t.contiguous()
+
+
 @pytest.mark.parametrize("Cin,Cout,R,B", [(1, 32, 6, 2), (32, 64, 5, 3), (64, 13, 4, 2), (13, 64, 4, 1),
-                                           (8, 16, 7, 1)])
+                                           (8, 16, 7, 1), (64, 64, 8, 2), (32, 13, 16, 1)])
 def test_conv_forward_matches_oracle(E, Cin, Cout, R, B):
     rng = np.random.default_rng(Cin * 100 + Cout)
     x = N.bf16_round(rng.standard_normal((B, R, R, R, Cin)))
@@ -47,10 +56,12 @@ def test_conv_forward_matches_oracle(E, Cin, Cout, R, B):
     b = rng.standard_normal(Cout)
     wf, _ = E.efunc_conv3d_pack_weights(PT.to_dev(W.reshape(-1)), Cin, Cout)
     V = B * R ** 3
+    ld = (V + 7) // 8 * 8 + 8
     yf = torch.empty(V * Cout, device=PT.DEV)
     ybf = torch.empty(V * Cout, device=PT.DEV, dtype=torch.bfloat16)
+    yT = torch.zeros(Cout, ld, device=PT.DEV, dtype=torch.bfloat16)
     E.efunc_conv3d_bf16(bf16_tensor(x), Cin, wf, Cout, R, bias=PT.to_dev(b.astype(np.float32)), relu=True,
-                        y_bf16=ybf, y_f32=yf)
+                        y_bf16=ybf, y_f32=yf, yT_bf16=yT)
     torch.cuda.synchronize()
     z, a = N.layer_forward(x, W, b.astype(np.float32).astype(np.float64), relu=True)
     got = yf.cpu().numpy().astype(np.float64).reshape(a.shape)
@@ -58,9 +69,13 @@ def test_conv_forward_matches_oracle(E, Cin, Cout, R, B):
     assert np.all(np.abs(got - a) <= tol), np.max(np.abs(got - a) / tol)
     # the bf16 output is the round-to-nearest-even of the fp32 output
     assert np.array_equal(ybf.float().cpu().numpy().reshape(a.shape), N.bf16_round(got))
+    # the channel-major copy is its transpose; the padding columns stay untouched
+    yt = yT.float().cpu().numpy()
+    assert np.array_equal(yt[:, :V], ybf.float().cpu().numpy().reshape(V, Cout).T)
+    assert not yt[:, V:].any()
 
 
-@pytest.mark.parametrize("Cin,Cout,R", [(32, 64, 5), (64, 13, 4), (1, 32, 4)])
+@pytest.mark.parametrize("Cin,Cout,R", [(32, 64, 5), (64, 13, 4), (1, 32, 4), (64, 64, 8)])
 def test_conv_data_gradient_matches_oracle(E, Cin, Cout, R):
     """dL/dx through the flipped packing, masked by the input activation > 0."""
     rng = np.random.default_rng(7 + Cin)
@@ -71,7 +86,8 @@ def test_conv_data_gradient_matches_oracle(E, Cin, Cout, R):
     _, wd = E.efunc_conv3d_pack_weights(PT.to_dev(W.reshape(-1)), Cin, Cout)
     V = B * R ** 3
     dx = torch.empty(V * Cin, device=PT.DEV)
-    E.efunc_conv3d_bf16(bf16_tensor(dz), Cout, wd, Cin, R, mask=bf16_tensor(x), y_f32=dx)
+    dxT = torch.empty(Cin, (V + 7) // 8 * 8, device=PT.DEV, dtype=torch.bfloat16)
+    E.efunc_conv3d_bf16(bf16_tensor(dz), Cout, wd, Cin, R, mask=bf16_tensor(x), y_f32=dx, yT_bf16=dxT)
     torch.cuda.synchronize()
     _, _, dx_ref = N.layer_backward(x, W, dz)
     dx_ref = dx_ref * (x > 0)
@@ -79,18 +95,23 @@ def test_conv_data_gradient_matches_oracle(E, Cin, Cout, R):
     got = dx.cpu().numpy().astype(np.float64).reshape(dx_ref.shape)
     tol = gamma(27 * Cout) * absref + U * np.abs(dx_ref) + 1e-30
     assert np.all(np.abs(got - dx_ref) <= tol), np.max(np.abs(got - dx_ref) / tol)
+    assert np.array_equal(dxT.float().cpu().numpy()[:, :V], N.bf16_round(got).reshape(V, Cin).T)
 
 
-@pytest.mark.parametrize("Cin,Cout,R,B", [(1, 32, 6, 2), (32, 64, 5, 2), (64, 13, 4, 3), (13, 16, 3, 1)])
+@pytest.mark.parametrize("Cin,Cout,R,B", [(1, 32, 6, 2), (32, 64, 5, 2), (64, 13, 4, 3), (13, 16, 3, 1),
+                                           (64, 64, 8, 2), (1, 32, 16, 1), (64, 13, 8, 3), (13, 64, 16, 1)])
 def test_conv_weight_gradient_matches_oracle(E, Cin, Cout, R, B):
-    rng = np.random.default_rng(11 + Cout)
+    """R a multiple of 8 takes the x-row path (shifted aligned loads), other R
+    the per-element path; several chunks of voxels per call at R = 16."""
+    rng = np.random.default_rng(11 + Cout + R)
     x = N.bf16_round(rng.standard_normal((B, R, R, R, Cin)))
     dz = N.bf16_round(rng.standard_normal((B, R, R, R, Cout)))
     W = rng.standard_normal((Cout, 27, Cin))
     V = B * R ** 3
+    ld = (V + 7) // 8 * 8 + 8
     dw = torch.zeros(Cout * 27 * Cin, device=PT.DEV)
     db = torch.zeros(Cout, device=PT.DEV)
-    E.efunc_conv3d_wgrad_bf16(bf16_tensor(x), Cin, bf16_tensor(dz), Cout, R, dw, db)
+    E.efunc_conv3d_wgrad_bf16(channel_major(x, Cin, ld), Cin, channel_major(dz, Cout, ld), Cout, R, V, dw, db)
     torch.cuda.synchronize()
     dW_ref, db_ref, _ = N.layer_backward(x, W, dz)
     dW_abs, db_abs, _ = N.layer_backward(np.abs(x), W, np.abs(dz))
@@ -101,14 +122,16 @@ def test_conv_weight_gradient_matches_oracle(E, Cin, Cout, R, B):
     assert np.all(np.abs(gb - db_ref) <= gamma(V) * db_abs + 1e-30)
 
 
-def test_network_forward_backward_against_oracle_layers(E):
+@pytest.mark.parametrize("R,B,ch", [(6, 2, (1, 16, 32, 16, 13)), (8, 2, (1, 16, 32, 16, 13)),
+                                    (8, 1, (1, 12, 20, 13))])
+def test_network_forward_backward_against_oracle_layers(E, R, B, ch):
     """The whole 4-layer network: the output and the parameter gradient
     against the oracle evaluated layer by layer on the same bf16 inputs (the
     GPU's rounding of intermediate activations to bf16 is reproduced by the
     oracle; fp32 accumulation may flip a rounding, so the comparison allows
-    a few bf16 ulps of the output scale)."""
-    R, B = 6, 2
-    ch = [1, 16, 32, 16, 13]
+    a few bf16 ulps of the output scale).  Channel counts that are not
+    multiples of 8 run on padded channels-last buffers inside the network."""
+    ch = list(ch)
     rng = np.random.default_rng(21)
     params = np.concatenate([np.concatenate([rng.standard_normal(co * 27 * ci) / np.sqrt(27 * ci),
                                              0.1 * rng.standard_normal(co)])
