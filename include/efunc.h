@@ -315,21 +315,23 @@ int efunc_initnet_backward(efunc_initnet* net, const float* dout, int32_t B, flo
  * (+ bias[co]) then ReLU when relu = 1, or times (mask[v][co] > 0) when mask
  * is given; w packed [Cout][Kpad], Kpad a multiple of 32 >= 27 Cin, zero
  * padded; V = B R^3 voxels; writes any of y_bf16 and y_f32 [V][Cout]
- * (channels-last) and yT_bf16 [Cout][ldT] (channel-major, ldT a multiple of 8
- * >= V; the columns V..ldT-1 are left untouched).  x, w and yT 16-byte aligned.
- * efunc_conv3d_wgrad_bf16: dw[co][tap][ci] += sum_v dyT[co][v] xT[ci][nbr(v,tap)]
- * and db[co] += sum_v dyT[co][v] (db optional), from channel-major operands
- * xT [Cin][ld] and dyT [Cout][ld] (ld a multiple of 8 >= V, 16-byte aligned;
- * columns V..ld-1 are read but ignored).  Accumulates with atomics: the
+ * (channels-last) and yT_bf16, the blocked channel-major copy: element
+ * (co, v) at ((v / 32) Cout + co) 32 + v % 32, ceil(V/32) 32 Cout elements
+ * (the slots of a last partial block past V are left untouched).  x, w and
+ * yT 16-byte aligned.
+ * efunc_conv3d_wgrad_bf16: dw[co][tap][ci] += sum_v dyT(co, v) xT(ci, nbr(v,tap))
+ * and db[co] += sum_v dyT(co, v) (db optional), from operands in that blocked
+ * channel-major layout (xT with Cin channels, dyT with Cout; 16-byte aligned;
+ * slots past V are read but ignored).  Accumulates with atomics: the
  * summation order, hence the last bits, may vary between calls.
  * efunc_conv3d_pack_weights: the forward packing wf [Cout][kpad(27 Cin)] and
  * the data-gradient packing wd [Cin][kpad(27 Cout)] (flipped taps, so that the
  * data gradient is efunc_conv3d_bf16 of dy with wd) of fp32 W[co][tap][ci]. */
 int efunc_conv3d_bf16(const void* x, int32_t Cin, const void* w, int32_t Kpad, int32_t Cout,
                       const float* bias, int32_t relu, const void* mask, int32_t R, int64_t V,
-                      void* y_bf16, float* y_f32, void* yT_bf16, int64_t ldT, void* stream);
-int efunc_conv3d_wgrad_bf16(const void* xT, int32_t Cin, const void* dyT, int32_t Cout, int64_t ld,
-                            int32_t R, int64_t V, float* dw, float* db, void* stream);
+                      void* y_bf16, float* y_f32, void* yT_bf16, void* stream);
+int efunc_conv3d_wgrad_bf16(const void* xT, int32_t Cin, const void* dyT, int32_t Cout, int32_t R,
+                            int64_t V, float* dw, float* db, void* stream);
 int efunc_conv3d_pack_weights(const float* W, int32_t Cin, int32_t Cout, void* wf, void* wd,
                               void* stream);
 

@@ -82,6 +82,12 @@ __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned n)
     return x < r ? x * (q + 1u) + j : r * (q + 1u) + (x - r) * q + j;
 }
 
+// Element (c, v) of a channel-major copy of C channels, blocked by 32 voxels:
+// [ceil(V/32)][C][32].  The 32-voxel step of all channels is one contiguous
+// block, so a wave's 16 channels x 8 voxels are one 1 KB run (an unblocked
+// [C][V] copy puts every channel row in its own pages).
+__device__ __forceinline__ int64_t tidx(int c, int64_t v, int C) { return ((v >> 5) * C + c) * 32 + (v & 31); }
+
 // Voxel index of the neighbour of (b, z, y, x) at tap, or -1 outside the lattice.
 __device__ __forceinline__ int64_t neighbour(int64_t b, int z, int y, int x, int tap, int D)
 {
@@ -99,15 +105,15 @@ __device__ __forceinline__ int64_t neighbour(int64_t b, int z, int y, int x, int
 // consecutive k share one tap and are one 16-byte load.  The epilogue writes
 // channels-last y (bf16 and/or fp32, row stride ycs >= Cout, the channels
 // Cout..ycs-1 set to zero; the mask has the same layout) and, when yT is
-// given, the channel-major bf16 copy yT[co][v] (row stride ldT) that the
-// weight gradient reads.
+// given, the blocked channel-major bf16 copy yT (tidx) that the weight
+// gradient reads.
 template <bool CVEC>
 __global__ __launch_bounds__(CONV_BLOCK) void k_conv(const u16* __restrict__ x, int Cin,
                                                      const u16* __restrict__ w, int Kpad, int Cout,
                                                      const float* __restrict__ bias, int relu,
                                                      const u16* __restrict__ mask, int D, int64_t V,
                                                      u16* __restrict__ ybf, float* __restrict__ yf, int ycs,
-                                                     u16* __restrict__ yT, int64_t ldT)
+                                                     u16* __restrict__ yT)
 {
     __shared__ __attribute__((aligned(16))) u16 sw[2][MAXC * SW_LD];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -278,7 +284,7 @@ __global__ __launch_bounds__(CONV_BLOCK) void k_conv(const u16* __restrict__ x, 
                 if (yf) yf[v * ycs + co] = val;
             }
             if (yT) {
-                u16* dst = yT + (int64_t)co * ldT + v0;
+                u16* dst = yT + tidx(co, v0, Cout);  // v0 .. v0 + 3 share a 32-voxel block
                 if (v0 + 4 <= V) {
                     *reinterpret_cast<u32x2*>(dst) =
                         u32x2{(uint32_t)hv[0] | ((uint32_t)hv[1] << 16), (uint32_t)hv[2] | ((uint32_t)hv[3] << 16)};
@@ -290,8 +296,8 @@ __global__ __launch_bounds__(CONV_BLOCK) void k_conv(const u16* __restrict__ x, 
     }
 }
 
-// dw[co][tap][ci] += sum_v dyT[co][v] xT[ci][nbr(v, tap)] from channel-major
-// operands (row stride ld), so that a lane's 8 consecutive voxels of one
+// dw[co][tap][ci] += sum_v dyT[co][v] xT[ci][nbr(v, tap)] from blocked
+// channel-major operands (tidx), so that a lane's 8 consecutive voxels of one
 // channel -- its MFMA k-slice -- are one aligned 16-byte load.  Workgroup =
 // three waves, the x-offsets -1, 0, +1 of one (dz, dy) pair (blockIdx.y) over
 // one chunk of voxels; each wave accumulates the whole Cout x Cin block of its
@@ -303,7 +309,7 @@ __global__ __launch_bounds__(CONV_BLOCK) void k_conv(const u16* __restrict__ x, 
 template <bool R8>
 __global__ __launch_bounds__(64 * WG_WAVES) void k_conv_wgrad(const u16* __restrict__ xT, int Cin,
                                                                const u16* __restrict__ dyT, int Cout,
-                                                               int64_t ld, int D, int64_t V, int64_t chunk,
+                                                               int D, int64_t V, int64_t chunk,
                                                                float* __restrict__ dw)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -339,7 +345,7 @@ __global__ __launch_bounds__(64 * WG_WAVES) void k_conv_wgrad(const u16* __restr
             a[m] = u32x4{0u, 0u, 0u, 0u};
             const int co = 16 * m + row;
             if (m < MT && co < Cout && live) {
-                a[m] = *reinterpret_cast<const u32x4*>(dyT + (int64_t)co * ld + v);
+                a[m] = *reinterpret_cast<const u32x4*>(dyT + tidx(co, v, Cout));
                 if (nval < 8) a[m] = keep_first(a[m], nval);
             }
         }
@@ -361,16 +367,15 @@ __global__ __launch_bounds__(64 * WG_WAVES) void k_conv_wgrad(const u16* __restr
                 b[n] = u32x4{0u, 0u, 0u, 0u};
                 const int ci = 16 * n + row;
                 if (n < NTc && ci < Cin && ok) {
-                    const u16* p = xT + (int64_t)ci * ld + nb;
-                    const u32x4 wq = *reinterpret_cast<const u32x4*>(p);
+                    const u32x4 wq = *reinterpret_cast<const u32x4*>(xT + tidx(ci, nb, Cin));
                     if (dx == 0) {
                         b[n] = wq;
                     } else if (dx > 0) {
-                        const uint32_t e = x0 + 8 < D ? (uint32_t)p[8] : 0u;
+                        const uint32_t e = x0 + 8 < D ? (uint32_t)xT[tidx(ci, nb + 8, Cin)] : 0u;
                         b[n] = u32x4{(wq[0] >> 16) | (wq[1] << 16), (wq[1] >> 16) | (wq[2] << 16),
                                      (wq[2] >> 16) | (wq[3] << 16), (wq[3] >> 16) | (e << 16)};
                     } else {
-                        const uint32_t e = x0 > 0 ? (uint32_t)p[-1] : 0u;
+                        const uint32_t e = x0 > 0 ? (uint32_t)xT[tidx(ci, nb - 1, Cin)] : 0u;
                         b[n] = u32x4{e | (wq[0] << 16), (wq[0] >> 16) | (wq[1] << 16),
                                      (wq[1] >> 16) | (wq[2] << 16), (wq[2] >> 16) | (wq[3] << 16)};
                     }
@@ -394,7 +399,7 @@ __global__ __launch_bounds__(64 * WG_WAVES) void k_conv_wgrad(const u16* __restr
                 const int ci = 16 * n + row;
 #pragma unroll
                 for (int i = 0; i < 8; ++i)
-                    h[i] = (n < NTc && ci < Cin && nv[i] >= 0) ? xT[(int64_t)ci * ld + nv[i]] : (u16)0;
+                    h[i] = (n < NTc && ci < Cin && nv[i] >= 0) ? xT[tidx(ci, nv[i], Cin)] : (u16)0;
                 b[n] = pack8(h);
             }
         }
@@ -434,8 +439,9 @@ __global__ __launch_bounds__(64 * WG_WAVES) void k_conv_wgrad(const u16* __restr
 
 constexpr int COLSUM_CHUNK = 8192;  // voxels per workgroup of the bias gradient
 
-// db[c] += sum_v dyT[c][v] from the channel-major copy: workgroup (chunk, c).
-__global__ __launch_bounds__(CONV_BLOCK) void k_rowsum(const u16* __restrict__ dyT, int64_t ld, int64_t V,
+// db[c] += sum_v dyT[c][v] from the blocked channel-major copy of C
+// channels: workgroup (chunk, c).
+__global__ __launch_bounds__(CONV_BLOCK) void k_rowsum(const u16* __restrict__ dyT, int C, int64_t V,
                                                        float* __restrict__ db)
 {
     __shared__ float sh[CONV_BLOCK / 64];
@@ -443,7 +449,7 @@ __global__ __launch_bounds__(CONV_BLOCK) void k_rowsum(const u16* __restrict__ d
     const int64_t vbeg = (int64_t)blockIdx.x * COLSUM_CHUNK;
     const int64_t vend = vbeg + COLSUM_CHUNK < V ? vbeg + COLSUM_CHUNK : V;
     float s = 0.0f;
-    for (int64_t v = vbeg + threadIdx.x; v < vend; v += CONV_BLOCK) s += bf2f(dyT[(int64_t)c * ld + v]);
+    for (int64_t v = vbeg + threadIdx.x; v < vend; v += CONV_BLOCK) s += bf2f(dyT[tidx(c, v, C)]);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
@@ -490,9 +496,9 @@ __global__ void k_to_bf16(const float* __restrict__ a, int64_t n, u16* __restric
 }
 
 // a [V][C] fp32 -> out [V][Cp] bf16 (channels C..Cp-1 zero) and the
-// channel-major copy outT [C][ld].
+// blocked channel-major copy outT (tidx).
 __global__ void k_to_bf16_both(const float* __restrict__ a, int64_t V, int C, int Cp, u16* __restrict__ out,
-                               u16* __restrict__ outT, int64_t ld)
+                               u16* __restrict__ outT)
 {
     const int64_t n = V * Cp;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -501,7 +507,7 @@ __global__ void k_to_bf16_both(const float* __restrict__ a, int64_t V, int C, in
         u16 h = 0;
         if (c < C) {
             h = f2bf(a[v * C + c]);
-            outT[(int64_t)c * ld + v] = h;
+            outT[tidx(c, v, C)] = h;
         }
         out[i] = h;
     }
@@ -520,16 +526,14 @@ static unsigned blocks_for(int64_t n, int per)
 }
 
 hipError_t run_conv(const u16* x, int Cin, const u16* w, int Kp, int Cout, const float* bias, int relu,
-                    const u16* mask, int D, int64_t V, u16* ybf, float* yf, int ycs, u16* yT, int64_t ldT,
-                    hipStream_t s)
+                    const u16* mask, int D, int64_t V, u16* ybf, float* yf, int ycs, u16* yT, hipStream_t s)
 {
     const int64_t per_block = 16 * CONV_MB * (CONV_BLOCK / 64);
     const unsigned grid = (unsigned)((V + per_block - 1) / per_block);
     if (Cin % 8 == 0)
-        k_conv<true><<<grid, CONV_BLOCK, 0, s>>>(x, Cin, w, Kp, Cout, bias, relu, mask, D, V, ybf, yf, ycs, yT, ldT);
+        k_conv<true><<<grid, CONV_BLOCK, 0, s>>>(x, Cin, w, Kp, Cout, bias, relu, mask, D, V, ybf, yf, ycs, yT);
     else
-        k_conv<false><<<grid, CONV_BLOCK, 0, s>>>(x, Cin, w, Kp, Cout, bias, relu, mask, D, V, ybf, yf, ycs, yT,
-                                                  ldT);
+        k_conv<false><<<grid, CONV_BLOCK, 0, s>>>(x, Cin, w, Kp, Cout, bias, relu, mask, D, V, ybf, yf, ycs, yT);
     return hipGetLastError();
 }
 
@@ -543,15 +547,15 @@ static int64_t wgrad_chunk(int64_t V)
     return c < 256 ? 256 : c;
 }
 
-hipError_t run_wgrad(const u16* xT, int Cin, const u16* dyT, int Cout, int64_t ld, int D, int64_t V, float* dw,
+hipError_t run_wgrad(const u16* xT, int Cin, const u16* dyT, int Cout, int D, int64_t V, float* dw,
                      hipStream_t s)
 {
     const int64_t chunk = wgrad_chunk(V);
     const dim3 grid((unsigned)((V + chunk - 1) / chunk), 9);
     if (D % 8 == 0)
-        k_conv_wgrad<true><<<grid, 64 * WG_WAVES, 0, s>>>(xT, Cin, dyT, Cout, ld, D, V, chunk, dw);
+        k_conv_wgrad<true><<<grid, 64 * WG_WAVES, 0, s>>>(xT, Cin, dyT, Cout, D, V, chunk, dw);
     else
-        k_conv_wgrad<false><<<grid, 64 * WG_WAVES, 0, s>>>(xT, Cin, dyT, Cout, ld, D, V, chunk, dw);
+        k_conv_wgrad<false><<<grid, 64 * WG_WAVES, 0, s>>>(xT, Cin, dyT, Cout, D, V, chunk, dw);
     return hipGetLastError();
 }
 
@@ -570,7 +574,7 @@ struct efunc_initnet {
     int64_t nparams = 0, V1 = 0;  // voxels per shape
     std::vector<u16*> wf, wd;     // packed weights per layer
     std::vector<u16*> act;        // L bf16 activations, channels-last: input + hidden layers
-    std::vector<u16*> actT;       // their channel-major copies [C][ld] (actT[0] = act[0]: one channel)
+    std::vector<u16*> actT;       // their blocked channel-major copies (actT[0] = act[0]: one channel)
     u16* gbuf[2] = {nullptr, nullptr};  // layer output gradients, channels-last
     u16* gT[2] = {nullptr, nullptr};    // and channel-major
     int last_B = 0;
@@ -688,7 +692,6 @@ int efunc_initnet_forward(efunc_initnet* n, const float* params, const float* sd
         k_pack_weights<<<blocks_for(np, 256), 256, 0, s>>>(params + n->woff[l], ci, co, n->cs[l], n->cs[l + 1],
                                                            n->kf[l], n->kd[l], n->wf[l], n->wd[l]);
     }
-    const int64_t ld = (V + 7) / 8 * 8;
     k_to_bf16<<<blocks_for(V, 256), 256, 0, s>>>(sdf, V, n->act[0]);
     hipError_t e = hipGetLastError();
     for (int l = 0; l < n->L && e == hipSuccess; ++l) {
@@ -696,7 +699,7 @@ int efunc_initnet_forward(efunc_initnet* n, const float* params, const float* sd
         const int co = n->ch[l + 1];
         e = run_conv(n->act[l], n->cs[l], n->wf[l], n->kf[l], co, params + n->boff[l], last ? 0 : 1, nullptr,
                      n->R, V, last ? nullptr : n->act[l + 1], last ? out : nullptr, last ? co : n->cs[l + 1],
-                     last ? nullptr : n->actT[l + 1], ld, s);
+                     last ? nullptr : n->actT[l + 1], s);
     }
     if (e != hipSuccess) return hip_fail(e, "initnet forward");
     n->last_B = B;
@@ -711,24 +714,22 @@ int efunc_initnet_backward(efunc_initnet* n, const float* dout, int32_t B, float
     hipStream_t s = (hipStream_t)stream;
     const int64_t V = n->V1 * B;
     const int L = n->L;
-    const int64_t ld = (V + 7) / 8 * 8;
-    k_to_bf16_both<<<blocks_for(V * n->cs[L], 256), 256, 0, s>>>(dout, V, n->ch[L], n->cs[L], n->gbuf[0], n->gT[0],
-                                                                  ld);
+    k_to_bf16_both<<<blocks_for(V * n->cs[L], 256), 256, 0, s>>>(dout, V, n->ch[L], n->cs[L], n->gbuf[0], n->gT[0]);
     hipError_t e = hipGetLastError();
     int cur = 0;
     const unsigned csum = (unsigned)((V + COLSUM_CHUNK - 1) / COLSUM_CHUNK);
     for (int l = L - 1; l >= 0 && e == hipSuccess; --l) {
         const int ci = n->ch[l], co = n->ch[l + 1];
-        e = run_wgrad(n->actT[l], ci, n->gT[cur], co, ld, n->R, V, dparams + n->woff[l], s);
+        e = run_wgrad(n->actT[l], ci, n->gT[cur], co, n->R, V, dparams + n->woff[l], s);
         if (e == hipSuccess) {
-            k_rowsum<<<dim3(csum, co), CONV_BLOCK, 0, s>>>(n->gT[cur], ld, V, dparams + n->boff[l]);
+            k_rowsum<<<dim3(csum, co), CONV_BLOCK, 0, s>>>(n->gT[cur], co, V, dparams + n->boff[l]);
             e = hipGetLastError();
         }
         if (l > 0 && e == hipSuccess) {
             // data gradient through the flipped weights, times the ReLU mask of
             // this layer's input (the previous layer's activation)
             e = run_conv(n->gbuf[cur], n->cs[l + 1], n->wd[l], n->kd[l], ci, nullptr, 0, n->act[l], n->R, V,
-                         n->gbuf[1 - cur], nullptr, n->cs[l], n->gT[1 - cur], ld, s);
+                         n->gbuf[1 - cur], nullptr, n->cs[l], n->gT[1 - cur], s);
             cur = 1 - cur;
         }
     }
@@ -738,7 +739,7 @@ int efunc_initnet_backward(efunc_initnet* n, const float* dout, int32_t B, float
 
 int efunc_conv3d_bf16(const void* x, int32_t Cin, const void* w, int32_t Kpad, int32_t Cout, const float* bias,
                       int32_t relu, const void* mask, int32_t R, int64_t V, void* y_bf16, float* y_f32,
-                      void* yT_bf16, int64_t ldT, void* stream)
+                      void* yT_bf16, void* stream)
 {
     clear_error();
     if (!x || !w || (!y_bf16 && !y_f32 && !yT_bf16)) return fail(EFUNC_EINVAL, "NULL argument");
@@ -747,32 +748,30 @@ int efunc_conv3d_bf16(const void* x, int32_t Cin, const void* w, int32_t Kpad, i
     if (R < 1 || V < 0 || V % ((int64_t)R * R * R) != 0) return fail(EFUNC_EINVAL, "V must be a multiple of R^3");
     if (Cin % 8 == 0 && (reinterpret_cast<uintptr_t>(x) % 16)) return fail(EFUNC_EINVAL, "x must be 16-byte aligned");
     if (reinterpret_cast<uintptr_t>(w) % 16) return fail(EFUNC_EINVAL, "w must be 16-byte aligned");
-    if (yT_bf16 && (ldT < V || ldT % 8 != 0 || reinterpret_cast<uintptr_t>(yT_bf16) % 16))
-        return fail(EFUNC_EINVAL, "yT needs ldT >= V, ldT a multiple of 8 and 16-byte alignment");
+    if (yT_bf16 && reinterpret_cast<uintptr_t>(yT_bf16) % 16) return fail(EFUNC_EINVAL, "yT must be 16-byte aligned");
     if (V == 0) return EFUNC_OK;
     hipError_t e = run_conv((const u16*)x, Cin, (const u16*)w, Kpad, Cout, bias, relu, (const u16*)mask, R, V,
-                            (u16*)y_bf16, y_f32, Cout, (u16*)yT_bf16, ldT, (hipStream_t)stream);
+                            (u16*)y_bf16, y_f32, Cout, (u16*)yT_bf16, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "conv3d launch");
     return EFUNC_OK;
 }
 
-int efunc_conv3d_wgrad_bf16(const void* xT, int32_t Cin, const void* dyT, int32_t Cout, int64_t ld, int32_t R,
+int efunc_conv3d_wgrad_bf16(const void* xT, int32_t Cin, const void* dyT, int32_t Cout, int32_t R,
                             int64_t V, float* dw, float* db, void* stream)
 {
     clear_error();
     if (!xT || !dyT || !dw) return fail(EFUNC_EINVAL, "NULL argument");
     if (Cin < 1 || Cin > MAXC || Cout < 1 || Cout > MAXC) return fail(EFUNC_EINVAL, "channels outside [1, %d]", MAXC);
     if (R < 1 || V < 0 || V % ((int64_t)R * R * R) != 0) return fail(EFUNC_EINVAL, "V must be a multiple of R^3");
-    if (ld < V || ld % 8 != 0) return fail(EFUNC_EINVAL, "ld must be a multiple of 8 and >= V");
     if ((reinterpret_cast<uintptr_t>(xT) | reinterpret_cast<uintptr_t>(dyT)) % 16)
         return fail(EFUNC_EINVAL, "xT and dyT must be 16-byte aligned");
     if (V == 0) return EFUNC_OK;
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = run_wgrad((const u16*)xT, Cin, (const u16*)dyT, Cout, ld, R, V, dw, s);
+    hipError_t e = run_wgrad((const u16*)xT, Cin, (const u16*)dyT, Cout, R, V, dw, s);
     if (e == hipSuccess && db) {
         // bias gradient: sum over the channel-major rows (the rows are the per-channel series)
         k_rowsum<<<dim3((unsigned)((V + COLSUM_CHUNK - 1) / COLSUM_CHUNK), Cout), CONV_BLOCK, 0, s>>>(
-            (const u16*)dyT, ld, V, db);
+            (const u16*)dyT, Cout, V, db);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return hip_fail(e, "conv3d wgrad launch");

@@ -125,8 +125,8 @@ def lib() -> C.CDLL:
         L.efunc_initnet_num_params.restype = i64
         L.efunc_initnet_forward.argtypes = [vp, vp, vp, i32, vp, vp]
         L.efunc_initnet_backward.argtypes = [vp, vp, i32, vp, vp]
-        L.efunc_conv3d_bf16.argtypes = [vp, i32, vp, i32, i32, vp, i32, vp, i32, i64, vp, vp, vp, i64, vp]
-        L.efunc_conv3d_wgrad_bf16.argtypes = [vp, i32, vp, i32, i64, i32, i64, vp, vp, vp]
+        L.efunc_conv3d_bf16.argtypes = [vp, i32, vp, i32, i32, vp, i32, vp, i32, i64, vp, vp, vp, vp]
+        L.efunc_conv3d_wgrad_bf16.argtypes = [vp, i32, vp, i32, i32, i64, vp, vp, vp]
         L.efunc_conv3d_pack_weights.argtypes = [vp, i32, i32, vp, vp, vp]
         L.efunc_adam_update.argtypes = [vp, vp, vp, vp, i64, i64, C.POINTER(efunc_adam), vp]
         L.efunc_loss_grad.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp]
@@ -423,27 +423,28 @@ def efunc_conv3d_pack_weights(W, Cin: int, Cout: int, stream=None):
     return wf, wd
 
 
+def blocked_size(V: int, C: int) -> int:
+    """Elements of a blocked channel-major copy ([ceil(V/32)][C][32])."""
+    return (V + 31) // 32 * 32 * C
+
+
 def efunc_conv3d_bf16(x, Cin: int, w, Cout: int, R: int, bias=None, relu=False, mask=None,
                       y_bf16=None, y_f32=None, yT_bf16=None, stream=None):
-    """yT_bf16, if given, is a [Cout][ld] bf16 tensor (ld a multiple of 8 >= V)."""
+    """yT_bf16, if given, receives the blocked channel-major copy (blocked_size(V, Cout) bf16)."""
     V = x.numel() // Cin
-    ldT = yT_bf16.shape[1] if yT_bf16 is not None else 0
     _check(lib().efunc_conv3d_bf16(_ptr(x, torch.bfloat16, "x", V * Cin), Cin,
                                    _ptr(w, torch.bfloat16, "w", Cout * w.shape[1]), w.shape[1], Cout,
                                    _ptr(bias, torch.float32, "bias", Cout), 1 if relu else 0,
                                    _ptr(mask, torch.bfloat16, "mask", V * Cout), R, V,
                                    _ptr(y_bf16, torch.bfloat16, "y_bf16", V * Cout),
                                    _ptr(y_f32, torch.float32, "y_f32", V * Cout),
-                                   _ptr(yT_bf16, torch.bfloat16, "yT_bf16", Cout * ldT), ldT, _stream(stream)))
+                                   _ptr(yT_bf16, torch.bfloat16, "yT_bf16", blocked_size(V, Cout)), _stream(stream)))
 
 
 def efunc_conv3d_wgrad_bf16(xT, Cin: int, dyT, Cout: int, R: int, V: int, dw, db=None, stream=None):
-    """xT [Cin][ld] and dyT [Cout][ld] channel-major bf16 (ld a multiple of 8 >= V)."""
-    ld = xT.shape[1]
-    if dyT.shape[1] != ld:
-        raise ValueError("xT and dyT need the same row stride")
-    _check(lib().efunc_conv3d_wgrad_bf16(_ptr(xT, torch.bfloat16, "xT", Cin * ld), Cin,
-                                         _ptr(dyT, torch.bfloat16, "dyT", Cout * ld), Cout, ld, R, V,
+    """xT and dyT in the blocked channel-major layout (blocked_size(V, C) bf16 each)."""
+    _check(lib().efunc_conv3d_wgrad_bf16(_ptr(xT, torch.bfloat16, "xT", blocked_size(V, Cin)), Cin,
+                                         _ptr(dyT, torch.bfloat16, "dyT", blocked_size(V, Cout)), Cout, R, V,
                                          _ptr(dw, torch.float32, "dw", Cout * 27 * Cin),
                                          _ptr(db, torch.float32, "db", Cout), _stream(stream)))
 

@@ -38,13 +38,26 @@ def conv_abs(x, w):
     return N._conv(np.abs(N.bf16_round(x)), np.abs(N.bf16_round(w)))
 
 
-def channel_major(a, C, ld):
-    """[V][C] values -> a [C][ld] bf16 device tensor (columns V..ld-1 hold
-    garbage that the kernels must ignore)."""
+def blocked(a, C):
+    """[V][C] values -> the blocked channel-major copy ([ceil(V/32)][C][32]) as
+    a bf16 device tensor; the slots past V hold NaN, which the kernels must
+    ignore."""
     V = a.size // C
-    t = torch.full((C, ld), float("nan"), device=PT.DEV, dtype=torch.bfloat16)
-    t[:, :V] = bf16_tensor(np.asarray(a).reshape(V, C).T)
-    return t.contiguous()
+    nb = (V + 31) // 32
+    t = np.full((nb * 32, C), np.nan, np.float32)
+    t[:V] = np.asarray(a, np.float32).reshape(V, C)
+    return bf16_tensor(t.reshape(nb, 32, C).transpose(0, 2, 1).reshape(-1))
+
+
+def unblocked(t, V, C):
+    """Blocked channel-major bf16 tensor -> [V][C] float values."""
+    nb = (V + 31) // 32
+    return t.float().cpu().numpy().reshape(nb, C, 32).transpose(0, 2, 1).reshape(nb * 32, C)[:V]
+
+
+def test_blocked_layout_helpers_round_trip():
+    a = np.arange(70 * 3, dtype=np.float32).reshape(70, 3)
+    assert np.array_equal(unblocked(blocked(a, 3), 70, 3), a)
 
 
 @pytest.mark.parametrize("Cin,Cout,R,B", [(1, 32, 6, 2), (32, 64, 5, 3), (64, 13, 4, 2), (13, 64, 4, 1),
@@ -56,10 +69,9 @@ def test_conv_forward_matches_oracle(E, Cin, Cout, R, B):
     b = rng.standard_normal(Cout)
     wf, _ = E.efunc_conv3d_pack_weights(PT.to_dev(W.reshape(-1)), Cin, Cout)
     V = B * R ** 3
-    ld = (V + 7) // 8 * 8 + 8
     yf = torch.empty(V * Cout, device=PT.DEV)
     ybf = torch.empty(V * Cout, device=PT.DEV, dtype=torch.bfloat16)
-    yT = torch.zeros(Cout, ld, device=PT.DEV, dtype=torch.bfloat16)
+    yT = torch.zeros(E.blocked_size(V, Cout), device=PT.DEV, dtype=torch.bfloat16)
     E.efunc_conv3d_bf16(bf16_tensor(x), Cin, wf, Cout, R, bias=PT.to_dev(b.astype(np.float32)), relu=True,
                         y_bf16=ybf, y_f32=yf, yT_bf16=yT)
     torch.cuda.synchronize()
@@ -69,10 +81,10 @@ def test_conv_forward_matches_oracle(E, Cin, Cout, R, B):
     assert np.all(np.abs(got - a) <= tol), np.max(np.abs(got - a) / tol)
     # the bf16 output is the round-to-nearest-even of the fp32 output
     assert np.array_equal(ybf.float().cpu().numpy().reshape(a.shape), N.bf16_round(got))
-    # the channel-major copy is its transpose; the padding columns stay untouched
-    yt = yT.float().cpu().numpy()
-    assert np.array_equal(yt[:, :V], ybf.float().cpu().numpy().reshape(V, Cout).T)
-    assert not yt[:, V:].any()
+    # the blocked channel-major copy holds the same values; slots past V stay untouched
+    assert np.array_equal(unblocked(yT, V, Cout), ybf.float().cpu().numpy().reshape(V, Cout))
+    nb = (V + 31) // 32
+    assert not yT.float().cpu().numpy().reshape(nb, Cout, 32)[-1, :, V - 32 * (nb - 1):].any()
 
 
 @pytest.mark.parametrize("Cin,Cout,R", [(32, 64, 5), (64, 13, 4), (1, 32, 4), (64, 64, 8)])
@@ -86,7 +98,7 @@ def test_conv_data_gradient_matches_oracle(E, Cin, Cout, R):
     _, wd = E.efunc_conv3d_pack_weights(PT.to_dev(W.reshape(-1)), Cin, Cout)
     V = B * R ** 3
     dx = torch.empty(V * Cin, device=PT.DEV)
-    dxT = torch.empty(Cin, (V + 7) // 8 * 8, device=PT.DEV, dtype=torch.bfloat16)
+    dxT = torch.empty(E.blocked_size(V, Cin), device=PT.DEV, dtype=torch.bfloat16)
     E.efunc_conv3d_bf16(bf16_tensor(dz), Cout, wd, Cin, R, mask=bf16_tensor(x), y_f32=dx, yT_bf16=dxT)
     torch.cuda.synchronize()
     _, _, dx_ref = N.layer_backward(x, W, dz)
@@ -95,7 +107,7 @@ def test_conv_data_gradient_matches_oracle(E, Cin, Cout, R):
     got = dx.cpu().numpy().astype(np.float64).reshape(dx_ref.shape)
     tol = gamma(27 * Cout) * absref + U * np.abs(dx_ref) + 1e-30
     assert np.all(np.abs(got - dx_ref) <= tol), np.max(np.abs(got - dx_ref) / tol)
-    assert np.array_equal(dxT.float().cpu().numpy()[:, :V], N.bf16_round(got).reshape(V, Cin).T)
+    assert np.array_equal(unblocked(dxT, V, Cin), N.bf16_round(got).reshape(V, Cin))
 
 
 @pytest.mark.parametrize("Cin,Cout,R,B", [(1, 32, 6, 2), (32, 64, 5, 2), (64, 13, 4, 3), (13, 16, 3, 1),
@@ -108,10 +120,9 @@ def test_conv_weight_gradient_matches_oracle(E, Cin, Cout, R, B):
     dz = N.bf16_round(rng.standard_normal((B, R, R, R, Cout)))
     W = rng.standard_normal((Cout, 27, Cin))
     V = B * R ** 3
-    ld = (V + 7) // 8 * 8 + 8
     dw = torch.zeros(Cout * 27 * Cin, device=PT.DEV)
     db = torch.zeros(Cout, device=PT.DEV)
-    E.efunc_conv3d_wgrad_bf16(channel_major(x, Cin, ld), Cin, channel_major(dz, Cout, ld), Cout, R, V, dw, db)
+    E.efunc_conv3d_wgrad_bf16(blocked(x, Cin), Cin, blocked(dz, Cout), Cout, R, V, dw, db)
     torch.cuda.synchronize()
     dW_ref, db_ref, _ = N.layer_backward(x, W, dz)
     dW_abs, db_abs, _ = N.layer_backward(np.abs(x), W, np.abs(dz))
