@@ -96,39 +96,60 @@ __device__ __forceinline__ int64_t neighbour(int64_t b, int z, int y, int x, int
     return ((b * D + zz) * D + yy) * (int64_t)D + xx;
 }
 
+// floor(k / c) by a multiply-high with r = ceil(2^20 / c), exact for
+// 0 <= k < 4096 when 1 <= c <= 64 and for 0 <= k < 288 when c <= 256 (the
+// error term k (r c - 2^20) / (c 2^20) stays below 1/c; checked exhaustively).
+__device__ __forceinline__ int small_div(int k, uint32_t r) { return (int)(((uint32_t)k * r) >> 20); }
+static inline uint32_t small_div_r(int c) { return (uint32_t)(((1u << 20) + (uint32_t)c - 1u) / (uint32_t)c); }
+
+// Zero the packed bf16 elements n..7 (n in 0..8) without a branch.
+__device__ __forceinline__ u32x4 keep_first_n(u32x4 a, int n)
+{
+    u32x4 r;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t lo = 2 * j < n ? 0x0000ffffu : 0u, hi = 2 * j + 1 < n ? 0xffff0000u : 0u;
+        r[j] = a[j] & (lo | hi);
+    }
+    return r;
+}
+
 // y[v][co] = sum_{tap, ci} x[nbr(v, tap)][ci] w[co][tap Cin + ci] (+ bias,
 // ReLU) or, for the data gradient, times (mask[v][co] > 0).  A wave computes
-// 64 voxels x all Cout (<= 64): 4 x 4 MFMA tiles.  The packed weights pass
-// through LDS CONV_KB columns at a time, shared by the four waves; the
-// activations are gathered straight from memory (a voxel's row is re-read by
-// its 27 neighbours, from the caches).  CVEC: Cin % 8 == 0, so a lane's 8
-// consecutive k share one tap and are one 16-byte load.  The epilogue writes
-// channels-last y (bf16 and/or fp32, row stride ycs >= Cout, the channels
-// Cout..ycs-1 set to zero; the mask has the same layout) and, when yT is
-// given, the blocked channel-major bf16 copy yT (tidx) that the weight
-// gradient reads.
-template <bool CVEC>
+// 64 voxels x 16 NT output channels (Cout <= 16 NT): CONV_MB x NT MFMA tiles.
+// The packed weights pass through LDS CONV_KB columns at a time (double
+// buffered, rows Cout..63 zero), shared by the four waves; the
+// activations are gathered straight from memory, one k-step ahead.  CVEC:
+// Cin % 8 == 0, so a lane's 8 consecutive k share one tap and are one 16-byte
+// load.  The loads of the main loop are unconditional, from addresses that
+// are always inside the buffers (a slice outside the lattice re-reads the
+// lane's own voxel row); validity bits zero the operands when they are
+// consumed.  That keeps branches, and with them early waits for the loads in
+// flight, out of the loop.  The epilogue writes channels-last y (bf16
+// and/or fp32, row stride ycs >= Cout, the channels Cout..ycs-1 set to zero;
+// the mask has the same layout) and, when yT is given, the blocked
+// channel-major bf16 copy yT (tidx) that the weight gradient reads.
+template <bool CVEC, int NT>
 __global__ __launch_bounds__(CONV_BLOCK) void k_conv(const u16* __restrict__ x, int Cin,
                                                      const u16* __restrict__ w, int Kpad, int Cout,
                                                      const float* __restrict__ bias, int relu,
                                                      const u16* __restrict__ mask, int D, int64_t V,
                                                      u16* __restrict__ ybf, float* __restrict__ yf, int ycs,
-                                                     u16* __restrict__ yT)
+                                                     u16* __restrict__ yT, uint32_t rcin)
 {
-    __shared__ __attribute__((aligned(16))) u16 sw[2][MAXC * SW_LD];
+    __shared__ __attribute__((aligned(16))) u16 sw[2][MAXC * SW_LD];  // all 64 rows: unguarded stores
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int row = lane & 15, kq = lane >> 4;
     const int64_t vw = ((int64_t)xcd_block(blockIdx.x, gridDim.x) * (CONV_BLOCK / 64) + wv) * (16 * CONV_MB);
-    const bool active = vw < V;  // whole wave; inactive waves still stage weights
     const int64_t D3 = (int64_t)D * D * D;
-    // per row tile: this lane's voxel and the 27-bit mask of its neighbours
-    // inside the lattice (bit tap)
+    // per row tile: this lane's voxel (voxel 0 past the end) and the 27-bit
+    // mask of its neighbours inside the lattice (bit tap; none past the end)
     int64_t vrow[CONV_MB];
     uint32_t nmask[CONV_MB];
 #pragma unroll
     for (int m = 0; m < CONV_MB; ++m) {
         const int64_t va = vw + 16 * m + row;
-        vrow[m] = va;
+        vrow[m] = va < V ? va : 0;
         nmask[m] = 0u;
         if (va < V) {
             const int64_t bb = va / D3;
@@ -145,25 +166,23 @@ __global__ __launch_bounds__(CONV_BLOCK) void k_conv(const u16* __restrict__ x, 
     int64_t vrowc[CONV_MB];  // element offset of this lane's voxel rows
 #pragma unroll
     for (int m = 0; m < CONV_MB; ++m) vrowc[m] = vrow[m] * Cin;
-    const int NT = (Cout + 15) >> 4;
     const int K = 27 * Cin;
-    const int nsteps = Kpad / 32;
-    // CVEC: this lane's (tap, ci) of its k-slice, advanced by 32 per step
-    int ctap = (8 * kq) / Cin, cci = (8 * kq) % Cin;
-    auto gather = [&](int step, u32x4* ra) {
+    const int nblk = (Kpad + CONV_KB - 1) / CONV_KB;
+    // A operand of k-step `step` into ra (raw) and its validity bits
+    auto gather = [&](int step, u32x4* ra, uint32_t& vbits) {
         const int k0 = 32 * step + 8 * kq;
+        vbits = 0u;
         if (CVEC) {
-            const int64_t toff = (int64_t)(((ctap / 9 - 1) * D + ((ctap / 3) % 3 - 1)) * D + (ctap % 3 - 1)) * Cin + cci;
+            const bool kin = k0 < K;
+            const int tap = kin ? small_div(k0, rcin) : 13;
+            const int ci = kin ? k0 - tap * Cin : 0;
+            const int64_t toff =
+                (int64_t)(((tap / 9 - 1) * D + ((tap / 3) % 3 - 1)) * D + (tap % 3 - 1)) * Cin;
 #pragma unroll
             for (int m = 0; m < CONV_MB; ++m) {
-                ra[m] = u32x4{0u, 0u, 0u, 0u};
-                if (k0 < K && ((nmask[m] >> ctap) & 1u))
-                    ra[m] = *reinterpret_cast<const u32x4*>(x + vrowc[m] + toff);
-            }
-            cci += 32;
-            while (cci >= Cin) {
-                cci -= Cin;
-                ++ctap;
+                const bool ok = kin && ((nmask[m] >> tap) & 1u);
+                ra[m] = *reinterpret_cast<const u32x4*>(x + vrowc[m] + (ok ? toff : 0) + ci);
+                vbits |= (ok ? 1u : 0u) << m;
             }
         } else {
 #pragma unroll
@@ -181,77 +200,77 @@ __global__ __launch_bounds__(CONV_BLOCK) void k_conv(const u16* __restrict__ x, 
                 }
                 ra[m] = pack8(h);
             }
+            vbits = (1u << CONV_MB) - 1u;
         }
     };
-    // weight staging: each thread moves up to two 16-byte chunks per block
-    const int nchunk = Cout * (CONV_KB / 8);
+    // weight staging: each thread moves two 16-byte chunks of a block of the
+    // 64 rows (clamped reads; rows >= Cout and columns >= Kpad stored as zero)
     auto wload = [&](int kb, u32x4* wr) {
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int i = threadIdx.x + j * CONV_BLOCK;
-            wr[j] = u32x4{0u, 0u, 0u, 0u};
-            if (i < nchunk) {
-                const int co = i / (CONV_KB / 8), c8 = i % (CONV_KB / 8);
-                const int k = kb + 8 * c8;
-                if (k < Kpad) wr[j] = *reinterpret_cast<const u32x4*>(w + (int64_t)co * Kpad + k);
-            }
+            const int co = i / (CONV_KB / 8), c8 = i % (CONV_KB / 8);
+            const int k = kb + 8 * c8;
+            const int coc = co < Cout ? co : Cout - 1, kc = k < Kpad ? k : Kpad - 8;
+            wr[j] = *reinterpret_cast<const u32x4*>(w + (int64_t)coc * Kpad + kc);
         }
     };
-    auto wstore = [&](int buf, const u32x4* wr) {
+    auto wstore = [&](int buf, int kb, const u32x4* wr) {
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int i = threadIdx.x + j * CONV_BLOCK;
-            if (i < nchunk) {
-                const int co = i / (CONV_KB / 8), c8 = i % (CONV_KB / 8);
-                *reinterpret_cast<u32x4*>(&sw[buf][co * SW_LD + 8 * c8]) = wr[j];
-            }
+            const int co = i / (CONV_KB / 8), c8 = i % (CONV_KB / 8);
+            const int k = kb + 8 * c8;
+            const bool ok = co < Cout && k < Kpad;
+            *reinterpret_cast<u32x4*>(&sw[buf][co * SW_LD + 8 * c8]) = ok ? wr[j] : u32x4{0u, 0u, 0u, 0u};
         }
     };
-    f32x4 acc[CONV_MB][4];
+    f32x4 acc[CONV_MB][NT];
 #pragma unroll
     for (int m = 0; m < CONV_MB; ++m)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) acc[m][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    // one k-step: zero the invalid slices of ra, then NT x CONV_MB MFMAs
+    auto mma = [&](const u16* swb, int ks, u32x4* ra, uint32_t vbits) {
+#pragma unroll
+        for (int m = 0; m < CONV_MB; ++m)
+            if (!((vbits >> m) & 1u)) ra[m] = u32x4{0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const u32x4 rb = *reinterpret_cast<const u32x4*>(swb + (t * 16 + row) * SW_LD + 32 * ks + 8 * kq);
+#pragma unroll
+            for (int m = 0; m < CONV_MB; ++m)
+                acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ra[m]), as_bf16x8(rb), acc[m][t], 0, 0,
+                                                                    0);
+        }
+    };
     u32x4 wr[2];
     wload(0, wr);
-    wstore(0, wr);
-    u32x4 ra_next[CONV_MB];
-    if (active) gather(0, ra_next);
-    const int nblk = (Kpad + CONV_KB - 1) / CONV_KB;
+    wstore(0, 0, wr);
+    // two register sets for the gathered operands: while one step's MFMAs
+    // read one set, the next step's loads land in the other (a single set
+    // would make the loads wait for the MFMAs that read it)
+    u32x4 g0[CONV_MB], g1[CONV_MB];
+    uint32_t b0 = 0u, b1 = 0u;
+    gather(0, g0, b0);
+    static_assert(CONV_KB == 64, "two k-steps per staged block");
     for (int blk = 0; blk < nblk; ++blk) {
         __syncthreads();  // sw[blk & 1] complete; every wave is done with sw[(blk + 1) & 1]
-        const bool more = blk + 1 < nblk;
-        if (more) wload((blk + 1) * CONV_KB, wr);  // in flight during this block's MFMAs
-        if (active) {
-            const u16* swb = sw[blk & 1];
-#pragma unroll
-            for (int ks = 0; ks < CONV_KB / 32; ++ks) {
-                const int step = blk * (CONV_KB / 32) + ks;
-                if (step >= nsteps) break;
-                u32x4 ra[CONV_MB];
-#pragma unroll
-                for (int m = 0; m < CONV_MB; ++m) ra[m] = ra_next[m];
-                if (step + 1 < nsteps) gather(step + 1, ra_next);
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    if (t < NT) {
-                        const int n = t * 16 + row;
-                        u32x4 rb = {0u, 0u, 0u, 0u};
-                        if (n < Cout) rb = *reinterpret_cast<const u32x4*>(swb + n * SW_LD + 32 * ks + 8 * kq);
-#pragma unroll
-                        for (int m = 0; m < CONV_MB; ++m)
-                            acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ra[m]), as_bf16x8(rb),
-                                                                                acc[m][t], 0, 0, 0);
-                    }
-                }
-            }
-        }
-        if (more) wstore((blk + 1) & 1, wr);
+        wload((blk + 1) * CONV_KB, wr);  // in flight during this block's MFMAs (unused past the end)
+        const u16* swb = sw[blk & 1];
+        // the scheduling barriers keep each gather ahead of the MFMAs it overlaps
+        // (left alone, the scheduler sinks the loads below them and then waits)
+        gather(2 * blk + 1, g1, b1);  // past the last step: valid addresses, zero bits
+        __builtin_amdgcn_sched_barrier(0);
+        mma(swb, 0, g0, b0);
+        gather(2 * blk + 2, g0, b0);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(swb, 1, g1, b1);
+        wstore((blk + 1) & 1, (blk + 1) * CONV_KB, wr);
     }
-    if (!active) return;
+    if (vw >= V) return;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        if (t >= NT) break;
+    for (int t = 0; t < NT; ++t) {
         const int co = t * 16 + row;
         if (co >= ycs) continue;
         if (co >= Cout) {  // padding channels of the channels-last rows: zeros
@@ -300,16 +319,19 @@ __global__ __launch_bounds__(CONV_BLOCK) void k_conv(const u16* __restrict__ x, 
 // channel-major operands (tidx), so that a lane's 8 consecutive voxels of one
 // channel -- its MFMA k-slice -- are one aligned 16-byte load.  Workgroup =
 // three waves, the x-offsets -1, 0, +1 of one (dz, dy) pair (blockIdx.y) over
-// one chunk of voxels; each wave accumulates the whole Cout x Cin block of its
-// tap (up to 4 x 4 MFMA tiles) and adds it to dw once.  R8: D % 8 == 0, so the
-// 8 voxels lie in one x-row and the neighbour's are that row shifted by the
-// tap's y/z offset and, for dx = +-1, by one element (a funnel shift of the
-// aligned load with the adjacent element, zero past the row's ends).
-// Otherwise every element's neighbour is located on its own.
-template <bool R8>
+// one chunk of voxels; each wave accumulates the Cout x Cin block of its tap
+// (MT x NT MFMA tiles, Cout <= 16 MT, Cin <= 16 NT) and adds it to dw once.
+// R8: D % 8 == 0, so the 8 voxels lie in one x-row and the neighbour's are
+// that row shifted by the tap's y/z offset and, for dx = +-1, by one element
+// (a funnel shift of the aligned load with the adjacent element, zero past
+// the row's ends).  As in k_conv, the loop's loads are unconditional from
+// in-range addresses, one step ahead, and zeroed by validity bits when
+// consumed.  Otherwise (any D, small lattices) every element's neighbour is
+// located on its own.
+template <bool R8, int MT, int NT>
 __global__ __launch_bounds__(64 * WG_WAVES) void k_conv_wgrad(const u16* __restrict__ xT, int Cin,
                                                                const u16* __restrict__ dyT, int Cout,
-                                                               int D, int64_t V, int64_t chunk,
+                                                               int D, int64_t V, int64_t chunk, uint32_t rd,
                                                                float* __restrict__ dw)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -318,15 +340,28 @@ __global__ __launch_bounds__(64 * WG_WAVES) void k_conv_wgrad(const u16* __restr
     const int row = lane & 15, kq = lane >> 4;
     const int64_t vbeg = (int64_t)blockIdx.x * chunk;
     const int64_t vend = vbeg + chunk < V ? vbeg + chunk : V;
-    const int MT = (Cout + 15) >> 4, NTc = (Cin + 15) >> 4;
     const int64_t D3 = (int64_t)D * D * D;
-    f32x4 acc[4][4];
+    int coc[MT], cic[NT];  // this lane's channel rows, clamped into range
+    uint32_t cobits = 0u, cibits = 0u;
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
+    for (int m = 0; m < MT; ++m) {
+        const int co = 16 * m + row;
+        coc[m] = co < Cout ? co : Cout - 1;
+        cobits |= (co < Cout ? 1u : 0u) << m;
+    }
 #pragma unroll
-        for (int n = 0; n < 4; ++n) acc[m][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    // R8: (x, y, z) of this lane's first voxel vbeg + 8 kq, kept up to date by
-    // load(), which is called once per step in order (no divisions in the loop)
+    for (int n = 0; n < NT; ++n) {
+        const int ci = 16 * n + row;
+        cic[n] = ci < Cin ? ci : Cin - 1;
+        cibits |= (ci < Cin ? 1u : 0u) << n;
+    }
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    // R8: (x, y, z) of this lane's next voxel slice, advanced by 32 voxels per
+    // issue() (carries by multiply-high, no loop)
     int lx = 0, ly = 0, lz = 0;
     if (R8) {
         const int64_t v = vbeg + 8 * kq;
@@ -335,58 +370,47 @@ __global__ __launch_bounds__(64 * WG_WAVES) void k_conv_wgrad(const u16* __restr
         ly = (int)(r % D);
         lz = (int)((r / D) % D);
     }
-    // fragments of the 32-voxel step at vb: a (dyT rows), b (shifted xT rows)
-    auto load = [&](int64_t vb, u32x4* a, u32x4* b) {
-        const int64_t v = vb + 8 * kq;  // this lane's 8 voxels v .. v + 7
+    // one step's raw operands: dyT slices, xT slices, adjacent elements and
+    // validity (voxels in the slice, neighbour slice exists, adjacent exists)
+    struct Ops {
+        u32x4 a[MT], b[NT];
+        uint32_t e[NT];
+        int n;
+        uint32_t bok, eok;
+    };
+    auto issue = [&](int64_t vb, Ops& o) {
+        const int64_t v = vb + 8 * kq;
         const bool live = v < vend;
-        const int nval = !live ? 0 : (vend - v >= 8 ? 8 : (int)(vend - v));
+        const int64_t vs = live ? v : vbeg;  // an in-range slice when past the end
+        o.n = !live ? 0 : (vend - v >= 8 ? 8 : (int)(vend - v));
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            a[m] = u32x4{0u, 0u, 0u, 0u};
-            const int co = 16 * m + row;
-            if (m < MT && co < Cout && live) {
-                a[m] = *reinterpret_cast<const u32x4*>(dyT + tidx(co, v, Cout));
-                if (nval < 8) a[m] = keep_first(a[m], nval);
-            }
-        }
+        for (int m = 0; m < MT; ++m) o.a[m] = *reinterpret_cast<const u32x4*>(dyT + tidx(coc[m], vs, Cout));
         if (R8) {
-            // lattice coordinates of v, then advanced by the 32-voxel step for the next call
             const int x0 = lx, y = ly, z = lz;
-            lx += 32;
-            while (lx >= D) {
-                lx -= D;
-                if (++ly == D) {
-                    ly = 0;
-                    if (++lz == D) lz = 0;
-                }
-            }
+            const int xs = lx + 32;
+            const int q = small_div(xs, rd);  // rows crossed
+            lx = xs - q * D;
+            const int ys = ly + q;
+            const int q2 = ys >= D ? 1 : 0;  // q <= 4 <= D: at most one plane crossed
+            ly = ys - q2 * D;
+            lz = lz + q2 >= D ? lz + q2 - D : lz + q2;
             const bool ok = live && y + dyo >= 0 && y + dyo < D && z + dz >= 0 && z + dz < D;
-            const int64_t nb = v + ((int64_t)dz * D + dyo) * D;
+            const int64_t nb = ok ? v + ((int64_t)dz * D + dyo) * D : vs;
+            const bool eok = ok && (dx > 0 ? x0 + 8 < D : (dx < 0 ? x0 > 0 : false));
+            const int64_t ne = eok ? (dx > 0 ? nb + 8 : nb - 1) : nb;
+            o.bok = ok ? 1u : 0u;
+            o.eok = eok ? 1u : 0u;
 #pragma unroll
-            for (int n = 0; n < 4; ++n) {
-                b[n] = u32x4{0u, 0u, 0u, 0u};
-                const int ci = 16 * n + row;
-                if (n < NTc && ci < Cin && ok) {
-                    const u32x4 wq = *reinterpret_cast<const u32x4*>(xT + tidx(ci, nb, Cin));
-                    if (dx == 0) {
-                        b[n] = wq;
-                    } else if (dx > 0) {
-                        const uint32_t e = x0 + 8 < D ? (uint32_t)xT[tidx(ci, nb + 8, Cin)] : 0u;
-                        b[n] = u32x4{(wq[0] >> 16) | (wq[1] << 16), (wq[1] >> 16) | (wq[2] << 16),
-                                     (wq[2] >> 16) | (wq[3] << 16), (wq[3] >> 16) | (e << 16)};
-                    } else {
-                        const uint32_t e = x0 > 0 ? (uint32_t)xT[tidx(ci, nb - 1, Cin)] : 0u;
-                        b[n] = u32x4{e | (wq[0] << 16), (wq[0] >> 16) | (wq[1] << 16),
-                                     (wq[1] >> 16) | (wq[2] << 16), (wq[2] >> 16) | (wq[3] << 16)};
-                    }
-                }
+            for (int n = 0; n < NT; ++n) {
+                o.b[n] = *reinterpret_cast<const u32x4*>(xT + tidx(cic[n], nb, Cin));
+                o.e[n] = xT[tidx(cic[n], ne, Cin)];
             }
         } else {
             int64_t nv[8];
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 nv[i] = -1;
-                if (i < nval) {
+                if (i < o.n) {
                     const int64_t vv = v + i;
                     const int64_t bb = vv / D3;
                     const int rr = (int)(vv - bb * D3);
@@ -394,39 +418,57 @@ __global__ __launch_bounds__(64 * WG_WAVES) void k_conv_wgrad(const u16* __restr
                 }
             }
 #pragma unroll
-            for (int n = 0; n < 4; ++n) {
+            for (int n = 0; n < NT; ++n) {
                 u16 h[8];
-                const int ci = 16 * n + row;
 #pragma unroll
-                for (int i = 0; i < 8; ++i)
-                    h[i] = (n < NTc && ci < Cin && nv[i] >= 0) ? xT[tidx(ci, nv[i], Cin)] : (u16)0;
-                b[n] = pack8(h);
+                for (int i = 0; i < 8; ++i) h[i] = nv[i] >= 0 ? xT[tidx(cic[n], nv[i], Cin)] : (u16)0;
+                o.b[n] = pack8(h);
+                o.e[n] = 0u;
             }
+            o.bok = 1u;
+            o.eok = 0u;
         }
     };
-    u32x4 a_next[4], b_next[4];
-    if (vbeg < vend) load(vbeg, a_next, b_next);
-    for (int64_t vb = vbeg; vb < vend; vb += 32) {
-        u32x4 a[4], b[4];
+    // consume one step: validity, tail and x-offset shift, then MT x NT MFMAs
+    auto mma = [&](Ops& o) {
+        u32x4 b[NT];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            a[m] = a_next[m];
-            b[m] = b_next[m];
+        for (int m = 0; m < MT; ++m)
+            o.a[m] = keep_first_n((cobits >> m) & 1u ? o.a[m] : u32x4{0u, 0u, 0u, 0u}, o.n);
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            const u32x4 wq = ((cibits >> n) & 1u) && o.bok ? o.b[n] : u32x4{0u, 0u, 0u, 0u};
+            const uint32_t en = o.eok ? (o.e[n] & 0xffffu) : 0u;
+            if (R8 && dx > 0)
+                b[n] = u32x4{(wq[0] >> 16) | (wq[1] << 16), (wq[1] >> 16) | (wq[2] << 16),
+                             (wq[2] >> 16) | (wq[3] << 16), (wq[3] >> 16) | (en << 16)};
+            else if (R8 && dx < 0)
+                b[n] = u32x4{en | (wq[0] << 16), (wq[0] >> 16) | (wq[1] << 16), (wq[1] >> 16) | (wq[2] << 16),
+                             (wq[2] >> 16) | (wq[3] << 16)};
+            else
+                b[n] = wq;
         }
-        if (vb + 32 < vend) load(vb + 32, a_next, b_next);  // in flight during this step's MFMAs
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+        for (int m = 0; m < MT; ++m)
 #pragma unroll
-            for (int n = 0; n < 4; ++n)
-                if (m < MT && n < NTc)
-                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a[m]), as_bf16x8(b[n]), acc[m][n],
-                                                                        0, 0, 0);
+            for (int n = 0; n < NT; ++n)
+                acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(o.a[m]), as_bf16x8(b[n]), acc[m][n], 0,
+                                                                    0, 0);
+    };
+    // two operand sets, steps taken in pairs (a step past the end is all zero):
+    // one set's loads are in flight while the other's MFMAs run
+    Ops o0, o1;
+    issue(vbeg, o0);
+    for (int64_t vb = vbeg; vb < vend; vb += 64) {
+        issue(vb + 32, o1);
+        mma(o0);
+        issue(vb + 64, o0);
+        mma(o1);
     }
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
+    for (int m = 0; m < MT; ++m)
 #pragma unroll
-        for (int n = 0; n < 4; ++n) {
-            if (m >= MT || n >= NTc) continue;
+        for (int n = 0; n < NT; ++n) {
             const int ci = 16 * n + row;
             if (ci >= Cin) continue;
 #pragma unroll
@@ -525,26 +567,67 @@ static unsigned blocks_for(int64_t n, int per)
     return (unsigned)b;
 }
 
+template <bool CVEC>
+static void launch_conv(int NT, unsigned grid, hipStream_t s, const u16* x, int Cin, const u16* w, int Kp,
+                        int Cout, const float* bias, int relu, const u16* mask, int D, int64_t V, u16* ybf,
+                        float* yf, int ycs, u16* yT, uint32_t rcin)
+{
+#define EFUNC_CONV(N)                                                                                         \
+    k_conv<CVEC, N><<<grid, CONV_BLOCK, 0, s>>>(x, Cin, w, Kp, Cout, bias, relu, mask, D, V, ybf, yf, ycs, yT, \
+                                                rcin)
+    switch (NT) {
+    case 1: EFUNC_CONV(1); break;
+    case 2: EFUNC_CONV(2); break;
+    case 3: EFUNC_CONV(3); break;
+    default: EFUNC_CONV(4); break;
+    }
+#undef EFUNC_CONV
+}
+
 hipError_t run_conv(const u16* x, int Cin, const u16* w, int Kp, int Cout, const float* bias, int relu,
                     const u16* mask, int D, int64_t V, u16* ybf, float* yf, int ycs, u16* yT, hipStream_t s)
 {
     const int64_t per_block = 16 * CONV_MB * (CONV_BLOCK / 64);
     const unsigned grid = (unsigned)((V + per_block - 1) / per_block);
+    const int NT = (Cout + 15) / 16;
     if (Cin % 8 == 0)
-        k_conv<true><<<grid, CONV_BLOCK, 0, s>>>(x, Cin, w, Kp, Cout, bias, relu, mask, D, V, ybf, yf, ycs, yT);
+        launch_conv<true>(NT, grid, s, x, Cin, w, Kp, Cout, bias, relu, mask, D, V, ybf, yf, ycs, yT,
+                          small_div_r(Cin));
     else
-        k_conv<false><<<grid, CONV_BLOCK, 0, s>>>(x, Cin, w, Kp, Cout, bias, relu, mask, D, V, ybf, yf, ycs, yT);
+        launch_conv<false>(NT, grid, s, x, Cin, w, Kp, Cout, bias, relu, mask, D, V, ybf, yf, ycs, yT,
+                           small_div_r(Cin));
     return hipGetLastError();
 }
 
 // Voxels per workgroup of the weight gradient, a multiple of the 32-voxel
-// MFMA step: about 256 chunks for large V (2304 workgroups of 3 waves, more
-// than two rounds at 2 waves per SIMD: measured faster than one full round
-// of longer waves, which leaves the load latency exposed).
+// MFMA step: about 256 chunks for large V (2304 workgroups of 3 waves).
 static int64_t wgrad_chunk(int64_t V)
 {
     int64_t c = ((V + 255) / 256 + 31) / 32 * 32;
     return c < 256 ? 256 : c;
+}
+
+template <bool R8>
+static void launch_wgrad(int MT, int NT, dim3 grid, hipStream_t s, const u16* xT, int Cin, const u16* dyT,
+                         int Cout, int D, int64_t V, int64_t chunk, uint32_t rd, float* dw)
+{
+#define EFUNC_WG(M, N) \
+    k_conv_wgrad<R8, M, N><<<grid, 64 * WG_WAVES, 0, s>>>(xT, Cin, dyT, Cout, D, V, chunk, rd, dw)
+#define EFUNC_WG_N(M)                 \
+    switch (NT) {                     \
+    case 1: EFUNC_WG(M, 1); break;    \
+    case 2: EFUNC_WG(M, 2); break;    \
+    case 3: EFUNC_WG(M, 3); break;    \
+    default: EFUNC_WG(M, 4); break;   \
+    }
+    switch (MT) {
+    case 1: EFUNC_WG_N(1); break;
+    case 2: EFUNC_WG_N(2); break;
+    case 3: EFUNC_WG_N(3); break;
+    default: EFUNC_WG_N(4); break;
+    }
+#undef EFUNC_WG_N
+#undef EFUNC_WG
 }
 
 hipError_t run_wgrad(const u16* xT, int Cin, const u16* dyT, int Cout, int D, int64_t V, float* dw,
@@ -552,10 +635,11 @@ hipError_t run_wgrad(const u16* xT, int Cin, const u16* dyT, int Cout, int D, in
 {
     const int64_t chunk = wgrad_chunk(V);
     const dim3 grid((unsigned)((V + chunk - 1) / chunk), 9);
+    const int MT = (Cout + 15) / 16, NT = (Cin + 15) / 16;
     if (D % 8 == 0)
-        k_conv_wgrad<true><<<grid, 64 * WG_WAVES, 0, s>>>(xT, Cin, dyT, Cout, D, V, chunk, dw);
+        launch_wgrad<true>(MT, NT, grid, s, xT, Cin, dyT, Cout, D, V, chunk, small_div_r(D), dw);
     else
-        k_conv_wgrad<false><<<grid, 64 * WG_WAVES, 0, s>>>(xT, Cin, dyT, Cout, D, V, chunk, dw);
+        launch_wgrad<false>(MT, NT, grid, s, xT, Cin, dyT, Cout, D, V, chunk, small_div_r(D), dw);
     return hipGetLastError();
 }
 
