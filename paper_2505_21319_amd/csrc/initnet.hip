@@ -57,21 +57,6 @@ __device__ __forceinline__ u32x4 pack8(const u16* h)
                  (uint32_t)h[4] | ((uint32_t)h[5] << 16), (uint32_t)h[6] | ((uint32_t)h[7] << 16)};
 }
 
-// Zero the elements n..7 of eight packed bf16 values.
-__device__ __forceinline__ u32x4 keep_first(u32x4 a, int n)
-{
-    u16 h[8];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        h[2 * i] = (u16)(a[i] & 0xffffu);
-        h[2 * i + 1] = (u16)(a[i] >> 16);
-    }
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-        if (i >= n) h[i] = 0;
-    return pack8(h);
-}
-
 // Workgroups are handed to the 8 XCDs round-robin by linear id.  Renumber
 // them so that XCD j works on the j-th contiguous eighth of the tiles: the
 // halo rows that neighbouring tiles share then stay in one XCD's L2.  A
@@ -316,154 +301,67 @@ __global__ __launch_bounds__(CONV_BLOCK) void k_conv(const u16* __restrict__ x, 
 }
 
 // dw[co][tap][ci] += sum_v dyT[co][v] xT[ci][nbr(v, tap)] from blocked
-// channel-major operands (tidx), so that a lane's 8 consecutive voxels of one
-// channel -- its MFMA k-slice -- are one aligned 16-byte load.  Workgroup =
-// three waves, the x-offsets -1, 0, +1 of one (dz, dy) pair (blockIdx.y) over
-// one chunk of voxels; each wave accumulates the Cout x Cin block of its tap
-// (MT x NT MFMA tiles, Cout <= 16 MT, Cin <= 16 NT) and adds it to dw once.
-// R8: D % 8 == 0, so the 8 voxels lie in one x-row and the neighbour's are
-// that row shifted by the tap's y/z offset and, for dx = +-1, by one element
-// (a funnel shift of the aligned load with the adjacent element, zero past
-// the row's ends).  As in k_conv, the loop's loads are unconditional from
-// in-range addresses, one step ahead, and zeroed by validity bits when
-// consumed.  Otherwise (any D, small lattices) every element's neighbour is
-// located on its own.
-template <bool R8, int MT, int NT>
+// channel-major operands (tidx), for any lattice size D: every element's
+// neighbour is located on its own (used for D % 8 != 0, small lattices;
+// k_conv_wgrad3 covers D % 8 == 0).  Workgroup = three waves, the x-offsets
+// -1, 0, +1 of one (dz, dy) pair over one chunk of voxels; each wave
+// accumulates the Cout x Cin block of its tap (MT x NT MFMA tiles) and adds it
+// to dw once.
+template <int MT, int NT>
 __global__ __launch_bounds__(64 * WG_WAVES) void k_conv_wgrad(const u16* __restrict__ xT, int Cin,
                                                                const u16* __restrict__ dyT, int Cout,
-                                                               int D, int64_t V, int64_t chunk, uint32_t rd,
+                                                               int D, int64_t V, int64_t chunk,
                                                                float* __restrict__ dw)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int tap = blockIdx.y * 3 + wv;
-    const int dz = tap / 9 - 1, dyo = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+    const unsigned wg = xcd_block(blockIdx.x, gridDim.x);
+    const int pair = (int)(wg % 9u);
+    const int tap = pair * 3 + wv;
     const int row = lane & 15, kq = lane >> 4;
-    const int64_t vbeg = (int64_t)blockIdx.x * chunk;
+    const int64_t vbeg = (int64_t)(wg / 9u) * chunk;
     const int64_t vend = vbeg + chunk < V ? vbeg + chunk : V;
     const int64_t D3 = (int64_t)D * D * D;
-    int coc[MT], cic[NT];  // this lane's channel rows, clamped into range
-    uint32_t cobits = 0u, cibits = 0u;
-#pragma unroll
-    for (int m = 0; m < MT; ++m) {
-        const int co = 16 * m + row;
-        coc[m] = co < Cout ? co : Cout - 1;
-        cobits |= (co < Cout ? 1u : 0u) << m;
-    }
-#pragma unroll
-    for (int n = 0; n < NT; ++n) {
-        const int ci = 16 * n + row;
-        cic[n] = ci < Cin ? ci : Cin - 1;
-        cibits |= (ci < Cin ? 1u : 0u) << n;
-    }
     f32x4 acc[MT][NT];
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
         for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    // R8: (x, y, z) of this lane's next voxel slice, advanced by 32 voxels per
-    // issue() (carries by multiply-high, no loop)
-    int lx = 0, ly = 0, lz = 0;
-    if (R8) {
-        const int64_t v = vbeg + 8 * kq;
-        const int64_t r = v / D;
-        lx = (int)(v - r * D);
-        ly = (int)(r % D);
-        lz = (int)((r / D) % D);
-    }
-    // one step's raw operands: dyT slices, xT slices, adjacent elements and
-    // validity (voxels in the slice, neighbour slice exists, adjacent exists)
-    struct Ops {
+    for (int64_t vb = vbeg; vb < vend; vb += 32) {
+        const int64_t v = vb + 8 * kq;  // this lane's 8 voxels v .. v + 7
+        const int nval = v >= vend ? 0 : (vend - v >= 8 ? 8 : (int)(vend - v));
         u32x4 a[MT], b[NT];
-        uint32_t e[NT];
-        int n;
-        uint32_t bok, eok;
-    };
-    auto issue = [&](int64_t vb, Ops& o) {
-        const int64_t v = vb + 8 * kq;
-        const bool live = v < vend;
-        const int64_t vs = live ? v : vbeg;  // an in-range slice when past the end
-        o.n = !live ? 0 : (vend - v >= 8 ? 8 : (int)(vend - v));
 #pragma unroll
-        for (int m = 0; m < MT; ++m) o.a[m] = *reinterpret_cast<const u32x4*>(dyT + tidx(coc[m], vs, Cout));
-        if (R8) {
-            const int x0 = lx, y = ly, z = lz;
-            const int xs = lx + 32;
-            const int q = small_div(xs, rd);  // rows crossed
-            lx = xs - q * D;
-            const int ys = ly + q;
-            const int q2 = ys >= D ? 1 : 0;  // q <= 4 <= D: at most one plane crossed
-            ly = ys - q2 * D;
-            lz = lz + q2 >= D ? lz + q2 - D : lz + q2;
-            const bool ok = live && y + dyo >= 0 && y + dyo < D && z + dz >= 0 && z + dz < D;
-            const int64_t nb = ok ? v + ((int64_t)dz * D + dyo) * D : vs;
-            const bool eok = ok && (dx > 0 ? x0 + 8 < D : (dx < 0 ? x0 > 0 : false));
-            const int64_t ne = eok ? (dx > 0 ? nb + 8 : nb - 1) : nb;
-            o.bok = ok ? 1u : 0u;
-            o.eok = eok ? 1u : 0u;
-#pragma unroll
-            for (int n = 0; n < NT; ++n) {
-                o.b[n] = *reinterpret_cast<const u32x4*>(xT + tidx(cic[n], nb, Cin));
-                o.e[n] = xT[tidx(cic[n], ne, Cin)];
-            }
-        } else {
-            int64_t nv[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                nv[i] = -1;
-                if (i < o.n) {
-                    const int64_t vv = v + i;
-                    const int64_t bb = vv / D3;
-                    const int rr = (int)(vv - bb * D3);
-                    nv[i] = neighbour(bb, rr / (D * D), (rr / D) % D, rr % D, tap, D);
-                }
-            }
-#pragma unroll
-            for (int n = 0; n < NT; ++n) {
-                u16 h[8];
-#pragma unroll
-                for (int i = 0; i < 8; ++i) h[i] = nv[i] >= 0 ? xT[tidx(cic[n], nv[i], Cin)] : (u16)0;
-                o.b[n] = pack8(h);
-                o.e[n] = 0u;
-            }
-            o.bok = 1u;
-            o.eok = 0u;
+        for (int m = 0; m < MT; ++m) {
+            const int co = 16 * m + row;
+            a[m] = u32x4{0u, 0u, 0u, 0u};
+            if (co < Cout && nval > 0)
+                a[m] = keep_first_n(*reinterpret_cast<const u32x4*>(dyT + tidx(co, v, Cout)), nval);
         }
-    };
-    // consume one step: validity, tail and x-offset shift, then MT x NT MFMAs
-    auto mma = [&](Ops& o) {
-        u32x4 b[NT];
+        int64_t nv[8];
 #pragma unroll
-        for (int m = 0; m < MT; ++m)
-            o.a[m] = keep_first_n((cobits >> m) & 1u ? o.a[m] : u32x4{0u, 0u, 0u, 0u}, o.n);
+        for (int i = 0; i < 8; ++i) {
+            nv[i] = -1;
+            if (i < nval) {
+                const int64_t vv = v + i;
+                const int64_t bb = vv / D3;
+                const int rr = (int)(vv - bb * D3);
+                nv[i] = neighbour(bb, rr / (D * D), (rr / D) % D, rr % D, tap, D);
+            }
+        }
 #pragma unroll
         for (int n = 0; n < NT; ++n) {
-            const u32x4 wq = ((cibits >> n) & 1u) && o.bok ? o.b[n] : u32x4{0u, 0u, 0u, 0u};
-            const uint32_t en = o.eok ? (o.e[n] & 0xffffu) : 0u;
-            if (R8 && dx > 0)
-                b[n] = u32x4{(wq[0] >> 16) | (wq[1] << 16), (wq[1] >> 16) | (wq[2] << 16),
-                             (wq[2] >> 16) | (wq[3] << 16), (wq[3] >> 16) | (en << 16)};
-            else if (R8 && dx < 0)
-                b[n] = u32x4{en | (wq[0] << 16), (wq[0] >> 16) | (wq[1] << 16), (wq[1] >> 16) | (wq[2] << 16),
-                             (wq[2] >> 16) | (wq[3] << 16)};
-            else
-                b[n] = wq;
+            u16 h[8];
+            const int ci = 16 * n + row;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) h[i] = (ci < Cin && nv[i] >= 0) ? xT[tidx(ci, nv[i], Cin)] : (u16)0;
+            b[n] = pack8(h);
         }
 #pragma unroll
         for (int m = 0; m < MT; ++m)
 #pragma unroll
             for (int n = 0; n < NT; ++n)
-                acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(o.a[m]), as_bf16x8(b[n]), acc[m][n], 0,
-                                                                    0, 0);
-    };
-    // two operand sets, steps taken in pairs (a step past the end is all zero):
-    // one set's loads are in flight while the other's MFMAs run
-    Ops o0, o1;
-    issue(vbeg, o0);
-    for (int64_t vb = vbeg; vb < vend; vb += 64) {
-        issue(vb + 32, o1);
-        mma(o0);
-        issue(vb + 64, o0);
-        mma(o1);
+                acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a[m]), as_bf16x8(b[n]), acc[m][n], 0, 0,
+                                                                    0);
     }
 #pragma unroll
     for (int m = 0; m < MT; ++m)
@@ -477,6 +375,155 @@ __global__ __launch_bounds__(64 * WG_WAVES) void k_conv_wgrad(const u16* __restr
                 if (co < Cout) unsafeAtomicAdd(&dw[((int64_t)co * 27 + tap) * Cin + ci], acc[m][n][r]);
             }
         }
+}
+
+// The weight gradient for D % 8 == 0: one wave per (chunk of voxels, (dz, dy)
+// pair) covers the pair's three x-offsets.  The three taps read the same dyT
+// slices and the same neighbour-row xT slice; the x-offsets -1 / +1 are
+// funnel shifts of that slice with the element before / after it (zero past
+// the row's ends).  One set of loads feeds 3 x MT x NT MFMAs, a third of the
+// operand traffic of a wave per tap.  Loads, validity and the two operand
+// sets as in k_conv_wgrad.
+template <int MT, int NT>
+__global__ __launch_bounds__(64) void k_conv_wgrad3(const u16* __restrict__ xT, int Cin,
+                                                     const u16* __restrict__ dyT, int Cout, int D, int64_t V,
+                                                     int64_t chunk, uint32_t rd, float* __restrict__ dw)
+{
+    const int lane = threadIdx.x & 63;
+    const int row = lane & 15, kq = lane >> 4;
+    const unsigned wg = xcd_block(blockIdx.x, gridDim.x);  // the nine pairs of a chunk: one XCD
+    const int pair = (int)(wg % 9u);
+    const int dz = pair / 3 - 1, dyo = pair % 3 - 1;
+    const int64_t vbeg = (int64_t)(wg / 9u) * chunk;
+    const int64_t vend = vbeg + chunk < V ? vbeg + chunk : V;
+    int coc[MT], cic[NT];
+    uint32_t cobits = 0u, cibits = 0u;
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        const int co = 16 * m + row;
+        coc[m] = co < Cout ? co : Cout - 1;
+        cobits |= (co < Cout ? 1u : 0u) << m;
+    }
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+        const int ci = 16 * n + row;
+        cic[n] = ci < Cin ? ci : Cin - 1;
+        cibits |= (ci < Cin ? 1u : 0u) << n;
+    }
+    f32x4 acc[3][MT][NT];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int n = 0; n < NT; ++n) acc[d][m][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    int lx, ly, lz;  // (x, y, z) of this lane's next slice
+    {
+        const int64_t v = vbeg + 8 * kq;
+        const int64_t r = v / D;
+        lx = (int)(v - r * D);
+        ly = (int)(r % D);
+        lz = (int)((r / D) % D);
+    }
+    struct Ops {
+        u32x4 a[MT], b[NT];
+        uint32_t el[NT], er[NT];
+        int n;
+        uint32_t ok, okl, okr;
+    };
+    auto issue = [&](int64_t vb, Ops& o) {
+        const int64_t v = vb + 8 * kq;
+        const bool live = v < vend;
+        const int64_t vs = live ? v : vbeg;
+        o.n = live ? 8 : 0;  // V % 8 == 0: a live slice is whole
+#pragma unroll
+        for (int m = 0; m < MT; ++m) o.a[m] = *reinterpret_cast<const u32x4*>(dyT + tidx(coc[m], vs, Cout));
+        const int x0 = lx, y = ly, z = lz;
+        const int xs = lx + 32;
+        const int q = small_div(xs, rd);
+        lx = xs - q * D;
+        const int ys = ly + q;
+        const int q2 = ys >= D ? 1 : 0;
+        ly = ys - q2 * D;
+        lz = lz + q2 >= D ? lz + q2 - D : lz + q2;
+        const bool ok = live && y + dyo >= 0 && y + dyo < D && z + dz >= 0 && z + dz < D;
+        const int64_t nb = ok ? v + ((int64_t)dz * D + dyo) * D : vs;
+        const bool okl = ok && x0 > 0, okr = ok && x0 + 8 < D;
+        const int64_t nl = okl ? nb - 1 : nb, nr = okr ? nb + 8 : nb;
+        o.ok = ok ? 1u : 0u;
+        o.okl = okl ? 1u : 0u;
+        o.okr = okr ? 1u : 0u;
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            o.b[n] = *reinterpret_cast<const u32x4*>(xT + tidx(cic[n], nb, Cin));
+            o.el[n] = xT[tidx(cic[n], nl, Cin)];
+            o.er[n] = xT[tidx(cic[n], nr, Cin)];
+        }
+    };
+    auto mma = [&](Ops& o) {
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+            o.a[m] = keep_first_n((cobits >> m) & 1u ? o.a[m] : u32x4{0u, 0u, 0u, 0u}, o.n);
+        u32x4 w[NT];
+#pragma unroll
+        for (int n = 0; n < NT; ++n) w[n] = ((cibits >> n) & 1u) && o.ok ? o.b[n] : u32x4{0u, 0u, 0u, 0u};
+        // dx = 0
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int n = 0; n < NT; ++n)
+                acc[1][m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(o.a[m]), as_bf16x8(w[n]), acc[1][m][n],
+                                                                       0, 0, 0);
+        // dx = -1: element i is the slice's element i - 1
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            const uint32_t e = o.okl ? (o.el[n] & 0xffffu) : 0u;
+            const u32x4 t = w[n];
+            const u32x4 b = {e | (t[0] << 16), (t[0] >> 16) | (t[1] << 16), (t[1] >> 16) | (t[2] << 16),
+                             (t[2] >> 16) | (t[3] << 16)};
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+                acc[0][m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(o.a[m]), as_bf16x8(b), acc[0][m][n],
+                                                                       0, 0, 0);
+        }
+        // dx = +1: element i is the slice's element i + 1
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            const uint32_t e = o.okr ? (o.er[n] & 0xffffu) : 0u;
+            const u32x4 t = w[n];
+            const u32x4 b = {(t[0] >> 16) | (t[1] << 16), (t[1] >> 16) | (t[2] << 16), (t[2] >> 16) | (t[3] << 16),
+                             (t[3] >> 16) | (e << 16)};
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+                acc[2][m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(o.a[m]), as_bf16x8(b), acc[2][m][n],
+                                                                       0, 0, 0);
+        }
+    };
+    Ops o0, o1;
+    issue(vbeg, o0);
+    for (int64_t vb = vbeg; vb < vend; vb += 64) {
+        issue(vb + 32, o1);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(o0);
+        issue(vb + 64, o0);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(o1);
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int n = 0; n < NT; ++n) {
+                const int ci = 16 * n + row;
+                if (ci >= Cin) continue;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int co = 16 * m + 4 * kq + r;
+                    if (co < Cout)
+                        unsafeAtomicAdd(&dw[((int64_t)co * 27 + pair * 3 + d) * Cin + ci], acc[d][m][n][r]);
+                }
+            }
 }
 
 constexpr int COLSUM_CHUNK = 8192;  // voxels per workgroup of the bias gradient
@@ -611,8 +658,11 @@ template <bool R8>
 static void launch_wgrad(int MT, int NT, dim3 grid, hipStream_t s, const u16* xT, int Cin, const u16* dyT,
                          int Cout, int D, int64_t V, int64_t chunk, uint32_t rd, float* dw)
 {
-#define EFUNC_WG(M, N) \
-    k_conv_wgrad<R8, M, N><<<grid, 64 * WG_WAVES, 0, s>>>(xT, Cin, dyT, Cout, D, V, chunk, rd, dw)
+#define EFUNC_WG(M, N)                                                                                              \
+    if (R8)                                                                                                         \
+        k_conv_wgrad3<M, N><<<grid, 64, 0, s>>>(xT, Cin, dyT, Cout, D, V, chunk, rd, dw);                          \
+    else                                                                                                            \
+        k_conv_wgrad<M, N><<<dim3(grid.x), 64 * WG_WAVES, 0, s>>>(xT, Cin, dyT, Cout, D, V, chunk, dw)
 #define EFUNC_WG_N(M)                 \
     switch (NT) {                     \
     case 1: EFUNC_WG(M, 1); break;    \
@@ -633,13 +683,18 @@ static void launch_wgrad(int MT, int NT, dim3 grid, hipStream_t s, const u16* xT
 hipError_t run_wgrad(const u16* xT, int Cin, const u16* dyT, int Cout, int D, int64_t V, float* dw,
                      hipStream_t s)
 {
-    const int64_t chunk = wgrad_chunk(V);
-    const dim3 grid((unsigned)((V + chunk - 1) / chunk), 9);
     const int MT = (Cout + 15) / 16, NT = (Cin + 15) / 16;
-    if (D % 8 == 0)
+    if (D % 8 == 0) {
+        // about 222 chunks x 9 pairs = 2 rounds of one wave per SIMD on 1024 SIMDs
+        int64_t chunk = ((V + 221) / 222 + 31) / 32 * 32;
+        if (chunk < 256) chunk = 256;
+        const dim3 grid((unsigned)((V + chunk - 1) / chunk) * 9);
         launch_wgrad<true>(MT, NT, grid, s, xT, Cin, dyT, Cout, D, V, chunk, small_div_r(D), dw);
-    else
+    } else {
+        const int64_t chunk = wgrad_chunk(V);
+        const dim3 grid((unsigned)((V + chunk - 1) / chunk) * 9);
         launch_wgrad<false>(MT, NT, grid, s, xT, Cin, dyT, Cout, D, V, chunk, small_div_r(D), dw);
+    }
     return hipGetLastError();
 }
 
