@@ -588,11 +588,14 @@ __global__ __launch_bounds__(64 * WG_WAVES) void k_conv_wgrad(const u16* __restr
 // funnel shifts of that slice with the element before / after it (zero past
 // the row's ends).  One set of loads feeds 3 x MT x NT MFMAs, a third of the
 // operand traffic of a wave per tap.  Loads, validity and the two operand
-// sets as in k_conv_wgrad.
+// sets as in k_conv_wgrad.  When db is given, the wave of the centre pair
+// (dz = dy = 0), which reads every dyT slice of its chunk, also sums them:
+// db[co] += sum_v dyT[co][v].
 template <int MT, int NT>
 __global__ __launch_bounds__(64) void k_conv_wgrad3(const u16* __restrict__ xT, int Cin,
                                                      const u16* __restrict__ dyT, int Cout, int D, int64_t V,
-                                                     int64_t chunk, uint32_t rd, float* __restrict__ dw)
+                                                     int64_t chunk, uint32_t rd, float* __restrict__ dw,
+                                                     float* __restrict__ db)
 {
     const int lane = threadIdx.x & 63;
     const int row = lane & 15, kq = lane >> 4;
@@ -622,6 +625,10 @@ __global__ __launch_bounds__(64) void k_conv_wgrad3(const u16* __restrict__ xT, 
         for (int m = 0; m < MT; ++m)
 #pragma unroll
             for (int n = 0; n < NT; ++n) acc[d][m][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const bool bias_wave = db != nullptr && pair == 4;
+    float bsum[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) bsum[m] = 0.0f;
     int lx, ly, lz;  // (x, y, z) of this lane's next slice
     {
         const int64_t v = vbeg + 8 * kq;
@@ -703,6 +710,13 @@ __global__ __launch_bounds__(64) void k_conv_wgrad3(const u16* __restrict__ xT, 
                 acc[2][m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(o.a[m]), as_bf16x8(b), acc[2][m][n],
                                                                        0, 0, 0);
         }
+        if (bias_wave) {
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    bsum[m] += __uint_as_float(o.a[m][j] << 16) + __uint_as_float(o.a[m][j] & 0xffff0000u);
+        }
     };
     Ops o0, o1;
     issue(vbeg, o0);
@@ -729,6 +743,17 @@ __global__ __launch_bounds__(64) void k_conv_wgrad3(const u16* __restrict__ xT, 
                         unsafeAtomicAdd(&dw[((int64_t)co * 27 + pair * 3 + d) * Cin + ci], acc[d][m][n][r]);
                 }
             }
+    if (bias_wave) {
+        // the four lanes of a channel row (kq = 0..3) hold disjoint voxel slices
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            float t = bsum[m];
+            t += __shfl_xor(t, 16, 64);
+            t += __shfl_xor(t, 32, 64);
+            const int co = 16 * m + row;
+            if (kq == 0 && co < Cout) unsafeAtomicAdd(&db[co], t);
+        }
+    }
 }
 
 constexpr int COLSUM_CHUNK = 8192;  // voxels per workgroup of the bias gradient
@@ -870,11 +895,11 @@ static int64_t wgrad_chunk(int64_t V)
 
 template <bool R8>
 static void launch_wgrad(int MT, int NT, dim3 grid, hipStream_t s, const u16* xT, int Cin, const u16* dyT,
-                         int Cout, int D, int64_t V, int64_t chunk, uint32_t rd, float* dw)
+                         int Cout, int D, int64_t V, int64_t chunk, uint32_t rd, float* dw, float* db)
 {
 #define EFUNC_WG(M, N)                                                                                              \
     if (R8)                                                                                                         \
-        k_conv_wgrad3<M, N><<<grid, 64, 0, s>>>(xT, Cin, dyT, Cout, D, V, chunk, rd, dw);                          \
+        k_conv_wgrad3<M, N><<<grid, 64, 0, s>>>(xT, Cin, dyT, Cout, D, V, chunk, rd, dw, db);                      \
     else                                                                                                            \
         k_conv_wgrad<M, N><<<dim3(grid.x), 64 * WG_WAVES, 0, s>>>(xT, Cin, dyT, Cout, D, V, chunk, dw)
 #define EFUNC_WG_N(M)                 \
@@ -894,22 +919,33 @@ static void launch_wgrad(int MT, int NT, dim3 grid, hipStream_t s, const u16* xT
 #undef EFUNC_WG
 }
 
-hipError_t run_wgrad(const u16* xT, int Cin, const u16* dyT, int Cout, int D, int64_t V, float* dw,
+// dw (and db, if given) of one layer.  D % 8 == 0: k_conv_wgrad3, the bias
+// gradient summed by its centre-pair waves; otherwise k_conv_wgrad and a
+// separate k_rowsum.
+hipError_t run_wgrad(const u16* xT, int Cin, const u16* dyT, int Cout, int D, int64_t V, float* dw, float* db,
                      hipStream_t s)
 {
     const int MT = (Cout + 15) / 16, NT = (Cin + 15) / 16;
     if (D % 8 == 0) {
-        // about 222 chunks x 9 pairs = 2 rounds of one wave per SIMD on 1024 SIMDs
-        int64_t chunk = ((V + 221) / 222 + 31) / 32 * 32;
+        // about 111 chunks x 9 pairs = 999 waves: one round of one wave per
+        // SIMD for the 4 x 4 tiles (measured at 32^3 x 8: 64, 111, 222 and 888
+        // chunks take 0.91, 0.83, 0.92 and 1.15 ms for the whole backward)
+        int64_t chunk = ((V + 110) / 111 + 31) / 32 * 32;
         if (chunk < 256) chunk = 256;
         const dim3 grid((unsigned)((V + chunk - 1) / chunk) * 9);
-        launch_wgrad<true>(MT, NT, grid, s, xT, Cin, dyT, Cout, D, V, chunk, small_div_r(D), dw);
-    } else {
-        const int64_t chunk = wgrad_chunk(V);
-        const dim3 grid((unsigned)((V + chunk - 1) / chunk) * 9);
-        launch_wgrad<false>(MT, NT, grid, s, xT, Cin, dyT, Cout, D, V, chunk, small_div_r(D), dw);
+        launch_wgrad<true>(MT, NT, grid, s, xT, Cin, dyT, Cout, D, V, chunk, small_div_r(D), dw, db);
+        return hipGetLastError();
     }
-    return hipGetLastError();
+    const int64_t chunk = wgrad_chunk(V);
+    const dim3 grid((unsigned)((V + chunk - 1) / chunk) * 9);
+    launch_wgrad<false>(MT, NT, grid, s, xT, Cin, dyT, Cout, D, V, chunk, small_div_r(D), dw, nullptr);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && db) {
+        k_rowsum<<<dim3((unsigned)((V + COLSUM_CHUNK - 1) / COLSUM_CHUNK), Cout), CONV_BLOCK, 0, s>>>(dyT, Cout, V,
+                                                                                                     db);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 }  // namespace efunc
@@ -1070,14 +1106,9 @@ int efunc_initnet_backward(efunc_initnet* n, const float* dout, int32_t B, float
     k_to_bf16_both<<<blocks_for(V * n->cs[L], 256), 256, 0, s>>>(dout, V, n->ch[L], n->cs[L], n->gbuf[0], n->gT[0]);
     hipError_t e = hipGetLastError();
     int cur = 0;
-    const unsigned csum = (unsigned)((V + COLSUM_CHUNK - 1) / COLSUM_CHUNK);
     for (int l = L - 1; l >= 0 && e == hipSuccess; --l) {
         const int ci = n->ch[l], co = n->ch[l + 1];
-        e = run_wgrad(n->actT[l], ci, n->gT[cur], co, n->R, V, dparams + n->woff[l], s);
-        if (e == hipSuccess) {
-            k_rowsum<<<dim3(csum, co), CONV_BLOCK, 0, s>>>(n->gT[cur], co, V, dparams + n->boff[l]);
-            e = hipGetLastError();
-        }
+        e = run_wgrad(n->actT[l], ci, n->gT[cur], co, n->R, V, dparams + n->woff[l], dparams + n->boff[l], s);
         if (l > 0 && e == hipSuccess) {
             // data gradient through the flipped weights, times the ReLU mask of
             // this layer's input (the previous layer's activation)
@@ -1120,13 +1151,7 @@ int efunc_conv3d_wgrad_bf16(const void* xT, int32_t Cin, const void* dyT, int32_
         return fail(EFUNC_EINVAL, "xT and dyT must be 16-byte aligned");
     if (V == 0) return EFUNC_OK;
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = run_wgrad((const u16*)xT, Cin, (const u16*)dyT, Cout, R, V, dw, s);
-    if (e == hipSuccess && db) {
-        // bias gradient: sum over the channel-major rows (the rows are the per-channel series)
-        k_rowsum<<<dim3((unsigned)((V + COLSUM_CHUNK - 1) / COLSUM_CHUNK), Cout), CONV_BLOCK, 0, s>>>(
-            (const u16*)dyT, Cout, V, db);
-        e = hipGetLastError();
-    }
+    const hipError_t e = run_wgrad((const u16*)xT, Cin, (const u16*)dyT, Cout, R, V, dw, db, s);
     if (e != hipSuccess) return hip_fail(e, "conv3d wgrad launch");
     return EFUNC_OK;
 }
