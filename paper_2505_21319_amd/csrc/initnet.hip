@@ -591,19 +591,23 @@ __global__ __launch_bounds__(64 * WG_WAVES) void k_conv_wgrad(const u16* __restr
 // sets as in k_conv_wgrad.  When db is given, the wave of the centre pair
 // (dz = dy = 0), which reads every dyT slice of its chunk, also sums them:
 // db[co] += sum_v dyT[co][v].
-template <int MT, int NT>
-__global__ __launch_bounds__(64) void k_conv_wgrad3(const u16* __restrict__ xT, int Cin,
-                                                     const u16* __restrict__ dyT, int Cout, int D, int64_t V,
-                                                     int64_t chunk, uint32_t rd, float* __restrict__ dw,
-                                                     float* __restrict__ db)
+template <int MT, int NT, int WPC>
+__global__ __launch_bounds__(64 * WPC) void k_conv_wgrad3(const u16* __restrict__ xT, int Cin,
+                                                           const u16* __restrict__ dyT, int Cout, int D, int64_t V,
+                                                           int64_t chunk, uint32_t rd, float* __restrict__ dw,
+                                                           float* __restrict__ db)
 {
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int row = lane & 15, kq = lane >> 4;
     const unsigned wg = xcd_block(blockIdx.x, gridDim.x);  // the nine pairs of a chunk: one XCD
     const int pair = (int)(wg % 9u);
     const int dz = pair / 3 - 1, dyo = pair % 3 - 1;
-    const int64_t vbeg = (int64_t)(wg / 9u) * chunk;
-    const int64_t vend = vbeg + chunk < V ? vbeg + chunk : V;
+    // WPC waves split the chunk into contiguous parts (multiples of 32 voxels)
+    const int64_t part = chunk / WPC;
+    const int64_t cbeg = (int64_t)(wg / 9u) * chunk;
+    const int64_t cend = cbeg + chunk < V ? cbeg + chunk : V;
+    const int64_t vbeg = cbeg + wv * part < cend ? cbeg + wv * part : cend;
+    const int64_t vend = vbeg + part < cend ? vbeg + part : cend;
     int coc[MT], cic[NT];
     uint32_t cobits = 0u, cibits = 0u;
 #pragma unroll
@@ -646,7 +650,7 @@ __global__ __launch_bounds__(64) void k_conv_wgrad3(const u16* __restrict__ xT, 
     auto issue = [&](int64_t vb, Ops& o) {
         const int64_t v = vb + 8 * kq;
         const bool live = v < vend;
-        const int64_t vs = live ? v : vbeg;
+        const int64_t vs = live ? v : cbeg;  // cbeg < V: an in-range slice
         o.n = live ? 8 : 0;  // V % 8 == 0: a live slice is whole
 #pragma unroll
         for (int m = 0; m < MT; ++m) o.a[m] = *reinterpret_cast<const u32x4*>(dyT + tidx(coc[m], vs, Cout));
@@ -727,6 +731,42 @@ __global__ __launch_bounds__(64) void k_conv_wgrad3(const u16* __restrict__ xT, 
         issue(vb + 64, o0);
         __builtin_amdgcn_sched_barrier(0);
         mma(o1);
+    }
+    if (WPC > 1) {
+        // partial sums of waves 1 .. WPC-1 into LDS, added by wave 0
+        constexpr int NV = 3 * MT * NT * 4 + MT;  // values per lane
+        __shared__ float red[WPC > 1 ? (WPC - 1) * NV * 64 : 1];
+        if (wv > 0) {
+            float* dst = red + (wv - 1) * NV * 64 + lane;
+            int k = 0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+#pragma unroll
+                    for (int n = 0; n < NT; ++n)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) dst[64 * k++] = acc[d][m][n][r];
+#pragma unroll
+            for (int m = 0; m < MT; ++m) dst[64 * k++] = bsum[m];
+        }
+        __syncthreads();
+        if (wv > 0) return;
+#pragma unroll
+        for (int w = 1; w < WPC; ++w) {
+            const float* src = red + (w - 1) * NV * 64 + lane;
+            int k = 0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+#pragma unroll
+                    for (int n = 0; n < NT; ++n)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) acc[d][m][n][r] += src[64 * k++];
+#pragma unroll
+            for (int m = 0; m < MT; ++m) bsum[m] += src[64 * k++];
+        }
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d)
@@ -893,13 +933,22 @@ static int64_t wgrad_chunk(int64_t V)
     return c < 256 ? 256 : c;
 }
 
+// waves per chunk: 4 for the smallest tiles (MT NT <= 2), 1 otherwise
+template <int M, int N>
+static void launch_wgrad3(dim3 grid, hipStream_t s, const u16* xT, int Cin, const u16* dyT, int Cout, int D,
+                          int64_t V, int64_t chunk, uint32_t rd, float* dw, float* db)
+{
+    constexpr int W = M * N <= 2 ? 4 : 1;
+    k_conv_wgrad3<M, N, W><<<grid, 64 * W, 0, s>>>(xT, Cin, dyT, Cout, D, V, chunk, rd, dw, db);
+}
+
 template <bool R8>
 static void launch_wgrad(int MT, int NT, dim3 grid, hipStream_t s, const u16* xT, int Cin, const u16* dyT,
                          int Cout, int D, int64_t V, int64_t chunk, uint32_t rd, float* dw, float* db)
 {
 #define EFUNC_WG(M, N)                                                                                              \
     if (R8)                                                                                                         \
-        k_conv_wgrad3<M, N><<<grid, 64, 0, s>>>(xT, Cin, dyT, Cout, D, V, chunk, rd, dw, db);                      \
+        launch_wgrad3<M, N>(grid, s, xT, Cin, dyT, Cout, D, V, chunk, rd, dw, db);                                 \
     else                                                                                                            \
         k_conv_wgrad<M, N><<<dim3(grid.x), 64 * WG_WAVES, 0, s>>>(xT, Cin, dyT, Cout, D, V, chunk, dw)
 #define EFUNC_WG_N(M)                 \
@@ -927,10 +976,13 @@ hipError_t run_wgrad(const u16* xT, int Cin, const u16* dyT, int Cout, int D, in
 {
     const int MT = (Cout + 15) / 16, NT = (Cin + 15) / 16;
     if (D % 8 == 0) {
-        // about 111 chunks x 9 pairs = 999 waves: one round of one wave per
-        // SIMD for the 4 x 4 tiles (measured at 32^3 x 8: 64, 111, 222 and 888
-        // chunks take 0.91, 0.83, 0.92 and 1.15 ms for the whole backward)
-        int64_t chunk = ((V + 110) / 111 + 31) / 32 * 32;
+        // about 111 chunks x 9 pairs (measured at 32^3 x 8: 64, 111, 222 and
+        // 888 chunks take 0.91, 0.83, 0.92 and 1.15 ms for the whole
+        // backward).  The smallest tiles (MT NT <= 2) split each chunk over 4 waves
+        // of a workgroup and add their partial sums in LDS first: their steps
+        // are too short to cover a load's latency with one wave, and more
+        // chunks would multiply the atomics on their few outputs
+        int64_t chunk = ((V + 110) / 111 + 127) / 128 * 128;  // 4 parts of whole 32-voxel steps
         if (chunk < 256) chunk = 256;
         const dim3 grid((unsigned)((V + chunk - 1) / chunk) * 9);
         launch_wgrad<true>(MT, NT, grid, s, xT, Cin, dyT, Cout, D, V, chunk, small_div_r(D), dw, db);

@@ -111,10 +111,13 @@ def test_conv_data_gradient_matches_oracle(E, Cin, Cout, R):
 
 
 @pytest.mark.parametrize("Cin,Cout,R,B", [(1, 32, 6, 2), (32, 64, 5, 2), (64, 13, 4, 3), (13, 16, 3, 1),
-                                           (64, 64, 8, 2), (1, 32, 16, 1), (64, 13, 8, 3), (13, 64, 16, 1)])
+                                           (64, 64, 8, 2), (1, 32, 16, 1), (64, 13, 8, 3), (13, 64, 16, 1),
+                                           (1, 32, 56, 1), (64, 13, 56, 1)])
 def test_conv_weight_gradient_matches_oracle(E, Cin, Cout, R, B):
     """R a multiple of 8 takes the x-row path (shifted aligned loads), other R
-    the per-element path; several chunks of voxels per call at R = 16."""
+    the per-element path; several chunks of voxels per call at R = 16; at
+    R = 56 the last chunk is partial (with the smallest tiles, some of its
+    waves get no voxels)."""
     rng = np.random.default_rng(11 + Cout + R)
     x = N.bf16_round(rng.standard_normal((B, R, R, R, Cin)))
     dz = N.bf16_round(rng.standard_normal((B, R, R, R, Cout)))
