@@ -107,6 +107,34 @@ __device__ __forceinline__ void conv_epilogue(f32x4 (&acc)[CONV_MB][NT], int64_t
                                               const u16* __restrict__ mask, int64_t V, u16* __restrict__ ybf,
                                               float* __restrict__ yf, u16* __restrict__ yT)
 {
+    // the mask values first, all loads issued together from in-range
+    // addresses (one at a time behind the bounds branches below, each would
+    // wait for its own round trip)
+    uint32_t mk[NT][CONV_MB];  // bit r: mask of voxel 4 kq + r of tile m at channel t 16 + row is > 0
+    if (mask) {
+        u16 raw[NT][CONV_MB][4];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int co = t * 16 + row;
+            const int cc = co < Cout ? co : 0;
+#pragma unroll
+            for (int m = 0; m < CONV_MB; ++m)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t v = vw + 16 * m + 4 * kq + r;
+                    raw[t][m][r] = mask[(v < V ? v : 0) * ycs + cc];
+                }
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int m = 0; m < CONV_MB; ++m) {
+                uint32_t b = 0u;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) b |= (bf2f(raw[t][m][r]) > 0.0f ? 1u : 0u) << r;
+                mk[t][m] = b;
+            }
+    }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         const int co = t * 16 + row;
@@ -135,7 +163,7 @@ __device__ __forceinline__ void conv_epilogue(f32x4 (&acc)[CONV_MB][NT], int64_t
                 if (v >= V) continue;
                 float val = acc[m][t][r] + bb;
                 if (relu) val = fmaxf(val, 0.0f);
-                if (mask && !(bf2f(mask[v * ycs + co]) > 0.0f)) val = 0.0f;
+                if (mask && !((mk[t][m] >> r) & 1u)) val = 0.0f;
                 hv[r] = f2bf(val);
                 if (ybf) ybf[v * ycs + co] = hv[r];
                 if (yf) yf[v * ycs + co] = val;
