@@ -112,28 +112,26 @@ __device__ __forceinline__ void conv_epilogue(f32x4 (&acc)[CONV_MB][NT], int64_t
     // wait for its own round trip)
     uint32_t mk[NT][CONV_MB];  // bit r: mask of voxel 4 kq + r of tile m at channel t 16 + row is > 0
     if (mask) {
-        u16 raw[NT][CONV_MB][4];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
+        for (int t = 0; t < NT; ++t) {  // one batch of 16 loads per output tile
             const int co = t * 16 + row;
             const int cc = co < Cout ? co : 0;
+            u16 raw[CONV_MB][4];
 #pragma unroll
             for (int m = 0; m < CONV_MB; ++m)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int64_t v = vw + 16 * m + 4 * kq + r;
-                    raw[t][m][r] = mask[(v < V ? v : 0) * ycs + cc];
+                    raw[m][r] = mask[(v < V ? v : 0) * ycs + cc];
                 }
-        }
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
 #pragma unroll
             for (int m = 0; m < CONV_MB; ++m) {
                 uint32_t b = 0u;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) b |= (bf2f(raw[t][m][r]) > 0.0f ? 1u : 0u) << r;
+                for (int r = 0; r < 4; ++r) b |= (bf2f(raw[m][r]) > 0.0f ? 1u : 0u) << r;
                 mk[t][m] = b;
             }
+        }
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -197,7 +195,7 @@ __device__ __forceinline__ void conv_epilogue(f32x4 (&acc)[CONV_MB][NT], int64_t
 // the mask has the same layout) and, when yT is given, the blocked
 // channel-major bf16 copy yT (tidx) that the weight gradient reads.
 template <bool CVEC, int NT>
-__global__ __launch_bounds__(CONV_BLOCK) void k_conv(const u16* __restrict__ x, int Cin,
+__global__ __launch_bounds__(CONV_BLOCK, 2) void k_conv(const u16* __restrict__ x, int Cin,
                                                      const u16* __restrict__ w, int Kpad, int Cout,
                                                      const float* __restrict__ bias, int relu,
                                                      const u16* __restrict__ mask, int D, int64_t V,
