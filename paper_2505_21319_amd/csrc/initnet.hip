@@ -337,48 +337,40 @@ __global__ __launch_bounds__(CONV_BLOCK, 2) void k_conv(const u16* __restrict__ 
     conv_epilogue<NT>(acc, vw, row, kq, Cout, ycs, bias, relu, mask, V, ybf, yf, yT);
 }
 
-constexpr int SW3_LD = 3 * MAXC + 8;  // LDS row stride of one (dz, dy) pair's three taps (bf16)
+constexpr int ST_ROWS = 16 * CONV_MB * (CONV_BLOCK / 64) + 2;  // staged voxel rows: 256 + the two edges
+constexpr int SA_LD = 32 + 8;                                  // LDS row stride of a staged row (bf16)
+constexpr int SB_LD = 3 * 32 + 8;                              // LDS row stride of the staged weights
 
-// Rotate each 16-lane row of a u32x4 by one lane: up = 1 gives lane r the
-// value of lane r - 1 (lane 0 that of lane 15), up = 0 gives lane r that of
-// lane r + 1 (lane 15 that of lane 0).  DPP row_ror:1 / row_ror:15.
-template <bool UP>
-__device__ __forceinline__ u32x4 row_rotate(u32x4 v)
-{
-    u32x4 r;
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-        r[j] = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v[j], UP ? 0x121 : 0x12F, 0xF, 0xF, false);
-    return r;
-}
-
-// k_conv for Cin % 32 == 0 with the three x-offsets of a (dz, dy) pair taken
-// from one gather.  The 16 rows of an MFMA tile are 16 consecutive voxels,
-// so the A fragment of tap (dz, dy, dx = +-1) is the dx = 0 fragment moved
-// by one row: a rotate within each 16-lane DPP row, the row at the tile's
-// edge taken from the neighbouring tile (or, at the wave's edges, from the
-// voxel before / after the wave, gathered as well).  A row whose neighbour
-// at that tap lies outside the lattice -- including the x-row's ends, where
-// the rotated value belongs to another x-row -- is zeroed by the voxel's own
-// 27-bit mask.  K runs over the 9 (dz, dy) pairs x Cin / 32 channel slices;
-// the weights of a pair's three taps are staged in LDS per pair (double
-// buffered).  Per slice: CONV_MB + 2 gathers feed 3 x CONV_MB x NT MFMAs.
+// k_conv for Cin % 32 == 0 with the activations staged through LDS.  For one
+// (dz, dy) pair, the neighbour rows of the workgroup's 256 consecutive
+// voxels are one contiguous range of voxels shifted by the pair's offset,
+// plus one row on either side for dx = -1 / +1.  Each step -- a pair and a
+// 32-channel slice -- copies those 258 rows and the slice's weights of the
+// pair's three taps into LDS with coalesced 16-byte loads (double buffered:
+// the next step's loads are in flight during this step's MFMAs), then every
+// wave reads its A fragments for the three taps as rows r - 1, r, r + 1.
+// A row whose neighbour at that tap lies outside the lattice is zeroed by
+// the voxel's own 27-bit mask (rows outside [0, V) are read clamped).
 template <int NT>
-__global__ __launch_bounds__(CONV_BLOCK, 2) void k_conv3(const u16* __restrict__ x, int Cin,
-                                                      const u16* __restrict__ w, int Kpad, int Cout,
-                                                      const float* __restrict__ bias, int relu,
-                                                      const u16* __restrict__ mask, int D, int64_t V,
-                                                      u16* __restrict__ ybf, float* __restrict__ yf, int ycs,
-                                                      u16* __restrict__ yT)
+__global__ __launch_bounds__(CONV_BLOCK, 2) void k_conv4(const u16* __restrict__ x, int Cin,
+                                                         const u16* __restrict__ w, int Kpad, int Cout,
+                                                         const float* __restrict__ bias, int relu,
+                                                         const u16* __restrict__ mask, int D, int64_t V,
+                                                         u16* __restrict__ ybf, float* __restrict__ yf, int ycs,
+                                                         u16* __restrict__ yT)
 {
-    __shared__ __attribute__((aligned(16))) u16 sw[2][MAXC * SW3_LD];
+    __shared__ __attribute__((aligned(16))) u16 sa[2][ST_ROWS * SA_LD];
+    __shared__ __attribute__((aligned(16))) u16 sb[2][MAXC * SB_LD];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int row = lane & 15, kq = lane >> 4;
-    const int64_t vw = ((int64_t)xcd_block(blockIdx.x, gridDim.x) * (CONV_BLOCK / 64) + wv) * (16 * CONV_MB);
+    const int64_t vg = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (16 * CONV_MB * (CONV_BLOCK / 64));
+    const int64_t vw = vg + wv * (16 * CONV_MB);
     const int64_t D3 = (int64_t)D * D * D;
-    // 27-bit mask of the neighbours of voxel va inside the lattice (none past V)
-    auto nbr_mask = [&](int64_t va) {
-        uint32_t msk = 0u;
+    uint32_t nmask[CONV_MB];
+#pragma unroll
+    for (int m = 0; m < CONV_MB; ++m) {
+        const int64_t va = vw + 16 * m + row;
+        nmask[m] = 0u;
         if (va < V) {
             const int64_t bb = va / D3;
             const int rr = (int)(va - bb * D3);
@@ -388,72 +380,49 @@ __global__ __launch_bounds__(CONV_BLOCK, 2) void k_conv3(const u16* __restrict__
             const uint32_t mx = (xx > 0 ? 1u : 0u) | 2u | (xx < D - 1 ? 4u : 0u);
 #pragma unroll
             for (int t = 0; t < 27; ++t)
-                msk |= ((mz >> (t / 9)) & (my >> ((t / 3) % 3)) & (mx >> (t % 3)) & 1u) << t;
+                nmask[m] |= ((mz >> (t / 9)) & (my >> ((t / 3) % 3)) & (mx >> (t % 3)) & 1u) << t;
         }
-        return msk;
-    };
-    int64_t vrow[CONV_MB];
-    uint32_t nmask[CONV_MB];
-#pragma unroll
-    for (int m = 0; m < CONV_MB; ++m) {
-        const int64_t va = vw + 16 * m + row;
-        vrow[m] = va < V ? va : 0;
-        nmask[m] = nbr_mask(va);
     }
-    // the voxels just before and after the wave feed its first and last rows
-    // at dx = -1 / +1; whether they are needed depends on the wave's first /
-    // last voxel, the same in every lane (the rotate moves lane 15 / lane 0)
-    const uint32_t mfirst = nbr_mask(vw), mlast = nbr_mask(vw + 16 * CONV_MB - 1);
-    const int64_t vprev = vw > 0 && vw - 1 < V ? vw - 1 : 0;
-    const int64_t vnext = vw + 16 * CONV_MB < V ? vw + 16 * CONV_MB : 0;
-    const bool first = row == 0, last = row == 15;
     const int nslice = Cin / 32;
     const int nsteps = 9 * nslice;
-    // gather of step s = (pair, slice): centre rows of the CONV_MB tiles and
-    // the two edge voxels; addresses always in range (an invalid row reads
-    // the lane's own voxel, zeroed later by its mask)
-    struct Frag {
-        u32x4 c[CONV_MB], p, n;
-    };
-    auto gather = [&](int step, Frag& f) {
-        const bool in = step < nsteps;
-        const int pair = in ? step / nslice : 4;
-        const int ci = in ? (step - pair * nslice) * 32 + 8 * kq : 8 * kq;
+    // staging loads of step s into registers: 258 rows x 4 chunks of the
+    // activations (5 per thread, the last partial) and 64 rows x 12 chunks
+    // of the weights (3 per thread); all addresses in range
+    constexpr int NA = (ST_ROWS * 4 + CONV_BLOCK - 1) / CONV_BLOCK;
+    auto sload = [&](int step, u32x4* ra, u32x4* rw) {
+        const int st = step < nsteps ? step : nsteps - 1;
+        const int pair = st / nslice, cs = st - pair * nslice;
         const int64_t off = ((int64_t)(pair / 3 - 1) * D + (pair % 3 - 1)) * D;
-        const int tc = pair * 3 + 1;  // the pair's dx = 0 tap
 #pragma unroll
-        for (int m = 0; m < CONV_MB; ++m) {
-            const bool ok = in && ((nmask[m] >> tc) & 1u);
-            f.c[m] = *reinterpret_cast<const u32x4*>(x + (vrow[m] + (ok ? off : 0)) * Cin + ci);
-        }
-        // edge voxels: needed only where the wave's first / last voxel has
-        // its dx = -1 / +1 neighbour, which puts them in its x-row
-        const bool okp = in && ((mfirst >> (tc - 1)) & 1u);
-        const bool okn = in && ((mlast >> (tc + 1)) & 1u);
-        f.p = *reinterpret_cast<const u32x4*>(x + (okp ? vprev + off : vrow[0]) * Cin + ci);
-        f.n = *reinterpret_cast<const u32x4*>(x + (okn ? vnext + off : vrow[0]) * Cin + ci);
-    };
-    // weights of pair p's three taps: wf[co][3 p Cin .. 3 (p + 1) Cin) -> sw[buf][co][0 .. 3 Cin)
-    const int wchunks = 3 * Cin / 8;  // 16-byte chunks per row
-    auto wload = [&](int pair, u32x4* wr) {
-        const int pc = pair < 9 ? pair : 8;
-#pragma unroll
-        for (int j = 0; j < 6; ++j) {
+        for (int j = 0; j < NA; ++j) {
             const int i = threadIdx.x + j * CONV_BLOCK;
-            const int co = i / wchunks, c8 = i - co * wchunks;
+            const int r = i >> 2, c = i & 3;
+            int64_t u = vg + off - 1 + (r < ST_ROWS ? r : 0);
+            u = u < 0 ? 0 : (u >= V ? V - 1 : u);
+            ra[j] = *reinterpret_cast<const u32x4*>(x + u * Cin + 32 * cs + 8 * c);
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int i = threadIdx.x + j * CONV_BLOCK;
+            const int co = i / 12, c = i - co * 12;  // c: tap c / 4, chunk c % 4
             const int coc = co < Cout ? co : Cout - 1;
-            const int k = 3 * pc * Cin + 8 * c8;
-            wr[j] = *reinterpret_cast<const u32x4*>(w + (int64_t)coc * Kpad + (k < Kpad ? k : Kpad - 8));
+            const int k = (3 * pair + c / 4) * Cin + 32 * cs + 8 * (c % 4);
+            rw[j] = *reinterpret_cast<const u32x4*>(w + (int64_t)coc * Kpad + k);
         }
     };
-    auto wstore = [&](int buf, const u32x4* wr) {
+    auto sstore = [&](int buf, const u32x4* ra, const u32x4* rw) {
 #pragma unroll
-        for (int j = 0; j < 6; ++j) {
+        for (int j = 0; j < NA; ++j) {
             const int i = threadIdx.x + j * CONV_BLOCK;
-            const int co = i / wchunks, c8 = i - co * wchunks;
-            if (co < MAXC)
-                *reinterpret_cast<u32x4*>(&sw[buf][co * SW3_LD + 8 * c8]) =
-                    co < Cout ? wr[j] : u32x4{0u, 0u, 0u, 0u};
+            const int r = i >> 2, c = i & 3;
+            if (r < ST_ROWS) *reinterpret_cast<u32x4*>(&sa[buf][r * SA_LD + 8 * c]) = ra[j];
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int i = threadIdx.x + j * CONV_BLOCK;
+            const int co = i / 12, c = i - co * 12;
+            *reinterpret_cast<u32x4*>(&sb[buf][co * SB_LD + 32 * (c / 4) + 8 * (c % 4)]) =
+                co < Cout ? rw[j] : u32x4{0u, 0u, 0u, 0u};
         }
     };
     f32x4 acc[CONV_MB][NT];
@@ -461,71 +430,36 @@ __global__ __launch_bounds__(CONV_BLOCK, 2) void k_conv3(const u16* __restrict__
     for (int m = 0; m < CONV_MB; ++m)
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    // MFMAs of step s from fragment f: the three taps of its pair
-    auto mma = [&](int step, const Frag& f) {
+    u32x4 ra[NA], rw[3];
+    sload(0, ra, rw);
+    sstore(0, ra, rw);
+    for (int step = 0; step < nsteps; ++step) {
+        __syncthreads();  // buffer step & 1 complete; the other one is free
+        sload(step + 1, ra, rw);  // in flight during this step's MFMAs (clamped past the end)
+        __builtin_amdgcn_sched_barrier(0);
         const int pair = step / nslice;
-        const int cs = step - pair * nslice;
-        const int tc = pair * 3 + 1;
-        const u16* swb = sw[pair & 1];
+        const u16* A = sa[step & 1];
+        const u16* B = sb[step & 1];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
+            const int tap = 3 * pair + d;
             u32x4 a[CONV_MB];
 #pragma unroll
             for (int m = 0; m < CONV_MB; ++m) {
-                u32x4 v;
-                if (d == 1) {
-                    v = f.c[m];
-                } else if (d == 0) {  // dx = -1: row r takes row r - 1
-                    const u32x4 own = row_rotate<true>(f.c[m]);
-                    const u32x4 edge = row_rotate<true>(m > 0 ? f.c[m - 1] : f.p);
-                    v = first ? edge : own;
-                } else {  // dx = +1: row r takes row r + 1
-                    const u32x4 own = row_rotate<false>(f.c[m]);
-                    const u32x4 edge = row_rotate<false>(m < CONV_MB - 1 ? f.c[m + 1] : f.n);
-                    v = last ? edge : own;
-                }
-                a[m] = ((nmask[m] >> (tc - 1 + d)) & 1u) ? v : u32x4{0u, 0u, 0u, 0u};
+                const int r = wv * (16 * CONV_MB) + 16 * m + row + d;  // staged row of voxel + dx, dx = d - 1
+                const u32x4 v = *reinterpret_cast<const u32x4*>(A + r * SA_LD + 8 * kq);
+                a[m] = ((nmask[m] >> tap) & 1u) ? v : u32x4{0u, 0u, 0u, 0u};
             }
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                const u32x4 rb = *reinterpret_cast<const u32x4*>(swb + (t * 16 + row) * SW3_LD + d * Cin + 32 * cs +
-                                                                 8 * kq);
+                const u32x4 rb = *reinterpret_cast<const u32x4*>(B + (t * 16 + row) * SB_LD + 32 * d + 8 * kq);
 #pragma unroll
                 for (int m = 0; m < CONV_MB; ++m)
                     acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a[m]), as_bf16x8(rb), acc[m][t],
                                                                         0, 0, 0);
             }
         }
-    };
-    u32x4 wr[6];
-    wload(0, wr);
-    wstore(0, wr);
-    Frag f0, f1;
-    gather(0, f0);
-    // steps in pairs with two fragment sets; the weights of a (dz, dy) pair
-    // change every nslice steps (nslice = 1 or 2): a barrier at each pair
-    // boundary, the next pair's weights loaded during the current one
-    for (int s0 = 0; s0 < nsteps; s0 += 2) {
-        // step s0
-        if (s0 % nslice == 0) {
-            __syncthreads();  // sw[(s0 / nslice) & 1] complete; the other buffer is free
-            wload(s0 / nslice + 1, wr);
-        }
-        gather(s0 + 1, f1);
-        __builtin_amdgcn_sched_barrier(0);
-        mma(s0, f0);
-        if ((s0 + 1) % nslice == 0) wstore(((s0 + 1) / nslice) & 1, wr);
-        if (s0 + 1 < nsteps) {
-            // step s0 + 1
-            if ((s0 + 1) % nslice == 0) {
-                __syncthreads();
-                wload((s0 + 1) / nslice + 1, wr);
-            }
-            gather(s0 + 2, f0);
-            __builtin_amdgcn_sched_barrier(0);
-            mma(s0 + 1, f1);
-            if ((s0 + 2) % nslice == 0) wstore(((s0 + 2) / nslice) & 1, wr);
-        }
+        sstore((step + 1) & 1, ra, rw);
     }
     if (vw >= V) return;
     conv_epilogue<NT>(acc, vw, row, kq, Cout, ycs, bias, relu, mask, V, ybf, yf, yT);
@@ -934,14 +868,14 @@ hipError_t run_conv(const u16* x, int Cin, const u16* w, int Kp, int Cout, const
     const unsigned grid = (unsigned)((V + per_block - 1) / per_block);
     const int NT = (Cout + 15) / 16;
     if (Cin % 32 == 0) {
-#define EFUNC_CONV3(N) k_conv3<N><<<grid, CONV_BLOCK, 0, s>>>(x, Cin, w, Kp, Cout, bias, relu, mask, D, V, ybf, yf, ycs, yT)
+#define EFUNC_CONV4(N) k_conv4<N><<<grid, CONV_BLOCK, 0, s>>>(x, Cin, w, Kp, Cout, bias, relu, mask, D, V, ybf, yf, ycs, yT)
         switch (NT) {
-        case 1: EFUNC_CONV3(1); break;
-        case 2: EFUNC_CONV3(2); break;
-        case 3: EFUNC_CONV3(3); break;
-        default: EFUNC_CONV3(4); break;
+        case 1: EFUNC_CONV4(1); break;
+        case 2: EFUNC_CONV4(2); break;
+        case 3: EFUNC_CONV4(3); break;
+        default: EFUNC_CONV4(4); break;
         }
-#undef EFUNC_CONV3
+#undef EFUNC_CONV4
     } else if (Cin % 8 == 0)
         launch_conv<true>(NT, grid, s, x, Cin, w, Kp, Cout, bias, relu, mask, D, V, ybf, yf, ycs, yT,
                           small_div_r(Cin));
