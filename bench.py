@@ -537,7 +537,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build measures one GPU only: the fused fit step "
+        print(json.dumps({"error": "this benchmark measures one GPU only: the fused fit step "
                                    "runs on a single device; run with --gpus 1"}))
         sys.exit(2)
 

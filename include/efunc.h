@@ -60,7 +60,7 @@ extern "C" {
 #define EFUNC_EHIP (-2)         /* HIP runtime error (message names the call) */
 #define EFUNC_ESIZE (-3)        /* J > max_points of the context */
 #define EFUNC_ENONFINITE (-4)   /* check_finite found a NaN/Inf parameter or point */
-#define EFUNC_EUNSUPPORTED (-5) /* option not available in this build */
+#define EFUNC_EUNSUPPORTED (-5) /* option not supported by this library */
 
 typedef struct efunc_ctx efunc_ctx;
 
