@@ -90,3 +90,42 @@ def test_channel_counts_of_paper_variants():
     c.grid_keys, c.offsets = 0, 0
     with pytest.raises(E.EfuncError):
         E.efunc_channels(c)
+
+
+def test_network_and_convolution_arguments_are_rejected_before_any_device_work(L):
+    """The learned-initialiser entry points validate on the host: every call
+    here fails one check before a kernel could be launched (the pointers are
+    never dereferenced)."""
+    from paper_2505_21319_amd import efunc as E
+    fake = C.c_void_p(4096)       # 16-byte aligned, never touched
+    odd = C.c_void_p(4096 + 2)    # misaligned
+    out = C.c_void_p()
+    ch = (C.c_int32 * 3)(1, 16, 13)
+    assert L.efunc_initnet_create(1, 2, 2, ch, C.byref(out)) == E.EFUNC_EINVAL      # R < 2
+    assert L.efunc_initnet_create(8, 2, 0, ch, C.byref(out)) == E.EFUNC_EINVAL      # no layer
+    bad = (C.c_int32 * 3)(1, 65, 13)
+    assert L.efunc_initnet_create(8, 2, 2, bad, C.byref(out)) == E.EFUNC_EINVAL     # > 64 channels
+    assert b"channels[1] = 65" in L.efunc_last_error()
+    assert L.efunc_initnet_forward(None, fake, fake, 1, fake, None) == E.EFUNC_EINVAL
+    assert L.efunc_initnet_backward(None, fake, 1, fake, None) == E.EFUNC_EINVAL
+    # conv3d: NULL output, channel range, Kpad, V not a multiple of R^3, alignment
+    assert L.efunc_conv3d_bf16(fake, 16, fake, 448, 16, None, 0, None, 4, 64, None, None, None, None) \
+        == E.EFUNC_EINVAL
+    assert L.efunc_conv3d_bf16(fake, 65, fake, 1760, 16, None, 0, None, 4, 64, fake, None, None, None) \
+        == E.EFUNC_EINVAL
+    assert L.efunc_conv3d_bf16(fake, 16, fake, 440, 16, None, 0, None, 4, 64, fake, None, None, None) \
+        == E.EFUNC_EINVAL                                                              # Kpad % 32 != 0
+    assert L.efunc_conv3d_bf16(fake, 16, fake, 448, 16, None, 0, None, 4, 65, fake, None, None, None) \
+        == E.EFUNC_EINVAL                                                              # V % R^3 != 0
+    assert L.efunc_conv3d_bf16(odd, 16, fake, 448, 16, None, 0, None, 4, 64, fake, None, None, None) \
+        == E.EFUNC_EINVAL                                                              # x misaligned
+    assert b"16-byte" in L.efunc_last_error()
+    assert L.efunc_conv3d_bf16(fake, 16, fake, 448, 16, None, 0, None, 4, 64, None, None, odd, None) \
+        == E.EFUNC_EINVAL                                                              # yT misaligned
+    assert L.efunc_conv3d_wgrad_bf16(None, 16, fake, 16, 4, 64, fake, None, None) == E.EFUNC_EINVAL
+    assert L.efunc_conv3d_wgrad_bf16(fake, 16, odd, 16, 4, 64, fake, None, None) == E.EFUNC_EINVAL
+    assert L.efunc_conv3d_wgrad_bf16(fake, 0, fake, 16, 4, 64, fake, None, None) == E.EFUNC_EINVAL
+    assert L.efunc_conv3d_pack_weights(None, 16, 16, fake, fake, None) == E.EFUNC_EINVAL
+    assert L.efunc_adam_update(None, fake, fake, fake, 10, 1, None, None) == E.EFUNC_EINVAL
+    assert L.efunc_adam_update(fake, fake, fake, fake, 10, 0, None, None) == E.EFUNC_EINVAL  # step 0
+    assert L.efunc_loss_grad(None, fake, fake, fake, 10, fake, None, None) == E.EFUNC_EINVAL
