@@ -11,6 +11,10 @@
 // for the data gradient as wd[ci][k'], k' = tap' Cout + co with the flipped
 // tap' = 26 - tap, so that the data gradient is the same convolution of the
 // output gradient.  Both packed arrays pad k to a multiple of 32 with zeros.
+// Inside the network the channels-last rows have their channel count rounded
+// up to 8 (zero channels), and every layer input and output gradient also
+// has a blocked channel-major copy, element (c, v) at ((v / 32) C + c) 32 +
+// v % 32, that the weight gradient reads 8 voxels at a time.
 //
 // MFMA 16x16x32 bf16 lane layout (checked on the device): lane l supplies
 // A[l % 16][8 (l / 16) + i] and B[8 (l / 16) + i][l % 16], i = 0..7, and
@@ -35,7 +39,7 @@ constexpr int CONV_BLOCK = 256;   // 4 waves
 constexpr int CONV_MB = 4;        // 16-voxel MFMA row tiles per wave: 64 voxels per wave
 constexpr int CONV_KB = 64;       // k per LDS stage of the packed weights (two MFMA steps)
 constexpr int SW_LD = CONV_KB + 8;  // LDS row stride of the staged weights (bf16 elements)
-constexpr int WG_WAVES = 3;       // weight gradient: one wave per x-offset of a (dz, dy) pair
+constexpr int WG_WAVES = 3;       // general-lattice weight gradient: one wave per x-offset of a (dz, dy) pair
 constexpr int MAXC = 64;          // channels per layer
 
 // float -> bf16, round to nearest even (NaN stays NaN)
