@@ -309,6 +309,10 @@ int efunc_create(const efunc_config* cfg, int64_t max_points, efunc_ctx** out)
     ALLOC(w.prank, mp);
     ALLOC(w.pcount, w.NK * PSPLIT);
     ALLOC(w.pstart, w.NK * PSPLIT + 1);
+    // LDS binning: one histogram row per workgroup of at least LBIN_PER queries
+    w.lnw = (int)((mp + LBIN_PER - 1) / LBIN_PER < LBIN_NW ? (mp + LBIN_PER - 1) / LBIN_PER : LBIN_NW);
+    w.hist = nullptr;
+    if (w.NK <= LBIN_MAX) ALLOC(w.hist, (int64_t)w.lnw * w.NK);
     ALLOC(w.btiles, w.NB3);
     ALLOC(w.tstart, w.NB3 + 1);
     ALLOC(w.tiles, w.max_tiles);

@@ -15,6 +15,10 @@ constexpr int MAXSEG = 1024;    // moved-key row segments per window ((2W+1)^2, 
 constexpr int WMAX = 15;        // largest window half-width
 constexpr int SCAN_TILE = 1024; // elements per block in the prefix scans
 constexpr int PSPLIT = 8;       // sub-counters per cell in the query histogram
+constexpr int LBIN_MAX = 32768; // query sort keys one workgroup bins in LDS (128 KB of counters)
+constexpr int LBIN_BLOCK = 1024;  // threads per LDS-binning workgroup
+constexpr int LBIN_NW = 64;     // most LDS-binning workgroups (rows of the key histogram)
+constexpr int LBIN_PER = 4096;  // queries per LDS-binning workgroup at least
 constexpr int SLICE_KEYS = 8;   // slice-index sort keys per cost bucket in the tile order
 constexpr float LOG2E = 1.4426950408889634f;
 constexpr float LN2 = 0.6931471805599453f;
@@ -93,6 +97,8 @@ struct Work {
     int* prank;           // [max_points]
     int* pcount;          // [NK*PSPLIT] queries per (cell, sub-counter), block-major order
     int* pstart;          // [NK*PSPLIT+1]
+    int* hist;            // [lnw NK] per-workgroup query counts per sort key (NK <= LBIN_MAX), else null
+    int lnw;              // rows of hist
     int* btiles;          // [NB3]  tiles per cell block
     int* tstart;          // [NB3+1]
     int4* tiles;          // [max_tiles]  {first cell, first query, count, extent bits}, heaviest first
