@@ -65,7 +65,9 @@ __device__ float block_max(float v, float* sh)
     return r;
 }
 
-// Exclusive scan over the workgroup; *total receives the sum.  sh: BLOCK/64 slots.
+// Exclusive scan over a workgroup of NT threads; *total receives the sum.
+// sh: NT/64 slots.
+template <int NT = BLOCK>
 __device__ int block_excl_scan(int v, int* sh, int* total)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -80,7 +82,7 @@ __device__ int block_excl_scan(int v, int* sh, int* total)
     __syncthreads();
     int before = 0, tot = 0;
 #pragma unroll
-    for (int i = 0; i < BLOCK / 64; ++i) {
+    for (int i = 0; i < NT / 64; ++i) {
         before += (i < wid) ? sh[i] : 0;
         tot += sh[i];
     }
@@ -112,8 +114,13 @@ __global__ void k_fill_float(float* __restrict__ p, int64_t n)
         p[i] = 0.0f;
 }
 
-__global__ void k_reset_stats(DevStats* st)
+// Resets the statistics and zeroes a[0, na) and b[0, nb) (grid-stride).
+__global__ void k_reset_front(DevStats* st, int* __restrict__ a, int64_t na, int* __restrict__ b, int64_t nb)
 {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < na; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nb; i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = 0;
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         st->bmin_bits = 0x7f800000u;  // +inf
         st->bgmax_bits = 0u;
@@ -274,6 +281,51 @@ __global__ __launch_bounds__(BLOCK) void k_scan_reduce(const int* __restrict__ c
     }
     sx = block_sum(sx, sh);
     if (threadIdx.x == 0) blk[blockIdx.x] = sx;
+}
+
+// Exclusive scan of 1 <= n <= SCAN1_MAX counts by one workgroup, one launch
+// instead of three.  Thread t scans elements [SCAN1_PER t, SCAN1_PER (t + 1));
+// loads and stores are coalesced and pass through LDS, padded by one slot
+// per SCAN1_PER elements so that each thread's run is read and written
+// without bank conflicts.
+constexpr int SCAN1_BLOCK = 1024;
+constexpr int SCAN1_PER = 32;
+constexpr int SCAN1_MAX = SCAN1_BLOCK * SCAN1_PER;
+
+__global__ __launch_bounds__(SCAN1_BLOCK) void k_scan_single(const int* __restrict__ cnt, int n,
+                                                             int* __restrict__ start)
+{
+    __shared__ int sv[SCAN1_MAX + SCAN1_BLOCK];
+    __shared__ int sh[SCAN1_BLOCK / 64];
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < SCAN1_PER; ++k) {
+        const int i = k * SCAN1_BLOCK + t;
+        const int v = cnt[i < n ? i : n - 1];
+        sv[i + i / SCAN1_PER] = i < n ? v : 0;
+    }
+    __syncthreads();
+    int cx[SCAN1_PER];
+    int sx = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN1_PER; ++k) {
+        cx[k] = sv[t * (SCAN1_PER + 1) + k];
+        sx += cx[k];
+    }
+    int tx;
+    int ox = block_excl_scan<SCAN1_BLOCK>(sx, sh, &tx);  // synchronises before its LDS use
+#pragma unroll
+    for (int k = 0; k < SCAN1_PER; ++k) {
+        sv[t * (SCAN1_PER + 1) + k] = ox;
+        ox += cx[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < SCAN1_PER; ++k) {
+        const int i = k * SCAN1_BLOCK + t;
+        if (i < n) start[i] = sv[i + i / SCAN1_PER];
+    }
+    if (t == 0) start[n] = tx;
 }
 
 __global__ __launch_bounds__(BLOCK) void k_scan_blocks(int* __restrict__ blk, int nb)
@@ -1826,6 +1878,10 @@ static inline unsigned grid_for(int64_t n, int per = BLOCK)
 
 static hipError_t scan(const int* cnt, int64_t n, int* blk, int* start, hipStream_t s)
 {
+    if (n >= 1 && n <= SCAN1_MAX) {
+        k_scan_single<<<1, SCAN1_BLOCK, 0, s>>>(cnt, (int)n, start);
+        return hipGetLastError();
+    }
     const int nb = (int)((n + SCAN_TILE - 1) / SCAN_TILE);
     k_scan_reduce<<<nb, BLOCK, 0, s>>>(cnt, n, blk);
     k_scan_blocks<<<1, BLOCK, 0, s>>>(blk, nb);
@@ -1844,12 +1900,14 @@ hipError_t run_front(const Work& w, const Problem& p, Mode mode, bool ordered, h
 {
     const Geo& g = p.g;
     const int64_t I = w.I, C = w.C, J = p.J;
-    k_reset_stats<<<1, 64, 0, s>>>(w.st);
     // LDS binning of the queries (sort keys fit in one workgroup's LDS) or
-    // device atomics into PSPLIT sub-counters per key
+    // device atomics into PSPLIT sub-counters per key, which start from zero
+    // like the moved-key counters
     const bool lbin = w.hist != nullptr;
-    if (!lbin) k_fill_int<<<grid_for(w.NK * PSPLIT, BLOCK * 8), BLOCK, 0, s>>>(w.pcount, w.NK * PSPLIT, 0);
-    if (p.offsets) k_fill_int<<<grid_for(C, BLOCK * 8), BLOCK, 0, s>>>(w.mcount, C, 0);
+    {
+        const int64_t na = p.offsets ? C : 0, nb = lbin ? 0 : w.NK * PSPLIT;
+        k_reset_front<<<grid_for(na > nb ? na : nb, BLOCK * 8), BLOCK, 0, s>>>(w.st, w.mcount, na, w.pcount, nb);
+    }
     // keys
     switch (p.L.degree) {
     case 0:
