@@ -39,8 +39,9 @@ __device__ __forceinline__ float wave_max(float v)
     return v;
 }
 
-// Sum over the workgroup; every thread gets the total.  sh: BLOCK/64 slots.
-template <typename T>
+// Sum over a workgroup of NT threads; every thread gets the total.
+// sh: NT/64 slots.
+template <typename T, int NT = BLOCK>
 __device__ T block_sum(T v, T* sh)
 {
     v = wave_sum(v);
@@ -49,7 +50,7 @@ __device__ T block_sum(T v, T* sh)
     __syncthreads();
     T r = 0;
 #pragma unroll
-    for (int i = 0; i < BLOCK / 64; ++i) r += sh[i];
+    for (int i = 0; i < NT / 64; ++i) r += sh[i];
     return r;
 }
 
@@ -1669,21 +1670,34 @@ __global__ void k_count_uncertified(const DevStats* st, int64_t* out)
 }
 
 // ------------------------------------------------------------- loss, Adam
-__global__ __launch_bounds__(BLOCK) void k_loss_finalize(const double2* __restrict__ lpart,
-                                                         const int* __restrict__ ntiles,
-                                                         const DevStats* __restrict__ st,
-                                                         double invJ, double* __restrict__ out)
+// One workgroup of LF_BLOCK threads; each pass issues four partials' loads
+// per thread (clamped addresses, selected sums) ahead of the additions.
+constexpr int LF_BLOCK = 1024;
+
+__global__ __launch_bounds__(LF_BLOCK) void k_loss_finalize(const double2* __restrict__ lpart,
+                                                            const int* __restrict__ ntiles,
+                                                            const DevStats* __restrict__ st,
+                                                            double invJ, double* __restrict__ out)
 {
-    __shared__ double sh[BLOCK / 64];
+    __shared__ double sh[LF_BLOCK / 64];
     const int n = *ntiles;
     double s2 = 0.0, s1 = 0.0;
-    for (int t = threadIdx.x; t < n; t += BLOCK) {
-        const double2 v = lpart[t];
-        s2 += v.x;
-        s1 += v.y;
+    for (int t0 = threadIdx.x; t0 < n; t0 += 4 * LF_BLOCK) {
+        double2 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int t = t0 + u * LF_BLOCK;
+            v[u] = lpart[t < n ? t : n - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const bool ok = t0 + u * LF_BLOCK < n;
+            s2 += ok ? v[u].x : 0.0;
+            s1 += ok ? v[u].y : 0.0;
+        }
     }
-    s2 = block_sum(s2, sh);
-    s1 = block_sum(s1, sh);
+    s2 = block_sum<double, LF_BLOCK>(s2, sh);
+    s1 = block_sum<double, LF_BLOCK>(s1, sh);
     if (threadIdx.x == 0) {
         out[0] = (s2 + st->fb_loss[0]) * invJ;
         out[1] = (s1 + st->fb_loss[1]) * invJ;
@@ -2102,7 +2116,7 @@ hipError_t run_step_advance(int64_t* step, hipStream_t s)
 
 hipError_t run_loss_finalize(const Work& w, int64_t J, double* loss_out, hipStream_t s)
 {
-    k_loss_finalize<<<1, BLOCK, 0, s>>>(w.lpart, w.tstart + w.NB3, w.st, 1.0 / (double)J, loss_out);
+    k_loss_finalize<<<1, LF_BLOCK, 0, s>>>(w.lpart, w.tstart + w.NB3, w.st, 1.0 / (double)J, loss_out);
     return hipGetLastError();
 }
 
