@@ -54,6 +54,7 @@ __device__ T block_sum(T v, T* sh)
     return r;
 }
 
+template <int NT = BLOCK>
 __device__ float block_max(float v, float* sh)
 {
     v = wave_max(v);
@@ -62,7 +63,7 @@ __device__ float block_max(float v, float* sh)
     __syncthreads();
     float r = -INFINITY;
 #pragma unroll
-    for (int i = 0; i < BLOCK / 64; ++i) r = fmaxf(r, sh[i]);
+    for (int i = 0; i < NT / 64; ++i) r = fmaxf(r, sh[i]);
     return r;
 }
 
@@ -1479,12 +1480,16 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(DEG == 2 
 // ---------------------------------------------------------------- fallback
 // Queries whose certificate failed: one workgroup per query sweeps every key
 // (the global-support definition).  Keys are taken relative to the query.
+// The sweeps are load-latency bound with few queries in flight, so the
+// workgroups are 1024 threads wide.
+constexpr int FB_BLOCK = 1024;
+
 template <int MODE, bool QGRAD, int DEG>
 __device__ __forceinline__ void fallback_run(const TileArgs& a)
 {
     constexpr int GW = gk_width(DEG), MW = mk_width(DEG);
     constexpr int NV = DEG == 0 ? 1 : (DEG == 1 ? 4 : 10);
-    __shared__ float shf[BLOCK / 64];
+    __shared__ float shf[FB_BLOCK / 64];
     __shared__ int s_item;
     const int tid = threadIdx.x;
     const Geo& g = a.g;
@@ -1509,7 +1514,9 @@ __device__ __forceinline__ void fallback_run(const TileArgs& a)
                        int64_t& vid) {
             float4 q0 = make_float4(0, 0, 0, 0), q1 = make_float4(0, 0, 0, 0);
             if (ka < ng) {
-                const int ix = (int)(ka / ((int64_t)R * R)), iy = (int)((ka / R) % R), iz = (int)(ka % R);
+                // 32-bit division: ka < I <= 512^3 < 2^31
+                const uint32_t k32 = (uint32_t)ka, r = (uint32_t)R, kr = k32 / r;
+                const int ix = (int)(kr / r), iy = (int)(kr - (kr / r) * r), iz = (int)(k32 - kr * r);
                 const float4 a0 = a.gk[GW * ka], a1 = a.gk[GW * ka + 1];
                 if (DEG == 2) {
                     q0 = a.gk[GW * ka + 2];
@@ -1544,7 +1551,7 @@ __device__ __forceinline__ void fallback_run(const TileArgs& a)
         float O, lse2, gj = 0.0f;
         if (MODE != MODE_GRAD) {
             float M = -INFINITY;
-            for (int64_t ka = tid; ka < nkeys; ka += BLOCK) {
+            for (int64_t ka = tid; ka < nkeys; ka += FB_BLOCK) {
                 float dx, dy, dz, nb;
                 float4 kv;
                 KeyQ<DEG> kq;
@@ -1552,9 +1559,9 @@ __device__ __forceinline__ void fallback_run(const TileArgs& a)
                 key(ka, dx, dy, dz, nb, kv, kq, vid);
                 M = fmaxf(M, nb * fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
             }
-            M = block_max(M, shf);
+            M = block_max<FB_BLOCK>(M, shf);
             float e = 0.0f, m = 0.0f;
-            for (int64_t ka = tid; ka < nkeys; ka += BLOCK) {
+            for (int64_t ka = tid; ka < nkeys; ka += FB_BLOCK) {
                 float dx, dy, dz, nb;
                 float4 kv;
                 KeyQ<DEG> kq;
@@ -1564,8 +1571,8 @@ __device__ __forceinline__ void fallback_run(const TileArgs& a)
                 e += l;
                 m = fmaf(l, poly<DEG>(kv, kq, dx, dy, dz), m);
             }
-            e = block_sum(e, shf);
-            m = block_sum(m, shf);
+            e = block_sum<float, FB_BLOCK>(e, shf);
+            m = block_sum<float, FB_BLOCK>(m, shf);
             O = m / e;
             lse2 = M + log2f(e);
             if (MODE == MODE_FIT) {
@@ -1582,7 +1589,7 @@ __device__ __forceinline__ void fallback_run(const TileArgs& a)
             }
             if (MODE == MODE_EVAL && QGRAD) {
                 float gx = 0.0f, gy = 0.0f, gz = 0.0f;
-                for (int64_t ka = tid; ka < nkeys; ka += BLOCK) {
+                for (int64_t ka = tid; ka < nkeys; ka += FB_BLOCK) {
                     float dx, dy, dz, nb;
                     float4 kv;
                     KeyQ<DEG> kq;
@@ -1597,9 +1604,9 @@ __device__ __forceinline__ void fallback_run(const TileArgs& a)
                     gy += fmaf(w, fy, t * dy);
                     gz += fmaf(w, fz, t * dz);
                 }
-                gx = block_sum(gx, shf);
-                gy = block_sum(gy, shf);
-                gz = block_sum(gz, shf);
+                gx = block_sum<float, FB_BLOCK>(gx, shf);
+                gy = block_sum<float, FB_BLOCK>(gy, shf);
+                gz = block_sum<float, FB_BLOCK>(gz, shf);
                 if (tid == 0) {
                     const int j = a.pidx[sp];
                     a.dOdq_out[3 * (int64_t)j] = gx;
@@ -1614,7 +1621,7 @@ __device__ __forceinline__ void fallback_run(const TileArgs& a)
             gj = pq.w;
         }
         if (MODE != MODE_EVAL && gj != 0.0f) {
-            for (int64_t ka = tid; ka < nkeys; ka += BLOCK) {
+            for (int64_t ka = tid; ka < nkeys; ka += FB_BLOCK) {
                 float dx, dy, dz, nb;
                 float4 kv;
                 KeyQ<DEG> kq;
@@ -1650,13 +1657,13 @@ __device__ __forceinline__ void fallback_run(const TileArgs& a)
 }
 
 template <int MODE, bool QGRAD, int DEG>
-__global__ __launch_bounds__(BLOCK) void k_fallback(TileArgs a)
+__global__ __launch_bounds__(FB_BLOCK) void k_fallback(TileArgs a)
 {
     fallback_run<MODE, QGRAD, DEG>(a);
 }
 
 template <int DEG>
-__global__ __launch_bounds__(BLOCK) void k_fallback_batch(const TileArgs* __restrict__ tab, int S)
+__global__ __launch_bounds__(FB_BLOCK) void k_fallback_batch(const TileArgs* __restrict__ tab, int S)
 {
     for (int s = 0; s < S; ++s) {
         const TileArgs a = tab[s];
@@ -2021,23 +2028,23 @@ static void launch_tiles(const TileArgs& a, Mode mode, bool qgrad, unsigned grid
     case MODE_FIT:
         k_tile<MODE_FIT, false, DEG><<<grid, BLOCK, 0, s>>>(a);
         if (ev_stop) (void)hipEventRecord(ev_stop, s);
-        k_fallback<MODE_FIT, false, DEG><<<fgrid, BLOCK, 0, s>>>(a);
+        k_fallback<MODE_FIT, false, DEG><<<fgrid, FB_BLOCK, 0, s>>>(a);
         break;
     case MODE_EVAL:
         if (qgrad) {
             k_tile<MODE_EVAL, true, DEG><<<grid, BLOCK, 0, s>>>(a);
             if (ev_stop) (void)hipEventRecord(ev_stop, s);
-            k_fallback<MODE_EVAL, true, DEG><<<fgrid, BLOCK, 0, s>>>(a);
+            k_fallback<MODE_EVAL, true, DEG><<<fgrid, FB_BLOCK, 0, s>>>(a);
         } else {
             k_tile<MODE_EVAL, false, DEG><<<grid, BLOCK, 0, s>>>(a);
             if (ev_stop) (void)hipEventRecord(ev_stop, s);
-            k_fallback<MODE_EVAL, false, DEG><<<fgrid, BLOCK, 0, s>>>(a);
+            k_fallback<MODE_EVAL, false, DEG><<<fgrid, FB_BLOCK, 0, s>>>(a);
         }
         break;
     case MODE_GRAD:
         k_tile<MODE_GRAD, false, DEG><<<grid, BLOCK, 0, s>>>(a);
         if (ev_stop) (void)hipEventRecord(ev_stop, s);
-        k_fallback<MODE_GRAD, false, DEG><<<fgrid, BLOCK, 0, s>>>(a);
+        k_fallback<MODE_GRAD, false, DEG><<<fgrid, FB_BLOCK, 0, s>>>(a);
         break;
     }
 }
@@ -2077,7 +2084,7 @@ static void launch_batch(const TileArgs* tab, int S, const int2* gtiles, const i
 {
     k_tile_batch<DEG><<<grid, BLOCK, 0, s>>>(tab, gtiles, ngt, gqueue);
     if (ev_stop) (void)hipEventRecord(ev_stop, s);
-    k_fallback_batch<DEG><<<fgrid, BLOCK, 0, s>>>(tab, S);
+    k_fallback_batch<DEG><<<fgrid, FB_BLOCK, 0, s>>>(tab, S);
 }
 
 hipError_t run_batch_tiles(int degree, const TileArgs* tab, int S, const int2* gtiles, const int* ngt,
