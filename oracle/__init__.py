@@ -17,6 +17,7 @@ from .oracle import (  # noqa: F401
     build_keys,
     eval_global,
     eval_qgrad,
+    eval_qgrad_scales,
     eval_cond,
     eval_trunc,
     grad_global,

@@ -76,6 +76,14 @@ void oracle_eval_cond(const double* keys, int64_t nkeys, const double* q, int64_
 void oracle_eval_qgrad(const double* keys, int64_t nkeys, const double* q,
                        int64_t J, double* dOdq);
 
+/* Tolerance scales of dO/dq (not part of the method), J x 3 each, any may be
+ * NULL: qsig = sum_a w_a (|d_a| + 2 beta_a |x_a| |O - f_a|) per component (the
+ * magnitudes of the terms of Eq. func-normal); qkap = first-order change of
+ * dO/dq per unit relative error of the logits, values and O; qtail = the most
+ * that omitting the keys with weight below e^-T can change it. */
+void oracle_eval_qgrad_scales(const double* keys, int64_t nkeys, const double* q, int64_t J,
+                              double T, double* qsig, double* qkap, double* qtail);
+
 /* Key-parameter gradients of sum_j dLdO_j * O(q_j) (Sec. 3.6 closed forms),
  * global support, key-parallel as in Alg. 2.  gk/ak/bk: nkeys x 8 laid out as
  * dc.x dc.y dc.z dbeta do dd.x dd.y dd.z; ak holds sum_j |term| per entry

@@ -213,6 +213,79 @@ void ovar_eval_qgrad(const double* keys, int64_t nkeys, int degree, const double
     }
 }
 
+/* Magnitudes of the terms of df/dq = d + S x, per component. */
+static void value_grad_abs(const double* k, int degree, const double* x, double* g)
+{
+    g[0] = g[1] = g[2] = 0.0;
+    if (degree >= 1) {
+        g[0] = fabs(k[5]);
+        g[1] = fabs(k[6]);
+        g[2] = fabs(k[7]);
+    }
+    if (degree >= 2) {
+        const double sxx = k[8], syy = k[9], szz = k[10], sxy = k[11], sxz = k[12], syz = k[13];
+        g[0] += fabs(sxx * x[0]) + fabs(sxy * x[1]) + fabs(sxz * x[2]);
+        g[1] += fabs(sxy * x[0]) + fabs(syy * x[1]) + fabs(syz * x[2]);
+        g[2] += fabs(sxz * x[0]) + fabs(syz * x[1]) + fabs(szz * x[2]);
+    }
+}
+
+/* Tolerance scales of dO/dq (not part of the method), with g_ak the term of
+ * key a in Eq. func-normal and G_k = sum_a w_a g_ak:
+ *   qsig_k  = sum_a w_a (|df_a/dq_k terms| + 2 beta_a |x_ak| |O - f_a|);
+ *   qkap_k  = sum_a w_a [|s_a| |g_ak - G_k| + 2 beta_a |x_ak| (kappa + sigma + sigma_a)];
+ *   qtail_k = sum_{a: w_a < e^-T} w_a (|g_ak| + |G_k|) + tail sum_a 2 beta_a w_a |x_ak|. */
+void ovar_eval_qgrad_scales(const double* keys, int64_t nkeys, int degree, const double* q,
+                            int64_t J, double T, double* qsig, double* qkap, double* qtail)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t j = 0; j < J; ++j) {
+        const double* qj = q + 3 * j;
+        double O, lse, sig;
+        eval_one(keys, nkeys, degree, qj, &O, &lse, &sig);
+        double G[3] = {0.0, 0.0, 0.0}, kap = 0.0, tl = 0.0;
+        for (int64_t a = 0; a < nkeys; ++a) {
+            const double* k = keys + a * OVAR_KEY;
+            const double s = logit(k, qj);
+            const double w = exp(s - lse);
+            const double x[3] = {qj[0] - k[0], qj[1] - k[1], qj[2] - k[2]};
+            const double r = O - value(k, degree, qj, NULL);
+            double df[3];
+            value_grad(k, degree, x, df);
+            kap += w * fabs(s) * fabs(r);
+            if (s - lse < -T) tl += w * fabs(r);
+            for (int d = 0; d < 3; ++d) G[d] += w * (df[d] + 2.0 * k[3] * x[d] * r);
+        }
+        double qs[3] = {0.0, 0.0, 0.0}, qk[3] = {0.0, 0.0, 0.0}, qt[3] = {0.0, 0.0, 0.0};
+        double bx[3] = {0.0, 0.0, 0.0};
+        for (int64_t a = 0; a < nkeys; ++a) {
+            const double* k = keys + a * OVAR_KEY;
+            const double s = logit(k, qj);
+            const double w = exp(s - lse);
+            const double x[3] = {qj[0] - k[0], qj[1] - k[1], qj[2] - k[2]};
+            double sa;
+            const double r = O - value(k, degree, qj, &sa);
+            double df[3], dfa[3];
+            value_grad(k, degree, x, df);
+            value_grad_abs(k, degree, x, dfa);
+            const int below = s - lse < -T;
+            for (int d = 0; d < 3; ++d) {
+                const double ga = df[d] + 2.0 * k[3] * x[d] * r;
+                const double bxa = 2.0 * k[3] * w * fabs(x[d]);
+                qs[d] += w * dfa[d] + bxa * fabs(r);
+                qk[d] += w * fabs(s) * fabs(ga - G[d]) + bxa * (kap + sig + sa);
+                if (below) qt[d] += w * (fabs(ga) + fabs(G[d]));
+                bx[d] += bxa;
+            }
+        }
+        for (int d = 0; d < 3; ++d) {
+            if (qsig) qsig[3 * j + d] = qs[d];
+            if (qkap) qkap[3 * j + d] = qk[d];
+            if (qtail) qtail[3 * j + d] = qt[d] + tl * bx[d];
+        }
+    }
+}
+
 /* Sec. 3.6 generalised to f^0..f^2: with w the softmax weight, x = q - c,
  * r = f(x) - O and delta = dL/dO w:
  *   dL/dv_k   = delta * monomial_k(x)

@@ -28,6 +28,21 @@ MUTANTS = {
     "offset_sign": ("b[1] = ky + (double)p[6];", "b[1] = ky - (double)p[6];"),
     "lse_drops_max": ("*lse = M + log(e);", "*lse = log(e);"),
     "truncation_too_tight": ("if (s >= t->M - t->T) {", "if (s >= t->M - 0.5 * t->T) {"),
+    # the tolerance scales every parity check rests on
+    "sigma_not_normalised": ("*sigma = sa / e;", "*sigma = sa;"),
+    "trunc_sigma_x10": ("if (sigma) sigma[j] = t.sa / t.e;", "if (sigma) sigma[j] = 10.0 * t.sa / t.e;"),
+    "grad_scale_x10": ("const double adw = fabs(dl) * w;", "const double adw = 10.0 * fabs(dl) * w;"),
+    "trunc_grad_scale_x10": ("adw = fabs(dLdO[j]) * w;", "adw = 10.0 * fabs(dLdO[j]) * w;"),
+    "grad_scale_beta_drops_r": ("adw * x2n * fabs(r),", "adw * x2n,"),
+    "kappa_x100": ("k += wr * fabs(s);", "k += 100.0 * wr * fabs(s);"),
+    "tail_x10": ("if (s - lse < -T) tl += wr;", "if (s - lse < -T) tl += 10.0 * wr;"),
+    "subthreshold_wrong_side": ("const int below = lw < -T;", "const int below = lw > -T;"),
+    "qsig_drops_factor_2": ("const double bxa = 2.0 * k[3] * w * fabs(x);",
+                            "const double bxa = k[3] * w * fabs(x);"),
+    "qkap_x100": ("qk[d] += w * fabs(s) * fabs(ga - G[d])", "qk[d] += 100.0 * w * fabs(s) * fabs(ga - G[d])"),
+    "qkap_drops_value_errors": ("bxa * (kap + sig + sa)", "bxa * kap"),
+    "qtail_drops_renormalisation": ("if (below) qt[d] += w * (fabs(ga) + fabs(G[d]));",
+                                    "if (below) qt[d] += w * fabs(ga);"),
 }
 
 PINS = [getattr(P, n) for n in dir(P) if n.startswith("test_")]

@@ -513,3 +513,241 @@ def test_truncation_tail_scales(orc):
     assert np.all(t_hi == 0) and np.all(t_mid <= t_lo) and np.all(t_mid >= 0)
     # all keys: sum_a w_a |f_a - O| >= |sum_a w_a (f_a - O)| = 0, and <= 2 max |f|
     assert np.all(t_lo <= 2 * (np.abs(keys[:, 4]).max() + 4 * np.abs(keys[:, 5:]).max()))
+
+
+# ------------------------------------------------------------ tolerance scales
+# The parity tolerances rest on these scales, so each is tied to something the
+# oracle does not compute itself: the pinned value or gradient in a case where
+# every contribution has one sign (a sum of magnitudes then equals the sum),
+# closed forms of the two-key logistic blend (Sec. 3.1, Eq. nrbf), or finite
+# differences of the pinned evaluation.
+
+def _below_keys(rng, n, lo=-1.0, hi=-0.6, beta=(5.0, 40.0)):
+    """Keys centred in [lo, hi]^3 with non-negative values and slopes: for
+    queries in [0, 1]^3 every x = q - c is positive, so every term of
+    f_a = o_a + x . d_a is non-negative."""
+    keys = np.empty((n, 8))
+    keys[:, :3] = rng.uniform(lo, hi, (n, 3))
+    keys[:, 3] = rng.uniform(*beta, n)
+    keys[:, 4] = rng.uniform(0.0, 1.0, n)
+    keys[:, 5:] = rng.uniform(0.0, 1.0, (n, 3))
+    return keys
+
+
+def _two_key_parts(keys, q):
+    """Logits, polynomial values and logistic weights of a two-key set."""
+    s = [-k[3] * ((q - k[:3]) ** 2).sum(1) for k in keys]
+    f = [k[4] + (q - k[:3]) @ k[5:] for k in keys]
+    return s, f, sps.expit(s[0] - s[1]), sps.expit(s[1] - s[0])
+
+
+def _cancel(s, f):
+    """Absolute rounding allowance of |f_a - O| (computed as a difference of
+    numbers of size |f|) times the logit magnitudes."""
+    return 1e-14 * (np.abs(s[0]) + np.abs(s[1]) + 1.0) * (np.abs(f[0]) + np.abs(f[1]))
+
+
+TWO_KEYS = np.array([[-0.3, -0.2, -0.25, 12.0, 0.8, 0.5, -0.3, 0.2],
+                     [0.35, 0.3, 0.2, 20.0, -0.6, -0.4, 0.7, 0.1]])
+
+
+def test_sigma_equals_value_when_every_term_is_nonnegative(orc):
+    """sigma = sum_a w_a (|o_a| + sum_k |x_k| |d_ak|) equals O when no term is
+    negative, and is unchanged by flipping the signs of values and slopes."""
+    rng = np.random.default_rng(41)
+    keys = _below_keys(rng, 40)
+    q = rng.uniform(0.0, 1.0, (60, 3))
+    O, _, sig = orc.eval_global(keys, q)
+    assert np.allclose(sig, O, rtol=1e-13, atol=0)
+    mixed = keys.copy()
+    mixed[:, 4:] *= rng.choice([-1.0, 1.0], size=(40, 4))
+    Om, _, sm = orc.eval_global(mixed, q)
+    assert np.allclose(sm, O, rtol=1e-13, atol=0)
+    assert np.all(sm >= np.abs(Om)) and np.any(sm > 1.5 * np.abs(Om))
+
+
+def test_truncated_scales_equal_global_ones_when_nothing_is_dropped(orc):
+    """With a threshold no pair falls below, the truncated mode's value scale
+    and gradient scales are the (pinned) global ones."""
+    rng = np.random.default_rng(43)
+    R = 4
+    g = orc.Grid(R=R)
+    keys = orc.build_keys(g, W.perturbed_theta(R, 44, rho0=3.0))
+    q = rand_q(rng, 80)
+    dl = rng.standard_normal(80)
+    _, _, sig = orc.eval_global(keys, q)
+    _, _, sig_t = orc.eval_trunc(g, keys, q, 1e4)
+    assert np.allclose(sig_t, sig, rtol=1e-12, atol=0)
+    _, ak = orc.grad_global(keys, q, dl)
+    _, ak_t = orc.grad_trunc(g, keys, q, dl, 1e4)
+    assert np.allclose(ak_t, ak, rtol=1e-10, atol=1e-300)
+
+
+def test_kappa_two_key_closed_form(orc):
+    """Two keys: f_1 - O = w_2 (f_1 - f_2) and f_2 - O = w_1 (f_2 - f_1), so
+    kappa = w_1 w_2 |f_1 - f_2| (|s_1| + |s_2|)."""
+    rng = np.random.default_rng(45)
+    q = rand_q(rng, 80, -0.8, 0.8)
+    kap = orc.eval_cond(TWO_KEYS, q)
+    s, f, w1, w2 = _two_key_parts(TWO_KEYS, q)
+    ref = w1 * w2 * np.abs(f[0] - f[1]) * (np.abs(s[0]) + np.abs(s[1]))
+    assert np.all(np.abs(kap - ref) <= 1e-11 * ref + _cancel(s, f))
+
+
+def test_kappa_is_the_worst_case_logit_sensitivity(orc):
+    """Moving every logit by eps |s_a| towards the sign of f_a - O changes O by
+    eps kappa to first order; with f^1 values that move is a scaling of
+    beta_a by 1 - eps sign(f_a - O) (beta enters O only through the logits).
+    Each f_a is the pinned one-key output."""
+    rng = np.random.default_rng(47)
+    g = orc.Grid(R=3)
+    keys = orc.build_keys(g, W.perturbed_theta(3, 48, rho0=1.5, rho_spread=1.0))
+    for q in rand_q(rng, 6, -0.9, 0.9):
+        q = q[None, :]
+        O, _, _ = orc.eval_global(keys, q)
+        f = np.array([orc.eval_global(keys[a:a + 1], q)[0][0] for a in range(len(keys))])
+        sgn = np.sign(f - O[0])
+        eps = 1e-6
+
+        def O_at(e):
+            k2 = keys.copy()
+            k2[:, 3] *= 1.0 - e * sgn
+            return orc.eval_global(k2, q)[0][0]
+
+        fd = (O_at(eps) - O_at(-eps)) / (2 * eps)
+        kap = orc.eval_cond(keys, q)[0]
+        assert abs(fd - kap) <= 1e-6 * kap + 1e-9, (fd, kap)
+
+
+def test_tail_two_key_closed_form(orc):
+    """Two keys: a key whose weight is below e^-T contributes
+    w_a |f_a - O| = w_1 w_2 |f_1 - f_2| to the tail."""
+    rng = np.random.default_rng(49)
+    q = rand_q(rng, 200, -0.9, 0.9)
+    s, f, w1, w2 = _two_key_parts(TWO_KEYS, q)
+    T = 4.0
+    _, tail = orc.eval_cond(TWO_KEYS, q, T, with_tail=True)
+    n_light = (w1 < np.exp(-T)).astype(float) + (w2 < np.exp(-T)).astype(float)
+    ref = n_light * w1 * w2 * np.abs(f[0] - f[1])
+    assert 0 < (n_light > 0).sum() < len(q)
+    assert np.all(np.abs(tail - ref) <= 1e-11 * ref + _cancel(s, f))
+
+
+def _one_sign_setup(rng):
+    """f^1 keys around the cube, plus key 0 below every query with the largest
+    values (r = f_0 - O > 0, x > 0, slopes <= 0) and key 1 above every query
+    with the smallest values and zero slopes (r < 0, x < 0)."""
+    n = 30
+    keys = np.empty((n, 8))
+    keys[:, :3] = rng.uniform(-1, 1, (n, 3))
+    keys[:, 3] = rng.uniform(1.0, 4.0, n)
+    keys[:, 4] = rng.uniform(-1, 1, n)
+    keys[:, 5:] = 0.2 * rng.standard_normal((n, 3))
+    keys[0] = [-1.2, -1.2, -1.2, 2.0, 6.0, -0.1, -0.2, -0.15]
+    keys[1] = [1.2, 1.2, 1.2, 2.0, -6.0, 0.0, 0.0, 0.0]
+    q = rand_q(rng, 70, -1.0, 1.0)
+    dl = rng.standard_normal(70)
+    return keys, q, dl
+
+
+def test_gradient_scale_is_the_gradient_of_magnitudes(orc):
+    """A = sum_j |term| per entry.  The value channel's term is dl_j w_aj, so
+    A_o(dl) = G_o(|dl|) for every key.  Keys 0 and 1 of the set-up have
+    terms of one sign in every channel, so there A equals |G(|dl|)|; the
+    gradient G is pinned by finite differences."""
+    rng = np.random.default_rng(51)
+    keys, q, dl = _one_sign_setup(rng)
+    _, ak = orc.grad_global(keys, q, dl)
+    gabs, _ = orc.grad_global(keys, q, np.abs(dl))
+    assert np.allclose(ak[:, 4], gabs[:, 4], rtol=1e-12, atol=0)
+    for a in (0, 1):
+        assert np.allclose(ak[a], np.abs(gabs[a]), rtol=1e-11, atol=1e-300), a
+    # the sign of dL/dO does not enter A; A is additive over queries
+    _, ak_neg = orc.grad_global(keys, q, -dl)
+    _, ak1 = orc.grad_global(keys, q[:30], dl[:30])
+    _, ak2 = orc.grad_global(keys, q[30:], dl[30:])
+    assert np.array_equal(ak, ak_neg)
+    assert np.allclose(ak, ak1 + ak2, rtol=1e-12, atol=1e-300)
+
+
+def test_subthreshold_gradient_scale_sums_the_light_pairs(orc):
+    """B is A restricted to the pairs whose weight is below e^-T: the sum of
+    the single-query scales over the queries where that key is light (weights
+    from scipy's softmax of the Eq. nrbf logits)."""
+    rng = np.random.default_rng(53)
+    g = orc.Grid(R=3)
+    keys = orc.build_keys(g, W.perturbed_theta(3, 54, rho0=2.0, rho_spread=1.0))
+    q = rand_q(rng, 25)
+    dl = rng.standard_normal(25)
+    T = 5.0
+    _, _, bk = orc.grad_global(keys, q, dl, T=T)
+    logits = -keys[None, :, 3] * ((q[:, None, :] - keys[None, :, :3]) ** 2).sum(-1)
+    w = sps.softmax(logits, axis=1)
+    ref = np.zeros_like(bk)
+    for j in range(len(q)):
+        _, aj = orc.grad_global(keys, q[j:j + 1], dl[j:j + 1])
+        ref += aj * (w[j] < np.exp(-T))[:, None]
+    assert 0 < (w < np.exp(-T)).sum() < w.size
+    assert np.allclose(bk, ref, rtol=1e-11, atol=1e-300)
+
+
+def _two_key_qgrad_parts(keys, q):
+    s, f, w1, w2 = _two_key_parts(keys, q)
+    O = w1 * f[0] + w2 * f[1]
+    g1 = keys[0, 5:] + 2 * keys[0, 3] * (q - keys[0, :3]) * (w2 * (f[1] - f[0]))[:, None]
+    g2 = keys[1, 5:] + 2 * keys[1, 3] * (q - keys[1, :3]) * (w1 * (f[0] - f[1]))[:, None]
+    return s, f, w1, w2, O, g1, g2
+
+
+def test_query_gradient_scales_two_key_closed_forms(orc):
+    """Two keys, with O - f_1 = w_2 (f_2 - f_1), O - f_2 = w_1 (f_1 - f_2) and
+    g_a = d_a + 2 beta_a x_a (O - f_a) (Eq. func-normal):
+      qsig  = w_1 (|d_1| + 2 beta_1 |x_1| |O - f_1|) + (same for key 2);
+      qkap  = w_1 w_2 (|s_1| + |s_2|) |g_1 - g_2|
+              + 2 (beta_1 w_1 |x_1| + beta_2 w_2 |x_2|)(kappa + sigma)
+              + 2 (beta_1 w_1 |x_1| sigma_1 + beta_2 w_2 |x_2| sigma_2);
+      qtail = for each key lighter than e^-T: w_a (|g_a| + |G|),
+              plus the value tail times 2 sum_a beta_a w_a |x_a|;
+    the query gradient G itself is pinned by central differences."""
+    rng = np.random.default_rng(55)
+    q = rand_q(rng, 150, -0.9, 0.9)
+    k = TWO_KEYS
+    T = 4.0
+    qs, qk, qt = orc.eval_qgrad_scales(k, q, T)
+    s, f, w1, w2, O, g1, g2 = _two_key_qgrad_parts(k, q)
+    x1, x2 = q - k[0, :3], q - k[1, :3]
+    b1 = 2 * k[0, 3] * w1[:, None] * np.abs(x1)
+    b2 = 2 * k[1, 3] * w2[:, None] * np.abs(x2)
+    ref_s = (w1[:, None] * np.abs(k[0, 5:]) + b1 * np.abs(O - f[0])[:, None]
+             + w2[:, None] * np.abs(k[1, 5:]) + b2 * np.abs(O - f[1])[:, None])
+    assert np.allclose(qs, ref_s, rtol=1e-11, atol=1e-300)
+    sig1 = np.abs(k[0, 4]) + np.abs(x1) @ np.abs(k[0, 5:])
+    sig2 = np.abs(k[1, 4]) + np.abs(x2) @ np.abs(k[1, 5:])
+    sig = w1 * sig1 + w2 * sig2
+    kap = w1 * w2 * np.abs(f[0] - f[1]) * (np.abs(s[0]) + np.abs(s[1]))
+    ref_k = ((w1 * w2 * (np.abs(s[0]) + np.abs(s[1])))[:, None] * np.abs(g1 - g2)
+             + (b1 + b2) * (kap + sig)[:, None] + b1 * sig1[:, None] + b2 * sig2[:, None])
+    assert np.allclose(qk, ref_k, rtol=1e-11, atol=1e-300)
+    G = w1[:, None] * g1 + w2[:, None] * g2
+    light1 = (w1 < np.exp(-T))[:, None]
+    light2 = (w2 < np.exp(-T))[:, None]
+    tail = (light1[:, 0] + light2[:, 0]) * w1 * w2 * np.abs(f[0] - f[1])
+    ref_t = (light1 * w1[:, None] * (np.abs(g1) + np.abs(G))
+             + light2 * w2[:, None] * (np.abs(g2) + np.abs(G)) + tail[:, None] * (b1 + b2))
+    assert 0 < (light1 | light2).sum() < len(q)
+    assert np.allclose(qt, ref_t, rtol=1e-11, atol=1e-300)
+    assert np.allclose(orc.eval_qgrad(k, q), G, rtol=1e-12, atol=1e-14)
+
+
+def test_query_gradient_scale_equals_gradient_when_terms_share_a_sign(orc):
+    """Key 1 below the query and key 2 above it on every axis, zero slopes
+    and f_2 > f_1: every term 2 beta_a x_a (O - f_a) is positive, so qsig
+    equals dO/dq, which is pinned by central differences."""
+    rng = np.random.default_rng(57)
+    q = rng.uniform(-0.2, 0.2, (50, 3))
+    k = np.array([[-0.5, -0.45, -0.55, 6.0, -0.7, 0.0, 0.0, 0.0],
+                  [0.5, 0.6, 0.45, 9.0, 0.9, 0.0, 0.0, 0.0]])
+    qs, _, _ = orc.eval_qgrad_scales(k, q)
+    G = orc.eval_qgrad(k, q)
+    assert np.all(G > 0)
+    assert np.allclose(qs, G, rtol=1e-12, atol=0)

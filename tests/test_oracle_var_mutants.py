@@ -30,6 +30,18 @@ MUTANTS = {
                             "k[3] = m->learn_scale ? exp((double)p[ro]) : 1.0;"),
     "scale_before_values": ("        l[0] = c; c += nv;\n        if (m->learn_scale) { l[1] = c; c += 1; }",
                             "        if (m->learn_scale) { l[1] = c; c += 1; }\n        l[0] = c; c += nv;"),
+    # the tolerance scales the variant parity checks rest on
+    "sigma_not_normalised": ("*sigma = sa / e;", "*sigma = sa;"),
+    "kappa_x100": ("kk += wr * fabs(s);", "kk += 100.0 * wr * fabs(s);"),
+    "tail_x10": ("if (s - lse < -T) tl += wr;", "if (s - lse < -T) tl += 10.0 * wr;"),
+    "grad_scale_x10": ("adl = fabs(dLdO[j]) * w;", "adl = 10.0 * fabs(dLdO[j]) * w;"),
+    "grad_scale_signed_monomial": ("ta[4 + c] = adl * fabs(mono[c]);", "ta[4 + c] = adl * mono[c];"),
+    "subthreshold_wrong_side": ("const int below = lw < -T;", "const int below = lw > -T;"),
+    "qsig_drops_curvature": ("g[0] += fabs(sxx * x[0]) + fabs(sxy * x[1]) + fabs(sxz * x[2]);",
+                             "g[0] += fabs(sxy * x[1]) + fabs(sxz * x[2]);"),
+    "qkap_x100": ("qk[d] += w * fabs(s) * fabs(ga - G[d])", "qk[d] += 100.0 * w * fabs(s) * fabs(ga - G[d])"),
+    "qtail_drops_renormalisation": ("if (below) qt[d] += w * (fabs(ga) + fabs(G[d]));",
+                                    "if (below) qt[d] += w * fabs(ga);"),
 }
 
 PINS = [getattr(P, n) for n in dir(P) if n.startswith("test_")]

@@ -272,3 +272,126 @@ def test_fit_step_composes_loss_gradient_and_adam(var):
     assert np.allclose(r["grad"], g, rtol=1e-13, atol=1e-15)
     t_ref, _, _ = O1.adam(th.reshape(-1).astype(np.float64), np.zeros(n), np.zeros(n), g, 1)
     assert np.allclose(r["theta"], t_ref, rtol=1e-14, atol=1e-15)
+
+
+# ------------------------------------------------------------ tolerance scales
+# Each scale the variant parity tolerances use is tied to the separately
+# pinned first-order oracle (degree 1), to the pinned value or gradient where
+# every contribution has one sign, or to a two-key closed form.
+
+def test_degree1_scales_match_first_order_oracle(var):
+    """Default model: sigma, kappa, tail, the gradient scales A and B and the
+    query-gradient scales agree with the first-order oracle's (pinned by
+    tests/test_oracle_pins.py)."""
+    m = V.Model(R=4)
+    th = random_theta(m, 61)
+    q = queries(150, 62)
+    kv = V.build_keys(m, th)
+    k1 = O1.build_keys(O1.Grid(R=4), th.reshape(4, 4, 4, 13))
+    T = 6.0
+    assert np.allclose(V.eval_global(kv, 1, q)[2], O1.eval_global(k1, q)[2], rtol=1e-13, atol=0)
+    kv_k, kv_t = V.eval_cond(kv, 1, q, T, with_tail=True)
+    k1_k, k1_t = O1.eval_cond(k1, q, T, with_tail=True)
+    assert np.allclose(kv_k, k1_k, rtol=1e-12, atol=1e-300)
+    assert np.allclose(kv_t, k1_t, rtol=1e-12, atol=1e-300)
+    dl = np.random.default_rng(63).standard_normal(len(q))
+    _, av, bv = V.grad_global(kv, 1, q, dl, T=T)
+    _, a1, b1 = O1.grad_global(k1, q, dl, T=T)
+    assert np.allclose(av[:, :8], a1, rtol=1e-12, atol=1e-300)
+    assert np.allclose(bv[:, :8], b1, rtol=1e-12, atol=1e-300)
+    for sv, s1 in zip(V.eval_qgrad_scales(kv, 1, q, T), O1.eval_qgrad_scales(k1, q, T)):
+        assert np.allclose(sv, s1, rtol=1e-12, atol=1e-300)
+
+
+def _below_keys2(rng, n):
+    """Degree-2 keys centred in [-1, -0.6]^3 with non-negative coefficients:
+    every monomial term is non-negative for queries in [0, 1]^3."""
+    keys = np.zeros((n, V.KEYW))
+    keys[:, :3] = rng.uniform(-1.0, -0.6, (n, 3))
+    keys[:, 3] = rng.uniform(5.0, 40.0, n)
+    keys[:, 4:14] = rng.uniform(0.0, 1.0, (n, 10))
+    return keys
+
+
+def test_degree2_sigma_equals_value_when_every_term_is_nonnegative(var):
+    rng = np.random.default_rng(65)
+    keys = _below_keys2(rng, 30)
+    q = rng.uniform(0.0, 1.0, (50, 3))
+    O, _, sig = V.eval_global(keys, 2, q)
+    assert np.allclose(sig, O, rtol=1e-13, atol=0)
+    mixed = keys.copy()
+    mixed[:, 4:14] *= rng.choice([-1.0, 1.0], size=(30, 10))
+    Om, _, sm = V.eval_global(mixed, 2, q)
+    assert np.allclose(sm, O, rtol=1e-13, atol=0)
+    assert np.all(sm >= np.abs(Om)) and np.any(sm > 1.5 * np.abs(Om))
+
+
+def test_degree2_gradient_scale_is_the_gradient_of_magnitudes(var):
+    """A = sum_j |term|: the monomials 1, x^2/2, y^2/2, z^2/2 are never
+    negative, so for those coefficients A(dl) = G(|dl|) for every key; for a
+    key below every query all monomials are non-negative."""
+    m = V.Model(R=3, degree=2)
+    keys = V.build_keys(m, random_theta(m, 67))
+    keys[0, :3] = [-1.3, -1.3, -1.3]
+    q = queries(70, 68, span=1.0)
+    dl = np.random.default_rng(69).standard_normal(len(q))
+    _, ak = V.grad_global(keys, 2, q, dl)
+    gabs, _ = V.grad_global(keys, 2, q, np.abs(dl))
+    for c in (4, 8, 9, 10):
+        assert np.allclose(ak[:, c], gabs[:, c], rtol=1e-12, atol=1e-300), c
+    assert np.allclose(ak[0, 4:14], gabs[0, 4:14], rtol=1e-12, atol=1e-300)
+    _, ak_neg = V.grad_global(keys, 2, q, -dl)
+    assert np.array_equal(ak, ak_neg)
+
+
+def test_degree2_subthreshold_scale_sums_the_light_pairs(var):
+    m = V.Model(R=3, degree=2)
+    keys = V.build_keys(m, random_theta(m, 71, rho=(1.5, 3.0)))
+    q = queries(20, 72, span=1.0)
+    dl = np.random.default_rng(73).standard_normal(len(q))
+    T = 5.0
+    _, _, bk = V.grad_global(keys, 2, q, dl, T=T)
+    logits = -keys[None, :, 3] * ((q[:, None, :] - keys[None, :, :3]) ** 2).sum(-1)
+    w = sps.softmax(logits, axis=1)
+    ref = np.zeros_like(bk)
+    for j in range(len(q)):
+        _, aj = V.grad_global(keys, 2, q[j:j + 1], dl[j:j + 1])
+        ref += aj * (w[j] < np.exp(-T))[:, None]
+    assert 0 < (w < np.exp(-T)).sum() < w.size
+    assert np.allclose(bk, ref, rtol=1e-11, atol=1e-300)
+
+
+def test_degree0_kappa_and_tail_two_key_closed_forms(var):
+    """f^0, two keys: kappa = w1 w2 |o1 - o2| (|s1| + |s2|); a key lighter
+    than e^-T adds w1 w2 |o1 - o2| to the tail."""
+    keys = np.zeros((2, 16))
+    keys[0, :5] = [-0.3, 0.1, 0.2, 6.0, 0.7]
+    keys[1, :5] = [0.4, -0.2, 0.1, 11.0, -1.3]
+    q = queries(200, 74, span=0.9)
+    s = -keys[:, 3][None, :] * ((q[:, None, :] - keys[None, :, :3]) ** 2).sum(-1)
+    w1, w2 = sps.expit(s[:, 0] - s[:, 1]), sps.expit(s[:, 1] - s[:, 0])
+    T = 4.0
+    kap, tail = V.eval_cond(keys, 0, q, T, with_tail=True)
+    d = abs(keys[0, 4] - keys[1, 4])
+    allow = 1e-14 * (np.abs(s).sum(1) + 1.0) * 2.0
+    assert np.all(np.abs(kap - w1 * w2 * d * np.abs(s).sum(1)) <= 1e-11 * kap + allow)
+    n_light = (w1 < np.exp(-T)).astype(float) + (w2 < np.exp(-T)).astype(float)
+    assert 0 < (n_light > 0).sum() < len(q)
+    assert np.all(np.abs(tail - n_light * w1 * w2 * d) <= 1e-11 * tail + allow)
+
+
+def test_degree2_query_gradient_scale_one_key(var):
+    """One key: w = 1 and O = f, so dO/dq = d + S x and qsig is the sum of
+    the magnitudes of its terms; with d, S and x all non-negative that is
+    dO/dq itself, which the quadratic-reproduction pin fixes."""
+    rng = np.random.default_rng(75)
+    keys = _below_keys2(rng, 1)
+    q = rng.uniform(0.0, 1.0, (40, 3))
+    qs, _, _ = V.eval_qgrad_scales(keys, 2, q)
+    G = V.eval_qgrad(keys, 2, q)
+    assert np.all(G > 0)
+    assert np.allclose(qs, G, rtol=1e-13, atol=0)
+    mixed = keys.copy()
+    mixed[0, 5:14] *= rng.choice([-1.0, 1.0], size=9)
+    qm, _, _ = V.eval_qgrad_scales(mixed, 2, q)
+    assert np.allclose(qm, G, rtol=1e-13, atol=0)
