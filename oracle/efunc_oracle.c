@@ -183,30 +183,27 @@ void oracle_eval_qgrad(const double* keys, int64_t nkeys, const double* q,
  * and G_k = sum_a w_a g_ak:
  *   qsig_k  = sum_a w_a (|d_ak| + 2 beta_a |x_ak| |O - f_a|), the sum of the
  *             magnitudes of the terms (running-error scale);
- *   qkap_k  = sum_a w_a [|s_a| |g_ak - G_k| + 2 beta_a |x_ak| (kappa + sigma + sigma_a)]:
- *             relative errors u in the logits move the weights and O, and
- *             errors u sigma_a in f_a and u sigma in O enter through O - f_a;
- *             each moves G_k by at most u qkap_k to first order;
- *   qtail_k = sum_{a: w_a < e^-T} w_a (|g_ak| + |G_k|)
- *             + tail * sum_a 2 beta_a w_a |x_ak|: omitting those keys drops
- *             their terms, renormalises the rest by their total weight and
- *             moves O by at most tail (see oracle_eval_cond). */
+ *   qkap_k  = sum_a w_a (|s_a| |g_ak - G_k| + 2 beta_a |x_ak| sigma_a): a
+ *             relative error u in every logit moves the normalised weights,
+ *             and an error u sigma_a in f_a enters through O - f_a; each moves
+ *             G_k by at most u qkap_k to first order;
+ *   qtail_k = sum_{a: w_a < e^-T} w_a (|g_ak| + |G_k|): omitting those keys
+ *             drops their terms and renormalises the rest by their weight;
+ *   qbx_k   = sum_a 2 beta_a w_a |x_ak| = the largest |dG_k/dO|, which turns
+ *             an error of O (including its own truncation tail) into one of G. */
 void oracle_eval_qgrad_scales(const double* keys, int64_t nkeys, const double* q, int64_t J,
-                              double T, double* qsig, double* qkap, double* qtail)
+                              double T, double* qsig, double* qkap, double* qtail, double* qbx)
 {
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t j = 0; j < J; ++j) {
         const double* qj = q + 3 * j;
         double O, lse, sig;
         eval_one(keys, nkeys, qj, &O, &lse, &sig);
-        double G[3] = {0.0, 0.0, 0.0}, kap = 0.0, tl = 0.0;
+        double G[3] = {0.0, 0.0, 0.0};
         for (int64_t a = 0; a < nkeys; ++a) {
             const double* k = keys + a * ORACLE_KEY;
-            const double s = logit(k, qj);
-            const double w = exp(s - lse);
+            const double w = exp(logit(k, qj) - lse);
             const double r = O - value(k, qj);
-            kap += w * fabs(s) * fabs(r);
-            if (s - lse < -T) tl += w * fabs(r);
             for (int d = 0; d < 3; ++d) G[d] += w * (k[5 + d] + 2.0 * k[3] * (qj[d] - k[d]) * r);
         }
         double qs[3] = {0.0, 0.0, 0.0}, qk[3] = {0.0, 0.0, 0.0}, qt[3] = {0.0, 0.0, 0.0};
@@ -223,7 +220,7 @@ void oracle_eval_qgrad_scales(const double* keys, int64_t nkeys, const double* q
                 const double ga = k[5 + d] + 2.0 * k[3] * x * r;
                 const double bxa = 2.0 * k[3] * w * fabs(x);
                 qs[d] += w * fabs(k[5 + d]) + bxa * fabs(r);
-                qk[d] += w * fabs(s) * fabs(ga - G[d]) + bxa * (kap + sig + sa);
+                qk[d] += w * fabs(s) * fabs(ga - G[d]) + bxa * sa;
                 if (below) qt[d] += w * (fabs(ga) + fabs(G[d]));
                 bx[d] += bxa;
             }
@@ -231,7 +228,8 @@ void oracle_eval_qgrad_scales(const double* keys, int64_t nkeys, const double* q
         for (int d = 0; d < 3; ++d) {
             if (qsig) qsig[3 * j + d] = qs[d];
             if (qkap) qkap[3 * j + d] = qk[d];
-            if (qtail) qtail[3 * j + d] = qt[d] + tl * bx[d];
+            if (qtail) qtail[3 * j + d] = qt[d];
+            if (qbx) qbx[3 * j + d] = bx[d];
         }
     }
 }

@@ -79,10 +79,12 @@ void oracle_eval_qgrad(const double* keys, int64_t nkeys, const double* q,
 /* Tolerance scales of dO/dq (not part of the method), J x 3 each, any may be
  * NULL: qsig = sum_a w_a (|d_a| + 2 beta_a |x_a| |O - f_a|) per component (the
  * magnitudes of the terms of Eq. func-normal); qkap = first-order change of
- * dO/dq per unit relative error of the logits, values and O; qtail = the most
- * that omitting the keys with weight below e^-T can change it. */
+ * dO/dq per unit relative error of the logits and the values; qtail = the
+ * most that omitting the keys with weight below e^-T changes it directly;
+ * qbx = sum_a 2 beta_a w_a |x_a|, the largest change of dO/dq per unit
+ * change of O. */
 void oracle_eval_qgrad_scales(const double* keys, int64_t nkeys, const double* q, int64_t J,
-                              double T, double* qsig, double* qkap, double* qtail);
+                              double T, double* qsig, double* qkap, double* qtail, double* qbx);
 
 /* Key-parameter gradients of sum_j dLdO_j * O(q_j) (Sec. 3.6 closed forms),
  * global support, key-parallel as in Alg. 2.  gk/ak/bk: nkeys x 8 laid out as

@@ -233,27 +233,26 @@ static void value_grad_abs(const double* k, int degree, const double* x, double*
 /* Tolerance scales of dO/dq (not part of the method), with g_ak the term of
  * key a in Eq. func-normal and G_k = sum_a w_a g_ak:
  *   qsig_k  = sum_a w_a (|df_a/dq_k terms| + 2 beta_a |x_ak| |O - f_a|);
- *   qkap_k  = sum_a w_a [|s_a| |g_ak - G_k| + 2 beta_a |x_ak| (kappa + sigma + sigma_a)];
- *   qtail_k = sum_{a: w_a < e^-T} w_a (|g_ak| + |G_k|) + tail sum_a 2 beta_a w_a |x_ak|. */
+ *   qkap_k  = sum_a w_a (|s_a| |g_ak - G_k| + 2 beta_a |x_ak| sigma_a);
+ *   qtail_k = sum_{a: w_a < e^-T} w_a (|g_ak| + |G_k|);
+ *   qbx_k   = sum_a 2 beta_a w_a |x_ak| (the largest |dG_k/dO|). */
 void ovar_eval_qgrad_scales(const double* keys, int64_t nkeys, int degree, const double* q,
-                            int64_t J, double T, double* qsig, double* qkap, double* qtail)
+                            int64_t J, double T, double* qsig, double* qkap, double* qtail,
+                            double* qbx)
 {
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t j = 0; j < J; ++j) {
         const double* qj = q + 3 * j;
         double O, lse, sig;
         eval_one(keys, nkeys, degree, qj, &O, &lse, &sig);
-        double G[3] = {0.0, 0.0, 0.0}, kap = 0.0, tl = 0.0;
+        double G[3] = {0.0, 0.0, 0.0};
         for (int64_t a = 0; a < nkeys; ++a) {
             const double* k = keys + a * OVAR_KEY;
-            const double s = logit(k, qj);
-            const double w = exp(s - lse);
+            const double w = exp(logit(k, qj) - lse);
             const double x[3] = {qj[0] - k[0], qj[1] - k[1], qj[2] - k[2]};
             const double r = O - value(k, degree, qj, NULL);
             double df[3];
             value_grad(k, degree, x, df);
-            kap += w * fabs(s) * fabs(r);
-            if (s - lse < -T) tl += w * fabs(r);
             for (int d = 0; d < 3; ++d) G[d] += w * (df[d] + 2.0 * k[3] * x[d] * r);
         }
         double qs[3] = {0.0, 0.0, 0.0}, qk[3] = {0.0, 0.0, 0.0}, qt[3] = {0.0, 0.0, 0.0};
@@ -273,7 +272,7 @@ void ovar_eval_qgrad_scales(const double* keys, int64_t nkeys, int degree, const
                 const double ga = df[d] + 2.0 * k[3] * x[d] * r;
                 const double bxa = 2.0 * k[3] * w * fabs(x[d]);
                 qs[d] += w * dfa[d] + bxa * fabs(r);
-                qk[d] += w * fabs(s) * fabs(ga - G[d]) + bxa * (kap + sig + sa);
+                qk[d] += w * fabs(s) * fabs(ga - G[d]) + bxa * sa;
                 if (below) qt[d] += w * (fabs(ga) + fabs(G[d]));
                 bx[d] += bxa;
             }
@@ -281,7 +280,8 @@ void ovar_eval_qgrad_scales(const double* keys, int64_t nkeys, int degree, const
         for (int d = 0; d < 3; ++d) {
             if (qsig) qsig[3 * j + d] = qs[d];
             if (qkap) qkap[3 * j + d] = qk[d];
-            if (qtail) qtail[3 * j + d] = qt[d] + tl * bx[d];
+            if (qtail) qtail[3 * j + d] = qt[d];
+            if (qbx) qbx[3 * j + d] = bx[d];
         }
     }
 }

@@ -73,10 +73,12 @@ void ovar_eval_qgrad(const double* keys, int64_t nkeys, int degree, const double
                      int64_t J, double* dOdq);
 /* Tolerance scales of dO/dq, J x 3 each (any may be NULL): the magnitudes of
  * the terms (qsig), the first-order change per unit relative error of the
- * logits, values and O (qkap), and the most that omitting keys with weight
- * below e^-T can change it (qtail). */
+ * logits and values (qkap), the most that omitting keys with weight below
+ * e^-T changes it directly (qtail), and its largest change per unit change
+ * of O (qbx). */
 void ovar_eval_qgrad_scales(const double* keys, int64_t nkeys, int degree, const double* q,
-                            int64_t J, double T, double* qsig, double* qkap, double* qtail);
+                            int64_t J, double T, double* qsig, double* qkap, double* qtail,
+                            double* qbx);
 /* Key gradients of sum_j dLdO_j O(q_j): per key dc (3), dbeta, dv (10);
  * ak = sums of |terms|, bk = the same over pairs with weight below e^-T
  * (ak, bk may be NULL). */

@@ -74,7 +74,7 @@ def load():
         lib.oracle_build_keys.argtypes = [_G, _F, _D]
         lib.oracle_eval.argtypes = [_D, _I64, _D, _I64, _D, _D, _D]
         lib.oracle_eval_qgrad.argtypes = [_D, _I64, _D, _I64, _D]
-        lib.oracle_eval_qgrad_scales.argtypes = [_D, _I64, _D, _I64, C.c_double, _D, _D, _D]
+        lib.oracle_eval_qgrad_scales.argtypes = [_D, _I64, _D, _I64, C.c_double, _D, _D, _D, _D]
         lib.oracle_eval_cond.argtypes = [_D, _I64, _D, _I64, _D, C.c_double, _D]
         lib.oracle_grad.argtypes = [_D, _I64, _D, _I64, _D, _D, _D, C.c_double, _D]
         lib.oracle_grad_theta.argtypes = [_G, _F, _D, _D]
@@ -179,13 +179,13 @@ def eval_qgrad(keys, q):
 
 
 def eval_qgrad_scales(keys, q, T: float = float("inf")):
-    """Tolerance scales of dO/dq (J x 3 each): (qsig, qkap, qtail), see
+    """Tolerance scales of dO/dq (J x 3 each): (qsig, qkap, qtail, qbx), see
     oracle_eval_qgrad_scales."""
     keys, q = _f64(keys), _f64(q).reshape(-1, 3)
-    qs, qk, qt = (np.empty_like(q) for _ in range(3))
+    qs, qk, qt, qb = (np.empty_like(q) for _ in range(4))
     load().oracle_eval_qgrad_scales(_d(keys), keys.shape[0], _d(q), q.shape[0], T, _d(qs),
-                                    _d(qk), _d(qt))
-    return qs, qk, qt
+                                    _d(qk), _d(qt), _d(qb))
+    return qs, qk, qt, qb
 
 
 def eval_trunc(g: Grid, keys, q, T: float = 20.0):

@@ -80,7 +80,7 @@ def load():
         lib.ovar_eval_cond.argtypes = [_D, _I64, C.c_int, _D, _I64, _D, C.c_double, _D]
         lib.ovar_eval_qgrad.argtypes = [_D, _I64, C.c_int, _D, _I64, _D]
         lib.ovar_eval_qgrad_scales.argtypes = [_D, _I64, C.c_int, _D, _I64, C.c_double, _D, _D,
-                                               _D]
+                                               _D, _D]
         lib.ovar_grad.argtypes = [_D, _I64, C.c_int, _D, _I64, _D, _D, _D, C.c_double, _D]
         lib.ovar_grad_theta.argtypes = [_M, _F, _D, _D]
         lib.ovar_fit_step.argtypes = [_M, _F, _D, _D, _I64, C.c_double, C.c_double, C.c_double,
@@ -166,12 +166,12 @@ def eval_qgrad(keys, degree, q):
 
 
 def eval_qgrad_scales(keys, degree, q, T: float = float("inf")):
-    """Tolerance scales of dO/dq (J x 3 each): (qsig, qkap, qtail)."""
+    """Tolerance scales of dO/dq (J x 3 each): (qsig, qkap, qtail, qbx)."""
     keys, q = _f64(keys), _f64(q)
-    qs, qk, qt = (np.empty((len(q), 3)) for _ in range(3))
+    qs, qk, qt, qb = (np.empty((len(q), 3)) for _ in range(4))
     load().ovar_eval_qgrad_scales(_d(keys), len(keys), degree, _d(q), len(q), T, _d(qs), _d(qk),
-                                  _d(qt))
-    return qs, qk, qt
+                                  _d(qt), _d(qb))
+    return qs, qk, qt, qb
 
 
 def grad_global(keys, degree, q, dLdO, T: float = None):

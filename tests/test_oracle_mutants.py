@@ -40,7 +40,10 @@ MUTANTS = {
     "qsig_drops_factor_2": ("const double bxa = 2.0 * k[3] * w * fabs(x);",
                             "const double bxa = k[3] * w * fabs(x);"),
     "qkap_x100": ("qk[d] += w * fabs(s) * fabs(ga - G[d])", "qk[d] += 100.0 * w * fabs(s) * fabs(ga - G[d])"),
-    "qkap_drops_value_errors": ("bxa * (kap + sig + sa)", "bxa * kap"),
+    "qkap_drops_value_errors": ("qk[d] += w * fabs(s) * fabs(ga - G[d]) + bxa * sa;",
+                                "qk[d] += w * fabs(s) * fabs(ga - G[d]);"),
+    "qbx_drops_abs": ("const double bxa = 2.0 * k[3] * w * fabs(x);\n                qs[d]",
+                      "const double bxa = 2.0 * k[3] * w * x;\n                qs[d]"),
     "qtail_drops_renormalisation": ("if (below) qt[d] += w * (fabs(ga) + fabs(G[d]));",
                                     "if (below) qt[d] += w * fabs(ga);"),
 }

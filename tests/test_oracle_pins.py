@@ -704,39 +704,63 @@ def test_query_gradient_scales_two_key_closed_forms(orc):
     g_a = d_a + 2 beta_a x_a (O - f_a) (Eq. func-normal):
       qsig  = w_1 (|d_1| + 2 beta_1 |x_1| |O - f_1|) + (same for key 2);
       qkap  = w_1 w_2 (|s_1| + |s_2|) |g_1 - g_2|
-              + 2 (beta_1 w_1 |x_1| + beta_2 w_2 |x_2|)(kappa + sigma)
               + 2 (beta_1 w_1 |x_1| sigma_1 + beta_2 w_2 |x_2| sigma_2);
-      qtail = for each key lighter than e^-T: w_a (|g_a| + |G|),
-              plus the value tail times 2 sum_a beta_a w_a |x_a|;
+      qtail = for each key lighter than e^-T: w_a (|g_a| + |G|);
+      qbx   = 2 (beta_1 w_1 |x_1| + beta_2 w_2 |x_2|), and dG/dO at fixed
+              weights, 2 (beta_1 w_1 x_1 + beta_2 w_2 x_2), is within it;
     the query gradient G itself is pinned by central differences."""
     rng = np.random.default_rng(55)
     q = rand_q(rng, 150, -0.9, 0.9)
     k = TWO_KEYS
     T = 4.0
-    qs, qk, qt = orc.eval_qgrad_scales(k, q, T)
+    qs, qk, qt, qb = orc.eval_qgrad_scales(k, q, T)
     s, f, w1, w2, O, g1, g2 = _two_key_qgrad_parts(k, q)
     x1, x2 = q - k[0, :3], q - k[1, :3]
     b1 = 2 * k[0, 3] * w1[:, None] * np.abs(x1)
     b2 = 2 * k[1, 3] * w2[:, None] * np.abs(x2)
+    allow = _cancel(s, f)[:, None] * (b1 + b2)
     ref_s = (w1[:, None] * np.abs(k[0, 5:]) + b1 * np.abs(O - f[0])[:, None]
              + w2[:, None] * np.abs(k[1, 5:]) + b2 * np.abs(O - f[1])[:, None])
-    assert np.allclose(qs, ref_s, rtol=1e-11, atol=1e-300)
+    assert np.all(np.abs(qs - ref_s) <= 1e-11 * ref_s + allow)
     sig1 = np.abs(k[0, 4]) + np.abs(x1) @ np.abs(k[0, 5:])
     sig2 = np.abs(k[1, 4]) + np.abs(x2) @ np.abs(k[1, 5:])
-    sig = w1 * sig1 + w2 * sig2
-    kap = w1 * w2 * np.abs(f[0] - f[1]) * (np.abs(s[0]) + np.abs(s[1]))
     ref_k = ((w1 * w2 * (np.abs(s[0]) + np.abs(s[1])))[:, None] * np.abs(g1 - g2)
-             + (b1 + b2) * (kap + sig)[:, None] + b1 * sig1[:, None] + b2 * sig2[:, None])
+             + b1 * sig1[:, None] + b2 * sig2[:, None])
     assert np.allclose(qk, ref_k, rtol=1e-11, atol=1e-300)
     G = w1[:, None] * g1 + w2[:, None] * g2
     light1 = (w1 < np.exp(-T))[:, None]
     light2 = (w2 < np.exp(-T))[:, None]
-    tail = (light1[:, 0] + light2[:, 0]) * w1 * w2 * np.abs(f[0] - f[1])
     ref_t = (light1 * w1[:, None] * (np.abs(g1) + np.abs(G))
-             + light2 * w2[:, None] * (np.abs(g2) + np.abs(G)) + tail[:, None] * (b1 + b2))
+             + light2 * w2[:, None] * (np.abs(g2) + np.abs(G)))
     assert 0 < (light1 | light2).sum() < len(q)
     assert np.allclose(qt, ref_t, rtol=1e-11, atol=1e-300)
+    assert np.allclose(qb, b1 + b2, rtol=1e-12, atol=0)
     assert np.allclose(orc.eval_qgrad(k, q), G, rtol=1e-12, atol=1e-14)
+
+
+def test_query_gradient_scale_bounds_its_change_with_O(orc):
+    """Two keys: raising the constant term of key 2 by c leaves the weights
+    alone, moves O by w_2 c and moves dO/dq by 2 w_1 w_2 (beta_1 x_1 -
+    beta_2 x_2) c (central differences of the pinned oracle), which qbx
+    bounds per unit change of O."""
+    rng = np.random.default_rng(59)
+    q = rand_q(rng, 60, -0.5, 0.5)
+    k = TWO_KEYS.copy()
+    qs, _, _, qb = orc.eval_qgrad_scales(k, q)
+    c = 1e-6
+    kp, km = k.copy(), k.copy()
+    kp[1, 4] += c
+    km[1, 4] -= c
+    dG = (orc.eval_qgrad(kp, q) - orc.eval_qgrad(km, q)) / (2 * c)
+    dO = (orc.eval_global(kp, q)[0] - orc.eval_global(km, q)[0]) / (2 * c)
+    s, f, w1, w2 = _two_key_parts(k, q)
+    assert np.allclose(dO, w2, rtol=1e-6, atol=1e-9)
+    # dG/dc = 2 beta_1 w_1 x_1 w_2 - 2 beta_2 w_2 x_2 w_1 (the weights do not
+    # depend on the values), i.e. exactly qbx's terms with signs
+    x1, x2 = q - k[0, :3], q - k[1, :3]
+    ref = 2 * k[0, 3] * (w1 * w2)[:, None] * x1 - 2 * k[1, 3] * (w1 * w2)[:, None] * x2
+    assert np.allclose(dG, ref, rtol=1e-5, atol=1e-8)
+    assert np.all(np.abs(dG) <= qb + 1e-8)
 
 
 def test_query_gradient_scale_equals_gradient_when_terms_share_a_sign(orc):
@@ -747,7 +771,7 @@ def test_query_gradient_scale_equals_gradient_when_terms_share_a_sign(orc):
     q = rng.uniform(-0.2, 0.2, (50, 3))
     k = np.array([[-0.5, -0.45, -0.55, 6.0, -0.7, 0.0, 0.0, 0.0],
                   [0.5, 0.6, 0.45, 9.0, 0.9, 0.0, 0.0, 0.0]])
-    qs, _, _ = orc.eval_qgrad_scales(k, q)
+    qs = orc.eval_qgrad_scales(k, q)[0]
     G = orc.eval_qgrad(k, q)
     assert np.all(G > 0)
     assert np.allclose(qs, G, rtol=1e-12, atol=0)

@@ -387,11 +387,11 @@ def test_degree2_query_gradient_scale_one_key(var):
     rng = np.random.default_rng(75)
     keys = _below_keys2(rng, 1)
     q = rng.uniform(0.0, 1.0, (40, 3))
-    qs, _, _ = V.eval_qgrad_scales(keys, 2, q)
+    qs = V.eval_qgrad_scales(keys, 2, q)[0]
     G = V.eval_qgrad(keys, 2, q)
     assert np.all(G > 0)
     assert np.allclose(qs, G, rtol=1e-13, atol=0)
     mixed = keys.copy()
     mixed[0, 5:14] *= rng.choice([-1.0, 1.0], size=9)
-    qm, _, _ = V.eval_qgrad_scales(mixed, 2, q)
+    qm = V.eval_qgrad_scales(mixed, 2, q)[0]
     assert np.allclose(qm, G, rtol=1e-13, atol=0)
