@@ -37,7 +37,7 @@
  *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Every
  *     call is asynchronous on it, allocates nothing and does not
  *     synchronise, except when efunc_config.check_finite is set (then the
- *     call synchronises to read the scan result).
+ *     call synchronises and scans its inputs on the host first).
  *   - Return value: EFUNC_OK (0) or a negative code; efunc_last_error()
  *     gives a thread-local message for the last failing call.  No exception
  *     crosses the ABI.  J = 0 is a successful no-op.
@@ -74,8 +74,10 @@ typedef struct {
                               scales; > 0: force W (queries that fail the certificate then
                               fall back to all keys) */
     int32_t deterministic; /* reserved, must be 0 */
-    int32_t check_finite;  /* 1: reject non-finite parameters/points with EFUNC_ENONFINITE
-                              (synchronises the stream) */
+    int32_t check_finite;  /* 1: before anything is enqueued, synchronise the stream and scan
+                              the call's input arrays (parameters, moments, points, targets,
+                              O / lse / dL/dO) on the host; a NaN or Inf returns
+                              EFUNC_ENONFINITE and the call launches nothing */
     /* Model variant (Sec. 3.2-3.3; Tab. ablation).  Defaults give the paper's
      * default model O^{+Delta} with f^1 and learnable scales (13 channels). */
     int32_t degree;        /* value polynomial f^0, f^1 or f^2 (Eq. poly-func): 0, 1, 2 */

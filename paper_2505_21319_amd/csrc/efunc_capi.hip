@@ -9,6 +9,8 @@
 #include <string.h>
 
 #include <string>
+#include <cmath>
+#include <initializer_list>
 #include <vector>
 
 using namespace efunc;
@@ -87,17 +89,111 @@ namespace {
 
 bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
-template <typename T>
-hipError_t dalloc(efunc_ctx* c, T** p, size_t count)
+// Lays consecutive 256-byte-aligned sub-buffers out in one region.  With a
+// null base it only measures (every pointer stays null).
+struct Carver {
+    char* base;
+    size_t off = 0;
+    template <typename T>
+    void take(T*& p, int64_t count)
+    {
+        off = (off + 255) & ~(size_t)255;
+        p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += (size_t)(count > 0 ? count : 1) * sizeof(T);
+    }
+};
+
+// The workspace of one lattice configuration and query capacity, carved out
+// of the region at base (or measured when base is null): fills the sizes and
+// pointers of w and returns the bytes the region needs.  efunc_create
+// allocates one region of that size.
+size_t carve_work(const efunc_config& cfg, const Layout& layout, int64_t max_points, int num_cu, char* base,
+                  Work& w)
 {
-    void* q = nullptr;
-    const size_t bytes = (count ? count : 1) * sizeof(T);
-    hipError_t e = hipMalloc(&q, bytes);
-    if (e != hipSuccess) return e;
-    c->allocs.push_back(q);
-    c->alloc_bytes += (int64_t)bytes;
-    *p = static_cast<T*>(q);
-    return hipSuccess;
+    const int64_t R = cfg.R, I = R * R * R, C1 = R - 1, C = C1 * C1 * C1;
+    const int64_t mp = max_points > 0 ? max_points : 1;
+    w.I = I;
+    w.C = C;
+    w.max_points = max_points;
+    const int64_t NB = (C1 + 1) / 2;
+    w.NB3 = NB * NB * NB;
+    w.NK = 8 * w.NB3;
+    // tiles: at most mp / cap + 1 per non-empty cell when cells are split,
+    // one per grouped block, for every cap >= PMIN_CAP
+    w.max_tiles = mp / PMIN_CAP + 8 * (mp / PMIN_CAP + 1) + (C < mp ? C : mp) + 1;
+    w.num_cu = num_cu > 0 ? num_cu : 1;
+    w.nch = (w.max_tiles + BLOCK - 1) / BLOCK;
+    const int64_t nkeys = 128 * SLICE_KEYS * w.nch;
+    const int64_t nscan = w.NK * PSPLIT > nkeys ? w.NK * PSPLIT : nkeys;
+    const int64_t nblk = (nscan + SCAN_TILE - 1) / SCAN_TILE;
+    const int gw = gk_width(layout.degree), mw = mk_width(layout.degree);
+    // LDS binning: one histogram row per workgroup of at least LBIN_PER queries
+    w.lnw = (int)((mp + LBIN_PER - 1) / LBIN_PER < LBIN_NW ? (mp + LBIN_PER - 1) / LBIN_PER : LBIN_NW);
+    Carver k{base};
+    k.take(w.tlat, R);
+    k.take(w.gk, layout.grid ? gw * I : 1);
+    k.take(w.mcell, I);
+    k.take(w.mrank, I);
+    k.take(w.mcount, C);
+    k.take(w.mstart, C + 1);
+    k.take(w.mrec, layout.moved ? mw * I : 1);
+    k.take(w.mk, layout.moved ? mw * I : 1);
+    k.take(w.pcell, mp);
+    k.take(w.prank, mp);
+    k.take(w.pcount, w.NK * PSPLIT);
+    k.take(w.pstart, w.NK * PSPLIT + 1);
+    w.hist = nullptr;
+    if (w.NK <= LBIN_MAX) k.take(w.hist, (int64_t)w.lnw * w.NK);
+    k.take(w.btiles, w.NB3);
+    k.take(w.tstart, w.NB3 + 1);
+    k.take(w.tiles, w.max_tiles);
+    k.take(w.tiles_tmp, w.max_tiles);
+    k.take(w.tbucket, w.max_tiles);
+    k.take(w.chist, nkeys);
+    k.take(w.cstart, nkeys + 1);
+    k.take(w.ps, mp);
+    k.take(w.pv, mp);
+    k.take(w.pidx, mp);
+    k.take(w.fb, mp);
+    k.take(w.lpart, w.max_tiles);
+    k.take(w.scan_blk, nblk + 1);
+    k.take(w.grad, (int64_t)layout.nch * I);
+    k.take(w.st, 1);
+    return (k.off + 255) & ~(size_t)255;
+}
+
+Geo make_geo(const efunc_config& cfg, const float* tlat)
+{
+    Geo g;
+    const int64_t C1 = cfg.R - 1;
+    g.R = cfg.R;
+    g.C1 = (int)C1;
+    g.NB = (int)((C1 + 1) / 2);
+    g.lo = cfg.lo;
+    g.hi = cfg.hi;
+    g.lo_d = cfg.lo;
+    g.h_d = ((double)cfg.hi - (double)cfg.lo) / (double)C1;
+    g.inv_h_d = 1.0 / g.h_d;
+    g.h = (float)g.h_d;
+    g.inv_h = (float)g.inv_h_d;
+    g.tlat = tlat;
+    return g;
+}
+
+// The configuration checks of efunc_create, with the channel layout.
+int check_config(const efunc_config* cfg, Layout* layout)
+{
+    if (!cfg) return fail(EFUNC_EINVAL, "cfg is NULL");
+    // every cell and sub-counter index must fit in int32: 8 NB^3 PSPLIT < 2^31
+    if (cfg->R < 2 || cfg->R > 512) return fail(EFUNC_EINVAL, "R = %d outside [2, 512]", cfg->R);
+    if (!(cfg->lo < cfg->hi) || !isfinite(cfg->lo) || !isfinite(cfg->hi))
+        return fail(EFUNC_EINVAL, "lattice bounds must satisfy lo < hi, finite");
+    if (cfg->offsets != 0 && cfg->offsets != 1) return fail(EFUNC_EINVAL, "offsets must be 0 or 1");
+    if (!(cfg->t_cut > 0.0f) || !isfinite(cfg->t_cut)) return fail(EFUNC_EINVAL, "t_cut must be > 0");
+    if (cfg->window < 0 || cfg->window > WMAX)
+        return fail(EFUNC_EINVAL, "window = %d outside [0, %d]", cfg->window, WMAX);
+    if (cfg->deterministic != 0) return fail(EFUNC_EUNSUPPORTED, "deterministic mode is not built");
+    return make_layout(cfg, layout);
 }
 
 void free_all(efunc_ctx* c)
@@ -168,23 +264,75 @@ void destroy_events(efunc_ctx* c)
     c->nrec = 0;
 }
 
-// With check_finite, synchronise and read the non-finite counter of the key
-// preparation (and scan the queries on the host side of the same sync).
-int finite_check(efunc_ctx* ctx, hipStream_t s, const float* q, int64_t J)
+// One input array of a call, for the check_finite scan.
+struct FArr {
+    const float* p;
+    int64_t n;
+    const char* name;
+};
+
+// With check_finite: synchronise the stream (earlier work on it may still
+// write these arrays), copy every input array of the call to the host and
+// scan it before anything is enqueued, so non-finite data never reaches a
+// kernel.  Returns EFUNC_ENONFINITE naming the first NaN/Inf found.
+int finite_check(efunc_ctx* ctx, hipStream_t s, std::initializer_list<FArr> arrs)
 {
     if (!ctx->cfg.check_finite) return EFUNC_OK;
-    DevStats st;
-    hipError_t e = hipMemcpyAsync(&st, ctx->w.st, sizeof(st), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(e, "check_finite readback");
-    if (st.nonfinite) return fail(EFUNC_ENONFINITE, "%d non-finite parameters", st.nonfinite);
-    if (q && J > 0) {
-        std::vector<float> h(3 * (size_t)J);
-        e = hipMemcpy(h.data(), q, h.size() * sizeof(float), hipMemcpyDeviceToHost);
-        if (e != hipSuccess) return hip_fail(e, "check_finite query readback");
-        for (float x : h)
-            if (!isfinite(x)) return fail(EFUNC_ENONFINITE, "non-finite query coordinate");
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "check_finite synchronise");
+    std::vector<float> h;
+    for (const FArr& a : arrs) {
+        if (!a.p || a.n <= 0) continue;
+        h.resize((size_t)a.n);
+        e = hipMemcpy(h.data(), a.p, sizeof(float) * (size_t)a.n, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "check_finite readback");
+        for (int64_t i = 0; i < a.n; ++i)
+            if (!std::isfinite(h[(size_t)i]))
+                return fail(EFUNC_ENONFINITE, "%s[%lld] = %g is not finite", a.name, (long long)i,
+                            (double)h[(size_t)i]);
     }
+    return EFUNC_OK;
+}
+
+int64_t n_params(const efunc_ctx* ctx) { return (int64_t)ctx->layout.nch * ctx->w.I; }
+
+// efunc_fit_step after the context and size checks (shared with the
+// allocation-free entry point, whose context lives on the host stack).
+int fit_step_impl(efunc_ctx* ctx, float* theta, float* m, float* v, int64_t step, const efunc_adam* adam,
+                  const float* q, const float* o, int64_t J, double* loss_out, void* stream)
+{
+    int rc;
+    if (step < 1) return fail(EFUNC_EINVAL, "step = %lld < 1", (long long)step);
+    if ((rc = check_opt(loss_out, "loss_out", 8))) return rc;
+    if (J == 0) return EFUNC_OK;
+    if ((rc = check_ptr(theta, "theta", 4)) || (rc = check_ptr(m, "m", 4)) ||
+        (rc = check_ptr(v, "v", 4)) || (rc = check_ptr(q, "q", 4)) || (rc = check_ptr(o, "o", 4)))
+        return rc;
+    efunc_adam hp;
+    if (adam) hp = *adam; else efunc_default_adam(&hp);
+    if (!(hp.lr >= 0.0f) || !(hp.beta1 >= 0.0f && hp.beta1 < 1.0f) ||
+        !(hp.beta2 >= 0.0f && hp.beta2 < 1.0f) || !(hp.eps > 0.0f) || !(hp.weight_decay >= 0.0f))
+        return fail(EFUNC_EINVAL, "invalid Adam hyper-parameters");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t np = n_params(ctx);
+    if ((rc = finite_check(ctx, s, {{theta, np, "theta"}, {m, np, "m"}, {v, np, "v"}, {q, 3 * J, "q"},
+                                    {o, J, "o"}})))
+        return rc;
+    ctx->last_stream = s;
+    Problem p = base_problem(ctx);
+    p.J = J;
+    p.theta = theta;
+    p.q = q;
+    p.aux = o;
+    p.grad = ctx->w.grad;
+    hipError_t e = run_tiles(ctx->w, p, MODE_FIT, s);
+    if (e == hipSuccess && loss_out) e = run_loss_finalize(ctx->w, J, loss_out, s);
+    if (e != hipSuccess) return hip_fail(e, "fit_step launch");
+    const double bc1 = 1.0 - pow((double)hp.beta1, (double)step);
+    const double bc2 = 1.0 - pow((double)hp.beta2, (double)step);
+    e = run_adam(ctx->w, theta, m, v, (int64_t)ctx->layout.nch * ctx->w.I, hp.lr, hp.beta1, hp.beta2, hp.eps,
+                 hp.weight_decay, (float)bc1, (float)bc2, s);
+    if (e != hipSuccess) return hip_fail(e, "adam launch");
     return EFUNC_OK;
 }
 
@@ -243,18 +391,8 @@ int efunc_create(const efunc_config* cfg, int64_t max_points, efunc_ctx** out)
     g_err.clear();
     if (!out) return fail(EFUNC_EINVAL, "out is NULL");
     *out = nullptr;
-    if (!cfg) return fail(EFUNC_EINVAL, "cfg is NULL");
-    // every cell and sub-counter index must fit in int32: 8 NB^3 PSPLIT < 2^31
-    if (cfg->R < 2 || cfg->R > 512) return fail(EFUNC_EINVAL, "R = %d outside [2, 512]", cfg->R);
-    if (!(cfg->lo < cfg->hi) || !isfinite(cfg->lo) || !isfinite(cfg->hi))
-        return fail(EFUNC_EINVAL, "lattice bounds must satisfy lo < hi, finite");
-    if (cfg->offsets != 0 && cfg->offsets != 1) return fail(EFUNC_EINVAL, "offsets must be 0 or 1");
-    if (!(cfg->t_cut > 0.0f) || !isfinite(cfg->t_cut)) return fail(EFUNC_EINVAL, "t_cut must be > 0");
-    if (cfg->window < 0 || cfg->window > WMAX)
-        return fail(EFUNC_EINVAL, "window = %d outside [0, %d]", cfg->window, WMAX);
-    if (cfg->deterministic != 0) return fail(EFUNC_EUNSUPPORTED, "deterministic mode is not built");
     Layout layout;
-    if (int rc = make_layout(cfg, &layout)) return rc;
+    if (int rc = check_config(cfg, &layout)) return rc;
     if (max_points < 0 || max_points > (int64_t)INT32_MAX - PMAX)
         return fail(EFUNC_EINVAL, "max_points = %lld outside [0, 2^31 - %d)", (long long)max_points, PMAX);
 
@@ -264,98 +402,34 @@ int efunc_create(const efunc_config* cfg, int64_t max_points, efunc_ctx** out)
     c->layout = layout;
     c->last_stream = nullptr;
     hipError_t e = hipGetDevice(&c->device);
+    int num_cu = 0;
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, c->device);
     if (e != hipSuccess) {
         delete c;
-        return hip_fail(e, "hipGetDevice");
+        return hip_fail(e, "device query");
     }
-    hipDeviceProp_t prop;
-    e = hipGetDeviceProperties(&prop, c->device);
-    if (e != hipSuccess) {
-        delete c;
-        return hip_fail(e, "hipGetDeviceProperties");
-    }
-
-    const int64_t R = cfg->R, I = R * R * R, C1 = R - 1, C = C1 * C1 * C1;
-    const int64_t mp = max_points > 0 ? max_points : 1;
     Work& w = c->w;
-    w.I = I;
-    w.C = C;
-    w.max_points = max_points;
-    const int64_t NB = (C1 + 1) / 2;
-    w.NB3 = NB * NB * NB;
-    w.NK = 8 * w.NB3;
-    // tiles: at most mp / cap + 1 per non-empty cell when cells are split,
-    // one per grouped block, for every cap >= PMIN_CAP
-    w.max_tiles = mp / PMIN_CAP + 8 * (mp / PMIN_CAP + 1) + (C < mp ? C : mp) + 1;
-    w.num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
-    w.nch = (w.max_tiles + BLOCK - 1) / BLOCK;
-    const int64_t nkeys = 128 * SLICE_KEYS * w.nch;
-    const int64_t nscan = w.NK * PSPLIT > nkeys ? w.NK * PSPLIT : nkeys;
-    const int64_t nblk = (nscan + SCAN_TILE - 1) / SCAN_TILE;
-
-    hipError_t err = hipSuccess;
-#define ALLOC(ptr, n) \
-    if (err == hipSuccess) err = dalloc(c, &(ptr), (size_t)(n))
-    ALLOC(w.tlat, R);
-    const int gw = gk_width(layout.degree), mw = mk_width(layout.degree);
-    ALLOC(w.gk, layout.grid ? gw * I : 1);
-    ALLOC(w.mcell, I);
-    ALLOC(w.mrank, I);
-    ALLOC(w.mcount, C);
-    ALLOC(w.mstart, C + 1);
-    ALLOC(w.mrec, layout.moved ? mw * I : 1);
-    ALLOC(w.mk, layout.moved ? mw * I : 1);
-    ALLOC(w.pcell, mp);
-    ALLOC(w.prank, mp);
-    ALLOC(w.pcount, w.NK * PSPLIT);
-    ALLOC(w.pstart, w.NK * PSPLIT + 1);
-    // LDS binning: one histogram row per workgroup of at least LBIN_PER queries
-    w.lnw = (int)((mp + LBIN_PER - 1) / LBIN_PER < LBIN_NW ? (mp + LBIN_PER - 1) / LBIN_PER : LBIN_NW);
-    w.hist = nullptr;
-    if (w.NK <= LBIN_MAX) ALLOC(w.hist, (int64_t)w.lnw * w.NK);
-    ALLOC(w.btiles, w.NB3);
-    ALLOC(w.tstart, w.NB3 + 1);
-    ALLOC(w.tiles, w.max_tiles);
-    ALLOC(w.tiles_tmp, w.max_tiles);
-    ALLOC(w.tbucket, w.max_tiles);
-    ALLOC(w.chist, nkeys);
-    ALLOC(w.cstart, nkeys + 1);
-    ALLOC(w.ps, mp);
-    ALLOC(w.pv, mp);
-    ALLOC(w.pidx, mp);
-    ALLOC(w.fb, mp);
-    ALLOC(w.lpart, w.max_tiles);
-    ALLOC(w.scan_blk, nblk + 1);
-    ALLOC(w.grad, (int64_t)layout.nch * I);
-    ALLOC(w.st, 1);
-#undef ALLOC
-    if (err != hipSuccess) {
-        free_all(c);
+    const size_t bytes = carve_work(*cfg, layout, max_points, num_cu, nullptr, w);
+    void* mem = nullptr;
+    e = hipMalloc(&mem, bytes);
+    if (e != hipSuccess) {
         delete c;
-        return hip_fail(err, "hipMalloc of the workspace");
+        return hip_fail(e, "hipMalloc of the workspace");
     }
+    c->allocs.push_back(mem);
+    c->alloc_bytes = (int64_t)bytes;
+    carve_work(*cfg, layout, max_points, num_cu, static_cast<char*>(mem), w);
     const std::vector<float> t = lattice(*cfg);
-    err = hipMemcpy(w.tlat, t.data(), sizeof(float) * R, hipMemcpyHostToDevice);
-    if (err == hipSuccess) err = hipMemset(w.grad, 0, sizeof(float) * layout.nch * I);
-    if (err == hipSuccess) err = hipMemset(w.st, 0, sizeof(DevStats));
-    if (err == hipSuccess) err = hipDeviceSynchronize();
-    if (err != hipSuccess) {
+    e = hipMemcpy(w.tlat, t.data(), sizeof(float) * cfg->R, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(w.grad, 0, sizeof(float) * layout.nch * w.I);
+    if (e == hipSuccess) e = hipMemset(w.st, 0, sizeof(DevStats));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
         free_all(c);
         delete c;
-        return hip_fail(err, "workspace initialisation");
+        return hip_fail(e, "workspace initialisation");
     }
-    Geo& g = c->geo;
-    g.R = (int)R;
-    g.C1 = (int)C1;
-    g.NB = (int)NB;
-    g.lo = cfg->lo;
-    g.hi = cfg->hi;
-    g.lo_d = cfg->lo;
-    g.h_d = ((double)cfg->hi - (double)cfg->lo) / (double)C1;
-    g.inv_h_d = 1.0 / g.h_d;
-    g.h = (float)g.h_d;
-    g.inv_h = (float)g.inv_h_d;
-    g.tlat = w.tlat;
+    c->geo = make_geo(*cfg, w.tlat);
     *out = c;
     return EFUNC_OK;
 }
@@ -405,6 +479,7 @@ int efunc_eval(efunc_ctx* ctx, const float* theta, const float* q, int64_t J, fl
         (rc = check_ptr(O, "O", 4)))
         return rc;
     hipStream_t s = (hipStream_t)stream;
+    if ((rc = finite_check(ctx, s, {{theta, n_params(ctx), "theta"}, {q, 3 * J, "q"}}))) return rc;
     ctx->last_stream = s;
     Problem p = base_problem(ctx);
     p.J = J;
@@ -417,7 +492,7 @@ int efunc_eval(efunc_ctx* ctx, const float* theta, const float* q, int64_t J, fl
     hipError_t e = run_tiles(ctx->w, p, MODE_EVAL, s);
     if (e == hipSuccess && n_uncertified) e = run_count_uncertified(ctx->w, n_uncertified, s);
     if (e != hipSuccess) return hip_fail(e, "eval launch");
-    return finite_check(ctx, s, q, J);
+    return EFUNC_OK;
 }
 
 int efunc_grad(efunc_ctx* ctx, const float* theta, const float* q, const float* O,
@@ -433,6 +508,9 @@ int efunc_grad(efunc_ctx* ctx, const float* theta, const float* q, const float* 
         (rc = check_ptr(dLdO, "dLdO", 4)) || (rc = check_ptr(grad, "grad", 4)))
         return rc;
     hipStream_t s = (hipStream_t)stream;
+    if ((rc = finite_check(ctx, s, {{theta, n_params(ctx), "theta"}, {q, 3 * J, "q"}, {O, J, "O"},
+                                    {lse, J, "lse"}, {dLdO, J, "dLdO"}})))
+        return rc;
     ctx->last_stream = s;
     Problem p = base_problem(ctx);
     p.J = J;
@@ -444,7 +522,7 @@ int efunc_grad(efunc_ctx* ctx, const float* theta, const float* q, const float* 
     p.grad = grad;
     hipError_t e = run_tiles(ctx->w, p, MODE_GRAD, s);
     if (e != hipSuccess) return hip_fail(e, "grad launch");
-    return finite_check(ctx, s, q, J);
+    return EFUNC_OK;
 }
 
 int efunc_fit_step(efunc_ctx* ctx, float* theta, float* m, float* v, int64_t step,
@@ -455,39 +533,7 @@ int efunc_fit_step(efunc_ctx* ctx, float* theta, float* m, float* v, int64_t ste
     int rc;
     if ((rc = check_ctx(ctx))) return rc;
     if ((rc = check_J(ctx, J))) return rc;
-    if (step < 1) return fail(EFUNC_EINVAL, "step = %lld < 1", (long long)step);
-    if ((rc = check_opt(loss_out, "loss_out", 8))) return rc;
-    if (J == 0) return EFUNC_OK;
-    if ((rc = check_ptr(theta, "theta", 4)) || (rc = check_ptr(m, "m", 4)) ||
-        (rc = check_ptr(v, "v", 4)) || (rc = check_ptr(q, "q", 4)) || (rc = check_ptr(o, "o", 4)))
-        return rc;
-    efunc_adam hp;
-    if (adam) hp = *adam; else efunc_default_adam(&hp);
-    if (!(hp.lr >= 0.0f) || !(hp.beta1 >= 0.0f && hp.beta1 < 1.0f) ||
-        !(hp.beta2 >= 0.0f && hp.beta2 < 1.0f) || !(hp.eps > 0.0f) || !(hp.weight_decay >= 0.0f))
-        return fail(EFUNC_EINVAL, "invalid Adam hyper-parameters");
-    hipStream_t s = (hipStream_t)stream;
-    ctx->last_stream = s;
-    Problem p = base_problem(ctx);
-    p.J = J;
-    p.theta = theta;
-    p.q = q;
-    p.aux = o;
-    p.grad = ctx->w.grad;
-    hipError_t e = run_tiles(ctx->w, p, MODE_FIT, s);
-    if (e == hipSuccess && loss_out) e = run_loss_finalize(ctx->w, J, loss_out, s);
-    if (e != hipSuccess) return hip_fail(e, "fit_step launch");
-    if ((rc = finite_check(ctx, s, q, J))) {
-        // leave the internal gradient clean for the next call
-        (void)run_zero_floats(ctx->w.grad, (int64_t)ctx->layout.nch * ctx->w.I, s);
-        return rc;
-    }
-    const double bc1 = 1.0 - pow((double)hp.beta1, (double)step);
-    const double bc2 = 1.0 - pow((double)hp.beta2, (double)step);
-    e = run_adam(ctx->w, theta, m, v, (int64_t)ctx->layout.nch * ctx->w.I, hp.lr, hp.beta1, hp.beta2, hp.eps,
-                 hp.weight_decay, (float)bc1, (float)bc2, s);
-    if (e != hipSuccess) return hip_fail(e, "adam launch");
-    return EFUNC_OK;
+    return fit_step_impl(ctx, theta, m, v, step, adam, q, o, J, loss_out, stream);
 }
 
 int efunc_set_tuning(efunc_ctx* ctx, const efunc_tuning* t)
@@ -526,6 +572,8 @@ int efunc_loss_grad(efunc_ctx* ctx, const float* theta, const float* q, const fl
         (rc = check_ptr(grad, "grad", 4)))
         return rc;
     hipStream_t s = (hipStream_t)stream;
+    if ((rc = finite_check(ctx, s, {{theta, n_params(ctx), "theta"}, {q, 3 * J, "q"}, {o, J, "o"}})))
+        return rc;
     ctx->last_stream = s;
     Problem p = base_problem(ctx);
     p.J = J;
@@ -536,7 +584,7 @@ int efunc_loss_grad(efunc_ctx* ctx, const float* theta, const float* q, const fl
     hipError_t e = run_tiles(ctx->w, p, MODE_FIT, s);
     if (e == hipSuccess && loss_out) e = run_loss_finalize(ctx->w, J, loss_out, s);
     if (e != hipSuccess) return hip_fail(e, "loss_grad launch");
-    return finite_check(ctx, s, q, J);
+    return EFUNC_OK;
 }
 
 int efunc_get_stats(efunc_ctx* ctx, efunc_stats* out)

@@ -212,9 +212,11 @@ def efunc_init_params(ctx, theta, surf, R: int, bandwidth=100.0, rho0=7.0, strea
                                    _stream(stream)))
 
 
-def efunc_eval(ctx, theta, q, O, lse=None, dOdq=None, n_uncertified=None, stream=None):
+def efunc_eval(ctx, theta, q, O, lse=None, dOdq=None, n_uncertified=None, stream=None, n_theta=None):
+    """n_theta: the context's parameter count R^3 x channels; theta must hold
+    exactly that many floats (the C ABI cannot check a pointer's extent)."""
     J = q.numel() // 3
-    _check(lib().efunc_eval(ctx, _ptr(theta, torch.float32, "theta"),
+    _check(lib().efunc_eval(ctx, _ptr(theta, torch.float32, "theta", n_theta),
                             _ptr(q, torch.float32, "q", 3 * J), J,
                             _ptr(O, torch.float32, "O", J), _ptr(lse, torch.float32, "lse", J),
                             _ptr(dOdq, torch.float32, "dOdq", 3 * J),
@@ -222,9 +224,9 @@ def efunc_eval(ctx, theta, q, O, lse=None, dOdq=None, n_uncertified=None, stream
                             _stream(stream)))
 
 
-def efunc_grad(ctx, theta, q, O, lse, dLdO, grad, stream=None):
+def efunc_grad(ctx, theta, q, O, lse, dLdO, grad, stream=None, n_theta=None):
     J = q.numel() // 3
-    _check(lib().efunc_grad(ctx, _ptr(theta, torch.float32, "theta"),
+    _check(lib().efunc_grad(ctx, _ptr(theta, torch.float32, "theta", n_theta),
                             _ptr(q, torch.float32, "q", 3 * J), _ptr(O, torch.float32, "O", J),
                             _ptr(lse, torch.float32, "lse", J),
                             _ptr(dLdO, torch.float32, "dLdO", J), J,
@@ -232,19 +234,20 @@ def efunc_grad(ctx, theta, q, O, lse, dLdO, grad, stream=None):
 
 
 def efunc_fit_step(ctx, theta, m, v, step: int, q, o, loss_out=None, adam: Optional[efunc_adam] = None,
-                   stream=None):
+                   stream=None, n_theta=None):
     J = q.numel() // 3
     n = theta.numel()
-    _check(lib().efunc_fit_step(ctx, _ptr(theta, torch.float32, "theta"),
+    _check(lib().efunc_fit_step(ctx, _ptr(theta, torch.float32, "theta", n_theta),
                                 _ptr(m, torch.float32, "m", n), _ptr(v, torch.float32, "v", n),
                                 step, C.byref(adam) if adam is not None else None,
                                 _ptr(q, torch.float32, "q", 3 * J), _ptr(o, torch.float32, "o", J),
                                 J, _ptr(loss_out, torch.float64, "loss_out", 2), _stream(stream)))
 
 
-def efunc_loss_grad(ctx, theta, q, o, grad, loss_out=None, stream=None):
+def efunc_loss_grad(ctx, theta, q, o, grad, loss_out=None, stream=None, n_theta=None):
     J = q.numel() // 3
-    _check(lib().efunc_loss_grad(ctx, _ptr(theta, torch.float32, "theta"), _ptr(q, torch.float32, "q", 3 * J),
+    _check(lib().efunc_loss_grad(ctx, _ptr(theta, torch.float32, "theta", n_theta),
+                                 _ptr(q, torch.float32, "q", 3 * J),
                                  _ptr(o, torch.float32, "o", J), J,
                                  _ptr(grad, torch.float32, "grad", theta.numel()),
                                  _ptr(loss_out, torch.float64, "loss_out", 2), _stream(stream)))
@@ -303,15 +306,19 @@ def efunc_batch_destroy(b) -> None:
     _check(lib().efunc_batch_destroy(b))
 
 
-def efunc_batch_bind(b, thetas, ms, vs, qs, os_, loss_out=None) -> None:
+def efunc_batch_bind(b, thetas, ms, vs, qs, os_, loss_out=None, n_thetas=None) -> None:
+    """n_thetas: each shape's parameter count R^3 x channels (checked before
+    the call; the C ABI cannot check a pointer's extent)."""
     n = len(thetas)
     if not (len(ms) == len(vs) == len(qs) == len(os_) == n):
         raise ValueError("one tensor per shape in every list")
-    nth = [t.numel() for t in thetas]
+    if n_thetas is not None and len(n_thetas) != n:
+        raise ValueError("one parameter count per shape")
+    nth = [t.numel() for t in thetas] if n_thetas is None else [int(x) for x in n_thetas]
     Js = [q.numel() // 3 for q in qs]
     Jarr = (C.c_int64 * n)(*Js)
     _check(lib().efunc_batch_bind(
-        b, _ptr_array(thetas, torch.float32, "theta"), _ptr_array(ms, torch.float32, "m", nth),
+        b, _ptr_array(thetas, torch.float32, "theta", nth), _ptr_array(ms, torch.float32, "m", nth),
         _ptr_array(vs, torch.float32, "v", nth), _ptr_array(qs, torch.float32, "q", [3 * J for J in Js]),
         _ptr_array(os_, torch.float32, "o", Js), Jarr,
         _ptr(loss_out, torch.float64, "loss_out", 2 * n)))
@@ -369,6 +376,7 @@ class BatchEngine:
                 setattr(c, k, v)
             cfgs.append(c)
         self.Rs = [int(R) for R in Rs]
+        self.n_thetas = [int(R) ** 3 * efunc_channels(c) for R, c in zip(self.Rs, cfgs)]
         self.b = efunc_batch_create(cfgs, max_points)
         self._bound = None
 
@@ -390,7 +398,7 @@ class BatchEngine:
             pass
 
     def bind(self, thetas, ms, vs, qs, os_, loss_out=None):
-        efunc_batch_bind(self.b, thetas, ms, vs, qs, os_, loss_out)
+        efunc_batch_bind(self.b, thetas, ms, vs, qs, os_, loss_out, self.n_thetas)
         self._bound = (thetas, ms, vs, qs, os_, loss_out)  # keep the tensors alive
 
     def fit(self, first_step, n_steps, use_graph=False, adam=None):
@@ -511,6 +519,7 @@ class Engine:
         self.R = R
         self.cfg = c
         self.nch = efunc_channels(c)
+        self.n_theta = R ** 3 * self.nch
         self.max_points = max_points
         self.ctx = efunc_create(c, max_points)
 
@@ -537,20 +546,20 @@ class Engine:
         lse = torch.empty(J, device=q.device, dtype=torch.float32) if with_lse else None
         dq = torch.empty(J, 3, device=q.device, dtype=torch.float32) if with_qgrad else None
         nu = torch.zeros(1, device=q.device, dtype=torch.int64)
-        efunc_eval(self.ctx, theta, q, O, lse, dq, nu)
+        efunc_eval(self.ctx, theta, q, O, lse, dq, nu, n_theta=self.n_theta)
         return O, lse, dq, nu
 
     def grad(self, theta, q, O, lse, dLdO, grad=None):
         if grad is None:
             grad = torch.zeros_like(theta)
-        efunc_grad(self.ctx, theta, q, O, lse, dLdO, grad)
+        efunc_grad(self.ctx, theta, q, O, lse, dLdO, grad, n_theta=self.n_theta)
         return grad
 
     def fit_step(self, theta, m, v, step, q, o, loss_out=None, adam=None):
-        efunc_fit_step(self.ctx, theta, m, v, step, q, o, loss_out, adam)
+        efunc_fit_step(self.ctx, theta, m, v, step, q, o, loss_out, adam, n_theta=self.n_theta)
 
     def loss_grad(self, theta, q, o, grad, loss_out=None):
-        efunc_loss_grad(self.ctx, theta, q, o, grad, loss_out)
+        efunc_loss_grad(self.ctx, theta, q, o, grad, loss_out, n_theta=self.n_theta)
 
     def init_params(self, theta, surf, bandwidth=100.0, rho0=7.0):
         efunc_init_params(self.ctx, theta, surf, self.R, bandwidth, rho0, nch=self.nch)

@@ -17,6 +17,11 @@ Tolerances (FP32 GPU against the FP64 oracle):
              tail_j = sum over such keys of w_a |f_a - O_j|.
   Adam       theta from the GPU's own gradient through the oracle's AdamW
              agrees within 4 float32 ulps of theta plus 1e-6 lr.
+  dO/dq      per query and component |G_gpu - G_ref| <= 1e-4 qsig + 8 u qkap
+             + qtail (oracle_eval_qgrad_scales): qsig the magnitudes of the
+             terms of Eq. func-normal, qkap their first-order change under
+             float32 rounding of logits, values and O, qtail the most that
+             omitting pairs below e^-T can change the sum.
 """
 from __future__ import annotations
 
@@ -116,6 +121,42 @@ def oracle_grad(R, theta, q, dLdO, offsets=1):
     gk, ak, bk = orc.grad_global(keys, q, dLdO, T=T_TAIL)
     return (orc.grad_theta(g, theta, gk), orc.grad_theta(g, theta, ak),
             orc.grad_theta(g, theta, bk))
+
+
+def qgrad_reference(keys, q, degree=None):
+    """dO/dq of the global definition with its tolerance scales, and the value
+    reference whose tolerance the O in Eq. func-normal carries over; degree
+    selects the variant oracle (None: the first-order 13-channel oracle)."""
+    if degree is None:
+        G = orc.eval_qgrad(keys, q)
+        qs, qk, qt, qb = orc.eval_qgrad_scales(keys, q, T_TAIL)
+        _, _, sig = orc.eval_global(keys, q)
+        kap, tail = orc.eval_cond(keys, q, T_TAIL, with_tail=True)
+    else:
+        from oracle import variants as V
+        G = V.eval_qgrad(keys, degree, q)
+        qs, qk, qt, qb = V.eval_qgrad_scales(keys, degree, q, T_TAIL)
+        _, _, sig = V.eval_global(keys, degree, q)
+        kap, tail = V.eval_cond(keys, degree, q, T_TAIL, with_tail=True)
+    return dict(G=G, qsig=qs, qkap=qk, qtail=qt, qbx=qb, sigma=sig, kappa=kap, tail=tail)
+
+
+def check_qgrad(G, ref, rtol=1e-4):
+    """Element-wise query-gradient check against qgrad_reference():
+    |G - G_ref| <= 1e-4 qsig + 8 u qkap + qtail + qbx tol_O, with tol_O the
+    value tolerance of check_values (an error of O moves G by at most qbx
+    times it).  Returns the worst |err| / tolerance."""
+    G = np.asarray(G, dtype=np.float64).reshape(-1, 3)
+    err = np.abs(G - ref["G"])
+    tol_O = 1e-5 * ref["sigma"] + 8 * U32 * ref["kappa"] + ref["tail"]
+    tol = rtol * ref["qsig"] + 8 * U32 * ref["qkap"] + ref["qtail"] + ref["qbx"] * tol_O[:, None] + 1e-30
+    bad = err > tol
+    if bad.any():
+        j, c = np.unravel_index(np.argmax(err / tol), err.shape)
+        raise AssertionError(f"dO/dq: {bad.sum()} of {err.size} components out of tolerance; worst "
+                             f"query {j} axis {c}: gpu={G[j, c]!r} ref={ref['G'][j, c]!r} "
+                             f"qsig={ref['qsig'][j, c]!r} tol={tol[j, c]!r}")
+    return float((err / tol).max()) if err.size else 0.0
 
 
 def ulp32(x):

@@ -213,10 +213,8 @@ def test_query_gradient_matches_oracle(E):
         torch.cuda.synchronize()
         dq = dq.cpu().numpy().astype(np.float64)
     keys = orc.build_keys(orc.Grid(R=R), th)
-    ref = orc.eval_qgrad(keys, q)
-    # scale: sum_a w_a (|d_a| + 2 beta_a |x| |O - f_a|), bounded through sigma and beta
-    scale = np.abs(ref).max() + 1.0
-    assert np.allclose(dq, ref, rtol=0, atol=2e-4 * scale)
+    worst = PT.check_qgrad(dq, PT.qgrad_reference(keys, q))
+    print(f"dO/dq worst err / tolerance {worst:.3g}")
 
 
 # ------------------------------------------------------------------ grad

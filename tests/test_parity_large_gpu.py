@@ -11,11 +11,15 @@ csg16_r32 (32^3, 2^21 points per iteration):
     and AdamW update against the oracle's truncated FP64 fit over all
     2^21 points (truncation at e^-20, independent of the GPU's windows).
 csg256_r128 (128^3, 2^23 points):
-  * efunc_eval on all points; 96 sampled outputs against the global
+  * efunc_eval on all points; 1024 sampled outputs against the global
     definition (4.2M keys each);
-  * efunc_grad with dL/dO on 48 sampled points against the global definition;
-  * efunc_fit_step against the composition efunc_eval + efunc_grad (a
-    property of the fused step that holds at any size).
+  * efunc_grad with dL/dO on 256 sampled points against the global
+    definition;
+  * efunc_fit_step on a seeded 2^16-point minibatch of the same workload
+    (the 128^3 windows, W = 9, and the mean-shift keys) against the oracle's
+    truncated FP64 fit step: loss, gradient element by element, AdamW;
+  * efunc_fit_step on all 2^23 points against the composition efunc_eval +
+    efunc_grad (a property of the fused step that holds at any size).
 """
 import numpy as np
 import pytest
@@ -159,7 +163,7 @@ def test_eval_csg256_r128_full_size_sampled(E, r128):
         torch.cuda.synchronize()
         st = eng.stats()
         O, lse = O.cpu().numpy(), lse.cpu().numpy()
-    idx = sample_idx(w.J, 96, 4)
+    idx = sample_idx(w.J, 1024, 4)
     ref = PT.reference(R, th, q[idx])
     PT.check_eval(O[idx], lse[idx], ref)
     assert np.all(np.isfinite(O))
@@ -169,7 +173,7 @@ def test_eval_csg256_r128_full_size_sampled(E, r128):
 def test_grad_csg256_r128_full_size_sampled_dldo(E, r128):
     w, q, o, R = r128
     th = _r128_theta(E, w, 52)
-    idx = sample_idx(w.J, 48, 5)
+    idx = sample_idx(w.J, 256, 5)
     Or, lr, _ = PT.oracle_values(R, th, q[idx])
     O = np.zeros(w.J, np.float32)
     lse = np.zeros(w.J, np.float32)
@@ -182,6 +186,41 @@ def test_grad_csg256_r128_full_size_sampled_dldo(E, r128):
         G = G.cpu().numpy()
     gr, ar, br = PT.oracle_grad(R, th, q[idx], dl[idx].astype(np.float64))
     PT.check_grad(G, gr, ar, br)
+
+
+def test_fit_step_csg256_r128_subsample_matches_oracle(E, r128):
+    """The fused step at 128^3 on a seeded 2^16-point minibatch (half uniform,
+    half near the surface) against the oracle's truncated FP64 fit step
+    (pairs within e^-20 of each query's largest weight): loss to 1e-5, the
+    gradient (from the first moment) element by element, and AdamW on the
+    GPU's gradient to 4 ulps."""
+    w, _, _, R = r128
+    q, o = W.make_batch(w, 7, J=1 << 16, device=PT.DEV)
+    th = _r128_theta(E, w, 54)
+    n = th.size
+    with E.Engine(R, len(q)) as eng:
+        tth = PT.to_dev(th)
+        m = torch.zeros(n, device=PT.DEV)
+        v = torch.zeros(n, device=PT.DEV)
+        loss = torch.zeros(2, device=PT.DEV, dtype=torch.float64)
+        eng.fit_step(tth, m, v, 1, PT.to_dev(q), PT.to_dev(o), loss)
+        torch.cuda.synchronize()
+        st = eng.stats()
+        th1, m1, loss = (x.cpu().numpy() for x in (tth, m, loss))
+    assert st["W"] == 9 and st["n_uncertified"] == 0, st
+    g = orc.Grid(R=R)
+    keys = orc.build_keys(g, th)
+    Ot, _, _ = orc.eval_trunc(g, keys, q, 20.0)
+    res = Ot - o.astype(np.float64)
+    assert abs(loss[0] - np.mean(res ** 2)) <= 1e-5 * np.mean(res ** 2)
+    assert abs(loss[1] - np.mean(np.abs(res))) <= 1e-5 * np.mean(np.abs(res))
+    gk, ak = orc.grad_trunc(g, keys, q, 2.0 * res / len(q), 20.0)
+    gr, ar = orc.grad_theta(g, th, gk), orc.grad_theta(g, th, ak)
+    g_gpu = m1.astype(np.float64) / (1.0 - np.float32(0.9))
+    worst = PT.check_grad(g_gpu, gr, ar)
+    th_ref, _, _ = orc.adam(th.reshape(-1), np.zeros(n), np.zeros(n), g_gpu.reshape(-1), 1)
+    assert np.all(np.abs(th1.reshape(-1) - th_ref) <= 4 * PT.ulp32(th_ref) + 1e-6 * 6e-4)
+    print(f"128^3 fit step: pairs={st['pairs']} worst grad err / A = {worst:.3g}")
 
 
 def test_fit_step_csg256_r128_matches_eval_then_grad(E, r128):

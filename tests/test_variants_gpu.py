@@ -66,9 +66,8 @@ def test_variant_eval_and_query_gradient(E, v):
         O, lse, dq = O.cpu().numpy(), lse.cpu().numpy(), dq.cpu().numpy()
     keys, ref = reference(m, th, q)
     PT.check_eval(O, lse, ref)
-    g = V.eval_qgrad(keys, m.degree, q)
-    scale = np.abs(g).max() + 1.0
-    assert np.abs(dq - g).max() <= 3e-4 * scale, np.abs(dq - g).max() / scale
+    worst = PT.check_qgrad(dq, PT.qgrad_reference(keys, q, degree=m.degree))
+    print(f"{v[0]}: dO/dq worst err / tolerance {worst:.3g}")
 
 
 @pytest.mark.parametrize("v", VARIANTS, ids=[v[0] for v in VARIANTS])
