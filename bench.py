@@ -33,20 +33,55 @@ sys.path.insert(0, ROOT)
 
 METRIC = "fit points·iters/sec (fused fwd+bwd)"
 
-# Algorithmic FP32 operations per key-query pair, counted from the arithmetic
-# each pass must do (an FMA, add, mul, sub or exp2 is one operation):
+# Algorithmic FP32 operations per key-query pair (an FMA, add, mul, sub or
+# exp2 is one operation).  Two counts are reported:
+# * the method's per-pair work as the closed forms state it (the headline
+#   fraction): forward 14 VALU + 1 exp (distance, logit, shifted exponent,
+#   polynomial, the two running sums); backward 19 VALU + 1 exp per grid
+#   pair (recomputed weight and polynomial, delta, r = f - O, the sums for o,
+#   d and beta); moved pairs add the centre gradient
+#   delta (-d + 2 beta x r), 8 more;
+OPS_FWD = 15
+OPS_BWD_GRID = 20
+OPS_BWD_MOVED = 28
+# * the operations this engine's factored form needs per pair:
 #   forward:  x = q - c (3), |x|^2 (3), exponent fma (1), exp2 (1),
 #             f = o + x.d (3), e += l (1), m += l f (1)                 = 13
 #   backward: x (3), |x|^2 (3), exponent fma (1), exp2 (1), f (3),
 #             delta = g w (1), u = delta (f - O) (2), sums for o, d, beta
 #             (1 + 3 + 1)                                              = 19
-#             moved keys add the centre sums u x (3)                   = 22
-OPS_FWD = 13
-OPS_BWD_GRID = 19
-OPS_BWD_MOVED = 22
+#             moved keys add the centre sums u x (3); the -d sum(delta)
+#             term is applied once per key, not per pair               = 22
+ENG_FWD = 13
+ENG_BWD_GRID = 19
+ENG_BWD_MOVED = 22
 # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: one FP32 lane-operation per lane
 # per clock (packed FP32 is not used), 39.3 T lane-ops/s.
 ROOFLINE_PEAK = 256 * 4 * 16 * 2.4e9
+
+
+def alu_roofline(kernel, tile_avg_s, pairs, bwd_pairs, bwd_moved, traffic):
+    """The tile kernel's roofline entry: algorithmic operations per launch
+    over its event-timed average duration, against the FP32 lane peak."""
+    ops = pairs * OPS_FWD + (bwd_pairs - bwd_moved) * OPS_BWD_GRID + bwd_moved * OPS_BWD_MOVED
+    eng = pairs * ENG_FWD + (bwd_pairs - bwd_moved) * ENG_BWD_GRID + bwd_moved * ENG_BWD_MOVED
+    return {
+        "bound": "alu",
+        "kernel": kernel,
+        "achieved": ops / tile_avg_s / 1e12,
+        "peak": ROOFLINE_PEAK / 1e12,
+        "unit": "Tops/s",
+        "frac": ops / tile_avg_s / ROOFLINE_PEAK,
+        "traffic": traffic,
+        "tile_kernel_ms": tile_avg_s * 1e3,
+        "ops_per_pair": {"fwd": OPS_FWD, "bwd_grid": OPS_BWD_GRID, "bwd_moved": OPS_BWD_MOVED},
+        "ops_per_launch": ops,
+        "frac_engine_count": eng / tile_avg_s / ROOFLINE_PEAK,
+        "engine_ops_per_pair": {"fwd": ENG_FWD, "bwd_grid": ENG_BWD_GRID, "bwd_moved": ENG_BWD_MOVED},
+        "fwd_pairs_per_launch": pairs,
+        "bwd_pairs_per_launch": bwd_pairs,
+        "bwd_moved_pairs_per_launch": bwd_moved,
+    }
 
 
 def kernel_source_sha() -> str:
@@ -71,23 +106,70 @@ def measured_traffic(workload: str):
     return int(float(fields["hbm_bytes_per_launch"]))
 
 
-def cpu_baseline(workload, q, o, R, theta, sample):
-    """The FP64 oracle's fit step (global support, the definition) timed on a
-    bounded sample of the same batch: half uniform, half near-surface."""
+_ORACLE_CHILD = """
+import sys, time
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+import oracle as orc
+d = np.load(sys.argv[2])
+th, q, o = d["theta"], d["q"], d["o"]
+g = orc.Grid(R=th.shape[0])
+n = th.size
+t0 = time.perf_counter()
+orc.fit_step(g, th, np.zeros(n), np.zeros(n), 1, q, o, mode=1, T=20.0)
+print(time.perf_counter() - t0, orc.threads())
+"""
+
+
+def cpu_baseline(workload, q, o, R, theta, sample, sample_global=4096, reps=3):
+    """The FP64 oracle's fit step timed on the host cores on a seeded
+    subsample of the same batch (half uniform, half near-surface):
+    * value: truncated mode (pairs within e^-20 of each query's largest
+      weight, the result the engine reproduces) on `sample` points, all
+      OpenMP threads, median of `reps`;
+    * one_thread: the same on one thread (a child process with
+      OMP_NUM_THREADS=1; it touches no GPU);
+    * global_support: the paper's definition (every key for every point) on
+      `sample_global` points, all threads."""
+    import subprocess
+    import tempfile
     import oracle as orc
     J = len(q)
+    rng = np.random.default_rng(12345)
     h = sample // 2
-    idx = np.concatenate([np.arange(h), J // 2 + np.arange(sample - h)])
+    idx = np.concatenate([rng.choice(J // 2, h, replace=False),
+                          J // 2 + rng.choice(J - J // 2, sample - h, replace=False)])
     qs, os_ = q[idx].astype(np.float64), o[idx].astype(np.float64)
     g = orc.Grid(R=R)
     n = theta.size
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        orc.fit_step(g, theta, np.zeros(n), np.zeros(n), 1, qs, os_, mode=1, T=20.0)
+        ts.append(time.perf_counter() - t0)
+    dt = float(np.median(ts))
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "sample.npz")
+        np.savez(path, theta=theta, q=qs, o=os_)
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        res = subprocess.run([sys.executable, "-c", _ORACLE_CHILD, ROOT, path], env=env,
+                             capture_output=True, text=True, check=True)
+        dt1, thr1 = res.stdout.split()
+        dt1 = float(dt1)
+    hg = sample_global // 2
+    gidx = np.concatenate([idx[:hg], idx[h:h + sample_global - hg]])
     t0 = time.perf_counter()
-    orc.fit_step(g, theta, np.zeros(n), np.zeros(n), 1, qs, os_)
-    dt = time.perf_counter() - t0
+    orc.fit_step(g, theta, np.zeros(n), np.zeros(n), 1, q[gidx].astype(np.float64),
+                 o[gidx].astype(np.float64), mode=0)
+    dtg = time.perf_counter() - t0
     return {"value": sample / dt, "unit": "points*iters/s", "cores": orc.threads(), "kind": "oracle",
-            "sample": f"{sample} points of iteration 0 ({h} uniform + {sample - h} near-surface), "
-                      f"one FP64 fit step with global support over all {2 * R ** 3} keys; "
-                      f"{dt:.1f} s"}
+            "sample": f"{sample} seeded points of iteration 0 ({h} uniform + {sample - h} near-surface), "
+                      f"one FP64 fit step in truncated mode (e^-20, the result the engine reproduces), "
+                      f"{orc.threads()} threads, median of {reps}: {dt:.2f} s",
+            "one_thread": {"value": sample / dt1, "cores": int(thr1), "seconds": dt1},
+            "global_support": {"value": sample_global / dtg, "cores": orc.threads(), "seconds": dtg,
+                               "sample": f"{sample_global} of the same points, every one of the "
+                                         f"{2 * R ** 3} keys per point (the paper's definition)"}}
 
 
 def naive_efunc(theta, q):
@@ -272,9 +354,7 @@ def bench_batch(args, torch):
     pairs = sum(st["pairs"] for st in sts)
     bp = sum(st["bwd_pairs"] for st in sts)
     bpm = sum(st["bwd_pairs_moved"] for st in sts)
-    ops = pairs * OPS_FWD + (bp - bpm) * OPS_BWD_GRID + bpm * OPS_BWD_MOVED
     tile_avg_s = tile_ms / max(launches, 1) * 1e-3
-    achieved = ops / tile_avg_s
     Rs = [w.R for w in ws]
     out = {
         "metric": "batched fit points·iters/sec (64 shapes, fused fwd+bwd)",
@@ -302,20 +382,7 @@ def bench_batch(args, torch):
             "tuning": B.tuning(),
             "autotuned_ms": tuned[1] if tuned else None,
         },
-        "roofline": {
-            "bound": "alu",
-            "kernel": "k_tile_batch",
-            "achieved": achieved / 1e12,
-            "peak": ROOFLINE_PEAK / 1e12,
-            "unit": "Tops/s",
-            "frac": achieved / ROOFLINE_PEAK,
-            "traffic": None,
-            "tile_kernel_ms": tile_avg_s * 1e3,
-            "fwd_pairs_per_launch": pairs,
-            "bwd_pairs_per_launch": bp,
-            "bwd_moved_pairs_per_launch": bpm,
-            "ops_per_launch": ops,
-        },
+        "roofline": alu_roofline("k_tile_batch", tile_avg_s, pairs, bp, bpm, None),
         "stats": {"uncertified": sum(st["n_uncertified"] for st in sts),
                   "tiles": sum(st["n_tiles"] for st in sts),
                   "loss_mse_mean": float(lossv[:, 0].mean()), "gen_seconds": t_gen,
@@ -514,7 +581,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="csg16_r32")
     ap.add_argument("--batches", type=int, default=4, help="distinct resident batches cycled")
-    ap.add_argument("--cpu-sample", type=int, default=32768)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--compare-autodiff", action="store_true",
                     help="print the fused vs materialising-autodiff comparison instead")
@@ -615,8 +682,6 @@ def main():
     tile_avg_s = tile_ms / max(launches, 1) * 1e-3
     pairs, pm = st["pairs"], st["pairs_moved"]
     bp, bpm = st["bwd_pairs"], st["bwd_pairs_moved"]
-    ops = pairs * OPS_FWD + (bp - bpm) * OPS_BWD_GRID + bpm * OPS_BWD_MOVED
-    achieved = ops / tile_avg_s
     traffic = measured_traffic(args.workload)
 
     out = {
@@ -645,21 +710,8 @@ def main():
             "resident_batches": args.batches,
             "tuning": eng.tuning(),
         },
-        "roofline": {
-            "bound": "alu",
-            "kernel": "k_tile<FIT>",
-            "achieved": achieved / 1e12,
-            "peak": ROOFLINE_PEAK / 1e12,
-            "unit": "Tops/s",
-            "frac": achieved / ROOFLINE_PEAK,
-            "traffic": traffic,
-            "tile_kernel_ms": tile_avg_s * 1e3,
-            "fwd_pairs_per_launch": pairs,
-            "fwd_moved_pairs_per_launch": pm,
-            "bwd_pairs_per_launch": bp,
-            "bwd_moved_pairs_per_launch": bpm,
-            "ops_per_launch": ops,
-        },
+        "roofline": dict(alu_roofline("k_tile<FIT>", tile_avg_s, pairs, bp, bpm, traffic),
+                         fwd_moved_pairs_per_launch=pm),
         "stats": {"W": st["W"], "tiles": st["n_tiles"], "uncertified": st["n_uncertified"],
                   "beta_min": st["beta_min"], "loss_mse": float(lossv[0]), "loss_l1": float(lossv[1]),
                   "gen_seconds": t_gen, "kernel_source_sha": kernel_source_sha()},
