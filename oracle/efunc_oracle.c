@@ -489,9 +489,14 @@ int oracle_eval_trunc(const oracle_grid* g, const double* keys, const double* q,
  * key-parallel (Alg. 2).  Pair (j, a) is kept iff s_a(q_j) >= M_j - T, so a
  * key only meets queries within sqrt((T - min_j M_j) / beta_a) of its centre;
  * those come from a uniform bin grid over the queries and are tested
- * exactly. */
+ * exactly.  With bk, also the part of the scale A that comes from pairs whose
+ * weight is below e^-Tb (s - lse_j < -Tb), taken over every pair with
+ * s >= M_j - T2 whether kept or not: two truncations of the global sums that
+ * both keep every pair at or above e^-Tb differ by at most this much, up to
+ * pairs below e^-T2 (the search radius grows to T2). */
 int oracle_grad_trunc(const oracle_grid* g, const double* keys, const double* q,
-                      int64_t J, double T, const double* dLdO, double* gk, double* ak)
+                      int64_t J, double T, const double* dLdO, double* gk, double* ak,
+                      double Tb, double T2, double* bk)
 {
     const int64_t R = g->R, nkeys = oracle_num_keys(g);
     const double h = (g->hi - g->lo) / (double)(R - 1);
@@ -519,8 +524,9 @@ int oracle_grad_trunc(const oracle_grid* g, const double* keys, const double* q,
 #pragma omp parallel for schedule(dynamic, 16)
         for (int64_t a = 0; a < nkeys; ++a) {
             const double* k = keys + a * ORACLE_KEY;
-            double gsum[8] = {0}, asum[8] = {0};
-            const double rad = J > 0 ? sqrt((T - Mmin) / k[3]) : 0.0;
+            double gsum[8] = {0}, asum[8] = {0}, bsum[8] = {0};
+            const double Tr = (bk && T2 > T) ? T2 : T;
+            const double rad = J > 0 ? sqrt((Tr - Mmin) / k[3]) : 0.0;
             int64_t blo[3], bhi[3];
             for (int d = 0; d < 3; ++d) {
                 blo[d] = clampi((int64_t)floor((k[d] - rad - pb.lo[d]) / pb.cell) - 1, 0, pb.n[d] - 1);
@@ -534,12 +540,21 @@ int oracle_grad_trunc(const oracle_grid* g, const double* keys, const double* q,
                             const int64_t j = pb.idx[t];
                             const double* qj = q + 3 * j;
                             const double s = logit(k, qj);
-                            if (s < M[j] - T) continue;
+                            if (s < M[j] - Tr) continue;
                             const double w = exp(s - lse[j]);
                             const double x0 = qj[0] - k[0], x1 = qj[1] - k[1], x2 = qj[2] - k[2];
                             const double r = value(k, qj) - O[j];
                             const double dw = dLdO[j] * w, adw = fabs(dLdO[j]) * w;
                             const double x2n = x0 * x0 + x1 * x1 + x2 * x2;
+                            if (bk && s - lse[j] < -Tb) {
+                                bsum[0] += adw * (fabs(k[5]) + 2.0 * k[3] * fabs(x0 * r));
+                                bsum[1] += adw * (fabs(k[6]) + 2.0 * k[3] * fabs(x1 * r));
+                                bsum[2] += adw * (fabs(k[7]) + 2.0 * k[3] * fabs(x2 * r));
+                                bsum[3] += adw * x2n * fabs(r);
+                                bsum[4] += adw;
+                                bsum[5] += adw * fabs(x0); bsum[6] += adw * fabs(x1); bsum[7] += adw * fabs(x2);
+                            }
+                            if (s < M[j] - T) continue;
                             gsum[0] += dw * (-k[5] + 2.0 * k[3] * x0 * r);
                             gsum[1] += dw * (-k[6] + 2.0 * k[3] * x1 * r);
                             gsum[2] += dw * (-k[7] + 2.0 * k[3] * x2 * r);
@@ -557,6 +572,7 @@ int oracle_grad_trunc(const oracle_grid* g, const double* keys, const double* q,
             for (int c = 0; c < 8; ++c) {
                 gk[a * 8 + c] = gsum[c];
                 if (ak) ak[a * 8 + c] = asum[c];
+                if (bk) bk[a * 8 + c] = bsum[c];
             }
         }
     }
@@ -656,7 +672,7 @@ int oracle_fit_step(const oracle_grid* g, const float* theta, const double* m,
         if (mode == 0)
             oracle_grad(keys, nkeys, q, J, dl, gk, NULL, INFINITY, NULL);
         else
-            rc = oracle_grad_trunc(g, keys, q, J, T, dl, gk, NULL);
+            rc = oracle_grad_trunc(g, keys, q, J, T, dl, gk, NULL, 0.0, T, NULL);
     }
     if (rc == 0) {
         oracle_grad_theta(g, theta, gk, gt);

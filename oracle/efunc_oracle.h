@@ -106,9 +106,13 @@ int oracle_eval_trunc(const oracle_grid* g, const double* keys, const double* q,
                       int64_t J, double T, double* O, double* lse, double* sigma);
 
 /* Truncated key gradients with the pair set of oracle_eval_trunc (same
- * layout as oracle_grad).  Returns 0, or -1 on allocation failure. */
+ * layout as oracle_grad).  bk (optional): the part of ak's scale from pairs
+ * with weight below e^-Tb, over all pairs with logit >= M_j - T2 (kept or
+ * not); it bounds how far another truncation that keeps every pair at or
+ * above e^-Tb can differ.  Returns 0, or -1 on allocation failure. */
 int oracle_grad_trunc(const oracle_grid* g, const double* keys, const double* q,
-                      int64_t J, double T, const double* dLdO, double* gk, double* ak);
+                      int64_t J, double T, const double* dLdO, double* gk, double* ak,
+                      double Tb, double T2, double* bk);
 
 /* Adam / AdamW with decoupled weight decay, bias-corrected, step >= 1
  * (Sec. 3.4 and Sec. 4.2).  Updates theta, m, v in place (double). */

@@ -80,7 +80,8 @@ def load():
         lib.oracle_grad_theta.argtypes = [_G, _F, _D, _D]
         lib.oracle_eval_trunc.argtypes = [_G, _D, _D, _I64, C.c_double, _D, _D, _D]
         lib.oracle_eval_trunc.restype = C.c_int
-        lib.oracle_grad_trunc.argtypes = [_G, _D, _D, _I64, C.c_double, _D, _D, _D]
+        lib.oracle_grad_trunc.argtypes = [_G, _D, _D, _I64, C.c_double, _D, _D, _D,
+                                          C.c_double, C.c_double, _D]
         lib.oracle_grad_trunc.restype = C.c_int
         lib.oracle_adam.argtypes = [_D, _D, _D, _D, _I64, _I64, C.c_double, C.c_double,
                                     C.c_double, C.c_double, C.c_double]
@@ -211,16 +212,21 @@ def grad_global(keys, q, dLdO, T: float = None):
     return (gk, ak) if T is None else (gk, ak, bk)
 
 
-def grad_trunc(g: Grid, keys, q, dLdO, T: float = 20.0):
+def grad_trunc(g: Grid, keys, q, dLdO, T: float = 20.0, Tb: float = None, T2: float = None):
+    """(gk, ak) of the truncated gradient; with Tb also bk, the part of the
+    scale from pairs below e^-Tb among those with logit >= M_j - T2 (T2
+    defaults to T + 10)."""
     keys, q, dLdO = _f64(keys), _f64(q).reshape(-1, 3), _f64(dLdO)
     gk = np.empty((keys.shape[0], 8))
     ak = np.empty((keys.shape[0], 8))
+    bk = np.empty((keys.shape[0], 8)) if Tb is not None else None
+    T2 = T + 10.0 if T2 is None else T2
     gc = g.c()
     rc = load().oracle_grad_trunc(C.byref(gc), _d(keys), _d(q), q.shape[0], T, _d(dLdO),
-                                  _d(gk), _d(ak))
+                                  _d(gk), _d(ak), 0.0 if Tb is None else Tb, T2, _d(bk))
     if rc != 0:
         raise MemoryError("oracle_grad_trunc failed")
-    return gk, ak
+    return (gk, ak) if Tb is None else (gk, ak, bk)
 
 
 def grad_theta(g: Grid, theta, gk) -> np.ndarray:

@@ -46,6 +46,9 @@ MUTANTS = {
                       "const double bxa = 2.0 * k[3] * w * x;\n                qs[d]"),
     "qtail_drops_renormalisation": ("if (below) qt[d] += w * (fabs(ga) + fabs(G[d]));",
                                     "if (below) qt[d] += w * fabs(ga);"),
+    "trunc_band_wrong_side": ("if (bk && s - lse[j] < -Tb) {", "if (bk && s - lse[j] > -Tb) {"),
+    "trunc_band_from_max": ("if (bk && s - lse[j] < -Tb) {", "if (bk && s - M[j] < -Tb) {"),
+    "trunc_band_search_too_short": ("const double Tr = (bk && T2 > T) ? T2 : T;", "const double Tr = T;"),
 }
 
 PINS = [getattr(P, n) for n in dir(P) if n.startswith("test_")]

@@ -775,3 +775,26 @@ def test_query_gradient_scale_equals_gradient_when_terms_share_a_sign(orc):
     G = orc.eval_qgrad(k, q)
     assert np.all(G > 0)
     assert np.allclose(qs, G, rtol=1e-12, atol=0)
+
+
+def test_truncated_band_scale_is_the_global_subthreshold_scale(orc):
+    """The truncated gradient's band scale (pairs below e^-Tb, searched down to
+    M_j - T2) equals the global B when T2 reaches every pair, and it bounds
+    how far the truncation at T moves the gradient from the definition."""
+    rng = np.random.default_rng(57)
+    R = 4
+    g = orc.Grid(R=R)
+    keys = orc.build_keys(g, W.perturbed_theta(R, 58, rho0=3.0))
+    q = rand_q(rng, 120)
+    dl = rng.standard_normal(120)
+    gk, ak, bk = orc.grad_global(keys, q, dl, T=5.0)
+    _, _, bt = orc.grad_trunc(g, keys, q, dl, 1e4, Tb=5.0, T2=1e4)
+    assert 0 < (bk > 0).sum() and np.any(bk < ak)
+    assert np.allclose(bt, bk, rtol=1e-10, atol=1e-300)
+    # truncating at T = 20 drops only pairs below e^-20, which B at Tb = 20 covers
+    _, _, b20 = orc.grad_global(keys, q, dl, T=20.0)
+    gt, at, bt = orc.grad_trunc(g, keys, q, dl, 20.0, Tb=20.0, T2=60.0)
+    # weights from the truncated lse, which is within K e^-20 of the global one
+    assert np.allclose(bt, b20, rtol=1e-6, atol=1e-300)
+    assert np.all(np.abs(gt - gk) <= bt + 1e-6 * at + 1e-300)
+    assert np.abs(gt - gk).max() > 0
