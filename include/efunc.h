@@ -188,6 +188,26 @@ int efunc_fit_step(efunc_ctx* ctx, float* theta, float* m, float* v, int64_t ste
 int efunc_loss_grad(efunc_ctx* ctx, const float* theta, const float* q, const float* o, int64_t J,
                     float* grad, double* loss_out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * efunc_fit_step without a context.  The workspace for (cfg, J) is carved
+ * from one fixed device array of EFUNC_STATIC_SCRATCH_MIB MiB per GPU, which
+ * the library holds from the first call on a device until the process ends;
+ * the call allocates nothing and runs the kernels of efunc_fit_step on the
+ * current device.  Arguments, outputs and the result are those of
+ * efunc_fit_step; the context's configuration is passed as cfg (host) and
+ * max_points is J.  J = 0 performs only the one-time per-device set-up (make
+ * such a call before capturing a graph).  Every call on a GPU uses the same
+ * array, so calls that overlap on one GPU (other streams, other host threads)
+ * race and give wrong results: serialise them.  check_finite must be 0.
+ * Errors: EFUNC_EINVAL, EFUNC_ESIZE (the workspace of R and J exceeds the
+ * array: about 70 B per query plus 1.7 MB per 32^3 parameters; R = 32 fits
+ * J <= 700k), EFUNC_EUNSUPPORTED, EFUNC_EHIP. */
+#define EFUNC_STATIC_SCRATCH_MIB 64
+int efunc_fit_step_static(const efunc_config* cfg, float* theta, float* m, float* v, int64_t step,
+                          const efunc_adam* adam, const float* q, const float* o, int64_t J,
+                          double* loss_out, void* stream);
+
 /* Copy the statistics of the last call into *out (host).  Synchronises the
  * stream of that call.  Errors: EFUNC_EINVAL, EFUNC_EHIP. */
 int efunc_get_stats(efunc_ctx* ctx, efunc_stats* out);

@@ -11,6 +11,7 @@
 #include <string>
 #include <cmath>
 #include <initializer_list>
+#include <mutex>
 #include <vector>
 
 using namespace efunc;
@@ -336,9 +337,85 @@ int fit_step_impl(efunc_ctx* ctx, float* theta, float* m, float* v, int64_t step
     return EFUNC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free fit step.  Its workspace is carved from this fixed device
+// array (one copy per GPU, held until the process ends).  Host code never
+// passes the array's name to a kernel or a copy: it takes the device address
+// from hipGetSymbolAddress once per device and uses that.
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)EFUNC_STATIC_SCRATCH_MIB << 20;
+static __device__ __align__(256) char scratch[STATIC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES];
+int g_scratch_cu[MAX_DEVICES];
+
+// Device address of the current device's scratch array and its compute
+// unit count, looked up on the first call on that device.
+int static_scratch(void** ptr, int* num_cu, int* device)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(EFUNC_EUNSUPPORTED, "device %d >= %d", dev, MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress of the static scratch");
+        if (!p) return fail(EFUNC_EHIP, "hipGetSymbolAddress returned NULL for the static scratch");
+        int cu = 0;
+        e = hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return hip_fail(e, "device query");
+        g_scratch_cu[dev] = cu;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    *num_cu = g_scratch_cu[dev];
+    *device = dev;
+    return EFUNC_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int efunc_fit_step_static(const efunc_config* cfg, float* theta, float* m, float* v, int64_t step,
+                          const efunc_adam* adam, const float* q, const float* o, int64_t J,
+                          double* loss_out, void* stream)
+{
+    g_err.clear();
+    int rc;
+    Layout layout;
+    if ((rc = check_config(cfg, &layout))) return rc;
+    if (cfg->check_finite)
+        return fail(EFUNC_EUNSUPPORTED, "check_finite copies inputs to the host; not available here");
+    if (J < 0) return fail(EFUNC_EINVAL, "J = %lld < 0", (long long)J);
+    if (J > (int64_t)INT32_MAX - PMAX) return fail(EFUNC_ESIZE, "J = %lld too large", (long long)J);
+    void* base = nullptr;
+    int num_cu = 0, dev = 0;
+    if ((rc = static_scratch(&base, &num_cu, &dev))) return rc;
+    if (J == 0) return EFUNC_OK;
+    efunc_ctx ctx;
+    ctx.cfg = *cfg;
+    ctx.layout = layout;
+    ctx.device = dev;
+    ctx.last_stream = nullptr;
+    const size_t need = carve_work(*cfg, layout, J, num_cu, nullptr, ctx.w);
+    if (need > STATIC_SCRATCH_BYTES)
+        return fail(EFUNC_ESIZE, "R = %d with J = %lld needs %zu bytes of workspace; the static scratch holds %zu",
+                    cfg->R, (long long)J, need, STATIC_SCRATCH_BYTES);
+    carve_work(*cfg, layout, J, num_cu, static_cast<char*>(base), ctx.w);
+    ctx.geo = make_geo(*cfg, ctx.w.tlat);
+    hipStream_t s = (hipStream_t)stream;
+    // The array keeps whatever the last call on this GPU left in it: write the
+    // lattice coordinates and clear the internal gradient (the fit step
+    // expects it zero) with kernels, before the step.
+    hipError_t e = run_lattice(ctx.w.tlat, cfg->R, (double)cfg->lo, (double)cfg->hi, s);
+    if (e == hipSuccess) e = run_zero_floats(ctx.w.grad, n_params(&ctx), s);
+    if (e != hipSuccess) return hip_fail(e, "static scratch set-up");
+    return fit_step_impl(&ctx, theta, m, v, step, adam, q, o, J, loss_out, stream);
+}
 
 void efunc_default_config(efunc_config* cfg, int32_t R)
 {

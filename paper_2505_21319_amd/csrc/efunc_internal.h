@@ -219,5 +219,7 @@ hipError_t run_init_params(const Work& w, const Geo& g, const Layout& L, float* 
                            hipStream_t s);
 hipError_t run_count_uncertified(const Work& w, int64_t* out, hipStream_t s);
 hipError_t run_zero_floats(float* p, int64_t n, hipStream_t s);
+// Writes the R float32 vertex coordinates of [lo, hi] into t (one workgroup).
+hipError_t run_lattice(float* t, int R, double lo, double hi, hipStream_t s);
 
 }  // namespace efunc

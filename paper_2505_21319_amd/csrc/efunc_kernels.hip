@@ -2144,6 +2144,21 @@ hipError_t run_init_params(const Work& w, const Geo& g, const Layout& L, float* 
     return hipGetLastError();
 }
 
+// Vertex coordinates t[n] = float32(lo + (hi - lo) n / (R - 1)), each
+// operation rounded in double as on the host (no contraction).
+__global__ void k_lattice(float* __restrict__ t, int R, double lo, double hi)
+{
+#pragma clang fp contract(off)
+    for (int n = threadIdx.x; n < R; n += blockDim.x)
+        t[n] = (float)(lo + (hi - lo) * (double)n / (double)(R - 1));
+}
+
+hipError_t run_lattice(float* t, int R, double lo, double hi, hipStream_t s)
+{
+    k_lattice<<<1, BLOCK, 0, s>>>(t, R, lo, hi);
+    return hipGetLastError();
+}
+
 hipError_t run_count_uncertified(const Work& w, int64_t* out, hipStream_t s)
 {
     k_count_uncertified<<<1, 64, 0, s>>>(w.st, out);

@@ -73,7 +73,7 @@ EXPORTS = ["efunc_default_config", "efunc_channels", "efunc_default_adam", "efun
            "efunc_batch_read_timing", "efunc_initnet_create", "efunc_initnet_destroy",
            "efunc_initnet_num_params", "efunc_initnet_forward", "efunc_initnet_backward",
            "efunc_conv3d_bf16", "efunc_conv3d_wgrad_bf16", "efunc_conv3d_pack_weights",
-           "efunc_adam_update", "efunc_loss_grad", "efunc_last_error"]
+           "efunc_adam_update", "efunc_loss_grad", "efunc_fit_step_static", "efunc_last_error"]
 
 _lib = None
 
@@ -130,6 +130,8 @@ def lib() -> C.CDLL:
         L.efunc_conv3d_pack_weights.argtypes = [vp, i32, i32, vp, vp, vp]
         L.efunc_adam_update.argtypes = [vp, vp, vp, vp, i64, i64, C.POINTER(efunc_adam), vp]
         L.efunc_loss_grad.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp]
+        L.efunc_fit_step_static.argtypes = [C.POINTER(efunc_config), vp, vp, vp, i64,
+                                             C.POINTER(efunc_adam), vp, vp, i64, vp, vp]
         L.efunc_last_error.argtypes = []
         L.efunc_last_error.restype = C.c_char_p
         for name in ("efunc_create", "efunc_destroy", "efunc_init_params", "efunc_eval",
@@ -141,7 +143,7 @@ def lib() -> C.CDLL:
                      "efunc_batch_read_timing", "efunc_initnet_create", "efunc_initnet_destroy",
                      "efunc_initnet_forward", "efunc_initnet_backward", "efunc_conv3d_bf16",
                      "efunc_conv3d_wgrad_bf16", "efunc_conv3d_pack_weights", "efunc_adam_update",
-                     "efunc_loss_grad"):
+                     "efunc_loss_grad", "efunc_fit_step_static"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -242,6 +244,19 @@ def efunc_fit_step(ctx, theta, m, v, step: int, q, o, loss_out=None, adam: Optio
                                 step, C.byref(adam) if adam is not None else None,
                                 _ptr(q, torch.float32, "q", 3 * J), _ptr(o, torch.float32, "o", J),
                                 J, _ptr(loss_out, torch.float64, "loss_out", 2), _stream(stream)))
+
+
+def efunc_fit_step_static(cfg: efunc_config, theta, m, v, step: int, q, o, loss_out=None,
+                          adam: Optional[efunc_adam] = None, stream=None):
+    """efunc_fit_step without a context: the workspace lives in the library's
+    fixed per-GPU scratch array (no device allocation)."""
+    J = q.numel() // 3
+    n = cfg.R ** 3 * efunc_channels(cfg)
+    _check(lib().efunc_fit_step_static(C.byref(cfg), _ptr(theta, torch.float32, "theta", n),
+                                       _ptr(m, torch.float32, "m", n), _ptr(v, torch.float32, "v", n),
+                                       step, C.byref(adam) if adam is not None else None,
+                                       _ptr(q, torch.float32, "q", 3 * J), _ptr(o, torch.float32, "o", J),
+                                       J, _ptr(loss_out, torch.float64, "loss_out", 2), _stream(stream)))
 
 
 def efunc_loss_grad(ctx, theta, q, o, grad, loss_out=None, stream=None, n_theta=None):
