@@ -11,8 +11,8 @@ constexpr int BLOCK = 256;      // threads per workgroup (4 wave64)
 constexpr int PMAX = 512;       // queries per tile (two per thread at most)
 constexpr int PMIN_CAP = 128;   // smallest tile query cap the workspace is sized for
 constexpr int KC = 256;         // keys per LDS chunk
-constexpr int MAXSEG = 1024;    // moved-key row segments per window ((2W+1)^2, W <= 15)
-constexpr int WMAX = 15;        // largest window half-width
+constexpr int MAXSEG = 1024;    // moved-key row segments per group (a window has (2W+2)^2 rows)
+constexpr int WMAX = 40;        // largest window half-width
 constexpr int SCAN_TILE = 1024; // elements per block in the prefix scans
 constexpr int PSPLIT = 8;       // sub-counters per cell in the query histogram
 constexpr int LBIN_MAX = 32768; // query sort keys one workgroup bins in LDS (128 KB of counters)

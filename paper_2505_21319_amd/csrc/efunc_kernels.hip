@@ -693,6 +693,7 @@ struct TileSmem {
         float fv[NF * KC];    // backward flush: NF channel values per kept key
     };
     int kid[KC];          // vertex index; -(vid + 1) for moved keys
+    int cand[2 * KC];     // tags of culled-in window keys awaiting a batch
     float4 pq[PMAX];      // query relative to the tile origin, aux (target or dL/dO)
     float4 pv[PMAX];      // O, lse2 (log2 units), g = dL/dO, reference exponent
     float2 red[PMAX];
@@ -834,16 +835,6 @@ __device__ void tile_bounds(float (&bl)[7], float* __restrict__ shbox)
     }
 }
 
-// Largest logit (log2 units, <= 0) any query inside the box can have against
-// a key centre: nb times the squared distance from the centre to the box.
-__device__ __forceinline__ float box_logit(const float (&bl)[7], float4 kc)
-{
-    const float dx = fmaxf(fmaxf(bl[0] - kc.x, kc.x - bl[3]), 0.0f);
-    const float dy = fmaxf(fmaxf(bl[1] - kc.y, kc.y - bl[4]), 0.0f);
-    const float dz = fmaxf(fmaxf(bl[2] - kc.z, kc.z - bl[5]), 0.0f);
-    return kc.w * fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-}
-
 // Forward sums over one staged chunk: keys k = ph, ph + Sf, ... against the
 // lane's query (Alg. 1 with the reference exponent M).
 template <int DEG>
@@ -913,513 +904,580 @@ __device__ __forceinline__ void flush_pairs(DevStats* st, const PairCount& c)
 // One tile: window, forward (Alg. 1), loss, backward (Alg. 2) and flush.
 // td is the tile descriptor, tile its index in a.tiles (loss partial slot);
 // W and bmin2 (smallest beta in log2 units) come from the shape's DevStats.
+//
+// Keys reach the pair loops in two steps.  The window's candidates are
+// visited in chunks of KC (grid vertices first, then the moved keys row
+// group by row group); each chunk is culled against the bounding box of the
+// tile's queries using key centres alone, and the survivors' tags are
+// appended to S.cand.  Once KC of them have gathered (or the window is
+// exhausted) the first KC are loaded in full into S.kc / S.kv / S.kid and
+// the pair loops run over that batch, so every batch but the last holds KC
+// kept keys whatever fraction of the window survives the cull.
 template <int MODE, bool QGRAD, int DEG>
 __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem<DEG>& S, const int4 td, const int tile,
                                          const int W, const float bmin2, PairCount& pc)
 {
     static_assert(KC == BLOCK, "one staged key per thread");
     constexpr int GW = gk_width(DEG), MW = mk_width(DEG);
+    constexpr float U3 = 3.0f / 16777216.0f;  // three float32 unit roundoffs
     const Layout& L = a.L;
     const int tid = threadIdx.x;
     const Geo& g = a.g;
     const int R = g.R, C1 = g.C1;
-    {
-        const int cell = td.x, p0 = td.y, P = td.z;
-        // the tile covers cells [c0, c1] per axis (one cell or a 2x2x2 block)
-        const int cx = cell / (C1 * C1), cy = (cell / C1) % C1, cz = cell % C1;
-        const int cx1 = cx + (td.w & 1), cy1 = cy + ((td.w >> 1) & 1), cz1 = cz + ((td.w >> 2) & 1);
+    const int cell = td.x, p0 = td.y, P = td.z;
+    // the tile covers cells [c0, c1] per axis (one cell or a 2x2x2 block)
+    const int cx = cell / (C1 * C1), cy = (cell / C1) % C1, cz = cell % C1;
+    const int cx1 = cx + (td.w & 1), cy1 = cy + ((td.w >> 1) & 1), cz1 = cz + ((td.w >> 2) & 1);
 
-        // ---- window: grid vertices and moved-key row segments
-        const int vx0 = max(cx - W + 1, 0), vx1 = min(cx1 + W, R - 1);
-        const int vy0 = max(cy - W + 1, 0), vy1 = min(cy1 + W, R - 1);
-        const int vz0 = max(cz - W + 1, 0), vz1 = min(cz1 + W, R - 1);
-        const int nvy = vy1 - vy0 + 1, nvz = vz1 - vz0 + 1;
-        const int Kg = L.grid ? (vx1 - vx0 + 1) * nvy * nvz : 0;
-        int Km = 0, nseg = 0;
-        if (a.offsets) {
-            const int mx0 = max(cx - W, 0), mx1 = min(cx1 + W, C1 - 1);
-            const int my0 = max(cy - W, 0), my1 = min(cy1 + W, C1 - 1);
-            const int mz0 = max(cz - W, 0), mz1 = min(cz1 + W, C1 - 1);
-            const int nmy = my1 - my0 + 1;
-            nseg = (mx1 - mx0 + 1) * nmy;
-            for (int base = 0; base < nseg; base += BLOCK) {
-                const int s = base + tid;
-                int len = 0;
-                if (s < nseg) {
-                    const int row = ((mx0 + s / nmy) * C1 + (my0 + s % nmy)) * C1;
-                    const int src = a.mstart[row + mz0];
-                    len = a.mstart[row + mz1 + 1] - src;
-                    S.seg_src[s] = src;
-                }
-                int total;
-                const int ex = block_excl_scan(len, S.isc, &total);
-                if (s < nseg) S.seg_off[s] = Km + ex;
-                Km += total;
-            }
-            if (tid == 0) S.seg_off[nseg] = Km;
+    // ---- window: grid vertices [c0 - W + 1, c1 + W] and moved-key cells
+    // [c0 - W, c1 + W] per axis, the latter as rows (x, y) of z-ranges
+    const int vx0 = max(cx - W + 1, 0), vx1 = min(cx1 + W, R - 1);
+    const int vy0 = max(cy - W + 1, 0), vy1 = min(cy1 + W, R - 1);
+    const int vz0 = max(cz - W + 1, 0), vz1 = min(cz1 + W, R - 1);
+    const int nvy = vy1 - vy0 + 1, nvz = vz1 - vz0 + 1;
+    const int Kg = L.grid ? (vx1 - vx0 + 1) * nvy * nvz : 0;
+    const int mx0 = max(cx - W, 0), mx1 = min(cx1 + W, C1 - 1);
+    const int my0 = max(cy - W, 0), my1 = min(cy1 + W, C1 - 1);
+    const int mz0 = max(cz - W, 0), mz1 = min(cz1 + W, C1 - 1);
+    const int nmy = my1 - my0 + 1;
+    const int nrow = a.offsets ? (mx1 - mx0 + 1) * nmy : 0;
+    const int ngroups = (nrow + MAXSEG - 1) / MAXSEG;
+    const int ngc = (Kg + KC - 1) / KC;
+    // Tile origin.  A float32 subtraction rounds the exact difference of
+    // two float32 coordinates once, so grid keys and queries are taken
+    // relative to it in float32; moved centres (hi + lo) use double.
+    const float oxf = g.tlat[cx], oyf = g.tlat[cy], ozf = g.tlat[cz];
+    const double ox = oxf, oy = oyf, oz = ozf;
+    // grid candidate index -> (x, y, z) offsets: float reciprocal quotients,
+    // exact after one correction step (indices < 2^24)
+    const int dyz = nvy * nvz;
+    const float rdyz = 1.0f / (float)dyz, rnz = 1.0f / (float)nvz;
+
+    // ---- queries into LDS, relative to the tile origin
+    for (int p = tid; p < P; p += BLOCK) {
+        const float4 v = a.ps[p0 + p];
+        S.pq[p] = make_float4(v.x - oxf, v.y - oyf, v.z - ozf, v.w);
+        if (MODE == MODE_GRAD) {
+            const float4 u = a.pv[p0 + p];
+            S.pv[p] = make_float4(u.x, u.y * LOG2E, v.w, 0.0f);
         }
-        const int K = Kg + Km;
-        // Tile origin.  A float32 subtraction rounds the exact difference of
-        // two float32 coordinates once, so grid keys and queries are taken
-        // relative to it in float32; moved centres (hi + lo) use double.
-        const float oxf = g.tlat[cx], oyf = g.tlat[cy], ozf = g.tlat[cz];
-        const double ox = oxf, oy = oyf, oz = ozf;
-        // floor(n / d) for the window index decode (n < 2^16, d <= 2048):
-        // multiply by m = floor((2^32 - 1) / d) + 1 and keep the high word
-        const int dyz = nvy * nvz;
-        const unsigned myz = dyz > 1 ? 0xFFFFFFFFu / (unsigned)dyz + 1u : 0u;
-        const unsigned mz = nvz > 1 ? 0xFFFFFFFFu / (unsigned)nvz + 1u : 0u;
+    }
 
-        // ---- queries into LDS, relative to the tile origin
-        for (int p = tid; p < P; p += BLOCK) {
-            const float4 v = a.ps[p0 + p];
-            S.pq[p] = make_float4(v.x - oxf, v.y - oyf, v.z - ozf, v.w);
-            if (MODE == MODE_GRAD) {
-                const float4 u = a.pv[p0 + p];
-                S.pv[p] = make_float4(u.x, u.y * LOG2E, v.w, 0.0f);
+    // ---- candidate gathering
+    int ncand = 0;              // tags in S.cand
+    int grp = -1, grpK = 0, grpN = 0;  // moved-row group whose segment table is built
+    struct Cursor {
+        int gc, gi, km;         // next grid chunk; moved-row group; next moved key in it
+    };
+    // Segment table of moved-row group gi: rows [gi MAXSEG, ...) of the window.
+    auto build_group = [&](int gi) {
+        const int r0 = gi * MAXSEG, nr = min(MAXSEG, nrow - r0);
+        int Km = 0;
+        for (int base = 0; base < nr; base += BLOCK) {
+            const int s = base + tid;
+            int len = 0;
+            if (s < nr) {
+                const int r = r0 + s;
+                const int row = ((mx0 + r / nmy) * C1 + (my0 + r % nmy)) * C1;
+                const int src = a.mstart[row + mz0];
+                len = a.mstart[row + mz1 + 1] - src;
+                S.seg_src[s] = src;
             }
+            int total;
+            const int ex = block_excl_scan(len, S.isc, &total);
+            if (s < nr) S.seg_off[s] = Km + ex;
+            Km += total;
         }
-
-        int nmoved = 0;  // moved keys among the last staged/reculled set
-        // Stage window keys [k0, k0 + nk) (nk <= BLOCK, one per thread) and keep
-        // those whose largest logit against the query box is >= cutoff: every
-        // dropped pair has weight below 2^(cutoff - lse2) <= e^-T.  Kept keys are
-        // compacted to LDS slots [0, n); moved keys carry the tag -(vid + 1).
-        auto stage_cull = [&](int k0, int nk, const float (&bl)[7], float cutoff) -> int {
-            float4 kc = make_float4(0, 0, 0, 0), kv = make_float4(0, 0, 0, 0);
-            float4 q0 = make_float4(0, 0, 0, 0), q1 = make_float4(0, 0, 0, 0);
-            int tag = 0;
-            bool keep = false;
-            if (tid < nk) {
-                const int kk = k0 + tid;
-                if (kk < Kg) {
-                    const int qx = dyz > 1 ? (int)__umulhi((unsigned)kk, myz) : kk;
-                    const int rr = kk - qx * dyz;
-                    const int qy = nvz > 1 ? (int)__umulhi((unsigned)rr, mz) : rr;
-                    const int ix = vx0 + qx, iy = vy0 + qy, iz = vz0 + (rr - qy * nvz);
-                    const int vid = (ix * R + iy) * R + iz;
-                    const float4 a0 = a.gk[GW * (int64_t)vid], a1 = a.gk[GW * (int64_t)vid + 1];
-                    kc = make_float4(g.tlat[ix] - oxf, g.tlat[iy] - oyf, g.tlat[iz] - ozf, a0.x);
-                    kv = make_float4(a0.y, a0.z, a0.w, a1.x);
-                    if (DEG == 2) {
-                        q0 = a.gk[GW * (int64_t)vid + 2];
-                        q1 = a.gk[GW * (int64_t)vid + 3];
-                    }
-                    tag = vid;
-                } else {
-                    const int km = kk - Kg;
-                    int lo = 0, hi = nseg - 1;
-                    while (lo < hi) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if (S.seg_off[mid] <= km) lo = mid; else hi = mid - 1;
-                    }
-                    const int64_t slot = (int64_t)S.seg_src[lo] + (km - S.seg_off[lo]);
-                    const float4 b0 = a.mk[MW * slot], b1 = a.mk[MW * slot + 1], b2 = a.mk[MW * slot + 2];
-                    if (DEG == 2) {
-                        q0 = a.mk[MW * slot + 3];
-                        q1 = a.mk[MW * slot + 4];
-                    }
-                    kc = make_float4((float)(((double)b0.x - ox) + (double)b2.x),
-                                     (float)(((double)b0.y - oy) + (double)b2.y),
-                                     (float)(((double)b0.z - oz) + (double)b2.z), b0.w);
-                    kv = b1;
-                    tag = -(__float_as_int(b2.w) + 1);
+        grp = gi;
+        grpK = Km;
+        grpN = nr;
+        __syncthreads();
+    };
+    // Cull candidates [k0, k0 + nk) of the grid part (grid) or of the built
+    // moved-row group: keep those whose largest logit against any point of
+    // the box reaches cutoff (every dropped pair weighs below
+    // 2^(cutoff - lse2) <= e^-T) and append their tags: packed vertex
+    // indices ix | iy << 9 | iz << 18 for grid keys, -(record + 1) for moved.
+    auto cull = [&](bool grid, int k0, int nk, const float (&bl)[7], float cutoff) {
+        int tag = 0;
+        bool keep = false;
+        if (tid < nk) {
+            const int kk = k0 + tid;
+            float4 kc;
+            float slack = 0.0f;
+            if (grid) {
+                int qx = (int)((float)kk * rdyz);
+                int rr = kk - qx * dyz;
+                qx += rr < 0 ? -1 : (rr >= dyz ? 1 : 0);
+                rr = kk - qx * dyz;
+                int qy = (int)((float)rr * rnz);
+                int rz = rr - qy * nvz;
+                qy += rz < 0 ? -1 : (rz >= nvz ? 1 : 0);
+                rz = rr - qy * nvz;
+                const int ix = vx0 + qx, iy = vy0 + qy, iz = vz0 + rz;
+                const int vid = (ix * R + iy) * R + iz;
+                const float nb = reinterpret_cast<const float*>(a.gk)[4 * GW * (int64_t)vid];
+                kc = make_float4(g.tlat[ix] - oxf, g.tlat[iy] - oyf, g.tlat[iz] - ozf, nb);
+                tag = ix | (iy << 9) | (iz << 18);
+            } else {
+                int lo = 0, hi = grpN - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (S.seg_off[mid] <= kk) lo = mid; else hi = mid - 1;
                 }
-                keep = box_logit(bl, kc) >= cutoff;
+                const int slot = S.seg_src[lo] + (kk - S.seg_off[lo]);
+                const float4 b0 = a.mk[MW * (int64_t)slot], b2 = a.mk[MW * (int64_t)slot + 2];
+                // float32 centre: within three roundoffs of the loaded one
+                kc = make_float4((b0.x - oxf) + b2.x, (b0.y - oyf) + b2.y, (b0.z - ozf) + b2.z, b0.w);
+                slack = U3;
+                tag = -(slot + 1);
             }
-            int tot;
-            const int pos = block_excl_scan(keep ? (tag < 0 ? 0x10001 : 1) : 0, S.isc, &tot) & 0xffff;
-            if (keep) {
-                S.kc[pos] = kc;
-                S.kv[pos] = kv;
-                if (DEG == 2) {
-                    S.kqa[pos] = q0;
-                    S.kqb[pos] = make_float2(q1.x, q1.y);
-                }
-                S.kid[pos] = tag;
-            }
-            __syncthreads();
-            nmoved = tot >> 16;
-            return tot & 0xffff;
-        };
-        // Re-apply the test to the n staged keys in place.
-        auto recull = [&](int n0, const float (&bl)[7], float cutoff) -> int {
-            float4 kc = make_float4(0, 0, 0, 0), kv = make_float4(0, 0, 0, 0);
-            float4 q0 = make_float4(0, 0, 0, 0);
-            float2 q1 = make_float2(0, 0);
-            int tag = 0;
-            bool keep = false;
-            if (tid < n0) {
-                kc = S.kc[tid];
-                kv = S.kv[tid];
-                if (DEG == 2) {
-                    q0 = S.kqa[tid];
-                    q1 = S.kqb[tid];
-                }
-                tag = S.kid[tid];
-                keep = box_logit(bl, kc) >= cutoff;
-            }
-            int tot;  // the scan synchronises before any slot is overwritten
-            const int pos = block_excl_scan(keep ? (tag < 0 ? 0x10001 : 1) : 0, S.isc, &tot) & 0xffff;
-            if (keep) {
-                S.kc[pos] = kc;
-                S.kv[pos] = kv;
-                if (DEG == 2) {
-                    S.kqa[pos] = q0;
-                    S.kqb[pos] = q1;
-                }
-                S.kid[pos] = tag;
-            }
-            __syncthreads();
-            nmoved = tot >> 16;
-            return tot & 0xffff;
-        };
-
-        const int nchunks = (K + KC - 1) / KC;
-        int staged = -1;  // chunk currently in LDS
-        int nstaged = 0, nstaged_moved = 0;  // its kept keys
-        unsigned long long fwd_pairs = 0ull, fwd_moved = 0ull;
-
-        if (MODE != MODE_GRAD) {
-            __syncthreads();
-            // ---- reference exponent: largest corner logit of the home cell
-            int need_exact = 0;
-            float bl[7] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, INFINITY};
-            for (int p = tid; p < P; p += BLOCK) {
-                const float4 pq = S.pq[p];
-                const float4 qa = a.ps[p0 + p];  // absolute position: the binning's home cell
-                const int hx = cell_of(qa.x, g), hy = cell_of(qa.y, g), hz = cell_of(qa.z, g);
-                float M0 = -INFINITY;  // without grid keys: the exact pass below
+            const float dx = fmaxf(fmaxf(bl[0] - kc.x, kc.x - bl[3]) - slack * fabsf(kc.x), 0.0f);
+            const float dy = fmaxf(fmaxf(bl[1] - kc.y, kc.y - bl[4]) - slack * fabsf(kc.y), 0.0f);
+            const float dz = fmaxf(fmaxf(bl[2] - kc.z, kc.z - bl[5]) - slack * fabsf(kc.z), 0.0f);
+            keep = kc.w * fmaf(dx, dx, fmaf(dy, dy, dz * dz)) >= cutoff;
+        }
+        // position among the kept: wave ballot, then the waves before
+        const unsigned long long bal = __ballot(keep);
+        const int lane = tid & 63, wv = tid >> 6;
+        __syncthreads();
+        if (lane == 0) S.isc[wv] = __popcll(bal);
+        __syncthreads();
+        int before = 0, tot = 0;
 #pragma unroll
-                for (int c8 = 0; c8 < 8; ++c8) {
-                    if (!L.grid) break;
-                    const int ix = hx + (c8 >> 2), iy = hy + ((c8 >> 1) & 1), iz = hz + (c8 & 1);
-                    const int vid = (ix * R + iy) * R + iz;
-                    const float nb = a.gk[GW * (int64_t)vid].x;
-                    const float dx = pq.x - (g.tlat[ix] - oxf);
-                    const float dy = pq.y - (g.tlat[iy] - oyf);
-                    const float dz = pq.z - (g.tlat[iz] - ozf);
-                    M0 = fmaxf(M0, nb * fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
-                }
-                S.pv[p] = make_float4(0.0f, 0.0f, 0.0f, M0);
-                // exp2(s - M0) <= 2^-M0 per key; keep the sum of K such terms finite
-                if (!(-M0 + log2f((float)K + 1.0f) < 120.0f)) need_exact = 1;
-                bl[0] = fminf(bl[0], pq.x); bl[1] = fminf(bl[1], pq.y); bl[2] = fminf(bl[2], pq.z);
-                bl[3] = fmaxf(bl[3], pq.x); bl[4] = fmaxf(bl[4], pq.y); bl[5] = fmaxf(bl[5], pq.z);
-                bl[6] = fminf(bl[6], M0);
+        for (int i = 0; i < BLOCK / 64; ++i) {
+            const int c = S.isc[i];
+            before += i < wv ? c : 0;
+            tot += c;
+        }
+        if (keep) S.cand[ncand + before + __popcll(bal & ((1ull << lane) - 1ull))] = tag;
+        ncand += tot;
+    };
+    // Cull chunks until KC tags have gathered or the window is exhausted.
+    auto gather = [&](Cursor& cu, const float (&bl)[7], float cutoff) {
+        while (ncand < KC) {
+            if (cu.gc < ngc) {
+                const int k0 = cu.gc * KC;
+                cull(true, k0, min(KC, Kg - k0), bl, cutoff);
+                ++cu.gc;
+                continue;
             }
-            const int exact = __syncthreads_or(need_exact);
-            tile_bounds(bl, &S.box[0][0]);
-            // M0 <= lse2 for every query, so this drops only pairs below e^-T
-            float fcut = bl[6] - a.T2;
-
-            // Query-to-lane mapping in two rounds: queries [0, P1) with Sf lanes each
-            // and queries [BLOCK, P) (at most BLOCK - 1 of them) with Sf2 lanes
-            // each; the partial sums of query p live in slots slot(p, 0..n-1).
-            const int P1 = min(P, BLOCK), P2 = P - P1;
-            const int Sf = max(1, BLOCK / P1);
-            const int Sf2 = P2 > 0 ? max(1, BLOCK / P2) : 1;
-            const int pme = tid / Sf, ph = tid - pme * Sf;
-            const int pme2 = tid / Sf2, ph2 = tid - pme2 * Sf2;
-            const bool act = pme < P1;
-            const bool act2 = pme2 < P2;
-            auto slot0 = [&](int p) { return p < BLOCK ? p * Sf : BLOCK + (p - BLOCK) * Sf2; };
-            auto nslot = [&](int p) { return p < BLOCK ? Sf : Sf2; };
-            const float4 q = S.pq[act ? pme : 0];
-            const float4 q2 = S.pq[act2 ? BLOCK + pme2 : 0];
-
-            if (exact) {
-                // exact maximum over the window first (very coarse lattices, or
-                // no grid keys to take the reference from)
-                float M = -INFINITY, M2 = -INFINITY;
-                for (int c = 0; c < nchunks; ++c) {
-                    const int k0 = c * KC, nk = min(KC, K - k0);
-                    __syncthreads();
-                    nstaged = stage_cull(k0, nk, bl, fcut);
-                    nstaged_moved = nmoved;
-                    staged = c;
-                    if (act) fwd_max<DEG>(S, nstaged, ph, Sf, q, M);
-                    if (act2) fwd_max<DEG>(S, nstaged, ph2, Sf2, q2, M2);
-                }
-                S.red[tid].x = M;
-                S.red[BLOCK + tid].x = M2;
-                __syncthreads();
-                float mn = INFINITY;
-                for (int p = tid; p < P; p += BLOCK) {
-                    float mx = S.pv[p].w;
-                    for (int s = 0; s < nslot(p); ++s) mx = fmaxf(mx, S.red[slot0(p) + s].x);
-                    S.pv[p].w = mx;
-                    mn = fminf(mn, mx);
-                }
-                // the exact maxima are tighter lower bounds of lse2
-                fcut = -block_max(-mn, S.fsc) - a.T2;
+            if (cu.gi >= ngroups) break;
+            if (grp != cu.gi) build_group(cu.gi);
+            if (cu.km < grpK) {
+                cull(false, cu.km, min(KC, grpK - cu.km), bl, cutoff);
+                cu.km += KC;
             }
-
-            // ---- forward: e = sum 2^(s - M), m = sum 2^(s - M) f   (Alg. 1)
-            float e = 0.0f, m = 0.0f, e2 = 0.0f, m2 = 0.0f;
-            __syncthreads();
-            const float Mr = S.pv[act ? pme : 0].w;
-            const float Mr2 = S.pv[act2 ? BLOCK + pme2 : 0].w;
-            for (int c = 0; c < nchunks; ++c) {
-                const int k0 = c * KC, nk = min(KC, K - k0);
-                if (staged != c) {
-                    __syncthreads();
-                    nstaged = stage_cull(k0, nk, bl, fcut);
-                    nstaged_moved = nmoved;
-                    staged = c;
-                }
-                fwd_pairs += (unsigned long long)nstaged * P;
-                fwd_moved += (unsigned long long)nstaged_moved * P;
-                if (act) fwd_sums<DEG>(S, nstaged, ph, Sf, q, Mr, e, m);
-                if (act2) fwd_sums<DEG>(S, nstaged, ph2, Sf2, q2, Mr2, e2, m2);
+            if (cu.km >= grpK) {
+                ++cu.gi;
+                cu.km = 0;
             }
-            __syncthreads();
-            S.red[tid] = make_float2(e, m);
-            S.red[BLOCK + tid] = make_float2(e2, m2);
-            __syncthreads();
+        }
+    };
+    // Load the first min(ncand, KC) gathered keys in full into slots
+    // [0, n) and keep the rest of the tags for the next batch; returns n and
+    // the number of moved keys among them.
+    auto load_batch = [&](int& nmoved) -> int {
+        const int n = min(ncand, KC), rem = ncand - n;
+        __syncthreads();  // tags complete; the previous batch is no longer read
+        const int t0 = tid < n ? S.cand[tid] : 0;
+        const int t1 = tid < rem ? S.cand[n + tid] : 0;
+        __syncthreads();
+        if (tid < rem) S.cand[tid] = t1;
+        ncand = rem;
+        if (tid < n) {
+            float4 kc, kv, q0 = make_float4(0, 0, 0, 0), q1 = make_float4(0, 0, 0, 0);
+            int kid;
+            if (t0 >= 0) {
+                const int ix = t0 & 511, iy = (t0 >> 9) & 511, iz = t0 >> 18;
+                const int vid = (ix * R + iy) * R + iz;
+                const float4 a0 = a.gk[GW * (int64_t)vid], a1 = a.gk[GW * (int64_t)vid + 1];
+                if (DEG == 2) {
+                    q0 = a.gk[GW * (int64_t)vid + 2];
+                    q1 = a.gk[GW * (int64_t)vid + 3];
+                }
+                kc = make_float4(g.tlat[ix] - oxf, g.tlat[iy] - oyf, g.tlat[iz] - ozf, a0.x);
+                kv = make_float4(a0.y, a0.z, a0.w, a1.x);
+                kid = vid;
+            } else {
+                const int64_t slot = -(int64_t)t0 - 1;
+                const float4 b0 = a.mk[MW * slot], b1 = a.mk[MW * slot + 1], b2 = a.mk[MW * slot + 2];
+                if (DEG == 2) {
+                    q0 = a.mk[MW * slot + 3];
+                    q1 = a.mk[MW * slot + 4];
+                }
+                kc = make_float4((float)(((double)b0.x - ox) + (double)b2.x),
+                                 (float)(((double)b0.y - oy) + (double)b2.y),
+                                 (float)(((double)b0.z - oz) + (double)b2.z), b0.w);
+                kv = b1;
+                kid = -(__float_as_int(b2.w) + 1);
+            }
+            S.kc[tid] = kc;
+            S.kv[tid] = kv;
+            if (DEG == 2) {
+                S.kqa[tid] = q0;
+                S.kqb[tid] = make_float2(q1.x, q1.y);
+            }
+            S.kid[tid] = kid;
+        }
+        nmoved = __syncthreads_count(tid < n && t0 < 0);
+        return n;
+    };
 
-            // ---- per query: O, lse, certificate, loss and dL/dO
-            // faces of the window box beyond which keys are excluded
-            const float flx = (cx - W + 1 > 0) ? g.tlat[cx - W] - oxf : -INFINITY;
-            const float fly = (cy - W + 1 > 0) ? g.tlat[cy - W] - oyf : -INFINITY;
-            const float flz = (cz - W + 1 > 0) ? g.tlat[cz - W] - ozf : -INFINITY;
-            const float fhx = (cx1 + W < R - 1) ? g.tlat[cx1 + W + 1] - oxf : INFINITY;
-            const float fhy = (cy1 + W < R - 1) ? g.tlat[cy1 + W + 1] - oyf : INFINITY;
-            const float fhz = (cz1 + W < R - 1) ? g.tlat[cz1 + W + 1] - ozf : INFINITY;
-            double lsq = 0.0, lab = 0.0;
+    // moved keys in the window (all row groups); group 0's table stays built
+    // for the first pass
+    int Kmt = 0;
+    if (ngroups > 0) {
+        build_group(0);
+        Kmt = grpK;
+        if (ngroups > 1) {
+            int part = 0;
+            for (int r = MAXSEG + tid; r < nrow; r += BLOCK) {
+                const int row = ((mx0 + r / nmy) * C1 + (my0 + r % nmy)) * C1;
+                part += a.mstart[row + mz1 + 1] - a.mstart[row + mz0];
+            }
+            Kmt += block_sum(part, S.isc);
+        }
+    }
+
+    unsigned long long fwd_pairs = 0ull, fwd_moved = 0ull;
+
+    if (MODE != MODE_GRAD) {
+        __syncthreads();
+        // ---- reference exponent: largest corner logit of the home cell
+        int need_exact = 0;
+        float bl[7] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, INFINITY};
+        for (int p = tid; p < P; p += BLOCK) {
+            const float4 pq = S.pq[p];
+            const float4 qa = a.ps[p0 + p];  // absolute position: the binning's home cell
+            const int hx = cell_of(qa.x, g), hy = cell_of(qa.y, g), hz = cell_of(qa.z, g);
+            float M0 = -INFINITY;  // without grid keys: the exact pass below
+#pragma unroll
+            for (int c8 = 0; c8 < 8; ++c8) {
+                if (!L.grid) break;
+                const int ix = hx + (c8 >> 2), iy = hy + ((c8 >> 1) & 1), iz = hz + (c8 & 1);
+                const int vid = (ix * R + iy) * R + iz;
+                const float nb = a.gk[GW * (int64_t)vid].x;
+                const float dx = pq.x - (g.tlat[ix] - oxf);
+                const float dy = pq.y - (g.tlat[iy] - oyf);
+                const float dz = pq.z - (g.tlat[iz] - ozf);
+                M0 = fmaxf(M0, nb * fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+            }
+            S.pv[p] = make_float4(0.0f, 0.0f, 0.0f, M0);
+            // exp2(s - M0) <= 2^-M0 per key; keep the sum of K such terms finite
+            if (!(-M0 + log2f((float)Kg + (float)Kmt + 1.0f) < 120.0f)) need_exact = 1;
+            bl[0] = fminf(bl[0], pq.x); bl[1] = fminf(bl[1], pq.y); bl[2] = fminf(bl[2], pq.z);
+            bl[3] = fmaxf(bl[3], pq.x); bl[4] = fmaxf(bl[4], pq.y); bl[5] = fmaxf(bl[5], pq.z);
+            bl[6] = fminf(bl[6], M0);
+        }
+        const int exact = __syncthreads_or(need_exact);
+        tile_bounds(bl, &S.box[0][0]);
+        // M0 <= lse2 for every query, so this drops only pairs below e^-T
+        float fcut = bl[6] - a.T2;
+
+        // Query-to-lane mapping in two rounds: queries [0, P1) with Sf lanes each
+        // and queries [BLOCK, P) (at most BLOCK - 1 of them) with Sf2 lanes
+        // each; the partial sums of query p live in slots slot(p, 0..n-1).
+        const int P1 = min(P, BLOCK), P2 = P - P1;
+        const int Sf = max(1, BLOCK / P1);
+        const int Sf2 = P2 > 0 ? max(1, BLOCK / P2) : 1;
+        const int pme = tid / Sf, ph = tid - pme * Sf;
+        const int pme2 = tid / Sf2, ph2 = tid - pme2 * Sf2;
+        const bool act = pme < P1;
+        const bool act2 = pme2 < P2;
+        auto slot0 = [&](int p) { return p < BLOCK ? p * Sf : BLOCK + (p - BLOCK) * Sf2; };
+        auto nslot = [&](int p) { return p < BLOCK ? Sf : Sf2; };
+        const float4 q = S.pq[act ? pme : 0];
+        const float4 q2 = S.pq[act2 ? BLOCK + pme2 : 0];
+
+        if (exact) {
+            // exact maximum over the window first (very coarse lattices, or
+            // no grid keys to take the reference from)
+            float M = -INFINITY, M2 = -INFINITY;
+            Cursor cu = {0, 0, 0};
+            ncand = 0;
+            for (;;) {
+                gather(cu, bl, fcut);
+                if (ncand == 0) break;
+                int nm;
+                const int n = load_batch(nm);
+                if (act) fwd_max<DEG>(S, n, ph, Sf, q, M);
+                if (act2) fwd_max<DEG>(S, n, ph2, Sf2, q2, M2);
+            }
+            S.red[tid].x = M;
+            S.red[BLOCK + tid].x = M2;
+            __syncthreads();
+            float mn = INFINITY;
             for (int p = tid; p < P; p += BLOCK) {
-                float ee = 0.0f, mm = 0.0f;
-                for (int s = 0; s < nslot(p); ++s) {
-                    const float2 r = S.red[slot0(p) + s];
-                    ee += r.x;
-                    mm += r.y;
-                }
-                const float4 pq = S.pq[p];
-                const float M = S.pv[p].w;
-                const float O = mm / ee;
-                const float lse2 = M + log2f(ee);
-                float D = fminf(fminf(pq.x - flx, fhx - pq.x),
-                                fminf(fminf(pq.y - fly, fhy - pq.y), fminf(pq.z - flz, fhz - pq.z)));
-                D = fmaxf(D * (1.0f - 1e-5f) - 1e-6f * g.h, 0.0f);
-                const bool cert = (bmin2 * D * D >= a.T2 - lse2) && (ee > 0.0f);
-                if (!cert) {
-                    const int slot = atomicAdd(&a.st->nfb, 1);
-                    a.fb[slot] = p0 + p;
-                }
-                if (MODE == MODE_FIT) {
-                    const float res = O - pq.w;
-                    float gj = 0.0f;
-                    if (cert) {
-                        gj = res * a.two_over_J;
-                        lsq += (double)res * (double)res;
-                        lab += fabs((double)res);
-                    }
-                    S.pv[p] = make_float4(O, lse2, gj, M);
-                } else {  // EVAL
-                    if (cert) {
-                        const int j = a.pidx[p0 + p];
-                        a.O_out[j] = O;
-                        if (a.lse_out) a.lse_out[j] = lse2 * LN2;
-                    }
-                    S.pv[p] = make_float4(O, lse2, cert ? 1.0f : 0.0f, M);
-                }
+                float mx = S.pv[p].w;
+                for (int s = 0; s < nslot(p); ++s) mx = fmaxf(mx, S.red[slot0(p) + s].x);
+                S.pv[p].w = mx;
+                mn = fminf(mn, mx);
+            }
+            // the exact maxima are tighter lower bounds of lse2
+            fcut = -block_max(-mn, S.fsc) - a.T2;
+        }
+
+        // ---- forward: e = sum 2^(s - M), m = sum 2^(s - M) f   (Alg. 1)
+        float e = 0.0f, m = 0.0f, e2 = 0.0f, m2 = 0.0f;
+        __syncthreads();
+        const float Mr = S.pv[act ? pme : 0].w;
+        const float Mr2 = S.pv[act2 ? BLOCK + pme2 : 0].w;
+        {
+            Cursor cu = {0, 0, 0};
+            ncand = 0;
+            for (;;) {
+                gather(cu, bl, fcut);
+                if (ncand == 0) break;
+                int nm;
+                const int n = load_batch(nm);
+                fwd_pairs += (unsigned long long)n * P;
+                fwd_moved += (unsigned long long)nm * P;
+                if (act) fwd_sums<DEG>(S, n, ph, Sf, q, Mr, e, m);
+                if (act2) fwd_sums<DEG>(S, n, ph2, Sf2, q2, Mr2, e2, m2);
+            }
+        }
+        __syncthreads();
+        S.red[tid] = make_float2(e, m);
+        S.red[BLOCK + tid] = make_float2(e2, m2);
+        __syncthreads();
+
+        // ---- per query: O, lse, certificate, loss and dL/dO
+        // faces of the window box beyond which keys are excluded
+        const float flx = (cx - W + 1 > 0) ? g.tlat[cx - W] - oxf : -INFINITY;
+        const float fly = (cy - W + 1 > 0) ? g.tlat[cy - W] - oyf : -INFINITY;
+        const float flz = (cz - W + 1 > 0) ? g.tlat[cz - W] - ozf : -INFINITY;
+        const float fhx = (cx1 + W < R - 1) ? g.tlat[cx1 + W + 1] - oxf : INFINITY;
+        const float fhy = (cy1 + W < R - 1) ? g.tlat[cy1 + W + 1] - oyf : INFINITY;
+        const float fhz = (cz1 + W < R - 1) ? g.tlat[cz1 + W + 1] - ozf : INFINITY;
+        double lsq = 0.0, lab = 0.0;
+        for (int p = tid; p < P; p += BLOCK) {
+            float ee = 0.0f, mm = 0.0f;
+            for (int s = 0; s < nslot(p); ++s) {
+                const float2 r = S.red[slot0(p) + s];
+                ee += r.x;
+                mm += r.y;
+            }
+            const float4 pq = S.pq[p];
+            const float M = S.pv[p].w;
+            const float O = mm / ee;
+            const float lse2 = M + log2f(ee);
+            float D = fminf(fminf(pq.x - flx, fhx - pq.x),
+                            fminf(fminf(pq.y - fly, fhy - pq.y), fminf(pq.z - flz, fhz - pq.z)));
+            D = fmaxf(D * (1.0f - 1e-5f) - 1e-6f * g.h, 0.0f);
+            const bool cert = (bmin2 * D * D >= a.T2 - lse2) && (ee > 0.0f);
+            if (!cert) {
+                const int slot = atomicAdd(&a.st->nfb, 1);
+                a.fb[slot] = p0 + p;
             }
             if (MODE == MODE_FIT) {
-                lsq = block_sum(lsq, S.dsc);
-                lab = block_sum(lab, S.dsc);
-                if (tid == 0) a.lpart[tile] = make_double2(lsq, lab);
-            }
-            __syncthreads();
-
-            if (MODE == MODE_EVAL && QGRAD) {
-                const float O1 = S.pv[act ? pme : 0].x, L1 = S.pv[act ? pme : 0].y;
-                const float O2 = S.pv[act2 ? BLOCK + pme2 : 0].x, L2 = S.pv[act2 ? BLOCK + pme2 : 0].y;
-                float gx = 0, gy = 0, gz = 0, hx = 0, hy = 0, hz = 0;
-                for (int c = nchunks - 1; c >= 0; --c) {
-                    const int k0 = c * KC, nk = min(KC, K - k0);
-                    if (staged != c) {
-                        __syncthreads();
-                        nstaged = stage_cull(k0, nk, bl, fcut);
-                        staged = c;
-                    }
-                    if (act) fwd_qgrad<DEG>(S, nstaged, ph, Sf, q, O1, L1, gx, gy, gz);
-                    if (act2) fwd_qgrad<DEG>(S, nstaged, ph2, Sf2, q2, O2, L2, hx, hy, hz);
+                const float res = O - pq.w;
+                float gj = 0.0f;
+                if (cert) {
+                    gj = res * a.two_over_J;
+                    lsq += (double)res * (double)res;
+                    lab += fabs((double)res);
                 }
-                __syncthreads();
-                float* zf = S.fv;  // keys no longer needed
-                S.red[tid] = make_float2(gx, gy);
-                zf[tid] = gz;
-                S.red[BLOCK + tid] = make_float2(hx, hy);
-                zf[BLOCK + tid] = hz;
-                staged = -1;
-                __syncthreads();
-                for (int p = tid; p < P; p += BLOCK) {
-                    if (S.pv[p].z == 0.0f) continue;  // uncertified: fallback writes it
-                    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
-                    for (int s = 0; s < nslot(p); ++s) {
-                        sx += S.red[slot0(p) + s].x;
-                        sy += S.red[slot0(p) + s].y;
-                        sz += zf[slot0(p) + s];
-                    }
+                S.pv[p] = make_float4(O, lse2, gj, M);
+            } else {  // EVAL
+                if (cert) {
                     const int j = a.pidx[p0 + p];
-                    a.dOdq_out[3 * (int64_t)j] = sx;
-                    a.dOdq_out[3 * (int64_t)j + 1] = sy;
-                    a.dOdq_out[3 * (int64_t)j + 2] = sz;
+                    a.O_out[j] = O;
+                    if (a.lse_out) a.lse_out[j] = lse2 * LN2;
                 }
-            }
-        } else {
-            // ---- backward only: certificate from the given lse
-            __syncthreads();
-            const float flx = (cx - W + 1 > 0) ? g.tlat[cx - W] - oxf : -INFINITY;
-            const float fly = (cy - W + 1 > 0) ? g.tlat[cy - W] - oyf : -INFINITY;
-            const float flz = (cz - W + 1 > 0) ? g.tlat[cz - W] - ozf : -INFINITY;
-            const float fhx = (cx1 + W < R - 1) ? g.tlat[cx1 + W + 1] - oxf : INFINITY;
-            const float fhy = (cy1 + W < R - 1) ? g.tlat[cy1 + W + 1] - oyf : INFINITY;
-            const float fhz = (cz1 + W < R - 1) ? g.tlat[cz1 + W + 1] - ozf : INFINITY;
-            for (int p = tid; p < P; p += BLOCK) {
-                const float4 pq = S.pq[p];
-                float4 pv = S.pv[p];
-                float D = fminf(fminf(pq.x - flx, fhx - pq.x),
-                                fminf(fminf(pq.y - fly, fhy - pq.y), fminf(pq.z - flz, fhz - pq.z)));
-                D = fmaxf(D * (1.0f - 1e-5f) - 1e-6f * g.h, 0.0f);
-                const bool cert = bmin2 * D * D >= a.T2 - pv.y;
-                if (!cert) {
-                    const int slot = atomicAdd(&a.st->nfb, 1);
-                    a.fb[slot] = p0 + p;
-                    pv.z = 0.0f;
-                    S.pv[p] = pv;
-                }
+                S.pv[p] = make_float4(O, lse2, cert ? 1.0f : 0.0f, M);
             }
         }
+        if (MODE == MODE_FIT) {
+            lsq = block_sum(lsq, S.dsc);
+            lab = block_sum(lab, S.dsc);
+            if (tid == 0) a.lpart[tile] = make_double2(lsq, lab);
+        }
+        __syncthreads();
 
-        unsigned long long bwd_pairs = 0ull, bwd_moved = 0ull;
-        if (MODE != MODE_EVAL) {
-            // ---- backward, key-parallel over the tile's queries (Alg. 2)
-            // Box and smallest lse2 of the queries that carry a gradient; keys
-            // whose every pair with them weighs below e^-T are skipped.
-            float bl[7] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, INFINITY};
+        if (MODE == MODE_EVAL && QGRAD) {
+            const float O1 = S.pv[act ? pme : 0].x, L1 = S.pv[act ? pme : 0].y;
+            const float O2 = S.pv[act2 ? BLOCK + pme2 : 0].x, L2 = S.pv[act2 ? BLOCK + pme2 : 0].y;
+            float gx = 0, gy = 0, gz = 0, hx = 0, hy = 0, hz = 0;
+            Cursor cu = {0, 0, 0};
+            ncand = 0;
+            for (;;) {
+                gather(cu, bl, fcut);
+                if (ncand == 0) break;
+                int nm;
+                const int n = load_batch(nm);
+                if (act) fwd_qgrad<DEG>(S, n, ph, Sf, q, O1, L1, gx, gy, gz);
+                if (act2) fwd_qgrad<DEG>(S, n, ph2, Sf2, q2, O2, L2, hx, hy, hz);
+            }
+            __syncthreads();
+            float* zf = S.fv;  // keys no longer needed
+            S.red[tid] = make_float2(gx, gy);
+            zf[tid] = gz;
+            S.red[BLOCK + tid] = make_float2(hx, hy);
+            zf[BLOCK + tid] = hz;
             __syncthreads();
             for (int p = tid; p < P; p += BLOCK) {
-                const float4 pv = S.pv[p];
-                if (pv.z == 0.0f) continue;
-                const float4 pq = S.pq[p];
-                bl[0] = fminf(bl[0], pq.x); bl[1] = fminf(bl[1], pq.y); bl[2] = fminf(bl[2], pq.z);
-                bl[3] = fmaxf(bl[3], pq.x); bl[4] = fmaxf(bl[4], pq.y); bl[5] = fmaxf(bl[5], pq.z);
-                bl[6] = fminf(bl[6], pv.y);
-            }
-            tile_bounds(bl, &S.box[0][0]);
-            const float bcut = bl[6] - a.T2;
-
-            for (int c = nchunks - 1; c >= 0; --c) {
-                const int k0 = c * KC, nk = min(KC, K - k0);
-                int n;
-                __syncthreads();
-                if (staged == c) {
-                    n = recull(nstaged, bl, bcut);
-                } else {
-                    n = stage_cull(k0, nk, bl, bcut);
+                if (S.pv[p].z == 0.0f) continue;  // uncertified: fallback writes it
+                float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+                for (int s = 0; s < nslot(p); ++s) {
+                    sx += S.red[slot0(p) + s].x;
+                    sy += S.red[slot0(p) + s].y;
+                    sz += zf[slot0(p) + s];
                 }
-                staged = -1;  // the flush below overwrites the staged keys
-                bwd_pairs += (unsigned long long)n * P;
-                bwd_moved += (unsigned long long)nmoved * P;
-                if (n == 0) continue;
-                int Sb = 1;
-                while (Sb < 64 && Sb * 2 * n <= BLOCK) Sb *= 2;
-                const int kk = tid / Sb, ph = tid - kk * Sb;
-                const bool act = kk < n;
-                constexpr int NA = NAcc<DEG>::n;
-                constexpr int NF = TileSmem<DEG>::NF;
-                constexpr int NV = DEG == 0 ? 1 : (DEG == 1 ? 4 : 10);
-                float acc[NA];
-#pragma unroll
-                for (int t = 0; t < NA; ++t) acc[t] = 0.0f;
-                float4 kc = make_float4(0, 0, 0, 0), kv = make_float4(0, 0, 0, 0);
-                KeyQ<DEG> kq;
-                int tag = 0;
-                if (act) {
-                    kc = S.kc[kk];
-                    kv = S.kv[kk];
-                    kq = load_q(S, kk);
-                    tag = S.kid[kk];
-                }
-                const bool moved = act && tag < 0;
-                if (__any(moved)) {
-                    if (act) bwd_key<true, DEG>(S, P, ph, Sb, kc, kv, kq, acc);
-                } else {
-                    if (act) bwd_key<false, DEG>(S, P, ph, Sb, kc, kv, kq, acc);
-                }
-                for (int off = 1; off < Sb; off <<= 1) {
-#pragma unroll
-                    for (int t = 0; t < NA; ++t) acc[t] += __shfl_xor(acc[t], off, 64);
-                }
-                // Final channel values (Sec. 3.6).  Grid key: values (nv), rho.
-                // Moved key: Delta = centre gradient, values (nv), rho'.
-                // dL/dv = sum delta * monomial; dL/drho = beta dL/dbeta =
-                // -beta sum u |x|^2; dL/dc = -sum delta grad_x f + 2 beta sum u x
-                // with sum delta grad_x f = d sum delta + S sum delta x.
-                const float beta = -kc.w * LN2;
-                float val[NF];
-#pragma unroll
-                for (int t = 0; t < NF; ++t) val[t] = 0.0f;
-                const int vo = moved ? 3 : 0;
-                val[vo] = acc[0];
-                if (DEG >= 1) {
-                    val[vo + 1] = acc[1];
-                    val[vo + 2] = acc[2];
-                    val[vo + 3] = acc[3];
-                }
-                if (DEG == 2) {
-#pragma unroll
-                    for (int t = 0; t < 6; ++t) val[vo + 4 + t] = acc[8 + t];
-                }
-                val[vo + NV] = -beta * acc[4];
-                if (moved) {
-                    float gx = 2.0f * beta * acc[5], gy = 2.0f * beta * acc[6], gz = 2.0f * beta * acc[7];
-                    if constexpr (DEG >= 1) {
-                        gx = fmaf(-kv.y, acc[0], gx);
-                        gy = fmaf(-kv.z, acc[0], gy);
-                        gz = fmaf(-kv.w, acc[0], gz);
-                    }
-                    if constexpr (DEG == 2) {  // - S sum(delta x)
-                        gx -= fmaf(2.0f * kq.a.x, acc[1], fmaf(kq.a.w, acc[2], kq.b.x * acc[3]));
-                        gy -= fmaf(kq.a.w, acc[1], fmaf(2.0f * kq.a.y, acc[2], kq.b.y * acc[3]));
-                        gz -= fmaf(kq.b.x, acc[1], fmaf(kq.b.y, acc[2], 2.0f * kq.a.z * acc[3]));
-                    }
-                    val[0] = gx;
-                    val[1] = gy;
-                    val[2] = gz;
-                }
-                __syncthreads();  // staged keys no longer needed: reuse their LDS
-                if (act && ph == 0) {
-#pragma unroll
-                    for (int t = 0; t < NF; ++t) S.fv[kk * NF + t] = val[t];
-                }
-                __syncthreads();
-                // one atomic per key channel, NF consecutive lanes per key
-                for (int t = tid; t < n * NF; t += BLOCK) {
-                    const int kq2 = t / NF, sl = t - kq2 * NF;
-                    const int tg = S.kid[kq2];
-                    const bool mv = tg < 0;
-                    const float x = S.fv[t];
-                    int c = -1;
-                    if (!mv) {
-                        c = sl < NV ? L.gval + sl : (sl == NV ? L.grho : -1);
-                    } else {
-                        c = sl < 3 ? L.mdel + sl
-                                   : (sl < 3 + NV ? L.mval + (sl - 3) : (sl == 3 + NV ? L.mrho : -1));
-                    }
-                    if (c >= 0 && x != 0.0f) {
-                        const int64_t v = mv ? (int64_t)(-tg - 1) : (int64_t)tg;
-                        unsafeAtomicAdd(a.grad + v * L.nch + c, x);
-                    }
-                }
+                const int j = a.pidx[p0 + p];
+                a.dOdq_out[3 * (int64_t)j] = sx;
+                a.dOdq_out[3 * (int64_t)j + 1] = sy;
+                a.dOdq_out[3 * (int64_t)j + 2] = sz;
             }
         }
-        pc.fwd += fwd_pairs;
-        pc.fwd_moved += fwd_moved;
-        pc.bwd += bwd_pairs;
-        pc.bwd_moved += bwd_moved;
+    } else {
+        // ---- backward only: certificate from the given lse
+        __syncthreads();
+        const float flx = (cx - W + 1 > 0) ? g.tlat[cx - W] - oxf : -INFINITY;
+        const float fly = (cy - W + 1 > 0) ? g.tlat[cy - W] - oyf : -INFINITY;
+        const float flz = (cz - W + 1 > 0) ? g.tlat[cz - W] - ozf : -INFINITY;
+        const float fhx = (cx1 + W < R - 1) ? g.tlat[cx1 + W + 1] - oxf : INFINITY;
+        const float fhy = (cy1 + W < R - 1) ? g.tlat[cy1 + W + 1] - oyf : INFINITY;
+        const float fhz = (cz1 + W < R - 1) ? g.tlat[cz1 + W + 1] - ozf : INFINITY;
+        for (int p = tid; p < P; p += BLOCK) {
+            const float4 pq = S.pq[p];
+            float4 pv = S.pv[p];
+            float D = fminf(fminf(pq.x - flx, fhx - pq.x),
+                            fminf(fminf(pq.y - fly, fhy - pq.y), fminf(pq.z - flz, fhz - pq.z)));
+            D = fmaxf(D * (1.0f - 1e-5f) - 1e-6f * g.h, 0.0f);
+            const bool cert = bmin2 * D * D >= a.T2 - pv.y;
+            if (!cert) {
+                const int slot = atomicAdd(&a.st->nfb, 1);
+                a.fb[slot] = p0 + p;
+                pv.z = 0.0f;
+                S.pv[p] = pv;
+            }
+        }
     }
+
+    unsigned long long bwd_pairs = 0ull, bwd_moved = 0ull;
+    if (MODE != MODE_EVAL) {
+        // ---- backward, key-parallel over the tile's queries (Alg. 2)
+        // Box and smallest lse2 of the queries that carry a gradient; keys
+        // whose every pair with them weighs below e^-T are skipped.
+        float bl[7] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, INFINITY};
+        __syncthreads();
+        for (int p = tid; p < P; p += BLOCK) {
+            const float4 pv = S.pv[p];
+            if (pv.z == 0.0f) continue;
+            const float4 pq = S.pq[p];
+            bl[0] = fminf(bl[0], pq.x); bl[1] = fminf(bl[1], pq.y); bl[2] = fminf(bl[2], pq.z);
+            bl[3] = fmaxf(bl[3], pq.x); bl[4] = fmaxf(bl[4], pq.y); bl[5] = fmaxf(bl[5], pq.z);
+            bl[6] = fminf(bl[6], pv.y);
+        }
+        tile_bounds(bl, &S.box[0][0]);
+        const float bcut = bl[6] - a.T2;
+
+        Cursor cu = {0, 0, 0};
+        ncand = 0;
+        for (;;) {
+            gather(cu, bl, bcut);
+            if (ncand == 0) break;
+            int nmv;
+            const int n = load_batch(nmv);
+            bwd_pairs += (unsigned long long)n * P;
+            bwd_moved += (unsigned long long)nmv * P;
+            int Sb = 1;
+            while (Sb < 64 && Sb * 2 * n <= BLOCK) Sb *= 2;
+            const int kk = tid / Sb, ph = tid - kk * Sb;
+            const bool act = kk < n;
+            constexpr int NA = NAcc<DEG>::n;
+            constexpr int NF = TileSmem<DEG>::NF;
+            constexpr int NV = DEG == 0 ? 1 : (DEG == 1 ? 4 : 10);
+            float acc[NA];
+#pragma unroll
+            for (int t = 0; t < NA; ++t) acc[t] = 0.0f;
+            float4 kc = make_float4(0, 0, 0, 0), kv = make_float4(0, 0, 0, 0);
+            KeyQ<DEG> kq;
+            int tag = 0;
+            if (act) {
+                kc = S.kc[kk];
+                kv = S.kv[kk];
+                kq = load_q(S, kk);
+                tag = S.kid[kk];
+            }
+            const bool moved = act && tag < 0;
+            if (__any(moved)) {
+                if (act) bwd_key<true, DEG>(S, P, ph, Sb, kc, kv, kq, acc);
+            } else {
+                if (act) bwd_key<false, DEG>(S, P, ph, Sb, kc, kv, kq, acc);
+            }
+            for (int off = 1; off < Sb; off <<= 1) {
+#pragma unroll
+                for (int t = 0; t < NA; ++t) acc[t] += __shfl_xor(acc[t], off, 64);
+            }
+            // Final channel values (Sec. 3.6).  Grid key: values (nv), rho.
+            // Moved key: Delta = centre gradient, values (nv), rho'.
+            // dL/dv = sum delta * monomial; dL/drho = beta dL/dbeta =
+            // -beta sum u |x|^2; dL/dc = -sum delta grad_x f + 2 beta sum u x
+            // with sum delta grad_x f = d sum delta + S sum delta x.
+            const float beta = -kc.w * LN2;
+            float val[NF];
+#pragma unroll
+            for (int t = 0; t < NF; ++t) val[t] = 0.0f;
+            const int vo = moved ? 3 : 0;
+            val[vo] = acc[0];
+            if (DEG >= 1) {
+                val[vo + 1] = acc[1];
+                val[vo + 2] = acc[2];
+                val[vo + 3] = acc[3];
+            }
+            if (DEG == 2) {
+#pragma unroll
+                for (int t = 0; t < 6; ++t) val[vo + 4 + t] = acc[8 + t];
+            }
+            val[vo + NV] = -beta * acc[4];
+            if (moved) {
+                float gx = 2.0f * beta * acc[5], gy = 2.0f * beta * acc[6], gz = 2.0f * beta * acc[7];
+                if constexpr (DEG >= 1) {
+                    gx = fmaf(-kv.y, acc[0], gx);
+                    gy = fmaf(-kv.z, acc[0], gy);
+                    gz = fmaf(-kv.w, acc[0], gz);
+                }
+                if constexpr (DEG == 2) {  // - S sum(delta x)
+                    gx -= fmaf(2.0f * kq.a.x, acc[1], fmaf(kq.a.w, acc[2], kq.b.x * acc[3]));
+                    gy -= fmaf(kq.a.w, acc[1], fmaf(2.0f * kq.a.y, acc[2], kq.b.y * acc[3]));
+                    gz -= fmaf(kq.b.x, acc[1], fmaf(kq.b.y, acc[2], 2.0f * kq.a.z * acc[3]));
+                }
+                val[0] = gx;
+                val[1] = gy;
+                val[2] = gz;
+            }
+            __syncthreads();  // staged keys no longer needed: reuse their LDS
+            if (act && ph == 0) {
+#pragma unroll
+                for (int t = 0; t < NF; ++t) S.fv[kk * NF + t] = val[t];
+            }
+            __syncthreads();
+            // one atomic per key channel, NF consecutive lanes per key
+            for (int t = tid; t < n * NF; t += BLOCK) {
+                const int kq2 = t / NF, sl = t - kq2 * NF;
+                const int tg = S.kid[kq2];
+                const bool mv = tg < 0;
+                const float x = S.fv[t];
+                int c = -1;
+                if (!mv) {
+                    c = sl < NV ? L.gval + sl : (sl == NV ? L.grho : -1);
+                } else {
+                    c = sl < 3 ? L.mdel + sl
+                               : (sl < 3 + NV ? L.mval + (sl - 3) : (sl == 3 + NV ? L.mrho : -1));
+                }
+                if (c >= 0 && x != 0.0f) {
+                    const int64_t v = mv ? (int64_t)(-tg - 1) : (int64_t)tg;
+                    unsafeAtomicAdd(a.grad + v * L.nch + c, x);
+                }
+            }
+        }
+    }
+    pc.fwd += fwd_pairs;
+    pc.fwd_moved += fwd_moved;
+    pc.bwd += bwd_pairs;
+    pc.bwd_moved += bwd_moved;
 }
 
 // Persistent tile kernel of one shape: workgroups pull tiles (heaviest

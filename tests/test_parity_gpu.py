@@ -177,6 +177,33 @@ def test_eval_coarse_lattice_exact_max_path(E):
     PT.check_eval(O, lse, ref)
 
 
+def test_wide_window_beyond_one_row_group(E):
+    """Small scales widen the window past 15 cells: at R = 40 with rho in
+    [2.5, 3.5] the certificate needs W = 26, so a tile's
+    moved-key rows (up to 39 x 39 cells) span two row groups.  Every query
+    inside the lattice must still be certified by its window (none falls back
+    to all keys), and values, gradient and a fit step match the global
+    definition."""
+    R, J = 40, 2048
+    w = W.get("sphere_r8")
+    q, o = W.make_batch(w, 21, J=J)
+    th = W.perturbed_theta(R, 22, rho0=3.0)
+    O, lse, nu, st = run_eval(E, R, th, q)
+    assert st["W"] == 26, st["W"]
+    assert nu == 0
+    ref = PT.reference(R, th, q)
+    PT.check_eval(O, lse, ref)
+    rng = np.random.default_rng(23)
+    dl = rng.standard_normal(J) / J
+    with E.Engine(R, J) as eng:
+        G = eng.grad(PT.to_dev(th), PT.to_dev(q), PT.to_dev(ref["O"]), PT.to_dev(ref["lse"]), PT.to_dev(dl))
+        torch.cuda.synchronize()
+        assert eng.stats()["n_uncertified"] == 0
+        G = G.cpu().numpy()
+    gr, ar, br = PT.oracle_grad(R, th, q, dl)
+    PT.check_grad(G, gr, ar, br)
+
+
 def test_eval_grid_keys_only(E):
     """offsets = 0 (Eq. func-interp, the ablation's G-6): theta holds only the
     five grid channels per vertex (value, slope, scale)."""
