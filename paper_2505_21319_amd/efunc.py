@@ -16,7 +16,9 @@ from typing import Optional
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libefunc.so")
+# EFUNC_LIBRARY selects another build of the same library (e.g. the host-
+# sanitised one); by default the in-tree libefunc.so next to this file.
+LIB_PATH = os.environ.get("EFUNC_LIBRARY") or os.path.join(HERE, "libefunc.so")
 NCH = 13
 
 EFUNC_OK = 0
