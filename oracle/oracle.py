@@ -16,20 +16,27 @@ import numpy as np
 NCH = 13
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "efunc_oracle.c")
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# EFUNC_ORACLE_LIB selects another build (the sanitised one of build_oracle)
+_LIB_PATH = os.environ.get("EFUNC_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
+# AddressSanitizer + UndefinedBehaviorSanitizer, every UB report fatal
+SANITIZE_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                  "-fno-sanitize-recover=undefined"]
 
 
-def build_oracle(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, OpenMP, IEEE semantics: no fast-math)."""
-    if force or not os.path.exists(_LIB_PATH):
-        tmp = _LIB_PATH + ".tmp"
+def build_oracle(force: bool = True, sanitize: bool = False, out: str = None) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, IEEE semantics: no fast-math);
+    sanitize=True builds an ASan/UBSan copy (load it with the gcc sanitizer
+    runtimes preloaded) at out."""
+    out = out or _LIB_PATH
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
+        opt = SANITIZE_FLAGS if sanitize else ["-O2"]
         subprocess.check_call(
-            ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
-             "-o", tmp, _SRC, "-lm"]
+            ["gcc", *opt, "-fopenmp", "-fPIC", "-shared", "-std=c99", "-o", tmp, _SRC, "-lm"]
         )
-        os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+        os.replace(tmp, out)
+    return out
 
 
 class _Grid(C.Structure):

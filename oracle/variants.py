@@ -13,19 +13,23 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "efunc_oracle_var.c")
-_LIB_PATH = os.path.join(_HERE, "liboracle_var.so")
+# EFUNC_ORACLE_VAR_LIB selects another build (the sanitised one of build_var_oracle)
+_LIB_PATH = os.environ.get("EFUNC_ORACLE_VAR_LIB") or os.path.join(_HERE, "liboracle_var.so")
 _lib = None
 KEYW = 16
 GRADW = 14
 
 
-def build_var_oracle(force: bool = True, src: str = None, out: str = None) -> str:
-    """Compile the variant oracle with gcc (-O2, OpenMP, IEEE semantics)."""
+def build_var_oracle(force: bool = True, src: str = None, out: str = None, sanitize: bool = False) -> str:
+    """Compile the variant oracle with gcc (-O2, OpenMP, IEEE semantics);
+    sanitize=True builds an ASan/UBSan copy."""
+    from .oracle import SANITIZE_FLAGS
     src = src or _SRC
     out = out or _LIB_PATH
     if force or not os.path.exists(out):
         tmp = out + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+        opt = SANITIZE_FLAGS if sanitize else ["-O2"]
+        subprocess.check_call(["gcc", *opt, "-fopenmp", "-fPIC", "-shared", "-std=c99",
                                "-I", _HERE, "-o", tmp, src, "-lm"])
         os.replace(tmp, out)
     return out

@@ -27,17 +27,26 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"),
+# Host-code AddressSanitizer + UndefinedBehaviorSanitizer for the C ABI; the
+# device code is built as usual (-Xarch_host keeps the sanitizers off it).
+# Load the result with clang's ASan runtime preloaded.
+SANITIZE_FLAGS = ["-O1", "-g", "-Xarch_host", "-fno-omit-frame-pointer",
+                  "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined"]
+
+
+def build(verbose: bool = False, sanitize: bool = False, out: str = None) -> str:
+    out = out or LIB
+    tmp = out + ".tmp"
+    flags = [f for f in HIPCC_FLAGS if f != "-O3"] + SANITIZE_FLAGS if sanitize else HIPCC_FLAGS
+    cmd = [hipcc(), *flags, "-I", os.path.join(ROOT, "include"),
            "-I", os.path.join(HERE, "csrc"), "-o", tmp, *SOURCES]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
     if verbose:
         print(res.stderr)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
