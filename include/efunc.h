@@ -73,7 +73,13 @@ typedef struct {
     int32_t window;        /* 0: choose the window half-width W per call from the current
                               scales; > 0: force W (queries that fail the certificate then
                               fall back to all keys) */
-    int32_t deterministic; /* reserved, must be 0 */
+    int32_t deterministic; /* 1: every result is a function of the inputs alone, bit for bit
+                              between calls and runs (same library, device and tuning): the
+                              query and moved-key orders come from stable radix sorts and the
+                              gradient and fallback-loss sums are exact fixed-point integer sums
+                              (scales from bounds of the call's data, rounding each contribution
+                              to within 2^-61 of its channel's bound).  Slower; contexts only
+                              (not batches, not efunc_fit_step_static).  0: default */
     int32_t check_finite;  /* 1: before anything is enqueued, synchronise the stream and scan
                               the call's input arrays (parameters, moments, points, targets,
                               O / lse / dL/dO) on the host; a NaN or Inf returns

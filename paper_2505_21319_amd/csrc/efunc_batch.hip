@@ -175,6 +175,8 @@ int efunc_batch_create(const efunc_config* cfgs, const int64_t* max_points, int3
     if (n_shapes < 1 || n_shapes > 65535) return fail(EFUNC_EINVAL, "n_shapes = %d outside [1, 65535]", n_shapes);
     for (int s = 0; s < n_shapes; ++s) {
         if (cfgs[s].check_finite) return fail(EFUNC_EUNSUPPORTED, "shape %d: check_finite is not available in a batch", s);
+        if (cfgs[s].deterministic)
+            return fail(EFUNC_EUNSUPPORTED, "shape %d: deterministic mode is not available in a batch", s);
         if (cfgs[s].degree != cfgs[0].degree)
             return fail(EFUNC_EUNSUPPORTED, "shape %d: every shape of a batch needs the same degree", s);
     }

@@ -160,6 +160,24 @@ size_t carve_work(const efunc_config& cfg, const Layout& layout, int64_t max_poi
     k.take(w.scan_blk, nblk + 1);
     k.take(w.grad, (int64_t)layout.nch * I);
     k.take(w.st, 1);
+    // deterministic mode: radix-sort buffers and fixed-point accumulators
+    w.rs_k[0] = w.rs_k[1] = w.rs_v[0] = w.rs_v[1] = nullptr;
+    w.rs_hist = w.rs_blk = nullptr;
+    w.gfix = nullptr;
+    w.det = nullptr;
+    w.rs_n = w.rs_nb = 0;
+    if (cfg.deterministic) {
+        w.rs_n = mp > I ? mp : I;
+        w.rs_nb = (w.rs_n + RS_TILE - 1) / RS_TILE;
+        for (int t = 0; t < 2; ++t) {
+            k.take(w.rs_k[t], w.rs_n);
+            k.take(w.rs_v[t], w.rs_n);
+        }
+        k.take(w.rs_hist, 2 * 256 * w.rs_nb + 1);
+        k.take(w.rs_blk, (256 * w.rs_nb + SCAN_TILE - 1) / SCAN_TILE + 1);
+        k.take(w.gfix, (int64_t)layout.nch * I);
+        k.take(w.det, 1);
+    }
     return (k.off + 255) & ~(size_t)255;
 }
 
@@ -193,7 +211,7 @@ int check_config(const efunc_config* cfg, Layout* layout)
     if (!(cfg->t_cut > 0.0f) || !isfinite(cfg->t_cut)) return fail(EFUNC_EINVAL, "t_cut must be > 0");
     if (cfg->window < 0 || cfg->window > WMAX)
         return fail(EFUNC_EINVAL, "window = %d outside [0, %d]", cfg->window, WMAX);
-    if (cfg->deterministic != 0) return fail(EFUNC_EUNSUPPORTED, "deterministic mode is not built");
+    if (cfg->deterministic != 0 && cfg->deterministic != 1) return fail(EFUNC_EINVAL, "deterministic must be 0 or 1");
     return make_layout(cfg, layout);
 }
 
@@ -390,6 +408,7 @@ int efunc_fit_step_static(const efunc_config* cfg, float* theta, float* m, float
     if ((rc = check_config(cfg, &layout))) return rc;
     if (cfg->check_finite)
         return fail(EFUNC_EUNSUPPORTED, "check_finite copies inputs to the host; not available here");
+    if (cfg->deterministic) return fail(EFUNC_EUNSUPPORTED, "deterministic mode needs a context");
     if (J < 0) return fail(EFUNC_EINVAL, "J = %lld < 0", (long long)J);
     if (J > (int64_t)INT32_MAX - PMAX) return fail(EFUNC_ESIZE, "J = %lld too large", (long long)J);
     void* base = nullptr;
@@ -499,6 +518,7 @@ int efunc_create(const efunc_config* cfg, int64_t max_points, efunc_ctx** out)
     const std::vector<float> t = lattice(*cfg);
     e = hipMemcpy(w.tlat, t.data(), sizeof(float) * cfg->R, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(w.grad, 0, sizeof(float) * layout.nch * w.I);
+    if (e == hipSuccess && w.gfix) e = hipMemset(w.gfix, 0, sizeof(unsigned long long) * layout.nch * w.I);
     if (e == hipSuccess) e = hipMemset(w.st, 0, sizeof(DevStats));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {

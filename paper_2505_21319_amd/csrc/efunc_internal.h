@@ -20,6 +20,7 @@ constexpr int LBIN_BLOCK = 1024;  // threads per LDS-binning workgroup
 constexpr int LBIN_NW = 64;     // most LDS-binning workgroups (rows of the key histogram)
 constexpr int LBIN_PER = 4096;  // queries per LDS-binning workgroup at least
 constexpr int SLICE_KEYS = 8;   // slice-index sort keys per cost bucket in the tile order
+constexpr int RS_TILE = 4 * BLOCK;  // elements per workgroup of the deterministic radix sort
 constexpr float LOG2E = 1.4426950408889634f;
 constexpr float LN2 = 0.6931471805599453f;
 
@@ -48,6 +49,26 @@ struct DevStats {
     int bcount[128];          // tiles per cost bucket (log2 of the window pair count)
 };
 static_assert(sizeof(DevStats) == 4 * 128 + 512, "DevStats layout");
+
+// Deterministic mode: bounds of the call's data (order-independent
+// atomicMax / atomicMin over ordered encodings), the fixed-point scales of
+// the gradient channels and of the fallback loss sums derived from them, and
+// the fallback loss accumulators.
+struct DetStats {
+    unsigned int omax_bits;    // max |value coefficient o| over keys
+    unsigned int d1max_bits;   // max sum_k |d_k| over keys
+    unsigned int dinf_bits;    // max |d_k| over keys and axes
+    unsigned int sabs_bits;    // max sum of |quadratic coefficients| over keys
+    unsigned int bmax_bits;    // max beta over keys
+    unsigned int amax_bits;    // max |target| (fit) or |dL/dO| (grad) over queries
+    unsigned int Omax_bits;    // max |O| over the given outputs (grad)
+    unsigned int lo_enc[3];    // ordered encodings of the smallest query / key-centre coordinate
+    unsigned int hi_enc[3];    // and of the largest
+    int pad0[19];
+    double dscale[32];         // per channel: gradient units per fixed-point count (a power of 2)
+    double lscale[2];          // fallback MSE and L1 sums
+    unsigned long long fbfix[2];
+};
 
 // Model variant and the per-vertex channel layout of theta (Sec. 3.2
 // Eq. poly-func degree; Eq. func-interp / func-with-offset / func-offset key
@@ -114,6 +135,15 @@ struct Work {
     double2* lpart;       // [max_tiles]  per-tile loss sums
     int* scan_blk;        // [ceil(max(8 NB3 PSPLIT, 128 SLICE_KEYS nch) / SCAN_TILE) + 1] scan block sums
     float* grad;          // [nch I] internal gradient of efunc_fit_step (kept zero)
+    // deterministic mode only (else null): stable radix sorts of the query and
+    // moved-key sort keys, fixed-point gradient accumulators
+    int* rs_k[2];         // [rs_n] sort keys, ping-pong
+    int* rs_v[2];         // [rs_n] sorted positions, ping-pong
+    int* rs_hist;         // [256 rs_nb + 1] digit counts per workgroup, then their scan
+    int* rs_blk;          // scan block sums
+    int64_t rs_n, rs_nb;
+    unsigned long long* gfix;  // [nch I] two's-complement fixed-point gradient (kept zero)
+    DetStats* det;
     DevStats* st;
     int num_cu;
     // launch tuning (runtime): tile query cap, whether sparse 2x2x2 cell
@@ -170,6 +200,9 @@ struct TileArgs {
     float* dOdq_out;
     float* grad;
     int64_t I;
+    // deterministic mode (else null): fixed-point gradient and loss sums
+    unsigned long long* gfix;
+    DetStats* det;
 };
 
 // Per-shape arguments of the batched tile ordering, loss reduction and AdamW.

@@ -142,6 +142,290 @@ __global__ void k_reset_front(DevStats* st, int* __restrict__ a, int64_t na, int
         for (int i = threadIdx.x; i < 128; i += blockDim.x) st->bcount[i] = 0;
 }
 
+// ---------------------------------------------------------- deterministic mode
+// Stable LSD radix sort of (key, value) pairs, 8-bit digits, RS_TILE
+// elements per workgroup.  Pass 1 writes each workgroup's digit histogram
+// (digit-major), the exclusive scan of it gives every (digit, workgroup)
+// its output offset, and pass 2 places each element after the earlier
+// elements of its workgroup with the same digit: wave ballots rank it among
+// its wave, per-wave counts in LDS rank the waves, a running count per
+// digit carries the earlier rounds.  Equal keys keep their input order.
+__global__ __launch_bounds__(BLOCK) void k_rs_hist(const int* __restrict__ key, int64_t n, int shift, int nb,
+                                                   int* __restrict__ hist)
+{
+    __shared__ int h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+#pragma unroll
+    for (int i = 0; i < RS_TILE / BLOCK; ++i) {
+        const int64_t e = base + i * BLOCK + threadIdx.x;
+        if (e < n) atomicAdd(&h[((unsigned)key[e] >> shift) & 255u], 1);
+    }
+    __syncthreads();
+    hist[threadIdx.x * (int64_t)nb + blockIdx.x] = h[threadIdx.x];
+}
+
+// vin == null: the values are the input positions.
+__global__ __launch_bounds__(BLOCK) void k_rs_scatter(const int* __restrict__ kin, const int* __restrict__ vin,
+                                                      int64_t n, int shift, int nb, const int* __restrict__ off,
+                                                      int* __restrict__ kout, int* __restrict__ vout)
+{
+    static_assert(BLOCK == 256, "one digit per thread");
+    __shared__ int run[256];
+    __shared__ int wc[BLOCK / 64][256];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    run[tid] = off[tid * (int64_t)nb + blockIdx.x];
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int i = 0; i < RS_TILE / BLOCK; ++i) {
+        const int64_t e = base + i * BLOCK + tid;
+        const bool ok = e < n;
+        const int k = ok ? kin[e] : 0;
+        const int v = ok ? (vin ? vin[e] : (int)e) : 0;
+        const int d = (int)(((unsigned)k >> shift) & 255u);
+        unsigned long long same = __ballot(ok);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1;
+            const unsigned long long m = __ballot(bit);
+            same &= bit ? m : ~m;
+        }
+        const int r = __popcll(same & ((1ull << lane) - 1ull));
+        __syncthreads();  // the previous round's counts are consumed
+#pragma unroll
+        for (int w = 0; w < BLOCK / 64; ++w) wc[w][tid] = 0;
+        __syncthreads();
+        if (ok && r == 0) wc[wv][d] = __popcll(same);
+        __syncthreads();
+        if (ok) {
+            int pos = run[d] + r;
+            for (int w = 0; w < wv; ++w) pos += wc[w][d];
+            kout[pos] = k;
+            vout[pos] = v;
+        }
+        __syncthreads();
+        int add = 0;
+#pragma unroll
+        for (int w = 0; w < BLOCK / 64; ++w) add += wc[w][tid];
+        run[tid] += add;
+    }
+}
+
+// Sorted queries: position p of the binned order takes query sorted[p].
+__global__ void k_det_gather_points(const int* __restrict__ sorted, const float* __restrict__ q,
+                                    const float* __restrict__ aux, const float* __restrict__ Oin,
+                                    const float* __restrict__ lsein, int64_t J, float4* __restrict__ ps,
+                                    float4* __restrict__ pv, int* __restrict__ pidx)
+{
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= J) return;
+    const int64_t j = sorted[p];
+    ps[p] = make_float4(q[3 * j], q[3 * j + 1], q[3 * j + 2], aux ? aux[j] : 0.0f);
+    if (Oin) pv[p] = make_float4(Oin[j], lsein[j], 0.0f, 0.0f);
+    if (pidx) pidx[p] = (int)j;
+}
+
+// Sorted moved keys: slot p of the binned records takes vertex sorted[p]'s.
+template <int DEG>
+__global__ void k_det_gather_keys(const int* __restrict__ sorted, int64_t I, const float4* __restrict__ mrec,
+                                  float4* __restrict__ mk)
+{
+    constexpr int MW = mk_width(DEG);
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= I) return;
+    const int64_t v = sorted[p];
+#pragma unroll
+    for (int t = 0; t < MW; ++t) mk[MW * p + t] = mrec[MW * v + t];
+}
+
+// Order-preserving unsigned encoding of a float (for atomicMin / atomicMax).
+__device__ __forceinline__ unsigned int fenc(float f)
+{
+    const unsigned int b = __float_as_uint(f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float fdec(unsigned int e)
+{
+    return __uint_as_float((e & 0x80000000u) ? (e & 0x7fffffffu) : ~e);
+}
+
+__global__ void k_det_reset(DetStats* det)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    det->omax_bits = det->d1max_bits = det->dinf_bits = det->sabs_bits = det->bmax_bits = 0u;
+    det->amax_bits = det->Omax_bits = 0u;
+    for (int d = 0; d < 3; ++d) {
+        det->lo_enc[d] = 0xffffffffu;
+        det->hi_enc[d] = 0u;
+    }
+    det->fbfix[0] = det->fbfix[1] = 0ull;
+}
+
+// Wave maxima of non-negative floats, one device atomic per wave.
+__device__ __forceinline__ void wave_atomic_max(unsigned int* dst, float v)
+{
+    v = wave_max(v);
+    if ((threadIdx.x & 63) == 0 && v > 0.0f) atomicMax(dst, __float_as_uint(v));
+}
+__device__ __forceinline__ void wave_atomic_range(unsigned int* lo, unsigned int* hi, float vmin, float vmax)
+{
+    vmin = -wave_max(-vmin);
+    vmax = wave_max(vmax);
+    if ((threadIdx.x & 63) == 0) {
+        if (vmin <= vmax) {
+            atomicMin(lo, fenc(vmin));
+            atomicMax(hi, fenc(vmax));
+        }
+    }
+}
+
+// Bounds over the keys: value, slope and curvature magnitudes, scales and
+// the box of the key centres.
+template <int DEG>
+__global__ __launch_bounds__(BLOCK) void k_det_bounds_keys(const float* __restrict__ theta, Geo g, Layout L,
+                                                          int64_t I, DetStats* __restrict__ det)
+{
+    const int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
+    float om = 0.0f, d1 = 0.0f, di = 0.0f, sa = 0.0f, bm = 0.0f;
+    float cmin[3] = {INFINITY, INFINITY, INFINITY}, cmax[3] = {-INFINITY, -INFINITY, -INFINITY};
+    if (i < I) {
+        const float* p = theta + i * L.nch;
+        const int R = g.R;
+        const int ix = (int)(i / ((int64_t)R * R)), iy = (int)((i / R) % R), iz = (int)(i % R);
+        const float t[3] = {g.tlat[ix], g.tlat[iy], g.tlat[iz]};
+        auto values = [&](int vo) {
+            om = fmaxf(om, fabsf(p[vo]));
+            if (DEG >= 1) {
+                float s1 = 0.0f;
+                for (int k = 1; k <= 3; ++k) {
+                    s1 += fabsf(p[vo + k]);
+                    di = fmaxf(di, fabsf(p[vo + k]));
+                }
+                d1 = fmaxf(d1, s1);
+            }
+            if (DEG == 2) {
+                float s2 = 0.0f;
+                for (int k = 4; k < 10; ++k) s2 += fabsf(p[vo + k]);
+                sa = fmaxf(sa, s2);
+            }
+        };
+        if (L.grid) {
+            values(L.gval);
+            bm = fmaxf(bm, L.learn ? expf(p[L.grho]) : expf(L.rho_fixed));
+            for (int d = 0; d < 3; ++d) {
+                cmin[d] = fminf(cmin[d], t[d]);
+                cmax[d] = fmaxf(cmax[d], t[d]);
+            }
+        }
+        if (L.moved) {
+            values(L.mval);
+            bm = fmaxf(bm, L.learn ? expf(p[L.mrho]) : expf(L.rho_fixed));
+            for (int d = 0; d < 3; ++d) {
+                const float c = t[d] + p[L.mdel + d];
+                cmin[d] = fminf(cmin[d], c);
+                cmax[d] = fmaxf(cmax[d], c);
+            }
+        }
+    }
+    wave_atomic_max(&det->omax_bits, om);
+    wave_atomic_max(&det->d1max_bits, d1);
+    wave_atomic_max(&det->dinf_bits, di);
+    wave_atomic_max(&det->sabs_bits, sa);
+    wave_atomic_max(&det->bmax_bits, bm);
+    for (int d = 0; d < 3; ++d) wave_atomic_range(&det->lo_enc[d], &det->hi_enc[d], cmin[d], cmax[d]);
+}
+
+// Bounds over the queries: their box, max |target or dL/dO| and max |O|.
+__global__ __launch_bounds__(BLOCK) void k_det_bounds_queries(const float* __restrict__ q, int64_t J,
+                                                             const float* __restrict__ aux,
+                                                             const float* __restrict__ Oin,
+                                                             DetStats* __restrict__ det)
+{
+    const int64_t j = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
+    float am = 0.0f, Om = 0.0f;
+    float qmin[3] = {INFINITY, INFINITY, INFINITY}, qmax[3] = {-INFINITY, -INFINITY, -INFINITY};
+    if (j < J) {
+        for (int d = 0; d < 3; ++d) qmin[d] = qmax[d] = q[3 * j + d];
+        if (aux) am = fabsf(aux[j]);
+        if (Oin) Om = fabsf(Oin[j]);
+    }
+    wave_atomic_max(&det->amax_bits, am);
+    wave_atomic_max(&det->Omax_bits, Om);
+    for (int d = 0; d < 3; ++d) wave_atomic_range(&det->lo_enc[d], &det->hi_enc[d], qmin[d], qmax[d]);
+}
+
+// Fixed-point scales (one thread).  With X the largest coordinate
+// difference between a query and a key centre, F = max|o| + max|d|_1 X +
+// max|S| X^2 bounds every |f_a(q)| and so |O|, G1 bounds sum_j |dL/dO_j|
+// (fit: 2 (F + max|o_j|); grad: J max|dL/dO|) and D bounds |f - O|.  The
+// sum over all pairs of |contribution| to one channel of one key is then at
+// most (Sec. 3.6 closed forms, sum_a w_a = 1 per query):
+//   value o: G1;  slope d: G1 X;  curvature: G1 X^2;
+//   rho: beta_max G1 3 X^2 D;  Delta: G1 (max|d| + 2 max|S| X + 2 beta_max X D).
+// Each channel counts in units of 2^-(61 - e) with 2^e above its bound, so
+// no partial sum leaves the int64 range and the sum is exact integer
+// arithmetic, independent of the order of the atomics.
+__global__ void k_det_scales(DetStats* __restrict__ det, Layout L, int fit, int64_t J)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double X = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        const double lo = fdec(det->lo_enc[d]), hi = fdec(det->hi_enc[d]);
+        if (hi >= lo) X = fmax(X, hi - lo);
+    }
+    X = X * (1.0 + 1e-6) + 1e-30;
+    const double om = __uint_as_float(det->omax_bits), d1 = __uint_as_float(det->d1max_bits);
+    const double di = __uint_as_float(det->dinf_bits), sa = __uint_as_float(det->sabs_bits);
+    const double bm = __uint_as_float(det->bmax_bits), am = __uint_as_float(det->amax_bits);
+    const double Om = __uint_as_float(det->Omax_bits);
+    const double F = om + d1 * X + sa * X * X;
+    const double G1 = fit ? 2.0 * (F + am) : (double)J * am;
+    const double D = fit ? 2.0 * F : F + Om;
+    const double bval[10] = {G1, G1 * X, G1 * X, G1 * X, G1 * X * X, G1 * X * X, G1 * X * X,
+                             G1 * X * X, G1 * X * X, G1 * X * X};
+    const double brho = bm * G1 * 3.0 * X * X * D;
+    const double bdel = G1 * (di + 2.0 * sa * X + 2.0 * bm * X * D);
+    double b[32];
+    for (int c = 0; c < 32; ++c) b[c] = 0.0;
+    auto part = [&](int vo, int ro) {
+        for (int t = 0; t < L.nv; ++t) b[vo + t] = bval[t];
+        if (ro >= 0) b[ro] = brho;
+    };
+    if (L.grid) part(L.gval, L.grho);
+    if (L.moved) {
+        part(L.mval, L.mrho);
+        for (int k = 0; k < 3; ++k) b[L.mdel + k] = bdel;
+    }
+    auto unit = [](double bound) {
+        if (!(bound > 0.0) || !(bound < 1e300)) return 1.0;
+        return ldexp(1.0, 61 - (ilogb(bound) + 1));
+    };
+    for (int c = 0; c < 32; ++c) det->dscale[c] = unit(b[c] * (1.0 + 1e-9));
+    const double r = F + am;
+    det->lscale[0] = unit((double)J * r * r * (1.0 + 1e-9));
+    det->lscale[1] = unit((double)J * r * (1.0 + 1e-9));
+}
+
+// Fixed-point count of a gradient contribution (round to nearest).
+__device__ __forceinline__ unsigned long long fixq(float x, double scale)
+{
+    return (unsigned long long)llrint((double)x * scale);
+}
+
+// grad += fixed-point sums in float, and the sums cleared for the next call.
+__global__ void k_det_finalize(unsigned long long* __restrict__ gfix, const DetStats* __restrict__ det,
+                               int nch, int64_t n, float* __restrict__ grad)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const long long v = (long long)gfix[i];
+        if (v != 0) {
+            grad[i] += (float)((double)v / det->dscale[(int)(i % nch)]);
+            gfix[i] = 0ull;
+        }
+    }
+}
+
 // --------------------------------------------------------- key preparation
 // Value record of a key from its theta channels vo..: {o, d.x, d.y, d.z} and,
 // for degree 2, {S_xx/2, S_yy/2, S_zz/2, S_xy}, {S_xz, S_yz, 0, 0}.
@@ -1469,7 +1753,10 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem<DEG>& S, co
                 }
                 if (c >= 0 && x != 0.0f) {
                     const int64_t v = mv ? (int64_t)(-tg - 1) : (int64_t)tg;
-                    unsafeAtomicAdd(a.grad + v * L.nch + c, x);
+                    if (a.gfix)
+                        atomicAdd(a.gfix + v * L.nch + c, fixq(x, a.det->dscale[c]));
+                    else
+                        unsafeAtomicAdd(a.grad + v * L.nch + c, x);
                 }
             }
         }
@@ -1637,8 +1924,14 @@ __device__ __forceinline__ void fallback_run(const TileArgs& a)
                 const float res = O - pq.w;
                 gj = res * a.two_over_J;
                 if (tid == 0) {
-                    unsafeAtomicAdd(&a.st->fb_loss[0], (double)res * (double)res);
-                    unsafeAtomicAdd(&a.st->fb_loss[1], fabs((double)res));
+                    if (a.det) {
+                        atomicAdd(&a.det->fbfix[0],
+                                  (unsigned long long)llrint((double)res * (double)res * a.det->lscale[0]));
+                        atomicAdd(&a.det->fbfix[1], (unsigned long long)llrint(fabs((double)res) * a.det->lscale[1]));
+                    } else {
+                        unsafeAtomicAdd(&a.st->fb_loss[0], (double)res * (double)res);
+                        unsafeAtomicAdd(&a.st->fb_loss[1], fabs((double)res));
+                    }
                 }
             } else if (tid == 0) {
                 const int j = a.pidx[sp];
@@ -1697,17 +1990,23 @@ __device__ __forceinline__ void fallback_run(const TileArgs& a)
                                   dx * dy, dx * dz, dy * dz};
                 const bool mv = vid < 0;
                 const int64_t v = mv ? -vid - 1 : vid;
-                float* gp = a.grad + v * L.nch;
+                // one channel of this key: float atomic, or fixed point (deterministic mode)
+                auto add = [&](int c, float x) {
+                    if (a.gfix)
+                        atomicAdd(a.gfix + v * L.nch + c, fixq(x, a.det->dscale[c]));
+                    else
+                        unsafeAtomicAdd(a.grad + v * L.nch + c, x);
+                };
                 const int vo = mv ? L.mval : L.gval, ro = mv ? L.mrho : L.grho;
 #pragma unroll
-                for (int c = 0; c < NV; ++c) unsafeAtomicAdd(gp + vo + c, del * mono[c]);
-                if (ro >= 0) unsafeAtomicAdd(gp + ro, -beta * u * r2);
+                for (int c = 0; c < NV; ++c) add(vo + c, del * mono[c]);
+                if (ro >= 0) add(ro, -beta * u * r2);
                 if (mv) {
                     float fx, fy, fz;
                     poly_grad<DEG>(kv, kq, dx, dy, dz, fx, fy, fz);
-                    unsafeAtomicAdd(gp + L.mdel, fmaf(-fx, del, 2.0f * beta * u * dx));
-                    unsafeAtomicAdd(gp + L.mdel + 1, fmaf(-fy, del, 2.0f * beta * u * dy));
-                    unsafeAtomicAdd(gp + L.mdel + 2, fmaf(-fz, del, 2.0f * beta * u * dz));
+                    add(L.mdel, fmaf(-fx, del, 2.0f * beta * u * dx));
+                    add(L.mdel + 1, fmaf(-fy, del, 2.0f * beta * u * dy));
+                    add(L.mdel + 2, fmaf(-fz, del, 2.0f * beta * u * dz));
                 }
             }
         }
@@ -1742,6 +2041,7 @@ constexpr int LF_BLOCK = 1024;
 __global__ __launch_bounds__(LF_BLOCK) void k_loss_finalize(const double2* __restrict__ lpart,
                                                             const int* __restrict__ ntiles,
                                                             const DevStats* __restrict__ st,
+                                                            const DetStats* __restrict__ det,
                                                             double invJ, double* __restrict__ out)
 {
     __shared__ double sh[LF_BLOCK / 64];
@@ -1764,8 +2064,11 @@ __global__ __launch_bounds__(LF_BLOCK) void k_loss_finalize(const double2* __res
     s2 = block_sum<double, LF_BLOCK>(s2, sh);
     s1 = block_sum<double, LF_BLOCK>(s1, sh);
     if (threadIdx.x == 0) {
-        out[0] = (s2 + st->fb_loss[0]) * invJ;
-        out[1] = (s1 + st->fb_loss[1]) * invJ;
+        // fallback queries' sums: fixed point in deterministic mode
+        const double f2 = det ? (double)(long long)det->fbfix[0] / det->lscale[0] : st->fb_loss[0];
+        const double f1 = det ? (double)(long long)det->fbfix[1] / det->lscale[1] : st->fb_loss[1];
+        out[0] = (s2 + f2) * invJ;
+        out[1] = (s1 + f1) * invJ;
     }
 }
 
@@ -1968,6 +2271,33 @@ static hipError_t scan(const int* cnt, int64_t n, int* blk, int* start, hipStrea
     return hipGetLastError();
 }
 
+// Stable sort of positions [0, n) by keys (values < nkeys), one 8-bit digit
+// per pass; *out receives the sorted positions (a workspace buffer).
+static hipError_t radix_sort(const Work& w, const int* keys, int64_t n, int64_t nkeys, const int** out,
+                             hipStream_t s)
+{
+    int bits = 0;
+    while (bits < 31 && (1ll << bits) < nkeys) ++bits;
+    const int passes = bits > 0 ? (bits + 7) / 8 : 1;
+    const int64_t nb = (n + RS_TILE - 1) / RS_TILE;
+    if (n > w.rs_n) return hipErrorInvalidValue;
+    const int* kin = keys;
+    const int* vin = nullptr;
+    for (int pass = 0; pass < passes; ++pass) {
+        int* ko = w.rs_k[pass & 1];
+        int* vo = w.rs_v[pass & 1];
+        k_rs_hist<<<(unsigned)nb, BLOCK, 0, s>>>(kin, n, 8 * pass, (int)nb, w.rs_hist);
+        hipError_t e = scan(w.rs_hist, 256 * nb, w.rs_blk, w.rs_hist + 256 * w.rs_nb + 1, s);
+        if (e != hipSuccess) return e;
+        k_rs_scatter<<<(unsigned)nb, BLOCK, 0, s>>>(kin, vin, n, 8 * pass, (int)nb, w.rs_hist + 256 * w.rs_nb + 1,
+                                                    ko, vo);
+        kin = ko;
+        vin = vo;
+    }
+    *out = vin;
+    return hipGetLastError();
+}
+
 hipError_t run_zero_floats(float* p, int64_t n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
@@ -1982,10 +2312,26 @@ hipError_t run_front(const Work& w, const Problem& p, Mode mode, bool ordered, h
     // LDS binning of the queries (sort keys fit in one workgroup's LDS) or
     // device atomics into PSPLIT sub-counters per key, which start from zero
     // like the moved-key counters
-    const bool lbin = w.hist != nullptr;
+    // Deterministic mode: the query counts come from the atomic sub-counters
+    // (exact totals whatever the order) and both orders from stable radix
+    // sorts; every float sum then runs in an order fixed by the data.
+    const bool det = w.det != nullptr;
+    const bool lbin = w.hist != nullptr && !det;
     {
         const int64_t na = p.offsets ? C : 0, nb = lbin ? 0 : w.NK * PSPLIT;
         k_reset_front<<<grid_for(na > nb ? na : nb, BLOCK * 8), BLOCK, 0, s>>>(w.st, w.mcount, na, w.pcount, nb);
+    }
+    if (det) {
+        k_det_reset<<<1, 64, 0, s>>>(w.det);
+        if (mode != MODE_EVAL) {
+            switch (p.L.degree) {
+            case 0: k_det_bounds_keys<0><<<grid_for(I), BLOCK, 0, s>>>(p.theta, g, p.L, I, w.det); break;
+            case 2: k_det_bounds_keys<2><<<grid_for(I), BLOCK, 0, s>>>(p.theta, g, p.L, I, w.det); break;
+            default: k_det_bounds_keys<1><<<grid_for(I), BLOCK, 0, s>>>(p.theta, g, p.L, I, w.det);
+            }
+            k_det_bounds_queries<<<grid_for(J), BLOCK, 0, s>>>(p.q, J, p.aux, p.O_in, w.det);
+            k_det_scales<<<1, 64, 0, s>>>(w.det, p.L, mode == MODE_FIT ? 1 : 0, J);
+        }
     }
     // keys
     switch (p.L.degree) {
@@ -2004,10 +2350,19 @@ hipError_t run_front(const Work& w, const Problem& p, Mode mode, bool ordered, h
     if (p.offsets) {
         hipError_t e = scan(w.mcount, C, w.scan_blk, w.mstart, s);
         if (e != hipSuccess) return e;
-        if (p.L.degree == 2)
+        if (det) {
+            const int* sorted = nullptr;
+            e = radix_sort(w, w.mcell, I, C, &sorted, s);
+            if (e != hipSuccess) return e;
+            if (p.L.degree == 2)
+                k_det_gather_keys<2><<<grid_for(I), BLOCK, 0, s>>>(sorted, I, w.mrec, w.mk);
+            else
+                k_det_gather_keys<1><<<grid_for(I), BLOCK, 0, s>>>(sorted, I, w.mrec, w.mk);
+        } else if (p.L.degree == 2) {
             k_scatter_keys<2><<<grid_for(I), BLOCK, 0, s>>>(I, w.mcell, w.mrank, w.mstart, w.mrec, w.mk);
-        else
+        } else {
             k_scatter_keys<1><<<grid_for(I), BLOCK, 0, s>>>(I, w.mcell, w.mrank, w.mstart, w.mrec, w.mk);
+        }
     }
     k_window<<<1, 64, 0, s>>>(w.st, g, p.T, p.window);
     // queries
@@ -2027,9 +2382,17 @@ hipError_t run_front(const Work& w, const Problem& p, Mode mode, bool ordered, h
         if (e != hipSuccess) return e;
     }
     // the fit step writes no per-query outputs and needs no original indices
-    k_scatter_points<<<grid_for(J), BLOCK, 0, s>>>(p.q, p.aux, p.O_in, p.lse_in, J, w.pcell,
-                                                   w.prank, w.pstart, lbin ? w.hist : nullptr, chunk,
-                                                   (int)w.NK, w.ps, w.pv, mode == MODE_FIT ? nullptr : w.pidx);
+    if (det) {
+        const int* sorted = nullptr;
+        hipError_t e = radix_sort(w, w.pcell, J, w.NK * PSPLIT, &sorted, s);
+        if (e != hipSuccess) return e;
+        k_det_gather_points<<<grid_for(J), BLOCK, 0, s>>>(sorted, p.q, p.aux, p.O_in, p.lse_in, J, w.ps, w.pv,
+                                                          mode == MODE_FIT ? nullptr : w.pidx);
+    } else {
+        k_scatter_points<<<grid_for(J), BLOCK, 0, s>>>(p.q, p.aux, p.O_in, p.lse_in, J, w.pcell,
+                                                       w.prank, w.pstart, lbin ? w.hist : nullptr, chunk,
+                                                       (int)w.NK, w.ps, w.pv, mode == MODE_FIT ? nullptr : w.pidx);
+    }
     k_block_tiles<<<grid_for(w.NB3), BLOCK, 0, s>>>(w.NB3, w.pstart, w.cap, w.group, w.btiles);
     {
         hipError_t e = scan(w.btiles, w.NB3, w.scan_blk, w.tstart, s);
@@ -2075,6 +2438,8 @@ TileArgs make_tile_args(const Work& w, const Problem& p, bool ordered)
     a.dOdq_out = p.dOdq_out;
     a.grad = p.grad;
     a.I = w.I;
+    a.gfix = w.det ? w.gfix : nullptr;
+    a.det = w.det;
     return a;
 }
 
@@ -2121,6 +2486,10 @@ hipError_t run_tiles(const Work& w, const Problem& p, Mode mode, hipStream_t s)
     case 0: launch_tiles<0>(a, mode, p.dOdq_out != nullptr, (unsigned)grid, fgrid, p.ev_stop, s); break;
     case 2: launch_tiles<2>(a, mode, p.dOdq_out != nullptr, (unsigned)grid, fgrid, p.ev_stop, s); break;
     default: launch_tiles<1>(a, mode, p.dOdq_out != nullptr, (unsigned)grid, fgrid, p.ev_stop, s);
+    }
+    if (w.det && mode != MODE_EVAL) {
+        const int64_t n = (int64_t)p.L.nch * w.I;
+        k_det_finalize<<<grid_for(n, BLOCK * 8), BLOCK, 0, s>>>(w.gfix, w.det, p.L.nch, n, p.grad);
     }
     return hipGetLastError();
 }
@@ -2181,7 +2550,7 @@ hipError_t run_step_advance(int64_t* step, hipStream_t s)
 
 hipError_t run_loss_finalize(const Work& w, int64_t J, double* loss_out, hipStream_t s)
 {
-    k_loss_finalize<<<1, LF_BLOCK, 0, s>>>(w.lpart, w.tstart + w.NB3, w.st, 1.0 / (double)J, loss_out);
+    k_loss_finalize<<<1, LF_BLOCK, 0, s>>>(w.lpart, w.tstart + w.NB3, w.st, w.det, 1.0 / (double)J, loss_out);
     return hipGetLastError();
 }
 

@@ -62,8 +62,14 @@ def test_invalid_arguments_are_rejected_before_any_device_work(L):
     assert L.efunc_create(C.byref(c), 10, C.byref(out)) == E.EFUNC_EINVAL
     c = E.efunc_default_config(8)
     assert L.efunc_create(C.byref(c), -5, C.byref(out)) == E.EFUNC_EINVAL
+    c.deterministic = 2
+    assert L.efunc_create(C.byref(c), 5, C.byref(out)) == E.EFUNC_EINVAL
     c.deterministic = 1
-    assert L.efunc_create(C.byref(c), 5, C.byref(out)) == E.EFUNC_EUNSUPPORTED
+    batch = C.c_void_p()
+    assert L.efunc_batch_create(C.byref(c), (C.c_int64 * 1)(5), 1, C.byref(batch)) == E.EFUNC_EUNSUPPORTED
+    assert b"deterministic" in L.efunc_last_error()
+    assert L.efunc_fit_step_static(C.byref(c), None, None, None, 1, None, None, None, 0, None, None) == \
+        E.EFUNC_EUNSUPPORTED
     assert L.efunc_eval(None, None, None, 0, None, None, None, None, None) == E.EFUNC_EINVAL
     assert L.efunc_fit_step(None, None, None, None, 1, None, None, None, 0, None, None) == E.EFUNC_EINVAL
     assert L.efunc_destroy(None) == E.EFUNC_OK
