@@ -583,6 +583,8 @@ def main():
     ap.add_argument("--batches", type=int, default=4, help="distinct resident batches cycled")
     ap.add_argument("--cpu-sample", type=int, default=1 << 16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--deterministic", action="store_true",
+                    help="run the fit step in the library's deterministic mode")
     ap.add_argument("--compare-autodiff", action="store_true",
                     help="print the fused vs materialising-autodiff comparison instead")
     ap.add_argument("--autotune", action="store_true",
@@ -643,7 +645,7 @@ def main():
     surf = W.surface_points(w, 16384, seed=W.seed_for(w, -2, "meanshift"), device=dev)
     t_gen = time.perf_counter() - t_gen
 
-    eng = E.Engine(R, J)
+    eng = E.Engine(R, J, deterministic=1 if args.deterministic else 0)
     if args.tuning:
         eng.set_tuning(*[int(x) for x in args.tuning.split(",")])
     theta = torch.empty(R, R, R, 13, device=dev, dtype=torch.float32)
@@ -709,10 +711,14 @@ def main():
             "t_cut": 20.0,
             "resident_batches": args.batches,
             "tuning": eng.tuning(),
+            "deterministic": bool(args.deterministic),
         },
         "roofline": dict(alu_roofline("k_tile<FIT>", tile_avg_s, pairs, bp, bpm, traffic),
                          fwd_moved_pairs_per_launch=pm),
         "stats": {"W": st["W"], "tiles": st["n_tiles"], "uncertified": st["n_uncertified"],
+                  "queries_per_tile": J / max(st["n_tiles"], 1),
+                  "window_keys_per_tile": st["window_keys"] / max(st["n_tiles"], 1),
+                  "kept_keys_per_tile": st["kept_keys"] / max(st["n_tiles"], 1),
                   "beta_min": st["beta_min"], "loss_mse": float(lossv[0]), "loss_l1": float(lossv[1]),
                   "gen_seconds": t_gen, "kernel_source_sha": kernel_source_sha()},
     }

@@ -121,6 +121,8 @@ typedef struct {
     float beta_grid_max;    /* largest scale over grid keys */
     int32_t n_nonfinite;    /* non-finite parameters seen by the last call */
     int64_t workspace_bytes;/* device memory owned by the context */
+    int64_t window_keys;    /* window keys the forward's cull tested, summed over tiles */
+    int64_t kept_keys;      /* of which kept for the pair loops */
 } efunc_stats;
 
 /* Fill *cfg with defaults for resolution R: [-1,1]^3, offsets on, T = 20,

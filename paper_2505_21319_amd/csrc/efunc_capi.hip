@@ -705,6 +705,8 @@ int efunc_get_stats(efunc_ctx* ctx, efunc_stats* out)
     out->pairs_moved = (int64_t)st.pairs_moved;
     out->bwd_pairs = (int64_t)st.bwd_pairs;
     out->bwd_pairs_moved = (int64_t)st.bwd_pairs_moved;
+    out->window_keys = (int64_t)st.cand;
+    out->kept_keys = (int64_t)st.kept;
     uint32_t b = st.bmin_bits, gb = st.bgmax_bits;
     memcpy(&out->beta_min, &b, 4);
     memcpy(&out->beta_grid_max, &gb, 4);

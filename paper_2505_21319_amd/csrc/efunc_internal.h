@@ -45,7 +45,9 @@ struct DevStats {
     unsigned long long bwd_pairs;    // pairs evaluated by the backward (after block truncation)
     unsigned long long bwd_pairs_moved;
     double fb_loss[2];        // loss sums of fallback queries
-    int pad3[20];
+    unsigned long long cand;  // window keys the forward's cull tested
+    unsigned long long kept;  // of which kept (loaded for the pair loops)
+    int pad3[16];
     int bcount[128];          // tiles per cost bucket (log2 of the window pair count)
 };
 static_assert(sizeof(DevStats) == 4 * 128 + 512, "DevStats layout");

@@ -135,6 +135,8 @@ __global__ void k_reset_front(DevStats* st, int* __restrict__ a, int64_t na, int
         st->pairs_moved = 0ull;
         st->bwd_pairs = 0ull;
         st->bwd_pairs_moved = 0ull;
+        st->cand = 0ull;
+        st->kept = 0ull;
         st->fb_loss[0] = 0.0;
         st->fb_loss[1] = 0.0;
     }
@@ -1172,7 +1174,7 @@ __device__ __forceinline__ void fwd_qgrad(const TileSmem<DEG>& S, int n, int ph,
 
 // Pair counts of the tiles a workgroup has run (flushed to DevStats once).
 struct PairCount {
-    unsigned long long fwd = 0, fwd_moved = 0, bwd = 0, bwd_moved = 0;
+    unsigned long long fwd = 0, fwd_moved = 0, bwd = 0, bwd_moved = 0, cand = 0, kept = 0;
 };
 
 __device__ __forceinline__ void flush_pairs(DevStats* st, const PairCount& c)
@@ -1182,6 +1184,8 @@ __device__ __forceinline__ void flush_pairs(DevStats* st, const PairCount& c)
         if (c.fwd_moved) atomicAdd(&st->pairs_moved, c.fwd_moved);
         if (c.bwd) atomicAdd(&st->bwd_pairs, c.bwd);
         if (c.bwd_moved) atomicAdd(&st->bwd_pairs_moved, c.bwd_moved);
+        if (c.cand) atomicAdd(&st->cand, c.cand);
+        if (c.kept) atomicAdd(&st->kept, c.kept);
     }
 }
 
@@ -1282,7 +1286,9 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem<DEG>& S, co
     // the box reaches cutoff (every dropped pair weighs below
     // 2^(cutoff - lse2) <= e^-T) and append their tags: packed vertex
     // indices ix | iy << 9 | iz << 18 for grid keys, -(record + 1) for moved.
+    unsigned long long ncull = 0ull;  // candidates tested (statistics)
     auto cull = [&](bool grid, int k0, int nk, const float (&bl)[7], float cutoff) {
+        ncull += nk;
         int tag = 0;
         bool keep = false;
         if (tid < nk) {
@@ -1517,9 +1523,11 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem<DEG>& S, co
                 const int n = load_batch(nm);
                 fwd_pairs += (unsigned long long)n * P;
                 fwd_moved += (unsigned long long)nm * P;
+                pc.kept += n;
                 if (act) fwd_sums<DEG>(S, n, ph, Sf, q, Mr, e, m);
                 if (act2) fwd_sums<DEG>(S, n, ph2, Sf2, q2, Mr2, e2, m2);
             }
+            pc.cand += ncull;
         }
         __syncthreads();
         S.red[tid] = make_float2(e, m);

@@ -59,7 +59,7 @@ class efunc_stats(C.Structure):
                 ("pairs", C.c_int64), ("pairs_moved", C.c_int64), ("bwd_pairs", C.c_int64),
                 ("bwd_pairs_moved", C.c_int64), ("beta_min", C.c_float),
                 ("beta_grid_max", C.c_float), ("n_nonfinite", C.c_int32),
-                ("workspace_bytes", C.c_int64)]
+                ("workspace_bytes", C.c_int64), ("window_keys", C.c_int64), ("kept_keys", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
