@@ -365,6 +365,24 @@ int efunc_conv3d_wgrad_bf16(const void* xT, int32_t Cin, const void* dyT, int32_
 int efunc_conv3d_pack_weights(const float* W, int32_t Cin, int32_t Cout, void* wf, void* wd,
                               void* stream);
 
+/* Starting parameters of the learned initialiser from B coarse fields sdf
+ * [B][R^3] (the signed distance at the lattice vertices, device): the
+ * gradient g at every vertex by central differences (one-sided on the faces,
+ * spacing h = 2 / (R - 1)) into grad [B][R^3][3] (optional), and theta
+ * [B][R^3][13] (optional): o = sdf, d = g, rho = rho0; the moved key one
+ * Newton step towards the zero set, Delta = -sdf g / |g|^2 (|g|^2 >= 1e-12)
+ * with its length capped at h, o' = o + Delta . g, d' = g, rho' = rho0; then
+ * plus res [B][R^3][13] (optional, e.g. the network's output) and both
+ * log-scales floored at rho_min (-inf: no floor), mask [B][R^3][2]
+ * (optional, uint8) recording the floored ones.  (The paper initialises from
+ * fixed values and a mean-shift step, Sec. 3.3; learned initialisation is
+ * its future work, Sec. 5.)  efunc_initnet_theta_backward zeroes the
+ * log-scale channels of dtheta [B][R^3][13] where mask is set (the floor's
+ * derivative).  Errors: EFUNC_EINVAL, EFUNC_EHIP. */
+int efunc_initnet_theta(const float* sdf, int32_t R, int32_t B, const float* res, float rho0, float rho_min,
+                        float* theta, uint8_t* mask, float* grad, void* stream);
+int efunc_initnet_theta_backward(const uint8_t* mask, int32_t R, int32_t B, float* dtheta, void* stream);
+
 /* AdamW step on any fp32 parameter vector p [n] with moments m, v and
  * gradient g (zeroed afterwards), step >= 1 (bias correction), adam host
  * pointer (NULL = defaults). */

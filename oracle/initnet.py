@@ -129,3 +129,51 @@ def backward(params, channels, x, dout):
         flat.append(dW.reshape(-1))
         flat.append(db)
     return np.concatenate(flat)
+
+
+def base_theta(sdf, R: int, rho0: float = 7.0, res=None, rho_min: float = -np.inf):
+    """Starting parameters of the learned initialiser from coarse fields sdf
+    [B][R^3] (float32 values at the lattice vertices), in float64: returns
+    (theta [B][R^3][13], mask [B][R^3][2] of floored log-scales, grad
+    [B][R^3][3]).  The definition, written out: g = central differences of
+    sdf with spacing h = 2 / (R - 1), one-sided on the faces; o = sdf, d = g,
+    rho = rho0; Delta = -sdf g / max(|g|^2, 1e-12), scaled down to length h
+    if longer (one Newton step towards the zero set); o' = o + Delta . g,
+    d' = g, rho' = rho0; then theta + res, both log-scales floored at
+    rho_min."""
+    s = np.asarray(sdf, dtype=np.float32).astype(np.float64).reshape(-1, R, R, R)
+    B = s.shape[0]
+    h = 2.0 / (R - 1)
+    g = np.empty(s.shape + (3,))
+    for ax in range(3):
+        a = np.moveaxis(s, ax + 1, 1)
+        d = np.empty_like(a)
+        d[:, 1:-1] = (a[:, 2:] - a[:, :-2]) / (2.0 * h)
+        d[:, 0] = (a[:, 1] - a[:, 0]) / h
+        d[:, -1] = (a[:, -1] - a[:, -2]) / h
+        g[..., ax] = np.moveaxis(d, 1, ax + 1)
+    s = s.reshape(B, -1)
+    g = g.reshape(B, -1, 3)
+    gn2 = np.maximum((g * g).sum(-1), 1e-12)
+    delta = -(s / gn2)[..., None] * g
+    ln = np.linalg.norm(delta, axis=-1)
+    delta = delta * np.minimum(h / np.maximum(ln, 1e-30), 1.0)[..., None]
+    th = np.empty((B, s.shape[1], 13))
+    th[..., 0] = s
+    th[..., 1:4] = g
+    th[..., 4] = rho0
+    th[..., 5:8] = delta
+    th[..., 8] = s + (delta * g).sum(-1)
+    th[..., 9:12] = g
+    th[..., 12] = rho0
+    if res is not None:
+        r32 = np.asarray(res, dtype=np.float32).reshape(th.shape)
+        th = th + r32.astype(np.float64)
+        # the floor decides per entry: taken, as in the kernel, on the float32
+        # sum rho0 + res (a residual below half an ulp of rho0 leaves it at rho0)
+        for c in (4, 12):
+            th[..., c] = (np.float32(rho0) + r32[..., c]).astype(np.float64)
+    mask = np.stack([th[..., 4] < rho_min, th[..., 12] < rho_min], axis=-1)
+    th[..., 4] = np.maximum(th[..., 4], rho_min)
+    th[..., 12] = np.maximum(th[..., 12], rho_min)
+    return th, mask, g

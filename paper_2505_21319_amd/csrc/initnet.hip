@@ -836,6 +836,73 @@ __global__ void k_to_bf16_both(const float* __restrict__ a, int64_t V, int C, in
     }
 }
 
+// ------------------------------------------------- base parameters of the initialiser
+// Central difference of the lattice field along one axis at index n (stride
+// st between neighbours), one-sided on the faces.
+__device__ __forceinline__ float lattice_diff(const float* __restrict__ s, int n, int R, int64_t st, float h,
+                                              float two_h)
+{
+    if (n == 0) return (s[st] - s[0]) / h;
+    if (n == R - 1) return (s[0] - s[-st]) / h;
+    return (s[st] - s[-st]) / two_h;
+}
+
+// Per vertex of B fields sdf [B][R^3]: grad [B][R^3][3] (optional) and the
+// base parameters theta [B][R^3][13] (optional): o = sdf, d = gradient,
+// rho = rho0, Delta = -sdf d / |d|^2 with |Delta| <= h, o' = o + Delta . d,
+// d' = d, rho' = rho0; plus res (optional) and the log-scales floored at
+// rho_min (mask: 1 per floored log-scale, optional).
+__global__ void k_initnet_theta(const float* __restrict__ sdf, int R, int64_t n, float h, float two_h,
+                                const float* __restrict__ res, float rho0, float rho_min,
+                                float* __restrict__ grad, float* __restrict__ theta, uint8_t* __restrict__ mask)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t I = (int64_t)R * R * R, v = i % I;
+    const int ix = (int)(v / ((int64_t)R * R)), iy = (int)((v / R) % R), iz = (int)(v % R);
+    const float* s = sdf + i;
+    const float g[3] = {lattice_diff(s, ix, R, (int64_t)R * R, h, two_h), lattice_diff(s, iy, R, R, h, two_h),
+                        lattice_diff(s, iz, R, 1, h, two_h)};
+    if (grad) {
+        for (int d = 0; d < 3; ++d) grad[3 * i + d] = g[d];
+    }
+    if (!theta) continue;
+    const float sv = s[0];
+    const float gn2 = fmaxf(g[0] * g[0] + g[1] * g[1] + g[2] * g[2], 1e-12f);
+    float dl[3];
+    for (int d = 0; d < 3; ++d) dl[d] = -(sv / gn2) * g[d];
+    const float ln = sqrtf(dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2]);
+    const float cap = fminf(h / fmaxf(ln, 1e-30f), 1.0f);
+    for (int d = 0; d < 3; ++d) dl[d] *= cap;
+    float t[13];
+    t[0] = sv;
+    t[4] = rho0;
+    t[8] = sv + (dl[0] * g[0] + dl[1] * g[1] + dl[2] * g[2]);
+    t[12] = rho0;
+    for (int d = 0; d < 3; ++d) {
+        t[1 + d] = g[d];
+        t[5 + d] = dl[d];
+        t[9 + d] = g[d];
+    }
+    float* o = theta + 13 * i;
+    for (int c = 0; c < 13; ++c) o[c] = res ? t[c] + res[13 * i + c] : t[c];
+    for (int k = 0; k < 2; ++k) {
+        const int c = k == 0 ? 4 : 12;
+        const bool low = o[c] < rho_min;
+        if (low) o[c] = rho_min;
+        if (mask) mask[2 * i + k] = low ? 1 : 0;
+    }
+    }
+}
+
+// dtheta's log-scale channels zeroed where the forward floored them.
+__global__ void k_initnet_theta_mask(const uint8_t* __restrict__ mask, int64_t n, float* __restrict__ dtheta)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (mask[2 * i]) dtheta[13 * i + 4] = 0.0f;
+        if (mask[2 * i + 1]) dtheta[13 * i + 12] = 0.0f;
+    }
+}
+
 static inline int cpad8(int c) { return (c + 7) / 8 * 8; }
 
 static inline int kpad(int k) { return (k + 31) / 32 * 32; }
@@ -1201,6 +1268,37 @@ int efunc_adam_update(float* p, float* m, float* v, float* g, int64_t n, int64_t
     hipError_t e = run_adam(w, p, m, v, n, hp.lr, hp.beta1, hp.beta2, hp.eps, hp.weight_decay, (float)bc1,
                             (float)bc2, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "adam launch");
+    return EFUNC_OK;
+}
+
+int efunc_initnet_theta(const float* sdf, int32_t R, int32_t B, const float* res, float rho0, float rho_min,
+                        float* theta, uint8_t* mask, float* grad, void* stream)
+{
+    clear_error();
+    if (!sdf) return fail(EFUNC_EINVAL, "sdf is NULL");
+    if (R < 2 || R > 512 || B < 0) return fail(EFUNC_EINVAL, "R = %d or B = %d out of range", R, B);
+    if (!theta && !grad) return fail(EFUNC_EINVAL, "neither theta nor grad requested");
+    if (!isfinite(rho0) || isnan(rho_min)) return fail(EFUNC_EINVAL, "rho0 must be finite, rho_min not NaN");
+    const int64_t n = (int64_t)B * R * R * R;
+    if (n == 0) return EFUNC_OK;
+    const float h = (float)(2.0 / (R - 1)), two_h = (float)(4.0 / (R - 1));
+    k_initnet_theta<<<blocks_for(n, 256), 256, 0, (hipStream_t)stream>>>(sdf, R, n, h, two_h, res, rho0, rho_min,
+                                                                         grad, theta, mask);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "initnet theta launch");
+    return EFUNC_OK;
+}
+
+int efunc_initnet_theta_backward(const uint8_t* mask, int32_t R, int32_t B, float* dtheta, void* stream)
+{
+    clear_error();
+    if (!mask || !dtheta) return fail(EFUNC_EINVAL, "NULL argument");
+    if (R < 2 || R > 512 || B < 0) return fail(EFUNC_EINVAL, "R = %d or B = %d out of range", R, B);
+    const int64_t n = (int64_t)B * R * R * R;
+    if (n == 0) return EFUNC_OK;
+    k_initnet_theta_mask<<<blocks_for(n, 256), 256, 0, (hipStream_t)stream>>>(mask, n, dtheta);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "initnet theta backward launch");
     return EFUNC_OK;
 }
 

@@ -75,7 +75,8 @@ EXPORTS = ["efunc_default_config", "efunc_channels", "efunc_default_adam", "efun
            "efunc_batch_read_timing", "efunc_initnet_create", "efunc_initnet_destroy",
            "efunc_initnet_num_params", "efunc_initnet_forward", "efunc_initnet_backward",
            "efunc_conv3d_bf16", "efunc_conv3d_wgrad_bf16", "efunc_conv3d_pack_weights",
-           "efunc_adam_update", "efunc_loss_grad", "efunc_fit_step_static", "efunc_last_error"]
+           "efunc_adam_update", "efunc_loss_grad", "efunc_fit_step_static", "efunc_initnet_theta",
+           "efunc_initnet_theta_backward", "efunc_last_error"]
 
 _lib = None
 
@@ -134,6 +135,8 @@ def lib() -> C.CDLL:
         L.efunc_loss_grad.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp]
         L.efunc_fit_step_static.argtypes = [C.POINTER(efunc_config), vp, vp, vp, i64,
                                              C.POINTER(efunc_adam), vp, vp, i64, vp, vp]
+        L.efunc_initnet_theta.argtypes = [vp, C.c_int32, C.c_int32, vp, C.c_float, C.c_float, vp, vp, vp, vp]
+        L.efunc_initnet_theta_backward.argtypes = [vp, C.c_int32, C.c_int32, vp, vp]
         L.efunc_last_error.argtypes = []
         L.efunc_last_error.restype = C.c_char_p
         for name in ("efunc_create", "efunc_destroy", "efunc_init_params", "efunc_eval",
@@ -145,7 +148,8 @@ def lib() -> C.CDLL:
                      "efunc_batch_read_timing", "efunc_initnet_create", "efunc_initnet_destroy",
                      "efunc_initnet_forward", "efunc_initnet_backward", "efunc_conv3d_bf16",
                      "efunc_conv3d_wgrad_bf16", "efunc_conv3d_pack_weights", "efunc_adam_update",
-                     "efunc_loss_grad", "efunc_fit_step_static"):
+                     "efunc_loss_grad", "efunc_fit_step_static", "efunc_initnet_theta",
+                     "efunc_initnet_theta_backward"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -259,6 +263,34 @@ def efunc_fit_step_static(cfg: efunc_config, theta, m, v, step: int, q, o, loss_
                                        step, C.byref(adam) if adam is not None else None,
                                        _ptr(q, torch.float32, "q", 3 * J), _ptr(o, torch.float32, "o", J),
                                        J, _ptr(loss_out, torch.float64, "loss_out", 2), _stream(stream)))
+
+
+def efunc_initnet_theta(sdf, R: int, res=None, rho0: float = 7.0, rho_min: float = float("-inf"),
+                        theta=True, mask=False, grad=False, stream=None):
+    """Starting parameters from coarse fields sdf [B, R^3] (or [R^3]): returns
+    (theta [B, R^3, 13] or None, mask [B, R^3, 2] uint8 or None, grad
+    [B, R^3, 3] or None) as requested; res [B, R^3, 13] is added before the
+    log-scale floor rho_min."""
+    B = sdf.numel() // R ** 3
+    n = B * R ** 3
+    dev = sdf.device
+    th = torch.empty(B, R ** 3, 13, device=dev) if theta else None
+    mk = torch.empty(B, R ** 3, 2, device=dev, dtype=torch.uint8) if mask else None
+    gr = torch.empty(B, R ** 3, 3, device=dev) if grad else None
+    _check(lib().efunc_initnet_theta(_ptr(sdf, torch.float32, "sdf", n), R, B,
+                                     _ptr(res, torch.float32, "res", 13 * n), rho0, rho_min,
+                                     _ptr(th, torch.float32, "theta", 13 * n),
+                                     _ptr(mk, torch.uint8, "mask", 2 * n),
+                                     _ptr(gr, torch.float32, "grad", 3 * n), _stream(stream)))
+    return th, mk, gr
+
+
+def efunc_initnet_theta_backward(mask, R: int, dtheta, stream=None) -> None:
+    """Zero dtheta's log-scale channels where mask records a floored value."""
+    B = mask.numel() // (2 * R ** 3)
+    _check(lib().efunc_initnet_theta_backward(_ptr(mask, torch.uint8, "mask", 2 * B * R ** 3), R, B,
+                                              _ptr(dtheta, torch.float32, "dtheta", 13 * B * R ** 3),
+                                              _stream(stream)))
 
 
 def efunc_loss_grad(ctx, theta, q, o, grad, loss_out=None, stream=None, n_theta=None):

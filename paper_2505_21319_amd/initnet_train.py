@@ -6,8 +6,8 @@ maps the coarse signed-distance field sampled at the lattice vertices to a
 full parameter tensor.  It is trained end to end on the fitting loss: theta =
 net(sdf), then efunc_loss_grad gives dL/dtheta of the shape's MSE on its
 sample points, the network backward gives dL/dparams, AdamW updates.  All
-arithmetic runs in the library (network, loss, gradients, optimiser); torch
-holds the buffers.
+arithmetic runs in the library (network, starting parameters, loss,
+gradients, optimiser); torch holds the buffers and draws the minibatches.
 
 The initialisations are compared by fitting held-out shapes from each with
 the batched fit step (fresh points every step, cycled from a pool):
@@ -44,25 +44,9 @@ def coarse_sdf(target_fn, R: int, device) -> torch.Tensor:
 
 
 def sdf_gradient(sdf: torch.Tensor, R: int) -> torch.Tensor:
-    """Central differences of the lattice SDF (one-sided at the faces): [R^3, 3]."""
-    h = 2.0 / (R - 1)
-    s = sdf.view(R, R, R)
-    out = []
-    for ax in range(3):
-        d = torch.empty_like(s)
-        sl = [slice(None)] * 3
-        lo, hi, mid = list(sl), list(sl), list(sl)
-        mid[ax] = slice(1, -1)
-        hi[ax] = slice(2, None)
-        lo[ax] = slice(0, -2)
-        d[tuple(mid)] = (s[tuple(hi)] - s[tuple(lo)]) / (2 * h)
-        a, b = list(sl), list(sl)
-        a[ax], b[ax] = 0, 1
-        d[tuple(a)] = (s[tuple(b)] - s[tuple(a)]) / h
-        a[ax], b[ax] = -1, -2
-        d[tuple(a)] = (s[tuple(a)] - s[tuple(b)]) / h
-        out.append(d.reshape(-1))
-    return torch.stack(out, dim=1)
+    """Central differences of the lattice SDF (one-sided at the faces): [R^3, 3]
+    (library kernel efunc_initnet_theta)."""
+    return E.efunc_initnet_theta(sdf, R, theta=False, grad=True)[2].reshape(R ** 3, 3)
 
 
 def newton_theta(sdf: torch.Tensor, R: int, rho0: float = 7.0) -> torch.Tensor:
@@ -70,22 +54,8 @@ def newton_theta(sdf: torch.Tensor, R: int, rho0: float = 7.0) -> torch.Tensor:
     d = its central-difference gradient at each vertex; the moved key takes
     one Newton step towards the zero set, Delta = -sdf d / |d|^2 (its length
     capped at one lattice spacing), with o' = o + Delta . d and d' = d; both
-    log-scales rho0."""
-    h = 2.0 / (R - 1)
-    g = sdf_gradient(sdf, R)
-    gn2 = (g * g).sum(dim=1).clamp(min=1e-12)
-    delta = -(sdf / gn2)[:, None] * g
-    ln = delta.norm(dim=1, keepdim=True)
-    delta = delta * torch.clamp(h / ln.clamp(min=1e-30), max=1.0)
-    th = torch.empty(R ** 3, 13, device=sdf.device, dtype=torch.float32)
-    th[:, 0] = sdf
-    th[:, 1:4] = g
-    th[:, 4] = rho0
-    th[:, 5:8] = delta
-    th[:, 8] = sdf + (delta * g).sum(dim=1)
-    th[:, 9:12] = g
-    th[:, 12] = rho0
-    return th
+    log-scales rho0 (library kernel efunc_initnet_theta)."""
+    return E.efunc_initnet_theta(sdf, R, rho0=rho0)[0].reshape(R ** 3, 13)
 
 
 def initial_params(seed: int) -> np.ndarray:
@@ -101,26 +71,24 @@ def initial_params(seed: int) -> np.ndarray:
     return np.concatenate(parts).astype(np.float32)
 
 
-def rho_floor(theta: torch.Tensor, rho_min: float = RHO_MIN) -> torch.Tensor:
-    """Clamp the log-scale channels of theta [..., 13] to >= rho_min in place;
-    returns the mask of clamped entries (their gradient is zero).
+def compose_theta(sdf: torch.Tensor, R: int, res: torch.Tensor, rho_min: float = RHO_MIN):
+    """newton_theta(sdf) + res for B shapes (sdf [B, R^3], res [B, R^3, 13]),
+    both log-scales floored at rho_min; returns (theta [B, R^3, 13], mask
+    [B, R^3, 2] of the floored entries, whose gradient is zero).
 
     A smaller log-scale widens a radial basis function, and with it the window
     of keys every query must visit: the cost of a fitting step grows with the
     cube of the reach.  Trained end to end without a floor, the network lowers
     the scales and makes the fit several times slower per step."""
-    raw = theta[..., RHO]
-    mask = raw < rho_min
-    theta[..., RHO] = raw.clamp(min=rho_min)
-    return mask
+    th, mask, _ = E.efunc_initnet_theta(sdf, R, res=res.contiguous(), rho0=7.0, rho_min=rho_min, mask=True)
+    return th, mask
 
 
 def learned_theta(net: "E.InitNet", params, sdf) -> torch.Tensor:
     """The learned initialisation of one shape (flat [R^3 x 13]):
     newton_theta(sdf) plus the network's residual, log-scales floored."""
-    th = net.forward(params, sdf[None]).reshape(-1, CHANNELS[-1]) + newton_theta(sdf, net.R)
-    rho_floor(th)
-    return th.reshape(-1).contiguous()
+    res = net.forward(params, sdf[None]).reshape(1, -1, CHANNELS[-1])
+    return compose_theta(sdf, net.R, res)[0].reshape(-1).contiguous()
 
 
 def train(net: "E.InitNet", params: torch.Tensor, shapes, steps: int, batch: int, lr: float, seed: int,
@@ -139,22 +107,19 @@ def train(net: "E.InitNet", params: torch.Tensor, shapes, steps: int, batch: int
     losses = []
     dev = params.device
     loss = torch.zeros(batch, 2, device=dev, dtype=torch.float64)
-    base = [newton_theta(sh[0], R) for sh in shapes]
     with E.Engine(R, J) as eng:
         for step in range(1, steps + 1):
             idx = rng.choice(len(shapes), batch, replace=False)
             sdf = torch.stack([shapes[i][0] for i in idx])
-            theta = net.forward(params, sdf) + torch.stack([base[i] for i in idx])
-            clamped = rho_floor(theta)
+            res = net.forward(params, sdf).reshape(batch, -1, CHANNELS[-1])
+            theta, mask = compose_theta(sdf, R, res)
             dtheta = torch.zeros_like(theta)
             for b, i in enumerate(idx):
                 _, qsets, osets = shapes[i]
                 k = int(rng.integers(len(qsets)))
-                eng.loss_grad(theta[b], qsets[k], osets[k], dtheta[b], loss[b])
-            dr = dtheta[..., RHO]
-            dr[clamped] = 0.0
-            dtheta[..., RHO] = dr
-            net.backward(dtheta, g)
+                eng.loss_grad(theta[b].reshape(-1), qsets[k], osets[k], dtheta[b].reshape(-1), loss[b])
+            E.efunc_initnet_theta_backward(mask, R, dtheta)
+            net.backward(dtheta.reshape(res.shape[0], -1, CHANNELS[-1]), g)
             E.efunc_adam_update(params, m, v, g, step, adam)
             if step % 100 == 0 or step == 1:
                 lv = float(loss[:, 0].mean())
