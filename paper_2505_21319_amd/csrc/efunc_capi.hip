@@ -135,6 +135,7 @@ size_t carve_work(const efunc_config& cfg, const Layout& layout, int64_t max_poi
     k.take(w.gk, layout.grid ? gw * I : 1);
     k.take(w.mcell, I);
     k.take(w.mrank, I);
+    k.take(w.mslot, I);
     k.take(w.mcount, C);
     k.take(w.mstart, C + 1);
     k.take(w.mrec, layout.moved ? mw * I : 1);
@@ -159,6 +160,7 @@ size_t carve_work(const efunc_config& cfg, const Layout& layout, int64_t max_poi
     k.take(w.lpart, w.max_tiles);
     k.take(w.scan_blk, nblk + 1);
     k.take(w.grad, (int64_t)layout.nch * I);
+    k.take(w.gslot, layout.moved ? (int64_t)flush_slots(layout.degree) * I : 1);
     k.take(w.st, 1);
     // deterministic mode: radix-sort buffers and fixed-point accumulators
     w.rs_k[0] = w.rs_k[1] = w.rs_v[0] = w.rs_v[1] = nullptr;
@@ -344,13 +346,21 @@ int fit_step_impl(efunc_ctx* ctx, float* theta, float* m, float* v, int64_t step
     p.q = q;
     p.aux = o;
     p.grad = ctx->w.grad;
+    // moved keys' records stay in gslot for the AdamW below (not in
+    // deterministic mode, whose gradient goes to grad by vertex)
+    const bool slots = ctx->layout.moved && !ctx->w.det;
+    p.defer_slots = slots ? 1 : 0;
     hipError_t e = run_tiles(ctx->w, p, MODE_FIT, s);
     if (e == hipSuccess && loss_out) e = run_loss_finalize(ctx->w, J, loss_out, s);
     if (e != hipSuccess) return hip_fail(e, "fit_step launch");
     const double bc1 = 1.0 - pow((double)hp.beta1, (double)step);
     const double bc2 = 1.0 - pow((double)hp.beta2, (double)step);
-    e = run_adam(ctx->w, theta, m, v, (int64_t)ctx->layout.nch * ctx->w.I, hp.lr, hp.beta1, hp.beta2, hp.eps,
-                 hp.weight_decay, (float)bc1, (float)bc2, s);
+    if (slots)
+        e = run_adam_fit(ctx->w, ctx->layout, theta, m, v, hp.lr, hp.beta1, hp.beta2, hp.eps, hp.weight_decay,
+                         (float)bc1, (float)bc2, s);
+    else
+        e = run_adam(ctx->w, theta, m, v, (int64_t)ctx->layout.nch * ctx->w.I, hp.lr, hp.beta1, hp.beta2, hp.eps,
+                     hp.weight_decay, (float)bc1, (float)bc2, s);
     if (e != hipSuccess) return hip_fail(e, "adam launch");
     return EFUNC_OK;
 }
@@ -432,6 +442,8 @@ int efunc_fit_step_static(const efunc_config* cfg, float* theta, float* m, float
     // expects it zero) with kernels, before the step.
     hipError_t e = run_lattice(ctx.w.tlat, cfg->R, (double)cfg->lo, (double)cfg->hi, s);
     if (e == hipSuccess) e = run_zero_floats(ctx.w.grad, n_params(&ctx), s);
+    if (e == hipSuccess && layout.moved)
+        e = run_zero_floats(ctx.w.gslot, (int64_t)flush_slots(layout.degree) * ctx.w.I, s);
     if (e != hipSuccess) return hip_fail(e, "static scratch set-up");
     return fit_step_impl(&ctx, theta, m, v, step, adam, q, o, J, loss_out, stream);
 }
@@ -518,6 +530,8 @@ int efunc_create(const efunc_config* cfg, int64_t max_points, efunc_ctx** out)
     const std::vector<float> t = lattice(*cfg);
     e = hipMemcpy(w.tlat, t.data(), sizeof(float) * cfg->R, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(w.grad, 0, sizeof(float) * layout.nch * w.I);
+    if (e == hipSuccess && layout.moved)
+        e = hipMemset(w.gslot, 0, sizeof(float) * flush_slots(layout.degree) * w.I);
     if (e == hipSuccess && w.gfix) e = hipMemset(w.gfix, 0, sizeof(unsigned long long) * layout.nch * w.I);
     if (e == hipSuccess) e = hipMemset(w.st, 0, sizeof(DevStats));
     if (e == hipSuccess) e = hipDeviceSynchronize();

@@ -112,6 +112,7 @@ struct Work {
     float4* gk;           // [gk_width I]  grid key records
     int* mcell;           // [I]    cell of each moved key
     int* mrank;           // [I]    rank inside its cell
+    int* mslot;           // [I]    binned record of each vertex's moved key
     int* mcount;          // [C]
     int* mstart;          // [C+1]
     float4* mrec;         // [mk_width I]  moved key records by vertex
@@ -137,6 +138,7 @@ struct Work {
     double2* lpart;       // [max_tiles]  per-tile loss sums
     int* scan_blk;        // [ceil(max(8 NB3 PSPLIT, 128 SLICE_KEYS nch) / SCAN_TILE) + 1] scan block sums
     float* grad;          // [nch I] internal gradient of efunc_fit_step (kept zero)
+    float* gslot;         // [nfl I] moved keys' gradient by binned record, flush-slot order (kept zero)
     // deterministic mode only (else null): stable radix sorts of the query and
     // moved-key sort keys, fixed-point gradient accumulators
     int* rs_k[2];         // [rs_n] sort keys, ping-pong
@@ -177,6 +179,9 @@ struct Problem {
     float* grad;        // FIT: internal; GRAD: caller's (accumulated)
     // optional events recorded around the tile kernel
     hipEvent_t ev_start, ev_stop;
+    // FIT: leave the moved keys' gradient records in gslot (the fit step's
+    // AdamW gathers them) instead of adding them to grad
+    int defer_slots;
 };
 
 // Arguments of the tile and fallback kernels for one shape.
@@ -201,6 +206,7 @@ struct TileArgs {
     float* lse_out;
     float* dOdq_out;
     float* grad;
+    float* gslot;  // moved keys' gradient by binned record (see Work)
     int64_t I;
     // deterministic mode (else null): fixed-point gradient and loss sums
     unsigned long long* gfix;
@@ -249,11 +255,21 @@ hipError_t run_loss_finalize(const Work& w, int64_t J, double* loss_out, hipStre
 hipError_t run_adam(const Work& w, float* theta, float* m, float* v, int64_t n, float lr,
                     float beta1, float beta2, float eps, float wd, float bc1, float bc2,
                     hipStream_t s);
+// AdamW of the fit step on theta [I][nch], the moved channels' gradient
+// taken from grad plus the vertex's record in gslot (both cleared).
+hipError_t run_adam_fit(const Work& w, const Layout& L, float* theta, float* m, float* v, float lr,
+                        float beta1, float beta2, float eps, float wd, float bc1, float bc2, hipStream_t s);
 hipError_t run_init_params(const Work& w, const Geo& g, const Layout& L, float* theta,
                            const float* surf, int64_t Ns, float bandwidth, float rho0,
                            hipStream_t s);
 hipError_t run_count_uncertified(const Work& w, int64_t* out, hipStream_t s);
 hipError_t run_zero_floats(float* p, int64_t n, hipStream_t s);
+// Flush slots per key of the tile kernel's backward (moved keys' gradient
+// records in gslot): 8, or 16 for degree 2.
+__host__ __device__ constexpr int flush_slots(int deg) { return deg == 2 ? 16 : 8; }
+// Adds the moved keys' gradient records (gslot, binned order) to grad
+// (vertex order) and clears them; batched form: one per shape of tab.
+hipError_t run_slot_finalize(const TileArgs& a, hipStream_t s);
 // Writes the R float32 vertex coordinates of [lo, hi] into t (one workgroup).
 hipError_t run_lattice(float* t, int R, double lo, double hi, hipStream_t s);
 

@@ -660,7 +660,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan_apply(const int* __restrict__ cn
 template <int DEG>
 __global__ void k_scatter_keys(int64_t I, const int* __restrict__ mcell, const int* __restrict__ mrank,
                                const int* __restrict__ mstart, const float4* __restrict__ mrec,
-                               float4* __restrict__ mk)
+                               float4* __restrict__ mk, int* __restrict__ mslot)
 {
     constexpr int MW = mk_width(DEG);
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -668,6 +668,7 @@ __global__ void k_scatter_keys(int64_t I, const int* __restrict__ mcell, const i
     const int64_t pos = (int64_t)mstart[mcell[i]] + mrank[i];
 #pragma unroll
     for (int k = 0; k < MW; ++k) mk[MW * pos + k] = mrec[MW * i + k];
+    mslot[i] = (int)pos;
 }
 
 // ------------------------------------------------------------ query binning
@@ -967,7 +968,7 @@ struct KeyQ<2> {
 
 template <int DEG>
 struct TileSmem {
-    static constexpr int NF = DEG == 2 ? 16 : 8;  // flush slots per key
+    static constexpr int NF = flush_slots(DEG);  // flush slots per key
     static constexpr int NQ = DEG == 2 ? KC : 1;
     union {
         struct {
@@ -1400,7 +1401,7 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem<DEG>& S, co
                                  (float)(((double)b0.y - oy) + (double)b2.y),
                                  (float)(((double)b0.z - oz) + (double)b2.z), b0.w);
                 kv = b1;
-                kid = -(__float_as_int(b2.w) + 1);
+                kid = (int)(-slot - 1);  // the record: moved gradients accumulate by record
             }
             S.kc[tid] = kc;
             S.kv[tid] = kv;
@@ -1760,11 +1761,18 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem<DEG>& S, co
                                : (sl < 3 + NV ? L.mval + (sl - 3) : (sl == 3 + NV ? L.mrho : -1));
                 }
                 if (c >= 0 && x != 0.0f) {
-                    const int64_t v = mv ? (int64_t)(-tg - 1) : (int64_t)tg;
-                    if (a.gfix)
+                    if (a.gfix) {
+                        // fixed point by vertex (the moved record carries its vertex)
+                        const int64_t v = mv ? (int64_t)__float_as_int(a.mk[MW * (int64_t)(-tg - 1) + 2].w)
+                                             : (int64_t)tg;
                         atomicAdd(a.gfix + v * L.nch + c, fixq(x, a.det->dscale[c]));
-                    else
-                        unsafeAtomicAdd(a.grad + v * L.nch + c, x);
+                    } else if (mv) {
+                        // consecutive kept moved keys are consecutive records:
+                        // their slots share cache lines
+                        unsafeAtomicAdd(a.gslot + (int64_t)(-tg - 1) * NF + sl, x);
+                    } else {
+                        unsafeAtomicAdd(a.grad + (int64_t)tg * L.nch + c, x);
+                    }
                 }
             }
         }
@@ -1998,10 +2006,14 @@ __device__ __forceinline__ void fallback_run(const TileArgs& a)
                                   dx * dy, dx * dz, dy * dz};
                 const bool mv = vid < 0;
                 const int64_t v = mv ? -vid - 1 : vid;
-                // one channel of this key: float atomic, or fixed point (deterministic mode)
+                // one channel of this key: fixed point by vertex (deterministic
+                // mode), else a float atomic into grad, or for a moved key into
+                // its record's slots (slot = channel - first moved channel)
                 auto add = [&](int c, float x) {
                     if (a.gfix)
                         atomicAdd(a.gfix + v * L.nch + c, fixq(x, a.det->dscale[c]));
+                    else if (mv)
+                        unsafeAtomicAdd(a.gslot + (ka - ng) * flush_slots(DEG) + (c - L.mdel), x);
                     else
                         unsafeAtomicAdd(a.grad + v * L.nch + c, x);
                 };
@@ -2034,6 +2046,42 @@ __global__ __launch_bounds__(FB_BLOCK) void k_fallback_batch(const TileArgs* __r
         const TileArgs a = tab[s];
         fallback_run<MODE_FIT, false, DEG>(a);
     }
+}
+
+// Moved keys' gradient records (binned order, flush slots) added to grad
+// at their vertices, and cleared.  Every vertex has one moved key, so no two
+// records meet.
+template <int DEG>
+__device__ __forceinline__ void slot_finalize(const TileArgs& a, int64_t p)
+{
+    constexpr int MW = mk_width(DEG), NF = flush_slots(DEG);
+    const int64_t v = __float_as_int(a.mk[MW * p + 2].w);
+    const int nm = a.L.nch - a.L.mdel;  // moved channels: Delta, values, rho'
+    float* g = a.gslot + p * NF;
+    float* d = a.grad + v * a.L.nch + a.L.mdel;
+    for (int sl = 0; sl < nm; ++sl) {
+        const float x = g[sl];
+        if (x != 0.0f) {
+            d[sl] += x;
+            g[sl] = 0.0f;
+        }
+    }
+}
+
+template <int DEG>
+__global__ void k_slot_finalize(TileArgs a)
+{
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < a.I; p += (int64_t)gridDim.x * blockDim.x)
+        slot_finalize<DEG>(a, p);
+}
+
+template <int DEG>
+__global__ void k_slot_finalize_batch(const TileArgs* __restrict__ tab)
+{
+    const TileArgs& a = tab[blockIdx.y];
+    if (!a.offsets || a.gfix) return;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < a.I; p += (int64_t)gridDim.x * blockDim.x)
+        slot_finalize<DEG>(a, p);
 }
 
 __global__ void k_count_uncertified(const DevStats* st, int64_t* out)
@@ -2088,6 +2136,34 @@ __global__ void k_adam(float* __restrict__ theta, float* __restrict__ m, float* 
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const float gi = grad[i];
+        const float mi = fmaf(b1, m[i], (1.0f - b1) * gi);
+        const float vi = fmaf(b2, v[i], (1.0f - b2) * gi * gi);
+        const float th = theta[i];
+        m[i] = mi;
+        v[i] = vi;
+        theta[i] = th - lr * wd * th - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+        grad[i] = 0.0f;
+    }
+}
+
+// The fit step's AdamW (same arithmetic as k_adam): the gradient of a moved
+// channel is grad plus its slot in the vertex's record in gslot (the record
+// the binning placed the key at, mslot); both are cleared.  n = nch I < 2^32.
+__global__ void k_adam_fit(float* __restrict__ theta, float* __restrict__ m, float* __restrict__ v,
+                           float* __restrict__ grad, float* __restrict__ gslot, const int* __restrict__ mslot,
+                           int64_t n, int nch, int mdel, int nfl, float lr, float b1, float b2, float eps,
+                           float wd, float bc1, float bc2)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        float gi = grad[i];
+        const uint32_t vx = (uint32_t)i / (uint32_t)nch;
+        const int c = (int)((uint32_t)i - vx * (uint32_t)nch);
+        if (c >= mdel) {
+            float* gs = gslot + (int64_t)mslot[vx] * nfl + (c - mdel);
+            gi += *gs;
+            *gs = 0.0f;
+        }
         const float mi = fmaf(b1, m[i], (1.0f - b1) * gi);
         const float vi = fmaf(b2, v[i], (1.0f - b2) * gi * gi);
         const float th = theta[i];
@@ -2367,9 +2443,9 @@ hipError_t run_front(const Work& w, const Problem& p, Mode mode, bool ordered, h
             else
                 k_det_gather_keys<1><<<grid_for(I), BLOCK, 0, s>>>(sorted, I, w.mrec, w.mk);
         } else if (p.L.degree == 2) {
-            k_scatter_keys<2><<<grid_for(I), BLOCK, 0, s>>>(I, w.mcell, w.mrank, w.mstart, w.mrec, w.mk);
+            k_scatter_keys<2><<<grid_for(I), BLOCK, 0, s>>>(I, w.mcell, w.mrank, w.mstart, w.mrec, w.mk, w.mslot);
         } else {
-            k_scatter_keys<1><<<grid_for(I), BLOCK, 0, s>>>(I, w.mcell, w.mrank, w.mstart, w.mrec, w.mk);
+            k_scatter_keys<1><<<grid_for(I), BLOCK, 0, s>>>(I, w.mcell, w.mrank, w.mstart, w.mrec, w.mk, w.mslot);
         }
     }
     k_window<<<1, 64, 0, s>>>(w.st, g, p.T, p.window);
@@ -2445,6 +2521,7 @@ TileArgs make_tile_args(const Work& w, const Problem& p, bool ordered)
     a.lse_out = p.lse_out;
     a.dOdq_out = p.dOdq_out;
     a.grad = p.grad;
+    a.gslot = w.gslot;
     a.I = w.I;
     a.gfix = w.det ? w.gfix : nullptr;
     a.det = w.det;
@@ -2495,6 +2572,10 @@ hipError_t run_tiles(const Work& w, const Problem& p, Mode mode, hipStream_t s)
     case 2: launch_tiles<2>(a, mode, p.dOdq_out != nullptr, (unsigned)grid, fgrid, p.ev_stop, s); break;
     default: launch_tiles<1>(a, mode, p.dOdq_out != nullptr, (unsigned)grid, fgrid, p.ev_stop, s);
     }
+    if (mode != MODE_EVAL && !p.defer_slots) {
+        hipError_t e2 = run_slot_finalize(a, s);
+        if (e2 != hipSuccess) return e2;
+    }
     if (w.det && mode != MODE_EVAL) {
         const int64_t n = (int64_t)p.L.nch * w.I;
         k_det_finalize<<<grid_for(n, BLOCK * 8), BLOCK, 0, s>>>(w.gfix, w.det, p.L.nch, n, p.grad);
@@ -2520,6 +2601,7 @@ static void launch_batch(const TileArgs* tab, int S, const int2* gtiles, const i
     k_tile_batch<DEG><<<grid, BLOCK, 0, s>>>(tab, gtiles, ngt, gqueue);
     if (ev_stop) (void)hipEventRecord(ev_stop, s);
     k_fallback_batch<DEG><<<fgrid, FB_BLOCK, 0, s>>>(tab, S);
+    k_slot_finalize_batch<DEG == 2 ? 2 : 1><<<dim3(256, S), BLOCK, 0, s>>>(tab);
 }
 
 hipError_t run_batch_tiles(int degree, const TileArgs* tab, int S, const int2* gtiles, const int* ngt,
@@ -2562,6 +2644,15 @@ hipError_t run_loss_finalize(const Work& w, int64_t J, double* loss_out, hipStre
     return hipGetLastError();
 }
 
+hipError_t run_adam_fit(const Work& w, const Layout& L, float* theta, float* m, float* v, float lr,
+                        float beta1, float beta2, float eps, float wd, float bc1, float bc2, hipStream_t s)
+{
+    const int64_t n = (int64_t)L.nch * w.I;
+    k_adam_fit<<<grid_for(n, BLOCK * 4), BLOCK, 0, s>>>(theta, m, v, w.grad, w.gslot, w.mslot, n, L.nch, L.mdel,
+                                                      flush_slots(L.degree), lr, beta1, beta2, eps, wd, bc1, bc2);
+    return hipGetLastError();
+}
+
 hipError_t run_adam(const Work& w, float* theta, float* m, float* v, int64_t n, float lr,
                     float beta1, float beta2, float eps, float wd, float bc1, float bc2,
                     hipStream_t s)
@@ -2591,6 +2682,17 @@ __global__ void k_lattice(float* __restrict__ t, int R, double lo, double hi)
 hipError_t run_lattice(float* t, int R, double lo, double hi, hipStream_t s)
 {
     k_lattice<<<1, BLOCK, 0, s>>>(t, R, lo, hi);
+    return hipGetLastError();
+}
+
+hipError_t run_slot_finalize(const TileArgs& a, hipStream_t s)
+{
+    if (!a.offsets || a.gfix) return hipSuccess;
+    const unsigned grid = grid_for(a.I, BLOCK * 4);
+    switch (a.L.degree) {
+    case 2: k_slot_finalize<2><<<grid, BLOCK, 0, s>>>(a); break;
+    default: k_slot_finalize<1><<<grid, BLOCK, 0, s>>>(a);
+    }
     return hipGetLastError();
 }
 
