@@ -161,6 +161,7 @@ size_t carve_work(const efunc_config& cfg, const Layout& layout, int64_t max_poi
     k.take(w.scan_blk, nblk + 1);
     k.take(w.grad, (int64_t)layout.nch * I);
     k.take(w.gslot, layout.moved ? (int64_t)flush_slots(layout.degree) * I : 1);
+    k.take(w.gslotg, layout.grid ? (int64_t)flush_slots(layout.degree) * I : 1);
     k.take(w.st, 1);
     // deterministic mode: radix-sort buffers and fixed-point accumulators
     w.rs_k[0] = w.rs_k[1] = w.rs_v[0] = w.rs_v[1] = nullptr;
@@ -346,9 +347,9 @@ int fit_step_impl(efunc_ctx* ctx, float* theta, float* m, float* v, int64_t step
     p.q = q;
     p.aux = o;
     p.grad = ctx->w.grad;
-    // moved keys' records stay in gslot for the AdamW below (not in
-    // deterministic mode, whose gradient goes to grad by vertex)
-    const bool slots = ctx->layout.moved && !ctx->w.det;
+    // the keys' gradient records stay in gslotg / gslot for the AdamW below
+    // (not in deterministic mode, whose gradient goes to grad by vertex)
+    const bool slots = !ctx->w.det;
     p.defer_slots = slots ? 1 : 0;
     hipError_t e = run_tiles(ctx->w, p, MODE_FIT, s);
     if (e == hipSuccess && loss_out) e = run_loss_finalize(ctx->w, J, loss_out, s);
@@ -444,6 +445,8 @@ int efunc_fit_step_static(const efunc_config* cfg, float* theta, float* m, float
     if (e == hipSuccess) e = run_zero_floats(ctx.w.grad, n_params(&ctx), s);
     if (e == hipSuccess && layout.moved)
         e = run_zero_floats(ctx.w.gslot, (int64_t)flush_slots(layout.degree) * ctx.w.I, s);
+    if (e == hipSuccess && layout.grid)
+        e = run_zero_floats(ctx.w.gslotg, (int64_t)flush_slots(layout.degree) * ctx.w.I, s);
     if (e != hipSuccess) return hip_fail(e, "static scratch set-up");
     return fit_step_impl(&ctx, theta, m, v, step, adam, q, o, J, loss_out, stream);
 }
@@ -532,6 +535,8 @@ int efunc_create(const efunc_config* cfg, int64_t max_points, efunc_ctx** out)
     if (e == hipSuccess) e = hipMemset(w.grad, 0, sizeof(float) * layout.nch * w.I);
     if (e == hipSuccess && layout.moved)
         e = hipMemset(w.gslot, 0, sizeof(float) * flush_slots(layout.degree) * w.I);
+    if (e == hipSuccess && layout.grid)
+        e = hipMemset(w.gslotg, 0, sizeof(float) * flush_slots(layout.degree) * w.I);
     if (e == hipSuccess && w.gfix) e = hipMemset(w.gfix, 0, sizeof(unsigned long long) * layout.nch * w.I);
     if (e == hipSuccess) e = hipMemset(w.st, 0, sizeof(DevStats));
     if (e == hipSuccess) e = hipDeviceSynchronize();

@@ -139,6 +139,7 @@ struct Work {
     int* scan_blk;        // [ceil(max(8 NB3 PSPLIT, 128 SLICE_KEYS nch) / SCAN_TILE) + 1] scan block sums
     float* grad;          // [nch I] internal gradient of efunc_fit_step (kept zero)
     float* gslot;         // [nfl I] moved keys' gradient by binned record, flush-slot order (kept zero)
+    float* gslotg;        // [nfl I] grid keys' gradient by vertex, flush-slot order (kept zero)
     // deterministic mode only (else null): stable radix sorts of the query and
     // moved-key sort keys, fixed-point gradient accumulators
     int* rs_k[2];         // [rs_n] sort keys, ping-pong
@@ -207,6 +208,7 @@ struct TileArgs {
     float* dOdq_out;
     float* grad;
     float* gslot;  // moved keys' gradient by binned record (see Work)
+    float* gslotg; // grid keys' gradient by vertex (see Work)
     int64_t I;
     // deterministic mode (else null): fixed-point gradient and loss sums
     unsigned long long* gfix;
@@ -255,8 +257,8 @@ hipError_t run_loss_finalize(const Work& w, int64_t J, double* loss_out, hipStre
 hipError_t run_adam(const Work& w, float* theta, float* m, float* v, int64_t n, float lr,
                     float beta1, float beta2, float eps, float wd, float bc1, float bc2,
                     hipStream_t s);
-// AdamW of the fit step on theta [I][nch], the moved channels' gradient
-// taken from grad plus the vertex's record in gslot (both cleared).
+// AdamW of the fit step on theta [I][nch], each channel's gradient taken
+// from grad plus its key's record slot in gslotg / gslot (all cleared).
 hipError_t run_adam_fit(const Work& w, const Layout& L, float* theta, float* m, float* v, float lr,
                         float beta1, float beta2, float eps, float wd, float bc1, float bc2, hipStream_t s);
 hipError_t run_init_params(const Work& w, const Geo& g, const Layout& L, float* theta,

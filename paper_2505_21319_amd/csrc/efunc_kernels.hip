@@ -1771,7 +1771,8 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem<DEG>& S, co
                         // their slots share cache lines
                         unsafeAtomicAdd(a.gslot + (int64_t)(-tg - 1) * NF + sl, x);
                     } else {
-                        unsafeAtomicAdd(a.grad + (int64_t)tg * L.nch + c, x);
+                        // grid key: its vertex's record (slot = channel)
+                        unsafeAtomicAdd(a.gslotg + (int64_t)tg * NF + sl, x);
                     }
                 }
             }
@@ -2015,7 +2016,7 @@ __device__ __forceinline__ void fallback_run(const TileArgs& a)
                     else if (mv)
                         unsafeAtomicAdd(a.gslot + (ka - ng) * flush_slots(DEG) + (c - L.mdel), x);
                     else
-                        unsafeAtomicAdd(a.grad + v * L.nch + c, x);
+                        unsafeAtomicAdd(a.gslotg + v * flush_slots(DEG) + c, x);
                 };
                 const int vo = mv ? L.mval : L.gval, ro = mv ? L.mrho : L.grho;
 #pragma unroll
@@ -2055,17 +2056,21 @@ template <int DEG>
 __device__ __forceinline__ void slot_finalize(const TileArgs& a, int64_t p)
 {
     constexpr int MW = mk_width(DEG), NF = flush_slots(DEG);
-    const int64_t v = __float_as_int(a.mk[MW * p + 2].w);
-    const int nm = a.L.nch - a.L.mdel;  // moved channels: Delta, values, rho'
-    float* g = a.gslot + p * NF;
-    float* d = a.grad + v * a.L.nch + a.L.mdel;
-    for (int sl = 0; sl < nm; ++sl) {
-        const float x = g[sl];
-        if (x != 0.0f) {
-            d[sl] += x;
-            g[sl] = 0.0f;
+    auto add = [&](float* g, float* d, int n) {
+        for (int sl = 0; sl < n; ++sl) {
+            const float x = g[sl];
+            if (x != 0.0f) {
+                d[sl] += x;
+                g[sl] = 0.0f;
+            }
         }
+    };
+    if (a.offsets) {  // moved key of record p: Delta, values, rho'
+        const int64_t v = __float_as_int(a.mk[MW * p + 2].w);
+        add(a.gslot + p * NF, a.grad + v * a.L.nch + a.L.mdel, a.L.nch - a.L.mdel);
     }
+    if (a.L.grid)  // grid key of vertex p: values, rho
+        add(a.gslotg + p * NF, a.grad + p * a.L.nch, a.L.moved ? a.L.mdel : a.L.nch);
 }
 
 template <int DEG>
@@ -2079,7 +2084,7 @@ template <int DEG>
 __global__ void k_slot_finalize_batch(const TileArgs* __restrict__ tab)
 {
     const TileArgs& a = tab[blockIdx.y];
-    if (!a.offsets || a.gfix) return;
+    if (a.gfix) return;
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < a.I; p += (int64_t)gridDim.x * blockDim.x)
         slot_finalize<DEG>(a, p);
 }
@@ -2146,24 +2151,24 @@ __global__ void k_adam(float* __restrict__ theta, float* __restrict__ m, float* 
     }
 }
 
-// The fit step's AdamW (same arithmetic as k_adam): the gradient of a moved
-// channel is grad plus its slot in the vertex's record in gslot (the record
-// the binning placed the key at, mslot); both are cleared.  n = nch I < 2^32.
+// The fit step's AdamW (same arithmetic as k_adam): the gradient of a
+// channel is grad plus its slot in its key's record, for a grid channel
+// (c < ngrid) the vertex's record in gslotg, for a moved one the record the
+// binning gave the vertex's moved key (mslot) in gslot; all are cleared.
+// n = nch I < 2^32.
 __global__ void k_adam_fit(float* __restrict__ theta, float* __restrict__ m, float* __restrict__ v,
-                           float* __restrict__ grad, float* __restrict__ gslot, const int* __restrict__ mslot,
-                           int64_t n, int nch, int mdel, int nfl, float lr, float b1, float b2, float eps,
-                           float wd, float bc1, float bc2)
+                           float* __restrict__ grad, float* __restrict__ gslotg, float* __restrict__ gslot,
+                           const int* __restrict__ mslot, int64_t n, int nch, int ngrid, int nfl, float lr,
+                           float b1, float b2, float eps, float wd, float bc1, float bc2)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         float gi = grad[i];
         const uint32_t vx = (uint32_t)i / (uint32_t)nch;
         const int c = (int)((uint32_t)i - vx * (uint32_t)nch);
-        if (c >= mdel) {
-            float* gs = gslot + (int64_t)mslot[vx] * nfl + (c - mdel);
-            gi += *gs;
-            *gs = 0.0f;
-        }
+        float* gs = c < ngrid ? gslotg + (int64_t)vx * nfl + c : gslot + (int64_t)mslot[vx] * nfl + (c - ngrid);
+        gi += *gs;
+        *gs = 0.0f;
         const float mi = fmaf(b1, m[i], (1.0f - b1) * gi);
         const float vi = fmaf(b2, v[i], (1.0f - b2) * gi * gi);
         const float th = theta[i];
@@ -2522,6 +2527,7 @@ TileArgs make_tile_args(const Work& w, const Problem& p, bool ordered)
     a.dOdq_out = p.dOdq_out;
     a.grad = p.grad;
     a.gslot = w.gslot;
+    a.gslotg = w.gslotg;
     a.I = w.I;
     a.gfix = w.det ? w.gfix : nullptr;
     a.det = w.det;
@@ -2648,8 +2654,10 @@ hipError_t run_adam_fit(const Work& w, const Layout& L, float* theta, float* m, 
                         float beta1, float beta2, float eps, float wd, float bc1, float bc2, hipStream_t s)
 {
     const int64_t n = (int64_t)L.nch * w.I;
-    k_adam_fit<<<grid_for(n, BLOCK * 4), BLOCK, 0, s>>>(theta, m, v, w.grad, w.gslot, w.mslot, n, L.nch, L.mdel,
-                                                      flush_slots(L.degree), lr, beta1, beta2, eps, wd, bc1, bc2);
+    const int ngrid = L.moved ? L.mdel : L.nch;  // grid channels come first
+    k_adam_fit<<<grid_for(n, BLOCK * 4), BLOCK, 0, s>>>(theta, m, v, w.grad, w.gslotg, w.gslot, w.mslot, n, L.nch,
+                                                      ngrid, flush_slots(L.degree), lr, beta1, beta2, eps, wd, bc1,
+                                                      bc2);
     return hipGetLastError();
 }
 
@@ -2687,7 +2695,7 @@ hipError_t run_lattice(float* t, int R, double lo, double hi, hipStream_t s)
 
 hipError_t run_slot_finalize(const TileArgs& a, hipStream_t s)
 {
-    if (!a.offsets || a.gfix) return hipSuccess;
+    if (a.gfix) return hipSuccess;
     const unsigned grid = grid_for(a.I, BLOCK * 4);
     switch (a.L.degree) {
     case 2: k_slot_finalize<2><<<grid, BLOCK, 0, s>>>(a); break;
