@@ -56,17 +56,19 @@ static_assert(sizeof(DevStats) == 4 * 128 + 512, "DevStats layout");
 // atomicMax / atomicMin over ordered encodings), the fixed-point scales of
 // the gradient channels and of the fallback loss sums derived from them, and
 // the fallback loss accumulators.
+// Workgroups of the deterministic-mode bounds kernels: each writes one
+// record of its maxima, reduced by one workgroup afterwards (device atomics
+// on a handful of addresses from every wave serialise at one L2 channel).
+constexpr int DET_PARTS = 1024;
+constexpr int DET_NF = 12;  // floats per record
+
 struct DetStats {
-    unsigned int omax_bits;    // max |value coefficient o| over keys
-    unsigned int d1max_bits;   // max sum_k |d_k| over keys
-    unsigned int dinf_bits;    // max |d_k| over keys and axes
-    unsigned int sabs_bits;    // max sum of |quadratic coefficients| over keys
-    unsigned int bmax_bits;    // max beta over keys
-    unsigned int amax_bits;    // max |target| (fit) or |dL/dO| (grad) over queries
-    unsigned int Omax_bits;    // max |O| over the given outputs (grad)
-    unsigned int lo_enc[3];    // ordered encodings of the smallest query / key-centre coordinate
-    unsigned int hi_enc[3];    // and of the largest
-    int pad0[19];
+    // keys, per workgroup: max |o|, max sum_k |d_k|, max |d_k|, max sum of
+    // |quadratic coefficients|, max beta, min / max key-centre coordinate (3 + 3)
+    float kpart[DET_PARTS][DET_NF];
+    // queries, per workgroup: max |target| (fit) or |dL/dO| (grad), max |O|
+    // of the given outputs (grad), min / max query coordinate (3 + 3)
+    float qpart[DET_PARTS][DET_NF];
     double dscale[32];         // per channel: gradient units per fixed-point count (a power of 2)
     double lscale[2];          // fallback MSE and L1 sums
     unsigned long long fbfix[2];

@@ -240,57 +240,40 @@ __global__ void k_det_gather_keys(const int* __restrict__ sorted, int64_t I, con
     for (int t = 0; t < MW; ++t) mk[MW * p + t] = mrec[MW * v + t];
 }
 
-// Order-preserving unsigned encoding of a float (for atomicMin / atomicMax).
-__device__ __forceinline__ unsigned int fenc(float f)
-{
-    const unsigned int b = __float_as_uint(f);
-    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
-}
-__device__ __forceinline__ float fdec(unsigned int e)
-{
-    return __uint_as_float((e & 0x80000000u) ? (e & 0x7fffffffu) : ~e);
-}
-
 __global__ void k_det_reset(DetStats* det)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    det->omax_bits = det->d1max_bits = det->dinf_bits = det->sabs_bits = det->bmax_bits = 0u;
-    det->amax_bits = det->Omax_bits = 0u;
-    for (int d = 0; d < 3; ++d) {
-        det->lo_enc[d] = 0xffffffffu;
-        det->hi_enc[d] = 0u;
-    }
     det->fbfix[0] = det->fbfix[1] = 0ull;
 }
 
-// Wave maxima of non-negative floats, one device atomic per wave.
-__device__ __forceinline__ void wave_atomic_max(unsigned int* dst, float v)
+// Workgroups of a bounds kernel over n elements (grid-stride beyond that).
+static inline unsigned det_blocks(int64_t n)
 {
-    v = wave_max(v);
-    if ((threadIdx.x & 63) == 0 && v > 0.0f) atomicMax(dst, __float_as_uint(v));
+    const int64_t b = (n + BLOCK - 1) / BLOCK;
+    return (unsigned)(b < 1 ? 1 : (b > DET_PARTS ? DET_PARTS : b));
 }
-__device__ __forceinline__ void wave_atomic_range(unsigned int* lo, unsigned int* hi, float vmin, float vmax)
+
+// The workgroup's maxima of v[0..nmax) and minima of v[nmax..nf) into rec.
+template <int NF>
+__device__ __forceinline__ void det_record(float (&v)[NF], int nmax, float* __restrict__ rec, float* sh)
 {
-    vmin = -wave_max(-vmin);
-    vmax = wave_max(vmax);
-    if ((threadIdx.x & 63) == 0) {
-        if (vmin <= vmax) {
-            atomicMin(lo, fenc(vmin));
-            atomicMax(hi, fenc(vmax));
-        }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        const float r = f < nmax ? block_max(v[f], sh) : -block_max(-v[f], sh);
+        if (threadIdx.x == 0) rec[f] = r;
     }
 }
 
 // Bounds over the keys: value, slope and curvature magnitudes, scales and
-// the box of the key centres.
+// the box of the key centres (record: om d1 di sa bm cmax[3] | cmin[3]).
 template <int DEG>
 __global__ __launch_bounds__(BLOCK) void k_det_bounds_keys(const float* __restrict__ theta, Geo g, Layout L,
                                                           int64_t I, DetStats* __restrict__ det)
 {
-    const int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
-    float om = 0.0f, d1 = 0.0f, di = 0.0f, sa = 0.0f, bm = 0.0f;
-    float cmin[3] = {INFINITY, INFINITY, INFINITY}, cmax[3] = {-INFINITY, -INFINITY, -INFINITY};
-    if (i < I) {
+    __shared__ float sh[BLOCK / 64];
+    float v[11] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, -INFINITY, -INFINITY, -INFINITY, INFINITY, INFINITY, INFINITY};
+    float &om = v[0], &d1 = v[1], &di = v[2], &sa = v[3], &bm = v[4];
+    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < I; i += (int64_t)gridDim.x * BLOCK) {
         const float* p = theta + i * L.nch;
         const int R = g.R;
         const int ix = (int)(i / ((int64_t)R * R)), iy = (int)((i / R) % R), iz = (int)(i % R);
@@ -315,8 +298,8 @@ __global__ __launch_bounds__(BLOCK) void k_det_bounds_keys(const float* __restri
             values(L.gval);
             bm = fmaxf(bm, L.learn ? expf(p[L.grho]) : expf(L.rho_fixed));
             for (int d = 0; d < 3; ++d) {
-                cmin[d] = fminf(cmin[d], t[d]);
-                cmax[d] = fmaxf(cmax[d], t[d]);
+                v[5 + d] = fmaxf(v[5 + d], t[d]);
+                v[8 + d] = fminf(v[8 + d], t[d]);
             }
         }
         if (L.moved) {
@@ -324,36 +307,33 @@ __global__ __launch_bounds__(BLOCK) void k_det_bounds_keys(const float* __restri
             bm = fmaxf(bm, L.learn ? expf(p[L.mrho]) : expf(L.rho_fixed));
             for (int d = 0; d < 3; ++d) {
                 const float c = t[d] + p[L.mdel + d];
-                cmin[d] = fminf(cmin[d], c);
-                cmax[d] = fmaxf(cmax[d], c);
+                v[5 + d] = fmaxf(v[5 + d], c);
+                v[8 + d] = fminf(v[8 + d], c);
             }
         }
     }
-    wave_atomic_max(&det->omax_bits, om);
-    wave_atomic_max(&det->d1max_bits, d1);
-    wave_atomic_max(&det->dinf_bits, di);
-    wave_atomic_max(&det->sabs_bits, sa);
-    wave_atomic_max(&det->bmax_bits, bm);
-    for (int d = 0; d < 3; ++d) wave_atomic_range(&det->lo_enc[d], &det->hi_enc[d], cmin[d], cmax[d]);
+    det_record(v, 8, det->kpart[blockIdx.x], sh);
 }
 
-// Bounds over the queries: their box, max |target or dL/dO| and max |O|.
+// Bounds over the queries: max |target or dL/dO|, max |O| and their box
+// (record: am Om qmax[3] | qmin[3]).
 __global__ __launch_bounds__(BLOCK) void k_det_bounds_queries(const float* __restrict__ q, int64_t J,
                                                              const float* __restrict__ aux,
                                                              const float* __restrict__ Oin,
                                                              DetStats* __restrict__ det)
 {
-    const int64_t j = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
-    float am = 0.0f, Om = 0.0f;
-    float qmin[3] = {INFINITY, INFINITY, INFINITY}, qmax[3] = {-INFINITY, -INFINITY, -INFINITY};
-    if (j < J) {
-        for (int d = 0; d < 3; ++d) qmin[d] = qmax[d] = q[3 * j + d];
-        if (aux) am = fabsf(aux[j]);
-        if (Oin) Om = fabsf(Oin[j]);
+    __shared__ float sh[BLOCK / 64];
+    float v[8] = {0.0f, 0.0f, -INFINITY, -INFINITY, -INFINITY, INFINITY, INFINITY, INFINITY};
+    for (int64_t j = blockIdx.x * (int64_t)BLOCK + threadIdx.x; j < J; j += (int64_t)gridDim.x * BLOCK) {
+        for (int d = 0; d < 3; ++d) {
+            const float c = q[3 * j + d];
+            v[2 + d] = fmaxf(v[2 + d], c);
+            v[5 + d] = fminf(v[5 + d], c);
+        }
+        if (aux) v[0] = fmaxf(v[0], fabsf(aux[j]));
+        if (Oin) v[1] = fmaxf(v[1], fabsf(Oin[j]));
     }
-    wave_atomic_max(&det->amax_bits, am);
-    wave_atomic_max(&det->Omax_bits, Om);
-    for (int d = 0; d < 3; ++d) wave_atomic_range(&det->lo_enc[d], &det->hi_enc[d], qmin[d], qmax[d]);
+    det_record(v, 5, det->qpart[blockIdx.x], sh);
 }
 
 // Fixed-point scales (one thread).  With X the largest coordinate
@@ -367,19 +347,41 @@ __global__ __launch_bounds__(BLOCK) void k_det_bounds_queries(const float* __res
 // Each channel counts in units of 2^-(61 - e) with 2^e above its bound, so
 // no partial sum leaves the int64 range and the sum is exact integer
 // arithmetic, independent of the order of the atomics.
-__global__ void k_det_scales(DetStats* __restrict__ det, Layout L, int fit, int64_t J)
+__global__ __launch_bounds__(BLOCK) void k_det_scales(DetStats* __restrict__ det, Layout L, int fit, int64_t J,
+                                                     int nk, int nq)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    // the records of the two bounds kernels reduced by this workgroup
+    __shared__ float sh[BLOCK / 64];
+    auto kmax = [&](int f) {
+        float m = -INFINITY;
+        for (int b = threadIdx.x; b < nk; b += BLOCK) m = fmaxf(m, det->kpart[b][f]);
+        return block_max(m, sh);
+    };
+    auto qmax = [&](int f) {
+        float m = -INFINITY;
+        for (int b = threadIdx.x; b < nq; b += BLOCK) m = fmaxf(m, det->qpart[b][f]);
+        return block_max(m, sh);
+    };
+    auto kmin = [&](int f) {
+        float m = -INFINITY;
+        for (int b = threadIdx.x; b < nk; b += BLOCK) m = fmaxf(m, -det->kpart[b][f]);
+        return -block_max(m, sh);
+    };
+    auto qmin = [&](int f) {
+        float m = -INFINITY;
+        for (int b = threadIdx.x; b < nq; b += BLOCK) m = fmaxf(m, -det->qpart[b][f]);
+        return -block_max(m, sh);
+    };
+    const double om = kmax(0), d1 = kmax(1), di = kmax(2), sa = kmax(3), bm = kmax(4);
+    const double am = qmax(0), Om = qmax(1);
+    // X: the largest coordinate difference over query and key-centre coordinates
     double X = 0.0;
     for (int d = 0; d < 3; ++d) {
-        const double lo = fdec(det->lo_enc[d]), hi = fdec(det->hi_enc[d]);
+        const double hi = fmaxf(kmax(5 + d), qmax(2 + d)), lo = fminf(kmin(8 + d), qmin(5 + d));
         if (hi >= lo) X = fmax(X, hi - lo);
     }
+    if (threadIdx.x != 0) return;
     X = X * (1.0 + 1e-6) + 1e-30;
-    const double om = __uint_as_float(det->omax_bits), d1 = __uint_as_float(det->d1max_bits);
-    const double di = __uint_as_float(det->dinf_bits), sa = __uint_as_float(det->sabs_bits);
-    const double bm = __uint_as_float(det->bmax_bits), am = __uint_as_float(det->amax_bits);
-    const double Om = __uint_as_float(det->Omax_bits);
     const double F = om + d1 * X + sa * X * X;
     const double G1 = fit ? 2.0 * (F + am) : (double)J * am;
     const double D = fit ? 2.0 * F : F + Om;
@@ -2414,12 +2416,13 @@ hipError_t run_front(const Work& w, const Problem& p, Mode mode, bool ordered, h
         k_det_reset<<<1, 64, 0, s>>>(w.det);
         if (mode != MODE_EVAL) {
             switch (p.L.degree) {
-            case 0: k_det_bounds_keys<0><<<grid_for(I), BLOCK, 0, s>>>(p.theta, g, p.L, I, w.det); break;
-            case 2: k_det_bounds_keys<2><<<grid_for(I), BLOCK, 0, s>>>(p.theta, g, p.L, I, w.det); break;
-            default: k_det_bounds_keys<1><<<grid_for(I), BLOCK, 0, s>>>(p.theta, g, p.L, I, w.det);
+            case 0: k_det_bounds_keys<0><<<det_blocks(I), BLOCK, 0, s>>>(p.theta, g, p.L, I, w.det); break;
+            case 2: k_det_bounds_keys<2><<<det_blocks(I), BLOCK, 0, s>>>(p.theta, g, p.L, I, w.det); break;
+            default: k_det_bounds_keys<1><<<det_blocks(I), BLOCK, 0, s>>>(p.theta, g, p.L, I, w.det);
             }
-            k_det_bounds_queries<<<grid_for(J), BLOCK, 0, s>>>(p.q, J, p.aux, p.O_in, w.det);
-            k_det_scales<<<1, 64, 0, s>>>(w.det, p.L, mode == MODE_FIT ? 1 : 0, J);
+            k_det_bounds_queries<<<det_blocks(J), BLOCK, 0, s>>>(p.q, J, p.aux, p.O_in, w.det);
+            k_det_scales<<<1, BLOCK, 0, s>>>(w.det, p.L, mode == MODE_FIT ? 1 : 0, J, (int)det_blocks(I),
+                                             (int)det_blocks(J));
         }
     }
     // keys

@@ -86,8 +86,8 @@ __device__ __forceinline__ int64_t neighbour(int64_t b, int z, int y, int x, int
 }
 
 // floor(k / c) by a multiply-high with r = ceil(2^20 / c), exact for
-// 0 <= k < 4096 when 1 <= c <= 64 and for 0 <= k < 288 when c <= 256 (the
-// error term k (r c - 2^20) / (c 2^20) stays below 1/c; checked exhaustively).
+// 0 <= k < 4096 when 1 <= c <= 256 (the error term k (r c - 2^20) / (c 2^20)
+// stays below 1/c - frac(k / c); checked exhaustively).
 __device__ __forceinline__ int small_div(int k, uint32_t r) { return (int)(((uint32_t)k * r) >> 20); }
 static inline uint32_t small_div_r(int c) { return (uint32_t)(((1u << 20) + (uint32_t)c - 1u) / (uint32_t)c); }
 
@@ -183,6 +183,101 @@ __device__ __forceinline__ void conv_epilogue(f32x4 (&acc)[CONV_MB][NT], int64_t
     }
 }
 
+constexpr int EP_LD = MAXC + 8;                           // LDS row stride of the epilogue's transpose (bf16)
+constexpr int EP_WAVE_BYTES = 16 * CONV_MB * EP_LD * 2;  // one wave's 64 voxel rows
+constexpr int EP_BYTES = EP_WAVE_BYTES * (CONV_BLOCK / 64);
+
+// The epilogue for bf16 outputs with ycs % 8 == 0, through a wave-private
+// LDS tile of 64 voxel rows (ep, EP_WAVE_BYTES): the mask tile comes in and
+// the channels-last output goes out as whole 16-byte chunks of voxel rows,
+// where the register layout of the accumulators (one channel, four voxels
+// per lane) would make every element its own 2-byte access.  Neighbouring
+// lanes hold neighbouring channels: one DPP exchange pairs them into
+// 4-byte LDS writes.  yT, whose 32-voxel runs per channel match the
+// register layout, is written from the registers as in conv_epilogue.
+template <int NT>
+__device__ __forceinline__ void conv_epilogue_lds(f32x4 (&acc)[CONV_MB][NT], int64_t vw, int lane, int Cout, int ycs,
+                                                  const float* __restrict__ bias, int relu,
+                                                  const u16* __restrict__ mask, int64_t V, u16* __restrict__ ybf,
+                                                  u16* __restrict__ yT, char* __restrict__ ep)
+{
+    const int row = lane & 15, kq = lane >> 4;
+    const int nc = ycs >> 3;               // 16-byte chunks per voxel row (<= 8)
+    const int c8 = lane & 7, vsub = lane >> 3;  // chunk c8 of rows vsub + 8 k
+    u16* sh = reinterpret_cast<u16*>(ep);
+    uint32_t mk[NT][CONV_MB];  // bit r: the mask of voxel 16 m + 4 kq + r at channel 16 t + row is > 0
+    if (mask) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int vv = vsub + 8 * k;
+            u32x4 mv = u32x4{0u, 0u, 0u, 0u};
+            if (c8 < nc && vw + vv < V) mv = *reinterpret_cast<const u32x4*>(mask + (vw + vv) * ycs + 8 * c8);
+            if (c8 < nc) *reinterpret_cast<u32x4*>(sh + vv * EP_LD + 8 * c8) = mv;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int co = t * 16 + row;  // < 64 <= EP_LD: inside the row
+#pragma unroll
+            for (int m = 0; m < CONV_MB; ++m) {
+                uint32_t b = 0u;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) b |= (bf2f(sh[(16 * m + 4 * kq + r) * EP_LD + co]) > 0.0f ? 1u : 0u) << r;
+                mk[t][m] = b;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    const bool odd = row & 1;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int co = t * 16 + row;
+        const float bb = bias && co < Cout ? bias[co] : 0.0f;  // channels >= Cout hold zeros
+#pragma unroll
+        for (int m = 0; m < CONV_MB; ++m) {
+            const int64_t v0 = vw + 16 * m + 4 * kq;
+            uint32_t hv[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float val = acc[m][t][r] + bb;
+                if (relu) val = fmaxf(val, 0.0f);
+                if (mask && !((mk[t][m] >> r) & 1u)) val = 0.0f;
+                hv[r] = f2bf(val);
+            }
+            if (yT && co < Cout) {
+                u16* dst = yT + tidx(co, v0, Cout);  // v0 .. v0 + 3 share a 32-voxel block
+                if (v0 + 4 <= V) {
+                    *reinterpret_cast<u32x2*>(dst) = u32x2{hv[0] | (hv[1] << 16), hv[2] | (hv[3] << 16)};
+                } else {
+                    for (int r = 0; v0 + r < V; ++r) dst[r] = (u16)hv[r];
+                }
+            }
+            // even lanes: channels (co, co + 1) of voxels 0, 1; odd lanes: (co - 1, co) of voxels 2, 3
+            const uint32_t send = odd ? (hv[0] | (hv[1] << 16)) : (hv[2] | (hv[3] << 16));
+            const uint32_t recv = (uint32_t)__builtin_amdgcn_mov_dpp((int)send, 0xB1, 0xF, 0xF, false);  // lane ^ 1
+            const uint32_t w0 = odd ? ((recv & 0xffffu) | (hv[2] << 16)) : (hv[0] | (recv << 16));
+            const uint32_t w1 = odd ? ((recv >> 16) | (hv[3] << 16)) : (hv[1] | (recv & 0xffff0000u));
+            const int vr = 16 * m + 4 * kq + (odd ? 2 : 0);
+            *reinterpret_cast<uint32_t*>(sh + vr * EP_LD + (co & ~1)) = w0;
+            *reinterpret_cast<uint32_t*>(sh + (vr + 1) * EP_LD + (co & ~1)) = w1;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int vv = vsub + 8 * k;
+        if (c8 < nc && vw + vv < V)
+            *reinterpret_cast<u32x4*>(ybf + (vw + vv) * ycs + 8 * c8) =
+                *reinterpret_cast<const u32x4*>(sh + vv * EP_LD + 8 * c8);
+    }
+}
+
 // y[v][co] = sum_{tap, ci} x[nbr(v, tap)][ci] w[co][tap Cin + ci] (+ bias,
 // ReLU) or, for the data gradient, times (mask[v][co] > 0).  A wave computes
 // 64 voxels x 16 NT output channels (Cout <= 16 NT): CONV_MB x NT MFMA tiles.
@@ -207,6 +302,7 @@ __global__ __launch_bounds__(CONV_BLOCK, 2) void k_conv(const u16* __restrict__ 
                                                      u16* __restrict__ yT, uint32_t rcin)
 {
     __shared__ __attribute__((aligned(16))) u16 sw[2][MAXC * SW_LD];  // all 64 rows: unguarded stores
+    __shared__ __attribute__((aligned(16))) char ep[EP_BYTES];         // the epilogue's transpose
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int row = lane & 15, kq = lane >> 4;
     const int64_t vw = ((int64_t)xcd_block(blockIdx.x, gridDim.x) * (CONV_BLOCK / 64) + wv) * (16 * CONV_MB);
@@ -338,135 +434,202 @@ __global__ __launch_bounds__(CONV_BLOCK, 2) void k_conv(const u16* __restrict__ 
         wstore((blk + 1) & 1, (blk + 1) * CONV_KB, wr);
     }
     if (vw >= V) return;
-    conv_epilogue<NT>(acc, vw, row, kq, Cout, ycs, bias, relu, mask, V, ybf, yf, yT);
+    if (!yf && ycs % 8 == 0)
+        conv_epilogue_lds<NT>(acc, vw, lane, Cout, ycs, bias, relu, mask, V, ybf, yT, ep + wv * EP_WAVE_BYTES);
+    else
+        conv_epilogue<NT>(acc, vw, row, kq, Cout, ycs, bias, relu, mask, V, ybf, yf, yT);
 }
 
 constexpr int ST_ROWS = 16 * CONV_MB * (CONV_BLOCK / 64) + 2;  // staged voxel rows: 256 + the two edges
 constexpr int SA_LD = 32 + 8;                                  // LDS row stride of a staged row (bf16)
 constexpr int SB_LD = 3 * 32 + 8;                              // LDS row stride of the staged weights
+constexpr uint32_t OOB = 0x80000000u;                          // buffer offset past every range: reads zero
+
+// Raw buffer resource over nbytes at p (stride 0): a load whose offset lies
+// past nbytes returns zero and touches no memory.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* p, uint32_t nbytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)nbytes, 0x00020000);
+}
+
+__device__ __forceinline__ u32x4 buffer_load16(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
 
 // k_conv for Cin % 32 == 0 with the activations staged through LDS.  For one
 // (dz, dy) pair, the neighbour rows of the workgroup's 256 consecutive
 // voxels are one contiguous range of voxels shifted by the pair's offset,
 // plus one row on either side for dx = -1 / +1.  Each step -- a pair and a
 // 32-channel slice -- copies those 258 rows and the slice's weights of the
-// pair's three taps into LDS with coalesced 16-byte loads (double buffered:
-// the next step's loads are in flight during this step's MFMAs), then every
-// wave reads its A fragments for the three taps as rows r - 1, r, r + 1.
-// A row whose neighbour at that tap lies outside the lattice is zeroed by
-// the voxel's own 27-bit mask (rows outside [0, V) are read clamped).
+// pair's three taps into LDS with 16-byte buffer loads; every wave then
+// reads its A fragments for the three taps as rows r - 1, r, r + 1.
+//
+// Staged row k is the dx = +1, 0, -1 neighbour of voxels k - 2, k - 1, k
+// (workgroup-relative), which share voxel k - 1's (y, z) except across a row
+// end, where the x test below rejects the tap anyway.  So a row whose voxel
+// k - 1 lies outside the lattice, or whose (y + dy, z + dz) does, is loaded
+// from an out-of-range buffer offset and reads as zero (as are weight rows
+// co >= Cout); the x test of a fragment selects its LDS address, the row
+// itself or an all-zero row kept past the staged ones.  All per-thread
+// offsets are fixed for the kernel: a step adds one uniform offset.  Loads
+// run two steps ahead (two register sets), so a load's latency is covered
+// by two steps of MFMAs.
 template <int NT>
 __global__ __launch_bounds__(CONV_BLOCK, 2) void k_conv4(const u16* __restrict__ x, int Cin,
                                                          const u16* __restrict__ w, int Kpad, int Cout,
                                                          const float* __restrict__ bias, int relu,
-                                                         const u16* __restrict__ mask, int D, int64_t V,
-                                                         u16* __restrict__ ybf, float* __restrict__ yf, int ycs,
-                                                         u16* __restrict__ yT)
+                                                         const u16* __restrict__ mask, int D, uint32_t rd,
+                                                         int64_t V, u16* __restrict__ ybf, float* __restrict__ yf,
+                                                         int ycs, u16* __restrict__ yT)
 {
-    __shared__ __attribute__((aligned(16))) u16 sa[2][ST_ROWS * SA_LD];
-    __shared__ __attribute__((aligned(16))) u16 sb[2][MAXC * SB_LD];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    constexpr int SA_ROWS = ST_ROWS + 1;  // + the zero row
+    constexpr int SA_BYTES = SA_ROWS * SA_LD * 2;
+    constexpr int SB_BYTES = MAXC * SB_LD * 2;
+    __shared__ __attribute__((aligned(16))) char sa[2 * SA_BYTES];
+    __shared__ __attribute__((aligned(16))) char sb[2 * SB_BYTES];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int row = lane & 15, kq = lane >> 4;
     const int64_t vg = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (16 * CONV_MB * (CONV_BLOCK / 64));
-    const int64_t vw = vg + wv * (16 * CONV_MB);
-    const int64_t D3 = (int64_t)D * D * D;
-    uint32_t nmask[CONV_MB];
+    const int64_t D2 = (int64_t)D * D;
+    // lattice coordinates of the workgroup's first voxel; the others are
+    // reached by small offsets (small_div is exact below 4096 for D <= 256)
+    const int x0 = (int)(vg % D), y0 = (int)((vg / D) % D), z0 = (int)((vg / D2) % D);
+    // (y, z) of workgroup-relative voxel l, -1 <= l < 512
+    auto yz = [&](int l, int& y, int& z) {
+        const int tx = x0 + l + D;                    // x + D, >= 0
+        const int yy = y0 + small_div(tx, rd) - 1 + D;  // y + D before the wrap into z, >= 0
+        const int qz = small_div(yy, rd);
+        y = yy - qz * D;
+        const int zz = z0 + qz - 1 + D;               // z + D, >= 0
+        z = zz - small_div(zz, rd) * D;
+    };
+    // A fragment addresses (bytes within a staged buffer) per row tile and x-offset
+    uint32_t aoff[CONV_MB][3];
 #pragma unroll
     for (int m = 0; m < CONV_MB; ++m) {
-        const int64_t va = vw + 16 * m + row;
-        nmask[m] = 0u;
-        if (va < V) {
-            const int64_t bb = va / D3;
-            const int rr = (int)(va - bb * D3);
-            const int z = rr / (D * D), y = (rr / D) % D, xx = rr % D;
-            const uint32_t mz = (z > 0 ? 1u : 0u) | 2u | (z < D - 1 ? 4u : 0u);
-            const uint32_t my = (y > 0 ? 1u : 0u) | 2u | (y < D - 1 ? 4u : 0u);
-            const uint32_t mx = (xx > 0 ? 1u : 0u) | 2u | (xx < D - 1 ? 4u : 0u);
+        const int l = wv * (16 * CONV_MB) + 16 * m + row;  // = its dx = -1 neighbour's staged row
+        const int xa = x0 + l;
+        const int xx = xa - small_div(xa, rd) * D;
 #pragma unroll
-            for (int t = 0; t < 27; ++t)
-                nmask[m] |= ((mz >> (t / 9)) & (my >> ((t / 3) % 3)) & (mx >> (t % 3)) & 1u) << t;
+        for (int d = 0; d < 3; ++d) {
+            const bool ok = d == 1 || (d == 0 ? xx > 0 : xx < D - 1);
+            aoff[m][d] = (uint32_t)(((ok ? l + d : ST_ROWS) * SA_LD + 8 * kq) * 2);
         }
     }
+    // activation rows through a buffer based at the lowest voxel any step
+    // reads, sized to the highest: every valid offset is in range, every
+    // OOB offset (plus a step's shift) is past it
+    const int64_t vbase = vg - D2 - D - 1 > 0 ? vg - D2 - D - 1 : 0;
+    int64_t vtop = vg + ST_ROWS + D2 + D;
+    vtop = vtop < V ? vtop : V;
+    const __amdgpu_buffer_rsrc_t ra_rs = buffer_rsrc(x + vbase * Cin, (uint32_t)((vtop - vbase) * Cin * 2));
+    const __amdgpu_buffer_rsrc_t rw_rs = buffer_rsrc(w, (uint32_t)((int64_t)Cout * Kpad * 2));
+    // thread t stages rows (t >> 2) + 64 j (j < 4) and, for t < 8, row 256 + (t >> 2);
+    // chunk t & 3 (8 channels) of each.  Bit p of pmask[j]: the row is
+    // valid for pair p (dz = p / 3 - 1, dy = p % 3 - 1)
+    constexpr int NA = 5;
+    static_assert(ST_ROWS == 258 && CONV_BLOCK == 256, "staging layout");
+    uint32_t abase[NA], pmask[NA];
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+        const int r = (t >> 2) + 64 * j;
+        const int64_t vk = vg + r - 1;
+        uint32_t pm = 0u;
+        if ((j < 4 || t < 8) && vk >= 0 && vk < V) {
+            int y, z;
+            yz(r - 1, y, z);
+#pragma unroll
+            for (int pr = 0; pr < 9; ++pr) {
+                const int zz = z + pr / 3 - 1, yy = y + pr % 3 - 1;
+                pm |= (zz >= 0 && zz < D && yy >= 0 && yy < D ? 1u : 0u) << pr;
+            }
+        }
+        pmask[j] = pm;
+        abase[j] = (uint32_t)(((vk - vbase) * Cin + 8 * (t & 3)) * 2);
+    }
+    // weights: thread t stages row co = t >> 2, chunk t & 3 of the three taps
+    const int wco = t >> 2;
+    const uint32_t wbase = wco < Cout ? (uint32_t)((wco * Kpad + 8 * (t & 3)) * 2) : OOB;
+    const uint32_t sta = (uint32_t)(((t >> 2) * SA_LD + 8 * (t & 3)) * 2);  // LDS byte offset of row t >> 2
+    const uint32_t stb = (uint32_t)((wco * SB_LD + 8 * (t & 3)) * 2);
     const int nslice = Cin / 32;
     const int nsteps = 9 * nslice;
-    // staging loads of step s into registers: 258 rows x 4 chunks of the
-    // activations (5 per thread, the last partial) and 64 rows x 12 chunks
-    // of the weights (3 per thread); all addresses in range
-    constexpr int NA = (ST_ROWS * 4 + CONV_BLOCK - 1) / CONV_BLOCK;
     auto sload = [&](int step, u32x4* ra, u32x4* rw) {
-        const int st = step < nsteps ? step : nsteps - 1;
-        const int pair = st / nslice, cs = st - pair * nslice;
-        const int64_t off = ((int64_t)(pair / 3 - 1) * D + (pair % 3 - 1)) * D;
+        const bool live = step < nsteps;
+        const int pair = live ? step / nslice : 0, cs = step - pair * nslice;
+        const uint32_t soff = (uint32_t)(((((pair / 3 - 1) * D2 + (pair % 3 - 1) * (int64_t)D) * Cin) + 32 * cs) * 2);
+        const uint32_t woff = (uint32_t)((3 * pair * Cin + 32 * cs) * 2);
 #pragma unroll
         for (int j = 0; j < NA; ++j) {
-            const int i = threadIdx.x + j * CONV_BLOCK;
-            const int r = i >> 2, c = i & 3;
-            int64_t u = vg + off - 1 + (r < ST_ROWS ? r : 0);
-            u = u < 0 ? 0 : (u >= V ? V - 1 : u);
-            ra[j] = *reinterpret_cast<const u32x4*>(x + u * Cin + 32 * cs + 8 * c);
+            const bool ok = live && ((pmask[j] >> pair) & 1u);
+            ra[j] = buffer_load16(ra_rs, ok ? abase[j] + soff : OOB);
         }
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const int i = threadIdx.x + j * CONV_BLOCK;
-            const int co = i / 12, c = i - co * 12;  // c: tap c / 4, chunk c % 4
-            const int coc = co < Cout ? co : Cout - 1;
-            const int k = (3 * pair + c / 4) * Cin + 32 * cs + 8 * (c % 4);
-            rw[j] = *reinterpret_cast<const u32x4*>(w + (int64_t)coc * Kpad + k);
-        }
+        for (int j = 0; j < 3; ++j) rw[j] = buffer_load16(rw_rs, live ? wbase + woff + (uint32_t)(j * Cin * 2) : OOB);
     };
     auto sstore = [&](int buf, const u32x4* ra, const u32x4* rw) {
+        char* A = sa + buf * SA_BYTES;
+        char* B = sb + buf * SB_BYTES;
 #pragma unroll
-        for (int j = 0; j < NA; ++j) {
-            const int i = threadIdx.x + j * CONV_BLOCK;
-            const int r = i >> 2, c = i & 3;
-            if (r < ST_ROWS) *reinterpret_cast<u32x4*>(&sa[buf][r * SA_LD + 8 * c]) = ra[j];
-        }
+        for (int j = 0; j < 4; ++j) *reinterpret_cast<u32x4*>(A + sta + j * 64 * SA_LD * 2) = ra[j];
+        if (t < 8) *reinterpret_cast<u32x4*>(A + sta + 4 * 64 * SA_LD * 2) = ra[4];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const int i = threadIdx.x + j * CONV_BLOCK;
-            const int co = i / 12, c = i - co * 12;
-            *reinterpret_cast<u32x4*>(&sb[buf][co * SB_LD + 32 * (c / 4) + 8 * (c % 4)]) =
-                co < Cout ? rw[j] : u32x4{0u, 0u, 0u, 0u};
-        }
+        for (int j = 0; j < 3; ++j) *reinterpret_cast<u32x4*>(B + stb + j * 64) = rw[j];
     };
+    // the zero rows of both buffers
+    if (t < 2 * 4)
+        *reinterpret_cast<u32x4*>(sa + (t >> 2) * SA_BYTES + (ST_ROWS * SA_LD + 8 * (t & 3)) * 2) =
+            u32x4{0u, 0u, 0u, 0u};
     f32x4 acc[CONV_MB][NT];
 #pragma unroll
     for (int m = 0; m < CONV_MB; ++m)
 #pragma unroll
-        for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    u32x4 ra[NA], rw[3];
-    sload(0, ra, rw);
-    sstore(0, ra, rw);
-    for (int step = 0; step < nsteps; ++step) {
-        __syncthreads();  // buffer step & 1 complete; the other one is free
-        sload(step + 1, ra, rw);  // in flight during this step's MFMAs (clamped past the end)
-        __builtin_amdgcn_sched_barrier(0);
-        const int pair = step / nslice;
-        const u16* A = sa[step & 1];
-        const u16* B = sb[step & 1];
+        for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const uint32_t boff = (uint32_t)((row * SB_LD + 8 * kq) * 2);
+    auto compute = [&](int buf) {
+        const char* A = sa + buf * SA_BYTES;
+        const char* B = sb + buf * SB_BYTES;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            const int tap = 3 * pair + d;
             u32x4 a[CONV_MB];
 #pragma unroll
-            for (int m = 0; m < CONV_MB; ++m) {
-                const int r = wv * (16 * CONV_MB) + 16 * m + row + d;  // staged row of voxel + dx, dx = d - 1
-                const u32x4 v = *reinterpret_cast<const u32x4*>(A + r * SA_LD + 8 * kq);
-                a[m] = ((nmask[m] >> tap) & 1u) ? v : u32x4{0u, 0u, 0u, 0u};
-            }
+            for (int m = 0; m < CONV_MB; ++m) a[m] = *reinterpret_cast<const u32x4*>(A + aoff[m][d]);
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const u32x4 rb = *reinterpret_cast<const u32x4*>(B + (t * 16 + row) * SB_LD + 32 * d + 8 * kq);
+            for (int n = 0; n < NT; ++n) {
+                const u32x4 rb = *reinterpret_cast<const u32x4*>(B + boff + (n * 16 * SB_LD + 32 * d) * 2);
 #pragma unroll
                 for (int m = 0; m < CONV_MB; ++m)
-                    acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a[m]), as_bf16x8(rb), acc[m][t],
+                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a[m]), as_bf16x8(rb), acc[m][n],
                                                                         0, 0, 0);
             }
         }
-        sstore((step + 1) & 1, ra, rw);
+    };
+    u32x4 ra0[NA], rw0[3], ra1[NA], rw1[3];
+    sload(0, ra0, rw0);
+    sload(1, ra1, rw1);
+    sstore(0, ra0, rw0);
+    for (int step = 0; step < nsteps; step += 2) {
+        __syncthreads();  // buffer 0 holds step `step`; every wave is done with buffer 1
+        sload(step + 2, ra0, rw0);  // two steps ahead (zero, no memory access, past the end)
+        __builtin_amdgcn_sched_barrier(0);
+        compute(0);
+        sstore(1, ra1, rw1);  // step + 1
+        if (step + 1 >= nsteps) break;
+        __syncthreads();
+        sload(step + 3, ra1, rw1);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(1);
+        sstore(0, ra0, rw0);  // step + 2
     }
+    const int64_t vw = vg + wv * (16 * CONV_MB);
+    __syncthreads();  // every wave is done with the staged rows: the epilogue reuses them
     if (vw >= V) return;
-    conv_epilogue<NT>(acc, vw, row, kq, Cout, ycs, bias, relu, mask, V, ybf, yf, yT);
+    static_assert(EP_BYTES <= 2 * SA_BYTES, "epilogue tile inside the staged rows");
+    if (!yf && ycs % 8 == 0)
+        conv_epilogue_lds<NT>(acc, vw, lane, Cout, ycs, bias, relu, mask, V, ybf, yT, sa + wv * EP_WAVE_BYTES);
+    else
+        conv_epilogue<NT>(acc, vw, row, kq, Cout, ycs, bias, relu, mask, V, ybf, yf, yT);
 }
 
 // dw[co][tap][ci] += sum_v dyT[co][v] xT[ci][nbr(v, tap)] from blocked
@@ -938,8 +1101,9 @@ hipError_t run_conv(const u16* x, int Cin, const u16* w, int Kp, int Cout, const
     const int64_t per_block = 16 * CONV_MB * (CONV_BLOCK / 64);
     const unsigned grid = (unsigned)((V + per_block - 1) / per_block);
     const int NT = (Cout + 15) / 16;
-    if (Cin % 32 == 0) {
-#define EFUNC_CONV4(N) k_conv4<N><<<grid, CONV_BLOCK, 0, s>>>(x, Cin, w, Kp, Cout, bias, relu, mask, D, V, ybf, yf, ycs, yT)
+    if (Cin % 32 == 0 && D <= 256) {
+#define EFUNC_CONV4(N) \
+    k_conv4<N><<<grid, CONV_BLOCK, 0, s>>>(x, Cin, w, Kp, Cout, bias, relu, mask, D, small_div_r(D), V, ybf, yf, ycs, yT)
         switch (NT) {
         case 1: EFUNC_CONV4(1); break;
         case 2: EFUNC_CONV4(2); break;

@@ -61,8 +61,12 @@ def test_blocked_layout_helpers_round_trip():
 
 
 @pytest.mark.parametrize("Cin,Cout,R,B", [(1, 32, 6, 2), (32, 64, 5, 3), (64, 13, 4, 2), (13, 64, 4, 1),
-                                           (8, 16, 7, 1), (64, 64, 8, 2), (32, 13, 16, 1)])
+                                           (8, 16, 7, 1), (64, 64, 8, 2), (32, 13, 16, 1), (32, 16, 13, 2),
+                                           (64, 32, 32, 1), (32, 8, 2, 3), (32, 4, 1, 5)])
 def test_conv_forward_matches_oracle(E, Cin, Cout, R, B):
+    """Cin % 32 == 0 runs the LDS-staged kernel: R = 1, 2, 4, 5 and 13 put
+    row, plane and shape ends inside one workgroup's 256 voxels (and R = 1
+    leaves only the centre tap), R = 32 is the network's lattice."""
     rng = np.random.default_rng(Cin * 100 + Cout)
     x = N.bf16_round(rng.standard_normal((B, R, R, R, Cin)))
     W = rng.standard_normal((Cout, 27, Cin)) / np.sqrt(27 * Cin)
