@@ -714,17 +714,21 @@ __global__ __launch_bounds__(64 * WG_WAVES) void k_conv_wgrad(const u16* __restr
 // slices and the same neighbour-row xT slice; the x-offsets -1 / +1 are
 // funnel shifts of that slice with the element before / after it (zero past
 // the row's ends).  One set of loads feeds 3 x MT x NT MFMAs, a third of the
-// operand traffic of a wave per tap.  Loads, validity and the two operand
-// sets as in k_conv_wgrad.  When db is given, the wave of the centre pair
+// operand traffic of a wave per tap.  Loads and validity as in
+// k_conv_wgrad; DEPTH operand sets keep DEPTH - 1 steps of loads in flight
+// behind the MFMAs of the current one (these waves run one per SIMD, so the
+// latency of the operand loads is covered by the pipeline alone).  When db is given, the wave of the centre pair
 // (dz = dy = 0), which reads every dyT slice of its chunk, also sums them:
 // db[co] += sum_v dyT[co][v].
-template <int MT, int NT, int WPC>
+template <int MT, int NT, int WPC, int DEPTH>
 __global__ __launch_bounds__(64 * WPC) void k_conv_wgrad3(const u16* __restrict__ xT, int Cin,
                                                            const u16* __restrict__ dyT, int Cout, int D, int64_t V,
                                                            int64_t chunk, uint32_t rd, float* __restrict__ dw,
                                                            float* __restrict__ db)
 {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // wv through readfirstlane: the wave's voxel range, and with it the buffer
+    // resources, are then known to be uniform (scalar registers)
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int row = lane & 15, kq = lane >> 4;
     const unsigned wg = xcd_block(blockIdx.x, gridDim.x);  // the nine pairs of a chunk: one XCD
     const int pair = (int)(wg % 9u);
@@ -735,19 +739,44 @@ __global__ __launch_bounds__(64 * WPC) void k_conv_wgrad3(const u16* __restrict_
     const int64_t cend = cbeg + chunk < V ? cbeg + chunk : V;
     const int64_t vbeg = cbeg + wv * part < cend ? cbeg + wv * part : cend;
     const int64_t vend = vbeg + part < cend ? vbeg + part : cend;
-    int coc[MT], cic[NT];
-    uint32_t cobits = 0u, cibits = 0u;
+    // Operands through raw buffer loads based at the wave's first block:
+    // every per-lane offset is fixed and a 32-voxel step adds one block;
+    // channels past Cout / Cin, slices past the wave's range and neighbour
+    // slices outside the lattice read as zero from an out-of-range offset.
+    const int64_t ab = vbeg >> 5;                       // dyT block of the first slice
+    const int64_t nblk = (V + 31) >> 5;
+    const int64_t off = ((int64_t)dz * D + dyo) * D;    // the pair's neighbour shift (a multiple of 8)
+    int64_t bb = (vbeg + off - 1) >> 5;                 // lowest xT block a valid load touches
+    bb = bb < 0 ? 0 : bb;
+    // bytes in range from a base block; none when the base lies past the end
+    // (a wave near the end whose neighbour plane is beyond the lattice): a
+    // negative count cast to 32 bits would honour every "out-of-range" offset
+    auto nrec = [](int64_t bytes) { return (uint32_t)(bytes <= 0 ? 0 : (bytes < 0x7fffffff ? bytes : 0x7fffffff)); };
+    const __amdgpu_buffer_rsrc_t rsa = buffer_rsrc(dyT + ab * Cout * 32, nrec((nblk - ab) * Cout * 64));
+    const __amdgpu_buffer_rsrc_t rsb = buffer_rsrc(xT + bb * Cin * 32, nrec((nblk - bb) * Cin * 64));
+    const uint32_t blka = (uint32_t)Cout * 64, blkb = (uint32_t)Cin * 64;  // bytes per 32-voxel block
+    uint32_t aoff[MT], boff[NT], eloff[NT], eroff[NT];
+    {
+        const int64_t v = vbeg + 8 * kq;  // this lane's first slice
+        const int64_t nb = v + off;       // its neighbour slice (loaded only where it is valid)
+        // byte offset from the base block, modulo 2^32: a slice that starts
+        // before the buffer is never loaded, and one step later its offset
+        // has grown by a block like every other
+        auto rel = [&](int c, int64_t u, int C, int64_t base) {
+            return (uint32_t)((tidx(c, u, C) - base * C * 32) * 2);
+        };
 #pragma unroll
-    for (int m = 0; m < MT; ++m) {
-        const int co = 16 * m + row;
-        coc[m] = co < Cout ? co : Cout - 1;
-        cobits |= (co < Cout ? 1u : 0u) << m;
-    }
+        for (int m = 0; m < MT; ++m) {
+            const int co = 16 * m + row;
+            aoff[m] = co < Cout ? rel(co, v, Cout, ab) : OOB;
+        }
 #pragma unroll
-    for (int n = 0; n < NT; ++n) {
-        const int ci = 16 * n + row;
-        cic[n] = ci < Cin ? ci : Cin - 1;
-        cibits |= (ci < Cin ? 1u : 0u) << n;
+        for (int n = 0; n < NT; ++n) {
+            const int ci = 16 * n + row;
+            boff[n] = ci < Cin ? rel(ci, nb, Cin, bb) : OOB;
+            eloff[n] = ci < Cin ? rel(ci, nb - 1, Cin, bb) : OOB;
+            eroff[n] = ci < Cin ? rel(ci, nb + 8, Cin, bb) : OOB;
+        }
     }
     f32x4 acc[3][MT][NT];
 #pragma unroll
@@ -771,16 +800,14 @@ __global__ __launch_bounds__(64 * WPC) void k_conv_wgrad3(const u16* __restrict_
     struct Ops {
         u32x4 a[MT], b[NT];
         uint32_t el[NT], er[NT];
-        int n;
-        uint32_t ok, okl, okr;
     };
+    uint32_t step = 0;  // slices issued so far
     auto issue = [&](int64_t vb, Ops& o) {
-        const int64_t v = vb + 8 * kq;
-        const bool live = v < vend;
-        const int64_t vs = live ? v : cbeg;  // cbeg < V: an in-range slice
-        o.n = live ? 8 : 0;  // V % 8 == 0: a live slice is whole
+        const bool live = vb + 8 * kq < vend;
+        const uint32_t sa = step * blka, sb = step * blkb;
+        ++step;
 #pragma unroll
-        for (int m = 0; m < MT; ++m) o.a[m] = *reinterpret_cast<const u32x4*>(dyT + tidx(coc[m], vs, Cout));
+        for (int m = 0; m < MT; ++m) o.a[m] = buffer_load16(rsa, live ? aoff[m] + sa : OOB);
         const int x0 = lx, y = ly, z = lz;
         const int xs = lx + 32;
         const int q = small_div(xs, rd);
@@ -790,38 +817,27 @@ __global__ __launch_bounds__(64 * WPC) void k_conv_wgrad3(const u16* __restrict_
         ly = ys - q2 * D;
         lz = lz + q2 >= D ? lz + q2 - D : lz + q2;
         const bool ok = live && y + dyo >= 0 && y + dyo < D && z + dz >= 0 && z + dz < D;
-        const int64_t nb = ok ? v + ((int64_t)dz * D + dyo) * D : vs;
         const bool okl = ok && x0 > 0, okr = ok && x0 + 8 < D;
-        const int64_t nl = okl ? nb - 1 : nb, nr = okr ? nb + 8 : nb;
-        o.ok = ok ? 1u : 0u;
-        o.okl = okl ? 1u : 0u;
-        o.okr = okr ? 1u : 0u;
 #pragma unroll
         for (int n = 0; n < NT; ++n) {
-            o.b[n] = *reinterpret_cast<const u32x4*>(xT + tidx(cic[n], nb, Cin));
-            o.el[n] = xT[tidx(cic[n], nl, Cin)];
-            o.er[n] = xT[tidx(cic[n], nr, Cin)];
+            o.b[n] = buffer_load16(rsb, ok ? boff[n] + sb : OOB);
+            o.el[n] = __builtin_amdgcn_raw_buffer_load_b16(rsb, okl ? eloff[n] + sb : OOB, 0, 0);
+            o.er[n] = __builtin_amdgcn_raw_buffer_load_b16(rsb, okr ? eroff[n] + sb : OOB, 0, 0);
         }
     };
-    auto mma = [&](Ops& o) {
-#pragma unroll
-        for (int m = 0; m < MT; ++m)
-            o.a[m] = keep_first_n((cobits >> m) & 1u ? o.a[m] : u32x4{0u, 0u, 0u, 0u}, o.n);
-        u32x4 w[NT];
-#pragma unroll
-        for (int n = 0; n < NT; ++n) w[n] = ((cibits >> n) & 1u) && o.ok ? o.b[n] : u32x4{0u, 0u, 0u, 0u};
+    auto mma = [&](const Ops& o) {
         // dx = 0
 #pragma unroll
         for (int m = 0; m < MT; ++m)
 #pragma unroll
             for (int n = 0; n < NT; ++n)
-                acc[1][m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(o.a[m]), as_bf16x8(w[n]), acc[1][m][n],
+                acc[1][m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(o.a[m]), as_bf16x8(o.b[n]), acc[1][m][n],
                                                                        0, 0, 0);
         // dx = -1: element i is the slice's element i - 1
 #pragma unroll
         for (int n = 0; n < NT; ++n) {
-            const uint32_t e = o.okl ? (o.el[n] & 0xffffu) : 0u;
-            const u32x4 t = w[n];
+            const uint32_t e = o.el[n] & 0xffffu;
+            const u32x4 t = o.b[n];
             const u32x4 b = {e | (t[0] << 16), (t[0] >> 16) | (t[1] << 16), (t[1] >> 16) | (t[2] << 16),
                              (t[2] >> 16) | (t[3] << 16)};
 #pragma unroll
@@ -832,8 +848,8 @@ __global__ __launch_bounds__(64 * WPC) void k_conv_wgrad3(const u16* __restrict_
         // dx = +1: element i is the slice's element i + 1
 #pragma unroll
         for (int n = 0; n < NT; ++n) {
-            const uint32_t e = o.okr ? (o.er[n] & 0xffffu) : 0u;
-            const u32x4 t = w[n];
+            const uint32_t e = o.er[n] & 0xffffu;
+            const u32x4 t = o.b[n];
             const u32x4 b = {(t[0] >> 16) | (t[1] << 16), (t[1] >> 16) | (t[2] << 16), (t[2] >> 16) | (t[3] << 16),
                              (t[3] >> 16) | (e << 16)};
 #pragma unroll
@@ -849,15 +865,18 @@ __global__ __launch_bounds__(64 * WPC) void k_conv_wgrad3(const u16* __restrict_
                     bsum[m] += __uint_as_float(o.a[m][j] << 16) + __uint_as_float(o.a[m][j] & 0xffff0000u);
         }
     };
-    Ops o0, o1;
-    issue(vbeg, o0);
-    for (int64_t vb = vbeg; vb < vend; vb += 64) {
-        issue(vb + 32, o1);
-        __builtin_amdgcn_sched_barrier(0);
-        mma(o0);
-        issue(vb + 64, o0);
-        __builtin_amdgcn_sched_barrier(0);
-        mma(o1);
+    // DEPTH operand sets: the loads of step s + DEPTH - 1 are issued before
+    // the MFMAs of step s (slices past the wave's range read as zero)
+    Ops o[DEPTH];
+#pragma unroll
+    for (int k = 0; k < DEPTH - 1; ++k) issue(vbeg + 32 * k, o[k]);
+    for (int64_t vb = vbeg; vb < vend; vb += 32 * DEPTH) {
+#pragma unroll
+        for (int k = 0; k < DEPTH; ++k) {
+            issue(vb + 32 * (k + DEPTH - 1), o[(k + DEPTH - 1) % DEPTH]);
+            __builtin_amdgcn_sched_barrier(0);
+            mma(o[k]);
+        }
     }
     if (WPC > 1) {
         // partial sums of waves 1 .. WPC-1 into LDS, added by wave 0
@@ -1134,7 +1153,8 @@ static void launch_wgrad3(dim3 grid, hipStream_t s, const u16* xT, int Cin, cons
                           int64_t V, int64_t chunk, uint32_t rd, float* dw, float* db)
 {
     constexpr int W = M * N <= 2 ? 4 : 1;
-    k_conv_wgrad3<M, N, W><<<grid, 64 * W, 0, s>>>(xT, Cin, dyT, Cout, D, V, chunk, rd, dw, db);
+    constexpr int DEPTH = M * N >= 16 ? 3 : (M * N >= 8 ? 4 : 8);  // operand sets in flight, within 512 registers
+    k_conv_wgrad3<M, N, W, DEPTH><<<grid, 64 * W, 0, s>>>(xT, Cin, dyT, Cout, D, V, chunk, rd, dw, db);
 }
 
 template <bool R8>
