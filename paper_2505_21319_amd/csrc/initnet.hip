@@ -1001,20 +1001,23 @@ __global__ void k_to_bf16(const float* __restrict__ a, int64_t n, u16* __restric
 }
 
 // a [V][C] fp32 -> out [V][Cp] bf16 (channels C..Cp-1 zero) and the
-// blocked channel-major copy outT (tidx).
-__global__ void k_to_bf16_both(const float* __restrict__ a, int64_t V, int C, int Cp, u16* __restrict__ out,
-                               u16* __restrict__ outT)
+// blocked channel-major copy outT (tidx).  One thread per voxel (C <= Cp <=
+// 64, Cp % 8 == 0): its row leaves as 16-byte stores, and for each channel
+// the wave's 64 consecutive voxels make one contiguous run of outT.
+__global__ __launch_bounds__(256) void k_to_bf16_both(const float* __restrict__ a, int64_t V, int C, int Cp,
+                                                      u16* __restrict__ out, u16* __restrict__ outT)
 {
-    const int64_t n = V * Cp;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t v = i / Cp;
-        const int c = (int)(i - v * Cp);
-        u16 h = 0;
-        if (c < C) {
-            h = f2bf(a[v * C + c]);
-            outT[tidx(c, v, C)] = h;
+    const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    for (int c0 = 0; c0 < Cp; c0 += 8) {
+        u16 h[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int c = c0 + i;
+            h[i] = c < C ? f2bf(a[v * C + c]) : (u16)0;
+            if (c < C) outT[tidx(c, v, C)] = h[i];
         }
-        out[i] = h;
+        *reinterpret_cast<u32x4*>(out + v * Cp + c0) = pack8(h);
     }
 }
 
@@ -1114,12 +1117,200 @@ static void launch_conv(int NT, unsigned grid, hipStream_t s, const u16* x, int 
 #undef EFUNC_CONV
 }
 
+// The forward of a one-channel input (the network's first layer): K = 27
+// fills one MFMA step to 27/32 and the gathered operand to one element per
+// voxel and tap, so it runs on the vector ALU instead: one thread per voxel
+// accumulates its Cout channels over the 27 neighbours (bf16 products are
+// exact in fp32, as on the matrix cores), with the packed weights in LDS as
+// fp32 (every lane reads the same address: broadcast).  Rows of y leave as
+// 16-byte stores; for each channel the wave's 64 consecutive voxels are one
+// contiguous run of yT.  Needs ycs % 8 == 0 and Cout <= ycs <= 64.
+template <int CO>
+__global__ __launch_bounds__(256) void k_conv_c1(const u16* __restrict__ x, const u16* __restrict__ w, int Kpad,
+                                                 int Cout, const float* __restrict__ bias, int relu, int D,
+                                                 uint32_t rd, int64_t V, u16* __restrict__ ybf, int ycs,
+                                                 u16* __restrict__ yT)
+{
+    __shared__ float sw[27][CO];
+    for (int i = threadIdx.x; i < 27 * CO; i += blockDim.x) {
+        const int tap = i / CO, co = i - tap * CO;
+        sw[tap][co] = co < Cout ? bf2f(w[(int64_t)co * Kpad + tap]) : 0.0f;
+    }
+    __syncthreads();
+    const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    const int64_t D2 = (int64_t)D * D;
+    const int xx = (int)(v % D), y = (int)((v / D) % D), z = (int)((v / D2) % D);
+    float acc[CO];
+#pragma unroll
+    for (int co = 0; co < CO; ++co) acc[co] = bias && co < Cout ? bias[co] : 0.0f;
+#pragma unroll 3
+    for (int tap = 0; tap < 27; ++tap) {  // not unrolled in full: the weights stay in LDS
+        const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+        const bool ok = z + dz >= 0 && z + dz < D && y + dy >= 0 && y + dy < D && xx + dx >= 0 && xx + dx < D;
+        const float xv = ok ? bf2f(x[v + (dz * D2 + dy * (int64_t)D + dx)]) : 0.0f;
+#pragma unroll
+        for (int c4 = 0; c4 < CO; c4 += 4) {
+            const float4 wv = *reinterpret_cast<const float4*>(&sw[tap][c4]);
+            acc[c4] = fmaf(wv.x, xv, acc[c4]);
+            acc[c4 + 1] = fmaf(wv.y, xv, acc[c4 + 1]);
+            acc[c4 + 2] = fmaf(wv.z, xv, acc[c4 + 2]);
+            acc[c4 + 3] = fmaf(wv.w, xv, acc[c4 + 3]);
+        }
+    }
+    (void)rd;
+#pragma unroll
+    for (int c0 = 0; c0 < CO; c0 += 8) {  // ycs <= CO
+        if (c0 >= ycs) break;
+        u16 h[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const float val = relu ? fmaxf(acc[c0 + i], 0.0f) : acc[c0 + i];
+            h[i] = c0 + i < Cout ? f2bf(val) : (u16)0;
+            if (yT && c0 + i < Cout) yT[tidx(c0 + i, v, Cout)] = h[i];
+        }
+        *reinterpret_cast<u32x4*>(ybf + v * ycs + c0) = pack8(h);
+    }
+}
+
+// Weight and bias gradient of a one-channel input, D % 8 == 0:
+// dw[co][tap] += sum_v dyT[co][v] x[nbr(v, tap)], db[co] += sum_v dyT[co][v].
+// The 27 taps are the MFMA's N (two 16-column tiles, taps 27..31 zero), the
+// output channels its M, 32 voxels its K.  Lane (row, kq) supplies the 8
+// voxels v .. v + 7 (one aligned slice of one x-row) of tap 16 n + row: the
+// slice of its (dz, dy) neighbour row, shifted by its dx with the element
+// before or after it (zero outside the lattice).  A wave covers WSTEPS
+// 32-voxel steps; the four waves of a workgroup add their sums in LDS, and
+// the workgroup adds them to dw / db.
+constexpr int C1_WSTEPS = 16;
+template <int MT>
+__global__ __launch_bounds__(256) void k_conv_wgrad_c1(const u16* __restrict__ x, const u16* __restrict__ dyT,
+                                                       int Cout, int D, uint32_t rd, int64_t V,
+                                                       float* __restrict__ dw, float* __restrict__ db)
+{
+    __shared__ float red[3][MT * 2 * 4 + MT][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int row = lane & 15, kq = lane >> 4;
+    const int64_t D2 = (int64_t)D * D;
+    const int64_t vbeg = ((int64_t)blockIdx.x * 4 + wv) * (32 * C1_WSTEPS);
+    f32x4 acc[MT][2];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) acc[m][0] = acc[m][1] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    float bsum[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) bsum[m] = 0.0f;
+    int tdz[2], tdy[2], tdx[2];
+    bool tok[2];
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+        const int tap = 16 * n + row;
+        tok[n] = tap < 27;
+        tdz[n] = tap / 9 - 1;
+        tdy[n] = (tap / 3) % 3 - 1;
+        tdx[n] = tap % 3 - 1;
+    }
+    for (int st = 0; st < C1_WSTEPS; ++st) {
+        const int64_t v = vbeg + 32 * st + 8 * kq;  // this lane's slice
+        if (vbeg + 32 * st >= V) break;             // uniform: V % 32 == 0 (D % 8 == 0)
+        const int x0 = (int)(v % D), y = (int)((v / D) % D), z = (int)((v / D2) % D);
+        u32x4 a[MT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            const int co = 16 * m + row;
+            a[m] = co < Cout ? *reinterpret_cast<const u32x4*>(dyT + tidx(co, v, Cout)) : u32x4{0u, 0u, 0u, 0u};
+            for (int j = 0; j < 4; ++j)
+                bsum[m] += __uint_as_float(a[m][j] << 16) + __uint_as_float(a[m][j] & 0xffff0000u);
+        }
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+            const bool ok = tok[n] && z + tdz[n] >= 0 && z + tdz[n] < D && y + tdy[n] >= 0 && y + tdy[n] < D;
+            const int64_t nb = v + tdz[n] * D2 + tdy[n] * (int64_t)D;  // the (dz, dy) neighbour slice
+            u32x4 t = u32x4{0u, 0u, 0u, 0u};
+            uint32_t e = 0u;
+            if (ok) {
+                t = *reinterpret_cast<const u32x4*>(x + nb);
+                if (tdx[n] < 0 && x0 > 0) e = x[nb - 1];
+                if (tdx[n] > 0 && x0 + 8 < D) e = x[nb + 8];
+            }
+            u32x4 b = t;
+            if (tdx[n] < 0)
+                b = u32x4{e | (t[0] << 16), (t[0] >> 16) | (t[1] << 16), (t[1] >> 16) | (t[2] << 16),
+                          (t[2] >> 16) | (t[3] << 16)};
+            else if (tdx[n] > 0)
+                b = u32x4{(t[0] >> 16) | (t[1] << 16), (t[1] >> 16) | (t[2] << 16), (t[2] >> 16) | (t[3] << 16),
+                          (t[3] >> 16) | (e << 16)};
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+                acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a[m]), as_bf16x8(b), acc[m][n], 0, 0, 0);
+        }
+    }
+    (void)rd;
+    // the workgroup's sum in wave 0
+    if (wv > 0) {
+        int k = 0;
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int n = 0; n < 2; ++n)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) red[wv - 1][k++][lane] = acc[m][n][r];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) red[wv - 1][k++][lane] = bsum[m];
+    }
+    __syncthreads();
+    if (wv > 0) return;
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+        int k = 0;
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int n = 0; n < 2; ++n)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[m][n][r] += red[w][k++][lane];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) bsum[m] += red[w][k++][lane];
+    }
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+            const int tap = 16 * n + row;
+            if (tap >= 27) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int co = 16 * m + 4 * kq + r;
+                if (co < Cout) unsafeAtomicAdd(&dw[(int64_t)co * 27 + tap], acc[m][n][r]);
+            }
+        }
+    if (db) {
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            float t = bsum[m];
+            t += __shfl_xor(t, 16, 64);
+            t += __shfl_xor(t, 32, 64);
+            const int co = 16 * m + row;
+            if (kq == 0 && co < Cout) unsafeAtomicAdd(&db[co], t);
+        }
+    }
+}
+
 hipError_t run_conv(const u16* x, int Cin, const u16* w, int Kp, int Cout, const float* bias, int relu,
                     const u16* mask, int D, int64_t V, u16* ybf, float* yf, int ycs, u16* yT, hipStream_t s)
 {
     const int64_t per_block = 16 * CONV_MB * (CONV_BLOCK / 64);
     const unsigned grid = (unsigned)((V + per_block - 1) / per_block);
     const int NT = (Cout + 15) / 16;
+    if (Cin == 1 && !mask && !yf && ybf && ycs % 8 == 0 && ycs <= MAXC) {
+        const unsigned g1 = (unsigned)((V + 255) / 256);
+        if (Cout <= 16)
+            k_conv_c1<16><<<g1, 256, 0, s>>>(x, w, Kp, Cout, bias, relu, D, small_div_r(D), V, ybf, ycs, yT);
+        else if (Cout <= 32)
+            k_conv_c1<32><<<g1, 256, 0, s>>>(x, w, Kp, Cout, bias, relu, D, small_div_r(D), V, ybf, ycs, yT);
+        else
+            k_conv_c1<64><<<g1, 256, 0, s>>>(x, w, Kp, Cout, bias, relu, D, small_div_r(D), V, ybf, ycs, yT);
+        return hipGetLastError();
+    }
     if (Cin % 32 == 0 && D <= 256) {
 #define EFUNC_CONV4(N) \
     k_conv4<N><<<grid, CONV_BLOCK, 0, s>>>(x, Cin, w, Kp, Cout, bias, relu, mask, D, small_div_r(D), V, ybf, yf, ycs, yT)
@@ -1190,6 +1381,17 @@ hipError_t run_wgrad(const u16* xT, int Cin, const u16* dyT, int Cout, int D, in
                      hipStream_t s)
 {
     const int MT = (Cout + 15) / 16, NT = (Cin + 15) / 16;
+    if (Cin == 1 && D % 8 == 0) {
+        // every element of x (one channel) is its own blocked copy
+        const unsigned g1 = (unsigned)((V + 4 * 32 * C1_WSTEPS - 1) / (4 * 32 * C1_WSTEPS));
+        switch (MT) {
+        case 1: k_conv_wgrad_c1<1><<<g1, 256, 0, s>>>(xT, dyT, Cout, D, small_div_r(D), V, dw, db); break;
+        case 2: k_conv_wgrad_c1<2><<<g1, 256, 0, s>>>(xT, dyT, Cout, D, small_div_r(D), V, dw, db); break;
+        case 3: k_conv_wgrad_c1<3><<<g1, 256, 0, s>>>(xT, dyT, Cout, D, small_div_r(D), V, dw, db); break;
+        default: k_conv_wgrad_c1<4><<<g1, 256, 0, s>>>(xT, dyT, Cout, D, small_div_r(D), V, dw, db); break;
+        }
+        return hipGetLastError();
+    }
     if (D % 8 == 0) {
         // about 111 chunks x 9 pairs (measured at 32^3 x 8: 64, 111, 222 and
         // 888 chunks take 0.91, 0.83, 0.92 and 1.15 ms for the whole
@@ -1370,7 +1572,7 @@ int efunc_initnet_backward(efunc_initnet* n, const float* dout, int32_t B, float
     hipStream_t s = (hipStream_t)stream;
     const int64_t V = n->V1 * B;
     const int L = n->L;
-    k_to_bf16_both<<<blocks_for(V * n->cs[L], 256), 256, 0, s>>>(dout, V, n->ch[L], n->cs[L], n->gbuf[0], n->gT[0]);
+    k_to_bf16_both<<<(unsigned)((V + 255) / 256), 256, 0, s>>>(dout, V, n->ch[L], n->cs[L], n->gbuf[0], n->gT[0]);
     hipError_t e = hipGetLastError();
     int cur = 0;
     for (int l = L - 1; l >= 0 && e == hipSuccess; --l) {
