@@ -632,6 +632,183 @@ __global__ __launch_bounds__(CONV_BLOCK, 2) void k_conv4(const u16* __restrict__
         conv_epilogue<NT>(acc, vw, row, kq, Cout, ycs, bias, relu, mask, V, ybf, yf, yT);
 }
 
+constexpr int C9_WAVES = 8;
+constexpr int C9_BLOCK = 64 * C9_WAVES;              // 512 threads
+constexpr int C9_VOX = 16 * CONV_MB * C9_WAVES;      // 512 voxels per workgroup
+constexpr int C9_DMAX = 128;                         // lattice sizes this kernel takes
+constexpr int C9_SMAX = C9_VOX + 2 * C9_DMAX + 2;    // staged rows of a dz segment at most
+constexpr int C9_WLD = 9 * 32 + 8;                   // LDS row stride of the staged weights (bf16)
+constexpr int C9_ABYTES = (C9_SMAX + 1) * SA_LD * 2; // + the zero row
+constexpr int C9_WBYTES = MAXC * C9_WLD * 2;
+constexpr int C9_NA = (4 * C9_SMAX + C9_BLOCK - 1) / C9_BLOCK;  // row chunks per thread
+constexpr int C9_NW = (MAXC * 36 + C9_BLOCK - 1) / C9_BLOCK;     // weight chunks per thread
+
+// k_conv for Cin % 32 == 0 and D <= 128, a workgroup of 512 voxels (8
+// waves of 64 x 16 NT).  A step is one z-offset dz and one 32-channel
+// slice: the neighbour rows of all nine (dy, dx) taps of that dz are one
+// contiguous voxel range, vg + dz D^2 - D - 1 ... vg + 511 + dz D^2 + D + 1
+// (512 + 2 D + 2 rows), staged once together with the slice's weights of the
+// nine taps; voxel w's neighbour at (dy, dx) is staged row w + (dy + 1) D +
+// dx + 1.  Against one (dz, dy) pair per step this stages each row once
+// instead of three times and the weights for eight waves instead of four.
+// The rows are staged without regard to the lattice (out-of-range voxels
+// read as zero through the buffer range); each fragment's own (x, y, z)
+// test selects its row or an all-zero row kept past the staged ones.  One
+// LDS buffer: the next step's loads are in flight in registers during the
+// current step's 144 MFMAs per wave.
+template <int NT>
+__global__ __launch_bounds__(C9_BLOCK, 1) void k_conv9(const u16* __restrict__ x, int Cin,
+                                                       const u16* __restrict__ w, int Kpad, int Cout,
+                                                       const float* __restrict__ bias, int relu,
+                                                       const u16* __restrict__ mask, int D, uint32_t rd,
+                                                       int64_t V, u16* __restrict__ ybf, float* __restrict__ yf,
+                                                       int ycs, u16* __restrict__ yT)
+{
+    static_assert(C9_ABYTES + C9_WBYTES >= EP_WAVE_BYTES * C9_WAVES, "epilogue tiles inside the staging area");
+    __shared__ __attribute__((aligned(16))) char smem[C9_ABYTES + C9_WBYTES];
+    char* const sA = smem;
+    char* const sB = smem + C9_ABYTES;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int row = lane & 15, kq = lane >> 4;
+    const int64_t vg = (int64_t)xcd_block(blockIdx.x, gridDim.x) * C9_VOX;
+    const int64_t D2 = (int64_t)D * D;
+    const int S = C9_VOX + 2 * D + 2;  // staged rows of this lattice
+    const int x0 = (int)(vg % D), y0 = (int)((vg / D) % D), z0 = (int)((vg / D2) % D);
+    // per row tile: the byte offset of its dx = -1, dy = -1 neighbour row and
+    // the validity of the 27 taps as (z bits) x (y bits) x (x bits)
+    uint32_t rb[CONV_MB], zb[CONV_MB], yxm[CONV_MB];
+#pragma unroll
+    for (int m = 0; m < CONV_MB; ++m) {
+        const int l = wv * (16 * CONV_MB) + 16 * m + row;  // workgroup-relative voxel
+        const int tx = x0 + l;
+        const int qy = small_div(tx, rd);
+        const int xx = tx - qy * D;
+        const int ty = y0 + qy;
+        const int qz = small_div(ty, rd);
+        const int yy = ty - qz * D;
+        const int tz = z0 + qz;
+        const int zz = tz - small_div(tz, rd) * D;
+        rb[m] = (uint32_t)((l * SA_LD + 8 * kq) * 2);
+        zb[m] = (zz > 0 ? 1u : 0u) | 2u | (zz < D - 1 ? 4u : 0u);
+        const uint32_t yb = (yy > 0 ? 1u : 0u) | 2u | (yy < D - 1 ? 4u : 0u);
+        const uint32_t xb = (xx > 0 ? 1u : 0u) | 2u | (xx < D - 1 ? 4u : 0u);
+        uint32_t mk = 0u;
+#pragma unroll
+        for (int tp = 0; tp < 9; ++tp) mk |= ((yb >> (tp / 3)) & (xb >> (tp % 3)) & 1u) << tp;
+        yxm[m] = mk;
+    }
+    const uint32_t zrow = (uint32_t)((S * SA_LD + 8 * kq) * 2);  // the zero row
+    // activation rows through a buffer based at the lowest voxel any step
+    // reads, sized to the highest
+    const int64_t vbase = vg - D2 - D - 1 > 0 ? vg - D2 - D - 1 : 0;
+    int64_t vtop = vg + C9_VOX + D2 + D + 1;
+    vtop = vtop < V ? vtop : V;
+    const __amdgpu_buffer_rsrc_t ra_rs = buffer_rsrc(x + vbase * Cin, (uint32_t)((vtop - vbase) * Cin * 2));
+    const __amdgpu_buffer_rsrc_t rw_rs = buffer_rsrc(w, (uint32_t)((int64_t)Cout * Kpad * 2));
+    // row chunks: i = t + 512 j -> row i / 4, chunk i % 4; bit dz + 1 of
+    // vdz[j]: the row's voxel at that dz lies inside [0, V)
+    uint32_t abase[C9_NA], vdz[C9_NA];
+#pragma unroll
+    for (int j = 0; j < C9_NA; ++j) {
+        const int i = t + C9_BLOCK * j;
+        const int r = i >> 2, c = i & 3;
+        const int64_t u0 = vg - D - 1 + r;  // the row's voxel at dz = 0
+        uint32_t vb = 0u;
+        if (r < S) {
+#pragma unroll
+            for (int dz = -1; dz <= 1; ++dz) {
+                const int64_t u = u0 + dz * D2;
+                vb |= (u >= 0 && u < V ? 1u : 0u) << (dz + 1);
+            }
+        }
+        vdz[j] = vb;
+        abase[j] = (uint32_t)(((u0 - vbase) * Cin + 8 * c) * 2);
+    }
+    // weight chunks: i = t + 512 j -> row co = i / 36, tap t9 = (i % 36) / 4, chunk i % 4
+    uint32_t wbase[C9_NW];
+#pragma unroll
+    for (int j = 0; j < C9_NW; ++j) {
+        const int i = t + C9_BLOCK * j;
+        const int co = i / 36, c = i - co * 36;
+        wbase[j] = i < MAXC * 36 && co < Cout ? (uint32_t)((co * Kpad + (c / 4) * Cin + 8 * (c % 4)) * 2) : OOB;
+    }
+    const int nslice = Cin / 32;
+    const int nsteps = 3 * nslice;
+    auto sload = [&](int step, u32x4* ra, u32x4* rw) {
+        const bool live = step < nsteps;
+        const int dzi = live ? step / nslice : 0, cs = step - dzi * nslice;  // dz = dzi - 1
+        const uint32_t soff = (uint32_t)((((int64_t)(dzi - 1) * D2 * Cin) + 32 * cs) * 2);
+        const uint32_t woff = (uint32_t)((9 * dzi * Cin + 32 * cs) * 2);
+#pragma unroll
+        for (int j = 0; j < C9_NA; ++j) {
+            const bool ok = live && ((vdz[j] >> dzi) & 1u);
+            ra[j] = buffer_load16(ra_rs, ok ? abase[j] + soff : OOB);
+        }
+#pragma unroll
+        for (int j = 0; j < C9_NW; ++j) rw[j] = buffer_load16(rw_rs, live ? wbase[j] + woff : OOB);
+    };
+    auto sstore = [&](const u32x4* ra, const u32x4* rw) {
+#pragma unroll
+        for (int j = 0; j < C9_NA; ++j) {
+            const int i = t + C9_BLOCK * j;
+            const int r = i >> 2, c = i & 3;
+            if (r < S) *reinterpret_cast<u32x4*>(sA + (r * SA_LD + 8 * c) * 2) = ra[j];
+        }
+#pragma unroll
+        for (int j = 0; j < C9_NW; ++j) {
+            const int i = t + C9_BLOCK * j;
+            const int co = i / 36, c = i - co * 36;
+            if (i < MAXC * 36) *reinterpret_cast<u32x4*>(sB + (co * C9_WLD + (c / 4) * 32 + 8 * (c % 4)) * 2) = rw[j];
+        }
+    };
+    f32x4 acc[CONV_MB][NT];
+#pragma unroll
+    for (int m = 0; m < CONV_MB; ++m)
+#pragma unroll
+        for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const uint32_t boff = (uint32_t)((row * C9_WLD + 8 * kq) * 2);
+    auto compute = [&](int dzi) {
+        uint32_t mk[CONV_MB];  // the nine taps' validity of each row tile at this dz
+#pragma unroll
+        for (int m = 0; m < CONV_MB; ++m) mk[m] = ((zb[m] >> dzi) & 1u) ? yxm[m] : 0u;
+#pragma unroll
+        for (int tp = 0; tp < 9; ++tp) {
+            const uint32_t toff = (uint32_t)((((tp / 3) * D + tp % 3) * SA_LD) * 2);
+            u32x4 a[CONV_MB];
+#pragma unroll
+            for (int m = 0; m < CONV_MB; ++m)
+                a[m] = *reinterpret_cast<const u32x4*>(sA + (((mk[m] >> tp) & 1u) ? rb[m] + toff : zrow));
+#pragma unroll
+            for (int n = 0; n < NT; ++n) {
+                const u32x4 b = *reinterpret_cast<const u32x4*>(sB + boff + (n * 16 * C9_WLD + tp * 32) * 2);
+#pragma unroll
+                for (int m = 0; m < CONV_MB; ++m)
+                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a[m]), as_bf16x8(b), acc[m][n],
+                                                                        0, 0, 0);
+            }
+        }
+    };
+    u32x4 ra[C9_NA], rw[C9_NW];
+    if (t < 4) *reinterpret_cast<u32x4*>(sA + (S * SA_LD + 8 * t) * 2) = u32x4{0u, 0u, 0u, 0u};
+    sload(0, ra, rw);
+    sstore(ra, rw);
+    for (int step = 0; step < nsteps; ++step) {
+        __syncthreads();            // the staging area holds step `step`
+        sload(step + 1, ra, rw);    // in flight during this step's MFMAs (zero past the end)
+        __builtin_amdgcn_sched_barrier(0);
+        compute(step / nslice);
+        __syncthreads();            // every wave is done with step `step`
+        sstore(ra, rw);
+    }
+    __syncthreads();
+    const int64_t vw = vg + wv * (16 * CONV_MB);
+    if (vw >= V) return;
+    if (!yf && ycs % 8 == 0)
+        conv_epilogue_lds<NT>(acc, vw, lane, Cout, ycs, bias, relu, mask, V, ybf, yT, smem + wv * EP_WAVE_BYTES);
+    else
+        conv_epilogue<NT>(acc, vw, row, kq, Cout, ycs, bias, relu, mask, V, ybf, yf, yT);
+}
+
 // dw[co][tap][ci] += sum_v dyT[co][v] xT[ci][nbr(v, tap)] from blocked
 // channel-major operands (tidx), for any lattice size D: every element's
 // neighbour is located on its own (used for D % 8 != 0, small lattices;
@@ -1309,6 +1486,19 @@ hipError_t run_conv(const u16* x, int Cin, const u16* w, int Kp, int Cout, const
             k_conv_c1<32><<<g1, 256, 0, s>>>(x, w, Kp, Cout, bias, relu, D, small_div_r(D), V, ybf, ycs, yT);
         else
             k_conv_c1<64><<<g1, 256, 0, s>>>(x, w, Kp, Cout, bias, relu, D, small_div_r(D), V, ybf, ycs, yT);
+        return hipGetLastError();
+    }
+    if (Cin % 32 == 0 && D <= C9_DMAX) {
+        const unsigned g9 = (unsigned)((V + C9_VOX - 1) / C9_VOX);
+#define EFUNC_CONV9(N) \
+    k_conv9<N><<<g9, C9_BLOCK, 0, s>>>(x, Cin, w, Kp, Cout, bias, relu, mask, D, small_div_r(D), V, ybf, yf, ycs, yT)
+        switch (NT) {
+        case 1: EFUNC_CONV9(1); break;
+        case 2: EFUNC_CONV9(2); break;
+        case 3: EFUNC_CONV9(3); break;
+        default: EFUNC_CONV9(4); break;
+        }
+#undef EFUNC_CONV9
         return hipGetLastError();
     }
     if (Cin % 32 == 0 && D <= 256) {
