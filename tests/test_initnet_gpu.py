@@ -91,6 +91,44 @@ def test_conv_forward_matches_oracle(E, Cin, Cout, R, B):
     assert not yT.float().cpu().numpy().reshape(nb, Cout, 32)[-1, :, V - 32 * (nb - 1):].any()
 
 
+@pytest.mark.parametrize("R", [130])
+def test_conv_forward_large_lattice_sampled(E, R):
+    """Past 128 lattice points per axis the Cin % 32 == 0 forward runs the
+    per-(dz, dy) staged kernel: its outputs on 4096 sampled voxels (all
+    lattice faces and edges among them) against the definition evaluated
+    at those voxels."""
+    Cin, Cout = 32, 8
+    rng = np.random.default_rng(130)
+    x = N.bf16_round(rng.standard_normal((1, R, R, R, Cin)).astype(np.float32))
+    W = rng.standard_normal((Cout, 27, Cin)) / np.sqrt(27 * Cin)
+    b = rng.standard_normal(Cout).astype(np.float32)
+    wf, _ = E.efunc_conv3d_pack_weights(PT.to_dev(W.reshape(-1)), Cin, Cout)
+    V = R ** 3
+    yf = torch.empty(V * Cout, device=PT.DEV)
+    E.efunc_conv3d_bf16(bf16_tensor(x), Cin, wf, Cout, R, bias=PT.to_dev(b), relu=False, y_f32=yf)
+    torch.cuda.synchronize()
+    got = yf.cpu().numpy().astype(np.float64).reshape(V, Cout)
+    idx = rng.integers(0, R, size=(4096, 3))
+    idx[:64] = rng.choice([0, R - 1], size=(64, 3))  # corners and faces
+    idx[64:256, rng.integers(0, 3)] = rng.choice([0, R - 1], size=192)
+    Wr = N.bf16_round(W)
+    xs = x[0]
+    ref = np.zeros((len(idx), Cout))
+    mag = np.zeros((len(idx), Cout))
+    for tap in range(27):
+        d = np.array([tap // 9 - 1, (tap // 3) % 3 - 1, tap % 3 - 1])
+        nb = idx + d
+        ok = np.all((nb >= 0) & (nb < R), axis=1)
+        nbc = np.clip(nb, 0, R - 1)
+        xv = xs[nbc[:, 0], nbc[:, 1], nbc[:, 2]] * ok[:, None]
+        ref += xv @ Wr[:, tap, :].T
+        mag += np.abs(xv) @ np.abs(Wr[:, tap, :]).T
+    ref += b
+    v = (idx[:, 0] * R + idx[:, 1]) * R + idx[:, 2]
+    tol = gamma(27 * Cin) * (mag + np.abs(b)) + U * np.abs(ref) + 1e-30
+    assert np.all(np.abs(got[v] - ref) <= tol), np.max(np.abs(got[v] - ref) / tol)
+
+
 @pytest.mark.parametrize("Cin,Cout,R", [(32, 64, 5), (64, 13, 4), (1, 32, 4), (64, 64, 8)])
 def test_conv_data_gradient_matches_oracle(E, Cin, Cout, R):
     """dL/dx through the flipped packing, masked by the input activation > 0."""
