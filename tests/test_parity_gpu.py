@@ -332,6 +332,41 @@ def test_fit_step_sphere_r8_full(E, init):
     assert np.allclose(v1.reshape(-1), (1 - b2) * g_gpu.reshape(-1) ** 2, rtol=1e-5, atol=1e-37)
 
 
+@pytest.mark.parametrize("R", [2, 3])
+def test_minimum_lattices_eval_grad_fit_step(E, R):
+    """The smallest lattices: one cell (R = 2) and eight (R = 3), so every
+    query's window is the whole lattice and every key is on a lattice face;
+    eval, grad and one fit step against the oracle, with queries inside and
+    a few outside the domain."""
+    rng = np.random.default_rng(40 + R)
+    q = rng.uniform(-1.0, 1.0, size=(3000, 3)).astype(np.float32)
+    q[-40:] *= np.float32(1.3)
+    o = (np.linalg.norm(q, axis=1) - 0.5).astype(np.float32)
+    th = W.perturbed_theta(R, 41 + R, rho0=3.0)
+    O, lse, nu, _ = run_eval(E, R, th, q)
+    ref = PT.reference(R, th, q)
+    PT.check_eval(O, lse, ref)
+    Or, lr, _ = PT.oracle_values(R, th, q)
+    dl = rng.standard_normal(len(q)) / len(q)
+    n = th.size
+    with E.Engine(R, len(q)) as eng:
+        tth = PT.to_dev(th)
+        G = eng.grad(tth, PT.to_dev(q), PT.to_dev(Or), PT.to_dev(lr), PT.to_dev(dl))
+        m = torch.zeros(n, device=PT.DEV)
+        v = torch.zeros(n, device=PT.DEV)
+        loss = torch.zeros(2, device=PT.DEV, dtype=torch.float64)
+        eng.fit_step(tth, m, v, 1, PT.to_dev(q), PT.to_dev(o), loss)
+        torch.cuda.synchronize()
+        G, m1, loss = G.cpu().numpy(), m.cpu().numpy(), loss.cpu().numpy()
+    gr, ar, br = PT.oracle_grad(R, th, q, dl)
+    PT.check_grad(G, gr, ar, br)
+    fref = orc.fit_step(orc.Grid(R=R), th, np.zeros(n), np.zeros(n), 1, q, o)
+    assert abs(loss[0] - fref["loss"]) <= 1e-5 * fref["loss"]
+    g_gpu = m1.astype(np.float64) / (1.0 - np.float32(0.9))
+    _, ar2, br2 = PT.oracle_grad(R, th, q, 2 * (Or - o) / len(q))
+    PT.check_grad(g_gpu, fref["grad"], ar2, br2)
+
+
 def test_second_fit_step_starts_from_clean_gradient(E):
     """Step 2 reports the loss of the parameters after step 1 and uses only
     their gradient: the internal gradient buffer is cleared by the update."""
