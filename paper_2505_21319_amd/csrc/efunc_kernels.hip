@@ -2364,12 +2364,14 @@ static hipError_t scan(const int* cnt, int64_t n, int* blk, int* start, hipStrea
 
 // Stable sort of positions [0, n) by keys (values < nkeys), one 8-bit digit
 // per pass; *out receives the sorted positions (a workspace buffer).
-static hipError_t radix_sort(const Work& w, const int* keys, int64_t n, int64_t nkeys, const int** out,
+// Stable sort of n keys in [0, nkeys) whose low `low` bits are zero (those
+// bits take no pass); *out receives the input positions in sorted order.
+static hipError_t radix_sort(const Work& w, const int* keys, int64_t n, int64_t nkeys, int low, const int** out,
                              hipStream_t s)
 {
     int bits = 0;
     while (bits < 31 && (1ll << bits) < nkeys) ++bits;
-    const int passes = bits > 0 ? (bits + 7) / 8 : 1;
+    const int passes = bits > low ? (bits - low + 7) / 8 : 1;
     const int64_t nb = (n + RS_TILE - 1) / RS_TILE;
     if (n > w.rs_n) return hipErrorInvalidValue;
     const int* kin = keys;
@@ -2377,10 +2379,10 @@ static hipError_t radix_sort(const Work& w, const int* keys, int64_t n, int64_t 
     for (int pass = 0; pass < passes; ++pass) {
         int* ko = w.rs_k[pass & 1];
         int* vo = w.rs_v[pass & 1];
-        k_rs_hist<<<(unsigned)nb, BLOCK, 0, s>>>(kin, n, 8 * pass, (int)nb, w.rs_hist);
+        k_rs_hist<<<(unsigned)nb, BLOCK, 0, s>>>(kin, n, low + 8 * pass, (int)nb, w.rs_hist);
         hipError_t e = scan(w.rs_hist, 256 * nb, w.rs_blk, w.rs_hist + 256 * w.rs_nb + 1, s);
         if (e != hipSuccess) return e;
-        k_rs_scatter<<<(unsigned)nb, BLOCK, 0, s>>>(kin, vin, n, 8 * pass, (int)nb, w.rs_hist + 256 * w.rs_nb + 1,
+        k_rs_scatter<<<(unsigned)nb, BLOCK, 0, s>>>(kin, vin, n, low + 8 * pass, (int)nb, w.rs_hist + 256 * w.rs_nb + 1,
                                                     ko, vo);
         kin = ko;
         vin = vo;
@@ -2403,11 +2405,13 @@ hipError_t run_front(const Work& w, const Problem& p, Mode mode, bool ordered, h
     // LDS binning of the queries (sort keys fit in one workgroup's LDS) or
     // device atomics into PSPLIT sub-counters per key, which start from zero
     // like the moved-key counters
-    // Deterministic mode: the query counts come from the atomic sub-counters
-    // (exact totals whatever the order) and both orders from stable radix
-    // sorts; every float sum then runs in an order fixed by the data.
+    // Deterministic mode: the query counts (exact totals whatever the order
+    // of the atomics) and sort keys come from either binning; both orders come
+    // from stable radix sorts, so every float sum runs in an order fixed by
+    // the data.  The LDS binning puts every query of a key in sub-counter 0:
+    // its keys are multiples of PSPLIT, whose low bits the sort skips.
     const bool det = w.det != nullptr;
-    const bool lbin = w.hist != nullptr && !det;
+    const bool lbin = w.hist != nullptr;
     {
         const int64_t na = p.offsets ? C : 0, nb = lbin ? 0 : w.NK * PSPLIT;
         k_reset_front<<<grid_for(na > nb ? na : nb, BLOCK * 8), BLOCK, 0, s>>>(w.st, w.mcount, na, w.pcount, nb);
@@ -2444,7 +2448,7 @@ hipError_t run_front(const Work& w, const Problem& p, Mode mode, bool ordered, h
         if (e != hipSuccess) return e;
         if (det) {
             const int* sorted = nullptr;
-            e = radix_sort(w, w.mcell, I, C, &sorted, s);
+            e = radix_sort(w, w.mcell, I, C, 0, &sorted, s);
             if (e != hipSuccess) return e;
             if (p.L.degree == 2)
                 k_det_gather_keys<2><<<grid_for(I), BLOCK, 0, s>>>(sorted, I, w.mrec, w.mk);
@@ -2476,7 +2480,8 @@ hipError_t run_front(const Work& w, const Problem& p, Mode mode, bool ordered, h
     // the fit step writes no per-query outputs and needs no original indices
     if (det) {
         const int* sorted = nullptr;
-        hipError_t e = radix_sort(w, w.pcell, J, w.NK * PSPLIT, &sorted, s);
+        static_assert(PSPLIT == 8, "three low key bits");
+        hipError_t e = radix_sort(w, w.pcell, J, w.NK * PSPLIT, lbin ? 3 : 0, &sorted, s);
         if (e != hipSuccess) return e;
         k_det_gather_points<<<grid_for(J), BLOCK, 0, s>>>(sorted, p.q, p.aux, p.O_in, p.lse_in, J, w.ps, w.pv,
                                                           mode == MODE_FIT ? nullptr : w.pidx);
