@@ -327,6 +327,8 @@ def bench_batch(args, torch):
     B = E.BatchEngine([w.R for w in ws], [w.J for w in ws])
     B.bind(thetas, ms_, vs_, qs, os_, loss)
     tuned = None
+    if args.tuning:
+        B.set_tuning(*[int(x) for x in args.tuning.split(",")])
     if args.autotune:
         tuned = B.autotune(reps=2)
     step = 1
@@ -590,7 +592,7 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="batch64: run the autotuner before timing")
     ap.add_argument("--tuning", default="",
-                    help="tile_cap,group_cells,blocks_per_cu for the tile kernel (default 512,1,8)")
+                    help="tile_cap,group_cells,blocks_per_cu for the tile kernel (default 512,2,8)")
     ap.add_argument("--initnet-train", type=int, default=256, help="initnet: training shapes")
     ap.add_argument("--initnet-test", type=int, default=64, help="initnet: held-out shapes")
     ap.add_argument("--initnet-steps", type=int, default=3000, help="initnet: network training steps")

@@ -103,8 +103,11 @@ typedef struct {
  * rule do not). */
 typedef struct {
     int32_t tile_cap;      /* queries per tile: 128, 256 or 512 (default 512) */
-    int32_t group_cells;   /* 1: a 2x2x2 block of cells with at most tile_cap queries
-                              shares one tile (default); 0: every cell has its own tiles */
+    int32_t group_cells;   /* 0: every cell has its own tiles; 1: a 2x2x2 block of cells
+                              with at most tile_cap queries shares one tile; 2 (default):
+                              as 1, and runs of 4 (or 2) such blocks adjacent in z share
+                              one tile when together they hold at most min(tile_cap, 24 W)
+                              (or min(tile_cap, 32 W)) queries, W the window in cells */
     int32_t blocks_per_cu; /* persistent workgroups launched per compute unit, 1..8 (default 8) */
 } efunc_tuning;
 
@@ -230,7 +233,7 @@ int efunc_get_stats(efunc_ctx* ctx, efunc_stats* out);
 int efunc_set_timing(efunc_ctx* ctx, int32_t enable);
 int efunc_read_timing(efunc_ctx* ctx, double* tile_ms, int64_t* launches);
 
-/* Default tuning: tile_cap 512, group_cells 1, blocks_per_cu 8. */
+/* Default tuning: tile_cap 512, group_cells 2, blocks_per_cu 8. */
 void efunc_default_tuning(efunc_tuning* t);
 
 /* Set / read the tuning of a context (host struct).  Takes effect from the
@@ -287,7 +290,7 @@ int efunc_batch_set_tuning(efunc_batch* b, const efunc_tuning* t);
 int efunc_batch_get_tuning(efunc_batch* b, efunc_tuning* t);
 
 /* Autotuner: times `reps` (>= 1) directly launched iterations on the bound
- * data for every candidate tuning (tile_cap 128/256/512 x group_cells 0/1 x
+ * data for every candidate tuning (tile_cap 128/256/512 x group_cells 0/2 x
  * blocks_per_cu 4/8), keeps the fastest (smallest median iteration time)
  * and sets it on the batch.  theta, m and v are saved first and restored
  * afterwards, so the bound data are unchanged; the call allocates that

@@ -410,13 +410,14 @@ int efunc_batch_autotune(efunc_batch* b, const efunc_adam* adam, int32_t reps, e
     efunc_tuning win = before;
     double win_ms = INFINITY;
     const int caps[3] = {128, 256, 512};
+    const int groups[2] = {0, 2};  // per cell; blocks and z-runs of sparse blocks
     const int bpcs[2] = {4, 8};
     for (int ci = 0; ci < 3 && e == hipSuccess; ++ci)
         for (int gi = 0; gi < 2 && e == hipSuccess; ++gi)
             for (int bi = 0; bi < 2 && e == hipSuccess; ++bi) {
                 efunc_tuning t;
                 t.tile_cap = caps[ci];
-                t.group_cells = gi;
+                t.group_cells = groups[gi];
                 t.blocks_per_cu = bpcs[bi];
                 apply_tuning(b, t);
                 e = run_step_set(b->step, 1, s);

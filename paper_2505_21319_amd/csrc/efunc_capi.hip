@@ -45,7 +45,7 @@ int check_tuning(const efunc_tuning* t)
     if (!t) return fail(EFUNC_EINVAL, "tuning is NULL");
     if (t->tile_cap != 128 && t->tile_cap != 256 && t->tile_cap != 512)
         return fail(EFUNC_EINVAL, "tile_cap = %d is not 128, 256 or 512", t->tile_cap);
-    if (t->group_cells != 0 && t->group_cells != 1) return fail(EFUNC_EINVAL, "group_cells must be 0 or 1");
+    if (t->group_cells < 0 || t->group_cells > 2) return fail(EFUNC_EINVAL, "group_cells = %d outside [0, 2]", t->group_cells);
     if (t->blocks_per_cu < 1 || t->blocks_per_cu > 8)
         return fail(EFUNC_EINVAL, "blocks_per_cu = %d outside [1, 8]", t->blocks_per_cu);
     return EFUNC_OK;
@@ -491,7 +491,7 @@ void efunc_default_tuning(efunc_tuning* t)
 {
     if (!t) return;
     t->tile_cap = PMAX;
-    t->group_cells = 1;
+    t->group_cells = 2;
     t->blocks_per_cu = 8;
 }
 

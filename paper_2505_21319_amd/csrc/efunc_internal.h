@@ -153,10 +153,11 @@ struct Work {
     DetStats* det;
     DevStats* st;
     int num_cu;
-    // launch tuning (runtime): tile query cap, whether sparse 2x2x2 cell
-    // blocks share one tile, persistent workgroups per CU
+    // launch tuning (runtime): tile query cap, cell grouping (0: per cell,
+    // 1: sparse 2x2x2 blocks share one tile, 2: and z-runs of sparse
+    // blocks), persistent workgroups per CU
     int cap = PMAX;
-    int group = 1;
+    int group = 2;
     int bpc = 8;
 };
 

@@ -787,15 +787,57 @@ __global__ void k_scatter_points(const float* __restrict__ q, const float* __res
 
 // Tiles per block: with grouping, a block with at most cap queries is one
 // tile spanning its cells; otherwise each cell gets balanced slices of at
-// most cap queries.
-// queries in cell s of block b (from the scanned sub-counters)
+// most cap queries.  With group 2, runs of non-empty blocks adjacent in z
+// (consecutive in the block-major query order) share one tile: four blocks
+// (bz = 4k .. 4k + 3, a 2 x 2 x 8 cell tile) that together hold at most
+// min(cap, 24 W) queries, else two (bz = 2k, 2k + 1) that together hold at
+// most min(cap, 32 W), W the window in cells.  Where the points are sparse
+// a 2x2x2 block holds few queries, and the per-tile work (culling the
+// window, loading and flushing every kept key) is then spread over more of
+// them, for a window that grows only in z and more pairs per query.  The
+// limits scale with W because that per-tile work grows with the window
+// (about W^3 keys) faster than the extra pairs per query (a factor of about
+// (2 + 2 r + 2) / (2 + 2 r), r the cull reach in cells).
 __device__ __forceinline__ int cell_count(const int* __restrict__ pstart, int64_t b, int s)
 {
     return pstart[(8 * b + s + 1) * PSPLIT] - pstart[(8 * b + s) * PSPLIT];
 }
 
-__global__ void k_block_tiles(int64_t NB3, const int* __restrict__ pstart, int cap, int group,
-                              int* __restrict__ btiles)
+__device__ __forceinline__ int block_count(const int* __restrict__ pstart, int64_t b)
+{
+    return pstart[8 * (b + 1) * PSPLIT] - pstart[8 * b * PSPLIT];
+}
+
+// The z-run of blocks whose queries share block b's tile: (first bz, blocks).
+__device__ __forceinline__ int2 block_run(const int* __restrict__ pstart, int64_t b, int tot, int NB, int cap,
+                                          int group, int W)
+{
+    const int bz = (int)(b % NB);
+    if (group < 2 || tot == 0) return make_int2(bz, 1);
+    const int64_t b0 = b - bz;  // block (bx, by, 0)
+    const int lim4 = min(cap, 24 * W), lim2 = min(cap, 32 * W);
+    const int q0 = bz & ~3;
+    if (q0 + 3 < NB) {
+        int sum = 0;
+        bool all = true;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int n = block_count(pstart, b0 + q0 + i);
+            all = all && n > 0;
+            sum += n;
+        }
+        if (all && sum <= lim4) return make_int2(q0, 4);
+    }
+    const int p0 = bz & ~1;
+    if (p0 + 1 < NB) {
+        const int n0 = block_count(pstart, b0 + p0), n1 = block_count(pstart, b0 + p0 + 1);
+        if (n0 > 0 && n1 > 0 && n0 + n1 <= lim2) return make_int2(p0, 2);
+    }
+    return make_int2(bz, 1);
+}
+
+__global__ void k_block_tiles(int64_t NB3, int NB, const int* __restrict__ pstart, int cap, int group,
+                              const DevStats* __restrict__ st, int* __restrict__ btiles)
 {
     const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (b >= NB3) return;
@@ -806,11 +848,19 @@ __global__ void k_block_tiles(int64_t NB3, const int* __restrict__ pstart, int c
         tot += n;
         split += (n + cap - 1) / cap;
     }
+    const int2 run = block_run(pstart, b, tot, NB, cap, group, st->W);
+    if (run.y > 1) {
+        btiles[b] = (int)(b % NB) == run.x ? 1 : 0;
+        return;
+    }
     btiles[b] = tot == 0 ? 0 : ((group && tot <= cap) ? 1 : split);
 }
 
+// Tile descriptor: (first cell, first query, queries, extents | slice << 5);
+// extents: bit 0 x, bit 1 y (cells - 1, 0..1), bits 2-4 z (cells - 1, 0..7).
 __global__ void k_build_tiles(int64_t NB3, Geo g, const int* __restrict__ pstart, int cap, int group,
-                              const int* __restrict__ tstart, int4* __restrict__ tiles)
+                              const DevStats* __restrict__ st, const int* __restrict__ tstart,
+                              int4* __restrict__ tiles)
 {
     const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (b >= NB3) return;
@@ -823,9 +873,20 @@ __global__ void k_build_tiles(int64_t NB3, Geo g, const int* __restrict__ pstart
     int tot = 0;
 #pragma unroll
     for (int s = 0; s < 8; ++s) tot += cell_count(pstart, b, s);
+    const int ex = min(2, C1 - 2 * bx), ey = min(2, C1 - 2 * by);
+    const int c0 = ((2 * bx) * C1 + 2 * by) * C1 + 2 * bz;
+    const int2 run = block_run(pstart, b, tot, NB, cap, group, st->W);
+    if (run.y > 1) {  // b leads the run (the others have no tiles)
+        int n = 0, ez = 0;
+        for (int i = 0; i < run.y; ++i) {
+            n += block_count(pstart, b + i);
+            ez += min(2, C1 - 2 * (bz + i));
+        }
+        tiles[t] = make_int4(c0, first, n, (ex - 1) | ((ey - 1) << 1) | ((ez - 1) << 2));
+        return;
+    }
     if (group && tot <= cap) {
-        const int ex = min(2, C1 - 2 * bx), ey = min(2, C1 - 2 * by), ez = min(2, C1 - 2 * bz);
-        const int c0 = ((2 * bx) * C1 + 2 * by) * C1 + 2 * bz;
+        const int ez = min(2, C1 - 2 * bz);
         tiles[t] = make_int4(c0, first, tot, (ex - 1) | ((ey - 1) << 1) | ((ez - 1) << 2));
         return;
     }
@@ -838,8 +899,8 @@ __global__ void k_build_tiles(int64_t NB3, Geo g, const int* __restrict__ pstart
         const int start = pstart[(8 * b + s) * PSPLIT];
         for (int i = 0; i < k; ++i) {
             const int lo = (int)((int64_t)i * n / k), hi = (int)((int64_t)(i + 1) * n / k);
-            // bits 3.. carry the slice index (ordering key; extents are bits 0..2)
-            tiles[t++] = make_int4(c, start + lo, hi - lo, min(i, SLICE_KEYS - 1) << 3);
+            // bits 5.. carry the slice index (ordering key; extents are bits 0..4)
+            tiles[t++] = make_int4(c, start + lo, hi - lo, min(i, SLICE_KEYS - 1) << 5);
         }
     }
 }
@@ -859,7 +920,7 @@ __global__ __launch_bounds__(BLOCK) void k_tile_cost(const int* __restrict__ nti
     for (int t = (int)((blockIdx.x * (int64_t)BLOCK + threadIdx.x) >> 6); t < n; t += nw) {
         const int4 tl = tiles[t];
         const int cx = tl.x / (C1 * C1), cy = (tl.x / C1) % C1, cz = tl.x % C1;
-        const int cx1 = cx + (tl.w & 1), cy1 = cy + ((tl.w >> 1) & 1), cz1 = cz + ((tl.w >> 2) & 1);
+        const int cx1 = cx + (tl.w & 1), cy1 = cy + ((tl.w >> 1) & 1), cz1 = cz + ((tl.w >> 2) & 7);
         long long K = 0;
         if (offsets) {
             const int mx0 = max(cx - W, 0), mx1 = min(cx1 + W, C1 - 1);
@@ -879,7 +940,7 @@ __global__ __launch_bounds__(BLOCK) void k_tile_cost(const int* __restrict__ nti
             const float c = (float)(K * (long long)tl.z);
             const int bk = min(127, max(0, (int)(4.0f * log2f(fmaxf(c, 1.0f)))));
             // sort key (descending): cost bucket, then ascending slice index
-            tbucket[t] = make_int2(bk * SLICE_KEYS + (SLICE_KEYS - 1 - (tl.w >> 3)), 0);
+            tbucket[t] = make_int2(bk * SLICE_KEYS + (SLICE_KEYS - 1 - (tl.w >> 5)), 0);
         }
     }
 }
@@ -1216,9 +1277,10 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem<DEG>& S, co
     const Geo& g = a.g;
     const int R = g.R, C1 = g.C1;
     const int cell = td.x, p0 = td.y, P = td.z;
-    // the tile covers cells [c0, c1] per axis (one cell or a 2x2x2 block)
+    // the tile covers cells [c0, c1] per axis (one cell, a 2x2x2 block or
+    // a run of two or four blocks adjacent in z)
     const int cx = cell / (C1 * C1), cy = (cell / C1) % C1, cz = cell % C1;
-    const int cx1 = cx + (td.w & 1), cy1 = cy + ((td.w >> 1) & 1), cz1 = cz + ((td.w >> 2) & 1);
+    const int cx1 = cx + (td.w & 1), cy1 = cy + ((td.w >> 1) & 1), cz1 = cz + ((td.w >> 2) & 7);
 
     // ---- window: grid vertices [c0 - W + 1, c1 + W] and moved-key cells
     // [c0 - W, c1 + W] per axis, the latter as rows (x, y) of z-ranges
@@ -2490,12 +2552,12 @@ hipError_t run_front(const Work& w, const Problem& p, Mode mode, bool ordered, h
                                                        w.prank, w.pstart, lbin ? w.hist : nullptr, chunk,
                                                        (int)w.NK, w.ps, w.pv, mode == MODE_FIT ? nullptr : w.pidx);
     }
-    k_block_tiles<<<grid_for(w.NB3), BLOCK, 0, s>>>(w.NB3, w.pstart, w.cap, w.group, w.btiles);
+    k_block_tiles<<<grid_for(w.NB3), BLOCK, 0, s>>>(w.NB3, g.NB, w.pstart, w.cap, w.group, w.st, w.btiles);
     {
         hipError_t e = scan(w.btiles, w.NB3, w.scan_blk, w.tstart, s);
         if (e != hipSuccess) return e;
     }
-    k_build_tiles<<<grid_for(w.NB3), BLOCK, 0, s>>>(w.NB3, g, w.pstart, w.cap, w.group, w.tstart,
+    k_build_tiles<<<grid_for(w.NB3), BLOCK, 0, s>>>(w.NB3, g, w.pstart, w.cap, w.group, w.st, w.tstart,
                                                     w.tiles_tmp);
     int64_t cgrid = (w.max_tiles + BLOCK / 64 - 1) / (BLOCK / 64);
     if (cgrid > (int64_t)w.num_cu * 16) cgrid = (int64_t)w.num_cu * 16;

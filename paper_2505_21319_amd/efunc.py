@@ -453,7 +453,7 @@ class BatchEngine:
     def fit(self, first_step, n_steps, use_graph=False, adam=None):
         efunc_batch_fit(self.b, first_step, n_steps, use_graph, adam)
 
-    def set_tuning(self, tile_cap=512, group_cells=1, blocks_per_cu=8):
+    def set_tuning(self, tile_cap=512, group_cells=2, blocks_per_cu=8):
         t = efunc_tuning(tile_cap, group_cells, blocks_per_cu)
         efunc_batch_set_tuning(self.b, t)
 
@@ -616,7 +616,7 @@ class Engine:
     def stats(self):
         return efunc_get_stats(self.ctx)
 
-    def set_tuning(self, tile_cap=512, group_cells=1, blocks_per_cu=8):
+    def set_tuning(self, tile_cap=512, group_cells=2, blocks_per_cu=8):
         efunc_set_tuning(self.ctx, efunc_tuning(tile_cap, group_cells, blocks_per_cu))
 
     def tuning(self):

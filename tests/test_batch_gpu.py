@@ -162,7 +162,7 @@ def test_batch_tuning_does_not_change_results(E, medium):
     first moment) as the default, up to the order of float additions."""
     Rs, Js = [d[0].R for d in medium], [d[0].J for d in medium]
     base = None
-    for cap, grp, bpc in [(512, 1, 8), (128, 0, 4), (256, 1, 2), (128, 1, 8), (512, 0, 1)]:
+    for cap, grp, bpc in [(512, 2, 8), (128, 0, 4), (256, 1, 2), (128, 1, 8), (512, 0, 1), (256, 2, 4)]:
         th, m, v, q, o, loss = _state(medium)
         with E.BatchEngine(Rs, Js) as B:
             B.set_tuning(cap, grp, bpc)
@@ -186,7 +186,7 @@ def test_batch_autotune_restores_state(E, medium):
     with E.BatchEngine(Rs, Js) as B:
         B.bind(th, m, v, q, o, loss)
         best, ms = B.autotune(reps=1)
-        assert best["tile_cap"] in (128, 256, 512) and best["group_cells"] in (0, 1)
+        assert best["tile_cap"] in (128, 256, 512) and best["group_cells"] in (0, 2)
         assert best["blocks_per_cu"] in (4, 8) and ms > 0
         assert B.tuning() == best
         for a, b in zip(th, th0):
@@ -204,7 +204,7 @@ def test_single_context_tuning_eval_parity(E):
     q, _ = W.make_batch(w, 4, J=30000)
     th = W.perturbed_theta(R, 71, rho0=6.5)
     ref = PT.reference(R, th, q)
-    for cap, grp, bpc in [(128, 0, 4), (256, 1, 1)]:
+    for cap, grp, bpc in [(128, 0, 4), (256, 1, 1), (128, 2, 8)]:
         with E.Engine(R, len(q)) as eng:
             eng.set_tuning(cap, grp, bpc)
             O, lse, _, nu = eng.eval(PT.to_dev(th), PT.to_dev(q))
@@ -231,6 +231,9 @@ def test_batch_argument_errors(E):
         assert ei.value.code == E.EFUNC_EINVAL
         with pytest.raises(EfuncError) as ei:
             B.set_tuning(512, 1, 9)
+        assert ei.value.code == E.EFUNC_EINVAL
+        with pytest.raises(EfuncError) as ei:
+            B.set_tuning(512, 3, 8)
         assert ei.value.code == E.EFUNC_EINVAL
     cfg = E.efunc_default_config(6)
     cfg.check_finite = 1

@@ -14,6 +14,8 @@ from tests import parity as PT
 
 pytestmark = pytest.mark.gpu
 
+MERGE = 2  # group_cells value that lets z-adjacent sparse blocks share a tile
+
 
 @pytest.fixture(scope="module")
 def E():
@@ -330,6 +332,40 @@ def test_fit_step_sphere_r8_full(E, init):
     # the library takes the hyper-parameters as float32: 1 - fl32(0.999)
     b2 = float(np.float32(0.999))
     assert np.allclose(v1.reshape(-1), (1 - b2) * g_gpu.reshape(-1) ** 2, rtol=1e-5, atol=1e-37)
+
+
+def test_merged_sparse_tiles_eval_grad_fit_step(E):
+    """Sparse queries with z-adjacent cell blocks sharing tiles (group_cells
+    = MERGE): fewer tiles than one per block, and eval, grad and a fit step
+    still match the oracle under the global definition."""
+    R, J = 16, 3000
+    q, o = W.make_batch(W.get("sphere_r8"), 2, J=J)
+    th = W.perturbed_theta(R, 41)
+    n = th.size
+    ntiles = {}
+    for grp in (1, MERGE):
+        with E.Engine(R, J) as eng:
+            eng.set_tuning(512, grp, 8)
+            tth = PT.to_dev(th)
+            O, lse, _, _ = eng.eval(tth, PT.to_dev(q))
+            ntiles[grp] = eng.stats()["n_tiles"]
+            ref = PT.reference(R, th, q)
+            dl = (2 * (ref["O"] - o) / J).astype(np.float32)
+            G = eng.grad(tth, PT.to_dev(q), PT.to_dev(ref["O"]), PT.to_dev(ref["lse"]), PT.to_dev(dl))
+            m = torch.zeros(n, device=PT.DEV)
+            v = torch.zeros(n, device=PT.DEV)
+            loss = torch.zeros(2, device=PT.DEV, dtype=torch.float64)
+            eng.fit_step(tth, m, v, 1, PT.to_dev(q), PT.to_dev(o), loss)
+            torch.cuda.synchronize()
+            O, lse, G, m1, loss = (x.cpu().numpy() for x in (O, lse, G, m, loss))
+        PT.check_eval(O, lse, ref)
+        gr, ar, br = PT.oracle_grad(R, th, q, dl)
+        PT.check_grad(G, gr, ar, br)
+        fr = orc.fit_step(orc.Grid(R=R), th, np.zeros(n), np.zeros(n), 1, q, o)
+        assert abs(loss[0] - fr["loss"]) <= 1e-5 * fr["loss"]
+        _, ar, br = PT.oracle_grad(R, th, q, 2 * (ref["O"] - o) / J)
+        PT.check_grad(m1.astype(np.float64) / (1.0 - np.float32(0.9)), fr["grad"], ar, br)
+    assert ntiles[MERGE] < 0.75 * ntiles[1], ntiles
 
 
 @pytest.mark.parametrize("R", [2, 3])
