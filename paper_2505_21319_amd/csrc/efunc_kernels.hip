@@ -791,7 +791,9 @@ __global__ void k_scatter_points(const float* __restrict__ q, const float* __res
 // (consecutive in the block-major query order) share one tile: four blocks
 // (bz = 4k .. 4k + 3, a 2 x 2 x 8 cell tile) that together hold at most
 // min(cap, 24 W) queries, else two (bz = 2k, 2k + 1) that together hold at
-// most min(cap, 32 W), W the window in cells.  Where the points are sparse
+// most min(cap, 32 W), W the window in cells; and in a block that is split
+// into cell tiles, z-adjacent cells that together hold at most min(cap,
+// 32 W) queries share one.  Where the points are sparse
 // a 2x2x2 block holds few queries, and the per-tile work (culling the
 // window, loading and flushing every kept key) is then spread over more of
 // them, for a window that grows only in z and more pairs per query.  The
@@ -806,6 +808,14 @@ __device__ __forceinline__ int cell_count(const int* __restrict__ pstart, int64_
 __device__ __forceinline__ int block_count(const int* __restrict__ pstart, int64_t b)
 {
     return pstart[8 * (b + 1) * PSPLIT] - pstart[8 * b * PSPLIT];
+}
+
+// With group 2, cells s and s + 1 (s even: adjacent in z) of a block that
+// is split into cell tiles share one tile when both hold queries and
+// together at most min(cap, 32 W): the sparse cells of a dense block.
+__device__ __forceinline__ bool cells_merged(int n0, int n1, int cap, int group, int W)
+{
+    return group >= 2 && n0 > 0 && n1 > 0 && n0 + n1 <= min(cap, 32 * W);
 }
 
 // The z-run of blocks whose queries share block b's tile: (first bz, blocks).
@@ -841,14 +851,15 @@ __global__ void k_block_tiles(int64_t NB3, int NB, const int* __restrict__ pstar
 {
     const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (b >= NB3) return;
+    const int W = st->W;
     int tot = 0, split = 0;
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-        const int n = cell_count(pstart, b, s);
-        tot += n;
-        split += (n + cap - 1) / cap;
+    for (int s = 0; s < 8; s += 2) {
+        const int n0 = cell_count(pstart, b, s), n1 = cell_count(pstart, b, s + 1);
+        tot += n0 + n1;
+        split += cells_merged(n0, n1, cap, group, W) ? 1 : (n0 + cap - 1) / cap + (n1 + cap - 1) / cap;
     }
-    const int2 run = block_run(pstart, b, tot, NB, cap, group, st->W);
+    const int2 run = block_run(pstart, b, tot, NB, cap, group, W);
     if (run.y > 1) {
         btiles[b] = (int)(b % NB) == run.x ? 1 : 0;
         return;
@@ -892,11 +903,19 @@ __global__ void k_build_tiles(int64_t NB3, Geo g, const int* __restrict__ pstart
     }
     for (int s = 0; s < 8; ++s) {
         const int n = cell_count(pstart, b, s);
-        if (n == 0) continue;
         const int cx = 2 * bx + (s >> 2), cy = 2 * by + ((s >> 1) & 1), cz = 2 * bz + (s & 1);
         const int c = (cx * C1 + cy) * C1 + cz;
-        const int k = (n + cap - 1) / cap;
         const int start = pstart[(8 * b + s) * PSPLIT];
+        if (!(s & 1)) {
+            const int n1 = cell_count(pstart, b, s + 1);
+            if (cells_merged(n, n1, cap, group, st->W)) {  // cells s and s + 1: z extent 2
+                tiles[t++] = make_int4(c, start, n + n1, 1 << 2);
+                ++s;
+                continue;
+            }
+        }
+        if (n == 0) continue;
+        const int k = (n + cap - 1) / cap;
         for (int i = 0; i < k; ++i) {
             const int lo = (int)((int64_t)i * n / k), hi = (int)((int64_t)(i + 1) * n / k);
             // bits 5.. carry the slice index (ordering key; extents are bits 0..4)

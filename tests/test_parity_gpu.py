@@ -334,18 +334,20 @@ def test_fit_step_sphere_r8_full(E, init):
     assert np.allclose(v1.reshape(-1), (1 - b2) * g_gpu.reshape(-1) ** 2, rtol=1e-5, atol=1e-37)
 
 
-def test_merged_sparse_tiles_eval_grad_fit_step(E):
-    """Sparse queries with z-adjacent cell blocks sharing tiles (group_cells
-    = MERGE): fewer tiles than one per block, and eval, grad and a fit step
-    still match the oracle under the global definition."""
-    R, J = 16, 3000
+@pytest.mark.parametrize("R,J,cap", [(16, 3000, 512), (8, 6000, 128)])
+def test_merged_sparse_tiles_eval_grad_fit_step(E, R, J, cap):
+    """Tiles shared by z-adjacent sparse cell blocks (R = 16: ~6 queries per
+    block) or by z-adjacent sparse cells of blocks split into cell tiles
+    (R = 8 with a 128-query cap) under group_cells = MERGE: fewer tiles than
+    with group_cells = 1, and eval, grad and a fit step still match the
+    oracle under the global definition."""
     q, o = W.make_batch(W.get("sphere_r8"), 2, J=J)
     th = W.perturbed_theta(R, 41)
     n = th.size
     ntiles = {}
     for grp in (1, MERGE):
         with E.Engine(R, J) as eng:
-            eng.set_tuning(512, grp, 8)
+            eng.set_tuning(cap, grp, 8)
             tth = PT.to_dev(th)
             O, lse, _, _ = eng.eval(tth, PT.to_dev(q))
             ntiles[grp] = eng.stats()["n_tiles"]
@@ -365,7 +367,7 @@ def test_merged_sparse_tiles_eval_grad_fit_step(E):
         assert abs(loss[0] - fr["loss"]) <= 1e-5 * fr["loss"]
         _, ar, br = PT.oracle_grad(R, th, q, 2 * (ref["O"] - o) / J)
         PT.check_grad(m1.astype(np.float64) / (1.0 - np.float32(0.9)), fr["grad"], ar, br)
-    assert ntiles[MERGE] < 0.75 * ntiles[1], ntiles
+    assert ntiles[MERGE] < (0.75 if cap == 512 else 0.95) * ntiles[1], ntiles
 
 
 @pytest.mark.parametrize("R", [2, 3])
