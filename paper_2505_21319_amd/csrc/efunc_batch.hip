@@ -284,7 +284,13 @@ int efunc_batch_bind(efunc_batch* b, float* const* theta, float* const* m, float
         d.m = m[s];
         d.v = v[s];
         d.grad = c->w.grad;
+        d.gslotg = c->w.gslotg;
+        d.gslot = c->w.gslot;
+        d.mslot = c->w.mslot;
         d.n = (int64_t)c->layout.nch * c->w.I;
+        d.nch = c->layout.nch;
+        d.ngrid = c->layout.moved ? c->layout.mdel : c->layout.nch;  // grid channels come first
+        d.nfl = flush_slots(c->layout.degree);
     }
     e = hipMemcpy(b->d_tab, b->tab.data(), sizeof(TileArgs) * b->S, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b->d_bs, b->bs.data(), sizeof(BatchShape) * b->S, hipMemcpyHostToDevice);

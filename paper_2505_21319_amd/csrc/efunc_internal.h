@@ -229,8 +229,12 @@ struct BatchShape {
     float* theta;
     float* m;
     float* v;
-    float* grad;
+    float* grad;           // the fallback's gradient (cleared by the AdamW step)
+    float* gslotg;         // gradient records of the grid keys (per vertex)
+    float* gslot;          // gradient records of the moved keys (flush slots)
+    const int* mslot;      // [R^3] the record of each vertex's moved key
     int64_t n;             // nch R^3
+    int nch, ngrid, nfl;   // channels per vertex; grid channels first; slots per record
 };
 
 struct AdamParams {

@@ -2163,15 +2163,6 @@ __global__ void k_slot_finalize(TileArgs a)
         slot_finalize<DEG>(a, p);
 }
 
-template <int DEG>
-__global__ void k_slot_finalize_batch(const TileArgs* __restrict__ tab)
-{
-    const TileArgs& a = tab[blockIdx.y];
-    if (a.gfix) return;
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < a.I; p += (int64_t)gridDim.x * blockDim.x)
-        slot_finalize<DEG>(a, p);
-}
-
 __global__ void k_count_uncertified(const DevStats* st, int64_t* out)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) *out = (int64_t)st->nfb;
@@ -2325,7 +2316,9 @@ __global__ __launch_bounds__(BLOCK) void k_batch_loss(const BatchShape* __restri
 }
 
 // AdamW over every shape (blockIdx.y) with the bias corrections of the step
-// held in device memory, so that a captured graph replays later steps.
+// held in device memory, so that a captured graph replays later steps.  The
+// gradient of a channel is gathered as in k_adam_fit: grad (the fallback's
+// part) plus its slot in its key's record; both are cleared.
 __global__ void k_batch_adam(const BatchShape* __restrict__ bs, const int64_t* __restrict__ step,
                              AdamParams ap)
 {
@@ -2335,7 +2328,13 @@ __global__ void k_batch_adam(const BatchShape* __restrict__ bs, const int64_t* _
     const float bc2 = (float)(1.0 - pow((double)ap.beta2, t));
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < b.n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const float gi = b.grad[i];
+        float gi = b.grad[i];
+        const uint32_t vx = (uint32_t)i / (uint32_t)b.nch;  // n < 2^32
+        const int c = (int)((uint32_t)i - vx * (uint32_t)b.nch);
+        float* gs = c < b.ngrid ? b.gslotg + (int64_t)vx * b.nfl + c
+                                : b.gslot + (int64_t)b.mslot[vx] * b.nfl + (c - b.ngrid);
+        gi += *gs;
+        *gs = 0.0f;
         const float mi = fmaf(ap.beta1, b.m[i], (1.0f - ap.beta1) * gi);
         const float vi = fmaf(ap.beta2, b.v[i], (1.0f - ap.beta2) * gi * gi);
         const float th = b.theta[i];
@@ -2696,7 +2695,6 @@ static void launch_batch(const TileArgs* tab, int S, const int2* gtiles, const i
     k_tile_batch<DEG><<<grid, BLOCK, 0, s>>>(tab, gtiles, ngt, gqueue);
     if (ev_stop) (void)hipEventRecord(ev_stop, s);
     k_fallback_batch<DEG><<<fgrid, FB_BLOCK, 0, s>>>(tab, S);
-    k_slot_finalize_batch<DEG == 2 ? 2 : 1><<<dim3(256, S), BLOCK, 0, s>>>(tab);
 }
 
 hipError_t run_batch_tiles(int degree, const TileArgs* tab, int S, const int2* gtiles, const int* ngt,
