@@ -1286,7 +1286,7 @@ __device__ __forceinline__ void flush_pairs(DevStats* st, const PairCount& c)
 // kept keys whatever fraction of the window survives the cull.
 template <int MODE, bool QGRAD, int DEG>
 __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem<DEG>& S, const int4 td, const int tile,
-                                         const int W, const float bmin2, PairCount& pc)
+                                         const int W, const float bmin2, PairCount& pc, const bool half_batches)
 {
     static_assert(KC == BLOCK, "one staged key per thread");
     constexpr int GW = gk_width(DEG), MW = mk_width(DEG);
@@ -1427,9 +1427,10 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem<DEG>& S, co
         if (keep) S.cand[ncand + before + __popcll(bal & ((1ull << lane) - 1ull))] = tag;
         ncand += tot;
     };
-    // Cull chunks until KC tags have gathered or the window is exhausted.
-    auto gather = [&](Cursor& cu, const float (&bl)[7], float cutoff) {
-        while (ncand < KC) {
+    // Cull chunks until lim (<= KC) tags have gathered or the window is
+    // exhausted.
+    auto gather = [&](Cursor& cu, const float (&bl)[7], float cutoff, int lim) {
+        while (ncand < lim) {
             if (cu.gc < ngc) {
                 const int k0 = cu.gc * KC;
                 cull(true, k0, min(KC, Kg - k0), bl, cutoff);
@@ -1448,11 +1449,11 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem<DEG>& S, co
             }
         }
     };
-    // Load the first min(ncand, KC) gathered keys in full into slots
-    // [0, n) and keep the rest of the tags for the next batch; returns n and
-    // the number of moved keys among them.
-    auto load_batch = [&](int& nmoved) -> int {
-        const int n = min(ncand, KC), rem = ncand - n;
+    // Load the first min(ncand, lim) gathered keys in full into slots
+    // [0, n) and keep the rest of the tags (fewer than KC) for the next
+    // batch; returns n and the number of moved keys among them.
+    auto load_batch = [&](int& nmoved, int lim) -> int {
+        const int n = min(ncand, lim), rem = ncand - n;
         __syncthreads();  // tags complete; the previous batch is no longer read
         const int t0 = tid < n ? S.cand[tid] : 0;
         const int t1 = tid < rem ? S.cand[n + tid] : 0;
@@ -1515,6 +1516,7 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem<DEG>& S, co
     }
 
     unsigned long long fwd_pairs = 0ull, fwd_moved = 0ull;
+    int kept_f = 0;  // keys the forward kept (0 without a forward)
 
     if (MODE != MODE_GRAD) {
         __syncthreads();
@@ -1571,10 +1573,10 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem<DEG>& S, co
             Cursor cu = {0, 0, 0};
             ncand = 0;
             for (;;) {
-                gather(cu, bl, fcut);
+                gather(cu, bl, fcut, KC);
                 if (ncand == 0) break;
                 int nm;
-                const int n = load_batch(nm);
+                const int n = load_batch(nm, KC);
                 if (act) fwd_max<DEG>(S, n, ph, Sf, q, M);
                 if (act2) fwd_max<DEG>(S, n, ph2, Sf2, q2, M2);
             }
@@ -1601,13 +1603,14 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem<DEG>& S, co
             Cursor cu = {0, 0, 0};
             ncand = 0;
             for (;;) {
-                gather(cu, bl, fcut);
+                gather(cu, bl, fcut, KC);
                 if (ncand == 0) break;
                 int nm;
-                const int n = load_batch(nm);
+                const int n = load_batch(nm, KC);
                 fwd_pairs += (unsigned long long)n * P;
                 fwd_moved += (unsigned long long)nm * P;
                 pc.kept += n;
+                kept_f += n;
                 if (act) fwd_sums<DEG>(S, n, ph, Sf, q, Mr, e, m);
                 if (act2) fwd_sums<DEG>(S, n, ph2, Sf2, q2, Mr2, e2, m2);
             }
@@ -1678,10 +1681,10 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem<DEG>& S, co
             Cursor cu = {0, 0, 0};
             ncand = 0;
             for (;;) {
-                gather(cu, bl, fcut);
+                gather(cu, bl, fcut, KC);
                 if (ncand == 0) break;
                 int nm;
-                const int n = load_batch(nm);
+                const int n = load_batch(nm, KC);
                 if (act) fwd_qgrad<DEG>(S, n, ph, Sf, q, O1, L1, gx, gy, gz);
                 if (act2) fwd_qgrad<DEG>(S, n, ph2, Sf2, q2, O2, L2, hx, hy, hz);
             }
@@ -1749,13 +1752,27 @@ __device__ __forceinline__ void tile_run(const TileArgs& a, TileSmem<DEG>& S, co
         tile_bounds(bl, &S.box[0][0]);
         const float bcut = bl[6] - a.T2;
 
+        // Batches of at most kb keys.  The last batch of a tile holds the
+        // remainder; with kb = 128 every full batch gives each key 2 lanes
+        // (half the queries each) and a remainder of at most 64 keys 4, so
+        // a tile with a few hundred kept keys leaves fewer lanes of its
+        // last, partly filled wave idle than with batches of 256 (one lane
+        // per key).  Tiles whose forward kept more than 512 keys keep 256:
+        // their remainder is one batch among several, and the extra batches
+        // cost more than the idle lanes; so do tiles with few queries.
+        // Without a forward (gradient calls) the window decides.  The
+        // batched kernel keeps 256 throughout: it spills registers, and
+        // every extra batch reloads them (measured 7 % slower over the
+        // 64-shape batch with half batches, 1.6 % faster at 32^3 here).
+        const int kb = half_batches && P >= 192 && (MODE == MODE_GRAD ? Kg + Kmt <= 1024 : kept_f <= 512)
+                           ? KC / 2 : KC;
         Cursor cu = {0, 0, 0};
         ncand = 0;
         for (;;) {
-            gather(cu, bl, bcut);
+            gather(cu, bl, bcut, kb);
             if (ncand == 0) break;
             int nmv;
-            const int n = load_batch(nmv);
+            const int n = load_batch(nmv, kb);
             bwd_pairs += (unsigned long long)n * P;
             bwd_moved += (unsigned long long)nmv * P;
             int Sb = 1;
@@ -1884,7 +1901,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(DEG == 2 
         __syncthreads();
         const int tile = S.tile;
         if (tile >= ntiles) break;
-        tile_run<MODE, QGRAD, DEG>(a, S, a.tiles[tile], tile, W, bmin2, pc);
+        tile_run<MODE, QGRAD, DEG>(a, S, a.tiles[tile], tile, W, bmin2, pc, true);
     }
     flush_pairs(a.st, pc);
 }
@@ -1917,7 +1934,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(DEG == 2 
         }
         const TileArgs& a = tab[sh];
         tile_run<MODE_FIT, false, DEG>(a, S, a.tiles[lt], lt, a.st->W,
-                                       __uint_as_float(a.st->bmin_bits) * LOG2E, pc);
+                                       __uint_as_float(a.st->bmin_bits) * LOG2E, pc, false);
     }
     if (cur >= 0) flush_pairs(tab[cur].st, pc);
 }
