@@ -107,7 +107,10 @@ typedef struct {
                               with at most tile_cap queries shares one tile; 2 (default):
                               as 1, and runs of 4 (or 2) such blocks adjacent in z share
                               one tile when together they hold at most min(tile_cap, 24 W)
-                              (or min(tile_cap, 32 W)) queries, W the window in cells */
+                              (or min(tile_cap, 32 W)) queries, W the window in cells;
+                              in a block split into cell tiles, two cells adjacent in z
+                              share one when together they hold at most
+                              min(tile_cap, 32 W) */
     int32_t blocks_per_cu; /* persistent workgroups launched per compute unit, 1..8 (default 8) */
 } efunc_tuning;
 
