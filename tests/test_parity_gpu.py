@@ -370,6 +370,45 @@ def test_merged_sparse_tiles_eval_grad_fit_step(E, R, J, cap):
     assert ntiles[MERGE] < (0.75 if cap == 512 else 0.95) * ntiles[1], ntiles
 
 
+def test_dense_tiles_half_batch_backward_fit_step_and_grad(E):
+    """Tiles of ~300 queries with at most a few hundred kept keys (R = 12,
+    2^16 points: 216 cell blocks): the single-shape kernel runs their
+    backward in batches of at most 128 keys, two lanes per key.  The fit
+    step's loss, gradient and AdamW update and the grad call match the
+    oracle under the global definition."""
+    R, J = 12, 1 << 16
+    q, o = W.make_batch(W.get("sphere_r8"), 7, J=J)
+    th = W.perturbed_theta(R, 43)
+    n = th.size
+    with E.Engine(R, J) as eng:
+        tth = PT.to_dev(th)
+        ref = PT.reference(R, th, q)
+        dl = (2 * (ref["O"] - o) / J).astype(np.float32)
+        G = eng.grad(tth, PT.to_dev(q), PT.to_dev(ref["O"]), PT.to_dev(ref["lse"]), PT.to_dev(dl))
+        m = torch.zeros(n, device=PT.DEV)
+        v = torch.zeros(n, device=PT.DEV)
+        loss = torch.zeros(2, device=PT.DEV, dtype=torch.float64)
+        eng.fit_step(tth, m, v, 1, PT.to_dev(q), PT.to_dev(o), loss)
+        torch.cuda.synchronize()
+        st = eng.stats()
+        th1, m1, G, loss = (x.cpu().numpy() for x in (tth, m, G, loss))
+    # the premise: many 2x2x2 blocks hold 192..512 queries, one tile each
+    h = 2.0 / (R - 1)
+    c = np.clip(np.floor((q.astype(np.float64) + 1.0) / h).astype(int), 0, R - 2)
+    nb = (R - 1 + 1) // 2
+    tot = np.bincount((c[:, 0] // 2 * nb + c[:, 1] // 2) * nb + c[:, 2] // 2, minlength=nb ** 3)
+    assert ((tot >= 192) & (tot <= 512)).sum() >= 40 and st["W"] <= 3, st
+    gr, ar, br = PT.oracle_grad(R, th, q, dl)
+    PT.check_grad(G, gr, ar, br)
+    fr = orc.fit_step(orc.Grid(R=R), th, np.zeros(n), np.zeros(n), 1, q, o)
+    assert abs(loss[0] - fr["loss"]) <= 1e-5 * fr["loss"]
+    assert abs(loss[1] - fr["l1"]) <= 1e-5 * fr["l1"]
+    g_gpu = m1.astype(np.float64) / (1.0 - np.float32(0.9))
+    PT.check_grad(g_gpu, fr["grad"], ar, br)
+    th_ref, _, _ = orc.adam(th.reshape(-1), np.zeros(n), np.zeros(n), g_gpu.reshape(-1), 1)
+    assert np.all(np.abs(th1.reshape(-1) - th_ref) <= 4 * PT.ulp32(th_ref) + 1e-6 * 6e-4)
+
+
 @pytest.mark.parametrize("R", [2, 3])
 def test_minimum_lattices_eval_grad_fit_step(E, R):
     """The smallest lattices: one cell (R = 2) and eight (R = 3), so every
